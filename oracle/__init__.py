@@ -1,0 +1,222 @@
+"""FP64 CPU oracle of the D3Q27 central-moment LBM with Hermite forcing.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+cpu_baseline leg of bench.py, never by the product package.  It shares no code
+with the HIP path.  The arithmetic lives in ``cmlbm_oracle.c`` (plain C, FP64,
+unshifted populations); this module only marshals numpy arrays through ctypes.
+
+Paper: De Rosis, Huang & Coreixas, Phys. Rev. E (2019), arXiv:1905.10182,
+Sec. II (method) -- see the header of cmlbm_oracle.c for the equation map and
+the readings taken where the paper is silent.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        path = _build.build(force=False)
+        lib = ctypes.CDLL(path)
+        lib.orc_lattice_constants.argtypes = [_ip, _ip, _ip, _dp, _ip]
+        lib.orc_feq.argtypes = [ctypes.c_double, _dp, _dp]
+        lib.orc_forcing.argtypes = [_dp, _dp, _dp]
+        lib.orc_basis.argtypes = [_dp, _dp]
+        lib.orc_central_moments.argtypes = [_dp, _dp, _dp]
+        lib.orc_macroscopic.argtypes = [_dp, _dp, _dp, _dp]
+        lib.orc_reconstruct_literal.argtypes = [_dp, _dp, _dp]
+        lib.orc_reconstruct_literal.restype = ctypes.c_int
+        lib.orc_reconstruct_fast.argtypes = [_dp, _dp, _dp]
+        lib.orc_collide_literal.argtypes = [_dp, _dp, ctypes.c_double, _dp]
+        lib.orc_collide_literal.restype = ctypes.c_int
+        lib.orc_collide_closed.argtypes = [_dp, _dp, ctypes.c_double, _dp]
+        lib.orc_pre_collision.argtypes = [_dp, _dp, _dp]
+        lib.orc_post_collision.argtypes = [ctypes.c_double, _dp, _dp, ctypes.c_double, _dp]
+        lib.orc_lattice_init.argtypes = [ctypes.c_int] * 4 + [_u8p, _dp, _dp, _dp]
+        lib.orc_lattice_step.argtypes = [ctypes.c_int] * 4 + [_ip, _u8p, _dp, ctypes.c_double,
+                                                              ctypes.c_int, ctypes.c_int, _dp, _dp]
+        lib.orc_lattice_step.restype = ctypes.c_int
+        lib.orc_lattice_moments.argtypes = [ctypes.c_int] * 4 + [_u8p, _dp, _dp, _dp, _dp]
+        lib.orc_num_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _vec(x, n):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(n))
+    return a
+
+
+def num_threads():
+    return _load().orc_num_threads()
+
+
+def constants():
+    """(cx, cy, cz, w, opp) of the D3Q27 lattice in the paper's order."""
+    lib = _load()
+    cx = np.zeros(27, np.int32)
+    cy = np.zeros(27, np.int32)
+    cz = np.zeros(27, np.int32)
+    w = np.zeros(27)
+    opp = np.zeros(27, np.int32)
+    ip = lambda a: a.ctypes.data_as(_ip)  # noqa: E731
+    lib.orc_lattice_constants(ip(cx), ip(cy), ip(cz), _d(w), ip(opp))
+    return cx, cy, cz, w, opp
+
+
+def feq(rho, u):
+    """Complete 27-Hermite equilibrium (eq. eq:truncation)."""
+    out = np.zeros(27)
+    _load().orc_feq(float(rho), _d(_vec(u, 3)), _d(out))
+    return out
+
+
+def forcing(u, F):
+    """Complete Hermite forcing term (eq. forcing), F a force density."""
+    out = np.zeros(27)
+    _load().orc_forcing(_d(_vec(u, 3)), _d(_vec(F, 3)), _d(out))
+    return out
+
+
+def basis(u):
+    """Transformation matrix T-bar with T[i, j] = T_j(c_i - u) (eq. basis)."""
+    out = np.zeros((27, 27))
+    _load().orc_basis(_d(_vec(u, 3)), _d(out))
+    return out
+
+
+def central_moments(u, f):
+    """k = T-bar^T f."""
+    out = np.zeros(27)
+    _load().orc_central_moments(_d(_vec(u, 3)), _d(_vec(f, 27)), _d(out))
+    return out
+
+
+def macroscopic(f, F=(0.0, 0.0, 0.0)):
+    """rho and the half-force-corrected u (eq. macroscopic)."""
+    rho = np.zeros(1)
+    u = np.zeros(3)
+    _load().orc_macroscopic(_d(_vec(f, 27)), _d(_vec(F, 3)), _d(rho), _d(u))
+    return float(rho[0]), u
+
+
+def reconstruct_literal(u, k):
+    out = np.zeros(27)
+    if _load().orc_reconstruct_literal(_d(_vec(u, 3)), _d(_vec(k, 27)), _d(out)) != 0:
+        raise ArithmeticError("singular central-moment matrix")
+    return out
+
+
+def reconstruct_fast(u, k):
+    out = np.zeros(27)
+    _load().orc_reconstruct_fast(_d(_vec(u, 3)), _d(_vec(k, 27)), _d(out))
+    return out
+
+
+def pre_collision(f, u):
+    """k_4..k_8 of eq. pre_collision."""
+    out = np.zeros(5)
+    _load().orc_pre_collision(_d(_vec(f, 27)), _d(_vec(u, 3)), _d(out))
+    return out
+
+
+def post_collision(rho, k48, F, omega):
+    """Basis-ordered post-collision central moments (eq. post_collision_central_moments_forcing)."""
+    out = np.zeros(27)
+    _load().orc_post_collision(float(rho), _d(_vec(k48, 5)), _d(_vec(F, 3)), float(omega), _d(out))
+    return out
+
+
+def collide_literal(f, F, omega):
+    out = np.zeros(27)
+    if _load().orc_collide_literal(_d(_vec(f, 27)), _d(_vec(F, 3)), float(omega), _d(out)) != 0:
+        raise ArithmeticError("singular central-moment matrix")
+    return out
+
+
+def collide_closed(f, F, omega):
+    out = np.zeros(27)
+    _load().orc_collide_closed(_d(_vec(f, 27)), _d(_vec(F, 3)), float(omega), _d(out))
+    return out
+
+
+class Lattice:
+    """A lattice of nb independent nx*ny*nz boxes advanced by the oracle.
+
+    State ``f`` is the pre-collision population array f(x, t), shape
+    (27, nb, nz, ny, nx), unshifted FP64, paper order.  ``wall`` gives per axis
+    (x, y, z) 0 = periodic or 1 = halfway bounce-back walls; ``solid`` is an
+    optional (nb, nz, ny, nx) mask; ``force`` an optional (3, nb, nz, ny, nx)
+    force-density field (constant in time).
+    """
+
+    VARIANTS = {"closed": 0, "literal": 1}
+
+    def __init__(self, nx, ny, nz, nb=1, tau=0.8, wall=(0, 0, 0), solid=None, force=None):
+        self.nx, self.ny, self.nz, self.nb = int(nx), int(ny), int(nz), int(nb)
+        self.shape = (self.nb, self.nz, self.ny, self.nx)
+        self.N = int(np.prod(self.shape))
+        if tau <= 0.5:
+            raise ValueError("tau must exceed 1/2")
+        self.tau = float(tau)
+        self.omega = 1.0 / self.tau
+        self.wall = np.ascontiguousarray(np.asarray(wall, np.int32).reshape(3))
+        self.solid = None if solid is None else np.ascontiguousarray(
+            np.asarray(solid).reshape(self.shape).astype(np.uint8))
+        self.set_force(force)
+        self.f = np.zeros((27,) + self.shape)
+        self._tmp = np.zeros_like(self.f)
+        self.t = 0
+
+    def set_force(self, force):
+        if force is None:
+            self.force = None
+        else:
+            self.force = np.ascontiguousarray(
+                np.broadcast_to(np.asarray(force, np.float64), (3,) + self.shape).copy())
+
+    def _solid_p(self):
+        return None if self.solid is None else self.solid.ctypes.data_as(_u8p)
+
+    def _force_p(self):
+        return None if self.force is None else _d(self.force)
+
+    def init(self, rho, u):
+        rho = np.ascontiguousarray(np.broadcast_to(np.asarray(rho, np.float64), self.shape))
+        u = np.ascontiguousarray(np.broadcast_to(np.asarray(u, np.float64), (3,) + self.shape))
+        _load().orc_lattice_init(self.nx, self.ny, self.nz, self.nb, self._solid_p(), _d(rho), _d(u),
+                                 _d(self.f))
+        self.t = 0
+
+    def load_populations(self, f):
+        self.f[...] = np.asarray(f, np.float64).reshape(self.f.shape)
+
+    def step(self, nsteps=1, variant="closed"):
+        rc = _load().orc_lattice_step(self.nx, self.ny, self.nz, self.nb, self.wall.ctypes.data_as(_ip),
+                                      self._solid_p(), self._force_p(), self.omega,
+                                      self.VARIANTS[variant], int(nsteps), _d(self.f), _d(self._tmp))
+        if rc != 0:
+            raise ArithmeticError("singular central-moment matrix during a literal step")
+        self.t += int(nsteps)
+
+    def moments(self):
+        """(rho, u) at the current time; solid cells report 0."""
+        rho = np.zeros(self.shape)
+        u = np.zeros((3,) + self.shape)
+        _load().orc_lattice_moments(self.nx, self.ny, self.nz, self.nb, self._solid_p(), self._force_p(),
+                                    _d(self.f), _d(rho), _d(u))
+        return rho, u

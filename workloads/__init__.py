@@ -1,0 +1,119 @@
+"""Seeded synthetic inputs shared by the oracle side and the GPU side.
+
+This module holds workload definitions only -- initial density and velocity
+fields, force densities, geometries and random draws -- and none of the
+method's arithmetic.  Random numbers come from numpy's PCG64 with explicit
+seeds, so every caller sees identical inputs.
+
+Workloads (sizes as used by the tests and the benchmark):
+  poiseuille      body-force channel, periodic x and z, bounce-back walls in y
+  taylor_green    3D Taylor-Green vortex in a periodic cube
+  kolmogorov      sinusoidally forced periodic cube
+  sphere_channels batch of forced channels with spherical obstacles
+"""
+import math
+
+import numpy as np
+
+
+def generator(seed):
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def poiseuille(nx=32, ny=16, nz=16, tau=0.8, fx=1e-6, steps=1000):
+    """Body-force Poiseuille channel 32x16x16: fluid at rest, rho = 1, uniform
+    force density (fx, 0, 0), walls at y = -1/2 and y = ny - 1/2."""
+    shape = (1, nz, ny, nx)
+    return dict(name=f"poiseuille_{nx}x{ny}x{nz}", shape=shape, tau=tau, rho0=1.0, wall=(0, 1, 0),
+                rho=np.ones(shape), u=np.zeros((3,) + shape), force=np.array([fx, 0.0, 0.0]), steps=steps)
+
+
+def taylor_green_viscosity(n, u0=0.05, re=1600.0):
+    """nu from Re = u0 (n / 2 pi) / nu (length scale 1/k)."""
+    return u0 * n / (2.0 * math.pi * re)
+
+
+def taylor_green(n, u0=0.05, re=1600.0, noise=1e-6, seed=1, rho0=1.0, steps=2000, dtype=np.float64):
+    """3D Taylor-Green vortex on an n^3 periodic box.
+
+    u = u0 (sin kx cos ky cos kz, -cos kx sin ky cos kz, 0), k = 2 pi / n,
+    rho = rho0 + 3 rho0 u0^2/16 (cos 2kx + cos 2ky)(cos 2kz + 2) + U(-noise, noise)
+    (the pressure field of the incompressible vortex divided by c_s^2 = 1/3),
+    tau = 3 nu + 1/2 with nu fixed by Re."""
+    nu = taylor_green_viscosity(n, u0, re)
+    tau = 3.0 * nu + 0.5
+    k = 2.0 * math.pi / n
+    c = np.arange(n, dtype=np.float64) * k
+    sx, cx_ = np.sin(c), np.cos(c)
+    c2 = np.cos(2 * c)
+    shape = (1, n, n, n)  # (b, z, y, x)
+    ux = u0 * (cx_[None, :, None] * sx[None, None, :]) * cx_[:, None, None]
+    uy = -u0 * (sx[None, :, None] * cx_[None, None, :]) * cx_[:, None, None]
+    u = np.zeros((3,) + shape, dtype=dtype)
+    u[0, 0] = ux
+    u[1, 0] = uy
+    rho = np.empty(shape, dtype=dtype)
+    rho[0] = rho0 + 3.0 * rho0 * u0 * u0 / 16.0 * (c2[None, None, :] + c2[None, :, None]) * (c2[:, None, None] + 2.0)
+    if noise:
+        rho[0] += generator(seed).uniform(-noise, noise, size=(n, n, n))
+    return dict(name=f"taylor_green_{n}", shape=shape, tau=tau, nu=nu, rho0=rho0, wall=(0, 0, 0), rho=rho, u=u,
+                force=None, steps=steps, u0=u0)
+
+
+def kolmogorov(n, f0=1e-5, tau=0.5005, kf=4, noise=1e-4, seed=2, steps=5000):
+    """Kolmogorov flow on an n^3 periodic box: force density
+    F_x(y) = f0 sin(2 pi kf y / n) on integer node rows y, rho = 1, velocity
+    components i.i.d. U(-noise, noise)."""
+    shape = (1, n, n, n)
+    y = np.arange(n, dtype=np.float64)
+    prof = np.zeros((n, 3))
+    prof[:, 0] = f0 * np.sin(2.0 * math.pi * kf * y / n)
+    u = generator(seed).uniform(-noise, noise, size=(3,) + shape)
+    return dict(name=f"kolmogorov_{n}", shape=shape, tau=tau, rho0=1.0, wall=(0, 0, 0), rho=np.ones(shape), u=u,
+                force_profile_y=prof, steps=steps)
+
+
+def sphere_channels(nb, nx=64, ny=32, nz=32, seed=1000, rmin=3.0, rmax=8.0, nmin=1, nmax=4, fmin=1e-6, fmax=1e-5,
+                    tau=0.8):
+    """Batch of nb forced channels (periodic x, z; walls in y) with 1-4 solid
+    spheres each.  Radius U[rmin, rmax]; centre x, z uniform, y uniform in
+    [r, ny - 1 - r]; node (x, y, z) is solid if its periodic distance (in x and
+    z) to a centre is <= r.  Force density (F_x, 0, 0), F_x ~ U[fmin, fmax].
+    Member b uses the seed seed + b, so members are reproducible one by one."""
+    solid = np.zeros((nb, nz, ny, nx), np.uint8)
+    fx = np.zeros(nb)
+    spheres = []
+    X = np.arange(nx)[None, None, :]
+    Y = np.arange(ny)[None, :, None]
+    Z = np.arange(nz)[:, None, None]
+    for b in range(nb):
+        g = generator(seed + b)
+        ns = int(g.integers(nmin, nmax + 1))
+        fx[b] = g.uniform(fmin, fmax)
+        lst = []
+        for _ in range(ns):
+            r = g.uniform(rmin, rmax)
+            cx = g.uniform(0, nx)
+            cy = g.uniform(r, ny - 1 - r)
+            cz = g.uniform(0, nz)
+            dx = np.abs(X - cx)
+            dx = np.minimum(dx, nx - dx)
+            dz = np.abs(Z - cz)
+            dz = np.minimum(dz, nz - dz)
+            solid[b] |= ((dx * dx + (Y - cy) ** 2 + dz * dz) <= r * r).astype(np.uint8)
+            lst.append((cx, cy, cz, r))
+        spheres.append(lst)
+    return dict(name=f"sphere_channels_{nb}x{nx}x{ny}x{nz}", shape=(nb, nz, ny, nx), tau=tau, rho0=1.0,
+                wall=(0, 1, 0), solid=solid, fx=fx, spheres=spheres)
+
+
+def random_populations(shape, seed, lo=0.8, hi=1.2):
+    """Positive populations f_i = U(lo, hi) / 27, array (27,) + shape: an
+    arbitrary (non-equilibrium) pre-collision state for parity tests."""
+    return generator(seed).uniform(lo, hi, size=(27,) + tuple(shape)) / 27.0
+
+
+def random_cells(n, seed, umax=0.1, rho_lo=0.9, rho_hi=1.1):
+    """n random (rho, u) pairs: rho ~ U[rho_lo, rho_hi], u_a ~ U[-umax, umax]."""
+    g = generator(seed)
+    return g.uniform(rho_lo, rho_hi, size=n), g.uniform(-umax, umax, size=(n, 3))
