@@ -16,20 +16,23 @@ import numpy as np
 
 from . import build as _build
 
-_lib = None
+_libs = {}
 
-_dp = ctypes.POINTER(ctypes.c_double)
+_dpp = ctypes.POINTER(ctypes.c_double)
+_ldp = ctypes.POINTER(ctypes.c_longdouble)
+_dp = _dpp
 _ip = ctypes.POINTER(ctypes.c_int)
 _u8p = ctypes.POINTER(ctypes.c_uint8)
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        path = _build.build(force=False)
+def _load(extended=False):
+    if extended not in _libs:
+        path = _build.build(force=False, extended=extended)
         lib = ctypes.CDLL(path)
+        _dp = _ldp if extended else _dpp
+        _real = ctypes.c_longdouble if extended else ctypes.c_double
         lib.orc_lattice_constants.argtypes = [_ip, _ip, _ip, _dp, _ip]
-        lib.orc_feq.argtypes = [ctypes.c_double, _dp, _dp]
+        lib.orc_feq.argtypes = [_real, _dp, _dp]
         lib.orc_forcing.argtypes = [_dp, _dp, _dp]
         lib.orc_basis.argtypes = [_dp, _dp]
         lib.orc_central_moments.argtypes = [_dp, _dp, _dp]
@@ -37,23 +40,27 @@ def _load():
         lib.orc_reconstruct_literal.argtypes = [_dp, _dp, _dp]
         lib.orc_reconstruct_literal.restype = ctypes.c_int
         lib.orc_reconstruct_fast.argtypes = [_dp, _dp, _dp]
-        lib.orc_collide_literal.argtypes = [_dp, _dp, ctypes.c_double, _dp]
+        lib.orc_collide_literal.argtypes = [_dp, _dp, _real, _dp]
         lib.orc_collide_literal.restype = ctypes.c_int
-        lib.orc_collide_closed.argtypes = [_dp, _dp, ctypes.c_double, _dp]
+        lib.orc_collide_closed.argtypes = [_dp, _dp, _real, _dp]
         lib.orc_pre_collision.argtypes = [_dp, _dp, _dp]
-        lib.orc_post_collision.argtypes = [ctypes.c_double, _dp, _dp, ctypes.c_double, _dp]
+        lib.orc_post_collision.argtypes = [_real, _dp, _dp, _real, _dp]
         lib.orc_lattice_init.argtypes = [ctypes.c_int] * 4 + [_u8p, _dp, _dp, _dp]
-        lib.orc_lattice_step.argtypes = [ctypes.c_int] * 4 + [_ip, _u8p, _dp, ctypes.c_double,
+        lib.orc_lattice_step.argtypes = [ctypes.c_int] * 4 + [_ip, _u8p, _dp, _real,
                                                               ctypes.c_int, ctypes.c_int, _dp, _dp]
         lib.orc_lattice_step.restype = ctypes.c_int
         lib.orc_lattice_moments.argtypes = [ctypes.c_int] * 4 + [_u8p, _dp, _dp, _dp, _dp]
         lib.orc_num_threads.restype = ctypes.c_int
-        _lib = lib
-    return _lib
+        lib.orc_collide_cells.argtypes = [ctypes.c_long, _dp, _dp, _real, ctypes.c_int, _dp]
+        lib.orc_collide_cells.restype = ctypes.c_int
+        _libs[extended] = lib
+    return _libs[extended]
 
 
 def _d(a):
-    return a.ctypes.data_as(_dp)
+    if a.dtype == np.longdouble and np.longdouble != np.float64:
+        return a.ctypes.data_as(_ldp)
+    return a.ctypes.data_as(_dpp)
 
 
 def _vec(x, n):
@@ -154,6 +161,22 @@ def collide_closed(f, F, omega):
     return out
 
 
+def collide_cells(f, F, omega, variant="closed", extended=False):
+    """Collide independent cells: f (27, n), F (3, n) or None -> f* (27, n)."""
+    dt = np.longdouble if extended else np.float64
+    f = np.ascontiguousarray(np.asarray(f, dt))
+    n = f.shape[1]
+    Fp = None
+    if F is not None:
+        F = np.ascontiguousarray(np.broadcast_to(np.asarray(F, dt), (3, n)))
+        Fp = _d(F)
+    out = np.zeros_like(f)
+    rc = _load(extended).orc_collide_cells(n, _d(f), Fp, omega, Lattice.VARIANTS[variant], _d(out))
+    if rc != 0:
+        raise ArithmeticError("singular central-moment matrix")
+    return out
+
+
 class Lattice:
     """A lattice of nb independent nx*ny*nz boxes advanced by the oracle.
 
@@ -161,24 +184,28 @@ class Lattice:
     (27, nb, nz, ny, nx), unshifted FP64, paper order.  ``wall`` gives per axis
     (x, y, z) 0 = periodic or 1 = halfway bounce-back walls; ``solid`` is an
     optional (nb, nz, ny, nx) mask; ``force`` an optional (3, nb, nz, ny, nx)
-    force-density field (constant in time).
+    force-density field (constant in time).  ``extended=True`` runs the same
+    oracle in 80-bit long double (arrays np.longdouble).
     """
 
     VARIANTS = {"closed": 0, "literal": 1}
 
-    def __init__(self, nx, ny, nz, nb=1, tau=0.8, wall=(0, 0, 0), solid=None, force=None):
+    def __init__(self, nx, ny, nz, nb=1, tau=0.8, wall=(0, 0, 0), solid=None, force=None, extended=False):
+        self.extended = bool(extended)
+        self.dtype = np.longdouble if self.extended else np.float64
+        self.lib = _load(self.extended)
         self.nx, self.ny, self.nz, self.nb = int(nx), int(ny), int(nz), int(nb)
         self.shape = (self.nb, self.nz, self.ny, self.nx)
         self.N = int(np.prod(self.shape))
         if tau <= 0.5:
             raise ValueError("tau must exceed 1/2")
         self.tau = float(tau)
-        self.omega = 1.0 / self.tau
+        self.omega = 1 / self.dtype(self.tau)
         self.wall = np.ascontiguousarray(np.asarray(wall, np.int32).reshape(3))
         self.solid = None if solid is None else np.ascontiguousarray(
             np.asarray(solid).reshape(self.shape).astype(np.uint8))
         self.set_force(force)
-        self.f = np.zeros((27,) + self.shape)
+        self.f = np.zeros((27,) + self.shape, self.dtype)
         self._tmp = np.zeros_like(self.f)
         self.t = 0
 
@@ -187,7 +214,7 @@ class Lattice:
             self.force = None
         else:
             self.force = np.ascontiguousarray(
-                np.broadcast_to(np.asarray(force, np.float64), (3,) + self.shape).copy())
+                np.broadcast_to(np.asarray(force, self.dtype), (3,) + self.shape).copy())
 
     def _solid_p(self):
         return None if self.solid is None else self.solid.ctypes.data_as(_u8p)
@@ -196,17 +223,17 @@ class Lattice:
         return None if self.force is None else _d(self.force)
 
     def init(self, rho, u):
-        rho = np.ascontiguousarray(np.broadcast_to(np.asarray(rho, np.float64), self.shape))
-        u = np.ascontiguousarray(np.broadcast_to(np.asarray(u, np.float64), (3,) + self.shape))
-        _load().orc_lattice_init(self.nx, self.ny, self.nz, self.nb, self._solid_p(), _d(rho), _d(u),
+        rho = np.ascontiguousarray(np.broadcast_to(np.asarray(rho, self.dtype), self.shape))
+        u = np.ascontiguousarray(np.broadcast_to(np.asarray(u, self.dtype), (3,) + self.shape))
+        self.lib.orc_lattice_init(self.nx, self.ny, self.nz, self.nb, self._solid_p(), _d(rho), _d(u),
                                  _d(self.f))
         self.t = 0
 
     def load_populations(self, f):
-        self.f[...] = np.asarray(f, np.float64).reshape(self.f.shape)
+        self.f[...] = np.asarray(f, self.dtype).reshape(self.f.shape)
 
     def step(self, nsteps=1, variant="closed"):
-        rc = _load().orc_lattice_step(self.nx, self.ny, self.nz, self.nb, self.wall.ctypes.data_as(_ip),
+        rc = self.lib.orc_lattice_step(self.nx, self.ny, self.nz, self.nb, self.wall.ctypes.data_as(_ip),
                                       self._solid_p(), self._force_p(), self.omega,
                                       self.VARIANTS[variant], int(nsteps), _d(self.f), _d(self._tmp))
         if rc != 0:
@@ -215,8 +242,8 @@ class Lattice:
 
     def moments(self):
         """(rho, u) at the current time; solid cells report 0."""
-        rho = np.zeros(self.shape)
-        u = np.zeros((3,) + self.shape)
-        _load().orc_lattice_moments(self.nx, self.ny, self.nz, self.nb, self._solid_p(), self._force_p(),
+        rho = np.zeros(self.shape, self.dtype)
+        u = np.zeros((3,) + self.shape, self.dtype)
+        self.lib.orc_lattice_moments(self.nx, self.ny, self.nz, self.nb, self._solid_p(), self._force_p(),
                                     _d(self.f), _d(rho), _d(u))
         return rho, u

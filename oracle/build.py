@@ -11,19 +11,26 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "cmlbm_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+LIB_EXT = os.path.join(HERE, "liboracle_ext.so")  # same source in 80-bit long double
 
 CFLAGS = ["-O3", "-march=x86-64-v3", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
           "-shared", "-fPIC", "-Wall", "-Wextra"]
 
 
-def build(force=True):
-    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
-        return LIB
-    tmp = LIB + ".tmp"
-    cmd = ["gcc", *CFLAGS, "-o", tmp, SRC, "-lm"]
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+def build_one(lib, defines, force):
+    if not force and os.path.exists(lib) and os.path.getmtime(lib) >= os.path.getmtime(SRC):
+        return lib
+    tmp = lib + ".tmp"
+    subprocess.run(["gcc", *CFLAGS, *defines, "-o", tmp, SRC, "-lm"], check=True)
+    os.replace(tmp, lib)
+    return lib
+
+
+def build(force=True, extended=False):
+    """Build the FP64 oracle (and the 80-bit one); return the requested path."""
+    a = build_one(LIB, [], force)
+    b = build_one(LIB_EXT, ["-DORC_EXTENDED"], force)
+    return b if extended else a
 
 
 if __name__ == "__main__":

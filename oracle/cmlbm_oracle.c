@@ -10,7 +10,7 @@
  * benchmark may load it.  The GPU library never links, calls or includes it,
  * and the two share no code, tables or constants.
  *
- * Everything is unshifted FP64 (the textbook populations f_i, not f_i - w_i rho0).
+ * Everything is unshifted FP64 (or 80-bit, see `real` below) (the textbook populations f_i, not f_i - w_i rho0).
  * Two collision routes are provided:
  *   - "literal" (orc_collide_literal): the matrix algebra of Sec. II as printed:
  *     build the central-moment basis T-bar (eq. "basis"), k = T^T f,
@@ -55,21 +55,32 @@
 
 #define Q 27
 
+/* Scalar type.  The default build is FP64; the extended build (-DORC_EXTENDED)
+ * runs the same arithmetic in x87 80-bit long double and serves as the
+ * reference where a bar is tighter than FP64 rounding of the unshifted form. */
+#ifdef ORC_EXTENDED
+typedef long double real;
+#define RFABS fabsl
+#else
+typedef double real;
+#define RFABS fabs
+#endif
+
 /* D3Q27 velocity components, in the order printed at the start of Sec. II. */
 static const int CX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
 static const int CY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, 1, -1, -1, 1, 1, -1, -1};
 static const int CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1, 1, 1, 1, 1, -1, -1, -1, -1};
 
 /* Lattice weights listed after eq. "eq:truncation". */
-static double weight(int i)
+static real weight(int i)
 {
-    if (i == 0) return 8.0 / 27.0;
-    if (i <= 6) return 2.0 / 27.0;
-    if (i <= 18) return 1.0 / 54.0;
-    return 1.0 / 216.0;
+    if (i == 0) return (real)8 / 27;
+    if (i <= 6) return (real)2 / 27;
+    if (i <= 18) return (real)1 / 54;
+    return (real)1 / 216;
 }
 
-static const double CS2 = 1.0 / 3.0; /* c_s^2, c_s = 1/sqrt(3) */
+static const real CS2 = (real)1 / 3; /* c_s^2, c_s = 1/sqrt(3) */
 
 static int opposite(int i)
 {
@@ -78,7 +89,7 @@ static int opposite(int i)
     return -1;
 }
 
-void orc_lattice_constants(int* cx, int* cy, int* cz, double* w, int* opp)
+void orc_lattice_constants(int* cx, int* cy, int* cz, real* w, int* opp)
 {
     for (int i = 0; i < Q; ++i) {
         cx[i] = CX[i];
@@ -91,7 +102,7 @@ void orc_lattice_constants(int* cx, int* cy, int* cz, double* w, int* opp)
 
 /* One-dimensional discrete Hermite polynomials of App. A: H^(0) = 1,
  * H^(1) = c, H^(2) = c^2 - c_s^2.  3D tensors are their products. */
-static double herm1d(int order, double c)
+static real herm1d(int order, real c)
 {
     if (order == 0) return 1.0;
     if (order == 1) return c;
@@ -100,19 +111,19 @@ static double herm1d(int order, double c)
 
 typedef struct {
     /* H^(n) tensors of App. A for one lattice velocity, named by index string */
-    double x, y, z;
-    double xx, yy, zz, xy, xz, yz;
-    double xxy, xxz, xyy, xzz, yzz, yyz, xyz;
-    double xxyy, xxzz, yyzz, xyzz, xyyz, xxyz;
-    double xxyzz, xxyyz, xyyzz;
-    double xxyyzz;
+    real x, y, z;
+    real xx, yy, zz, xy, xz, yz;
+    real xxy, xxz, xyy, xzz, yzz, yyz, xyz;
+    real xxyy, xxzz, yyzz, xyzz, xyyz, xxyz;
+    real xxyzz, xxyyz, xyyzz;
+    real xxyyzz;
 } hermite_set;
 
 static void hermite_tensors(int i, hermite_set* h)
 {
-    const double cx = CX[i], cy = CY[i], cz = CZ[i];
-    const double Hx = herm1d(1, cx), Hy = herm1d(1, cy), Hz = herm1d(1, cz);
-    const double Hxx = herm1d(2, cx), Hyy = herm1d(2, cy), Hzz = herm1d(2, cz);
+    const real cx = CX[i], cy = CY[i], cz = CZ[i];
+    const real Hx = herm1d(1, cx), Hy = herm1d(1, cy), Hz = herm1d(1, cz);
+    const real Hxx = herm1d(2, cx), Hyy = herm1d(2, cy), Hzz = herm1d(2, cz);
     h->x = Hx;
     h->y = Hy;
     h->z = Hz;
@@ -142,14 +153,14 @@ static void hermite_tensors(int i, hermite_set* h)
 }
 
 /* Complete 27-Hermite equilibrium, eq. "eq:truncation", term by term. */
-void orc_feq(double rho, const double u[3], double out[Q])
+void orc_feq(real rho, const real u[3], real out[Q])
 {
-    const double ux = u[0], uy = u[1], uz = u[2];
-    const double cs4 = CS2 * CS2, cs6 = cs4 * CS2, cs8 = cs4 * cs4, cs10 = cs8 * CS2, cs12 = cs6 * cs6;
+    const real ux = u[0], uy = u[1], uz = u[2];
+    const real cs4 = CS2 * CS2, cs6 = cs4 * CS2, cs8 = cs4 * cs4, cs10 = cs8 * CS2, cs12 = cs6 * cs6;
     for (int i = 0; i < Q; ++i) {
         hermite_set H;
         hermite_tensors(i, &H);
-        double s = 1.0;
+        real s = 1.0;
         s += (CX[i] * ux + CY[i] * uy + CZ[i] * uz) / CS2;
         s += (H.xx * ux * ux + H.yy * uy * uy + H.zz * uz * uz +
               2.0 * (H.xy * ux * uy + H.xz * ux * uz + H.yz * uy * uz)) /
@@ -170,15 +181,15 @@ void orc_feq(double rho, const double u[3], double out[Q])
 
 /* Complete Hermite forcing term, eq. "forcing", term by term, under reading R1
  * (F is a force density, so the rho prefactor of the printed formula is 1). */
-void orc_forcing(const double u[3], const double F[3], double out[Q])
+void orc_forcing(const real u[3], const real F[3], real out[Q])
 {
-    const double ux = u[0], uy = u[1], uz = u[2];
-    const double Fx = F[0], Fy = F[1], Fz = F[2];
-    const double cs4 = CS2 * CS2, cs6 = cs4 * CS2, cs8 = cs4 * cs4, cs10 = cs8 * CS2, cs12 = cs6 * cs6;
+    const real ux = u[0], uy = u[1], uz = u[2];
+    const real Fx = F[0], Fy = F[1], Fz = F[2];
+    const real cs4 = CS2 * CS2, cs6 = cs4 * CS2, cs8 = cs4 * cs4, cs10 = cs8 * CS2, cs12 = cs6 * cs6;
     for (int i = 0; i < Q; ++i) {
         hermite_set H;
         hermite_tensors(i, &H);
-        double s = (Fx * CX[i] + Fy * CY[i] + Fz * CZ[i]) / CS2;
+        real s = (Fx * CX[i] + Fy * CY[i] + Fz * CZ[i]) / CS2;
         s += (H.xx * (2 * ux * Fx) + H.yy * (2 * uy * Fy) + H.zz * (2 * uz * Fz) +
               2 * H.xy * (ux * Fy + uy * Fx) + 2 * H.xz * (ux * Fz + uz * Fx) + 2 * H.yz * (uy * Fz + uz * Fy)) /
              (2 * cs4);
@@ -206,9 +217,9 @@ void orc_forcing(const double u[3], const double F[3], double out[Q])
 }
 
 /* The 27 basis polynomials of eq. "basis" evaluated at one shifted velocity. */
-static void basis_polys(double X, double Y, double Z, double T[Q])
+static void basis_polys(real X, real Y, real Z, real T[Q])
 {
-    const double X2 = X * X, Y2 = Y * Y, Z2 = Z * Z;
+    const real X2 = X * X, Y2 = Y * Y, Z2 = Z * Z;
     T[0] = 1.0;
     T[1] = X;
     T[2] = Y;
@@ -241,27 +252,27 @@ static void basis_polys(double X, double Y, double Z, double T[Q])
 /* Transformation matrix T-bar: column j is the basis polynomial T_j evaluated at
  * the shifted velocities c-bar_i = c_i - u of eq. "central_directions".
  * Stored row-major: Tbar[i*27 + j] = T_j(c-bar_i). */
-void orc_basis(const double u[3], double Tbar[Q * Q])
+void orc_basis(const real u[3], real Tbar[Q * Q])
 {
     for (int i = 0; i < Q; ++i) basis_polys(CX[i] - u[0], CY[i] - u[1], CZ[i] - u[2], &Tbar[i * Q]);
 }
 
 /* k = T^T f, i.e. k_j = sum_i T_j(c-bar_i) f_i. */
-void orc_central_moments(const double u[3], const double f[Q], double k[Q])
+void orc_central_moments(const real u[3], const real f[Q], real k[Q])
 {
-    double T[Q * Q];
+    real T[Q * Q];
     orc_basis(u, T);
     for (int j = 0; j < Q; ++j) {
-        double s = 0.0;
+        real s = 0.0;
         for (int i = 0; i < Q; ++i) s += T[i * Q + j] * f[i];
         k[j] = s;
     }
 }
 
 /* Eq. "macroscopic": rho = sum f, rho u = sum f c + F/2. */
-void orc_macroscopic(const double f[Q], const double F[3], double* rho, double u[3])
+void orc_macroscopic(const real f[Q], const real F[3], real* rho, real u[3])
 {
-    double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+    real r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
     for (int i = 0; i < Q; ++i) {
         r += f[i];
         jx += f[i] * CX[i];
@@ -276,36 +287,36 @@ void orc_macroscopic(const double f[Q], const double F[3], double* rho, double u
 
 /* Solve A x = b for a dense n x n system by Gaussian elimination with partial
  * pivoting (A row-major, overwritten).  Returns 0 on success, -1 if singular. */
-static int dense_solve(int n, double* A, double* b, double* x)
+static int dense_solve(int n, real* A, real* b, real* x)
 {
     for (int c = 0; c < n; ++c) {
         int piv = c;
-        double best = fabs(A[c * n + c]);
+        real best = RFABS(A[c * n + c]);
         for (int r = c + 1; r < n; ++r)
-            if (fabs(A[r * n + c]) > best) {
-                best = fabs(A[r * n + c]);
+            if (RFABS(A[r * n + c]) > best) {
+                best = RFABS(A[r * n + c]);
                 piv = r;
             }
         if (best == 0.0) return -1;
         if (piv != c) {
             for (int k = 0; k < n; ++k) {
-                double t = A[c * n + k];
+                real t = A[c * n + k];
                 A[c * n + k] = A[piv * n + k];
                 A[piv * n + k] = t;
             }
-            double t = b[c];
+            real t = b[c];
             b[c] = b[piv];
             b[piv] = t;
         }
         for (int r = c + 1; r < n; ++r) {
-            double m = A[r * n + c] / A[c * n + c];
+            real m = A[r * n + c] / A[c * n + c];
             if (m == 0.0) continue;
             for (int k = c; k < n; ++k) A[r * n + k] -= m * A[c * n + k];
             b[r] -= m * b[c];
         }
     }
     for (int r = n - 1; r >= 0; --r) {
-        double s = b[r];
+        real s = b[r];
         for (int k = r + 1; k < n; ++k) s -= A[r * n + k] * x[k];
         x[r] = s / A[r * n + r];
     }
@@ -313,12 +324,12 @@ static int dense_solve(int n, double* A, double* b, double* x)
 }
 
 /* Relaxation matrix of eq. "eq:relaxationMatrix": omega on k_4..k_8, 1 elsewhere. */
-static double relax_rate(int j, double omega) { return (j >= 4 && j <= 8) ? omega : 1.0; }
+static real relax_rate(int j, real omega) { return (j >= 4 && j <= 8) ? omega : 1.0; }
 
 /* Solve T^T f = k for f at velocity u (eq. "system"). */
-int orc_reconstruct_literal(const double u[3], const double k[Q], double f[Q])
+int orc_reconstruct_literal(const real u[3], const real k[Q], real f[Q])
 {
-    double T[Q * Q], A[Q * Q], b[Q];
+    real T[Q * Q], A[Q * Q], b[Q];
     orc_basis(u, T);
     for (int j = 0; j < Q; ++j)
         for (int i = 0; i < Q; ++i) A[j * Q + i] = T[i * Q + j]; /* A = T^T */
@@ -328,29 +339,29 @@ int orc_reconstruct_literal(const double u[3], const double k[Q], double f[Q])
 
 /* Literal collision: every central-moment vector is formed by the matrix
  * products of Sec. II; k^eq and R come from eqs. "eq:truncation" and "forcing". */
-int orc_collide_literal(const double f[Q], const double F[3], double omega, double fstar[Q])
+int orc_collide_literal(const real f[Q], const real F[3], real omega, real fstar[Q])
 {
-    double rho, u[3];
+    real rho, u[3];
     orc_macroscopic(f, F, &rho, u);
-    double feq[Q], ff[Q], k[Q], keq[Q], R[Q], ks[Q];
+    real feq[Q], ff[Q], k[Q], keq[Q], R[Q], ks[Q];
     orc_feq(rho, u, feq);
     orc_forcing(u, F, ff);
     orc_central_moments(u, f, k);
     orc_central_moments(u, feq, keq);
     orc_central_moments(u, ff, R);
     for (int j = 0; j < Q; ++j) {
-        const double L = relax_rate(j, omega);
+        const real L = relax_rate(j, omega);
         ks[j] = (1.0 - L) * k[j] + L * keq[j] + (1.0 - 0.5 * L) * R[j];
     }
     return orc_reconstruct_literal(u, ks, fstar);
 }
 
 /* Eq. "pre_collision": k_4..k_8 as direct sums with the shifted velocities. */
-void orc_pre_collision(const double f[Q], const double u[3], double k48[5])
+void orc_pre_collision(const real f[Q], const real u[3], real k48[5])
 {
-    double k4 = 0, k5 = 0, k6 = 0, k7 = 0, k8 = 0;
+    real k4 = 0, k5 = 0, k6 = 0, k7 = 0, k8 = 0;
     for (int i = 0; i < Q; ++i) {
-        const double X = CX[i] - u[0], Y = CY[i] - u[1], Z = CZ[i] - u[2];
+        const real X = CX[i] - u[0], Y = CY[i] - u[1], Z = CZ[i] - u[2];
         k4 += f[i] * X * Y;
         k5 += f[i] * X * Z;
         k6 += f[i] * Y * Z;
@@ -366,9 +377,9 @@ void orc_pre_collision(const double f[Q], const double u[3], double k48[5])
 
 /* Eq. "post_collision_central_moments_forcing": the nineteen non-zero
  * post-collision central moments, all others zero. */
-void orc_post_collision(double rho, const double k48[5], const double F[3], double omega, double ks[Q])
+void orc_post_collision(real rho, const real k48[5], const real F[3], real omega, real ks[Q])
 {
-    const double cs4 = CS2 * CS2, cs6 = cs4 * CS2;
+    const real cs4 = CS2 * CS2, cs6 = cs4 * CS2;
     for (int j = 0; j < Q; ++j) ks[j] = 0.0;
     ks[0] = rho;
     ks[1] = F[0] / 2;
@@ -395,10 +406,10 @@ void orc_post_collision(double rho, const double k48[5], const double F[3], doub
  * {-1, 0, +1} shifted by u: given m0 = sum g, m1 = sum g (c-u),
  * m2 = sum g (c-u)^2, return g(-1), g(0), g(+1).  From m1 + u m0 = g+ - g- and
  * m2 + 2u m1 + u^2 m0 = g+ + g-. */
-static void inverse_1d(double m0, double m1, double m2, double u, double g[3])
+static void inverse_1d(real m0, real m1, real m2, real u, real g[3])
 {
-    const double odd = m1 + u * m0;                    /* g+ - g- */
-    const double even = m2 + 2 * u * m1 + u * u * m0; /* g+ + g- */
+    const real odd = m1 + u * m0;                    /* g+ - g- */
+    const real even = m2 + 2 * u * m1 + u * u * m0; /* g+ + g- */
     g[0] = 0.5 * (even - odd);
     g[1] = m0 - even;
     g[2] = 0.5 * (even + odd);
@@ -408,9 +419,9 @@ static void inverse_1d(double m0, double m1, double m2, double u, double g[3])
  * inverse of k = T^T f).  Step 1 maps the basis of eq. "basis" to monomial
  * central moments K[p][q][r] = sum f (cx-ux)^p (cy-uy)^q (cz-uz)^r by
  * inverting its definitions; step 2 applies inverse_1d along z, y, x. */
-void orc_reconstruct_fast(const double u[3], const double k[Q], double f[Q])
+void orc_reconstruct_fast(const real u[3], const real k[Q], real f[Q])
 {
-    double K[3][3][3];
+    real K[3][3][3];
     K[0][0][0] = k[0];
     K[1][0][0] = k[1];
     K[0][1][0] = k[2];
@@ -442,7 +453,7 @@ void orc_reconstruct_fast(const double u[3], const double k[Q], double f[Q])
     K[2][2][1] = k[25];
     K[2][2][2] = k[26];
 
-    double A[3][3][3], B[3][3][3], C[3][3][3], g[3];
+    real A[3][3][3], B[3][3][3], C[3][3][3], g[3];
     for (int p = 0; p < 3; ++p) /* along z: A[p][q][cz] = sum_{fixed cz} f cbar_x^p cbar_y^q */
         for (int q = 0; q < 3; ++q) {
             inverse_1d(K[p][q][0], K[p][q][1], K[p][q][2], u[2], g);
@@ -463,9 +474,9 @@ void orc_reconstruct_fast(const double u[3], const double k[Q], double f[Q])
 
 /* Closed-form collision: the five steps listed at the end of Sec. II, minus the
  * streaming, which the lattice driver applies. */
-void orc_collide_closed(const double f[Q], const double F[3], double omega, double fstar[Q])
+void orc_collide_closed(const real f[Q], const real F[3], real omega, real fstar[Q])
 {
-    double rho, u[3], k48[5], ks[Q];
+    real rho, u[3], k48[5], ks[Q];
     orc_macroscopic(f, F, &rho, u);
     orc_pre_collision(f, u, k48);
     orc_post_collision(rho, k48, F, omega, ks);
@@ -479,11 +490,11 @@ typedef struct {
     int nx, ny, nz, nb;
     int wall[3];          /* per axis x,y,z: 0 periodic, 1 halfway bounce-back walls */
     const uint8_t* solid; /* [N], nonzero = solid node, or NULL */
-    const double* force;  /* [3][N] force density, or NULL */
+    const real* force;  /* [3][N] force density, or NULL */
 } grid_t;
 
 static void make_grid(grid_t* g, int nx, int ny, int nz, int nb, const int* wall, const uint8_t* solid,
-                      const double* force)
+                      const real* force)
 {
     g->nx = nx;
     g->ny = ny;
@@ -498,7 +509,7 @@ static long ncells(const grid_t* g) { return (long)g->nb * g->nz * g->ny * g->nx
 
 static int is_solid(const grid_t* g, long n) { return g->solid && g->solid[n]; }
 
-static void cell_force(const grid_t* g, long n, double F[3])
+static void cell_force(const grid_t* g, long n, real F[3])
 {
     const long N = ncells(g);
     for (int a = 0; a < 3; ++a) F[a] = g->force ? g->force[a * N + n] : 0.0;
@@ -524,19 +535,19 @@ static long neighbour(const grid_t* g, long n, int i)
     return m;
 }
 
-void orc_lattice_init(int nx, int ny, int nz, int nb, const uint8_t* solid, const double* rho,
-                      const double* u, double* f)
+void orc_lattice_init(int nx, int ny, int nz, int nb, const uint8_t* solid, const real* rho,
+                      const real* u, real* f)
 {
     grid_t g;
     make_grid(&g, nx, ny, nz, nb, NULL, solid, NULL);
     const long N = ncells(&g);
 #pragma omp parallel for schedule(static)
     for (long n = 0; n < N; ++n) {
-        double fe[Q];
+        real fe[Q];
         if (is_solid(&g, n)) {
             for (int i = 0; i < Q; ++i) fe[i] = 0.0;
         } else {
-            const double uu[3] = {u[n], u[N + n], u[2 * N + n]};
+            const real uu[3] = {u[n], u[N + n], u[2 * N + n]};
             orc_feq(rho[n], uu, fe);
         }
         for (int i = 0; i < Q; ++i) f[i * N + n] = fe[i];
@@ -549,7 +560,7 @@ void orc_lattice_init(int nx, int ny, int nz, int nb, const uint8_t* solid, cons
  * tmp is caller scratch of the same size as f.  Returns 0, or -1 if a literal
  * solve met a singular matrix. */
 int orc_lattice_step(int nx, int ny, int nz, int nb, const int* wall, const uint8_t* solid,
-                     const double* force, double omega, int variant, int nsteps, double* f, double* tmp)
+                     const real* force, real omega, int variant, int nsteps, real* f, real* tmp)
 {
     grid_t g;
     make_grid(&g, nx, ny, nz, nb, wall, solid, force);
@@ -559,7 +570,7 @@ int orc_lattice_step(int nx, int ny, int nz, int nb, const int* wall, const uint
 #pragma omp parallel for schedule(static)
         for (long n = 0; n < N; ++n) {
             if (is_solid(&g, n)) continue;
-            double fc[Q], fs[Q], F[3];
+            real fc[Q], fs[Q], F[3];
             for (int i = 0; i < Q; ++i) fc[i] = f[i * N + n];
             cell_force(&g, n, F);
             if (variant == 1) {
@@ -589,8 +600,8 @@ int orc_lattice_step(int nx, int ny, int nz, int nb, const int* wall, const uint
 }
 
 /* Eq. "macroscopic" on every fluid cell; solid cells report rho = 0, u = 0. */
-void orc_lattice_moments(int nx, int ny, int nz, int nb, const uint8_t* solid, const double* force,
-                         const double* f, double* rho, double* u)
+void orc_lattice_moments(int nx, int ny, int nz, int nb, const uint8_t* solid, const real* force,
+                         const real* f, real* rho, real* u)
 {
     grid_t g;
     make_grid(&g, nx, ny, nz, nb, NULL, solid, force);
@@ -602,7 +613,7 @@ void orc_lattice_moments(int nx, int ny, int nz, int nb, const uint8_t* solid, c
             u[n] = u[N + n] = u[2 * N + n] = 0.0;
             continue;
         }
-        double fc[Q], F[3], r, uu[3];
+        real fc[Q], F[3], r, uu[3];
         for (int i = 0; i < Q; ++i) fc[i] = f[i * N + n];
         cell_force(&g, n, F);
         orc_macroscopic(fc, F, &r, uu);
@@ -611,6 +622,29 @@ void orc_lattice_moments(int nx, int ny, int nz, int nb, const uint8_t* solid, c
         u[N + n] = uu[1];
         u[2 * N + n] = uu[2];
     }
+}
+
+/* Collide n independent cells (sampled checks): f, out are [27][n], F is
+ * [3][n] or NULL.  variant 0 = closed form, 1 = literal. */
+int orc_collide_cells(long n, const real* f, const real* F, real omega, int variant, real* out)
+{
+    int status = 0;
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < n; ++c) {
+        real fc[Q], fs[Q], Fc[3];
+        for (int i = 0; i < Q; ++i) fc[i] = f[i * n + c];
+        for (int a = 0; a < 3; ++a) Fc[a] = F ? F[a * n + c] : 0.0;
+        if (variant == 1) {
+            if (orc_collide_literal(fc, Fc, omega, fs) != 0) {
+#pragma omp atomic write
+                status = -1;
+            }
+        } else {
+            orc_collide_closed(fc, Fc, omega, fs);
+        }
+        for (int i = 0; i < Q; ++i) out[i * n + c] = fs[i];
+    }
+    return status;
 }
 
 int orc_num_threads(void)
