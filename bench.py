@@ -1,0 +1,193 @@
+"""Benchmark of the fused D3Q27 CM-LBM step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp16]
+
+Headline workload: 3D Taylor-Green vortex, 256^3 periodic, FP32 populations,
+u0 = 0.05, Re = 1600, zero force.  A step is one pass of the whole hot path
+(one fused pull-stream + collide launch over every cell).  Prints one JSON line:
+value = GLUPS (10^9 lattice-cell updates per second) of the timed K steps,
+plus the HBM roofline of the step kernel, the FP16-storage variant at 512^3,
+and the FP64 CPU oracle timed on the host cores on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+BYTES_PER_CELL = {"fp64": 432, "fp32": 216, "fp16": 108, "bf16": 108}  # 27 reads + 27 writes
+STEP_KERNEL = {"fp32": "k_step<1, false, false>", "fp16": "k_step<2, false, false>",
+               "bf16": "k_step<3, false, false>", "fp64": "k_step<0, false, false>"}
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_step_tgv256_fp32_counters.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1905_10182_amd", "csrc", f) for f in ("cmlbm.hip", "d3q27.hpp")]
+
+
+def source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None if there is none or the kernel sources changed since it was taken."""
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    text = open(COUNTERS_FILE).read()
+    m = re.search(r"source_digest:\s*([0-9a-f]+)", text)
+    t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not t or m.group(1) != source_digest():
+        return None
+    return float(t.group(1))
+
+
+def time_steps(lat, steps, warmup):
+    import torch
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    lat.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / 1e3, wall
+
+
+def run_gpu(n, storage, steps, warmup):
+    import workloads
+    from paper_1905_10182_amd import Lattice
+
+    wl = workloads.taylor_green(n, seed=1)
+    lat = Lattice(n, n, n, tau=wl["tau"], storage=storage, device="cuda:0")
+    lat.init(wl["rho"], wl["u"])
+    del wl
+    r0 = lat.reduce()
+    secs, wall = time_steps(lat, steps, warmup)
+    r1 = lat.reduce()
+    ncell = n ** 3
+    mass_drift = abs(r1[0, 0] / r0[0, 0] - 1)
+    assert r1[0, 6] == 0, "non-finite state"
+    lat.close()
+    return dict(secs=secs, wall=wall, glups=ncell * steps / secs / 1e9, ms_per_step=secs / steps * 1e3,
+                launch_s=secs / steps, bytes_per_launch=BYTES_PER_CELL[storage] * ncell, mass_drift=mass_drift,
+                umax=float(r1[0, 5]))
+
+
+def copy_bandwidth():
+    import torch
+    n = 1 << 30  # 4 GiB of float32
+    a = torch.empty(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    reps = 10
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * 4 * n * reps / s / 1e9
+
+
+def cpu_baseline():
+    """The FP64 oracle (closed-form route, OpenMP) on a bounded sample of the
+    same workload: Taylor-Green 128^3, 24 steps."""
+    import oracle
+    import workloads
+
+    n, steps = 128, 24
+    wl = workloads.taylor_green(n, seed=1)
+    L = oracle.Lattice(n, n, n, tau=wl["tau"])
+    L.init(wl["rho"], wl["u"])
+    L.step(1)
+    t0 = time.perf_counter()
+    L.step(steps)
+    s = time.perf_counter() - t0
+    return {"value": n ** 3 * steps / s / 1e9, "unit": "GLUPS", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"taylor_green {n}^3 fp64, {steps} steps ({s:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp16", action="store_true")
+    ap.add_argument("--n", type=int, default=256)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the solver here is single-GPU "
+              "(multi-GPU z-slab sharding is described in DESIGN.md, not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "no GPU"
+    print(f"[bench] TGV {args.n}^3 fp32: {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr,
+          flush=True)
+    main_run = run_gpu(args.n, "fp32", args.steps, args.warmup)
+    print(f"[bench] fp32 {main_run['glups']:.2f} GLUPS", file=sys.stderr, flush=True)
+    extra = {}
+    if not args.no_fp16:
+        n16 = 512 if args.n == 256 else args.n
+        print(f"[bench] TGV {n16}^3 fp16 storage", file=sys.stderr, flush=True)
+        r16 = run_gpu(n16, "fp16", max(args.steps // 4, 10), max(args.warmup // 4, 5))
+        extra["fp16_storage"] = {
+            "workload": f"taylor_green_{n16} fp16-stored shifted populations, fp32 compute",
+            "glups": round(r16["glups"], 3), "ms_per_step": round(r16["ms_per_step"], 4),
+            "hbm_gbs": round(r16["bytes_per_launch"] / r16["launch_s"] / 1e9, 1),
+            "hbm_frac": round(r16["bytes_per_launch"] / r16["launch_s"] / 1e9 / HBM_PEAK_GBS, 4),
+            "speedup_vs_fp32_glups": round(r16["glups"] / main_run["glups"], 3)}
+        print(f"[bench] fp16 {r16['glups']:.2f} GLUPS", file=sys.stderr, flush=True)
+    extra["device_copy_gbs"] = round(copy_bandwidth(), 1)
+    achieved = main_run["bytes_per_launch"] / main_run["launch_s"] / 1e9
+    traffic = measured_traffic()
+    cpu = None
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline()
+    out = {
+        "metric": "D3Q27 CM-LBM GLUPS & %HBM peak, FP32 vs FP16-store; warm-start speedup",
+        "value": round(main_run["glups"], 4),
+        "unit": "GLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_run["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"taylor_green_{args.n} periodic, fp32 populations, u0=0.05, Re=1600, "
+                               f"zero force, seeded 1e-6 density noise", "cells": args.n ** 3,
+                   "tau": round(3 * 0.05 * args.n / (2 * math.pi * 1600) + 0.5, 6)},
+        "roofline": {"bound": "hbm", "kernel": STEP_KERNEL["fp32"], "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "bytes_per_cell": BYTES_PER_CELL["fp32"]},
+        "cpu_baseline": cpu,
+        "mass_drift": main_run["mass_drift"],
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

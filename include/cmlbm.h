@@ -1,0 +1,194 @@
+/*
+ * cmlbm.h -- C ABI of the MI355X (gfx950) D3Q27 central-moment lattice
+ * Boltzmann solver with Hermite-expanded external forcing.
+ *
+ * Method: De Rosis, Huang & Coreixas, "Three-dimensional central-moments-based
+ * lattice Boltzmann method with external forcing", Phys. Rev. E (2019),
+ * arXiv:1905.10182, Sec. II.  One time step is the five-step algorithm that
+ * closes Sec. II: macroscopic variables with the half-force correction
+ * (eq. "macroscopic"), the five pre-collision central moments
+ * (eq. "pre_collision"), the nineteen non-zero post-collision central moments
+ * (eq. "post_collision_central_moments_forcing"), reconstruction of the
+ * post-collision populations (eq. "system"), and streaming (eq. "streaming").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns int: CMLBM_OK (0) or a negative CMLBM_E* code.
+ *   No C++ exception crosses this boundary.  After an error the handle keeps
+ *   a message readable with cmlbm_last_error().
+ * - Cells: N = nbatch * nz * ny * nx.  Caller-visible per-cell arrays are
+ *   x-fastest, [nbatch][nz][ny][nx]; vector fields are [3][N] (component
+ *   slowest).  Population arrays are [27][N] in the velocity order of Sec. II.
+ * - "dev" pointers are HIP device pointers, "host" pointers are host memory.
+ * - Ownership: the two population buffers and the scratch buffer are
+ *   allocated by the caller (sizes from cmlbm_required_bytes, 256-byte aligned)
+ *   and borrowed for the life of the handle; the handle owns only host state.
+ *   Output arrays are caller-owned.  A force field passed to cmlbm_set_force is
+ *   borrowed until the next cmlbm_set_force or cmlbm_destroy.
+ * - Streams: every device operation is enqueued on the hipStream_t passed as
+ *   `hip_stream` (NULL = the null stream) and returns without waiting, except
+ *   cmlbm_reduce, which waits for its own result.
+ * - Not thread-safe per handle; distinct handles are independent.
+ * - Storage: populations are stored shifted, s_i = f_i - w_i * rho0, in the
+ *   storage type; all arithmetic is FP32 for FP32/FP16/BF16 storage and FP64
+ *   for FP64 storage.  16-bit conversions round to nearest even.
+ * - Time: after cmlbm_init the state is the pre-collision f(x, 0); each step
+ *   advances t by one.  Moments at time t use the force in effect.
+ * - Walls: halfway bounce-back at rest on every axis flagged
+ *   CMLBM_BOUNCEBACK and around solid nodes; a population that would leave
+ *   through a wall or into a solid node returns to its node with the opposite
+ *   velocity.  (The paper only names no-slip walls; this is the reading used.)
+ */
+#ifndef CMLBM_H
+#define CMLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define CMLBM_OK 0
+#define CMLBM_EINVAL (-1)    /* invalid argument; nothing was enqueued */
+#define CMLBM_ENOMEM (-2)    /* a caller buffer is too small */
+#define CMLBM_EHIP (-3)      /* a HIP runtime call or kernel launch failed */
+#define CMLBM_EUNSTABLE (-4) /* cmlbm_reduce saw a non-finite rho or u */
+#define CMLBM_ESTATE (-5)    /* call not valid in the handle's state */
+
+/* population storage types */
+#define CMLBM_FP64 0
+#define CMLBM_FP32 1
+#define CMLBM_FP16 2
+#define CMLBM_BF16 3
+
+/* per-axis boundary kinds */
+#define CMLBM_PERIODIC 0
+#define CMLBM_BOUNCEBACK 1
+
+/* force modes of cmlbm_set_force */
+#define CMLBM_FORCE_NONE 0      /* F = 0 */
+#define CMLBM_FORCE_UNIFORM 1   /* host_values[3]: one force density for every cell */
+#define CMLBM_FORCE_BATCH 2     /* host_values[nbatch][3]: one force density per batch member */
+#define CMLBM_FORCE_PROFILE_Y 3 /* host_values[ny][3]: force density depends on y only */
+#define CMLBM_FORCE_FIELD 4     /* dev_field[3][N]: per-cell force density (borrowed) */
+
+/* cmlbm_params.flags */
+#define CMLBM_FLAG_SOLID 1u    /* reserve room for a solid-node mask (cmlbm_set_solid) */
+#define CMLBM_FLAG_RESIDUAL 2u /* reserve room for the velocity snapshot of the residual */
+
+/* cmlbm_reduce: `what` bits and the layout of one row of its output */
+#define CMLBM_REDUCE_RESIDUAL 1u /* compare u with the last snapshot */
+#define CMLBM_REDUCE_SNAPSHOT 2u /* store u as the new snapshot (after the comparison) */
+#define CMLBM_RED_MASS 0         /* sum of rho over fluid cells */
+#define CMLBM_RED_MOMX 1         /* sum over fluid cells of sum_i f_i c_i (no half-force term), x */
+#define CMLBM_RED_MOMY 2
+#define CMLBM_RED_MOMZ 3
+#define CMLBM_RED_KE 4        /* sum of rho |u|^2 / 2, u half-force corrected */
+#define CMLBM_RED_UMAX 5      /* max |u| */
+#define CMLBM_RED_NONFINITE 6 /* number of fluid cells with a non-finite rho or u */
+#define CMLBM_RED_FLUID 7     /* number of fluid cells */
+#define CMLBM_RED_DU2 8       /* sum |u - u_snapshot|^2 (0 unless RESIDUAL) */
+#define CMLBM_RED_U2 9        /* sum |u|^2 */
+#define CMLBM_RED_RESIDUAL 10 /* sqrt(DU2 / U2) (0 unless RESIDUAL) */
+#define CMLBM_NRED 11
+
+typedef struct cmlbm_lattice cmlbm_lattice; /* opaque handle */
+
+typedef struct {
+    int32_t nx, ny, nz; /* lattice extent, each >= 1 (x is the fastest axis) */
+    int32_t nbatch;     /* independent lattices advanced together, >= 1 */
+    double tau;         /* relaxation time, > 1/2; omega = 1/tau, nu = (tau - 1/2)/3 (text after
+                           eq. "macroscopic") */
+    double rho0;        /* reference density of the storage shift and of rho = NULL in init, > 0 */
+    int32_t storage;    /* CMLBM_FP64 | CMLBM_FP32 | CMLBM_FP16 | CMLBM_BF16 */
+    int32_t wall[3];    /* x, y, z: CMLBM_PERIODIC or CMLBM_BOUNCEBACK */
+    uint32_t flags;     /* CMLBM_FLAG_* */
+} cmlbm_params;
+
+/* Bytes the caller must provide for each of the two population buffers and for
+ * the scratch buffer.  Pure host computation.  EINVAL on invalid params. */
+int cmlbm_required_bytes(const cmlbm_params* params, size_t* pop_buffer_bytes, size_t* scratch_bytes);
+
+/* Create a handle over caller-allocated device buffers (borrowed; each must be
+ * 256-byte aligned and at least cmlbm_required_bytes large -- the sizes given
+ * are checked).  Host-only: validates and records; enqueues nothing.  The
+ * state is undefined until cmlbm_init or cmlbm_load_populations. */
+int cmlbm_create(const cmlbm_params* params, void* pop_a, size_t pop_a_bytes, void* pop_b,
+                 size_t pop_b_bytes, void* scratch, size_t scratch_bytes, cmlbm_lattice** out);
+
+/* Mark solid nodes: dev_solid[N] (uint8, nonzero = solid) is read on the
+ * stream and folded, together with the walls, into the handle's link mask.
+ * Needs CMLBM_FLAG_SOLID.  NULL clears all solid nodes.  Call before
+ * cmlbm_init / cmlbm_load_populations; changing geometry afterwards makes the
+ * state undefined until the next init.  Solid nodes are not updated and
+ * report rho = rho0, u = 0. */
+int cmlbm_set_solid(cmlbm_lattice* lat, const uint8_t* dev_solid, void* hip_stream);
+
+/* Set the external force density F (eq. "macroscopic", eq. "forcing" with F a
+ * force density).  Table modes copy host_values on the stream; FIELD borrows
+ * dev_field[3][N] of io_dtype, which must be CMLBM_FP64 for FP64 storage and
+ * CMLBM_FP32 otherwise.  Takes effect for subsequent steps and moments. */
+int cmlbm_set_force(cmlbm_lattice* lat, int mode, const double* host_values, const void* dev_field,
+                    int io_dtype, void* hip_stream);
+
+/* Initialise f(x, 0) = f^eq(rho(x), u(x)), the complete 27-Hermite
+ * equilibrium of eq. "eq:truncation".  dev_rho[N] (NULL = rho0) and
+ * dev_u[3][N] (NULL = 0) are of io_dtype CMLBM_FP64 or CMLBM_FP32.
+ * Resets the step counter to 0. */
+int cmlbm_init(cmlbm_lattice* lat, const void* dev_rho, const void* dev_u, int io_dtype, void* hip_stream);
+
+/* Advance nsteps >= 0 time steps: each step is one fused launch doing the
+ * pull-streaming gather (eq. "streaming"), collision in central-moment space
+ * (eqs. "macroscopic", "pre_collision",
+ * "post_collision_central_moments_forcing", "system") and the store. */
+int cmlbm_step(cmlbm_lattice* lat, int32_t nsteps, void* hip_stream);
+
+/* rho(x, t) into dev_rho[N] and u(x, t) = (sum f c + F/2)/rho into dev_u[3][N]
+ * (either may be NULL), io_dtype CMLBM_FP64 or CMLBM_FP32. */
+int cmlbm_moments(cmlbm_lattice* lat, void* dev_rho, void* dev_u, int io_dtype, void* hip_stream);
+
+/* FP64 reductions over fluid cells, one row of CMLBM_NRED doubles per batch
+ * member into host_out[nbatch][CMLBM_NRED] (layout CMLBM_RED_*).  The sums
+ * use a fixed order, so results are bitwise reproducible.  RESIDUAL and
+ * SNAPSHOT need CMLBM_FLAG_RESIDUAL; RESIDUAL without a prior snapshot is
+ * ESTATE.  Waits for the stream.  Returns CMLBM_EUNSTABLE (output still
+ * filled) if any fluid cell has a non-finite rho or u. */
+int cmlbm_reduce(cmlbm_lattice* lat, uint32_t what, double* host_out, void* hip_stream);
+
+/* Export the pre-collision populations f_i(x, t) (unshifted, FP64) into
+ * dev_out[27][N], paper order.  Solid cells are written as 0. */
+int cmlbm_populations(cmlbm_lattice* lat, double* dev_out, void* hip_stream);
+
+/* Import pre-collision populations dev_in[27][N] (FP64, unshifted, paper
+ * order) as the state at the current step counter (checkpoint restore). */
+int cmlbm_load_populations(cmlbm_lattice* lat, const double* dev_in, void* hip_stream);
+
+/* Bitwise checkpoint: copy the state exactly as stored (shifted populations in
+ * the storage type, internal padded layout; pop_buffer_bytes of
+ * cmlbm_required_bytes) into dev_blob.  The blob is opaque and restores only
+ * into a handle created with identical params.  Save the step counter with
+ * cmlbm_get_time.  ENOMEM if blob_bytes is too small. */
+int cmlbm_save_state(cmlbm_lattice* lat, void* dev_blob, size_t blob_bytes, void* hip_stream);
+/* Restore a blob written by cmlbm_save_state as the current state (the step
+ * counter is left unchanged; set it with cmlbm_set_time). */
+int cmlbm_restore_state(cmlbm_lattice* lat, const void* dev_blob, size_t blob_bytes, void* hip_stream);
+
+/* Step counter (number of steps since init). */
+int cmlbm_get_time(const cmlbm_lattice* lat, int64_t* t);
+/* Set the step counter (checkpoint restore). */
+int cmlbm_set_time(cmlbm_lattice* lat, int64_t t);
+
+/* Release the handle (the borrowed buffers are untouched).  NULL is OK. */
+int cmlbm_destroy(cmlbm_lattice* lat);
+
+/* Message of the last error on this handle ("" if none); never NULL. */
+const char* cmlbm_last_error(const cmlbm_lattice* lat);
+/* Static name of a status code. */
+const char* cmlbm_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CMLBM_H */

@@ -1,0 +1,1062 @@
+// libcmlbm: MI355X (gfx950) D3Q27 central-moment lattice Boltzmann solver with
+// Hermite-expanded external forcing (De Rosis, Huang & Coreixas, PRE 2019,
+// Sec. II).  C ABI in include/cmlbm.h.
+//
+// Kernels
+//   k_step       fused pull-stream gather + collision + store (the hot path)
+//   k_init       inverse of the gather: writes a given pre-collision state
+//   k_gather     rho/u or FP64 populations from the current state
+//   k_reduce     per-block FP64 partial sums; k_reduce_final finishes them
+//   k_linkmask   per-cell 27-bit bounce-back mask from walls and solid nodes
+//   k_fill       plain fill (used instead of memset so work stays in kernels)
+//
+// Memory layout in HBM (structure of arrays): population plane i holds one
+// value per cell, rows of nxp elements (nx rounded up to 256 bytes), cells
+// ordered [nbatch][nz][ny][nxp]; two such buffers alternate between steps.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "cmlbm.h"
+#include "d3q27.hpp"
+
+using namespace cmlbm;
+
+namespace {
+
+constexpr int kBlock = 256;   // threads per workgroup of every kernel
+constexpr int kNPart = 10;    // partial-sum slots of k_reduce
+constexpr int kMaxRedBlocks = 256;  // reduce workgroups per batch member
+constexpr uint32_t kSolidBit = 1u << 27;
+
+// ---------------------------------------------------------------------------
+// storage types
+
+template <int ST>
+struct storage;
+template <>
+struct storage<CMLBM_FP64> {
+    typedef double S;
+    typedef double T;
+    static __device__ __forceinline__ T load(const S* p) { return *p; }
+    static __device__ __forceinline__ S pack(T v) { return v; }
+};
+template <>
+struct storage<CMLBM_FP32> {
+    typedef float S;
+    typedef float T;
+    static __device__ __forceinline__ T load(const S* p) { return *p; }
+    static __device__ __forceinline__ S pack(T v) { return v; }
+};
+template <>
+struct storage<CMLBM_FP16> {
+    typedef _Float16 S;
+    typedef float T;
+    static __device__ __forceinline__ T load(const S* p) { return (float)*p; }
+    static __device__ __forceinline__ S pack(T v) { return (_Float16)v; }  // round to nearest even
+};
+template <>
+struct storage<CMLBM_BF16> {
+    typedef __bf16 S;
+    typedef float T;
+    static __device__ __forceinline__ T load(const S* p) { return (float)*p; }
+    static __device__ __forceinline__ S pack(T v) { return (__bf16)v; }  // round to nearest even
+};
+
+size_t storage_bytes(int st) { return st == CMLBM_FP64 ? 8 : st == CMLBM_FP32 ? 4 : 2; }
+
+// ---------------------------------------------------------------------------
+// geometry passed to every kernel
+
+struct Geom {
+    int nx, ny, nz, nb;
+    int nxp;           // padded row length (elements)
+    int rows;          // ny * nz * nb
+    int xblocks;       // workgroups along x per row group
+    int bx, by;        // workgroup shape: bx threads along x (multiple of 64), by rows
+    uint64_t pstride;  // elements per population plane
+    uint64_t ncell;    // nb * nz * ny * nx (unpadded)
+};
+
+struct Cell {
+    int x, y, z, b;
+    bool valid;
+    uint32_t own;     // padded index within a plane
+    uint64_t lin;     // unpadded linear index
+};
+
+// Cell of this thread.  Each wave lies within one row (bx is a multiple of 64),
+// so y, z, b are wave-uniform and live in scalar registers.
+__device__ __forceinline__ Cell locate(const Geom& g)
+{
+    Cell c;
+    const int blk = blockIdx.x;
+    const int xb = blk % g.xblocks;
+    const int rb = blk / g.xblocks;
+    int row = rb * g.by + (int)threadIdx.y;
+    row = __builtin_amdgcn_readfirstlane(row);
+    c.x = xb * g.bx + (int)threadIdx.x;
+    c.valid = row < g.rows && c.x < g.nx;
+    const int y = row % g.ny;
+    const int zb = row / g.ny;
+    c.y = y;
+    c.z = zb % g.nz;
+    c.b = zb / g.nz;
+    c.own = (uint32_t)row * (uint32_t)g.nxp + (uint32_t)c.x;
+    c.lin = (uint64_t)row * (uint64_t)g.nx + (uint64_t)c.x;
+    return c;
+}
+
+__device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Source offsets (within a population plane) of the pull gather for the 27
+// directions: direction i reads cell x - c_i with periodic wrap.
+struct Pull {
+    uint32_t rowoff[3][3];  // [cy+1][cz+1] offset of the source row (wave-uniform)
+    uint32_t xs[3];         // [cx+1] source x
+};
+
+__device__ __forceinline__ Pull make_pull(const Geom& g, const Cell& c)
+{
+    Pull p;
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int ys = wrap(c.y - (b - 1), g.ny);
+            const int zs = wrap(c.z - (d - 1), g.nz);
+            p.rowoff[b][d] = (uint32_t)(((c.b * g.nz + zs) * g.ny + ys) * g.nxp);
+        }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) p.xs[a] = (uint32_t)wrap(c.x - (a - 1), g.nx);
+    return p;
+}
+
+// Gather the 27 shifted pre-collision populations of one cell.
+template <int ST, bool MASK>
+__device__ __forceinline__ void gather(const typename storage<ST>::S* __restrict__ src, const Geom& g,
+                                       const Cell& c, uint32_t m, typename storage<ST>::T h[27])
+{
+    using SS = storage<ST>;
+    const Pull p = make_pull(g, c);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const uint32_t off = p.rowoff[vel_y(i) + 1][vel_z(i) + 1] + p.xs[vel_x(i) + 1];
+        if (MASK) {
+            const bool bounce = (m >> i) & 1u;
+            const uint64_t e = bounce ? (uint64_t)opposite(i) * g.pstride + c.own : (uint64_t)i * g.pstride + off;
+            h[i] = SS::load(src + e);
+        } else {
+            const typename SS::S* plane = src + (uint64_t)i * g.pstride;
+            h[i] = SS::load(plane + off);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the hot path: one time step
+
+template <int ST, bool MASK, bool FIELD>
+__global__ __launch_bounds__(kBlock) void k_step(const typename storage<ST>::S* __restrict__ src,
+                                                 typename storage<ST>::S* __restrict__ dst, Geom g,
+                                                 typename storage<ST>::T omega, typename storage<ST>::T rho0,
+                                                 const typename storage<ST>::T* __restrict__ ftab,
+                                                 const typename storage<ST>::T* __restrict__ field,
+                                                 const uint32_t* __restrict__ mask)
+{
+    using SS = storage<ST>;
+    using T = typename SS::T;
+    const Cell c = locate(g);
+    if (!c.valid) return;
+    uint32_t m = 0;
+    if (MASK) {
+        m = mask[c.own];
+        if (m & kSolidBit) return;
+    }
+    T h[27];
+    gather<ST, MASK>(src, g, c, m, h);
+    T Fx, Fy, Fz;
+    if (FIELD) {
+        Fx = field[c.lin];
+        Fy = field[g.ncell + c.lin];
+        Fz = field[2 * g.ncell + c.lin];
+    } else {
+        const T* fr = ftab + 3 * (c.b * g.ny + c.y);
+        Fx = fr[0];
+        Fy = fr[1];
+        Fz = fr[2];
+    }
+    T rho, ux, uy, uz;
+    collide<T>(h, Fx, Fy, Fz, omega, rho0, rho, ux, uy, uz);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) dst[(uint64_t)i * g.pstride + c.own] = SS::pack(h[i]);
+}
+
+// ---------------------------------------------------------------------------
+// initialisation: scatter a pre-collision state through the inverse gather
+
+enum InitSrc { INIT_EQ_F64 = 0, INIT_EQ_F32 = 1, INIT_POPS_F64 = 2 };
+
+template <int ST, bool MASK, int SRC>
+__global__ __launch_bounds__(kBlock) void k_init(typename storage<ST>::S* __restrict__ dst, Geom g, double rho0,
+                                                 const void* __restrict__ rho_in, const void* __restrict__ u_in,
+                                                 const double* __restrict__ pops, const uint32_t* __restrict__ mask)
+{
+    using SS = storage<ST>;
+    using T = typename SS::T;
+    const Cell c = locate(g);
+    if (!c.valid) return;
+    uint32_t m = 0;
+    if (MASK) {
+        m = mask[c.own];
+        if (m & kSolidBit) return;
+    }
+    T e[27];
+    if (SRC == INIT_POPS_F64) {
+#pragma unroll
+        for (int i = 0; i < 27; ++i) e[i] = (T)(pops[(uint64_t)i * g.ncell + c.lin] - weight(i) * rho0);
+    } else {
+        // complete 27-Hermite equilibrium (eq. "eq:truncation"); it factors over
+        // the axes as w_i rho prod_a (1 + c_a u_a / cs^2 + (c_a^2 - cs^2) u_a^2 / (2 cs^4)),
+        // evaluated here as w_i [drho P_i + rho0 (P_i - 1)] to keep the deviation small.
+        T drho, u[3];
+        if (SRC == INIT_EQ_F64) {
+            const double* R = (const double*)rho_in;
+            const double* U = (const double*)u_in;
+            drho = R ? (T)(R[c.lin] - rho0) : T(0);
+            for (int a = 0; a < 3; ++a) u[a] = U ? (T)U[a * g.ncell + c.lin] : T(0);
+        } else {
+            const float* R = (const float*)rho_in;
+            const float* U = (const float*)u_in;
+            drho = R ? (T)((double)R[c.lin] - rho0) : T(0);
+            for (int a = 0; a < 3; ++a) u[a] = U ? (T)U[a * g.ncell + c.lin] : T(0);
+        }
+        T am[3][3];  // am[axis][c+1] = P_axis(c) - 1
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const T uu = u[a];
+            am[a][0] = T(-3) * uu + T(3) * uu * uu;
+            am[a][1] = T(-1.5) * uu * uu;
+            am[a][2] = T(3) * uu + T(3) * uu * uu;
+        }
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            const T ax = am[0][vel_x(i) + 1], ay = am[1][vel_y(i) + 1], az = am[2][vel_z(i) + 1];
+            const T pm1 = ax + ay + az + ax * ay + ax * az + ay * az + ax * ay * az;
+            e[i] = (T)weight(i) * (drho * (T(1) + pm1) + (T)rho0 * pm1);
+        }
+    }
+    const Pull p = make_pull(g, c);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const uint32_t off = p.rowoff[vel_y(i) + 1][vel_z(i) + 1] + p.xs[vel_x(i) + 1];
+        const bool bounce = MASK && ((m >> i) & 1u);
+        const uint64_t d = bounce ? (uint64_t)opposite(i) * g.pstride + c.own : (uint64_t)i * g.pstride + off;
+        dst[d] = SS::pack(e[i]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// diagnostics: gather in FP64
+
+template <int ST, bool MASK>
+__device__ __forceinline__ bool gather_f64(const typename storage<ST>::S* __restrict__ src, const Geom& g,
+                                           const Cell& c, const uint32_t* __restrict__ mask, double h[27])
+{
+    using SS = storage<ST>;
+    uint32_t m = 0;
+    if (MASK) {
+        m = mask[c.own];
+        if (m & kSolidBit) return false;
+    }
+    typename SS::T t[27];
+    gather<ST, MASK>(src, g, c, m, t);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) h[i] = (double)t[i];
+    return true;
+}
+
+__device__ __forceinline__ void cell_force64(const Geom& g, const Cell& c, const double* ftab, const void* field,
+                                             int field_f64, double F[3])
+{
+    if (field) {
+        for (int a = 0; a < 3; ++a)
+            F[a] = field_f64 ? ((const double*)field)[a * g.ncell + c.lin]
+                             : (double)((const float*)field)[a * g.ncell + c.lin];
+    } else {
+        const double* fr = ftab + 3 * (c.b * g.ny + c.y);
+        F[0] = fr[0];
+        F[1] = fr[1];
+        F[2] = fr[2];
+    }
+}
+
+__device__ __forceinline__ void macro64(const double h[27], double rho0, const double F[3], double& rho, double u[3],
+                                        double j[3], double& drho)
+{
+    double s = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        s += h[i];
+        jx += vel_x(i) * h[i];
+        jy += vel_y(i) * h[i];
+        jz += vel_z(i) * h[i];
+    }
+    drho = s;
+    rho = rho0 + s;
+    j[0] = jx;
+    j[1] = jy;
+    j[2] = jz;
+    u[0] = (jx + 0.5 * F[0]) / rho;
+    u[1] = (jy + 0.5 * F[1]) / rho;
+    u[2] = (jz + 0.5 * F[2]) / rho;
+}
+
+// rho/u (io FP64 or FP32) or FP64 populations of the current state
+template <int ST, bool MASK>
+__global__ __launch_bounds__(kBlock) void k_gather(const typename storage<ST>::S* __restrict__ src, Geom g,
+                                                   double rho0, const double* __restrict__ ftab,
+                                                   const void* __restrict__ field, int field_f64,
+                                                   const uint32_t* __restrict__ mask, void* rho_out, void* u_out,
+                                                   int out_f64, double* pops_out)
+{
+    const Cell c = locate(g);
+    if (!c.valid) return;
+    double h[27];
+    const bool fluid = gather_f64<ST, MASK>(src, g, c, mask, h);
+    if (pops_out) {
+#pragma unroll
+        for (int i = 0; i < 27; ++i) pops_out[(uint64_t)i * g.ncell + c.lin] = fluid ? h[i] + weight(i) * rho0 : 0.0;
+    }
+    if (!rho_out && !u_out) return;
+    double rho = rho0, u[3] = {0, 0, 0};
+    if (fluid) {
+        double F[3], j[3], drho;
+        cell_force64(g, c, ftab, field, field_f64, F);
+        macro64(h, rho0, F, rho, u, j, drho);
+    }
+    if (out_f64) {
+        if (rho_out) ((double*)rho_out)[c.lin] = rho;
+        if (u_out)
+            for (int a = 0; a < 3; ++a) ((double*)u_out)[a * g.ncell + c.lin] = u[a];
+    } else {
+        if (rho_out) ((float*)rho_out)[c.lin] = (float)rho;
+        if (u_out)
+            for (int a = 0; a < 3; ++a) ((float*)u_out)[a * g.ncell + c.lin] = (float)u[a];
+    }
+}
+
+// FP64 reductions.  Each batch member is split into `gpb` workgroups that
+// stride over its cells; every workgroup writes kNPart partial values, summed
+// in a fixed tree order, so results are reproducible bit for bit.
+template <int ST, bool MASK>
+__global__ __launch_bounds__(kBlock) void k_reduce(const typename storage<ST>::S* __restrict__ src, Geom g,
+                                                   double rho0, const double* __restrict__ ftab,
+                                                   const void* __restrict__ field, int field_f64,
+                                                   const uint32_t* __restrict__ mask, int gpb, int residual,
+                                                   int snapshot, double* __restrict__ snap, double* __restrict__ part)
+{
+    __shared__ double sh[kNPart][kBlock];
+    const int b = blockIdx.x / gpb;
+    const int gblk = blockIdx.x % gpb;
+    const int tid = threadIdx.x;
+    const uint64_t per = (uint64_t)g.nz * g.ny * g.nx;
+    double acc[kNPart];
+    for (int k = 0; k < kNPart; ++k) acc[k] = 0.0;
+    for (uint64_t k = (uint64_t)gblk * kBlock + tid; k < per; k += (uint64_t)gpb * kBlock) {
+        const int x = (int)(k % g.nx);
+        const uint64_t r = k / g.nx;
+        Cell c;
+        c.x = x;
+        c.y = (int)(r % g.ny);
+        c.z = (int)(r / g.ny);
+        c.b = b;
+        const int row = (b * g.nz + c.z) * g.ny + c.y;
+        c.own = (uint32_t)row * (uint32_t)g.nxp + (uint32_t)x;
+        c.lin = (uint64_t)row * g.nx + x;
+        c.valid = true;
+        double h[27];
+        if (!gather_f64<ST, MASK>(src, g, c, mask, h)) continue;
+        double F[3], rho, u[3], j[3], drho;
+        cell_force64(g, c, ftab, field, field_f64, F);
+        macro64(h, rho0, F, rho, u, j, drho);
+        const double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        const bool finite = isfinite(rho) && isfinite(u2);
+        acc[7] += 1.0;
+        if (!finite) {
+            acc[6] += 1.0;
+            continue;
+        }
+        acc[0] += drho;
+        acc[1] += j[0];
+        acc[2] += j[1];
+        acc[3] += j[2];
+        acc[4] += 0.5 * rho * u2;
+        acc[5] = fmax(acc[5], sqrt(u2));
+        acc[9] += u2;
+        if (residual) {
+            const double d0 = u[0] - snap[c.lin], d1 = u[1] - snap[g.ncell + c.lin], d2 = u[2] - snap[2 * g.ncell + c.lin];
+            acc[8] += d0 * d0 + d1 * d1 + d2 * d2;
+        }
+        if (snapshot) {
+            snap[c.lin] = u[0];
+            snap[g.ncell + c.lin] = u[1];
+            snap[2 * g.ncell + c.lin] = u[2];
+        }
+    }
+    for (int k = 0; k < kNPart; ++k) sh[k][tid] = acc[k];
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (tid < s)
+            for (int k = 0; k < kNPart; ++k)
+                sh[k][tid] = (k == 5) ? fmax(sh[k][tid], sh[k][tid + s]) : sh[k][tid] + sh[k][tid + s];
+        __syncthreads();
+    }
+    if (tid < kNPart) part[(uint64_t)blockIdx.x * kNPart + tid] = sh[tid][0];
+}
+
+__global__ void k_reduce_final(const double* __restrict__ part, int gpb, double rho0, double* __restrict__ out)
+{
+    const int b = blockIdx.x;
+    const int k = threadIdx.x;
+    if (k >= kNPart) return;
+    double s = 0.0;
+    for (int i = 0; i < gpb; ++i) {
+        const double v = part[((uint64_t)b * gpb + i) * kNPart + k];
+        s = (k == 5) ? fmax(s, v) : s + v;
+    }
+    double* o = out + (uint64_t)b * CMLBM_NRED;
+    switch (k) {
+        case 0: o[CMLBM_RED_MASS] = s; break;  // completed on the host with rho0 * fluid
+        case 1: o[CMLBM_RED_MOMX] = s; break;
+        case 2: o[CMLBM_RED_MOMY] = s; break;
+        case 3: o[CMLBM_RED_MOMZ] = s; break;
+        case 4: o[CMLBM_RED_KE] = s; break;
+        case 5: o[CMLBM_RED_UMAX] = s; break;
+        case 6: o[CMLBM_RED_NONFINITE] = s; break;
+        case 7: o[CMLBM_RED_FLUID] = s; break;
+        case 8: o[CMLBM_RED_DU2] = s; break;
+        case 9: o[CMLBM_RED_U2] = s; break;
+    }
+}
+
+// Per-cell link mask: bit i set if the node x - c_i lies beyond a wall or is
+// solid (the population pulled along c_i then comes from the opposite
+// direction at x itself), bit 27 set if x is solid.
+__global__ __launch_bounds__(kBlock) void k_linkmask(Geom g, int wx, int wy, int wz,
+                                                     const uint8_t* __restrict__ solid, uint32_t* __restrict__ mask)
+{
+    const Cell c = locate(g);
+    if (!c.valid) return;
+    const int dims[3] = {g.nx, g.ny, g.nz};
+    const int walls[3] = {wx, wy, wz};
+    uint32_t m = 0;
+    if (solid && solid[c.lin]) m |= kSolidBit;
+    for (int i = 0; i < 27; ++i) {
+        int s[3] = {c.x - vel_x(i), c.y - vel_y(i), c.z - vel_z(i)};
+        bool bounce = false;
+        for (int a = 0; a < 3; ++a) {
+            if (s[a] < 0 || s[a] >= dims[a]) {
+                if (walls[a]) bounce = true;
+                s[a] = wrap(s[a], dims[a]);
+            }
+        }
+        if (!bounce && solid) {
+            const uint64_t n = ((uint64_t)(c.b * g.nz + s[2]) * g.ny + s[1]) * g.nx + s[0];
+            bounce = solid[n] != 0;
+        }
+        if (bounce) m |= 1u << i;
+    }
+    mask[c.own] = m;
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host side
+
+struct cmlbm_lattice {
+    cmlbm_params p;
+    Geom g;
+    void* pop[2];
+    int cur;  // buffer holding the state
+    uint8_t* scratch;
+    size_t off_ftab64, off_ftab32, off_mask, off_part, off_final, off_snap;
+    int gpb;
+    bool needs_mask, mask_ready, initialized, snap_valid;
+    int force_mode;
+    const void* field;
+    int field_dtype;
+    int64_t t;
+    std::string err;
+};
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Layout {
+    Geom g;
+    size_t pop_bytes, scratch_bytes;
+    size_t off_ftab64, off_ftab32, off_mask, off_part, off_final, off_snap;
+    int gpb;
+    bool needs_mask;
+};
+
+int validate(const cmlbm_params* p)
+{
+    if (!p) return CMLBM_EINVAL;
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1 || p->nbatch < 1) return CMLBM_EINVAL;
+    if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return CMLBM_EINVAL;
+    if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return CMLBM_EINVAL;
+    if (p->storage < CMLBM_FP64 || p->storage > CMLBM_BF16) return CMLBM_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if (p->wall[a] != CMLBM_PERIODIC && p->wall[a] != CMLBM_BOUNCEBACK) return CMLBM_EINVAL;
+    if (p->flags & ~(CMLBM_FLAG_SOLID | CMLBM_FLAG_RESIDUAL)) return CMLBM_EINVAL;
+    // an axis of extent 1 with walls would bounce everything; periodic is required there
+    const int dims[3] = {p->nx, p->ny, p->nz};
+    for (int a = 0; a < 3; ++a)
+        if (p->wall[a] == CMLBM_BOUNCEBACK && dims[a] < 2) return CMLBM_EINVAL;
+    return CMLBM_OK;
+}
+
+int make_layout(const cmlbm_params* p, Layout* L)
+{
+    int rc = validate(p);
+    if (rc) return rc;
+    const size_t sb = storage_bytes(p->storage);
+    const size_t row_bytes = align256((size_t)p->nx * sb);
+    Geom& g = L->g;
+    g.nx = p->nx;
+    g.ny = p->ny;
+    g.nz = p->nz;
+    g.nb = p->nbatch;
+    g.nxp = (int)(row_bytes / sb);
+    const uint64_t rows = (uint64_t)p->ny * p->nz * p->nbatch;
+    if (rows > 0x7fffffffULL) return CMLBM_EINVAL;
+    g.rows = (int)rows;
+    g.pstride = rows * (uint64_t)g.nxp;
+    if (g.pstride >= (1ULL << 32)) return CMLBM_EINVAL;  // per-plane offsets are 32-bit
+    g.ncell = rows * (uint64_t)p->nx;
+    const int nx64 = (p->nx + 63) / 64 * 64;
+    g.bx = nx64 < kBlock ? nx64 : kBlock;
+    g.by = kBlock / g.bx;
+    g.xblocks = (p->nx + g.bx - 1) / g.bx;
+    const uint64_t nblocks = (uint64_t)g.xblocks * ((rows + g.by - 1) / g.by);
+    if (nblocks > 0x7fffffffULL) return CMLBM_EINVAL;
+
+    L->pop_bytes = align256(27 * g.pstride * sb);
+    L->needs_mask = (p->flags & CMLBM_FLAG_SOLID) || p->wall[0] || p->wall[1] || p->wall[2];
+    const uint64_t per = (uint64_t)p->nz * p->ny * p->nx;
+    uint64_t gpb = (per + kBlock - 1) / kBlock;
+    if (gpb > (uint64_t)kMaxRedBlocks) gpb = kMaxRedBlocks;
+    L->gpb = (int)gpb;
+    size_t off = 0;
+    L->off_ftab64 = off;
+    off = align256(off + (size_t)p->nbatch * p->ny * 3 * sizeof(double));
+    L->off_ftab32 = off;
+    off = align256(off + (size_t)p->nbatch * p->ny * 3 * sizeof(float));
+    L->off_mask = off;
+    if (L->needs_mask) off = align256(off + g.pstride * sizeof(uint32_t));
+    L->off_part = off;
+    off = align256(off + (size_t)p->nbatch * gpb * kNPart * sizeof(double));
+    L->off_final = off;
+    off = align256(off + (size_t)p->nbatch * CMLBM_NRED * sizeof(double));
+    L->off_snap = off;
+    if (p->flags & CMLBM_FLAG_RESIDUAL) off = align256(off + 3 * g.ncell * sizeof(double));
+    L->scratch_bytes = off;
+    return CMLBM_OK;
+}
+
+int fail(cmlbm_lattice* lat, int code, const std::string& msg)
+{
+    if (lat) lat->err = msg;
+    return code;
+}
+
+int hip_check(cmlbm_lattice* lat, hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return CMLBM_OK;
+    return fail(lat, CMLBM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int launch_check(cmlbm_lattice* lat, const char* what) { return hip_check(lat, hipGetLastError(), what); }
+
+dim3 grid_of(const Geom& g) { return dim3(g.xblocks * ((g.rows + g.by - 1) / g.by)); }
+dim3 block_of(const Geom& g) { return dim3(g.bx, g.by); }
+
+uint32_t* mask_ptr(cmlbm_lattice* lat) { return lat->needs_mask ? (uint32_t*)(lat->scratch + lat->off_mask) : nullptr; }
+
+int build_mask(cmlbm_lattice* lat, const uint8_t* solid, hipStream_t s)
+{
+    const Geom& g = lat->g;
+    uint32_t* m = mask_ptr(lat);
+    k_fill_u32<<<1024, 256, 0, s>>>(m, g.pstride, kSolidBit);  // padding columns count as solid
+    int rc = launch_check(lat, "link mask clear");
+    if (rc) return rc;
+    k_linkmask<<<grid_of(g), block_of(g), 0, s>>>(g, lat->p.wall[0], lat->p.wall[1], lat->p.wall[2], solid, m);
+    rc = launch_check(lat, "link mask");
+    if (rc) return rc;
+    lat->mask_ready = true;
+    return CMLBM_OK;
+}
+
+int ensure_mask(cmlbm_lattice* lat, hipStream_t s)
+{
+    if (!lat->needs_mask || lat->mask_ready) return CMLBM_OK;
+    return build_mask(lat, nullptr, s);
+}
+
+// ---- kernel dispatch over (storage, mask, field)
+
+template <int ST>
+int launch_step_st(cmlbm_lattice* lat, hipStream_t s)
+{
+    using SS = storage<ST>;
+    using T = typename SS::T;
+    const Geom& g = lat->g;
+    const auto* src = (const typename SS::S*)lat->pop[lat->cur];
+    auto* dst = (typename SS::S*)lat->pop[1 - lat->cur];
+    const T omega = (T)(1.0 / lat->p.tau), rho0 = (T)lat->p.rho0;
+    const T* ftab = (const T*)(lat->scratch + (ST == CMLBM_FP64 ? lat->off_ftab64 : lat->off_ftab32));
+    const T* field = (const T*)lat->field;
+    const uint32_t* m = mask_ptr(lat);
+    const bool F = lat->force_mode == CMLBM_FORCE_FIELD;
+    if (lat->needs_mask) {
+        if (F)
+            k_step<ST, true, true><<<grid_of(g), block_of(g), 0, s>>>(src, dst, g, omega, rho0, ftab, field, m);
+        else
+            k_step<ST, true, false><<<grid_of(g), block_of(g), 0, s>>>(src, dst, g, omega, rho0, ftab, field, m);
+    } else {
+        if (F)
+            k_step<ST, false, true><<<grid_of(g), block_of(g), 0, s>>>(src, dst, g, omega, rho0, ftab, field, m);
+        else
+            k_step<ST, false, false><<<grid_of(g), block_of(g), 0, s>>>(src, dst, g, omega, rho0, ftab, field, m);
+    }
+    return launch_check(lat, "step");
+}
+
+int launch_step(cmlbm_lattice* lat, hipStream_t s)
+{
+    switch (lat->p.storage) {
+        case CMLBM_FP64: return launch_step_st<CMLBM_FP64>(lat, s);
+        case CMLBM_FP32: return launch_step_st<CMLBM_FP32>(lat, s);
+        case CMLBM_FP16: return launch_step_st<CMLBM_FP16>(lat, s);
+        default: return launch_step_st<CMLBM_BF16>(lat, s);
+    }
+}
+
+template <int ST, bool MASK>
+void launch_init_m(cmlbm_lattice* lat, int src_kind, const void* rho, const void* u, const double* pops, hipStream_t s)
+{
+    using SS = storage<ST>;
+    const Geom& g = lat->g;
+    auto* dst = (typename SS::S*)lat->pop[lat->cur];
+    const uint32_t* m = mask_ptr(lat);
+    const double rho0 = lat->p.rho0;
+    if (src_kind == INIT_EQ_F64)
+        k_init<ST, MASK, INIT_EQ_F64><<<grid_of(g), block_of(g), 0, s>>>(dst, g, rho0, rho, u, pops, m);
+    else if (src_kind == INIT_EQ_F32)
+        k_init<ST, MASK, INIT_EQ_F32><<<grid_of(g), block_of(g), 0, s>>>(dst, g, rho0, rho, u, pops, m);
+    else
+        k_init<ST, MASK, INIT_POPS_F64><<<grid_of(g), block_of(g), 0, s>>>(dst, g, rho0, rho, u, pops, m);
+}
+
+template <int ST>
+int launch_init_st(cmlbm_lattice* lat, int src_kind, const void* rho, const void* u, const double* pops,
+                   hipStream_t s)
+{
+    if (lat->needs_mask)
+        launch_init_m<ST, true>(lat, src_kind, rho, u, pops, s);
+    else
+        launch_init_m<ST, false>(lat, src_kind, rho, u, pops, s);
+    return launch_check(lat, "init");
+}
+
+int launch_init(cmlbm_lattice* lat, int src_kind, const void* rho, const void* u, const double* pops, hipStream_t s)
+{
+    switch (lat->p.storage) {
+        case CMLBM_FP64: return launch_init_st<CMLBM_FP64>(lat, src_kind, rho, u, pops, s);
+        case CMLBM_FP32: return launch_init_st<CMLBM_FP32>(lat, src_kind, rho, u, pops, s);
+        case CMLBM_FP16: return launch_init_st<CMLBM_FP16>(lat, src_kind, rho, u, pops, s);
+        default: return launch_init_st<CMLBM_BF16>(lat, src_kind, rho, u, pops, s);
+    }
+}
+
+const double* ftab64(cmlbm_lattice* lat) { return (const double*)(lat->scratch + lat->off_ftab64); }
+const void* field64_or_null(cmlbm_lattice* lat)
+{
+    return lat->force_mode == CMLBM_FORCE_FIELD ? lat->field : nullptr;
+}
+
+template <int ST, bool MASK>
+void launch_gather_m(cmlbm_lattice* lat, void* rho, void* u, int out_f64, double* pops, hipStream_t s)
+{
+    using SS = storage<ST>;
+    const Geom& g = lat->g;
+    k_gather<ST, MASK><<<grid_of(g), block_of(g), 0, s>>>(
+        (const typename SS::S*)lat->pop[lat->cur], g, lat->p.rho0, ftab64(lat), field64_or_null(lat),
+        lat->p.storage == CMLBM_FP64, mask_ptr(lat), rho, u, out_f64, pops);
+}
+
+template <int ST>
+int launch_gather_st(cmlbm_lattice* lat, void* rho, void* u, int out_f64, double* pops, hipStream_t s)
+{
+    if (lat->needs_mask)
+        launch_gather_m<ST, true>(lat, rho, u, out_f64, pops, s);
+    else
+        launch_gather_m<ST, false>(lat, rho, u, out_f64, pops, s);
+    return launch_check(lat, "gather");
+}
+
+int launch_gather(cmlbm_lattice* lat, void* rho, void* u, int out_f64, double* pops, hipStream_t s)
+{
+    switch (lat->p.storage) {
+        case CMLBM_FP64: return launch_gather_st<CMLBM_FP64>(lat, rho, u, out_f64, pops, s);
+        case CMLBM_FP32: return launch_gather_st<CMLBM_FP32>(lat, rho, u, out_f64, pops, s);
+        case CMLBM_FP16: return launch_gather_st<CMLBM_FP16>(lat, rho, u, out_f64, pops, s);
+        default: return launch_gather_st<CMLBM_BF16>(lat, rho, u, out_f64, pops, s);
+    }
+}
+
+template <int ST, bool MASK>
+void launch_reduce_m(cmlbm_lattice* lat, int residual, int snapshot, hipStream_t s)
+{
+    using SS = storage<ST>;
+    const Geom& g = lat->g;
+    double* snap = (lat->p.flags & CMLBM_FLAG_RESIDUAL) ? (double*)(lat->scratch + lat->off_snap) : nullptr;
+    k_reduce<ST, MASK><<<dim3(g.nb * lat->gpb), dim3(kBlock), 0, s>>>(
+        (const typename SS::S*)lat->pop[lat->cur], g, lat->p.rho0, ftab64(lat), field64_or_null(lat),
+        lat->p.storage == CMLBM_FP64, mask_ptr(lat), lat->gpb, residual, snapshot, snap,
+        (double*)(lat->scratch + lat->off_part));
+}
+
+template <int ST>
+void launch_reduce_st(cmlbm_lattice* lat, int residual, int snapshot, hipStream_t s)
+{
+    if (lat->needs_mask)
+        launch_reduce_m<ST, true>(lat, residual, snapshot, s);
+    else
+        launch_reduce_m<ST, false>(lat, residual, snapshot, s);
+}
+
+int launch_reduce(cmlbm_lattice* lat, int residual, int snapshot, hipStream_t s)
+{
+    switch (lat->p.storage) {
+        case CMLBM_FP64: launch_reduce_st<CMLBM_FP64>(lat, residual, snapshot, s); break;
+        case CMLBM_FP32: launch_reduce_st<CMLBM_FP32>(lat, residual, snapshot, s); break;
+        case CMLBM_FP16: launch_reduce_st<CMLBM_FP16>(lat, residual, snapshot, s); break;
+        default: launch_reduce_st<CMLBM_BF16>(lat, residual, snapshot, s); break;
+    }
+    int rc = launch_check(lat, "reduce");
+    if (rc) return rc;
+    k_reduce_final<<<dim3(lat->g.nb), dim3(64), 0, s>>>((const double*)(lat->scratch + lat->off_part), lat->gpb,
+                                                       lat->p.rho0, (double*)(lat->scratch + lat->off_final));
+    return launch_check(lat, "reduce final");
+}
+
+bool aligned256(const void* p) { return ((uintptr_t)p & 255u) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+int cmlbm_required_bytes(const cmlbm_params* params, size_t* pop_buffer_bytes, size_t* scratch_bytes)
+{
+    Layout L;
+    const int rc = make_layout(params, &L);
+    if (rc) return rc;
+    if (pop_buffer_bytes) *pop_buffer_bytes = L.pop_bytes;
+    if (scratch_bytes) *scratch_bytes = L.scratch_bytes;
+    return CMLBM_OK;
+}
+
+int cmlbm_create(const cmlbm_params* params, void* pop_a, size_t pop_a_bytes, void* pop_b, size_t pop_b_bytes,
+                 void* scratch, size_t scratch_bytes, cmlbm_lattice** out)
+{
+    if (!out) return CMLBM_EINVAL;
+    *out = nullptr;
+    Layout L;
+    int rc = make_layout(params, &L);
+    if (rc) return rc;
+    if (!pop_a || !pop_b || !scratch || pop_a == pop_b) return CMLBM_EINVAL;
+    if (!aligned256(pop_a) || !aligned256(pop_b) || !aligned256(scratch)) return CMLBM_EINVAL;
+    if (pop_a_bytes < L.pop_bytes || pop_b_bytes < L.pop_bytes || scratch_bytes < L.scratch_bytes)
+        return CMLBM_ENOMEM;
+    cmlbm_lattice* lat = new (std::nothrow) cmlbm_lattice();
+    if (!lat) return CMLBM_ENOMEM;
+    lat->p = *params;
+    lat->g = L.g;
+    lat->pop[0] = pop_a;
+    lat->pop[1] = pop_b;
+    lat->cur = 0;
+    lat->scratch = (uint8_t*)scratch;
+    lat->off_ftab64 = L.off_ftab64;
+    lat->off_ftab32 = L.off_ftab32;
+    lat->off_mask = L.off_mask;
+    lat->off_part = L.off_part;
+    lat->off_final = L.off_final;
+    lat->off_snap = L.off_snap;
+    lat->gpb = L.gpb;
+    lat->needs_mask = L.needs_mask;
+    lat->mask_ready = false;
+    lat->initialized = false;
+    lat->snap_valid = false;
+    lat->force_mode = -1;  // table not yet written
+    lat->field = nullptr;
+    lat->field_dtype = CMLBM_FP64;
+    lat->t = 0;
+    *out = lat;
+    return CMLBM_OK;
+}
+
+int cmlbm_set_solid(cmlbm_lattice* lat, const uint8_t* dev_solid, void* hip_stream)
+{
+    if (!lat) return CMLBM_EINVAL;
+    if (!(lat->p.flags & CMLBM_FLAG_SOLID)) return fail(lat, CMLBM_ESTATE, "set_solid needs CMLBM_FLAG_SOLID");
+    lat->initialized = false;
+    lat->snap_valid = false;
+    return build_mask(lat, dev_solid, (hipStream_t)hip_stream);
+}
+
+int cmlbm_set_force(cmlbm_lattice* lat, int mode, const double* host_values, const void* dev_field, int io_dtype,
+                    void* hip_stream)
+{
+    if (!lat) return CMLBM_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const Geom& g = lat->g;
+    const size_t n = (size_t)g.nb * g.ny;
+    std::vector<double> tab(3 * n, 0.0);
+    switch (mode) {
+        case CMLBM_FORCE_NONE: break;
+        case CMLBM_FORCE_UNIFORM:
+            if (!host_values) return fail(lat, CMLBM_EINVAL, "UNIFORM force needs host_values[3]");
+            for (size_t r = 0; r < n; ++r)
+                for (int a = 0; a < 3; ++a) tab[3 * r + a] = host_values[a];
+            break;
+        case CMLBM_FORCE_BATCH:
+            if (!host_values) return fail(lat, CMLBM_EINVAL, "BATCH force needs host_values[nbatch][3]");
+            for (int b = 0; b < g.nb; ++b)
+                for (int y = 0; y < g.ny; ++y)
+                    for (int a = 0; a < 3; ++a) tab[3 * ((size_t)b * g.ny + y) + a] = host_values[3 * b + a];
+            break;
+        case CMLBM_FORCE_PROFILE_Y:
+            if (!host_values) return fail(lat, CMLBM_EINVAL, "PROFILE_Y force needs host_values[ny][3]");
+            for (int b = 0; b < g.nb; ++b)
+                for (int y = 0; y < g.ny; ++y)
+                    for (int a = 0; a < 3; ++a) tab[3 * ((size_t)b * g.ny + y) + a] = host_values[3 * y + a];
+            break;
+        case CMLBM_FORCE_FIELD: {
+            const int need = lat->p.storage == CMLBM_FP64 ? CMLBM_FP64 : CMLBM_FP32;
+            if (!dev_field) return fail(lat, CMLBM_EINVAL, "FIELD force needs dev_field[3][N]");
+            if (io_dtype != need)
+                return fail(lat, CMLBM_EINVAL, "FIELD force dtype must be FP64 for FP64 storage, FP32 otherwise");
+            if ((uintptr_t)dev_field & (need == CMLBM_FP64 ? 7u : 3u))
+                return fail(lat, CMLBM_EINVAL, "FIELD force pointer misaligned");
+            break;
+        }
+        default: return fail(lat, CMLBM_EINVAL, "unknown force mode");
+    }
+    for (double v : tab)
+        if (!std::isfinite(v)) return fail(lat, CMLBM_EINVAL, "non-finite force");
+    std::vector<float> tab32(tab.begin(), tab.end());
+    int rc = hip_check(lat,
+                       hipMemcpyAsync(lat->scratch + lat->off_ftab64, tab.data(), tab.size() * sizeof(double),
+                                      hipMemcpyHostToDevice, s),
+                       "force table copy");
+    if (rc) return rc;
+    rc = hip_check(lat,
+                   hipMemcpyAsync(lat->scratch + lat->off_ftab32, tab32.data(), tab32.size() * sizeof(float),
+                                  hipMemcpyHostToDevice, s),
+                   "force table copy");
+    if (rc) return rc;
+    // the host vectors die on return: make sure the copies have consumed them
+    rc = hip_check(lat, hipStreamSynchronize(s), "force table sync");
+    if (rc) return rc;
+    lat->force_mode = mode;
+    lat->field = mode == CMLBM_FORCE_FIELD ? dev_field : nullptr;
+    lat->field_dtype = io_dtype;
+    return CMLBM_OK;
+}
+
+static int ensure_force(cmlbm_lattice* lat, hipStream_t s)
+{
+    if (lat->force_mode >= 0) return CMLBM_OK;
+    return cmlbm_set_force(lat, CMLBM_FORCE_NONE, nullptr, nullptr, CMLBM_FP64, s);
+}
+
+int cmlbm_init(cmlbm_lattice* lat, const void* dev_rho, const void* dev_u, int io_dtype, void* hip_stream)
+{
+    if (!lat) return CMLBM_EINVAL;
+    if (io_dtype != CMLBM_FP64 && io_dtype != CMLBM_FP32) return fail(lat, CMLBM_EINVAL, "io_dtype must be FP64/FP32");
+    hipStream_t s = (hipStream_t)hip_stream;
+    int rc = ensure_mask(lat, s);
+    if (rc) return rc;
+    rc = ensure_force(lat, s);
+    if (rc) return rc;
+    rc = launch_init(lat, io_dtype == CMLBM_FP64 ? INIT_EQ_F64 : INIT_EQ_F32, dev_rho, dev_u, nullptr, s);
+    if (rc) return rc;
+    lat->initialized = true;
+    lat->snap_valid = false;
+    lat->t = 0;
+    return CMLBM_OK;
+}
+
+int cmlbm_load_populations(cmlbm_lattice* lat, const double* dev_in, void* hip_stream)
+{
+    if (!lat || !dev_in) return CMLBM_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    int rc = ensure_mask(lat, s);
+    if (rc) return rc;
+    rc = ensure_force(lat, s);
+    if (rc) return rc;
+    rc = launch_init(lat, INIT_POPS_F64, nullptr, nullptr, dev_in, s);
+    if (rc) return rc;
+    lat->initialized = true;
+    lat->snap_valid = false;
+    return CMLBM_OK;
+}
+
+int cmlbm_step(cmlbm_lattice* lat, int32_t nsteps, void* hip_stream)
+{
+    if (!lat || nsteps < 0) return CMLBM_EINVAL;
+    if (!lat->initialized) return fail(lat, CMLBM_ESTATE, "step before init");
+    hipStream_t s = (hipStream_t)hip_stream;
+    for (int32_t k = 0; k < nsteps; ++k) {
+        int rc = launch_step(lat, s);
+        if (rc) return rc;
+        lat->cur = 1 - lat->cur;
+        lat->t += 1;
+    }
+    return CMLBM_OK;
+}
+
+int cmlbm_moments(cmlbm_lattice* lat, void* dev_rho, void* dev_u, int io_dtype, void* hip_stream)
+{
+    if (!lat) return CMLBM_EINVAL;
+    if (io_dtype != CMLBM_FP64 && io_dtype != CMLBM_FP32) return fail(lat, CMLBM_EINVAL, "io_dtype must be FP64/FP32");
+    if (!lat->initialized) return fail(lat, CMLBM_ESTATE, "moments before init");
+    if (!dev_rho && !dev_u) return CMLBM_OK;
+    return launch_gather(lat, dev_rho, dev_u, io_dtype == CMLBM_FP64, nullptr, (hipStream_t)hip_stream);
+}
+
+int cmlbm_populations(cmlbm_lattice* lat, double* dev_out, void* hip_stream)
+{
+    if (!lat || !dev_out) return CMLBM_EINVAL;
+    if (!lat->initialized) return fail(lat, CMLBM_ESTATE, "populations before init");
+    return launch_gather(lat, nullptr, nullptr, 1, dev_out, (hipStream_t)hip_stream);
+}
+
+int cmlbm_reduce(cmlbm_lattice* lat, uint32_t what, double* host_out, void* hip_stream)
+{
+    if (!lat || !host_out) return CMLBM_EINVAL;
+    if (what & ~(CMLBM_REDUCE_RESIDUAL | CMLBM_REDUCE_SNAPSHOT)) return fail(lat, CMLBM_EINVAL, "unknown reduce bits");
+    if (!lat->initialized) return fail(lat, CMLBM_ESTATE, "reduce before init");
+    const bool residual = what & CMLBM_REDUCE_RESIDUAL, snapshot = what & CMLBM_REDUCE_SNAPSHOT;
+    if ((residual || snapshot) && !(lat->p.flags & CMLBM_FLAG_RESIDUAL))
+        return fail(lat, CMLBM_ESTATE, "residual/snapshot need CMLBM_FLAG_RESIDUAL");
+    if (residual && !lat->snap_valid) return fail(lat, CMLBM_ESTATE, "residual before any snapshot");
+    hipStream_t s = (hipStream_t)hip_stream;
+    int rc = launch_reduce(lat, residual, snapshot, s);
+    if (rc) return rc;
+    const size_t nb = lat->g.nb;
+    rc = hip_check(lat,
+                   hipMemcpyAsync(host_out, lat->scratch + lat->off_final, nb * CMLBM_NRED * sizeof(double),
+                                  hipMemcpyDeviceToHost, s),
+                   "reduce copy");
+    if (rc) return rc;
+    rc = hip_check(lat, hipStreamSynchronize(s), "reduce sync");
+    if (rc) return rc;
+    if (snapshot) lat->snap_valid = true;
+    bool unstable = false;
+    for (size_t b = 0; b < nb; ++b) {
+        double* o = host_out + b * CMLBM_NRED;
+        o[CMLBM_RED_MASS] += lat->p.rho0 * (o[CMLBM_RED_FLUID] - o[CMLBM_RED_NONFINITE]);
+        o[CMLBM_RED_RESIDUAL] = residual && o[CMLBM_RED_U2] > 0 ? std::sqrt(o[CMLBM_RED_DU2] / o[CMLBM_RED_U2]) : 0.0;
+        if (!residual) o[CMLBM_RED_DU2] = 0.0;
+        if (o[CMLBM_RED_NONFINITE] > 0) unstable = true;
+    }
+    if (unstable) return fail(lat, CMLBM_EUNSTABLE, "non-finite density or velocity");
+    return CMLBM_OK;
+}
+
+int cmlbm_save_state(cmlbm_lattice* lat, void* dev_blob, size_t blob_bytes, void* hip_stream)
+{
+    if (!lat || !dev_blob) return CMLBM_EINVAL;
+    if (!lat->initialized) return fail(lat, CMLBM_ESTATE, "save_state before init");
+    Layout L;
+    make_layout(&lat->p, &L);
+    if (blob_bytes < L.pop_bytes) return fail(lat, CMLBM_ENOMEM, "state blob too small");
+    return hip_check(lat,
+                     hipMemcpyAsync(dev_blob, lat->pop[lat->cur], L.pop_bytes, hipMemcpyDeviceToDevice,
+                                    (hipStream_t)hip_stream),
+                     "save_state copy");
+}
+
+int cmlbm_restore_state(cmlbm_lattice* lat, const void* dev_blob, size_t blob_bytes, void* hip_stream)
+{
+    if (!lat || !dev_blob) return CMLBM_EINVAL;
+    Layout L;
+    make_layout(&lat->p, &L);
+    if (blob_bytes < L.pop_bytes) return fail(lat, CMLBM_ENOMEM, "state blob too small");
+    hipStream_t s = (hipStream_t)hip_stream;
+    int rc = ensure_mask(lat, s);
+    if (rc) return rc;
+    rc = ensure_force(lat, s);
+    if (rc) return rc;
+    rc = hip_check(lat, hipMemcpyAsync(lat->pop[lat->cur], dev_blob, L.pop_bytes, hipMemcpyDeviceToDevice, s),
+                   "restore_state copy");
+    if (rc) return rc;
+    lat->initialized = true;
+    lat->snap_valid = false;
+    return CMLBM_OK;
+}
+
+int cmlbm_get_time(const cmlbm_lattice* lat, int64_t* t)
+{
+    if (!lat || !t) return CMLBM_EINVAL;
+    *t = lat->t;
+    return CMLBM_OK;
+}
+
+int cmlbm_set_time(cmlbm_lattice* lat, int64_t t)
+{
+    if (!lat || t < 0) return CMLBM_EINVAL;
+    lat->t = t;
+    return CMLBM_OK;
+}
+
+int cmlbm_destroy(cmlbm_lattice* lat)
+{
+    delete lat;
+    return CMLBM_OK;
+}
+
+const char* cmlbm_last_error(const cmlbm_lattice* lat) { return lat ? lat->err.c_str() : ""; }
+
+const char* cmlbm_status_string(int status)
+{
+    switch (status) {
+        case CMLBM_OK: return "CMLBM_OK";
+        case CMLBM_EINVAL: return "CMLBM_EINVAL";
+        case CMLBM_ENOMEM: return "CMLBM_ENOMEM";
+        case CMLBM_EHIP: return "CMLBM_EHIP";
+        case CMLBM_EUNSTABLE: return "CMLBM_EUNSTABLE";
+        case CMLBM_ESTATE: return "CMLBM_ESTATE";
+        default: return "CMLBM_UNKNOWN";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,184 @@
+// D3Q27 lattice constants and the per-cell collision of the central-moment
+// lattice Boltzmann method with Hermite forcing (De Rosis, Huang & Coreixas,
+// PRE 2019, Sec. II), written for gfx950 register-resident evaluation.
+//
+// The collision is done in "deviation form": populations are handled as
+// h_i = f_i - w_i rho0 and every moment is carried minus its value for the
+// rest state (rho0, populations w_i rho0), so FP32 arithmetic keeps its
+// relative precision on the small quantities that carry the flow.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cmlbm {
+
+// Velocity components in the order of Sec. II.
+__host__ __device__ constexpr int vel_x(int i)
+{
+    constexpr int v[27] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
+    return v[i];
+}
+__host__ __device__ constexpr int vel_y(int i)
+{
+    constexpr int v[27] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, 1, -1, -1, 1, 1, -1, -1};
+    return v[i];
+}
+__host__ __device__ constexpr int vel_z(int i)
+{
+    constexpr int v[27] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1, 1, 1, 1, 1, -1, -1, -1, -1};
+    return v[i];
+}
+// Index of the velocity (a, b, c), each in {-1, 0, 1}.
+__host__ __device__ constexpr int vel_index(int a, int b, int c)
+{
+    for (int i = 0; i < 27; ++i)
+        if (vel_x(i) == a && vel_y(i) == b && vel_z(i) == c) return i;
+    return -1;
+}
+__host__ __device__ constexpr int opposite(int i) { return vel_index(-vel_x(i), -vel_y(i), -vel_z(i)); }
+
+// Lattice weight: the tensor product of the 1D weights (1/6, 2/3, 1/6),
+// equal to 8/27, 2/27, 1/54, 1/216 for |c|^2 = 0, 1, 2, 3.
+__host__ __device__ constexpr double weight(int i)
+{
+    return (vel_x(i) ? 1.0 / 6.0 : 2.0 / 3.0) * (vel_y(i) ? 1.0 / 6.0 : 2.0 / 3.0) *
+           (vel_z(i) ? 1.0 / 6.0 : 2.0 / 3.0);
+}
+
+// Inverse of the 1D central-moment map on {-1, 0, +1} shifted by u:
+// (m0, m1, m2) = sum g * (1, c - u, (c - u)^2)  ->  (g-, g0, g+).
+template <typename T>
+__device__ __forceinline__ void inv1d(T m0, T m1, T m2, T u, T& gm, T& g0, T& gp)
+{
+    const T odd = m1 + u * m0;                     // g+ - g-
+    const T even = m2 + u * (T(2) * m1 + u * m0);  // g+ + g-
+    gm = T(0.5) * (even - odd);
+    g0 = m0 - even;
+    gp = T(0.5) * (even + odd);
+}
+
+// Collide one cell in place.
+//   h[27]   in: pre-collision h_i = f_i - w_i rho0; out: post-collision h*_i
+//   F       force density at the cell
+//   omega   1/tau
+//   rho0    reference density of the shift
+// Outputs the density and the half-force-corrected velocity as well.
+template <typename T>
+__device__ __forceinline__ void collide(T h[27], T Fx, T Fy, T Fz, T omega, T rho0, T& rho_out, T& ux_out,
+                                        T& uy_out, T& uz_out)
+{
+    // Raw moments of h up to second order, by three 1D sums (x, then y, then z).
+    T X[3][3][3];  // X[p][b][c] = sum_a h(a,b,c) a^p
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const T hm = h[vel_index(-1, b - 1, c - 1)];
+            const T h0 = h[vel_index(0, b - 1, c - 1)];
+            const T hp = h[vel_index(1, b - 1, c - 1)];
+            X[0][b][c] = hm + h0 + hp;
+            X[1][b][c] = hp - hm;
+            X[2][b][c] = hp + hm;
+        }
+    T Y[3][3][3];  // Y[p][q][c]
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Y[p][0][c] = X[p][0][c] + X[p][1][c] + X[p][2][c];
+            Y[p][1][c] = X[p][2][c] - X[p][0][c];
+            Y[p][2][c] = X[p][2][c] + X[p][0][c];
+        }
+    auto zsum = [&](int p, int q, int r) -> T {
+        if (r == 0) return Y[p][q][0] + Y[p][q][1] + Y[p][q][2];
+        if (r == 1) return Y[p][q][2] - Y[p][q][0];
+        return Y[p][q][2] + Y[p][q][0];
+    };
+    const T drho = zsum(0, 0, 0);
+    const T jx = zsum(1, 0, 0), jy = zsum(0, 1, 0), jz = zsum(0, 0, 1);
+    const T Sxx = zsum(2, 0, 0), Syy = zsum(0, 2, 0), Szz = zsum(0, 0, 2);
+    const T Sxy = zsum(1, 1, 0), Sxz = zsum(1, 0, 1), Syz = zsum(0, 1, 1);
+
+    // Macroscopic variables with the half-force correction (eq. "macroscopic").
+    const T rho = rho0 + drho;
+    const T inv_rho = T(1) / rho;
+    const T ux = (jx + T(0.5) * Fx) * inv_rho;
+    const T uy = (jy + T(0.5) * Fy) * inv_rho;
+    const T uz = (jz + T(0.5) * Fz) * inv_rho;
+    rho_out = rho;
+    ux_out = ux;
+    uy_out = uy;
+    uz_out = uz;
+
+    // The five pre-collision central moments k4..k8 (eq. "pre_collision"),
+    // from raw moments: sum f (cx-ux)(cy-uy) = Pxy - rho ux uy + (ux Fy + uy Fx)/2,
+    // where the rest state contributes nothing to Pxy or Pxx - Pyy.
+    const T k4 = Sxy - rho * ux * uy + T(0.5) * (ux * Fy + uy * Fx);
+    const T k5 = Sxz - rho * ux * uz + T(0.5) * (ux * Fz + uz * Fx);
+    const T k6 = Syz - rho * uy * uz + T(0.5) * (uy * Fz + uz * Fy);
+    const T k7 = (Sxx - Syy) - rho * (ux * ux - uy * uy) + (ux * Fx - uy * Fy);
+    const T k8 = (Sxx - Szz) - rho * (ux * ux - uz * uz) + (ux * Fx - uz * Fz);
+
+    // Post-collision central moments (eq. "post_collision_central_moments_forcing")
+    // rewritten on the monomials (cx-ux)^p (cy-uy)^q (cz-uz)^r, minus the central
+    // moments of the rest state rho0 w_i, which factor as rho0 M_p(ux) M_q(uy) M_r(uz)
+    // with M_0 = 1, M_1(u) = -u, M_2(u) = 1/3 + u^2.
+    const T om1 = T(1) - omega;
+    const T third = T(1.0 / 3.0);
+    const T ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz;
+    const T ax = third + ux2, ay = third + uy2, az = third + uz2;
+    T D[3][3][3];
+    D[0][0][0] = drho;
+    D[1][0][0] = T(0.5) * Fx + rho0 * ux;
+    D[0][1][0] = T(0.5) * Fy + rho0 * uy;
+    D[0][0][1] = T(0.5) * Fz + rho0 * uz;
+    D[1][1][0] = om1 * k4 - rho0 * ux * uy;
+    D[1][0][1] = om1 * k5 - rho0 * ux * uz;
+    D[0][1][1] = om1 * k6 - rho0 * uy * uz;
+    D[2][0][0] = (om1 * (k7 + k8) + drho) * third - rho0 * ux2;
+    D[0][2][0] = (om1 * (k8 - T(2) * k7) + drho) * third - rho0 * uy2;
+    D[0][0][2] = (om1 * (k7 - T(2) * k8) + drho) * third - rho0 * uz2;
+    const T sixth = T(1.0 / 6.0);
+    D[1][2][0] = sixth * Fx + rho0 * ux * ay;
+    D[1][0][2] = sixth * Fx + rho0 * ux * az;
+    D[2][1][0] = sixth * Fy + rho0 * uy * ax;
+    D[0][1][2] = sixth * Fy + rho0 * uy * az;
+    D[2][0][1] = sixth * Fz + rho0 * uz * ax;
+    D[0][2][1] = sixth * Fz + rho0 * uz * ay;
+    D[1][1][1] = rho0 * ux * uy * uz;
+    const T ninth = T(1.0 / 9.0);
+    D[2][2][0] = ninth * drho - rho0 * ((ux2 + uy2) * third + ux2 * uy2);
+    D[2][0][2] = ninth * drho - rho0 * ((ux2 + uz2) * third + ux2 * uz2);
+    D[0][2][2] = ninth * drho - rho0 * ((uy2 + uz2) * third + uy2 * uz2);
+    D[2][1][1] = -rho0 * ax * uy * uz;
+    D[1][2][1] = -rho0 * ay * ux * uz;
+    D[1][1][2] = -rho0 * az * ux * uy;
+    const T f18 = T(1.0 / 18.0);
+    D[1][2][2] = f18 * Fx + rho0 * ux * ay * az;
+    D[2][1][2] = f18 * Fy + rho0 * uy * ax * az;
+    D[2][2][1] = f18 * Fz + rho0 * uz * ax * ay;
+    D[2][2][2] = T(1.0 / 27.0) * drho -
+                 rho0 * ((ux2 + uy2 + uz2) * ninth + (ux2 * uy2 + ux2 * uz2 + uy2 * uz2) * third + ux2 * uy2 * uz2);
+
+    // Reconstruction (eq. "system") by the factorised inverse transform:
+    // along z, then y, then x.
+    T A[3][3][3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) inv1d(D[p][q][0], D[p][q][1], D[p][q][2], uz, A[p][q][0], A[p][q][1], A[p][q][2]);
+    T B[3][3][3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) inv1d(A[p][0][c], A[p][1][c], A[p][2][c], uy, B[p][0][c], B[p][1][c], B[p][2][c]);
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            inv1d(B[0][b][c], B[1][b][c], B[2][b][c], ux, h[vel_index(-1, b - 1, c - 1)], h[vel_index(0, b - 1, c - 1)],
+                  h[vel_index(1, b - 1, c - 1)]);
+}
+
+}  // namespace cmlbm

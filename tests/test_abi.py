@@ -1,0 +1,125 @@
+"""CPU-side checks of the C ABI (include/cmlbm.h): the library loads, exports
+every declared entry point, and rejects invalid arguments on the host before
+any device work.  No call here reaches the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1905_10182_amd import cmlbm as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cmlbm.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return B.load_library()
+
+
+def declared_functions(path):
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cmlbm_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions(HEADER) == sorted(B.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions(HEADER):
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    assert lib.cmlbm_status_string(0) == b"CMLBM_OK"
+    assert lib.cmlbm_status_string(-4) == b"CMLBM_EUNSTABLE"
+    assert lib.cmlbm_status_string(17) == b"CMLBM_UNKNOWN"
+    assert lib.cmlbm_last_error(None) == b""
+
+
+def req(**kw):
+    base = dict(nx=32, ny=16, nz=16, nbatch=1, tau=0.8, rho0=1.0, storage="fp32", wall=(0, 0, 0), flags=0)
+    base.update(kw)
+    return B.make_params(**base)
+
+
+def test_required_bytes_padding():
+    # rows padded to 256 bytes; 27 planes of rows * padded row length
+    pop, scratch = B.required_bytes(req(nx=32, storage="fp32"))
+    assert pop == 27 * 16 * 16 * 64 * 4
+    pop, _ = B.required_bytes(req(nx=256, ny=256, nz=256, storage="fp32"))
+    assert pop == 27 * 256 ** 3 * 4
+    pop, _ = B.required_bytes(req(nx=512, ny=512, nz=512, storage="fp16"))
+    assert pop == 27 * 512 ** 3 * 2
+    pop, _ = B.required_bytes(req(nx=37, ny=13, nz=11, nbatch=2, storage="fp64"))
+    assert pop == 27 * 13 * 11 * 2 * 64 * 8
+    # a mask (walls/solid) and the residual snapshot enlarge the scratch
+    _, s0 = B.required_bytes(req())
+    _, s1 = B.required_bytes(req(wall=(0, 1, 0)))
+    _, s2 = B.required_bytes(req(flags=B.FLAG_RESIDUAL))
+    assert s1 >= s0 + 16 * 16 * 64 * 4
+    assert s2 >= s0 + 3 * 32 * 16 * 16 * 8
+
+
+@pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=0.3), dict(tau=float("nan")), dict(nx=0), dict(ny=-1),
+                                dict(nbatch=0), dict(rho0=0.0), dict(storage=7), dict(wall=(2, 0, 0)),
+                                dict(flags=8), dict(nz=1, wall=(0, 0, 1))])
+def test_invalid_params(kw):
+    with pytest.raises(B.CmlbmError) as e:
+        B.required_bytes(req(**kw))
+    assert e.value.code == B.EINVAL
+
+
+def create(lib, params, a, na, b, nb, s, ns):
+    h = ctypes.c_void_p()
+    rc = lib.cmlbm_create(ctypes.byref(params), a, na, b, nb, s, ns, ctypes.byref(h))
+    return rc, h
+
+
+def test_create_validates_buffers(lib):
+    p = req()
+    pop, scr = B.required_bytes(p)
+    A, Bp, S = 0x10000000, 0x20000000, 0x30000000  # never dereferenced: create is host-only
+    assert create(lib, p, None, pop, Bp, pop, S, scr)[0] == B.EINVAL
+    assert create(lib, p, A, pop, A, pop, S, scr)[0] == B.EINVAL
+    assert create(lib, p, A + 8, pop, Bp, pop, S, scr)[0] == B.EINVAL
+    assert create(lib, p, A, pop - 1, Bp, pop, S, scr)[0] == B.ENOMEM
+    assert create(lib, p, A, pop, Bp, pop, S, scr - 1)[0] == B.ENOMEM
+    rc, h = create(lib, p, A, pop, Bp, pop, S, scr)
+    assert rc == B.OK and h.value
+    # state checks happen before any device call
+    assert lib.cmlbm_step(h, 1, None) == B.ESTATE
+    assert b"before init" in lib.cmlbm_last_error(h)
+    assert lib.cmlbm_step(h, -1, None) == B.EINVAL
+    assert lib.cmlbm_moments(h, None, None, 5, None) == B.EINVAL
+    out = (ctypes.c_double * B.NRED)()
+    assert lib.cmlbm_reduce(h, 0, out, None) == B.ESTATE
+    assert lib.cmlbm_reduce(h, 8, out, None) == B.EINVAL
+    assert lib.cmlbm_set_solid(h, None, None) == B.ESTATE  # no CMLBM_FLAG_SOLID
+    assert lib.cmlbm_set_force(h, 99, None, None, 0, None) == B.EINVAL
+    assert lib.cmlbm_set_force(h, B.FORCE_UNIFORM, None, None, 0, None) == B.EINVAL
+    assert lib.cmlbm_set_force(h, B.FORCE_FIELD, None, None, B.FP32, None) == B.EINVAL
+    assert lib.cmlbm_set_force(h, B.FORCE_FIELD, None, ctypes.c_void_p(0x40000000), B.FP64, None) == B.EINVAL
+    t = ctypes.c_int64()
+    assert lib.cmlbm_get_time(h, ctypes.byref(t)) == B.OK and t.value == 0
+    assert lib.cmlbm_set_time(h, 12) == B.OK
+    assert lib.cmlbm_get_time(h, ctypes.byref(t)) == B.OK and t.value == 12
+    assert lib.cmlbm_set_time(h, -1) == B.EINVAL
+    assert lib.cmlbm_destroy(h) == B.OK
+    assert lib.cmlbm_destroy(None) == B.OK
+
+
+def test_null_handle_is_einval(lib):
+    assert lib.cmlbm_step(None, 1, None) == B.EINVAL
+    assert lib.cmlbm_init(None, None, None, 0, None) == B.EINVAL
+    assert lib.cmlbm_populations(None, None, None) == B.EINVAL
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(B, "_lib", None)
+    monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(OSError):
+        B.load_library()

@@ -1,0 +1,384 @@
+"""Parity of the HIP solver (through the C ABI) with the CPU oracle.
+
+Tolerances: FP64 storage 1e-12 relative, FP32 storage 1e-5 relative in
+velocity (relative L2 over fluid cells), 16-bit storage checked per
+population against round-to-nearest of the oracle's post-collision value.
+
+FP64-storage runs are compared with the oracle built in 80-bit long double:
+on slow flows (Poiseuille, |u| ~ 3e-4) the FP64 textbook form's own rounding
+of sum f c over populations of order 1 is about 2e-12 relative in u, above
+the 1e-12 bar, while the extended build is exact to that bar.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+CX, CY, CZ, WGT, OPP = O.constants()
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+def Lat(**kw):
+    from paper_1905_10182_amd import Lattice
+    return Lattice(device="cuda:0", **kw)
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def fluid_rel(u, ref, solid=None):
+    if solid is None:
+        return rel(u, ref)
+    m = ~np.asarray(solid, bool)
+    return rel(np.asarray(u)[:, m], np.asarray(ref)[:, m])
+
+
+def tgv_pair(n, storage, steps, re=1600.0):
+    wl = W.taylor_green(n, re=re, seed=1)
+    ref = O.Lattice(n, n, n, tau=wl["tau"], extended=storage == "fp64")
+    ref.init(wl["rho"], wl["u"])
+    ref.step(steps)
+    lat = Lat(nx=n, ny=n, nz=n, tau=wl["tau"], storage=storage)
+    lat.init(wl["rho"], wl["u"])
+    lat.step(steps)
+    return ref, lat
+
+
+# ---------------------------------------------------------------------------
+# state import/export
+
+def test_population_roundtrip_bit_exact_fp64(torch):
+    """load_populations followed by populations is the identity (the init
+    scatter is the exact inverse of the pull gather) on a ragged batch with
+    walls on two axes and solid nodes."""
+    log("roundtrip fp64 37x13x11 nb=2")
+    shape = (2, 11, 13, 37)
+    g = W.generator(21)
+    solid = (g.uniform(size=shape) < 0.1).astype(np.uint8)
+    f = WGT.reshape(27, 1, 1, 1, 1) * g.uniform(0.6, 1.6, size=(27,) + shape)  # f in [w/2, 2w]
+    f[:, solid.astype(bool)] = 0.0
+    lat = Lat(nx=37, ny=13, nz=11, nbatch=2, tau=0.7, storage="fp64", wall=(0, 1, 1), solid=True)
+    lat.set_solid(solid)
+    lat.load_populations(f)
+    out = lat.populations().cpu().numpy()
+    assert np.array_equal(out, f)
+
+
+def test_population_roundtrip_fp32(torch):
+    log("roundtrip fp32 40x9x7")
+    shape = (1, 7, 9, 40)
+    f = WGT.reshape(27, 1, 1, 1, 1) * W.generator(22).uniform(0.6, 1.6, size=(27,) + shape)
+    lat = Lat(nx=40, ny=9, nz=7, tau=0.7, storage="fp32")
+    lat.load_populations(f)
+    out = lat.populations().cpu().numpy()
+    dev = (f - WGT.reshape(27, 1, 1, 1, 1)).astype(np.float32).astype(np.float64) + WGT.reshape(27, 1, 1, 1, 1)
+    np.testing.assert_array_equal(out, dev)
+
+
+# ---------------------------------------------------------------------------
+# FP64 parity
+
+def test_fp64_random_state_field_force_walls_solid(torch):
+    """Non-equilibrium random populations, per-cell force field, walls in y
+    and z, solid nodes, a ragged batch of two: 5 steps, every population."""
+    log("fp64 random state 37x13x11 nb=2, 5 steps")
+    shape = (2, 11, 13, 37)
+    g = W.generator(23)
+    solid = (g.uniform(size=shape) < 0.08).astype(np.uint8)
+    f0 = W.random_populations(shape, seed=24)
+    f0[:, solid.astype(bool)] = 0.0
+    force = g.uniform(-1e-3, 1e-3, size=(3,) + shape)
+    ref = O.Lattice(37, 13, 11, nb=2, tau=0.73, wall=(0, 1, 1), solid=solid, force=force, extended=True)
+    ref.load_populations(f0)
+    ref.step(5)
+    lat = Lat(nx=37, ny=13, nz=11, nbatch=2, tau=0.73, storage="fp64", wall=(0, 1, 1), solid=True)
+    lat.set_solid(solid)
+    lat.set_force("field", field=force)
+    lat.load_populations(f0)
+    lat.step(5)
+    out = lat.populations().cpu().numpy()
+    fr = ref.f.astype(np.float64)
+    err = np.abs(out - fr).max() / np.abs(fr).max()
+    log(f"  max population error {err:.3e}")
+    assert err < 1e-13
+    rho, u = lat.moments()
+    rr, ur = ref.moments()
+    assert fluid_rel(u.cpu().numpy(), ur, solid) < 1e-12
+    m = ~solid.astype(bool)
+    assert rel(rho.cpu().numpy()[m], rr[m]) < 1e-14
+
+
+def test_fp64_taylor_green_32(torch):
+    log("fp64 TGV 32^3, 200 steps")
+    ref, lat = tgv_pair(32, "fp64", 200)
+    _, u = lat.moments()
+    _, ur = ref.moments()
+    err = rel(u.cpu().numpy(), ur)
+    perr = rel(lat.populations().cpu().numpy(), ref.f)
+    log(f"  velocity {err:.3e} populations {perr:.3e}")
+    assert err < 1e-12 and perr < 1e-12
+
+
+def test_fp64_poiseuille_config(torch):
+    """Body-force Poiseuille channel 32x16x16, tau 0.8, F_x 1e-6, 1000 steps."""
+    log("fp64 Poiseuille 32x16x16, 1000 steps")
+    wl = W.poiseuille()
+    nb, nz, ny, nx = wl["shape"]
+    ref = O.Lattice(nx, ny, nz, tau=wl["tau"], wall=wl["wall"], force=wl["force"].reshape(3, 1, 1, 1, 1),
+                    extended=True)
+    ref.init(wl["rho"], wl["u"])
+    ref.step(wl["steps"])
+    lat = Lat(nx=nx, ny=ny, nz=nz, tau=wl["tau"], storage="fp64", wall=wl["wall"])
+    lat.set_force("uniform", wl["force"])
+    lat.init(wl["rho"], wl["u"])
+    lat.step(wl["steps"])
+    _, u = lat.moments()
+    _, ur = ref.moments()
+    err = rel(u.cpu().numpy(), ur)
+    log(f"  velocity {err:.3e}")
+    assert err < 1e-12
+
+
+def test_fp64_kolmogorov_profile_force(torch):
+    log("fp64 Kolmogorov 48^3, 100 steps")
+    wl = W.kolmogorov(48, f0=1e-4, tau=0.6)
+    prof = wl["force_profile_y"]
+    field = np.broadcast_to(prof.T[:, None, None, :, None], (3,) + wl["shape"])
+    ref = O.Lattice(48, 48, 48, tau=wl["tau"], force=field, extended=True)
+    ref.init(wl["rho"], wl["u"])
+    ref.step(100)
+    lat = Lat(nx=48, ny=48, nz=48, tau=wl["tau"], storage="fp64")
+    lat.set_force("profile_y", prof)
+    lat.init(wl["rho"], wl["u"])
+    lat.step(100)
+    _, u = lat.moments()
+    _, ur = ref.moments()
+    err = rel(u.cpu().numpy(), ur)
+    log(f"  velocity {err:.3e}")
+    assert err < 1e-12
+
+
+def test_fp64_sphere_channels_batch_force(torch):
+    log("fp64 sphere channels 3x(40x20x16), 60 steps")
+    wl = W.sphere_channels(3, nx=40, ny=20, nz=16, seed=77, rmin=2.0, rmax=4.0)
+    solid = wl["solid"]
+    nb, nz, ny, nx = wl["shape"]
+    field = np.zeros((3,) + wl["shape"])
+    field[0] = wl["fx"][:, None, None, None]
+    ref = O.Lattice(nx, ny, nz, nb=nb, tau=wl["tau"], wall=wl["wall"], solid=solid, force=field, extended=True)
+    rho0 = np.ones(wl["shape"])
+    ref.init(rho0, np.zeros((3,) + wl["shape"]))
+    ref.step(60)
+    lat = Lat(nx=nx, ny=ny, nz=nz, nbatch=nb, tau=wl["tau"], storage="fp64", wall=wl["wall"], solid=True)
+    lat.set_solid(solid)
+    lat.set_force("batch", np.stack([wl["fx"], 0 * wl["fx"], 0 * wl["fx"]], axis=1))
+    lat.init(None, None)
+    lat.step(60)
+    _, u = lat.moments()
+    _, ur = ref.moments()
+    err = fluid_rel(u.cpu().numpy(), ur, solid)
+    log(f"  velocity {err:.3e}")
+    assert err < 1e-12
+    assert np.abs(u.cpu().numpy()[:, solid.astype(bool)]).max() == 0.0
+
+
+# ---------------------------------------------------------------------------
+# FP32 / 16-bit storage
+
+def test_fp32_taylor_green_32(torch):
+    log("fp32 TGV 32^3, 200 steps")
+    ref, lat = tgv_pair(32, "fp32", 200)
+    _, u = lat.moments()
+    _, ur = ref.moments()
+    err = rel(u.cpu().numpy(), ur)
+    log(f"  velocity {err:.3e}")
+    assert err < 1e-5
+
+
+def test_fp32_poiseuille_config(torch):
+    log("fp32 Poiseuille 32x16x16, 1000 steps")
+    wl = W.poiseuille()
+    nb, nz, ny, nx = wl["shape"]
+    ref = O.Lattice(nx, ny, nz, tau=wl["tau"], wall=wl["wall"], force=wl["force"].reshape(3, 1, 1, 1, 1))
+    ref.init(wl["rho"], wl["u"])
+    ref.step(wl["steps"])
+    lat = Lat(nx=nx, ny=ny, nz=nz, tau=wl["tau"], storage="fp32", wall=wl["wall"])
+    lat.set_force("uniform", wl["force"])
+    lat.init(wl["rho"], wl["u"])
+    lat.step(wl["steps"])
+    _, u = lat.moments()
+    _, ur = ref.moments()
+    err = rel(u.cpu().numpy(), ur)
+    log(f"  velocity {err:.3e}")
+    assert err < 1e-5
+
+
+@pytest.mark.parametrize("storage,bound", [("fp16", 5e-3), ("bf16", 5e-2)])
+def test_16bit_taylor_green_32_error(torch, storage, bound):
+    log(f"{storage} TGV 32^3, 200 steps")
+    ref, lat = tgv_pair(32, storage, 200)
+    _, u = lat.moments()
+    _, ur = ref.moments()
+    err = rel(u.cpu().numpy(), ur)
+    log(f"  velocity error vs FP64 oracle {err:.3e}")
+    assert err < bound
+
+
+# ---------------------------------------------------------------------------
+# full-size configurations, sampled
+
+def sampled_one_step(torch, n, storage, nsample, seed):
+    """One fused step at full size; at nsample random cells s the oracle
+    collides the exported pre-collision populations P0[:, s] and each result
+    f*_i must appear at P1[i, s + c_i]."""
+    wl = W.taylor_green(n, seed=1)
+    lat = Lat(nx=n, ny=n, nz=n, tau=wl["tau"], storage=storage)
+    lat.init(wl["rho"], wl["u"])
+    del wl
+    g = W.generator(seed)
+    s = g.integers(0, n, size=(nsample, 3))  # (x, y, z)
+    P0 = lat.populations()
+    lin0 = torch.as_tensor((s[:, 2] * n + s[:, 1]) * n + s[:, 0], device=P0.device)
+    f0 = P0.reshape(27, -1)[:, lin0].cpu().numpy()
+    del P0
+    lat.step(1)
+    P1 = lat.populations().reshape(27, -1)
+    got = np.empty((27, nsample))
+    for i in range(27):
+        d = (s + np.array([CX[i], CY[i], CZ[i]])) % n
+        lin = torch.as_tensor((d[:, 2] * n + d[:, 1]) * n + d[:, 0], device=P1.device)
+        got[i] = P1[i, lin].cpu().numpy()
+    del P1
+    ref = O.collide_cells(f0, None, 1.0 / lat.params.tau)
+    lat.close()
+    return got, ref
+
+
+def test_full_size_taylor_green_256_fp32_sampled(torch):
+    log("fp32 TGV 256^3 one step, 4096 sampled cells")
+    got, ref = sampled_one_step(torch, 256, "fp32", 4096, seed=31)
+    err = np.abs(got - ref) / WGT[:, None]
+    log(f"  max |f* - oracle| / w = {err.max():.3e}")
+    assert err.max() < 1e-6
+
+
+def test_full_size_taylor_green_512_fp16_sampled(torch):
+    """16-bit storage at 512^3: every sampled post-collision population is the
+    oracle's value rounded to FP16 (within one unit in the last place, which
+    absorbs the FP32 arithmetic)."""
+    log("fp16 TGV 512^3 one step, 4096 sampled cells")
+    got, ref = sampled_one_step(torch, 512, "fp16", 4096, seed=32)
+    h_ref = ref - WGT[:, None]
+    h_got = got - WGT[:, None]
+    ulp = np.spacing(np.abs(h_ref).astype(np.float16)).astype(np.float64)
+    ratio = np.abs(h_got - h_ref) / ulp
+    log(f"  max error in FP16 ulps {ratio.max():.3f}")
+    assert ratio.max() <= 1.0
+
+
+# ---------------------------------------------------------------------------
+# reductions, residual, checkpoint, failure detection
+
+def test_reduce_matches_oracle_sums(torch):
+    log("reduce vs oracle sums")
+    shape = (2, 5, 6, 70)
+    f0 = W.random_populations(shape, seed=41)
+    lat = Lat(nx=70, ny=6, nz=5, nbatch=2, tau=0.9, storage="fp64")
+    lat.load_populations(f0)
+    r = lat.reduce()
+    C = np.stack([CX, CY, CZ], 1).astype(float)
+    for b in range(2):
+        fb = f0[:, b].reshape(27, -1)
+        assert abs(r[b, 0] / fb.sum() - 1) < 1e-14
+        np.testing.assert_allclose(r[b, 1:4], fb.sum(axis=1) @ C, rtol=1e-12, atol=1e-13)
+        assert r[b, 7] == fb.shape[1] and r[b, 6] == 0
+    r2 = lat.reduce()
+    assert np.array_equal(r, r2)  # fixed summation order
+
+
+def test_periodic_momentum_gain_equals_force(torch):
+    log("momentum bookkeeping fp64 periodic 64x8x8, 50 steps")
+    F = np.array([2e-5, -1e-5, 3e-6])
+    lat = Lat(nx=64, ny=8, nz=8, tau=0.7, storage="fp64")
+    lat.set_force("uniform", F)
+    lat.init(None, None)
+    r0 = lat.reduce()
+    lat.step(50)
+    r1 = lat.reduce()
+    ncell = 64 * 8 * 8
+    np.testing.assert_allclose(r1[0, 1:4] - r0[0, 1:4], 50 * ncell * F, rtol=1e-11)
+    assert abs(r1[0, 0] / r0[0, 0] - 1) < 1e-14
+
+
+def test_residual_snapshot_semantics(torch):
+    log("residual semantics")
+    wl = W.taylor_green(24, re=200.0)
+    lat = Lat(nx=24, ny=24, nz=24, tau=wl["tau"], storage="fp64", residual=True)
+    lat.init(wl["rho"], wl["u"])
+    _, ua = lat.moments()
+    lat.reduce(snapshot=True)
+    lat.step(3)
+    _, ub = lat.moments()
+    r = lat.reduce(residual=True, snapshot=True)
+    a, b = ua.cpu().numpy(), ub.cpu().numpy()
+    expect = np.linalg.norm(b - a) / np.linalg.norm(b)
+    assert abs(r[0, 10] / expect - 1) < 1e-10
+
+
+def test_checkpoint_restart_is_bitwise(torch):
+    """save_state / restore_state: 40 steps in one go equal 20 steps, a
+    checkpoint, a restore into a fresh handle and 20 more, bit for bit (every
+    kernel is deterministic).  The FP64 population export/import path is
+    exact up to one rounding of f - w rho0."""
+    for storage in ("fp64", "fp32", "fp16"):
+        log(f"checkpoint restart {storage} TGV 24^3")
+        wl = W.taylor_green(24, re=400.0)
+        A = Lat(nx=24, ny=24, nz=24, tau=wl["tau"], storage=storage)
+        A.init(wl["rho"], wl["u"])
+        A.step(40)
+        B = Lat(nx=24, ny=24, nz=24, tau=wl["tau"], storage=storage)
+        B.init(wl["rho"], wl["u"])
+        B.step(20)
+        blob, t = B.save_state()
+        C = Lat(nx=24, ny=24, nz=24, tau=wl["tau"], storage=storage)
+        C.restore_state(blob, t)
+        C.step(20)
+        assert C.time == 40
+        assert torch.equal(A.populations(), C.populations())
+    D = Lat(nx=24, ny=24, nz=24, tau=wl["tau"], storage="fp64")
+    D.load_populations(B.populations())
+    np.testing.assert_allclose(D.populations().cpu().numpy(), B.populations().cpu().numpy(), rtol=0, atol=1e-16)
+
+
+def test_nonfinite_state_reports_unstable(torch):
+    from paper_1905_10182_amd import cmlbm as B
+    log("non-finite detection")
+    f = WGT.reshape(27, 1, 1, 1, 1) * np.ones((27, 1, 4, 4, 64))
+    f[3, 0, 1, 2, 5] = np.nan
+    lat = Lat(nx=64, ny=4, nz=4, tau=0.7, storage="fp32")
+    lat.load_populations(f)
+    with pytest.raises(B.CmlbmError) as e:
+        lat.reduce()
+    assert e.value.code == B.EUNSTABLE
+    r = lat.reduce(allow_unstable=True)
+    assert r[0, 6] == 1 and r[0, 7] == 64 * 16
