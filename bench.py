@@ -108,11 +108,11 @@ def copy_bandwidth():
 
 def cpu_baseline():
     """The FP64 oracle (closed-form route, OpenMP) on a bounded sample of the
-    same workload: Taylor-Green 128^3, 24 steps."""
+    same workload: Taylor-Green 128^3, 400 steps."""
     import oracle
     import workloads
 
-    n, steps = 128, 24
+    n, steps = 128, 400
     wl = workloads.taylor_green(n, seed=1)
     L = oracle.Lattice(n, n, n, tau=wl["tau"])
     L.init(wl["rho"], wl["u"])
@@ -134,8 +134,8 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the solver here is single-GPU "
-              "(multi-GPU z-slab sharding is described in DESIGN.md, not built).", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}): the solver is single-GPU; "
+              "a z-slab decomposition over several GPUs is not built.", file=sys.stderr)
         sys.exit(2)
 
     import torch
