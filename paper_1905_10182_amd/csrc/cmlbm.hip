@@ -162,40 +162,212 @@ __device__ __forceinline__ void gather(const typename storage<ST>::S* __restrict
 // ---------------------------------------------------------------------------
 // the hot path: one time step
 
-template <int ST, bool MASK, bool FIELD>
-__global__ __launch_bounds__(kBlock) void k_step(const typename storage<ST>::S* __restrict__ src,
-                                                 typename storage<ST>::S* __restrict__ dst, Geom g,
-                                                 typename storage<ST>::T omega, typename storage<ST>::T rho0,
-                                                 const typename storage<ST>::T* __restrict__ ftab,
-                                                 const typename storage<ST>::T* __restrict__ field,
-                                                 const uint32_t* __restrict__ mask)
+// ---------------------------------------------------------------------------
+// cross-lane shifts for the vectorised row access of k_step
+
+// lane l receives the value of lane l-1 (mod 64) / lane l+1 (mod 64)
+__device__ __forceinline__ int dpp_from_prev(int v) { return __builtin_amdgcn_mov_dpp(v, 0x13C, 0xF, 0xF, false); }
+__device__ __forceinline__ int dpp_from_next(int v) { return __builtin_amdgcn_mov_dpp(v, 0x134, 0xF, 0xF, false); }
+
+template <typename S>
+__device__ __forceinline__ S lane_shift(S v, bool from_prev)
 {
-    using SS = storage<ST>;
-    using T = typename SS::T;
-    const Cell c = locate(g);
-    if (!c.valid) return;
-    uint32_t m = 0;
-    if (MASK) {
-        m = mask[c.own];
-        if (m & kSolidBit) return;
-    }
-    T h[27];
-    gather<ST, MASK>(src, g, c, m, h);
-    T Fx, Fy, Fz;
-    if (FIELD) {
-        Fx = field[c.lin];
-        Fy = field[g.ncell + c.lin];
-        Fz = field[2 * g.ncell + c.lin];
+    if constexpr (sizeof(S) == 4) {
+        const int r = from_prev ? dpp_from_prev(__builtin_bit_cast(int, v)) : dpp_from_next(__builtin_bit_cast(int, v));
+        return __builtin_bit_cast(S, r);
+    } else if constexpr (sizeof(S) == 8) {
+        const int2 w = __builtin_bit_cast(int2, v);
+        int2 r;
+        r.x = from_prev ? dpp_from_prev(w.x) : dpp_from_next(w.x);
+        r.y = from_prev ? dpp_from_prev(w.y) : dpp_from_next(w.y);
+        return __builtin_bit_cast(S, r);
     } else {
-        const T* fr = ftab + 3 * (c.b * g.ny + c.y);
-        Fx = fr[0];
-        Fy = fr[1];
-        Fz = fr[2];
+        const int w = (int)__builtin_bit_cast(unsigned short, v);
+        const int r = from_prev ? dpp_from_prev(w) : dpp_from_next(w);
+        return __builtin_bit_cast(S, (unsigned short)r);
     }
-    T rho, ux, uy, uz;
-    collide<T>(h, Fx, Fy, Fz, omega, rho0, rho, ux, uy, uz);
+}
+
+// ---------------------------------------------------------------------------
+// the hot path: one fused time step
+//
+// Every cell pulls its 27 populations from x - c_i (eq. "streaming" read
+// backwards), collides in central-moment space (collide() in d3q27.hpp) and
+// stores its 27 post-collision populations at its own index with
+// non-temporal stores (they are not read again in this step).
+//
+// Wave w owns segment (w mod segs) of row (w / segs): 64 lanes x V cells.
+// With V > 1 a lane reads every plane as one aligned V-element vector; the
+// 18 populations with c_x = +-1 need the row shifted by one cell, done in
+// registers: the element crossing a lane boundary comes from the neighbouring
+// lane by a DPP wave rotation (which also performs the periodic wrap when a
+// row is exactly one wave), and the lanes at the ends of a segment otherwise
+// reload that one element.
+// All row-dependent address arithmetic is wave-uniform and lives in scalar
+// registers; each access is a scalar base pointer plus a 32-bit per-lane byte
+// offset (one of three x offsets for the loads, one for every store), which
+// maps onto the global_load/store "saddr + voffset" form.  Needs per-plane
+// byte offsets below 4 GiB.
+
+template <typename X>
+__device__ __forceinline__ X ld_off(const void* base, uint32_t byte_off)
+{
+    return *(const X*)((const char*)base + byte_off);
+}
+
+template <bool NT, typename X>
+__device__ __forceinline__ void st_off(void* base, uint32_t byte_off, X v)
+{
+    X* p = (X*)((char*)base + byte_off);
+    if constexpr (NT) {
+        if constexpr (sizeof(X) == 16) {
+            typedef int i4 __attribute__((ext_vector_type(4)));
+            __builtin_nontemporal_store(__builtin_bit_cast(i4, v), (i4*)p);
+        } else if constexpr (sizeof(X) == 8) {
+            __builtin_nontemporal_store(__builtin_bit_cast(unsigned long long, v), (unsigned long long*)p);
+        } else if constexpr (sizeof(X) == 4) {
+            __builtin_nontemporal_store(__builtin_bit_cast(unsigned, v), (unsigned*)p);
+        } else {
+            __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, v), (unsigned short*)p);
+        }
+    } else {
+        *p = v;
+    }
+}
+
+template <int ST, int V, bool MASK, bool FIELD, bool NT>
+__global__ __launch_bounds__(kBlock) void k_step(const typename storage<ST>::S* __restrict__ src,
+                                                  typename storage<ST>::S* __restrict__ dst, Geom g, int segs,
+                                                  typename storage<ST>::T omega, typename storage<ST>::T rho0,
+                                                  const typename storage<ST>::T* __restrict__ ftab,
+                                                  const typename storage<ST>::T* __restrict__ field,
+                                                  const uint32_t* __restrict__ mask)
+{
+    static_assert(V == 1 || !MASK, "bounce-back masks use one cell per lane");
+    using SS = storage<ST>;
+    using S = typename SS::S;
+    using T = typename SS::T;
+    typedef S vt __attribute__((ext_vector_type(V == 1 ? 2 : V)));
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)));
+    const int row = wave / segs;
+    if (row >= g.rows) return;  // whole wave
+    const int seg = wave - row * segs;
+    const int y = row % g.ny;
+    const int zb = row / g.ny;
+    const int z = zb % g.nz;
+    const int b = zb / g.nz;
+    const int x0 = (seg * 64 + lane) * V;
+    const bool active = x0 < g.nx;
+    // wave-uniform row pointers: rowp[i] = plane i at the source row of direction i
+    const S* srow[3][3];
 #pragma unroll
-    for (int i = 0; i < 27; ++i) dst[(uint64_t)i * g.pstride + c.own] = SS::pack(h[i]);
+    for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int ys = wrap(y - (bb - 1), g.ny);
+            const int zs = wrap(z - (d - 1), g.nz);
+            srow[bb][d] = src + (uint64_t)(((b * g.nz + zs) * g.ny + ys) * g.nxp);
+        }
+    const uint32_t own_row = (uint32_t)row * (uint32_t)g.nxp;
+    T h[V][27];
+    if constexpr (V == 1) {
+        const uint32_t bx[3] = {(uint32_t)wrap(x0 + 1, g.nx) * (uint32_t)sizeof(S), (uint32_t)x0 * (uint32_t)sizeof(S),
+                                (uint32_t)wrap(x0 - 1, g.nx) * (uint32_t)sizeof(S)};
+        uint32_t m = 0;
+        if (MASK) m = active ? mask[own_row + x0] : kSolidBit;
+        if (!active || (m & kSolidBit)) return;
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            const S* plane_row = srow[vel_y(i) + 1][vel_z(i) + 1] + (uint64_t)i * g.pstride;
+            S e;
+            if (MASK && ((m >> i) & 1u))
+                e = ld_off<S>(src + (uint64_t)opposite(i) * g.pstride + own_row, bx[1]);
+            else
+                e = ld_off<S>(plane_row, bx[vel_x(i) + 1]);
+            h[0][i] = SS::load(&e);
+        }
+    } else {
+        const bool whole = g.nx == 64 * V;
+        const bool prev_in_reg = whole || lane > 0;
+        const bool next_in_reg = whole || (lane < 63 && x0 + V < g.nx);
+        const uint32_t bxm = (uint32_t)(x0 == 0 ? g.nx - 1 : x0 - 1) * (uint32_t)sizeof(S);
+        const uint32_t bxp = (uint32_t)(x0 + V >= g.nx ? 0 : x0 + V) * (uint32_t)sizeof(S);
+        const uint32_t bx0 = (uint32_t)x0 * (uint32_t)sizeof(S);
+        vt v[27];
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            const S* plane_row = srow[vel_y(i) + 1][vel_z(i) + 1] + (uint64_t)i * g.pstride;
+            v[i] = active ? ld_off<vt>(plane_row, bx0) : vt(0);
+        }
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            if (vel_x(i) == 0) continue;
+            const bool from_prev = vel_x(i) == 1;
+            S e = lane_shift<S>(from_prev ? v[i][V - 1] : v[i][0], from_prev);
+            const bool in_reg = from_prev ? prev_in_reg : next_in_reg;
+            if (!in_reg && active) {
+                const S* plane_row = srow[vel_y(i) + 1][vel_z(i) + 1] + (uint64_t)i * g.pstride;
+                e = ld_off<S>(plane_row, from_prev ? bxm : bxp);
+            }
+            // place the shifted row into h: cell c of c_x = +1 reads element c-1, of c_x = -1 element c+1
+#pragma unroll
+            for (int c = 0; c < V; ++c) {
+                S src_e;
+                if (from_prev)
+                    src_e = c == 0 ? e : v[i][c - 1];
+                else
+                    src_e = c == V - 1 ? e : v[i][c + 1];
+                h[c][i] = SS::load(&src_e);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            if (vel_x(i) != 0) continue;
+#pragma unroll
+            for (int c = 0; c < V; ++c) {
+                S e = v[i][c];
+                h[c][i] = SS::load(&e);
+            }
+        }
+        if (!active) return;
+    }
+    T Fx[V], Fy[V], Fz[V];
+    if (FIELD) {
+        const uint64_t lin = (uint64_t)row * (uint64_t)g.nx + (uint64_t)x0;
+#pragma unroll
+        for (int c = 0; c < V; ++c) {
+            Fx[c] = field[lin + c];
+            Fy[c] = field[g.ncell + lin + c];
+            Fz[c] = field[2 * g.ncell + lin + c];
+        }
+    } else {
+        const T* fr = ftab + 3 * (b * g.ny + y);
+#pragma unroll
+        for (int c = 0; c < V; ++c) {
+            Fx[c] = fr[0];
+            Fy[c] = fr[1];
+            Fz[c] = fr[2];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < V; ++c) {
+        T rho, ux, uy, uz;
+        collide<T>(h[c], Fx[c], Fy[c], Fz[c], omega, rho0, rho, ux, uy, uz);
+    }
+    const uint32_t bst = (uint32_t)x0 * (uint32_t)sizeof(S);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        S* plane_row = dst + (uint64_t)i * g.pstride + own_row;
+        if constexpr (V == 1) {
+            st_off<NT>(plane_row, bst, SS::pack(h[0][i]));
+        } else {
+            vt o;
+#pragma unroll
+            for (int c = 0; c < V; ++c) o[c] = SS::pack(h[c][i]);
+            st_off<NT>(plane_row, bst, o);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -548,7 +720,7 @@ int make_layout(const cmlbm_params* p, Layout* L)
     if (rows > 0x7fffffffULL) return CMLBM_EINVAL;
     g.rows = (int)rows;
     g.pstride = rows * (uint64_t)g.nxp;
-    if (g.pstride >= (1ULL << 32)) return CMLBM_EINVAL;  // per-plane offsets are 32-bit
+    if (g.pstride * sb >= (1ULL << 32)) return CMLBM_EINVAL;  // per-plane byte offsets are 32-bit
     g.ncell = rows * (uint64_t)p->nx;
     const int nx64 = (p->nx + 63) / 64 * 64;
     g.bx = nx64 < kBlock ? nx64 : kBlock;
@@ -621,29 +793,65 @@ int ensure_mask(cmlbm_lattice* lat, hipStream_t s)
 
 // ---- kernel dispatch over (storage, mask, field)
 
-template <int ST>
-int launch_step_st(cmlbm_lattice* lat, hipStream_t s)
+// Cells per lane of k_step: 16-bit storage reads 4 cells (8 bytes) per lane
+// where the row length allows, everything else one cell per lane.
+int step_lanes(const cmlbm_lattice* lat)
+{
+    if (lat->needs_mask) return 1;
+    if (lat->p.storage == CMLBM_FP16 || lat->p.storage == CMLBM_BF16) {
+        if (lat->g.nx % 4 == 0) return 4;
+        if (lat->g.nx % 2 == 0) return 2;
+    }
+    return 1;
+}
+
+template <int ST, int V, bool MASK, bool FIELD>
+void launch_step_v(cmlbm_lattice* lat, hipStream_t s)
 {
     using SS = storage<ST>;
     using T = typename SS::T;
     const Geom& g = lat->g;
-    const auto* src = (const typename SS::S*)lat->pop[lat->cur];
-    auto* dst = (typename SS::S*)lat->pop[1 - lat->cur];
-    const T omega = (T)(1.0 / lat->p.tau), rho0 = (T)lat->p.rho0;
+    const int segs = (g.nx + 64 * V - 1) / (64 * V);
+    const uint64_t waves = (uint64_t)g.rows * (uint64_t)segs;
+    const dim3 grid((unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64)));
     const T* ftab = (const T*)(lat->scratch + (ST == CMLBM_FP64 ? lat->off_ftab64 : lat->off_ftab32));
-    const T* field = (const T*)lat->field;
-    const uint32_t* m = mask_ptr(lat);
+    k_step<ST, V, MASK, FIELD, true><<<grid, dim3(kBlock), 0, s>>>(
+        (const typename SS::S*)lat->pop[lat->cur], (typename SS::S*)lat->pop[1 - lat->cur], g, segs,
+        (T)(1.0 / lat->p.tau), (T)lat->p.rho0, ftab, (const T*)lat->field, mask_ptr(lat));
+}
+
+template <int ST>
+int launch_step_st(cmlbm_lattice* lat, hipStream_t s)
+{
     const bool F = lat->force_mode == CMLBM_FORCE_FIELD;
+    const int V = step_lanes(lat);
     if (lat->needs_mask) {
         if (F)
-            k_step<ST, true, true><<<grid_of(g), block_of(g), 0, s>>>(src, dst, g, omega, rho0, ftab, field, m);
+            launch_step_v<ST, 1, true, true>(lat, s);
         else
-            k_step<ST, true, false><<<grid_of(g), block_of(g), 0, s>>>(src, dst, g, omega, rho0, ftab, field, m);
+            launch_step_v<ST, 1, true, false>(lat, s);
+    } else if constexpr (ST == CMLBM_FP16 || ST == CMLBM_BF16) {
+        if (V == 4) {
+            if (F)
+                launch_step_v<ST, 4, false, true>(lat, s);
+            else
+                launch_step_v<ST, 4, false, false>(lat, s);
+        } else if (V == 2) {
+            if (F)
+                launch_step_v<ST, 2, false, true>(lat, s);
+            else
+                launch_step_v<ST, 2, false, false>(lat, s);
+        } else {
+            if (F)
+                launch_step_v<ST, 1, false, true>(lat, s);
+            else
+                launch_step_v<ST, 1, false, false>(lat, s);
+        }
     } else {
         if (F)
-            k_step<ST, false, true><<<grid_of(g), block_of(g), 0, s>>>(src, dst, g, omega, rho0, ftab, field, m);
+            launch_step_v<ST, 1, false, true>(lat, s);
         else
-            k_step<ST, false, false><<<grid_of(g), block_of(g), 0, s>>>(src, dst, g, omega, rho0, ftab, field, m);
+            launch_step_v<ST, 1, false, false>(lat, s);
     }
     return launch_check(lat, "step");
 }

@@ -64,6 +64,14 @@ def test_required_bytes_padding():
     assert s2 >= s0 + 3 * 32 * 16 * 16 * 8
 
 
+def test_plane_size_limit():
+    # per-plane byte offsets are 32-bit: 1024^3 FP32 planes (4 GiB) are refused, FP16 ones accepted
+    with pytest.raises(B.CmlbmError):
+        B.required_bytes(req(nx=1024, ny=1024, nz=1024, storage="fp32"))
+    pop, _ = B.required_bytes(req(nx=1024, ny=1024, nz=1024, storage="fp16"))
+    assert pop == 27 * 1024 ** 3 * 2
+
+
 @pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=0.3), dict(tau=float("nan")), dict(nx=0), dict(ny=-1),
                                 dict(nbatch=0), dict(rho0=0.0), dict(storage=7), dict(wall=(2, 0, 0)),
                                 dict(flags=8), dict(nz=1, wall=(0, 0, 1))])
