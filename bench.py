@@ -66,12 +66,12 @@ def time_steps(lat, steps, warmup):
     return e0.elapsed_time(e1) / 1e3, wall
 
 
-def run_gpu(n, storage, steps, warmup):
+def run_gpu(n, storage, steps, warmup, stochastic=False):
     import workloads
     from paper_1905_10182_amd import Lattice
 
     wl = workloads.taylor_green(n, seed=1)
-    lat = Lattice(n, n, n, tau=wl["tau"], storage=storage, device="cuda:0")
+    lat = Lattice(n, n, n, tau=wl["tau"], storage=storage, stochastic=stochastic, device="cuda:0")
     lat.init(wl["rho"], wl["u"])
     del wl
     r0 = lat.reduce()
@@ -156,6 +156,12 @@ def main():
             "hbm_frac": round(r16["bytes_per_launch"] / r16["launch_s"] / 1e9 / HBM_PEAK_GBS, 4),
             "speedup_vs_fp32_glups": round(r16["glups"] / main_run["glups"], 3)}
         print(f"[bench] fp16 {r16['glups']:.2f} GLUPS", file=sys.stderr, flush=True)
+        r16s = run_gpu(n16, "fp16", max(args.steps // 4, 10), max(args.warmup // 4, 5), stochastic=True)
+        extra["fp16_storage_stochastic_rounding"] = {
+            "glups": round(r16s["glups"], 3), "ms_per_step": round(r16s["ms_per_step"], 4),
+            "hbm_frac": round(r16s["bytes_per_launch"] / r16s["launch_s"] / 1e9 / HBM_PEAK_GBS, 4),
+            "speedup_vs_fp32_glups": round(r16s["glups"] / main_run["glups"], 3)}
+        print(f"[bench] fp16 stochastic rounding {r16s['glups']:.2f} GLUPS", file=sys.stderr, flush=True)
     extra["device_copy_gbs"] = round(copy_bandwidth(), 1)
     achieved = main_run["bytes_per_launch"] / main_run["launch_s"] / 1e9
     traffic = measured_traffic()

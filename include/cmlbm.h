@@ -30,8 +30,10 @@
  *   cmlbm_reduce, which waits for its own result.
  * - Not thread-safe per handle; distinct handles are independent.
  * - Storage: populations are stored shifted, s_i = f_i - w_i * rho0, in the
- *   storage type; all arithmetic is FP32 for FP32/FP16/BF16 storage and FP64
- *   for FP64 storage.  16-bit conversions round to nearest even.
+ *   storage type (FP16 stores 256 * s_i so small values stay normal); all
+ *   arithmetic is FP32 for FP32/FP16/BF16 storage and FP64 for FP64 storage.
+ *   16-bit conversions round to nearest even, or stochastically with
+ *   CMLBM_FLAG_STOCHASTIC.
  * - Time: after cmlbm_init the state is the pre-collision f(x, 0); each step
  *   advances t by one.  Moments at time t use the force in effect.
  * - Walls: halfway bounce-back at rest on every axis flagged
@@ -77,6 +79,9 @@ extern "C" {
 /* cmlbm_params.flags */
 #define CMLBM_FLAG_SOLID 1u    /* reserve room for a solid-node mask (cmlbm_set_solid) */
 #define CMLBM_FLAG_RESIDUAL 2u /* reserve room for the velocity snapshot of the residual */
+#define CMLBM_FLAG_STOCHASTIC 4u /* 16-bit storage: stochastic (unbiased) instead of nearest-even rounding
+                                    of the post-collision populations; bits from a counter-based hash
+                                    of (cell, step), so runs are reproducible */
 
 /* cmlbm_reduce: `what` bits and the layout of one row of its output */
 #define CMLBM_REDUCE_RESIDUAL 1u /* compare u with the last snapshot */

@@ -54,20 +54,59 @@ struct storage<CMLBM_FP32> {
     static __device__ __forceinline__ T load(const S* p) { return *p; }
     static __device__ __forceinline__ S pack(T v) { return v; }
 };
+// 16-bit formats.  pack() rounds to nearest even; pack_sr() rounds
+// stochastically: r8 (8 random bits) is added to the top 8 of the discarded
+// FP32 significand bits, together with half a step of the remaining ones
+// (so the truncation of those is unbiased on average), and the discarded bits
+// are cleared.  The value then rounds away from zero with probability equal
+// to its fractional position (resolved to 1/256 of an ulp): an unbiased
+// rounding.  FP16 values carry a factor 2^8 (h * 256 is
+// stored) so that even the smallest shifted populations stay in FP16's
+// normal range, where the bit-level rounding above is exact.
 template <>
 struct storage<CMLBM_FP16> {
     typedef _Float16 S;
     typedef float T;
-    static __device__ __forceinline__ T load(const S* p) { return (float)*p; }
-    static __device__ __forceinline__ S pack(T v) { return (_Float16)v; }  // round to nearest even
+    static __device__ __forceinline__ T load(const S* p) { return (float)*p * 0.00390625f; }
+    static __device__ __forceinline__ S pack(T v) { return (_Float16)(v * 256.0f); }
+    static __device__ __forceinline__ S pack_sr(T v, uint32_t r8)
+    {
+        const uint32_t b = (__builtin_bit_cast(uint32_t, v * 256.0f) + (r8 << 5) + 16u) & 0xFFFFE000u;
+        return (_Float16)__builtin_bit_cast(float, b);  // exact: b has an FP16 significand
+    }
 };
 template <>
 struct storage<CMLBM_BF16> {
     typedef __bf16 S;
     typedef float T;
     static __device__ __forceinline__ T load(const S* p) { return (float)*p; }
-    static __device__ __forceinline__ S pack(T v) { return (__bf16)v; }  // round to nearest even
+    static __device__ __forceinline__ S pack(T v) { return (__bf16)v; }
+    static __device__ __forceinline__ S pack_sr(T v, uint32_t r8)
+    {
+        const uint32_t b = (__builtin_bit_cast(uint32_t, v) + (r8 << 8) + 128u) & 0xFFFF0000u;
+        return __builtin_bit_cast(__bf16, (unsigned short)(b >> 16));
+    }
 };
+
+// Counter-based random bits for stochastic rounding: one hashed 32-bit seed
+// per (cell, step) -- a 32-bit integer finaliser (xor-shift / multiply
+// rounds) -- then an xorshift32 stream, 8 bits per population.
+__device__ __forceinline__ uint32_t mix32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+__device__ __forceinline__ uint32_t xorshift32(uint32_t x)
+{
+    x ^= x << 13;
+    x ^= x >> 17;
+    x ^= x << 5;
+    return x;
+}
 
 size_t storage_bytes(int st) { return st == CMLBM_FP64 ? 8 : st == CMLBM_FP32 ? 4 : 2; }
 
@@ -241,7 +280,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename storage<ST>::S* 
                                                   typename storage<ST>::T omega, typename storage<ST>::T rho0,
                                                   const typename storage<ST>::T* __restrict__ ftab,
                                                   const typename storage<ST>::T* __restrict__ field,
-                                                  const uint32_t* __restrict__ mask)
+                                                  const uint32_t* __restrict__ mask, int sr, uint32_t step)
 {
     static_assert(V == 1 || !MASK, "bounce-back masks use one cell per lane");
     using SS = storage<ST>;
@@ -356,6 +395,34 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename storage<ST>::S* 
         collide<T>(h[c], Fx[c], Fy[c], Fz[c], omega, rho0, rho, ux, uy, uz);
     }
     const uint32_t bst = (uint32_t)x0 * (uint32_t)sizeof(S);
+    if constexpr (sizeof(S) == 2) {
+        if (sr) {  // wave-uniform
+            // stochastic rounding: 7 words of random bits per cell, byte (i % 4) of word i / 4
+            uint32_t rw[V][7];
+#pragma unroll
+            for (int c = 0; c < V; ++c) {
+                const uint32_t lin = (uint32_t)((uint64_t)row * (uint64_t)g.nx + (uint64_t)(x0 + c));
+                uint32_t w = mix32(lin ^ mix32(step * 0x9E3779B9u + 0x632BE5ABu));
+#pragma unroll
+                for (int k = 0; k < 7; ++k) {
+                    w = xorshift32(w | 1u);
+                    rw[c][k] = w;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 27; ++i) {
+                S* plane_row = dst + (uint64_t)i * g.pstride + own_row;
+                vt o;
+#pragma unroll
+                for (int c = 0; c < V; ++c) o[c] = SS::pack_sr(h[c][i], (rw[c][i / 4] >> (8 * (i % 4))) & 0xFFu);
+                if constexpr (V == 1)
+                    st_off<NT>(plane_row, bst, o[0]);
+                else
+                    st_off<NT>(plane_row, bst, o);
+            }
+            return;
+        }
+    }
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         S* plane_row = dst + (uint64_t)i * g.pstride + own_row;
@@ -696,7 +763,7 @@ int validate(const cmlbm_params* p)
     if (p->storage < CMLBM_FP64 || p->storage > CMLBM_BF16) return CMLBM_EINVAL;
     for (int a = 0; a < 3; ++a)
         if (p->wall[a] != CMLBM_PERIODIC && p->wall[a] != CMLBM_BOUNCEBACK) return CMLBM_EINVAL;
-    if (p->flags & ~(CMLBM_FLAG_SOLID | CMLBM_FLAG_RESIDUAL)) return CMLBM_EINVAL;
+    if (p->flags & ~(CMLBM_FLAG_SOLID | CMLBM_FLAG_RESIDUAL | CMLBM_FLAG_STOCHASTIC)) return CMLBM_EINVAL;
     // an axis of extent 1 with walls would bounce everything; periodic is required there
     const int dims[3] = {p->nx, p->ny, p->nz};
     for (int a = 0; a < 3; ++a)
@@ -817,7 +884,8 @@ void launch_step_v(cmlbm_lattice* lat, hipStream_t s)
     const T* ftab = (const T*)(lat->scratch + (ST == CMLBM_FP64 ? lat->off_ftab64 : lat->off_ftab32));
     k_step<ST, V, MASK, FIELD, true><<<grid, dim3(kBlock), 0, s>>>(
         (const typename SS::S*)lat->pop[lat->cur], (typename SS::S*)lat->pop[1 - lat->cur], g, segs,
-        (T)(1.0 / lat->p.tau), (T)lat->p.rho0, ftab, (const T*)lat->field, mask_ptr(lat));
+        (T)(1.0 / lat->p.tau), (T)lat->p.rho0, ftab, (const T*)lat->field, mask_ptr(lat),
+        (lat->p.flags & CMLBM_FLAG_STOCHASTIC) ? 1 : 0, (uint32_t)lat->t);
 }
 
 template <int ST>

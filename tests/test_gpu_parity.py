@@ -247,7 +247,7 @@ def test_16bit_taylor_green_32_error(torch, storage, bound):
 # ---------------------------------------------------------------------------
 # full-size configurations, sampled
 
-def sampled_one_step(torch, n, storage, nsample, seed, dims=None, re=1600.0):
+def sampled_one_step(torch, n, storage, nsample, seed, dims=None, re=1600.0, stochastic=False):
     """One fused step; at nsample random cells s (every cell if nsample is
     None) the oracle collides the exported pre-collision populations P0[:, s]
     and each result f*_i must appear at P1[i, s + c_i]."""
@@ -256,7 +256,7 @@ def sampled_one_step(torch, n, storage, nsample, seed, dims=None, re=1600.0):
     rho, u = wl["rho"], wl["u"]
     if dims is not None:  # a periodic box cut from a larger vortex: still a valid state
         rho, u = rho[:, :nz, :ny, :nx], u[:, :, :nz, :ny, :nx]
-    lat = Lat(nx=nx, ny=ny, nz=nz, tau=wl["tau"], storage=storage)
+    lat = Lat(nx=nx, ny=ny, nz=nz, tau=wl["tau"], storage=storage, stochastic=stochastic)
     lat.init(rho, u)
     del wl, rho, u
     if nsample is None:
@@ -284,9 +284,10 @@ def sampled_one_step(torch, n, storage, nsample, seed, dims=None, re=1600.0):
 
 
 def ulp16(h, storage):
-    """Spacing of the 16-bit format at |h| (FP16 via numpy, BF16: 8-bit significand)."""
+    """Spacing of the stored 16-bit value at |h|: FP16 holds 256 h, BF16 holds h
+    with an 8-bit significand."""
     if storage == "fp16":
-        return np.spacing(np.abs(h).astype(np.float16)).astype(np.float64)
+        return np.spacing((np.abs(h) * 256).astype(np.float16)).astype(np.float64) / 256
     a = np.maximum(np.abs(h).astype(np.float32), np.float32(2.0 ** -126))
     return np.ldexp(1.0, np.floor(np.log2(a)).astype(np.int64) - 7)
 
@@ -307,6 +308,27 @@ def test_16bit_one_step_every_cell_is_rounded_oracle(torch, storage, nx):
     ulp = ulp16(h_ref, storage)
     log(f"  max error in ulps {(err / ulp).max():.3f}")
     assert np.all(err <= 0.5 * ulp + 2e-7 * WGT[:, None])
+
+
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+@pytest.mark.parametrize("nx", [40, 37])
+def test_16bit_stochastic_rounding_is_unbiased(torch, storage, nx):
+    """Stochastic rounding: every stored population is one of the two 16-bit
+    neighbours of the oracle's value (|error| <= 1 ulp + FP32 error), and the
+    signed error averages to zero (unbiased) over the ~130k populations."""
+    log(f"{storage} stochastic rounding, one step, {nx}x12x10")
+    got, ref = sampled_one_step(torch, 64, storage, None, 0, dims=(nx, 12, 10), re=200.0, stochastic=True)
+    h_ref = ref - WGT[:, None]
+    d = (got - WGT[:, None]) - h_ref
+    ulp = ulp16(h_ref, storage)
+    assert np.all(np.abs(d) <= ulp + 2e-7 * WGT[:, None])
+    big = np.abs(h_ref) > 1e-4 * WGT[:, None]  # skip values that are exact zeros
+    mean = float(np.mean(d[big] / ulp[big]))
+    frac_away = float(np.mean(np.abs(got - WGT[:, None])[big] > np.abs(h_ref)[big]))
+    log(f"  mean signed error {mean:+.4f} ulp, rounded away from zero {frac_away:.3f}")
+    assert abs(mean) < 0.01
+    got2, _ = sampled_one_step(torch, 64, storage, None, 0, dims=(nx, 12, 10), re=200.0, stochastic=True)
+    assert np.array_equal(got, got2)  # counter-based bits: reproducible
 
 
 def test_full_size_taylor_green_256_fp32_sampled(torch):
