@@ -1,0 +1,110 @@
+/*
+ * cmnn.h -- C ABI of the gfx950 kernels of the learned warm start: a small
+ * 3D convolutional U-Net trained on the GPU to predict the steady velocity of
+ * forced obstacle channels, whose prediction initialises the lattice
+ * Boltzmann solver of cmlbm.h (an extension of the method of De Rosis, Huang
+ * & Coreixas, PRE 2019; the paper itself has no learned component).
+ *
+ * Conventions
+ * - Activations are BF16, layout NDHWC: [n][d][h][w][c], c fastest, with the
+ *   channel count padded to a multiple of 32 (CMNN_CALIGN); padded channels
+ *   hold zeros.  d, h, w are the lattice z, y, x axes.
+ * - Convolutions are 3x3x3, stride 1, "same" size.  Per axis the padding is
+ *   periodic (the lattice's periodic axes) or zero (the wall axis).  Tap
+ *   t = (dz+1)*9 + (dy+1)*3 + (dx+1) reads the input at (d+dz, h+dy, w+dx):
+ *   a cross-correlation, y[v][co] = sum_t sum_ci x[v + off(t)][ci] w[t][co][ci].
+ * - Forward weights are BF16 [27][cout][cin] (cin fastest), bias FP32 [cout].
+ *   The data gradient uses the transposed copy [27][cin][cout] written by
+ *   cmnn_pack_weights.  Weight and bias gradients are FP32.
+ * - Products run on BF16 MFMA (v_mfma_f32_16x16x32_bf16) with FP32
+ *   accumulation; elementwise work is FP32 arithmetic on BF16 storage.
+ * - Every function enqueues on hip_stream (NULL = null stream), returns 0 or
+ *   a negative CMNN_E* code, checks its arguments on the host first and
+ *   never allocates: buffers are caller-owned device memory, 16-byte aligned.
+ */
+#ifndef CMNN_H
+#define CMNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CMNN_OK 0
+#define CMNN_EINVAL (-1) /* bad argument; nothing enqueued */
+#define CMNN_EHIP (-3)   /* HIP launch failure */
+
+#define CMNN_CALIGN 32 /* channel padding of every activation tensor */
+
+#define CMNN_ACT_NONE 0
+#define CMNN_ACT_LEAKY 1 /* leaky ReLU, slope 0.1 for negative inputs */
+
+typedef struct {
+    int32_t n, d, h, w;   /* batch and spatial extent (z, y, x) */
+    int32_t periodic[3];  /* d, h, w axes: 1 periodic padding, 0 zero padding */
+} cmnn_geom;
+
+/* y = act(conv3x3x3(x, w) + bias).  x [n][d][h][w][cin], y [..][cout]. */
+int cmnn_conv3d_fwd(const cmnn_geom* g, const void* x, int32_t cin, const void* w, const float* bias,
+                    int32_t cout, int32_t act, void* y, void* hip_stream);
+
+/* dx = transposed convolution of dy (pre-activation gradient) with the
+ * transposed weights w_t [27][cin][cout]; dx [..][cin], dy [..][cout]. */
+int cmnn_conv3d_bwd_data(const cmnn_geom* g, const void* dy, int32_t cout, const void* w_t, int32_t cin, void* dx,
+                         void* hip_stream);
+
+/* Workspace bytes needed by cmnn_conv3d_bwd_weight. */
+int cmnn_conv3d_bwd_weight_workspace(const cmnn_geom* g, int32_t cin, int32_t cout, size_t* bytes);
+
+/* dw[t][co][ci] = sum_v dy[v][co] x[v + off(t)][ci] and dbias[co] = sum_v dy[v][co]
+ * (dbias may be NULL), FP32, overwritten.  Deterministic: per-chunk partials
+ * in the workspace are summed in a fixed order. */
+int cmnn_conv3d_bwd_weight(const cmnn_geom* g, const void* x, int32_t cin, const void* dy, int32_t cout, float* dw,
+                           float* dbias, void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* dpre = dy * act'(.) evaluated from the activation output y; n elements. */
+int cmnn_act_bwd(const void* y, const void* dy, void* dpre, size_t n, int32_t act, void* hip_stream);
+
+/* 2x2x2 average pooling; g is the fine geometry (d, h, w even). */
+int cmnn_pool2_fwd(const cmnn_geom* g, const void* x, int32_t c, void* y, void* hip_stream);
+int cmnn_pool2_bwd(const cmnn_geom* g, const void* dy, int32_t c, void* dx, void* hip_stream);
+
+/* 2x nearest upsampling; g is the coarse geometry. */
+int cmnn_up2_fwd(const cmnn_geom* g, const void* x, int32_t c, void* y, void* hip_stream);
+int cmnn_up2_bwd(const cmnn_geom* g, const void* dy, int32_t c, void* dx, void* hip_stream);
+
+/* Channel concatenation y = [a | b] over nvox voxels, and its split. */
+int cmnn_concat_fwd(size_t nvox, const void* a, int32_t ca, const void* b, int32_t cb, void* y, void* hip_stream);
+int cmnn_concat_bwd(size_t nvox, const void* dy, int32_t ca, int32_t cb, void* da, void* db, void* hip_stream);
+
+/* y = a + b elementwise (BF16), n elements. */
+int cmnn_add(size_t n, const void* a, const void* b, void* y, void* hip_stream);
+
+/* Masked mean-squared error over the first creal channels of pred
+ * [nvox][c] against target [creal][nvox] (FP32), weight [nvox] (FP32, e.g.
+ * 1 on fluid cells): loss = sum_v wt_v sum_k (p - t)^2 / (creal sum_v wt_v)
+ * into loss_out[0] and the normaliser creal sum_v wt_v into loss_out[1]
+ * (device FP32[2]), and, if dpred is not NULL, the gradient into dpred (BF16
+ * [nvox][c], zero in padded channels).  workspace: cmnn_mse_workspace bytes. */
+int cmnn_mse_workspace(size_t nvox, size_t* bytes);
+int cmnn_mse(size_t nvox, const void* pred, int32_t c, int32_t creal, const float* target, const float* weight,
+             float* loss_out, void* dpred, void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* Adam with decoupled weight decay on FP32 master parameters (step >= 1). */
+int cmnn_adam(size_t n, float* param, const float* grad, float* m, float* v, float lr, float beta1, float beta2,
+              float eps, float weight_decay, int32_t step, void* hip_stream);
+
+/* BF16 forward weights [27][cout][cin] and transposed [27][cin][cout] from
+ * FP32 master weights [27][cout][cin]. */
+int cmnn_pack_weights(const float* w, int32_t cin, int32_t cout, void* w_fwd, void* w_t, void* hip_stream);
+
+/* FP32 planar [cs][nvox] -> BF16 NDHWC [nvox][c] (c >= cs, rest zero), and back. */
+int cmnn_pack_channels(size_t nvox, const float* src, int32_t cs, void* dst, int32_t c, void* hip_stream);
+int cmnn_unpack_channels(size_t nvox, const void* src, int32_t c, float* dst, int32_t cs, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CMNN_H */

@@ -3,7 +3,8 @@
     python -m paper_1905_10182_amd.build
 
 produces paper_1905_10182_amd/libcmlbm.so (the solver, C ABI in
-include/cmlbm.h).  Cross-compiles on a machine without a GPU.
+include/cmlbm.h) and libcmnn.so (the warm-start network kernels, C ABI in
+include/cmnn.h).  Cross-compiles on a machine without a GPU.
 """
 import os
 import subprocess
@@ -22,6 +23,7 @@ HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
 
 LIBS = {
     "libcmlbm.so": ["cmlbm.hip"],
+    "libcmnn.so": ["cmnn.hip"],
 }
 
 

@@ -1,0 +1,167 @@
+"""Python binding of libcmnn (C ABI in include/cmnn.h): argument marshalling
+for torch device tensors.  All arithmetic runs in the HIP kernels; the module
+raises if the library is missing (no CPU fallback)."""
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libcmnn.so")
+
+OK, EINVAL, EHIP = 0, -1, -3
+CALIGN = 32
+ACT_NONE, ACT_LEAKY = 0, 1
+
+EXPORTS = ["cmnn_conv3d_fwd", "cmnn_conv3d_bwd_data", "cmnn_conv3d_bwd_weight_workspace", "cmnn_conv3d_bwd_weight",
+           "cmnn_act_bwd", "cmnn_pool2_fwd", "cmnn_pool2_bwd", "cmnn_up2_fwd", "cmnn_up2_bwd", "cmnn_concat_fwd",
+           "cmnn_concat_bwd", "cmnn_add", "cmnn_mse_workspace", "cmnn_mse", "cmnn_adam", "cmnn_pack_weights",
+           "cmnn_pack_channels", "cmnn_unpack_channels"]
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("d", ctypes.c_int32), ("h", ctypes.c_int32), ("w", ctypes.c_int32),
+                ("periodic", ctypes.c_int32 * 3)]
+
+
+def geom(n, d, h, w, periodic=(1, 0, 1)):
+    g = Geom()
+    g.n, g.d, g.h, g.w = int(n), int(d), int(h), int(w)
+    for a in range(3):
+        g.periodic[a] = int(periodic[a])
+    return g
+
+
+class CmnnError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load_library():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise OSError(f"{LIB_PATH} is missing: build it with `python -m paper_1905_10182_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, sz, i32, f32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_float
+    G = ctypes.POINTER(Geom)
+    lib.cmnn_conv3d_fwd.argtypes = [G, vp, i32, vp, vp, i32, i32, vp, vp]
+    lib.cmnn_conv3d_bwd_data.argtypes = [G, vp, i32, vp, i32, vp, vp]
+    lib.cmnn_conv3d_bwd_weight_workspace.argtypes = [G, i32, i32, ctypes.POINTER(sz)]
+    lib.cmnn_conv3d_bwd_weight.argtypes = [G, vp, i32, vp, i32, vp, vp, vp, sz, vp]
+    lib.cmnn_act_bwd.argtypes = [vp, vp, vp, sz, i32, vp]
+    for f in (lib.cmnn_pool2_fwd, lib.cmnn_pool2_bwd, lib.cmnn_up2_fwd, lib.cmnn_up2_bwd):
+        f.argtypes = [G, vp, i32, vp, vp]
+    lib.cmnn_concat_fwd.argtypes = [sz, vp, i32, vp, i32, vp, vp]
+    lib.cmnn_concat_bwd.argtypes = [sz, vp, i32, i32, vp, vp, vp]
+    lib.cmnn_add.argtypes = [sz, vp, vp, vp, vp]
+    lib.cmnn_mse_workspace.argtypes = [sz, ctypes.POINTER(sz)]
+    lib.cmnn_mse.argtypes = [sz, vp, i32, i32, vp, vp, vp, vp, vp, sz, vp]
+    lib.cmnn_adam.argtypes = [sz, vp, vp, vp, vp, f32, f32, f32, f32, f32, i32, vp]
+    lib.cmnn_pack_weights.argtypes = [vp, i32, i32, vp, vp, vp]
+    lib.cmnn_pack_channels.argtypes = [sz, vp, i32, vp, i32, vp]
+    lib.cmnn_unpack_channels.argtypes = [sz, vp, i32, vp, i32, vp]
+    for name in EXPORTS:
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _s():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check(rc, what):
+    if rc != OK:
+        raise CmnnError(f"{what} failed with status {rc}")
+
+
+def nvox(g):
+    return g.n * g.d * g.h * g.w
+
+
+def conv_fwd(g, x, cin, w, b, cout, act, y):
+    _check(load_library().cmnn_conv3d_fwd(ctypes.byref(g), _p(x), cin, _p(w), _p(b), cout, act, _p(y), _s()),
+           "conv3d_fwd")
+
+
+def conv_bwd_data(g, dy, cout, w_t, cin, dx):
+    _check(load_library().cmnn_conv3d_bwd_data(ctypes.byref(g), _p(dy), cout, _p(w_t), cin, _p(dx), _s()),
+           "conv3d_bwd_data")
+
+
+def conv_bwd_weight_workspace(g, cin, cout):
+    n = ctypes.c_size_t()
+    _check(load_library().cmnn_conv3d_bwd_weight_workspace(ctypes.byref(g), cin, cout, ctypes.byref(n)),
+           "bwd_weight_workspace")
+    return n.value
+
+
+def conv_bwd_weight(g, x, cin, dy, cout, dw, db, ws):
+    _check(load_library().cmnn_conv3d_bwd_weight(ctypes.byref(g), _p(x), cin, _p(dy), cout, _p(dw), _p(db), _p(ws),
+                                                 ws.numel() * ws.element_size(), _s()), "conv3d_bwd_weight")
+
+
+def act_bwd(y, dy, dpre, act=ACT_LEAKY):
+    _check(load_library().cmnn_act_bwd(_p(y), _p(dy), _p(dpre), y.numel(), act, _s()), "act_bwd")
+
+
+def pool2_fwd(g, x, c, y):
+    _check(load_library().cmnn_pool2_fwd(ctypes.byref(g), _p(x), c, _p(y), _s()), "pool2_fwd")
+
+
+def pool2_bwd(g, dy, c, dx):
+    _check(load_library().cmnn_pool2_bwd(ctypes.byref(g), _p(dy), c, _p(dx), _s()), "pool2_bwd")
+
+
+def up2_fwd(g, x, c, y):
+    _check(load_library().cmnn_up2_fwd(ctypes.byref(g), _p(x), c, _p(y), _s()), "up2_fwd")
+
+
+def up2_bwd(g, dy, c, dx):
+    _check(load_library().cmnn_up2_bwd(ctypes.byref(g), _p(dy), c, _p(dx), _s()), "up2_bwd")
+
+
+def concat_fwd(nv, a, ca, b, cb, y):
+    _check(load_library().cmnn_concat_fwd(nv, _p(a), ca, _p(b), cb, _p(y), _s()), "concat_fwd")
+
+
+def concat_bwd(nv, dy, ca, cb, da, db):
+    _check(load_library().cmnn_concat_bwd(nv, _p(dy), ca, cb, _p(da), _p(db), _s()), "concat_bwd")
+
+
+def add(a, b, y):
+    _check(load_library().cmnn_add(a.numel(), _p(a), _p(b), _p(y), _s()), "add")
+
+
+def mse_workspace(nv):
+    n = ctypes.c_size_t()
+    _check(load_library().cmnn_mse_workspace(nv, ctypes.byref(n)), "mse_workspace")
+    return n.value
+
+
+def mse(nv, pred, c, creal, target, weight, loss2, dpred, ws):
+    _check(load_library().cmnn_mse(nv, _p(pred), c, creal, _p(target), _p(weight), _p(loss2), _p(dpred), _p(ws),
+                                   ws.numel() * ws.element_size(), _s()), "mse")
+
+
+def adam(p, g, m, v, lr, b1, b2, eps, wd, step):
+    _check(load_library().cmnn_adam(p.numel(), _p(p), _p(g), _p(m), _p(v), lr, b1, b2, eps, wd, step, _s()), "adam")
+
+
+def pack_weights(w, cin, cout, w_fwd, w_t):
+    _check(load_library().cmnn_pack_weights(_p(w), cin, cout, _p(w_fwd), _p(w_t), _s()), "pack_weights")
+
+
+def pack_channels(nv, src, cs, dst, c):
+    _check(load_library().cmnn_pack_channels(nv, _p(src), cs, _p(dst), c, _s()), "pack_channels")
+
+
+def unpack_channels(nv, src, c, dst, cs):
+    _check(load_library().cmnn_unpack_channels(nv, _p(src), c, _p(dst), cs, _s()), "unpack_channels")

@@ -1,0 +1,697 @@
+// libcmnn: gfx950 kernels of the learned warm start (C ABI in include/cmnn.h).
+//
+// Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16.  Operand
+// layout of that instruction (checked on the hardware): lane l holds
+// A[l % 16][(l / 16) * 8 + i] and B[(l / 16) * 8 + i][l % 16] for i < 8, and
+// receives D[(l / 16) * 4 + i][l % 16] for i < 4.
+//
+//   k_conv_fwd      y[v][co] = act(sum_t sum_ci x[v + s*off(t)][ci] w[t][co][ci] + b[co])
+//                   (s = +1; the data gradient is the same kernel with s = -1 and
+//                   the transposed weights).  A = 16 voxels x 32 input channels,
+//                   one 16-byte load per lane; B = 32 channels x 16 outputs.
+//   k_conv_bwd_w    dw[t][co][ci] = sum_v dy[v][co] x[v + off(t)][ci]: the voxel
+//                   axis is the MFMA K axis, so 32-voxel tiles of dy and x are
+//                   staged through LDS transposed (channel-major) and read back
+//                   as 16-byte fragments; per-chunk partials, fixed-order sum.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "cmnn.h"
+
+namespace {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
+constexpr float kLeak = 0.1f;
+
+struct G {
+    int n, d, h, w;
+    int per[3];
+    long long nvox;
+};
+
+G make_g(const cmnn_geom* g)
+{
+    G r;
+    r.n = g->n;
+    r.d = g->d;
+    r.h = g->h;
+    r.w = g->w;
+    for (int a = 0; a < 3; ++a) r.per[a] = g->periodic[a];
+    r.nvox = (long long)g->n * g->d * g->h * g->w;
+    return r;
+}
+
+bool geom_ok(const cmnn_geom* g)
+{
+    return g && g->n > 0 && g->d > 0 && g->h > 0 && g->w > 0;
+}
+bool chan_ok(int c) { return c > 0 && c % CMNN_CALIGN == 0; }
+bool al16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+__device__ __forceinline__ bool shift_axis(int v, int dv, int n, int periodic, int& out)
+{
+    int s = v + dv;
+    if (s < 0 || s >= n) {
+        if (!periodic) return false;
+        s = s < 0 ? s + n : s - n;
+    }
+    out = s;
+    return true;
+}
+
+// Neighbour voxel of linear voxel m along tap t (sign s = +1 or -1); false if
+// it falls into zero padding.
+__device__ __forceinline__ bool neighbour(const G& g, long long m, int t, int s, long long& out)
+{
+    const int w = (int)(m % g.w);
+    long long r = m / g.w;
+    const int h = (int)(r % g.h);
+    r /= g.h;
+    const int d = (int)(r % g.d);
+    const long long n = r / g.d;
+    const int dz = s * (t / 9 - 1), dy = s * ((t / 3) % 3 - 1), dx = s * (t % 3 - 1);
+    int nd, nh, nw;
+    if (!shift_axis(d, dz, g.d, g.per[0], nd)) return false;
+    if (!shift_axis(h, dy, g.h, g.per[1], nh)) return false;
+    if (!shift_axis(w, dx, g.w, g.per[2], nw)) return false;
+    out = ((n * g.d + nd) * g.h + nh) * g.w + nw;
+    return true;
+}
+
+__device__ __forceinline__ bf16x8 ld8(const bf16* p) { return __builtin_bit_cast(bf16x8, *(const u4*)p); }
+
+// ---------------------------------------------------------------------------
+// forward convolution (and, with SIGN = -1, the data gradient)
+//
+// Workgroup = 4 waves = 64 consecutive voxels x (16 * NB) output channels;
+// wave w owns voxels [16w, 16w + 16) and NB 16-channel output blocks.
+
+template <int NB, int SIGN, int ACT>
+__global__ __launch_bounds__(256) void k_conv_fwd(G g, const bf16* __restrict__ x, int cin, const bf16* __restrict__ wt,
+                                                  const float* __restrict__ bias, int cout, bf16* __restrict__ y)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long long m0 = (long long)blockIdx.x * 64 + wave * 16;
+    const int co0 = blockIdx.y * 16 * NB;
+    const long long mrow = m0 + (lane & 15);  // voxel of this lane's A row
+    const int kq = lane >> 4;
+    f4 acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < 27; ++t) {
+        long long src = 0;
+        const bool valid = mrow < g.nvox && neighbour(g, mrow, t, SIGN, src);
+        const bf16* xp = x + src * cin + kq * 8;
+        const bf16* wp = wt + ((long long)t * cout + co0 + (lane & 15)) * cin + kq * 8;
+        for (int c0 = 0; c0 < cin; c0 += 32) {
+            bf16x8 a;
+            if (valid)
+                a = ld8(xp + c0);
+            else
+                a = __builtin_bit_cast(bf16x8, u4{0u, 0u, 0u, 0u});
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const bf16x8 bw = ld8(wp + (long long)b * 16 * cin + c0);
+                acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw, acc[b], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int co = co0 + 16 * b + (lane & 15);
+        const float bb = bias ? bias[co] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const long long m = m0 + kq * 4 + i;
+            if (m >= g.nvox) continue;
+            float v = acc[b][i] + bb;
+            if (ACT == CMNN_ACT_LEAKY) v = v > 0.f ? v : kLeak * v;
+            y[m * cout + co] = (bf16)v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// weight gradient
+//
+// Workgroup (chunk, tap, co tile of 32, ci tile of 32) accumulates over the
+// chunk's voxels in steps of 32: 128 threads stage dy[32 voxels][32 co] and
+// 128 stage x[32 shifted voxels][32 ci] into LDS transposed ([channel][voxel],
+// rows padded to 40 elements = 80 bytes, 16-byte aligned); wave w then
+// computes the 16 x 16 block (co block w / 2, ci block w % 2).
+
+constexpr int kLdsRow = 40;
+
+__global__ __launch_bounds__(256) void k_conv_bwd_w(G g, const bf16* __restrict__ x, int cin,
+                                                    const bf16* __restrict__ dy, int cout, long long chunk,
+                                                    float* __restrict__ part)
+{
+    __shared__ __attribute__((aligned(16))) bf16 sdy[32 * kLdsRow];
+    __shared__ __attribute__((aligned(16))) bf16 sx[32 * kLdsRow];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ct = cout / 32, it = cin / 32;
+    int bid = blockIdx.x;
+    const int cit = bid % it;
+    bid /= it;
+    const int cot = bid % ct;
+    bid /= ct;
+    const int t = bid % 27;
+    const long long ch = bid / 27;
+    const long long v0 = ch * chunk;
+    const long long v1 = v0 + chunk < g.nvox ? v0 + chunk : g.nvox;
+    // staging role: threads 0..127 load dy, 128..255 load x; each 16 bytes (8 channels) of one voxel
+    const int st = tid & 127, sv = st >> 2, sc = (st & 3) * 8;
+    f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+    const int cob = wave >> 1, cib = wave & 1;
+    for (long long vb = v0; vb < v1; vb += 32) {
+        const long long v = vb + sv;
+        bf16x8 e = __builtin_bit_cast(bf16x8, u4{0u, 0u, 0u, 0u});
+        if (tid < 128) {
+            if (v < v1) e = ld8(dy + v * cout + cot * 32 + sc);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) sdy[(sc + i) * kLdsRow + sv] = e[i];
+        } else {
+            long long s;
+            if (v < v1 && neighbour(g, v, t, 1, s)) e = ld8(x + s * cin + cit * 32 + sc);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) sx[(sc + i) * kLdsRow + sv] = e[i];
+        }
+        __syncthreads();
+        const bf16x8 a = *(const bf16x8*)&sdy[(cob * 16 + (lane & 15)) * kLdsRow + (lane >> 4) * 8];
+        const bf16x8 b = *(const bf16x8*)&sx[(cib * 16 + (lane & 15)) * kLdsRow + (lane >> 4) * 8];
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+        __syncthreads();
+    }
+    // D[co][ci]: row (lane/16)*4 + i, column lane % 16
+    float* p = part + ((ch * 27 + t) * (long long)cout) * cin;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int co = cot * 32 + cob * 16 + (lane >> 4) * 4 + i;
+        const int ci = cit * 32 + cib * 16 + (lane & 15);
+        p[(long long)co * cin + ci] = acc[i];
+    }
+}
+
+__global__ void k_sum_chunks(const float* __restrict__ part, long long per, int nchunk, float* __restrict__ out)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < per; i += (long long)gridDim.x * blockDim.x) {
+        float s = 0.f;
+        for (int c = 0; c < nchunk; ++c) s += part[(long long)c * per + i];
+        out[i] = s;
+    }
+}
+
+// Per-chunk column sums of a [rows][cols] BF16 matrix (cols <= 256): thread t
+// sums column t % cols over every (256 / cols)-th row of the block's chunk,
+// then the row groups are added in LDS in a fixed order.
+constexpr int kColSumBlocks = 1024;
+
+__global__ __launch_bounds__(256) void k_colsum_part(const bf16* __restrict__ a, long long rows, int cols,
+                                                     long long chunk, float* __restrict__ part)
+{
+    __shared__ float sh[256];
+    const int t = threadIdx.x;
+    const int rpi = 256 / cols;
+    const int c = t % cols, roff = t / cols;
+    const long long r0 = (long long)blockIdx.x * chunk;
+    const long long r1 = r0 + chunk < rows ? r0 + chunk : rows;
+    float s = 0.f;
+    if (roff < rpi)
+        for (long long r = r0 + roff; r < r1; r += rpi) s += (float)a[r * cols + c];
+    sh[t] = s;
+    __syncthreads();
+    if (t < cols) {
+        float q = 0.f;
+        for (int k = 0; k < rpi; ++k) q += sh[k * cols + t];
+        part[(long long)blockIdx.x * cols + t] = q;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// elementwise
+
+__global__ void k_act_bwd(const bf16* __restrict__ y, const bf16* __restrict__ dy, bf16* __restrict__ dp, long long n,
+                          int act)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        float d = (float)dy[i];
+        if (act == CMNN_ACT_LEAKY && (float)y[i] <= 0.f) d *= kLeak;
+        dp[i] = (bf16)d;
+    }
+}
+
+__global__ void k_pool2_fwd(G g, const bf16* __restrict__ x, int c, bf16* __restrict__ y)
+{
+    const int d2 = g.d / 2, h2 = g.h / 2, w2 = g.w / 2;
+    const long long total = (long long)g.n * d2 * h2 * w2 * c;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int ch = (int)(i % c);
+        long long r = i / c;
+        const int w = (int)(r % w2);
+        r /= w2;
+        const int h = (int)(r % h2);
+        r /= h2;
+        const int d = (int)(r % d2);
+        const long long n = r / d2;
+        float s = 0.f;
+        for (int k = 0; k < 8; ++k) {
+            const long long v = ((n * g.d + 2 * d + (k >> 2)) * g.h + 2 * h + ((k >> 1) & 1)) * g.w + 2 * w + (k & 1);
+            s += (float)x[v * c + ch];
+        }
+        y[i] = (bf16)(0.125f * s);
+    }
+}
+
+__global__ void k_pool2_bwd(G g, const bf16* __restrict__ dy, int c, bf16* __restrict__ dx)
+{
+    const long long total = g.nvox * c;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int ch = (int)(i % c);
+        long long r = i / c;
+        const int w = (int)(r % g.w);
+        r /= g.w;
+        const int h = (int)(r % g.h);
+        r /= g.h;
+        const int d = (int)(r % g.d);
+        const long long n = r / g.d;
+        const long long v = ((n * (g.d / 2) + d / 2) * (g.h / 2) + h / 2) * (g.w / 2) + w / 2;
+        dx[i] = (bf16)(0.125f * (float)dy[v * c + ch]);
+    }
+}
+
+// coarse geometry g; fine voxel (2d + a, 2h + b, 2w + e) copies coarse (d, h, w)
+__global__ void k_up2_fwd(G g, const bf16* __restrict__ x, int c, bf16* __restrict__ y)
+{
+    const int D = 2 * g.d, H = 2 * g.h, W = 2 * g.w;
+    const long long total = (long long)g.n * D * H * W * c;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int ch = (int)(i % c);
+        long long r = i / c;
+        const int w = (int)(r % W);
+        r /= W;
+        const int h = (int)(r % H);
+        r /= H;
+        const int d = (int)(r % D);
+        const long long n = r / D;
+        const long long v = ((n * g.d + d / 2) * g.h + h / 2) * g.w + w / 2;
+        y[i] = x[v * c + ch];
+    }
+}
+
+__global__ void k_up2_bwd(G g, const bf16* __restrict__ dy, int c, bf16* __restrict__ dx)
+{
+    const int H = 2 * g.h, W = 2 * g.w;
+    const long long total = g.nvox * c;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int ch = (int)(i % c);
+        long long r = i / c;
+        const int w = (int)(r % g.w);
+        r /= g.w;
+        const int h = (int)(r % g.h);
+        r /= g.h;
+        const int d = (int)(r % g.d);
+        const long long n = r / g.d;
+        float s = 0.f;
+        for (int k = 0; k < 8; ++k) {
+            const long long v = ((n * (2 * g.d) + 2 * d + (k >> 2)) * H + 2 * h + ((k >> 1) & 1)) * W + 2 * w + (k & 1);
+            s += (float)dy[v * c + ch];
+        }
+        dx[i] = (bf16)s;
+    }
+}
+
+__global__ void k_concat_fwd(long long nvox, const bf16* __restrict__ a, int ca, const bf16* __restrict__ b, int cb,
+                             bf16* __restrict__ y)
+{
+    const int c = ca + cb;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nvox * c;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long v = i / c;
+        const int ch = (int)(i % c);
+        y[i] = ch < ca ? a[v * ca + ch] : b[v * cb + ch - ca];
+    }
+}
+
+__global__ void k_concat_bwd(long long nvox, const bf16* __restrict__ dy, int ca, int cb, bf16* __restrict__ da,
+                             bf16* __restrict__ db)
+{
+    const int c = ca + cb;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nvox * c;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long v = i / c;
+        const int ch = (int)(i % c);
+        if (ch < ca) {
+            if (da) da[v * ca + ch] = dy[i];
+        } else if (db) {
+            db[v * cb + ch - ca] = dy[i];
+        }
+    }
+}
+
+__global__ void k_add(long long n, const bf16* __restrict__ a, const bf16* __restrict__ b, bf16* __restrict__ y)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        y[i] = (bf16)((float)a[i] + (float)b[i]);
+}
+
+// masked MSE: per-block partial (sum wt * sq, sum wt), then a single-block final
+constexpr int kMseBlocks = 1024;
+
+__global__ __launch_bounds__(256) void k_mse_part(long long nvox, const bf16* __restrict__ pred, int c, int creal,
+                                                  const float* __restrict__ tgt, const float* __restrict__ wt,
+                                                  float* __restrict__ part)
+{
+    __shared__ float s0[256], s1[256];
+    float a = 0.f, b = 0.f;
+    for (long long v = (long long)blockIdx.x * 256 + threadIdx.x; v < nvox; v += (long long)gridDim.x * 256) {
+        const float w = wt[v];
+        float q = 0.f;
+        for (int k = 0; k < creal; ++k) {
+            const float d = (float)pred[v * c + k] - tgt[(long long)k * nvox + v];
+            q += d * d;
+        }
+        a += w * q;
+        b += w;
+    }
+    s0[threadIdx.x] = a;
+    s1[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            s0[threadIdx.x] += s0[threadIdx.x + s];
+            s1[threadIdx.x] += s1[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s0[0];
+        part[2 * blockIdx.x + 1] = s1[0];
+    }
+}
+
+__global__ void k_mse_final(const float* __restrict__ part, int nb, int creal, float* __restrict__ out)
+{
+    if (threadIdx.x != 0) return;
+    float a = 0.f, b = 0.f;
+    for (int i = 0; i < nb; ++i) {
+        a += part[2 * i];
+        b += part[2 * i + 1];
+    }
+    out[0] = b > 0.f ? a / (b * creal) : 0.f;  // loss
+    out[1] = b * creal;                        // normaliser, read by k_mse_grad
+}
+
+__global__ void k_mse_grad(long long nvox, const bf16* __restrict__ pred, int c, int creal,
+                           const float* __restrict__ tgt, const float* __restrict__ wt,
+                           const float* __restrict__ norm, bf16* __restrict__ dpred)
+{
+    const float scale = norm[1] > 0.f ? 2.f / norm[1] : 0.f;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nvox * c;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long v = i / c;
+        const int k = (int)(i % c);
+        float d = 0.f;
+        if (k < creal) d = scale * wt[v] * ((float)pred[i] - tgt[(long long)k * nvox + v]);
+        dpred[i] = (bf16)d;
+    }
+}
+
+__global__ void k_adam(long long n, float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, float lr, float b1, float b2, float eps, float wd, float c1, float c2)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        const float mh = mi / c1, vh = vi / c2;
+        p[i] -= lr * (mh / (sqrtf(vh) + eps) + wd * p[i]);
+    }
+}
+
+__global__ void k_pack_w(const float* __restrict__ w, int cin, int cout, bf16* __restrict__ wf, bf16* __restrict__ wtr)
+{
+    const long long total = 27LL * cin * cout;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int ci = (int)(i % cin);
+        long long r = i / cin;
+        const int co = (int)(r % cout);
+        const int t = (int)(r / cout);
+        const bf16 b = (bf16)w[i];
+        wf[i] = b;
+        wtr[((long long)t * cin + ci) * cout + co] = b;
+    }
+}
+
+__global__ void k_pack_ch(long long nvox, const float* __restrict__ src, int cs, bf16* __restrict__ dst, int c)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nvox * c;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long v = i / c;
+        const int k = (int)(i % c);
+        dst[i] = k < cs ? (bf16)src[(long long)k * nvox + v] : (bf16)0.f;
+    }
+}
+
+__global__ void k_unpack_ch(long long nvox, const bf16* __restrict__ src, int c, float* __restrict__ dst, int cs)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nvox * cs;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int k = (int)(i / nvox);
+        const long long v = i % nvox;
+        dst[i] = (float)src[v * c + k];
+    }
+}
+
+int launched() { return hipGetLastError() == hipSuccess ? CMNN_OK : CMNN_EHIP; }
+
+dim3 grid_for(long long n)
+{
+    long long b = (n + 255) / 256;
+    if (b > 65536) b = 65536;
+    if (b < 1) b = 1;
+    return dim3((unsigned)b);
+}
+
+int bwd_w_chunks(long long nvox)
+{
+    long long c = (nvox + 4095) / 4096;  // at least 4096 voxels per chunk
+    return (int)(c < 64 ? c : 64);
+}
+
+template <int SIGN, int ACT>
+int conv_dispatch(const G& g, const bf16* x, int cin, const bf16* w, const float* bias, int cout, bf16* y,
+                  hipStream_t s)
+{
+    const unsigned mb = (unsigned)((g.nvox + 63) / 64);
+    if (cout % 64 == 0)
+        k_conv_fwd<4, SIGN, ACT><<<dim3(mb, cout / 64), 256, 0, s>>>(g, x, cin, w, bias, cout, y);
+    else
+        k_conv_fwd<2, SIGN, ACT><<<dim3(mb, cout / 32), 256, 0, s>>>(g, x, cin, w, bias, cout, y);
+    return launched();
+}
+
+}  // namespace
+
+extern "C" {
+
+int cmnn_conv3d_fwd(const cmnn_geom* g, const void* x, int32_t cin, const void* w, const float* bias, int32_t cout,
+                    int32_t act, void* y, void* hip_stream)
+{
+    if (!geom_ok(g) || !chan_ok(cin) || !chan_ok(cout) || !x || !w || !y) return CMNN_EINVAL;
+    if (!al16(x) || !al16(w) || act < CMNN_ACT_NONE || act > CMNN_ACT_LEAKY) return CMNN_EINVAL;
+    const G gg = make_g(g);
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (act == CMNN_ACT_LEAKY)
+        return conv_dispatch<1, CMNN_ACT_LEAKY>(gg, (const bf16*)x, cin, (const bf16*)w, bias, cout, (bf16*)y, s);
+    return conv_dispatch<1, CMNN_ACT_NONE>(gg, (const bf16*)x, cin, (const bf16*)w, bias, cout, (bf16*)y, s);
+}
+
+int cmnn_conv3d_bwd_data(const cmnn_geom* g, const void* dy, int32_t cout, const void* w_t, int32_t cin, void* dx,
+                         void* hip_stream)
+{
+    if (!geom_ok(g) || !chan_ok(cin) || !chan_ok(cout) || !dy || !w_t || !dx) return CMNN_EINVAL;
+    if (!al16(dy) || !al16(w_t)) return CMNN_EINVAL;
+    const G gg = make_g(g);
+    // the data gradient is the forward kernel with negated tap offsets, input dy
+    // (cout channels), transposed weights [27][cin][cout] and cin outputs
+    return conv_dispatch<-1, CMNN_ACT_NONE>(gg, (const bf16*)dy, cout, (const bf16*)w_t, nullptr, cin, (bf16*)dx,
+                                            (hipStream_t)hip_stream);
+}
+
+int cmnn_conv3d_bwd_weight_workspace(const cmnn_geom* g, int32_t cin, int32_t cout, size_t* bytes)
+{
+    if (!geom_ok(g) || !chan_ok(cin) || !chan_ok(cout) || !bytes) return CMNN_EINVAL;
+    const G gg = make_g(g);
+    const size_t nc = (size_t)bwd_w_chunks(gg.nvox);
+    *bytes = nc * 27 * (size_t)cin * cout * sizeof(float) + (size_t)kColSumBlocks * cout * sizeof(float);
+    return CMNN_OK;
+}
+
+int cmnn_conv3d_bwd_weight(const cmnn_geom* g, const void* x, int32_t cin, const void* dy, int32_t cout, float* dw,
+                           float* dbias, void* workspace, size_t workspace_bytes, void* hip_stream)
+{
+    size_t need = 0;
+    if (cmnn_conv3d_bwd_weight_workspace(g, cin, cout, &need) != CMNN_OK) return CMNN_EINVAL;
+    if (!x || !dy || !dw || !workspace || workspace_bytes < need || !al16(x) || !al16(dy)) return CMNN_EINVAL;
+    if (cout > 256) return CMNN_EINVAL;
+    const G gg = make_g(g);
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int nc = bwd_w_chunks(gg.nvox);
+    const long long chunk = (gg.nvox + nc - 1) / nc;
+    float* part = (float*)workspace;
+    const unsigned nblk = (unsigned)(nc * 27 * (cout / 32) * (cin / 32));
+    k_conv_bwd_w<<<nblk, 256, 0, s>>>(gg, (const bf16*)x, cin, (const bf16*)dy, cout, chunk, part);
+    if (launched()) return CMNN_EHIP;
+    const long long per = 27LL * cin * cout;
+    k_sum_chunks<<<grid_for(per), 256, 0, s>>>(part, per, nc, dw);
+    if (launched()) return CMNN_EHIP;
+    if (dbias) {
+        float* bpart = part + (long long)nc * per;
+        long long nb = (gg.nvox + 1023) / 1024;
+        if (nb > kColSumBlocks) nb = kColSumBlocks;
+        const long long bchunk = (gg.nvox + nb - 1) / nb;
+        k_colsum_part<<<(unsigned)nb, 256, 0, s>>>((const bf16*)dy, gg.nvox, cout, bchunk, bpart);
+        if (launched()) return CMNN_EHIP;
+        k_sum_chunks<<<1, 256, 0, s>>>(bpart, cout, (int)nb, dbias);
+        if (launched()) return CMNN_EHIP;
+    }
+    return CMNN_OK;
+}
+
+int cmnn_act_bwd(const void* y, const void* dy, void* dpre, size_t n, int32_t act, void* hip_stream)
+{
+    if (!y || !dy || !dpre || act < CMNN_ACT_NONE || act > CMNN_ACT_LEAKY) return CMNN_EINVAL;
+    k_act_bwd<<<grid_for((long long)n), 256, 0, (hipStream_t)hip_stream>>>((const bf16*)y, (const bf16*)dy,
+                                                                         (bf16*)dpre, (long long)n, act);
+    return launched();
+}
+
+int cmnn_pool2_fwd(const cmnn_geom* g, const void* x, int32_t c, void* y, void* hip_stream)
+{
+    if (!geom_ok(g) || c <= 0 || !x || !y || (g->d | g->h | g->w) & 1) return CMNN_EINVAL;
+    const G gg = make_g(g);
+    k_pool2_fwd<<<grid_for(gg.nvox * c / 8), 256, 0, (hipStream_t)hip_stream>>>(gg, (const bf16*)x, c, (bf16*)y);
+    return launched();
+}
+
+int cmnn_pool2_bwd(const cmnn_geom* g, const void* dy, int32_t c, void* dx, void* hip_stream)
+{
+    if (!geom_ok(g) || c <= 0 || !dy || !dx || (g->d | g->h | g->w) & 1) return CMNN_EINVAL;
+    const G gg = make_g(g);
+    k_pool2_bwd<<<grid_for(gg.nvox * c), 256, 0, (hipStream_t)hip_stream>>>(gg, (const bf16*)dy, c, (bf16*)dx);
+    return launched();
+}
+
+int cmnn_up2_fwd(const cmnn_geom* g, const void* x, int32_t c, void* y, void* hip_stream)
+{
+    if (!geom_ok(g) || c <= 0 || !x || !y) return CMNN_EINVAL;
+    const G gg = make_g(g);
+    k_up2_fwd<<<grid_for(gg.nvox * c * 8), 256, 0, (hipStream_t)hip_stream>>>(gg, (const bf16*)x, c, (bf16*)y);
+    return launched();
+}
+
+int cmnn_up2_bwd(const cmnn_geom* g, const void* dy, int32_t c, void* dx, void* hip_stream)
+{
+    if (!geom_ok(g) || c <= 0 || !dy || !dx) return CMNN_EINVAL;
+    const G gg = make_g(g);
+    k_up2_bwd<<<grid_for(gg.nvox * c), 256, 0, (hipStream_t)hip_stream>>>(gg, (const bf16*)dy, c, (bf16*)dx);
+    return launched();
+}
+
+int cmnn_concat_fwd(size_t nvox, const void* a, int32_t ca, const void* b, int32_t cb, void* y, void* hip_stream)
+{
+    if (!a || !b || !y || ca <= 0 || cb <= 0) return CMNN_EINVAL;
+    k_concat_fwd<<<grid_for((long long)nvox * (ca + cb)), 256, 0, (hipStream_t)hip_stream>>>(
+        (long long)nvox, (const bf16*)a, ca, (const bf16*)b, cb, (bf16*)y);
+    return launched();
+}
+
+int cmnn_concat_bwd(size_t nvox, const void* dy, int32_t ca, int32_t cb, void* da, void* db, void* hip_stream)
+{
+    if (!dy || ca <= 0 || cb <= 0) return CMNN_EINVAL;
+    k_concat_bwd<<<grid_for((long long)nvox * (ca + cb)), 256, 0, (hipStream_t)hip_stream>>>(
+        (long long)nvox, (const bf16*)dy, ca, cb, (bf16*)da, (bf16*)db);
+    return launched();
+}
+
+int cmnn_add(size_t n, const void* a, const void* b, void* y, void* hip_stream)
+{
+    if (!a || !b || !y) return CMNN_EINVAL;
+    k_add<<<grid_for((long long)n), 256, 0, (hipStream_t)hip_stream>>>((long long)n, (const bf16*)a, (const bf16*)b,
+                                                                     (bf16*)y);
+    return launched();
+}
+
+int cmnn_mse_workspace(size_t nvox, size_t* bytes)
+{
+    if (!bytes || nvox == 0) return CMNN_EINVAL;
+    *bytes = 2 * kMseBlocks * sizeof(float);
+    return CMNN_OK;
+}
+
+int cmnn_mse(size_t nvox, const void* pred, int32_t c, int32_t creal, const float* target, const float* weight,
+             float* loss_out, void* dpred, void* workspace, size_t workspace_bytes, void* hip_stream)
+{
+    if (!pred || !target || !weight || !loss_out || !workspace || nvox == 0) return CMNN_EINVAL;
+    if (c <= 0 || creal <= 0 || creal > c || workspace_bytes < 2 * kMseBlocks * sizeof(float)) return CMNN_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    float* part = (float*)workspace;
+    k_mse_part<<<kMseBlocks, 256, 0, s>>>((long long)nvox, (const bf16*)pred, c, creal, target, weight, part);
+    if (launched()) return CMNN_EHIP;
+    // loss_out[0] = loss, loss_out[1] = normaliser (callers pass two floats)
+    k_mse_final<<<1, 64, 0, s>>>(part, kMseBlocks, creal, loss_out);
+    if (launched()) return CMNN_EHIP;
+    if (dpred) {
+        k_mse_grad<<<grid_for((long long)nvox * c), 256, 0, s>>>((long long)nvox, (const bf16*)pred, c, creal, target,
+                                                               weight, loss_out, (bf16*)dpred);
+        if (launched()) return CMNN_EHIP;
+    }
+    return CMNN_OK;
+}
+
+int cmnn_adam(size_t n, float* param, const float* grad, float* m, float* v, float lr, float beta1, float beta2,
+              float eps, float weight_decay, int32_t step, void* hip_stream)
+{
+    if (!param || !grad || !m || !v || step < 1) return CMNN_EINVAL;
+    const float c1 = 1.f - powf(beta1, (float)step), c2 = 1.f - powf(beta2, (float)step);
+    k_adam<<<grid_for((long long)n), 256, 0, (hipStream_t)hip_stream>>>((long long)n, param, grad, m, v, lr, beta1,
+                                                                      beta2, eps, weight_decay, c1, c2);
+    return launched();
+}
+
+int cmnn_pack_weights(const float* w, int32_t cin, int32_t cout, void* w_fwd, void* w_t, void* hip_stream)
+{
+    if (!w || !w_fwd || !w_t || cin <= 0 || cout <= 0) return CMNN_EINVAL;
+    k_pack_w<<<grid_for(27LL * cin * cout), 256, 0, (hipStream_t)hip_stream>>>(w, cin, cout, (bf16*)w_fwd, (bf16*)w_t);
+    return launched();
+}
+
+int cmnn_pack_channels(size_t nvox, const float* src, int32_t cs, void* dst, int32_t c, void* hip_stream)
+{
+    if (!src || !dst || cs <= 0 || c < cs) return CMNN_EINVAL;
+    k_pack_ch<<<grid_for((long long)nvox * c), 256, 0, (hipStream_t)hip_stream>>>((long long)nvox, src, cs, (bf16*)dst,
+                                                                                c);
+    return launched();
+}
+
+int cmnn_unpack_channels(size_t nvox, const void* src, int32_t c, float* dst, int32_t cs, void* hip_stream)
+{
+    if (!src || !dst || cs <= 0 || c < cs) return CMNN_EINVAL;
+    k_unpack_ch<<<grid_for((long long)nvox * cs), 256, 0, (hipStream_t)hip_stream>>>((long long)nvox, (const bf16*)src,
+                                                                                   c, dst, cs);
+    return launched();
+}
+
+}  // extern "C"

@@ -1,0 +1,202 @@
+"""GPU checks of the warm-start network kernels (libcmnn, through the C ABI)
+against the FP64 network oracle on BF16-exact inputs.
+
+BF16 x BF16 products are exact in FP32, so the kernels differ from the oracle
+only by FP32 accumulation order and the final rounding of BF16 outputs:
+BF16 outputs must be within one BF16 ulp (2^-8 relative) of the oracle plus
+1e-5 of the accumulated magnitude; FP32 outputs within 1e-5 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import conv_oracle as C
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def nn():
+    from paper_1905_10182_amd import cmnn
+    cmnn.load_library()
+    return cmnn
+
+
+def bf16_tensor(torch, a):
+    """(device BF16 tensor, the same values as float64 numpy)."""
+    t = torch.as_tensor(np.asarray(a, np.float32)).to(torch.bfloat16).to("cuda:0")
+    return t, t.float().cpu().numpy().astype(np.float64)
+
+
+def randn(shape, seed, scale=1.0):
+    return W.generator(seed).standard_normal(shape) * scale
+
+
+def close_bf16(got, ref, mag):
+    err = np.abs(got - ref)
+    bound = np.abs(ref) * 2.0 ** -8 + 1e-5 * mag + 1e-30
+    return float((err / bound).max())
+
+
+SHAPES = [((2, 3, 5, 7), 32, 64, (1, 0, 1)), ((1, 4, 6, 8), 64, 32, (0, 1, 0)), ((1, 2, 4, 6), 32, 96, (1, 1, 1))]
+
+
+@pytest.mark.parametrize("dims,cin,cout,per", SHAPES)
+def test_conv_forward(torch, nn, dims, cin, cout, per):
+    log(f"conv fwd {dims} {cin}->{cout} periodic={per}")
+    g = nn.geom(*dims, periodic=per)
+    x, xr = bf16_tensor(torch, randn(dims + (cin,), 1))
+    w, wr = bf16_tensor(torch, randn((27, cout, cin), 2, 0.1))
+    b = torch.as_tensor(randn((cout,), 3, 0.1), dtype=torch.float32, device="cuda:0")
+    for act in (nn.ACT_NONE, nn.ACT_LEAKY):
+        y = torch.empty(dims + (cout,), dtype=torch.bfloat16, device="cuda:0")
+        nn.conv_fwd(g, x, cin, w, b, cout, act, y)
+        ref = C.conv3d(xr, wr, b.cpu().numpy().astype(np.float64), per)
+        if act == nn.ACT_LEAKY:
+            ref = C.leaky(ref)
+        mag = C.conv3d(np.abs(xr), np.abs(wr), None, per)
+        r = close_bf16(y.float().cpu().numpy(), ref, mag)
+        log(f"  act={act}: max error / bound = {r:.3f}")
+        assert r <= 1.0
+
+
+@pytest.mark.parametrize("dims,cin,cout,per", SHAPES)
+def test_conv_backward(torch, nn, dims, cin, cout, per):
+    log(f"conv bwd {dims} {cin}->{cout} periodic={per}")
+    g = nn.geom(*dims, periodic=per)
+    x, xr = bf16_tensor(torch, randn(dims + (cin,), 4))
+    wm = torch.as_tensor(randn((27, cout, cin), 5, 0.1), dtype=torch.float32, device="cuda:0")
+    wf = torch.empty((27, cout, cin), dtype=torch.bfloat16, device="cuda:0")
+    wt = torch.empty((27, cin, cout), dtype=torch.bfloat16, device="cuda:0")
+    nn.pack_weights(wm, cin, cout, wf, wt)
+    wr = wf.float().cpu().numpy().astype(np.float64)
+    assert np.array_equal(wt.float().cpu().numpy(), wf.float().cpu().numpy().transpose(0, 2, 1))
+    dy, dyr = bf16_tensor(torch, randn(dims + (cout,), 6))
+    dx = torch.empty(dims + (cin,), dtype=torch.bfloat16, device="cuda:0")
+    nn.conv_bwd_data(g, dy, cout, wt, cin, dx)
+    rdx, rdw, rdb = C.conv3d_grads(xr, wr, dyr, per)
+    magx, _, _ = C.conv3d_grads(np.abs(xr), np.abs(wr), np.abs(dyr), per)
+    r = close_bf16(dx.float().cpu().numpy(), rdx, magx)
+    log(f"  dx: max error / bound = {r:.3f}")
+    assert r <= 1.0
+    ws = torch.empty(nn.conv_bwd_weight_workspace(g, cin, cout) // 4, dtype=torch.float32, device="cuda:0")
+    dw = torch.empty((27, cout, cin), dtype=torch.float32, device="cuda:0")
+    db = torch.empty((cout,), dtype=torch.float32, device="cuda:0")
+    nn.conv_bwd_weight(g, x, cin, dy, cout, dw, db, ws)
+    e_w = np.linalg.norm(dw.cpu().numpy() - rdw) / np.linalg.norm(rdw)
+    e_b = np.linalg.norm(db.cpu().numpy() - rdb) / np.linalg.norm(rdb)
+    log(f"  dw rel {e_w:.2e}  db rel {e_b:.2e}")
+    assert e_w < 1e-5 and e_b < 1e-5
+    dw2 = torch.empty_like(dw)
+    nn.conv_bwd_weight(g, x, cin, dy, cout, dw2, None, ws)
+    assert torch.equal(dw, dw2)  # deterministic
+
+
+def test_conv_large_voxel_count(torch, nn):
+    """A full warm-start level (4 x 32 x 32 x 64 voxels) at the widest level-0
+    layer, checked on sampled outputs and through the fixed-order weight
+    gradient on a second, smaller case."""
+    dims, cin, cout = (4, 32, 32, 64), 96, 32
+    log(f"conv fwd sampled {dims} {cin}->{cout}")
+    g = nn.geom(*dims)
+    x, xr = bf16_tensor(torch, randn(dims + (cin,), 7))
+    w, wr = bf16_tensor(torch, randn((27, cout, cin), 8, 0.05))
+    y = torch.empty(dims + (cout,), dtype=torch.bfloat16, device="cuda:0")
+    nn.conv_fwd(g, x, cin, w, None, cout, nn.ACT_NONE, y)
+    yg = y.float().cpu().numpy()
+    gen = W.generator(9)
+    for _ in range(64):
+        n, d, h, ww = (int(gen.integers(s)) for s in dims)
+        acc = np.zeros(cout)
+        for t, (dz, dyy, dx) in enumerate(C.taps()):
+            hh = h + dyy
+            if hh < 0 or hh >= dims[2]:
+                continue
+            acc += wr[t] @ xr[n, (d + dz) % dims[1], hh, (ww + dx) % dims[3]]
+        assert np.all(np.abs(yg[n, d, h, ww] - acc) <= np.abs(acc) * 2.0 ** -8 + 1e-3)
+
+
+def test_elementwise_ops(torch, nn):
+    log("pool / upsample / concat / add / act_bwd")
+    dims, c = (2, 4, 6, 8), 32
+    g = nn.geom(*dims)
+    gc = nn.geom(2, 2, 3, 4)
+    x, xr = bf16_tensor(torch, randn(dims + (c,), 10))
+    y = torch.empty((2, 2, 3, 4, c), dtype=torch.bfloat16, device="cuda:0")
+    nn.pool2_fwd(g, x, c, y)
+    assert close_bf16(y.float().cpu().numpy(), C.pool2(xr), np.abs(C.pool2(np.abs(xr)))) <= 1.0
+    dy, dyr = bf16_tensor(torch, randn((2, 2, 3, 4, c), 11))
+    dx = torch.empty(dims + (c,), dtype=torch.bfloat16, device="cuda:0")
+    nn.pool2_bwd(g, dy, c, dx)
+    assert np.array_equal(dx.float().cpu().numpy(), C.pool2_grad(dyr))  # exact: division by 8
+    u = torch.empty(dims + (c,), dtype=torch.bfloat16, device="cuda:0")
+    nn.up2_fwd(gc, dy, c, u)
+    assert np.array_equal(u.float().cpu().numpy(), C.up2(dyr))
+    du = torch.empty((2, 2, 3, 4, c), dtype=torch.bfloat16, device="cuda:0")
+    nn.up2_bwd(gc, x, c, du)
+    assert close_bf16(du.float().cpu().numpy(), C.up2_grad(xr), C.up2_grad(np.abs(xr))) <= 1.0
+    a, ar = bf16_tensor(torch, randn((30, 32), 12))
+    b, br = bf16_tensor(torch, randn((30, 64), 13))
+    cat = torch.empty((30, 96), dtype=torch.bfloat16, device="cuda:0")
+    nn.concat_fwd(30, a, 32, b, 64, cat)
+    assert np.array_equal(cat.float().cpu().numpy(), np.concatenate([ar, br], 1))
+    da = torch.empty_like(a)
+    db = torch.empty_like(b)
+    nn.concat_bwd(30, cat, 32, 64, da, db)
+    assert torch.equal(da, a) and torch.equal(db, b)
+    s = torch.empty_like(a)
+    nn.add(a, a, s)
+    assert torch.equal(s.float(), 2 * a.float())
+    yl, ylr = bf16_tensor(torch, randn((1000,), 14))
+    gl, glr = bf16_tensor(torch, randn((1000,), 15))
+    out = torch.empty_like(yl)
+    nn.act_bwd(yl, gl, out)
+    assert close_bf16(out.float().cpu().numpy(), C.leaky_grad_from_output(ylr, glr), np.abs(glr)) <= 1.0
+
+
+def test_mse_adam_and_channel_packing(torch, nn):
+    log("mse / adam / pack channels")
+    nv, c, creal = 5000, 32, 3
+    p, pr = bf16_tensor(torch, randn((nv, c), 16))
+    tgt = torch.as_tensor(randn((creal, nv), 17), dtype=torch.float32, device="cuda:0")
+    wt = torch.as_tensor((randn((nv,), 18) > -0.5).astype(np.float32), device="cuda:0")
+    loss = torch.empty(2, dtype=torch.float32, device="cuda:0")
+    dp = torch.empty_like(p)
+    ws = torch.empty(nn.mse_workspace(nv) // 4, dtype=torch.float32, device="cuda:0")
+    nn.mse(nv, p, c, creal, tgt, wt, loss, dp, ws)
+    rl, rg = C.mse(pr, tgt.cpu().numpy().astype(np.float64), wt.cpu().numpy().astype(np.float64))
+    assert abs(loss[0].item() / rl - 1) < 1e-5
+    assert close_bf16(dp.float().cpu().numpy(), rg, np.abs(rg)) <= 1.0
+    n = 777
+    pm = torch.as_tensor(randn((n,), 19), dtype=torch.float32, device="cuda:0")
+    gm = torch.as_tensor(randn((n,), 20), dtype=torch.float32, device="cuda:0")
+    m = torch.zeros_like(pm)
+    v = torch.zeros_like(pm)
+    ref_p, ref_m, ref_v = pm.cpu().numpy().astype(np.float64), np.zeros(n), np.zeros(n)
+    g64 = gm.cpu().numpy().astype(np.float64)
+    for step in (1, 2, 3):
+        nn.adam(pm, gm, m, v, 1e-3, 0.9, 0.999, 1e-8, 1e-4, step)
+        ref_p, ref_m, ref_v = C.adam(ref_p, g64, ref_m, ref_v, 1e-3, 0.9, 0.999, 1e-8, 1e-4, step)
+    np.testing.assert_allclose(pm.cpu().numpy(), ref_p, rtol=0, atol=1e-6)
+    src = torch.as_tensor(randn((2, 100), 21), dtype=torch.float32, device="cuda:0")
+    packed = torch.empty((100, 32), dtype=torch.bfloat16, device="cuda:0")
+    nn.pack_channels(100, src, 2, packed, 32)
+    assert np.array_equal(packed.float().cpu().numpy()[:, :2], src.to(torch.bfloat16).float().cpu().numpy().T)
+    assert np.all(packed.float().cpu().numpy()[:, 2:] == 0)
+    back = torch.empty((2, 100), dtype=torch.float32, device="cuda:0")
+    nn.unpack_channels(100, packed, 32, back, 2)
+    assert torch.equal(back, src.to(torch.bfloat16).float())
