@@ -79,6 +79,14 @@ int cmnn_up2_bwd(const cmnn_geom* g, const void* dy, int32_t c, void* dx, void* 
 int cmnn_concat_fwd(size_t nvox, const void* a, int32_t ca, const void* b, int32_t cb, void* y, void* hip_stream);
 int cmnn_concat_bwd(size_t nvox, const void* dy, int32_t ca, int32_t cb, void* da, void* db, void* hip_stream);
 
+/* Per-sample channel mean broadcast over the voxels (global context):
+ * y[n][v][c] = (1/V) sum_v' x[n][v'][c], V = d*h*w, c <= 256.  The map is a
+ * symmetric projection, so the same call on dy gives the gradient.
+ * workspace: cmnn_channel_mean_workspace bytes. */
+int cmnn_channel_mean_workspace(const cmnn_geom* g, int32_t c, size_t* bytes);
+int cmnn_channel_mean(const cmnn_geom* g, const void* x, int32_t c, void* y, void* workspace, size_t workspace_bytes,
+                      void* hip_stream);
+
 /* y = a + b elementwise (BF16), n elements. */
 int cmnn_add(size_t n, const void* a, const void* b, void* y, void* hip_stream);
 

@@ -9,7 +9,8 @@ Definitions written out with numpy in float64 on NDHWC arrays [n, d, h, w, c]:
 - its gradients, obtained as the adjoint of each shifted read (a zero-padded
   read at v + off is adjoint to a zero-padded write at v - off);
 - leaky ReLU (slope 0.1), 2x2x2 average pooling, 2x nearest upsampling,
-  channel concatenation, masked mean-squared error, Adam.
+  channel concatenation, per-sample channel means, masked mean-squared
+  error, Adam.
 """
 import numpy as np
 
@@ -97,6 +98,11 @@ def up2(x):
 def up2_grad(dy):
     n, d, h, w, c = dy.shape
     return dy.reshape(n, d // 2, 2, h // 2, 2, w // 2, 2, c).sum(axis=(2, 4, 6))
+
+
+def channel_mean(x):
+    """Per-sample channel means broadcast back over the voxels (a symmetric projection)."""
+    return np.broadcast_to(x.mean(axis=(1, 2, 3), keepdims=True), x.shape).copy()
 
 
 def mse(pred, target, weight):

@@ -13,7 +13,7 @@ ACT_NONE, ACT_LEAKY = 0, 1
 
 EXPORTS = ["cmnn_conv3d_fwd", "cmnn_conv3d_bwd_data", "cmnn_conv3d_bwd_weight_workspace", "cmnn_conv3d_bwd_weight",
            "cmnn_act_bwd", "cmnn_pool2_fwd", "cmnn_pool2_bwd", "cmnn_up2_fwd", "cmnn_up2_bwd", "cmnn_concat_fwd",
-           "cmnn_concat_bwd", "cmnn_add", "cmnn_mse_workspace", "cmnn_mse", "cmnn_adam", "cmnn_pack_weights",
+           "cmnn_concat_bwd", "cmnn_add", "cmnn_channel_mean_workspace", "cmnn_channel_mean", "cmnn_mse_workspace", "cmnn_mse", "cmnn_adam", "cmnn_pack_weights",
            "cmnn_pack_channels", "cmnn_unpack_channels"]
 
 
@@ -56,6 +56,8 @@ def load_library():
     lib.cmnn_concat_fwd.argtypes = [sz, vp, i32, vp, i32, vp, vp]
     lib.cmnn_concat_bwd.argtypes = [sz, vp, i32, i32, vp, vp, vp]
     lib.cmnn_add.argtypes = [sz, vp, vp, vp, vp]
+    lib.cmnn_channel_mean_workspace.argtypes = [G, i32, ctypes.POINTER(sz)]
+    lib.cmnn_channel_mean.argtypes = [G, vp, i32, vp, vp, sz, vp]
     lib.cmnn_mse_workspace.argtypes = [sz, ctypes.POINTER(sz)]
     lib.cmnn_mse.argtypes = [sz, vp, i32, i32, vp, vp, vp, vp, vp, sz, vp]
     lib.cmnn_adam.argtypes = [sz, vp, vp, vp, vp, f32, f32, f32, f32, f32, i32, vp]
@@ -138,6 +140,17 @@ def concat_bwd(nv, dy, ca, cb, da, db):
 
 def add(a, b, y):
     _check(load_library().cmnn_add(a.numel(), _p(a), _p(b), _p(y), _s()), "add")
+
+
+def channel_mean_workspace(g, c):
+    n = ctypes.c_size_t()
+    _check(load_library().cmnn_channel_mean_workspace(ctypes.byref(g), c, ctypes.byref(n)), "channel_mean_workspace")
+    return n.value
+
+
+def channel_mean(g, x, c, y, ws):
+    _check(load_library().cmnn_channel_mean(ctypes.byref(g), _p(x), c, _p(y), _p(ws), ws.numel() * ws.element_size(),
+                                            _s()), "channel_mean")
 
 
 def mse_workspace(nv):

@@ -474,6 +474,46 @@ __global__ void k_unpack_ch(long long nvox, const bf16* __restrict__ src, int c,
     }
 }
 
+// Per-sample channel means broadcast back over the voxels:
+// y[n][v][c] = (1/V) sum_v' x[n][v'][c].  The operator is a symmetric
+// projection, so the same two kernels also give its gradient.
+__global__ __launch_bounds__(256) void k_chmean_part(const bf16* __restrict__ x, long long vps, int c,
+                                                     int parts, float* __restrict__ part)
+{
+    // block (n, p): voxels [p * chunk, (p + 1) * chunk) of sample n; thread t sums channel t % c
+    __shared__ float sh[256];
+    const int n = blockIdx.x / parts, p = blockIdx.x % parts;
+    const long long chunk = (vps + parts - 1) / parts;
+    const long long v0 = p * chunk, v1 = v0 + chunk < vps ? v0 + chunk : vps;
+    const int t = threadIdx.x, rpi = 256 / c, ch = t % c, roff = t / c;
+    float s = 0.f;
+    if (roff < rpi)
+        for (long long v = v0 + roff; v < v1; v += rpi) s += (float)x[((long long)n * vps + v) * c + ch];
+    sh[t] = s;
+    __syncthreads();
+    if (t < c) {
+        float q = 0.f;
+        for (int k = 0; k < rpi; ++k) q += sh[k * c + t];
+        part[((long long)n * parts + p) * c + t] = q;
+    }
+}
+
+__global__ void k_chmean_bcast(const float* __restrict__ part, long long vps, int c, int nsamp, int parts,
+                               bf16* __restrict__ y)
+{
+    const long long total = (long long)nsamp * vps * c;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int ch = (int)(i % c);
+        const long long n = i / c / vps;
+        float s = 0.f;
+        for (int p = 0; p < parts; ++p) s += part[(n * parts + p) * c + ch];
+        y[i] = (bf16)(s / (float)vps);
+    }
+}
+
+constexpr int kMeanParts = 64;
+
 int launched() { return hipGetLastError() == hipSuccess ? CMNN_OK : CMNN_EHIP; }
 
 dim3 grid_for(long long n)
@@ -631,6 +671,28 @@ int cmnn_add(size_t n, const void* a, const void* b, void* y, void* hip_stream)
     if (!a || !b || !y) return CMNN_EINVAL;
     k_add<<<grid_for((long long)n), 256, 0, (hipStream_t)hip_stream>>>((long long)n, (const bf16*)a, (const bf16*)b,
                                                                      (bf16*)y);
+    return launched();
+}
+
+int cmnn_channel_mean_workspace(const cmnn_geom* g, int32_t c, size_t* bytes)
+{
+    if (!geom_ok(g) || c <= 0 || c > 256 || !bytes) return CMNN_EINVAL;
+    *bytes = (size_t)g->n * kMeanParts * c * sizeof(float);
+    return CMNN_OK;
+}
+
+int cmnn_channel_mean(const cmnn_geom* g, const void* x, int32_t c, void* y, void* workspace, size_t workspace_bytes,
+                      void* hip_stream)
+{
+    size_t need = 0;
+    if (cmnn_channel_mean_workspace(g, c, &need) != CMNN_OK || !x || !y || !workspace || workspace_bytes < need)
+        return CMNN_EINVAL;
+    const G gg = make_g(g);
+    hipStream_t s = (hipStream_t)hip_stream;
+    const long long vps = (long long)g->d * g->h * g->w;
+    k_chmean_part<<<(unsigned)(g->n * kMeanParts), 256, 0, s>>>((const bf16*)x, vps, c, kMeanParts, (float*)workspace);
+    if (launched()) return CMNN_EHIP;
+    k_chmean_bcast<<<grid_for(gg.nvox * c), 256, 0, s>>>((const float*)workspace, vps, c, g->n, kMeanParts, (bf16*)y);
     return launched();
 }
 

@@ -1,0 +1,406 @@
+"""Learned warm start of the solver for forced obstacle channels.
+
+    python -m paper_1905_10182_amd.warmstart generate --first 0 --batches 16 --out train.npz
+    python -m paper_1905_10182_amd.warmstart train --data train.npz --steps 3000 --out unet.npz
+    python -m paper_1905_10182_amd.warmstart evaluate --model unet.npz [--first 1000]
+
+Workload: batches of 64 channels 64 x 32 x 32 (x, y, z), periodic in x and z,
+halfway bounce-back walls at y = -1/2 and y = 31 + 1/2, 1-4 solid spheres of
+radius 3-8, force density F_x ~ U[1e-6, 1e-5], tau = 0.8 (seeded by
+workloads.sphere_channels; member b of a batch starting at seed s uses seed
+s + b).
+
+- generate: the FP64 solver (libcmlbm) runs every channel from rest to a
+  single-step velocity residual ||u_t - u_{t-1}|| / ||u_t|| <= tol (checked
+  every 100 steps); the steady velocity normalised by the Poiseuille centre
+  velocity U = F_x H^2 / (8 nu), minus the normalised empty-channel profile,
+  and the normalised density are the training targets.
+- train: the U-Net of unet.py (BF16 MFMA kernels of libcmnn) learns the
+  normalised velocity and density from the fluid mask and a wall-distance
+  feature, by Adam on the masked mean-squared error, entirely on the GPU.
+  Velocity is predicted as a correction to the empty-channel profile (the
+  wall feature on the x component), density as (rho - 1) / (3 F_x L_x) (the
+  scale of the pressure drop the force sustains over the channel length).
+- evaluate: steps to residual 1e-8 for the same channels from three
+  initial states -- rest (cold), the analytic Poiseuille profile of the empty
+  channel (a non-learned control), and the network prediction (warm) --
+  with the solver itself as the judge of convergence.  A prediction that is
+  non-finite or exceeds |u| = 0.1 falls back to rest.  The converged fields
+  of the warm and cold runs are compared.
+"""
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+import workloads
+from . import cmnn
+from .cmlbm import RED, Lattice
+from .unet import UNet3D
+
+NX, NY, NZ = 64, 32, 32
+TAU = 0.8
+NU = (TAU - 0.5) / 3.0
+H = NY  # channel width between the halfway walls
+
+
+def u_ref(fx):
+    """Centre velocity of the empty Poiseuille channel, F H^2 / (8 nu)."""
+    return np.asarray(fx) * H * H / (8.0 * NU)
+
+
+def wall_feature():
+    """4 y'(H - y') / H^2 with y' = y + 1/2: 0 at the walls, 1 on the axis."""
+    yp = np.arange(NY) + 0.5
+    return 4.0 * yp * (H - yp) / (H * H)
+
+
+NOUT = 4  # u_x, u_y, u_z, rho
+
+
+def rho_scale(fx):
+    """Density scale 3 F_x L_x: the pressure drop F_x L_x over c_s^2."""
+    return 3.0 * np.asarray(fx) * NX
+
+
+def base_field(solid):
+    """(nb, NOUT, nz, ny, nx) FP32 normalised empty-channel profile (zero in solids)."""
+    nb = solid.shape[0]
+    b = np.zeros((nb, NOUT, NZ, NY, NX), np.float32)
+    b[:, 0] = (solid == 0) * wall_feature()[None, None, :, None]
+    return b
+
+
+def make_inputs(solid):
+    """(nb, 2, nz, ny, nx) FP32: fluid mask, wall feature (zero in solids)."""
+    nb = solid.shape[0]
+    fluid = (solid == 0).astype(np.float32)
+    x = np.zeros((nb, 2, NZ, NY, NX), np.float32)
+    x[:, 0] = fluid
+    x[:, 1] = fluid * wall_feature()[None, None, :, None]
+    return x
+
+
+def poiseuille_field(solid, fx):
+    """(3, nb, nz, ny, nx) FP64 analytic profile of the empty channel, zero in solids."""
+    nb = solid.shape[0]
+    yp = np.arange(NY) + 0.5
+    prof = yp * (H - yp) / (2.0 * NU)
+    u = np.zeros((3, nb, NZ, NY, NX))
+    u[0] = np.asarray(fx)[:, None, None, None] * prof[None, None, :, None]
+    u[:, solid.astype(bool)] = 0.0
+    return u
+
+
+def new_lattice(nb):
+    return Lattice(NX, NY, NZ, nbatch=nb, tau=TAU, storage="fp64", wall=(0, 1, 0), solid=True, residual=True,
+                   device="cuda:0")
+
+
+def run_to_residual(lat, tol, max_steps, check=100, log=None):
+    """Advance until every member's residual is <= tol.  The residual is the
+    per-step change measured over two steps, ||u_t - u_{t-2}|| / (2 ||u_t||):
+    halfway bounce-back around obstacles excites a non-decaying period-2
+    (staggered) oscillation of the lattice, which a single-step difference
+    would report as a floor (about 2e-6 in these channels) and which cancels
+    over two steps.  Returns (steps-to-tol per member (-1 if never), final
+    residuals)."""
+    import torch
+
+    nb = lat.shape[0]
+    reached = np.full(nb, -1, np.int64)
+    res = np.full(nb, np.inf)
+    t = 0
+    while t < max_steps:
+        lat.step(check - 2)
+        lat.reduce(snapshot=True)
+        lat.step(2)
+        t += check
+        r = lat.reduce(residual=True, allow_unstable=True)
+        res = r[:, RED["residual"]] / 2.0
+        bad = r[:, RED["nonfinite"]] > 0
+        if bad.any():
+            raise RuntimeError(f"solver blew up in members {np.nonzero(bad)[0].tolist()}")
+        newly = (res <= tol) & (reached < 0)
+        reached[newly] = t
+        if log and t % (20 * check) == 0:
+            log(f"  step {t}: max residual {res.max():.2e}, converged {int((reached >= 0).sum())}/{nb}")
+        if (reached >= 0).all():
+            break
+    torch.cuda.synchronize()
+    return reached, res
+
+
+def steady_moments(lat):
+    """Mean of (rho, u) over two consecutive steps (removes the period-2 mode), FP64 numpy."""
+    ra, a = lat.moments()
+    lat.step(1)
+    rb, b = lat.moments()
+    return 0.5 * (ra + rb).cpu().numpy(), 0.5 * (a + b).cpu().numpy()
+
+
+def generate(first_seed, batches, nb=64, tol=1e-7, max_steps=40000, log=print):
+    """Steady states of sphere channels -> dict of arrays."""
+    import torch
+
+    X, Y, Wt, FX, STEPS = [], [], [], [], []
+    for k in range(batches):
+        seed = first_seed + k * nb
+        wl = workloads.sphere_channels(nb, NX, NY, NZ, seed=seed)
+        lat = new_lattice(nb)
+        lat.set_solid(wl["solid"])
+        lat.set_force("batch", np.stack([wl["fx"], 0 * wl["fx"], 0 * wl["fx"]], 1))
+        lat.init(None, None)
+        t0 = time.perf_counter()
+        reached, res = run_to_residual(lat, tol, max_steps)
+        rho, u = steady_moments(lat)  # (nb, nz, ny, nx), (3, nb, nz, ny, nx)
+        dt = time.perf_counter() - t0
+        log(f"batch {k} seeds {seed}..{seed + nb - 1}: steps to {tol:g} median {int(np.median(reached))}, "
+            f"max {int(reached.max())}, {dt:.1f} s")
+        uh = u / u_ref(wl["fx"])[None, :, None, None, None]
+        rh = (rho - 1.0) / rho_scale(wl["fx"])[:, None, None, None]
+        rh[wl["solid"].astype(bool)] = 0.0
+        tgt = np.concatenate([np.transpose(uh, (1, 0, 2, 3, 4)), rh[:, None]], axis=1).astype(np.float32)
+        X.append(make_inputs(wl["solid"]))
+        Y.append(tgt - base_field(wl["solid"]))
+        Wt.append((wl["solid"] == 0).astype(np.float32))
+        FX.append(wl["fx"])
+        STEPS.append(reached)
+        del lat
+        torch.cuda.empty_cache()
+    return dict(x=np.concatenate(X), y=np.concatenate(Y), w=np.concatenate(Wt), fx=np.concatenate(FX),
+                steps=np.concatenate(STEPS), tol=tol, first_seed=first_seed)
+
+
+class Trainer:
+    """Minibatch training of UNet3D on (inputs, normalised targets, weights)."""
+
+    def __init__(self, net, data, batch=8):
+        import torch
+
+        self.torch = torch
+        self.net = net
+        self.batch = batch
+        n = data["x"].shape[0]
+        self.n = n
+        nvs = NX * NY * NZ
+        dev = net.device
+        # planar layouts so that a minibatch is a contiguous slice after index_select on axis 1
+        self.X = torch.as_tensor(np.ascontiguousarray(np.transpose(data["x"].reshape(n, 2, nvs), (1, 0, 2))),
+                                 device=dev)
+        self.Y = torch.as_tensor(np.ascontiguousarray(np.transpose(data["y"].reshape(n, NOUT, nvs), (1, 0, 2))),
+                                 device=dev)
+        self.W = torch.as_tensor(data["w"].reshape(n, nvs), device=dev)
+        self.nvox = batch * nvs
+        self.xb = torch.empty((batch, NZ, NY, NX, net.cin0), dtype=torch.bfloat16, device=dev)
+        self.dy = torch.empty((batch, NZ, NY, NX, net.cout_head), dtype=torch.bfloat16, device=dev)
+        self.loss = torch.zeros(2, dtype=torch.float32, device=dev)
+        self.ws = torch.empty(cmnn.mse_workspace(self.nvox) // 4, dtype=torch.float32, device=dev)
+        self.gen = np.random.Generator(np.random.PCG64(12345))
+
+    def minibatch(self, idx):
+        t = self.torch
+        ii = t.as_tensor(idx, device=self.net.device)
+        xs = self.X.index_select(1, ii).contiguous()
+        cmnn.pack_channels(self.nvox, xs, 2, self.xb, self.net.cin0)
+        ys = self.Y.index_select(1, ii).contiguous()
+        ws = self.W.index_select(0, ii).contiguous()
+        return ys, ws
+
+    def step(self, lr):
+        idx = self.gen.choice(self.n, self.batch, replace=False)
+        ys, ws = self.minibatch(idx)
+        out = self.net.forward(self.xb)
+        cmnn.mse(self.nvox, out, self.net.cout_head, NOUT, ys, ws, self.loss, self.dy, self.ws)
+        self.net.backward(self.dy)
+        self.net.adam_step(lr)
+        return self.loss
+
+    def evaluate_loss(self, data=None):
+        """Mean masked MSE over a dataset (default: the training data)."""
+        tr = self if data is None else Trainer(self.net, data, self.batch)
+        tot, cnt = 0.0, 0
+        for s in range(0, tr.n - tr.batch + 1, tr.batch):
+            ys, ws = tr.minibatch(np.arange(s, s + tr.batch))
+            out = self.net.forward(tr.xb)
+            cmnn.mse(tr.nvox, out, self.net.cout_head, NOUT, ys, ws, tr.loss, None, tr.ws)
+            tot += float(tr.loss[0].item())
+            cnt += 1
+        return tot / max(cnt, 1)
+
+
+def train(data, steps=3000, batch=8, lr=5e-4, lr_min=5e-6, seed=0, log=print, test=None):
+    import torch
+
+    net = UNet3D((NZ, NY, NX), out_ch=NOUT, seed=seed)
+    tr = Trainer(net, data, batch)
+    log(f"U-Net: {net.nparams_real} parameters ({net.nparams} with channel padding), "
+        f"{net.flops_per_sample() / 1e9:.1f} GFLOP per sample forward")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = []
+    for s in range(1, steps + 1):
+        lr_s = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * (s - 1) / steps))
+        loss = tr.step(lr_s)
+        if s % 500 == 0 or s == 1:
+            lv = float(loss[0].item())
+            hist.append((s, lv))
+            log(f"  step {s}: loss {lv:.3e} lr {lr_s:.2e} ({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    flops = 3 * net.flops_per_sample() * batch * steps
+    info = {"train_seconds": dt, "train_tflops": flops / dt / 1e12, "steps": steps, "batch": batch,
+            "params": net.nparams_real, "loss_history": hist, "train_loss": tr.evaluate_loss()}
+    if test is not None:
+        info["test_loss"] = tr.evaluate_loss(test)
+    return net, info
+
+
+def predict(net, solid, fx, batch=8):
+    """Network (rho (nb, nz, ny, nx), u (3, nb, nz, ny, nx)) in FP64 for
+    channels with the given solids and forces: the normalised prediction
+    scaled back, rho = 1 and u = 0 in solids."""
+    import torch
+
+    nb = solid.shape[0]
+    x = make_inputs(solid)
+    out = np.zeros((NOUT, nb, NZ, NY, NX))
+    nvs = NX * NY * NZ
+    dev = net.device
+    for s in range(0, nb, batch):
+        e = min(nb, s + batch)
+        n = e - s
+        xp = torch.as_tensor(np.ascontiguousarray(np.transpose(x[s:e].reshape(n, 2, nvs), (1, 0, 2))), device=dev)
+        xb = torch.empty((n, NZ, NY, NX, net.cin0), dtype=torch.bfloat16, device=dev)
+        cmnn.pack_channels(n * nvs, xp, 2, xb, net.cin0)
+        y = net.forward(xb)
+        uo = torch.empty((NOUT, n * nvs), dtype=torch.float32, device=dev)
+        cmnn.unpack_channels(n * nvs, y, net.cout_head, uo, NOUT)
+        out[:, s:e] = uo.cpu().numpy().reshape(NOUT, n, NZ, NY, NX)
+    out += np.transpose(base_field(solid), (1, 0, 2, 3, 4))
+    u = out[:3] * u_ref(fx)[None, :, None, None, None]
+    rho = 1.0 + out[3] * rho_scale(fx)[:, None, None, None]
+    u[:, solid.astype(bool)] = 0.0
+    rho[solid.astype(bool)] = 1.0
+    return rho, u
+
+
+def evaluate(net, first_seed=1000, nb=64, tol=1e-8, max_steps=40000, log=print):
+    import torch
+
+    wl = workloads.sphere_channels(nb, NX, NY, NZ, seed=first_seed)
+    solid, fx = wl["solid"], wl["fx"]
+    force = np.stack([fx, 0 * fx, 0 * fx], 1)
+    results = {}
+    fields = {}
+    t0 = time.perf_counter()
+    rho_warm, u_warm = predict(net, solid, fx) if net is not None else (None, None)
+    torch.cuda.synchronize()
+    t_infer = time.perf_counter() - t0
+    fallback = np.zeros(nb, bool)
+    if u_warm is not None:
+        bad = ~np.isfinite(u_warm).all(axis=(0, 2, 3, 4)) | (np.abs(u_warm).max(axis=(0, 2, 3, 4)) > 0.1)
+        bad |= ~np.isfinite(rho_warm).all(axis=(1, 2, 3)) | (np.abs(rho_warm - 1).max(axis=(1, 2, 3)) > 0.1)
+        u_warm[:, bad] = 0.0
+        rho_warm[bad] = 1.0
+        fallback = bad
+    inits = {"cold": (None, None), "poiseuille": (None, poiseuille_field(solid, fx))}
+    if u_warm is not None:
+        inits["warm"] = (rho_warm, u_warm)
+    for name in list(inits) + ["exact"]:
+        # "exact": the converged cold-start moments themselves, the best any
+        # moment-based initialisation can do (the non-equilibrium parts of
+        # the populations still relax)
+        r0, u0 = inits[name] if name != "exact" else fields["cold"]
+        lat = new_lattice(nb)
+        lat.set_solid(solid)
+        lat.set_force("batch", force)
+        lat.init(r0, u0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        reached, res = run_to_residual(lat, tol, max_steps)
+        dt = time.perf_counter() - t1
+        fields[name] = steady_moments(lat)
+        results[name] = {"steps": reached.tolist(), "median_steps": float(np.median(reached)),
+                         "mean_steps": float(np.mean(reached)), "solve_seconds": dt,
+                         "all_converged": bool((reached >= 0).all())}
+        log(f"{name}: steps to {tol:g} median {np.median(reached):.0f} mean {np.mean(reached):.0f} "
+            f"max {reached.max()} ({dt:.1f} s)")
+        del lat
+        torch.cuda.empty_cache()
+    fl = ~solid.astype(bool)
+    rho_ref, u_ref_field = fields["cold"][0][fl], fields["cold"][1][:, fl]
+    summary = {"tol": tol, "nb": nb, "first_seed": first_seed, "results": results, "inference_seconds": t_infer,
+               "fallbacks": int(fallback.sum())}
+    for name in fields:
+        if name != "cold":
+            summary[f"{name}_vs_cold_final_rel"] = float(
+                np.linalg.norm(fields[name][1][:, fl] - u_ref_field) / np.linalg.norm(u_ref_field))
+            summary[f"speedup_steps_{name}"] = results["cold"]["mean_steps"] / results[name]["mean_steps"]
+    if u_warm is not None:
+        summary["prediction_rel_error_u"] = float(np.linalg.norm(u_warm[:, fl] - u_ref_field) /
+                                                  np.linalg.norm(u_ref_field))
+        summary["prediction_rel_error_rho"] = float(np.linalg.norm(rho_warm[fl] - rho_ref) /
+                                                    np.linalg.norm(rho_ref - 1.0))
+        summary["speedup_wall_warm"] = results["cold"]["solve_seconds"] / (results["warm"]["solve_seconds"] + t_infer)
+    summary["poiseuille_rel_error_u"] = float(np.linalg.norm(inits["poiseuille"][1][:, fl] - u_ref_field) /
+                                              np.linalg.norm(u_ref_field))
+    return summary
+
+
+def save_model(net, path, info=None):
+    sd = net.state_dict()
+    np.savez(path, params=sd["params"], widths=sd["widths"], dims=sd["dims"], out_ch=sd["out_ch"],
+             info=json.dumps(info or {}, default=float))
+
+
+def load_model(path):
+    z = np.load(path, allow_pickle=False)
+    net = UNet3D(tuple(int(v) for v in z["dims"]), out_ch=int(z["out_ch"]), widths=tuple(int(v) for v in z["widths"]))
+    net.load_state(z["params"])
+    return net
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    g = sub.add_parser("generate")
+    g.add_argument("--first", type=int, default=0)
+    g.add_argument("--batches", type=int, default=16)
+    g.add_argument("--tol", type=float, default=1e-7)
+    g.add_argument("--out", required=True)
+    t = sub.add_parser("train")
+    t.add_argument("--data", required=True)
+    t.add_argument("--test")
+    t.add_argument("--steps", type=int, default=3000)
+    t.add_argument("--batch", type=int, default=8)
+    t.add_argument("--lr", type=float, default=5e-4)
+    t.add_argument("--out", required=True)
+    e = sub.add_parser("evaluate")
+    e.add_argument("--model")
+    e.add_argument("--first", type=int, default=1000)
+    e.add_argument("--out")
+    a = ap.parse_args(argv)
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    if a.cmd == "generate":
+        d = generate(a.first, a.batches, tol=a.tol, log=log)
+        np.savez(a.out, **d)
+    elif a.cmd == "train":
+        z = dict(np.load(a.data, allow_pickle=False))
+        test = dict(np.load(a.test, allow_pickle=False)) if a.test else None
+        net, info = train(z, steps=a.steps, batch=a.batch, lr=a.lr, log=log, test=test)
+        save_model(net, a.out, info)
+        print(json.dumps({k: v for k, v in info.items() if k != "loss_history"}))
+    else:
+        net = load_model(a.model) if a.model else None
+        s = evaluate(net, a.first, log=log)
+        if a.out:
+            json.dump(s, open(a.out, "w"), indent=1)
+        print(json.dumps({k: v for k, v in s.items() if k != "results"}))
+
+
+if __name__ == "__main__":
+    main()

@@ -108,3 +108,12 @@ def test_adam_first_step_is_sign_step():
     g = rnd((10,), 20)
     p1, _, _ = C.adam(p, g, np.zeros(10), np.zeros(10), 1e-2, 0.9, 0.999, 1e-12, 0.0, 1)
     np.testing.assert_allclose(p1, p - 1e-2 * np.sign(g), atol=1e-9)
+
+
+def test_channel_mean_is_symmetric_projection():
+    x = rnd((2, 3, 4, 5, 3), 21)
+    y = rnd((2, 3, 4, 5, 3), 22)
+    P = C.channel_mean
+    np.testing.assert_allclose(P(P(x)), P(x), atol=1e-15)
+    assert abs((P(x) * y).sum() - (x * P(y)).sum()) < 1e-12
+    np.testing.assert_allclose(P(x)[1, 2, 3, 4], x[1].reshape(-1, 3).mean(axis=0), atol=1e-15)

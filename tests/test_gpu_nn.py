@@ -168,6 +168,18 @@ def test_elementwise_ops(torch, nn):
     assert close_bf16(out.float().cpu().numpy(), C.leaky_grad_from_output(ylr, glr), np.abs(glr)) <= 1.0
 
 
+def test_channel_mean(torch, nn):
+    log("channel mean broadcast")
+    dims, c = (3, 4, 6, 10), 64
+    g = nn.geom(*dims)
+    x, xr = bf16_tensor(torch, randn(dims + (c,), 30))
+    y = torch.empty_like(x)
+    ws = torch.empty(nn.channel_mean_workspace(g, c) // 4, dtype=torch.float32, device="cuda:0")
+    nn.channel_mean(g, x, c, y, ws)
+    ref = C.channel_mean(xr)
+    assert close_bf16(y.float().cpu().numpy(), ref, C.channel_mean(np.abs(xr))) <= 1.0
+
+
 def test_mse_adam_and_channel_packing(torch, nn):
     log("mse / adam / pack channels")
     nv, c, creal = 5000, 32, 3

@@ -1,0 +1,160 @@
+"""End-to-end checks of the U-Net on the libcmnn kernels: loss and every
+layer's weight gradient against an FP64 oracle of the same architecture
+(oracle/conv_oracle.py ops on the same BF16 weights and inputs), and a short
+training run that must reduce the loss.
+
+The GPU rounds every activation and activation gradient to BF16 (8-bit
+significand), so after ~11 layers the network-level tolerance is a few per
+cent in norm; a wrong transpose, tap order or concat order gives O(1)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import conv_oracle as C
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_unet(x, P, widths, tgt, wt, per=(1, 0, 1)):
+    """Forward + backward of the documented architecture in FP64.
+    P[name] = (w [27, cout, cin], b [cout]); returns (loss, {name: (dw, db)})."""
+    w0, w1, w2 = widths
+    A = {}
+
+    def conv(name, inp, act=True):
+        w, b = P[name]
+        y = C.conv3d(inp, w, b, per)
+        return C.leaky(y) if act else y
+
+    A["e0a"] = conv("e0a", x)
+    A["s0"] = conv("e0b", A["e0a"])
+    A["p0"] = C.pool2(A["s0"])
+    A["e1a"] = conv("e1a", A["p0"])
+    A["s1"] = conv("e1b", A["e1a"])
+    A["p1"] = C.pool2(A["s1"])
+    A["ma"] = conv("ma", A["p1"])
+    A["mb"] = conv("mb", A["ma"])
+    A["c1"] = np.concatenate([A["s1"], C.up2(A["mb"])], axis=-1)
+    A["d1a"] = conv("d1a", A["c1"])
+    A["d1b"] = conv("d1b", A["d1a"])
+    A["c0"] = np.concatenate([A["s0"], C.up2(A["d1b"])], axis=-1)
+    A["d0a"] = conv("d0a", A["c0"])
+    A["d0b"] = conv("d0b", A["d0a"])
+    y = conv("head", A["d0b"], act=False)
+    nvox = int(np.prod(y.shape[:4]))
+    loss, g = C.mse(y.reshape(nvox, -1), tgt, wt)
+    G = {}
+
+    def back(name, inp, out, dy, act=True):
+        w, _ = P[name]
+        dpre = C.leaky_grad_from_output(out, dy) if act else dy
+        dx, dw, db = C.conv3d_grads(inp, w, dpre, per)
+        G[name] = (dw, db)
+        return dx
+
+    d = back("head", A["d0b"], y, g.reshape(y.shape), act=False)
+    d = back("d0b", A["d0a"], A["d0b"], d)
+    d = back("d0a", A["c0"], A["d0a"], d)
+    ds0c, du0 = d[..., :w0], d[..., w0:]
+    d = C.up2_grad(du0)
+    d = back("d1b", A["d1a"], A["d1b"], d)
+    d = back("d1a", A["c1"], A["d1a"], d)
+    ds1c, du1 = d[..., :w1], d[..., w1:]
+    d = C.up2_grad(du1)
+    d = back("mb", A["ma"], A["mb"], d)
+    d = back("ma", A["p1"], A["ma"], d)
+    ds1 = ds1c + C.pool2_grad(d)
+    d = back("e1b", A["e1a"], A["s1"], ds1)
+    d = back("e1a", A["p0"], A["e1a"], d)
+    ds0 = ds0c + C.pool2_grad(d)
+    d = back("e0b", A["e0a"], A["s0"], ds0)
+    back("e0a", x, A["e0a"], d)
+    return loss, G
+
+
+def test_unet_gradients_match_oracle():
+    import torch
+    from paper_1905_10182_amd import cmnn
+    from paper_1905_10182_amd.unet import UNet3D
+
+    n, dims, widths = 2, (4, 8, 8), (32, 64, 32)
+    log(f"U-Net gradient check n={n} dims={dims} widths={widths}")
+    net = UNet3D(dims, widths=widths, seed=3)
+    g = W.generator(4)
+    # give the biases non-zero values so that their gradients and the activations are exercised
+    for L in net.layers.values():
+        L["b"].copy_(torch.as_tensor(g.normal(0, 0.05, L["b"].shape), dtype=torch.float32))
+    net.pack()
+    nvox = n * int(np.prod(dims))
+    xin = np.zeros((2, nvox), np.float32)
+    xin[0] = (g.uniform(size=nvox) > 0.2)
+    xin[1] = g.uniform(size=nvox)
+    xs = torch.as_tensor(xin, device="cuda:0")
+    xb = torch.empty((n,) + dims + (net.cin0,), dtype=torch.bfloat16, device="cuda:0")
+    cmnn.pack_channels(nvox, xs, 2, xb, net.cin0)
+    tgt = torch.as_tensor(g.normal(0, 0.3, (3, nvox)), dtype=torch.float32, device="cuda:0")
+    wt = torch.as_tensor(xin[0], device="cuda:0")
+    out = net.forward(xb)
+    loss = torch.empty(2, dtype=torch.float32, device="cuda:0")
+    dy = torch.empty_like(out)
+    ws = torch.empty(cmnn.mse_workspace(nvox) // 4, dtype=torch.float32, device="cuda:0")
+    cmnn.mse(nvox, out, net.cout_head, 3, tgt, wt, loss, dy, ws)
+    net.backward(dy)
+    P = {k: (L["wf"].float().cpu().numpy().astype(np.float64), L["b"].cpu().numpy().astype(np.float64))
+         for k, L in net.layers.items()}
+    x64 = xb.float().cpu().numpy().astype(np.float64)
+    rl, RG = oracle_unet(x64, P, widths, tgt.cpu().numpy().astype(np.float64), xin[0].astype(np.float64))
+    el = abs(loss[0].item() / rl - 1)
+    log(f"  loss gpu {loss[0].item():.6e} oracle {rl:.6e} rel {el:.2e}")
+    assert el < 2e-2
+    worst = 0.0
+    for k, L in net.layers.items():
+        dw, db = RG[k]
+        ew = np.linalg.norm(L["dw"].cpu().numpy() - dw) / np.linalg.norm(dw)
+        eb = np.linalg.norm(L["db"].cpu().numpy() - db) / max(np.linalg.norm(db), 1e-30)
+        log(f"  {k}: dW rel {ew:.2e}  db rel {eb:.2e}")
+        worst = max(worst, ew, eb)
+    assert worst < 5e-2
+
+
+def test_unet_training_reduces_loss():
+    """Fit a smooth target (a per-sample Poiseuille-like field times the fluid
+    mask) from random geometry: the loss must fall by 10x in 150 Adam steps."""
+    import torch
+    from paper_1905_10182_amd import cmnn
+    from paper_1905_10182_amd.unet import UNet3D
+
+    n, dims = 4, (8, 8, 16)
+    log(f"U-Net training sanity n={n} dims={dims}")
+    net = UNet3D(dims, seed=5)
+    g = W.generator(6)
+    nvox = n * int(np.prod(dims))
+    solid = g.uniform(size=(n,) + dims) < 0.15
+    y = (np.arange(dims[1]) + 0.5) / dims[1]
+    prof = (4 * y * (1 - y))[None, None, :, None] * np.ones((n,) + dims)
+    xin = np.stack([(~solid).ravel(), (prof * ~solid).ravel()]).astype(np.float32)
+    tgt = np.stack([prof.ravel() * (~solid).ravel(), 0.3 * prof.ravel(), 0 * prof.ravel()]).astype(np.float32)
+    xs = torch.as_tensor(xin, device="cuda:0")
+    xb = torch.empty((n,) + dims + (net.cin0,), dtype=torch.bfloat16, device="cuda:0")
+    cmnn.pack_channels(nvox, xs, 2, xb, net.cin0)
+    tg = torch.as_tensor(tgt, device="cuda:0")
+    wt = torch.ones(nvox, dtype=torch.float32, device="cuda:0")
+    loss = torch.empty(2, dtype=torch.float32, device="cuda:0")
+    ws = torch.empty(cmnn.mse_workspace(nvox) // 4, dtype=torch.float32, device="cuda:0")
+    hist = []
+    for s in range(150):
+        out = net.forward(xb)
+        dy = torch.empty_like(out)
+        cmnn.mse(nvox, out, net.cout_head, 3, tg, wt, loss, dy, ws)
+        net.backward(dy)
+        net.adam_step(5e-4)
+        hist.append(loss[0].item())
+    log(f"  loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+    assert np.isfinite(hist).all() and hist[-1] < hist[0] / 10
