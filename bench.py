@@ -106,6 +106,27 @@ def copy_bandwidth():
     return 2 * 4 * n * reps / s / 1e9
 
 
+def warm_start():
+    """Steps to the 1e-8 residual for 64 held-out sphere channels (FP64
+    solver) from rest and from the shipped U-Net's prediction."""
+    from paper_1905_10182_amd import warmstart as ws
+
+    net = ws.load_model()
+    s = ws.evaluate(net, first_seed=1_000_000, nb=64, tol=1e-8, log=lambda m: print(f"[bench]   {m}", file=sys.stderr,
+                                                                                    flush=True))
+    r = s["results"]
+    return {"workload": "64 channels 64x32x32, 1-4 spheres r 3-8, F_x ~ U[1e-6, 1e-5], tau 0.8, fp64, "
+                        "seeds 1000000..1000063",
+            "mean_steps_cold": r["cold"]["mean_steps"], "mean_steps_warm": r["warm"]["mean_steps"],
+            "mean_steps_exact_moments": r["exact"]["mean_steps"],
+            "speedup_steps": round(s["speedup_steps_warm"], 3), "speedup_wall": round(s["speedup_wall_warm"], 3),
+            "speedup_steps_exact_moments": round(s["speedup_steps_exact"], 3),
+            "prediction_rel_error_u": round(s["prediction_rel_error_u"], 5),
+            "prediction_rel_error_rho": round(s["prediction_rel_error_rho"], 5),
+            "warm_vs_cold_final_rel": s["warm_vs_cold_final_rel"], "inference_s": round(s["inference_seconds"], 4),
+            "fallbacks": s["fallbacks"]}
+
+
 def cpu_baseline():
     """The FP64 oracle (closed-form route, OpenMP) on a bounded sample of the
     same workload: Taylor-Green 128^3, 400 steps."""
@@ -131,6 +152,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp16", action="store_true")
+    ap.add_argument("--no-warmstart", action="store_true")
     ap.add_argument("--n", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -163,6 +185,9 @@ def main():
             "speedup_vs_fp32_glups": round(r16s["glups"] / main_run["glups"], 3)}
         print(f"[bench] fp16 stochastic rounding {r16s['glups']:.2f} GLUPS", file=sys.stderr, flush=True)
     extra["device_copy_gbs"] = round(copy_bandwidth(), 1)
+    if not args.no_warmstart:
+        print("[bench] warm start: 64 sphere channels 64x32x32, cold vs U-Net init", file=sys.stderr, flush=True)
+        extra["warm_start"] = warm_start()
     achieved = main_run["bytes_per_launch"] / main_run["launch_s"] / 1e9
     traffic = measured_traffic()
     cpu = None

@@ -100,6 +100,15 @@ int cmnn_mse_workspace(size_t nvox, size_t* bytes);
 int cmnn_mse(size_t nvox, const void* pred, int32_t c, int32_t creal, const float* target, const float* weight,
              float* loss_out, void* dpred, void* workspace, size_t workspace_bytes, void* hip_stream);
 
+/* Global gradient-norm clipping, in place: norm = ||grad||_2 (FP64 sum of
+ * FP32 partials), grad *= min(1, max_norm / norm); max_norm = 0 only
+ * measures.  A non-finite norm zeroes grad.  norm_out (device, 2 floats)
+ * receives {norm before clipping, scale applied}.  workspace:
+ * cmnn_clip_grad_norm_workspace bytes. */
+int cmnn_clip_grad_norm_workspace(size_t n, size_t* bytes);
+int cmnn_clip_grad_norm(size_t n, float* grad, float max_norm, float* norm_out, void* workspace,
+                        size_t workspace_bytes, void* hip_stream);
+
 /* Adam with decoupled weight decay on FP32 master parameters (step >= 1). */
 int cmnn_adam(size_t n, float* param, const float* grad, float* m, float* v, float lr, float beta1, float beta2,
               float eps, float weight_decay, int32_t step, void* hip_stream);

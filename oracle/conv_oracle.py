@@ -10,7 +10,7 @@ Definitions written out with numpy in float64 on NDHWC arrays [n, d, h, w, c]:
   read at v + off is adjoint to a zero-padded write at v - off);
 - leaky ReLU (slope 0.1), 2x2x2 average pooling, 2x nearest upsampling,
   channel concatenation, per-sample channel means, masked mean-squared
-  error, Adam.
+  error, gradient-norm clipping, Adam.
 """
 import numpy as np
 
@@ -115,6 +115,13 @@ def mse(pred, target, weight):
     g = np.zeros_like(pred, dtype=np.float64)
     g[:, :creal] = 2.0 * weight[:, None] * d / norm
     return loss, g
+
+
+def clip_grad_norm(g, max_norm):
+    """(g * min(1, max_norm / ||g||), ||g||); max_norm = 0 leaves g unchanged."""
+    norm = float(np.sqrt((np.asarray(g, np.float64) ** 2).sum()))
+    scale = max_norm / norm if 0 < max_norm < norm else 1.0
+    return g * scale, norm
 
 
 def adam(p, g, m, v, lr, b1, b2, eps, wd, step):

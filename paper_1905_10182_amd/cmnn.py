@@ -13,7 +13,8 @@ ACT_NONE, ACT_LEAKY = 0, 1
 
 EXPORTS = ["cmnn_conv3d_fwd", "cmnn_conv3d_bwd_data", "cmnn_conv3d_bwd_weight_workspace", "cmnn_conv3d_bwd_weight",
            "cmnn_act_bwd", "cmnn_pool2_fwd", "cmnn_pool2_bwd", "cmnn_up2_fwd", "cmnn_up2_bwd", "cmnn_concat_fwd",
-           "cmnn_concat_bwd", "cmnn_add", "cmnn_channel_mean_workspace", "cmnn_channel_mean", "cmnn_mse_workspace", "cmnn_mse", "cmnn_adam", "cmnn_pack_weights",
+           "cmnn_concat_bwd", "cmnn_add", "cmnn_channel_mean_workspace", "cmnn_channel_mean", "cmnn_mse_workspace",
+           "cmnn_mse", "cmnn_clip_grad_norm_workspace", "cmnn_clip_grad_norm", "cmnn_adam", "cmnn_pack_weights",
            "cmnn_pack_channels", "cmnn_unpack_channels"]
 
 
@@ -60,6 +61,8 @@ def load_library():
     lib.cmnn_channel_mean.argtypes = [G, vp, i32, vp, vp, sz, vp]
     lib.cmnn_mse_workspace.argtypes = [sz, ctypes.POINTER(sz)]
     lib.cmnn_mse.argtypes = [sz, vp, i32, i32, vp, vp, vp, vp, vp, sz, vp]
+    lib.cmnn_clip_grad_norm_workspace.argtypes = [sz, ctypes.POINTER(sz)]
+    lib.cmnn_clip_grad_norm.argtypes = [sz, vp, f32, vp, vp, sz, vp]
     lib.cmnn_adam.argtypes = [sz, vp, vp, vp, vp, f32, f32, f32, f32, f32, i32, vp]
     lib.cmnn_pack_weights.argtypes = [vp, i32, i32, vp, vp, vp]
     lib.cmnn_pack_channels.argtypes = [sz, vp, i32, vp, i32, vp]
@@ -162,6 +165,17 @@ def mse_workspace(nv):
 def mse(nv, pred, c, creal, target, weight, loss2, dpred, ws):
     _check(load_library().cmnn_mse(nv, _p(pred), c, creal, _p(target), _p(weight), _p(loss2), _p(dpred), _p(ws),
                                    ws.numel() * ws.element_size(), _s()), "mse")
+
+
+def clip_grad_norm_workspace(n):
+    k = ctypes.c_size_t()
+    _check(load_library().cmnn_clip_grad_norm_workspace(n, ctypes.byref(k)), "clip_grad_norm_workspace")
+    return k.value
+
+
+def clip_grad_norm(g, max_norm, norm_out, ws):
+    _check(load_library().cmnn_clip_grad_norm(g.numel(), _p(g), max_norm, _p(norm_out), _p(ws),
+                                              ws.numel() * ws.element_size(), _s()), "clip_grad_norm")
 
 
 def adam(p, g, m, v, lr, b1, b2, eps, wd, step):

@@ -439,6 +439,49 @@ __global__ void k_adam(long long n, float* __restrict__ p, const float* __restri
     }
 }
 
+// Global gradient-norm clipping: per-block partial sums of g^2, a single
+// thread that forms the norm and the scale min(1, max_norm / norm) (0 for a
+// non-finite norm, which turns the update into a no-gradient step), then an
+// in-place scale read from device memory (no host round trip).
+constexpr int kClipBlocks = 512;
+
+__global__ __launch_bounds__(256) void k_sumsq_part(long long n, const float* __restrict__ g, float* __restrict__ part)
+{
+    __shared__ float sh[256];
+    float a = 0.f;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+        const float x = g[i];
+        a += x * x;
+    }
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_clip_final(const float* __restrict__ part, int nb, float max_norm, float* __restrict__ out)
+{
+    if (threadIdx.x != 0) return;
+    double a = 0.0;
+    for (int i = 0; i < nb; ++i) a += part[i];
+    const float norm = (float)sqrt(a);
+    float scale = 1.f;
+    if (!(norm < INFINITY)) scale = 0.f;
+    else if (max_norm > 0.f && norm > max_norm) scale = max_norm / norm;
+    out[0] = norm;
+    out[1] = scale;
+}
+
+__global__ void k_scale(long long n, float* __restrict__ g, const float* __restrict__ sc)
+{
+    const float a = sc[1];
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        g[i] = a == 0.f ? 0.f : g[i] * a;
+}
+
 __global__ void k_pack_w(const float* __restrict__ w, int cin, int cout, bf16* __restrict__ wf, bf16* __restrict__ wtr)
 {
     const long long total = 27LL * cin * cout;
@@ -721,6 +764,29 @@ int cmnn_mse(size_t nvox, const void* pred, int32_t c, int32_t creal, const floa
         if (launched()) return CMNN_EHIP;
     }
     return CMNN_OK;
+}
+
+int cmnn_clip_grad_norm_workspace(size_t n, size_t* bytes)
+{
+    if (!bytes || n == 0) return CMNN_EINVAL;
+    *bytes = kClipBlocks * sizeof(float);
+    return CMNN_OK;
+}
+
+int cmnn_clip_grad_norm(size_t n, float* grad, float max_norm, float* norm_out, void* workspace,
+                        size_t workspace_bytes, void* hip_stream)
+{
+    if (!grad || !norm_out || !workspace || n == 0 || workspace_bytes < kClipBlocks * sizeof(float) ||
+        !(max_norm >= 0.f))
+        return CMNN_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    float* part = (float*)workspace;
+    k_sumsq_part<<<kClipBlocks, 256, 0, s>>>((long long)n, grad, part);
+    if (launched()) return CMNN_EHIP;
+    k_clip_final<<<1, 64, 0, s>>>(part, kClipBlocks, max_norm, norm_out);
+    if (launched()) return CMNN_EHIP;
+    k_scale<<<grid_for((long long)n), 256, 0, s>>>((long long)n, grad, norm_out);
+    return launched();
 }
 
 int cmnn_adam(size_t n, float* param, const float* grad, float* m, float* v, float lr, float beta1, float beta2,

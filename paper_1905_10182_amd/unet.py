@@ -6,11 +6,13 @@ runs in libcmnn; PyTorch only allocates the tensors.  Layout NDHWC BF16 with
 channels padded to 32; padding is periodic in z and x, zero in y (the walls).
 
 Architecture (widths w0, w1, w2; leaky ReLU after every 3x3x3 convolution
-except the head):
+except the head; the channel means at the bottleneck give every voxel the
+sample-wide context, e.g. the total blockage that sets the flow rate):
 
     enc0: conv(in -> w0), conv(w0 -> w0)              full resolution  -> s0
     enc1: pool, conv(w0 -> w1), conv(w1 -> w1)         1/2              -> s1
-    mid:  pool, conv(w1 -> w2), conv(w2 -> w2)         1/4
+    mid:  pool, conv(w1 -> w2), concat(per-sample channel means),
+          conv(2 w2 -> w2)                             1/4
     dec1: up, concat(s1), conv(w1 + w2 -> w1), conv(w1 -> w1)
     dec0: up, concat(s0), conv(w0 + w1 -> w0), conv(w0 -> w0)
     head: conv(w0 -> out)
@@ -40,7 +42,7 @@ class UNet3D:
         spec = [  # name, cin (padded), cout (padded), real cin, real cout, activation
             ("e0a", self.cin0, w0, in_ch, w0, cmnn.ACT_LEAKY), ("e0b", w0, w0, w0, w0, cmnn.ACT_LEAKY),
             ("e1a", w0, w1, w0, w1, cmnn.ACT_LEAKY), ("e1b", w1, w1, w1, w1, cmnn.ACT_LEAKY),
-            ("ma", w1, w2, w1, w2, cmnn.ACT_LEAKY), ("mb", w2, w2, w2, w2, cmnn.ACT_LEAKY),
+            ("ma", w1, w2, w1, w2, cmnn.ACT_LEAKY), ("mb", 2 * w2, w2, 2 * w2, w2, cmnn.ACT_LEAKY),
             ("d1a", w1 + w2, w1, w1 + w2, w1, cmnn.ACT_LEAKY), ("d1b", w1, w1, w1, w1, cmnn.ACT_LEAKY),
             ("d0a", w0 + w1, w0, w0 + w1, w0, cmnn.ACT_LEAKY), ("d0b", w0, w0, w0, w0, cmnn.ACT_LEAKY),
             ("head", w0, self.cout_head, w0, out_ch, cmnn.ACT_NONE),
@@ -78,6 +80,9 @@ class UNet3D:
         self.nparams_real = sum(27 * rco * rci + rco for (_, _, _, rci, rco, _) in spec)
         self.step_count = 0
         self._ws = None
+        self._mws = None
+        self._cws = None
+        self.grad_norm = None
         self.pack()
 
     # -- parameters
@@ -126,7 +131,11 @@ class UNet3D:
         A["p1"] = self._t(n, 2, w1)
         cmnn.pool2_fwd(g1, A["s1"], w1, A["p1"])
         A["ma"] = self._conv("ma", g2, A["p1"], 2)
-        A["mb"] = self._conv("mb", g2, A["ma"], 2)
+        gm = self._t(n, 2, w2)
+        cmnn.channel_mean(g2, A["ma"], w2, gm, self._mean_ws(g2, w2))
+        A["cm"] = self._t(n, 2, 2 * w2)
+        cmnn.concat_fwd(cmnn.nvox(g2), A["ma"], w2, gm, w2, A["cm"])
+        A["mb"] = self._conv("mb", g2, A["cm"], 2)
         A["u1"] = self._t(n, 1, w2)
         cmnn.up2_fwd(g2, A["mb"], w2, A["u1"])
         A["c1"] = self._t(n, 1, w1 + w2)
@@ -154,6 +163,12 @@ class UNet3D:
         if self._ws is None or self._ws.numel() * 4 < need:
             self._ws = self.torch.empty((need + 3) // 4, dtype=self.torch.float32, device=self.device)
         return self._ws
+
+    def _mean_ws(self, g, c):
+        need = cmnn.channel_mean_workspace(g, c)
+        if self._mws is None or self._mws.numel() * 4 < need:
+            self._mws = self.torch.empty((need + 3) // 4, dtype=self.torch.float32, device=self.device)
+        return self._mws
 
     def _conv_bwd(self, name, g, x, y, dy, level, need_dx=True):
         """dy: gradient w.r.t. the layer output y; returns the gradient w.r.t. x."""
@@ -190,7 +205,13 @@ class UNet3D:
         cmnn.concat_bwd(cmnn.nvox(g1), d, w1, w2, ds1c, du1)
         d = self._t(n, 2, w2)
         cmnn.up2_bwd(g2, du1, w2, d)
-        d = self._conv_bwd("mb", g2, A["ma"], A["mb"], d, 2)
+        d = self._conv_bwd("mb", g2, A["cm"], A["mb"], d, 2)
+        dma, dgm = self._t(n, 2, w2), self._t(n, 2, w2)
+        cmnn.concat_bwd(cmnn.nvox(g2), d, w2, w2, dma, dgm)
+        dmean = self._t(n, 2, w2)
+        cmnn.channel_mean(g2, dgm, w2, dmean, self._mean_ws(g2, w2))  # the mean map is self-adjoint
+        d = self._t(n, 2, w2)
+        cmnn.add(dma, dmean, d)
         d = self._conv_bwd("ma", g2, A["p1"], A["ma"], d, 2)
         ds1p = self._t(n, 1, w1)
         cmnn.pool2_bwd(g1, d, w1, ds1p)
@@ -205,7 +226,16 @@ class UNet3D:
         d = self._conv_bwd("e0b", g0, A["e0a"], A["s0"], ds0, 0)
         self._conv_bwd("e0a", g0, A["x"], A["e0a"], d, 0, need_dx=False)
 
-    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0, clip=None):
+        """One Adam update from self.grads.  clip: global gradient-norm limit
+        (0 measures only); the pre-clip norm and the applied scale land in
+        self.grad_norm (device FP32[2])."""
+        if clip is not None:
+            if self._cws is None:
+                self._cws = self.torch.empty(cmnn.clip_grad_norm_workspace(self.nparams) // 4,
+                                             dtype=self.torch.float32, device=self.device)
+                self.grad_norm = self.torch.zeros(2, dtype=self.torch.float32, device=self.device)
+            cmnn.clip_grad_norm(self.grads, float(clip), self.grad_norm, self._cws)
         self.step_count += 1
         cmnn.adam(self.params, self.grads, self.m, self.v, lr, beta1, beta2, eps, weight_decay, self.step_count)
         self.pack()

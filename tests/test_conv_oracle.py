@@ -117,3 +117,14 @@ def test_channel_mean_is_symmetric_projection():
     np.testing.assert_allclose(P(P(x)), P(x), atol=1e-15)
     assert abs((P(x) * y).sum() - (x * P(y)).sum()) < 1e-12
     np.testing.assert_allclose(P(x)[1, 2, 3, 4], x[1].reshape(-1, 3).mean(axis=0), atol=1e-15)
+
+
+def test_clip_grad_norm_projects_onto_ball():
+    g = rnd((7, 5), 23)
+    n = np.linalg.norm(g)
+    c, n0 = C.clip_grad_norm(g, 0.5 * n)
+    assert n0 == pytest.approx(n)
+    assert np.linalg.norm(c) == pytest.approx(0.5 * n)
+    np.testing.assert_allclose(c / np.linalg.norm(c), g / n, atol=1e-15)  # direction kept
+    np.testing.assert_array_equal(C.clip_grad_norm(g, 2 * n)[0], g)  # inside the ball: unchanged
+    np.testing.assert_array_equal(C.clip_grad_norm(g, 0.0)[0], g)  # 0: measure only

@@ -180,6 +180,25 @@ def test_channel_mean(torch, nn):
     assert close_bf16(y.float().cpu().numpy(), ref, C.channel_mean(np.abs(xr))) <= 1.0
 
 
+def test_clip_grad_norm(torch, nn):
+    log("gradient-norm clipping")
+    g64 = randn((100003,), 31)
+    n = int(g64.size)
+    ws = torch.empty(nn.clip_grad_norm_workspace(n) // 4, dtype=torch.float32, device="cuda:0")
+    out = torch.empty(2, dtype=torch.float32, device="cuda:0")
+    for frac in (0.3, 2.0, 0.0):
+        g32 = g64.astype(np.float32)
+        ref, norm = C.clip_grad_norm(g32.astype(np.float64), frac * np.linalg.norm(g32.astype(np.float64)))
+        g = torch.as_tensor(g32, device="cuda:0")
+        nn.clip_grad_norm(g, float(frac * norm), out, ws)
+        assert abs(out[0].item() / norm - 1) < 1e-5
+        np.testing.assert_allclose(g.cpu().numpy(), ref, rtol=2e-5, atol=1e-7 * np.abs(ref).max())
+    g = torch.as_tensor(g64.astype(np.float32), device="cuda:0")
+    g[7] = float("inf")
+    nn.clip_grad_norm(g, 1.0, out, ws)
+    assert out[1].item() == 0.0 and not g.abs().max().item()
+
+
 def test_mse_adam_and_channel_packing(torch, nn):
     log("mse / adam / pack channels")
     nv, c, creal = 5000, 32, 3

@@ -40,7 +40,8 @@ def oracle_unet(x, P, widths, tgt, wt, per=(1, 0, 1)):
     A["s1"] = conv("e1b", A["e1a"])
     A["p1"] = C.pool2(A["s1"])
     A["ma"] = conv("ma", A["p1"])
-    A["mb"] = conv("mb", A["ma"])
+    A["cm"] = np.concatenate([A["ma"], C.channel_mean(A["ma"])], axis=-1)
+    A["mb"] = conv("mb", A["cm"])
     A["c1"] = np.concatenate([A["s1"], C.up2(A["mb"])], axis=-1)
     A["d1a"] = conv("d1a", A["c1"])
     A["d1b"] = conv("d1b", A["d1a"])
@@ -68,7 +69,8 @@ def oracle_unet(x, P, widths, tgt, wt, per=(1, 0, 1)):
     d = back("d1a", A["c1"], A["d1a"], d)
     ds1c, du1 = d[..., :w1], d[..., w1:]
     d = C.up2_grad(du1)
-    d = back("mb", A["ma"], A["mb"], d)
+    d = back("mb", A["cm"], A["mb"], d)
+    d = d[..., :w2] + C.channel_mean(d[..., w2:])
     d = back("ma", A["p1"], A["ma"], d)
     ds1 = ds1c + C.pool2_grad(d)
     d = back("e1b", A["e1a"], A["s1"], ds1)
@@ -158,3 +160,21 @@ def test_unet_training_reduces_loss():
         hist.append(loss[0].item())
     log(f"  loss {hist[0]:.3e} -> {hist[-1]:.3e}")
     assert np.isfinite(hist).all() and hist[-1] < hist[0] / 10
+
+
+def test_shipped_model_warm_start():
+    """The shipped network on 8 held-out channels: prediction within 5% of the
+    converged FP64 velocity, fewer solver steps to the 1e-8 residual than from
+    rest, and the same converged state (the warm start changes only the path)."""
+    from paper_1905_10182_amd import warmstart as WS
+
+    log("shipped U-Net warm start on 8 held-out channels")
+    net = WS.load_model()
+    s = WS.evaluate(net, first_seed=1_000_000, nb=8, tol=1e-8, log=log)
+    log(f"  u error {s['prediction_rel_error_u']:.3e} rho error {s['prediction_rel_error_rho']:.3e} "
+        f"speedup {s['speedup_steps_warm']:.2f}")
+    assert s["fallbacks"] == 0
+    assert all(r["all_converged"] for r in s["results"].values())
+    assert s["prediction_rel_error_u"] < 0.05
+    assert s["speedup_steps_warm"] > 1.2
+    assert s["warm_vs_cold_final_rel"] < 2e-5
