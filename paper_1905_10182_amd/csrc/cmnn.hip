@@ -83,6 +83,24 @@ __device__ __forceinline__ bool neighbour(const G& g, long long m, int t, int s,
     return true;
 }
 
+#define GRID_STRIDE(i, total) \
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < (total); i += (long long)gridDim.x * blockDim.x)
+
+__device__ __forceinline__ void unpack8(u4 v, float (&f)[8])
+{
+    const bf16x8 b = __builtin_bit_cast(bf16x8, v);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) f[i] = (float)b[i];
+}
+
+__device__ __forceinline__ u4 pack8(const float (&f)[8])
+{
+    bf16x8 b;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) b[i] = (bf16)f[i];
+    return __builtin_bit_cast(u4, b);
+}
+
 __device__ __forceinline__ bf16x8 ld8(const bf16* p) { return __builtin_bit_cast(bf16x8, *(const u4*)p); }
 
 // ---------------------------------------------------------------------------
@@ -132,6 +150,97 @@ __global__ __launch_bounds__(256) void k_conv_fwd(G g, const bf16* __restrict__ 
             float v = acc[b][i] + bb;
             if (ACT == CMNN_ACT_LEAKY) v = v > 0.f ? v : kLeak * v;
             y[m * cout + co] = (bf16)v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// brick-tiled forward convolution (and data gradient), for extents that are
+// multiples of the 4 x 4 x 16 (d, h, w) brick
+//
+// Workgroup = one brick of 256 output voxels x (16 * NB) output channels.
+// Per 32-channel input chunk the brick's 6 x 6 x 18 halo is staged once in LDS
+// (voxel stride 80 bytes: 16 consecutive voxels of a 16-byte fragment read
+// land on distinct bank groups), and every one of the 27 taps reads its A
+// fragments from there: each input value is fetched from memory once per
+// brick instead of once per tap.  Wave w owns the 4 brick rows (d, h) =
+// (w, 0..3), i.e. 4 MFMA row blocks of 16 x-consecutive voxels, and keeps
+// 4 x NB accumulator tiles: each B fragment (weights, through L1) feeds 4
+// MFMAs and each A fragment (LDS) feeds NB.
+
+constexpr int kTD = 4, kTH = 4, kTW = 16;
+constexpr int kHD = kTD + 2, kHH = kTH + 2, kHW = kTW + 2;
+constexpr int kHalo = kHD * kHH * kHW;  // 648 voxels
+constexpr int kVStride = 40;            // bf16 per staged voxel (32 channels + 8 pad)
+
+template <int NB, int SIGN, int ACT>
+__global__ __launch_bounds__(256) void k_conv_tile(G g, const bf16* __restrict__ x, int cin,
+                                                   const bf16* __restrict__ wt, const float* __restrict__ bias,
+                                                   int cout, bf16* __restrict__ y, unsigned xcd_span)
+{
+    __shared__ __attribute__((aligned(16))) bf16 sx[kHalo * kVStride];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // blocks are dealt round-robin to the 8 XCDs: give each XCD a contiguous
+    // run of bricks so that halo overlaps and weights share its L2
+    unsigned bid = blockIdx.x;
+    if (xcd_span) bid = (bid & 7u) * xcd_span + (bid >> 3);
+    const int nbw = g.w / kTW, nbh = g.h / kTH, nbd = g.d / kTD;
+    int r = (int)bid;
+    const int x0 = (r % nbw) * kTW;
+    r /= nbw;
+    const int h0 = (r % nbh) * kTH;
+    r /= nbh;
+    const int d0 = (r % nbd) * kTD;
+    const long long n = r / nbd;
+    const int co0 = blockIdx.y * 16 * NB;
+    f4 acc[4][NB];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[m][b] = f4{0.f, 0.f, 0.f, 0.f};
+    const bf16* wl = wt + (long long)(co0 + (lane & 15)) * cin + (lane >> 4) * 8;
+    for (int c0 = 0; c0 < cin; c0 += 32) {
+        __syncthreads();
+        for (int p = tid; p < kHalo * 4; p += 256) {
+            const int hv = p >> 2, part = p & 3;
+            const int hx = hv % kHW, hh = (hv / kHW) % kHH, hd = hv / (kHW * kHH);
+            int sd = 0, sh = 0, sw = 0;
+            u4 v = u4{0u, 0u, 0u, 0u};
+            if (shift_axis(d0, hd - 1, g.d, g.per[0], sd) && shift_axis(h0, hh - 1, g.h, g.per[1], sh) &&
+                shift_axis(x0, hx - 1, g.w, g.per[2], sw))
+                v = *(const u4*)(x + (((n * g.d + sd) * g.h + sh) * g.w + sw) * cin + c0 + part * 8);
+            *(u4*)&sx[hv * kVStride + part * 8] = v;
+        }
+        __syncthreads();
+#pragma unroll 3
+        for (int t = 0; t < 27; ++t) {
+            const int dz = SIGN * (t / 9 - 1), dy = SIGN * ((t / 3) % 3 - 1), dx = SIGN * (t % 3 - 1);
+            bf16x8 bw[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) bw[b] = ld8(wl + ((long long)t * cout + 16 * b) * cin + c0);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int hv = ((wave + 1 + dz) * kHH + (m + 1 + dy)) * kHW + (lane & 15) + 1 + dx;
+                const bf16x8 a = *(const bf16x8*)&sx[hv * kVStride + (lane >> 4) * 8];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) acc[m][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[b], acc[m][b], 0, 0, 0);
+            }
+        }
+    }
+    // D[row][col]: row = voxel (lane / 16) * 4 + i of the block's x-row, col = output channel lane % 16
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const long long vrow = ((n * g.d + d0 + wave) * g.h + h0 + m) * g.w + x0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int co = co0 + 16 * b + (lane & 15);
+            const float bb = bias ? bias[co] : 0.f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float v = acc[m][b][i] + bb;
+                if (ACT == CMNN_ACT_LEAKY) v = v > 0.f ? v : kLeak * v;
+                y[(vrow + (lane >> 4) * 4 + i) * cout + co] = (bf16)v;
+            }
         }
     }
 }
@@ -197,13 +306,189 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(G g, const bf16* __restrict_
     }
 }
 
-__global__ void k_sum_chunks(const float* __restrict__ part, long long per, int nchunk, float* __restrict__ out)
+// ---------------------------------------------------------------------------
+// brick-tiled weight gradient (extents multiples of the 4 x 4 x 16 brick)
+//
+// Workgroup (chunk of bricks, 32 output channels, 32 input channels), all 27
+// taps.  Per brick, dy and the halo of x are staged in LDS channel-major (the
+// MFMA K axis is the voxel axis, so a fragment is 8 consecutive voxels of one
+// channel): dy as [co][256 voxels], x as three copies [dx][ci][36 halo rows x
+// 16 voxels], copy dx holding x positions x0 + dx .. x0 + dx + 15, so that every
+// tap's fragment is an aligned 16-byte LDS read.  Each thread stages 8 x 8
+// (voxel x channel) blocks: eight 16-byte global loads, a register transpose,
+// eight 16-byte LDS stores.  Row strides are padded by 16 bytes so the 16 rows
+// of a fragment read fall on distinct bank groups.  Wave w accumulates the
+// 2 x 2 blocks of 16 x 16 for taps w, w + 4, ... (7 or 6 taps): the dy
+// fragments of a K step are read once and serve all of them.
+
+constexpr int kDyStride = 256 + 8;        // bf16 per co row of staged dy
+constexpr int kXStride = 36 * 16 + 8;     // bf16 per ci row of one staged x copy
+constexpr int kXCopy = 32 * kXStride;     // bf16 per copy
+
+__device__ __forceinline__ void transpose8x8(const u4 (&in)[8], u4 (&out)[8])
 {
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < per; i += (long long)gridDim.x * blockDim.x) {
-        float s = 0.f;
-        for (int c = 0; c < nchunk; ++c) s += part[(long long)c * per + i];
-        out[i] = s;
+    // in[i] holds channels 0..7 of voxel i (bf16 pairs per dword); out[c] holds voxels 0..7 of channel c
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int k = c >> 1, hi = c & 1;
+        unsigned o[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const unsigned a = in[2 * j][k], b = in[2 * j + 1][k];
+            o[j] = hi ? ((a >> 16) | (b & 0xffff0000u)) : ((a & 0xffffu) | (b << 16));
+        }
+        out[c] = u4{o[0], o[1], o[2], o[3]};
     }
+}
+
+__global__ __launch_bounds__(256) void k_conv_bwd_w_tile(G g, const bf16* __restrict__ x, int cin,
+                                                         const bf16* __restrict__ dy, int cout, int bricks_per_chunk,
+                                                         float* __restrict__ part, float* __restrict__ bpart)
+{
+    __shared__ __attribute__((aligned(16))) bf16 sdy[32 * kDyStride];
+    __shared__ __attribute__((aligned(16))) bf16 sxc[3 * kXCopy];
+    __shared__ float sbias[256];
+    // bias gradient (column sums of dy) from the staged dy, by the ci-tile-0 workgroups:
+    // thread (co = tid / 8, segment tid % 8) sums 32 voxels of each brick
+    const bool do_bias = bpart != nullptr && blockIdx.x % (cin / 32) == 0;
+    float bsum = 0.f;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ct = cout / 32, it = cin / 32;
+    int bid = blockIdx.x;
+    const int cit = bid % it;
+    bid /= it;
+    const int cot = bid % ct;
+    const int ch = bid / ct;
+    const int nbw = g.w / kTW, nbh = g.h / kTH, nbd = g.d / kTD;
+    const long long nbricks = (long long)g.n * nbd * nbh * nbw;
+    f4 acc[7][2][2];
+#pragma unroll
+    for (int k = 0; k < 7; ++k)
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) acc[k][a][b] = f4{0.f, 0.f, 0.f, 0.f};
+    const long long b0 = (long long)ch * bricks_per_chunk;
+    const long long b1 = b0 + bricks_per_chunk < nbricks ? b0 + bricks_per_chunk : nbricks;
+    for (long long br = b0; br < b1; ++br) {
+        long long r = br;
+        const int x0 = (int)(r % nbw) * kTW;
+        r /= nbw;
+        const int h0 = (int)(r % nbh) * kTH;
+        r /= nbh;
+        const int d0 = (int)(r % nbd) * kTD;
+        const long long n = r / nbd;
+        __syncthreads();
+        // dy: 32 x-octets (16 rows x 2) x 4 channel groups = 128 blocks
+        if (tid < 128) {
+            const int oc = tid >> 2, cg = tid & 3;
+            const int row = oc >> 1, xo = (oc & 1) * 8;
+            const long long v = ((n * g.d + d0 + (row >> 2)) * g.h + h0 + (row & 3)) * g.w + x0 + xo;
+            const bf16* src = dy + v * cout + cot * 32 + cg * 8;
+            u4 in[8], out[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) in[i] = *(const u4*)(src + (long long)i * cout);
+            transpose8x8(in, out);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) *(u4*)&sdy[(cg * 8 + c) * kDyStride + row * 16 + xo] = out[c];
+        }
+        // x: 3 copies x 36 halo rows x 2 octets x 4 channel groups = 864 blocks
+        for (int p = tid; p < 864; p += 256) {
+            const int cg = p & 3, oc = (p >> 2) % 72, cx = p / 288;
+            const int hr = oc >> 1, xo = (oc & 1) * 8;
+            const int hd = hr / 6, hh = hr % 6;
+            int sd = 0, sh = 0;
+            const bool rok = shift_axis(d0, hd - 1, g.d, g.per[0], sd) && shift_axis(h0, hh - 1, g.h, g.per[1], sh);
+            const long long rowbase = ((n * g.d + sd) * g.h + sh) * g.w;
+            u4 in[8], out[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                int sw = 0;
+                in[i] = u4{0u, 0u, 0u, 0u};
+                if (rok && shift_axis(x0, cx - 1 + xo + i, g.w, g.per[2], sw))
+                    in[i] = *(const u4*)(x + (rowbase + sw) * cin + cit * 32 + cg * 8);
+            }
+            transpose8x8(in, out);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) *(u4*)&sxc[cx * kXCopy + (cg * 8 + c) * kXStride + hr * 16 + xo] = out[c];
+        }
+        __syncthreads();
+        if (do_bias) {
+            const bf16* q = &sdy[(tid >> 3) * kDyStride + (tid & 7) * 32];
+#pragma unroll 8
+            for (int k = 0; k < 32; ++k) bsum += (float)q[k];
+        }
+        // 8 K steps of 32 voxels (two brick rows); lane group j = lane / 16 takes voxels 8j..8j+7
+        const int j = lane >> 4, l16 = lane & 15;
+#pragma unroll 2
+        for (int ks = 0; ks < 8; ++ks) {
+            const int row = ks * 2 + (j >> 1), xo = (j & 1) * 8;
+            bf16x8 a[2];
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) a[cb] = *(const bf16x8*)&sdy[(cb * 16 + l16) * kDyStride + row * 16 + xo];
+            const int dd = row >> 2, hh = row & 3;
+#pragma unroll
+            for (int k = 0; k < 7; ++k) {
+                const int t = wave + 4 * k;
+                if (t < 27) {
+                    const int dz = t / 9 - 1, dyy = (t / 3) % 3 - 1, cx = t % 3;
+                    const int hr = (dd + 1 + dz) * 6 + hh + 1 + dyy;
+#pragma unroll
+                    for (int ib = 0; ib < 2; ++ib) {
+                        const bf16x8 b =
+                            *(const bf16x8*)&sxc[cx * kXCopy + (ib * 16 + l16) * kXStride + hr * 16 + xo];
+#pragma unroll
+                        for (int cb = 0; cb < 2; ++cb)
+                            acc[k][cb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[cb], b, acc[k][cb][ib], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+    if (do_bias) {
+        sbias[tid] = bsum;
+        __syncthreads();
+        if (tid < 32) {
+            float b = 0.f;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) b += sbias[tid * 8 + k];
+            bpart[(long long)ch * cout + cot * 32 + tid] = b;
+        }
+    }
+    // D[co][ci]: row (lane / 16) * 4 + i, column lane % 16
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        const int t = wave + 4 * k;
+        if (t >= 27) continue;
+        float* p = part + (((long long)ch * 27 + t) * cout) * cin;
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int co = cot * 32 + cb * 16 + (lane >> 4) * 4 + i;
+                    const int ci = cit * 32 + ib * 16 + (lane & 15);
+                    p[(long long)co * cin + ci] = acc[k][cb][ib][i];
+                }
+    }
+}
+
+// out[e] = sum over chunks of part[chunk][e], in a fixed order: wave s of a
+// workgroup sums chunks s, s + 4, s + 8, ... for 64 consecutive elements, then
+// the four wave sums are added in order.
+__global__ __launch_bounds__(256) void k_sum_chunks(const float* __restrict__ part, long long per, int nchunk,
+                                                    float* __restrict__ out)
+{
+    __shared__ float sh[4][64];
+    const int e = threadIdx.x & 63, sl = threadIdx.x >> 6;
+    const long long i = (long long)blockIdx.x * 64 + e;
+    float acc = 0.f;
+    if (i < per)
+        for (int c = sl; c < nchunk; c += 4) acc += part[(long long)c * per + i];
+    sh[sl][e] = acc;
+    __syncthreads();
+    if (sl == 0 && i < per) out[i] = ((sh[0][e] + sh[1][e]) + sh[2][e]) + sh[3][e];
 }
 
 // Per-chunk column sums of a [rows][cols] BF16 matrix (cols <= 256): thread t
@@ -361,6 +646,157 @@ __global__ void k_add(long long n, const bf16* __restrict__ a, const bf16* __res
 {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         y[i] = (bf16)((float)a[i] + (float)b[i]);
+}
+
+// 16-byte variants of the elementwise kernels (8 channels per thread), used when
+// the channel counts are multiples of 8 and the pointers 16-byte aligned
+
+__global__ void k_act_bwd8(const u4* __restrict__ y, const u4* __restrict__ dy, u4* __restrict__ dp, long long n8, int act)
+{
+    GRID_STRIDE(i, n8)
+    {
+        float fy[8], fd[8];
+        unpack8(y[i], fy);
+        unpack8(dy[i], fd);
+        if (act == CMNN_ACT_LEAKY)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) fd[k] = fy[k] <= 0.f ? kLeak * fd[k] : fd[k];
+        dp[i] = pack8(fd);
+    }
+}
+
+__global__ void k_pool2_fwd8(G g, const bf16* __restrict__ x, int c, bf16* __restrict__ y)
+{
+    const int d2 = g.d / 2, h2 = g.h / 2, w2 = g.w / 2, q8 = c / 8;
+    GRID_STRIDE(i, (long long)g.n * d2 * h2 * w2 * q8)
+    {
+        const int q = (int)(i % q8);
+        long long r = i / q8;
+        const int w = (int)(r % w2);
+        r /= w2;
+        const int h = (int)(r % h2);
+        r /= h2;
+        const int d = (int)(r % d2);
+        const long long n = r / d2;
+        float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, f[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const long long v = ((n * g.d + 2 * d + (k >> 2)) * g.h + 2 * h + ((k >> 1) & 1)) * g.w + 2 * w + (k & 1);
+            unpack8(*(const u4*)(x + v * c + 8 * q), f);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) s[e] += f[e];
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s[e] *= 0.125f;
+        *(u4*)(y + i * 8) = pack8(s);
+    }
+}
+
+__global__ void k_pool2_bwd8(G g, const bf16* __restrict__ dy, int c, bf16* __restrict__ dx)
+{
+    const int q8 = c / 8;
+    GRID_STRIDE(i, g.nvox * q8)
+    {
+        const int q = (int)(i % q8);
+        long long r = i / q8;
+        const int w = (int)(r % g.w);
+        r /= g.w;
+        const int h = (int)(r % g.h);
+        r /= g.h;
+        const int d = (int)(r % g.d);
+        const long long n = r / g.d;
+        const long long v = ((n * (g.d / 2) + d / 2) * (g.h / 2) + h / 2) * (g.w / 2) + w / 2;
+        float f[8];
+        unpack8(*(const u4*)(dy + v * c + 8 * q), f);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) f[e] *= 0.125f;
+        *(u4*)(dx + i * 8) = pack8(f);
+    }
+}
+
+__global__ void k_up2_fwd8(G g, const bf16* __restrict__ x, int c, bf16* __restrict__ y)
+{
+    const int D = 2 * g.d, H = 2 * g.h, W = 2 * g.w, q8 = c / 8;
+    GRID_STRIDE(i, (long long)g.n * D * H * W * q8)
+    {
+        const int q = (int)(i % q8);
+        long long r = i / q8;
+        const int w = (int)(r % W);
+        r /= W;
+        const int h = (int)(r % H);
+        r /= H;
+        const int d = (int)(r % D);
+        const long long n = r / D;
+        const long long v = ((n * g.d + d / 2) * g.h + h / 2) * g.w + w / 2;
+        *(u4*)(y + i * 8) = *(const u4*)(x + v * c + 8 * q);
+    }
+}
+
+__global__ void k_up2_bwd8(G g, const bf16* __restrict__ dy, int c, bf16* __restrict__ dx)
+{
+    const int H = 2 * g.h, W = 2 * g.w, q8 = c / 8;
+    GRID_STRIDE(i, g.nvox * q8)
+    {
+        const int q = (int)(i % q8);
+        long long r = i / q8;
+        const int w = (int)(r % g.w);
+        r /= g.w;
+        const int h = (int)(r % g.h);
+        r /= g.h;
+        const int d = (int)(r % g.d);
+        const long long n = r / g.d;
+        float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, f[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const long long v = ((n * (2 * g.d) + 2 * d + (k >> 2)) * H + 2 * h + ((k >> 1) & 1)) * W + 2 * w + (k & 1);
+            unpack8(*(const u4*)(dy + v * c + 8 * q), f);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) s[e] += f[e];
+        }
+        *(u4*)(dx + i * 8) = pack8(s);
+    }
+}
+
+__global__ void k_concat_fwd8(long long nvox, const bf16* __restrict__ a, int ca, const bf16* __restrict__ b, int cb,
+                              bf16* __restrict__ y)
+{
+    const int qa = ca / 8, q8 = (ca + cb) / 8;
+    GRID_STRIDE(i, nvox * q8)
+    {
+        const long long v = i / q8;
+        const int q = (int)(i % q8);
+        *(u4*)(y + i * 8) = q < qa ? *(const u4*)(a + v * ca + 8 * q) : *(const u4*)(b + v * cb + 8 * (q - qa));
+    }
+}
+
+__global__ void k_concat_bwd8(long long nvox, const bf16* __restrict__ dy, int ca, int cb, bf16* __restrict__ da,
+                              bf16* __restrict__ db)
+{
+    const int qa = ca / 8, q8 = (ca + cb) / 8;
+    GRID_STRIDE(i, nvox * q8)
+    {
+        const long long v = i / q8;
+        const int q = (int)(i % q8);
+        const u4 e = *(const u4*)(dy + i * 8);
+        if (q < qa) {
+            if (da) *(u4*)(da + v * ca + 8 * q) = e;
+        } else if (db) {
+            *(u4*)(db + v * cb + 8 * (q - qa)) = e;
+        }
+    }
+}
+
+__global__ void k_add8(long long n8, const u4* __restrict__ a, const u4* __restrict__ b, u4* __restrict__ y)
+{
+    GRID_STRIDE(i, n8)
+    {
+        float fa[8], fb[8];
+        unpack8(a[i], fa);
+        unpack8(b[i], fb);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) fa[e] += fb[e];
+        y[i] = pack8(fa);
+    }
 }
 
 // masked MSE: per-block partial (sum wt * sq, sum wt), then a single-block final
@@ -541,6 +977,34 @@ __global__ __launch_bounds__(256) void k_chmean_part(const bf16* __restrict__ x,
     }
 }
 
+__global__ void k_chmean_final(const float* __restrict__ part, long long vps, int c, int nsamp, int parts,
+                               float* __restrict__ mean)
+{
+    GRID_STRIDE(i, (long long)nsamp * c)
+    {
+        const long long n = i / c;
+        const int ch = (int)(i % c);
+        float s = 0.f;
+        for (int p = 0; p < parts; ++p) s += part[(n * parts + p) * c + ch];
+        mean[i] = s / (float)vps;
+    }
+}
+
+__global__ void k_chmean_bcast8(const float* __restrict__ mean, long long vps, int c, bf16* __restrict__ y,
+                                long long total8)
+{
+    const int q8 = c / 8;
+    GRID_STRIDE(i, total8)
+    {
+        const int q = (int)(i % q8);
+        const long long n = i / q8 / vps;
+        float f[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) f[e] = mean[n * c + 8 * q + e];
+        *(u4*)(y + i * 8) = pack8(f);
+    }
+}
+
 __global__ void k_chmean_bcast(const float* __restrict__ part, long long vps, int c, int nsamp, int parts,
                                bf16* __restrict__ y)
 {
@@ -567,16 +1031,47 @@ dim3 grid_for(long long n)
     return dim3((unsigned)b);
 }
 
-int bwd_w_chunks(long long nvox)
+bool brick_ok(const G& g) { return g.d % kTD == 0 && g.h % kTH == 0 && g.w % kTW == 0; }
+
+// Voxel chunks of the weight gradient (partials summed in a fixed order).
+// Brick path: about 256 workgroups (one per CU: the staging takes 128 KB of
+// LDS), whole bricks per chunk.  Generic path: >= 4096 voxels per chunk.
+int bwd_w_chunks(const G& g, int cin, int cout)
 {
-    long long c = (nvox + 4095) / 4096;  // at least 4096 voxels per chunk
+    if (brick_ok(g)) {
+        const long long bricks = g.nvox / (kTD * kTH * kTW);
+        const long long tiles = (long long)(cin / 32) * (cout / 32);
+        long long c = (256 + tiles - 1) / tiles;
+        if (c > bricks) c = bricks;
+        const long long per = (bricks + c - 1) / c;
+        return (int)((bricks + per - 1) / per);
+    }
+    long long c = (g.nvox + 4095) / 4096;
     return (int)(c < 64 ? c : 64);
+}
+
+template <int NB, int SIGN, int ACT>
+int conv_tile_launch(const G& g, const bf16* x, int cin, const bf16* w, const float* bias, int cout, bf16* y,
+                     hipStream_t s)
+{
+    const unsigned bricks = (unsigned)(g.nvox / (kTD * kTH * kTW));
+    const unsigned span = bricks % 8 == 0 ? bricks / 8 : 0;
+    k_conv_tile<NB, SIGN, ACT><<<dim3(bricks, cout / (16 * NB)), 256, 0, s>>>(g, x, cin, w, bias, cout, y, span);
+    return launched();
 }
 
 template <int SIGN, int ACT>
 int conv_dispatch(const G& g, const bf16* x, int cin, const bf16* w, const float* bias, int cout, bf16* y,
                   hipStream_t s)
 {
+    if (brick_ok(g)) {
+        // widest output tile that still leaves >= 512 workgroups (two per CU)
+        const long long bricks = g.nvox / (kTD * kTH * kTW);
+        const int c16 = cout / 16;
+        if (c16 % 6 == 0 && bricks * (c16 / 6) >= 512) return conv_tile_launch<6, SIGN, ACT>(g, x, cin, w, bias, cout, y, s);
+        if (c16 % 4 == 0 && bricks * (c16 / 4) >= 512) return conv_tile_launch<4, SIGN, ACT>(g, x, cin, w, bias, cout, y, s);
+        return conv_tile_launch<2, SIGN, ACT>(g, x, cin, w, bias, cout, y, s);
+    }
     const unsigned mb = (unsigned)((g.nvox + 63) / 64);
     if (cout % 64 == 0)
         k_conv_fwd<4, SIGN, ACT><<<dim3(mb, cout / 64), 256, 0, s>>>(g, x, cin, w, bias, cout, y);
@@ -617,7 +1112,7 @@ int cmnn_conv3d_bwd_weight_workspace(const cmnn_geom* g, int32_t cin, int32_t co
 {
     if (!geom_ok(g) || !chan_ok(cin) || !chan_ok(cout) || !bytes) return CMNN_EINVAL;
     const G gg = make_g(g);
-    const size_t nc = (size_t)bwd_w_chunks(gg.nvox);
+    const size_t nc = (size_t)bwd_w_chunks(gg, cin, cout);
     *bytes = nc * 27 * (size_t)cin * cout * sizeof(float) + (size_t)kColSumBlocks * cout * sizeof(float);
     return CMNN_OK;
 }
@@ -631,23 +1126,39 @@ int cmnn_conv3d_bwd_weight(const cmnn_geom* g, const void* x, int32_t cin, const
     if (cout > 256) return CMNN_EINVAL;
     const G gg = make_g(g);
     hipStream_t s = (hipStream_t)hip_stream;
-    const int nc = bwd_w_chunks(gg.nvox);
-    const long long chunk = (gg.nvox + nc - 1) / nc;
+    const int nc = bwd_w_chunks(gg, cin, cout);
     float* part = (float*)workspace;
-    const unsigned nblk = (unsigned)(nc * 27 * (cout / 32) * (cin / 32));
-    k_conv_bwd_w<<<nblk, 256, 0, s>>>(gg, (const bf16*)x, cin, (const bf16*)dy, cout, chunk, part);
-    if (launched()) return CMNN_EHIP;
     const long long per = 27LL * cin * cout;
-    k_sum_chunks<<<grid_for(per), 256, 0, s>>>(part, per, nc, dw);
+    float* bpart = part + (long long)nc * per;
+    if (brick_ok(gg)) {
+        const long long bricks = gg.nvox / (kTD * kTH * kTW);
+        const int per_chunk = (int)((bricks + nc - 1) / nc);
+        const unsigned nblk = (unsigned)(nc * (cout / 32) * (cin / 32));
+        k_conv_bwd_w_tile<<<nblk, 256, 0, s>>>(gg, (const bf16*)x, cin, (const bf16*)dy, cout, per_chunk, part,
+                                               dbias ? bpart : nullptr);
+        if (launched()) return CMNN_EHIP;
+        k_sum_chunks<<<(unsigned)((per + 63) / 64), 256, 0, s>>>(part, per, nc, dw);
+        if (launched()) return CMNN_EHIP;
+        if (dbias) {
+            k_sum_chunks<<<(unsigned)((cout + 63) / 64), 256, 0, s>>>(bpart, cout, nc, dbias);
+            if (launched()) return CMNN_EHIP;
+        }
+        return CMNN_OK;
+    } else {
+        const long long chunk = (gg.nvox + nc - 1) / nc;
+        const unsigned nblk = (unsigned)(nc * 27 * (cout / 32) * (cin / 32));
+        k_conv_bwd_w<<<nblk, 256, 0, s>>>(gg, (const bf16*)x, cin, (const bf16*)dy, cout, chunk, part);
+    }
+    if (launched()) return CMNN_EHIP;
+    k_sum_chunks<<<(unsigned)((per + 63) / 64), 256, 0, s>>>(part, per, nc, dw);
     if (launched()) return CMNN_EHIP;
     if (dbias) {
-        float* bpart = part + (long long)nc * per;
         long long nb = (gg.nvox + 1023) / 1024;
         if (nb > kColSumBlocks) nb = kColSumBlocks;
         const long long bchunk = (gg.nvox + nb - 1) / nb;
         k_colsum_part<<<(unsigned)nb, 256, 0, s>>>((const bf16*)dy, gg.nvox, cout, bchunk, bpart);
         if (launched()) return CMNN_EHIP;
-        k_sum_chunks<<<1, 256, 0, s>>>(bpart, cout, (int)nb, dbias);
+        k_sum_chunks<<<(unsigned)((cout + 63) / 64), 256, 0, s>>>(bpart, cout, (int)nb, dbias);
         if (launched()) return CMNN_EHIP;
     }
     return CMNN_OK;
@@ -656,6 +1167,11 @@ int cmnn_conv3d_bwd_weight(const cmnn_geom* g, const void* x, int32_t cin, const
 int cmnn_act_bwd(const void* y, const void* dy, void* dpre, size_t n, int32_t act, void* hip_stream)
 {
     if (!y || !dy || !dpre || act < CMNN_ACT_NONE || act > CMNN_ACT_LEAKY) return CMNN_EINVAL;
+    if (n % 8 == 0 && al16(y) && al16(dy) && al16(dpre)) {
+        k_act_bwd8<<<grid_for((long long)n / 8), 256, 0, (hipStream_t)hip_stream>>>(
+            (const u4*)y, (const u4*)dy, (u4*)dpre, (long long)n / 8, act);
+        return launched();
+    }
     k_act_bwd<<<grid_for((long long)n), 256, 0, (hipStream_t)hip_stream>>>((const bf16*)y, (const bf16*)dy,
                                                                          (bf16*)dpre, (long long)n, act);
     return launched();
@@ -665,7 +1181,10 @@ int cmnn_pool2_fwd(const cmnn_geom* g, const void* x, int32_t c, void* y, void* 
 {
     if (!geom_ok(g) || c <= 0 || !x || !y || (g->d | g->h | g->w) & 1) return CMNN_EINVAL;
     const G gg = make_g(g);
-    k_pool2_fwd<<<grid_for(gg.nvox * c / 8), 256, 0, (hipStream_t)hip_stream>>>(gg, (const bf16*)x, c, (bf16*)y);
+    if (c % 8 == 0 && al16(x) && al16(y))
+        k_pool2_fwd8<<<grid_for(gg.nvox * c / 64), 256, 0, (hipStream_t)hip_stream>>>(gg, (const bf16*)x, c, (bf16*)y);
+    else
+        k_pool2_fwd<<<grid_for(gg.nvox * c / 8), 256, 0, (hipStream_t)hip_stream>>>(gg, (const bf16*)x, c, (bf16*)y);
     return launched();
 }
 
@@ -673,7 +1192,10 @@ int cmnn_pool2_bwd(const cmnn_geom* g, const void* dy, int32_t c, void* dx, void
 {
     if (!geom_ok(g) || c <= 0 || !dy || !dx || (g->d | g->h | g->w) & 1) return CMNN_EINVAL;
     const G gg = make_g(g);
-    k_pool2_bwd<<<grid_for(gg.nvox * c), 256, 0, (hipStream_t)hip_stream>>>(gg, (const bf16*)dy, c, (bf16*)dx);
+    if (c % 8 == 0 && al16(dy) && al16(dx))
+        k_pool2_bwd8<<<grid_for(gg.nvox * c / 8), 256, 0, (hipStream_t)hip_stream>>>(gg, (const bf16*)dy, c, (bf16*)dx);
+    else
+        k_pool2_bwd<<<grid_for(gg.nvox * c), 256, 0, (hipStream_t)hip_stream>>>(gg, (const bf16*)dy, c, (bf16*)dx);
     return launched();
 }
 
@@ -681,7 +1203,10 @@ int cmnn_up2_fwd(const cmnn_geom* g, const void* x, int32_t c, void* y, void* hi
 {
     if (!geom_ok(g) || c <= 0 || !x || !y) return CMNN_EINVAL;
     const G gg = make_g(g);
-    k_up2_fwd<<<grid_for(gg.nvox * c * 8), 256, 0, (hipStream_t)hip_stream>>>(gg, (const bf16*)x, c, (bf16*)y);
+    if (c % 8 == 0 && al16(x) && al16(y))
+        k_up2_fwd8<<<grid_for(gg.nvox * c), 256, 0, (hipStream_t)hip_stream>>>(gg, (const bf16*)x, c, (bf16*)y);
+    else
+        k_up2_fwd<<<grid_for(gg.nvox * c * 8), 256, 0, (hipStream_t)hip_stream>>>(gg, (const bf16*)x, c, (bf16*)y);
     return launched();
 }
 
@@ -689,38 +1214,53 @@ int cmnn_up2_bwd(const cmnn_geom* g, const void* dy, int32_t c, void* dx, void* 
 {
     if (!geom_ok(g) || c <= 0 || !dy || !dx) return CMNN_EINVAL;
     const G gg = make_g(g);
-    k_up2_bwd<<<grid_for(gg.nvox * c), 256, 0, (hipStream_t)hip_stream>>>(gg, (const bf16*)dy, c, (bf16*)dx);
+    if (c % 8 == 0 && al16(dy) && al16(dx))
+        k_up2_bwd8<<<grid_for(gg.nvox * c / 8), 256, 0, (hipStream_t)hip_stream>>>(gg, (const bf16*)dy, c, (bf16*)dx);
+    else
+        k_up2_bwd<<<grid_for(gg.nvox * c), 256, 0, (hipStream_t)hip_stream>>>(gg, (const bf16*)dy, c, (bf16*)dx);
     return launched();
 }
 
 int cmnn_concat_fwd(size_t nvox, const void* a, int32_t ca, const void* b, int32_t cb, void* y, void* hip_stream)
 {
     if (!a || !b || !y || ca <= 0 || cb <= 0) return CMNN_EINVAL;
-    k_concat_fwd<<<grid_for((long long)nvox * (ca + cb)), 256, 0, (hipStream_t)hip_stream>>>(
-        (long long)nvox, (const bf16*)a, ca, (const bf16*)b, cb, (bf16*)y);
+    if (ca % 8 == 0 && cb % 8 == 0 && al16(a) && al16(b) && al16(y))
+        k_concat_fwd8<<<grid_for((long long)nvox * (ca + cb) / 8), 256, 0, (hipStream_t)hip_stream>>>(
+            (long long)nvox, (const bf16*)a, ca, (const bf16*)b, cb, (bf16*)y);
+    else
+        k_concat_fwd<<<grid_for((long long)nvox * (ca + cb)), 256, 0, (hipStream_t)hip_stream>>>(
+            (long long)nvox, (const bf16*)a, ca, (const bf16*)b, cb, (bf16*)y);
     return launched();
 }
 
 int cmnn_concat_bwd(size_t nvox, const void* dy, int32_t ca, int32_t cb, void* da, void* db, void* hip_stream)
 {
     if (!dy || ca <= 0 || cb <= 0) return CMNN_EINVAL;
-    k_concat_bwd<<<grid_for((long long)nvox * (ca + cb)), 256, 0, (hipStream_t)hip_stream>>>(
-        (long long)nvox, (const bf16*)dy, ca, cb, (bf16*)da, (bf16*)db);
+    if (ca % 8 == 0 && cb % 8 == 0 && al16(dy) && al16(da) && al16(db))
+        k_concat_bwd8<<<grid_for((long long)nvox * (ca + cb) / 8), 256, 0, (hipStream_t)hip_stream>>>(
+            (long long)nvox, (const bf16*)dy, ca, cb, (bf16*)da, (bf16*)db);
+    else
+        k_concat_bwd<<<grid_for((long long)nvox * (ca + cb)), 256, 0, (hipStream_t)hip_stream>>>(
+            (long long)nvox, (const bf16*)dy, ca, cb, (bf16*)da, (bf16*)db);
     return launched();
 }
 
 int cmnn_add(size_t n, const void* a, const void* b, void* y, void* hip_stream)
 {
     if (!a || !b || !y) return CMNN_EINVAL;
-    k_add<<<grid_for((long long)n), 256, 0, (hipStream_t)hip_stream>>>((long long)n, (const bf16*)a, (const bf16*)b,
-                                                                     (bf16*)y);
+    if (n % 8 == 0 && al16(a) && al16(b) && al16(y))
+        k_add8<<<grid_for((long long)n / 8), 256, 0, (hipStream_t)hip_stream>>>((long long)n / 8, (const u4*)a,
+                                                                               (const u4*)b, (u4*)y);
+    else
+        k_add<<<grid_for((long long)n), 256, 0, (hipStream_t)hip_stream>>>((long long)n, (const bf16*)a,
+                                                                         (const bf16*)b, (bf16*)y);
     return launched();
 }
 
 int cmnn_channel_mean_workspace(const cmnn_geom* g, int32_t c, size_t* bytes)
 {
     if (!geom_ok(g) || c <= 0 || c > 256 || !bytes) return CMNN_EINVAL;
-    *bytes = (size_t)g->n * kMeanParts * c * sizeof(float);
+    *bytes = (size_t)g->n * (kMeanParts + 1) * c * sizeof(float);
     return CMNN_OK;
 }
 
@@ -735,6 +1275,14 @@ int cmnn_channel_mean(const cmnn_geom* g, const void* x, int32_t c, void* y, voi
     const long long vps = (long long)g->d * g->h * g->w;
     k_chmean_part<<<(unsigned)(g->n * kMeanParts), 256, 0, s>>>((const bf16*)x, vps, c, kMeanParts, (float*)workspace);
     if (launched()) return CMNN_EHIP;
+    if (c % 8 == 0 && al16(y)) {
+        float* mean = (float*)workspace + (size_t)g->n * kMeanParts * c;
+        k_chmean_final<<<grid_for((long long)g->n * c), 256, 0, s>>>((const float*)workspace, vps, c, g->n,
+                                                                     kMeanParts, mean);
+        if (launched()) return CMNN_EHIP;
+        k_chmean_bcast8<<<grid_for(gg.nvox * c / 8), 256, 0, s>>>(mean, vps, c, (bf16*)y, gg.nvox * c / 8);
+        return launched();
+    }
     k_chmean_bcast<<<grid_for(gg.nvox * c), 256, 0, s>>>((const float*)workspace, vps, c, g->n, kMeanParts, (bf16*)y);
     return launched();
 }

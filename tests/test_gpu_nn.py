@@ -52,7 +52,12 @@ def close_bf16(got, ref, mag):
     return float((err / bound).max())
 
 
-SHAPES = [((2, 3, 5, 7), 32, 64, (1, 0, 1)), ((1, 4, 6, 8), 64, 32, (0, 1, 0)), ((1, 2, 4, 6), 32, 96, (1, 1, 1))]
+# the first three take the generic kernel (extents not multiples of the 4 x 4 x 16 brick),
+# the rest the brick-tiled one: several bricks with periodic, zero and mixed padding, a single
+# brick that wraps onto itself, and every output-tile width (16 * NB for NB = 2, 4, 6)
+SHAPES = [((2, 3, 5, 7), 32, 64, (1, 0, 1)), ((1, 4, 6, 8), 64, 32, (0, 1, 0)), ((1, 2, 4, 6), 32, 96, (1, 1, 1)),
+          ((2, 4, 8, 32), 32, 64, (1, 0, 1)), ((1, 8, 4, 16), 96, 32, (0, 1, 0)), ((1, 4, 4, 16), 64, 96, (1, 1, 1)),
+          ((2, 4, 4, 16), 32, 160, (1, 0, 1)), ((1, 4, 8, 16), 192, 64, (0, 0, 0))]
 
 
 @pytest.mark.parametrize("dims,cin,cout,per", SHAPES)
@@ -106,33 +111,59 @@ def test_conv_backward(torch, nn, dims, cin, cout, per):
     assert torch.equal(dw, dw2)  # deterministic
 
 
-def test_conv_large_voxel_count(torch, nn):
-    """A full warm-start level (4 x 32 x 32 x 64 voxels) at the widest level-0
-    layer, checked on sampled outputs and through the fixed-order weight
-    gradient on a second, smaller case."""
-    dims, cin, cout = (4, 32, 32, 64), 96, 32
-    log(f"conv fwd sampled {dims} {cin}->{cout}")
-    g = nn.geom(*dims)
-    x, xr = bf16_tensor(torch, randn(dims + (cin,), 7))
+LARGE = [("fwd", (4, 32, 32, 64), 96, 32, (1, 0, 1)),    # brick kernel, 16-channel-pair tiles (NB = 2)
+         ("fwd", (16, 16, 16, 32), 64, 96, (1, 0, 1)),   # 512 bricks: 96-wide tiles (NB = 6)
+         ("fwd", (16, 16, 16, 32), 32, 64, (0, 1, 1)),   # 64-wide tiles (NB = 4)
+         ("bwd", (16, 16, 16, 32), 96, 64, (1, 0, 1)),   # data gradient with 96 outputs (NB = 6)
+         ("bwd", (16, 16, 16, 32), 64, 32, (1, 1, 0))]   # data gradient with 64 outputs (NB = 4)
+
+
+@pytest.mark.parametrize("kind,dims,cin,cout,per", LARGE)
+def test_conv_large_sampled(torch, nn, kind, dims, cin, cout, per):
+    """Warm-start-sized levels in the launch configurations training uses,
+    checked on 64 sampled output voxels computed directly from the definition
+    (forward: sum over taps of w[t] x[v + off]; data gradient: sum over taps of
+    w[t]^T dy[v - off], zero padding where the shifted voxel leaves a
+    non-periodic axis)."""
+    log(f"conv {kind} sampled {dims} layer {cin}->{cout} periodic={per}")
+    g = nn.geom(*dims, periodic=per)
+    cx, cy = (cin, cout) if kind == "fwd" else (cout, cin)  # input / output channels of the launch
+    x, xr = bf16_tensor(torch, randn(dims + (cx,), 7))
     w, wr = bf16_tensor(torch, randn((27, cout, cin), 8, 0.05))
-    y = torch.empty(dims + (cout,), dtype=torch.bfloat16, device="cuda:0")
-    nn.conv_fwd(g, x, cin, w, None, cout, nn.ACT_NONE, y)
+    y = torch.empty(dims + (cy,), dtype=torch.bfloat16, device="cuda:0")
+    if kind == "fwd":
+        nn.conv_fwd(g, x, cin, w, None, cout, nn.ACT_NONE, y)
+        sign, wmat = 1, wr  # y = w[t] @ x
+    else:
+        wt = torch.empty((27, cin, cout), dtype=torch.bfloat16, device="cuda:0")
+        wt.copy_(w.transpose(1, 2))
+        nn.conv_bwd_data(g, x, cout, wt, cin, y)
+        sign, wmat = -1, wr.transpose(0, 2, 1)  # dx = w[t]^T @ dy
     yg = y.float().cpu().numpy()
     gen = W.generator(9)
     for _ in range(64):
-        n, d, h, ww = (int(gen.integers(s)) for s in dims)
-        acc = np.zeros(cout)
-        for t, (dz, dyy, dx) in enumerate(C.taps()):
-            hh = h + dyy
-            if hh < 0 or hh >= dims[2]:
-                continue
-            acc += wr[t] @ xr[n, (d + dz) % dims[1], hh, (ww + dx) % dims[3]]
-        assert np.all(np.abs(yg[n, d, h, ww] - acc) <= np.abs(acc) * 2.0 ** -8 + 1e-3)
+        v = [int(gen.integers(s_)) for s_ in dims]
+        acc = np.zeros(cy)
+        for t, off in enumerate(C.taps()):
+            src, ok = [v[0]], True
+            for a in range(3):
+                q = v[a + 1] + sign * off[a]
+                if not 0 <= q < dims[a + 1]:
+                    if not per[a]:
+                        ok = False
+                        break
+                    q %= dims[a + 1]
+                src.append(q)
+            if ok:
+                acc += wmat[t] @ xr[tuple(src)]
+        assert np.all(np.abs(yg[tuple(v)] - acc) <= np.abs(acc) * 2.0 ** -8 + 1e-3), (v, kind)
 
 
-def test_elementwise_ops(torch, nn):
-    log("pool / upsample / concat / add / act_bwd")
-    dims, c = (2, 4, 6, 8), 32
+@pytest.mark.parametrize("c,ca,cb,nl", [(32, 32, 64, 1000), (12, 12, 20, 1001)])
+def test_elementwise_ops(torch, nn, c, ca, cb, nl):
+    """Channel counts that are multiples of 8 take the 16-byte kernels, the others the scalar ones."""
+    log(f"pool / upsample / concat / add / act_bwd c={c} concat {ca}+{cb} n={nl}")
+    dims = (2, 4, 6, 8)
     g = nn.geom(*dims)
     gc = nn.geom(2, 2, 3, 4)
     x, xr = bf16_tensor(torch, randn(dims + (c,), 10))
@@ -149,28 +180,32 @@ def test_elementwise_ops(torch, nn):
     du = torch.empty((2, 2, 3, 4, c), dtype=torch.bfloat16, device="cuda:0")
     nn.up2_bwd(gc, x, c, du)
     assert close_bf16(du.float().cpu().numpy(), C.up2_grad(xr), C.up2_grad(np.abs(xr))) <= 1.0
-    a, ar = bf16_tensor(torch, randn((30, 32), 12))
-    b, br = bf16_tensor(torch, randn((30, 64), 13))
-    cat = torch.empty((30, 96), dtype=torch.bfloat16, device="cuda:0")
-    nn.concat_fwd(30, a, 32, b, 64, cat)
+    a, ar = bf16_tensor(torch, randn((30, ca), 12))
+    b, br = bf16_tensor(torch, randn((30, cb), 13))
+    cat = torch.empty((30, ca + cb), dtype=torch.bfloat16, device="cuda:0")
+    nn.concat_fwd(30, a, ca, b, cb, cat)
     assert np.array_equal(cat.float().cpu().numpy(), np.concatenate([ar, br], 1))
     da = torch.empty_like(a)
     db = torch.empty_like(b)
-    nn.concat_bwd(30, cat, 32, 64, da, db)
+    nn.concat_bwd(30, cat, ca, cb, da, db)
     assert torch.equal(da, a) and torch.equal(db, b)
     s = torch.empty_like(a)
     nn.add(a, a, s)
     assert torch.equal(s.float(), 2 * a.float())
-    yl, ylr = bf16_tensor(torch, randn((1000,), 14))
-    gl, glr = bf16_tensor(torch, randn((1000,), 15))
+    yl, ylr = bf16_tensor(torch, randn((nl,), 14))
+    gl, glr = bf16_tensor(torch, randn((nl,), 15))
+    sl = torch.empty_like(yl)
+    nn.add(yl, gl, sl)
+    assert close_bf16(sl.float().cpu().numpy(), ylr + glr, np.abs(ylr) + np.abs(glr)) <= 1.0
     out = torch.empty_like(yl)
     nn.act_bwd(yl, gl, out)
     assert close_bf16(out.float().cpu().numpy(), C.leaky_grad_from_output(ylr, glr), np.abs(glr)) <= 1.0
 
 
-def test_channel_mean(torch, nn):
-    log("channel mean broadcast")
-    dims, c = (3, 4, 6, 10), 64
+@pytest.mark.parametrize("c", [64, 12])
+def test_channel_mean(torch, nn, c):
+    log(f"channel mean broadcast c={c}")
+    dims = (3, 4, 6, 10)
     g = nn.geom(*dims)
     x, xr = bf16_tensor(torch, randn(dims + (c,), 30))
     y = torch.empty_like(x)
