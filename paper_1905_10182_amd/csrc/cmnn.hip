@@ -310,20 +310,26 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(G g, const bf16* __restrict_
 // brick-tiled weight gradient (extents multiples of the 4 x 4 x 16 brick)
 //
 // Workgroup (chunk of bricks, 32 output channels, 32 input channels), all 27
-// taps.  Per brick, dy and the halo of x are staged in LDS channel-major (the
-// MFMA K axis is the voxel axis, so a fragment is 8 consecutive voxels of one
-// channel): dy as [co][256 voxels], x as three copies [dx][ci][36 halo rows x
-// 16 voxels], copy dx holding x positions x0 + dx .. x0 + dx + 15, so that every
-// tap's fragment is an aligned 16-byte LDS read.  Each thread stages 8 x 8
-// (voxel x channel) blocks: eight 16-byte global loads, a register transpose,
-// eight 16-byte LDS stores.  Row strides are padded by 16 bytes so the 16 rows
-// of a fragment read fall on distinct bank groups.  Wave w accumulates the
-// 2 x 2 blocks of 16 x 16 for taps w, w + 4, ... (7 or 6 taps): the dy
-// fragments of a K step are read once and serve all of them.
+// taps, 8 waves.  The MFMA K axis is the voxel axis, so a fragment is 8
+// consecutive voxels of one channel: per brick, dy ([co][256 voxels]) and the
+// 6 x 6 x 18 halo of x ([ci][36 halo rows][24], positions x0 - 1 .. x0 + 16)
+// are staged in LDS channel-major.  A staging task is an 8 x 8 (voxel x
+// channel) block: eight 16-byte global loads, a register transpose, eight
+// 16-byte LDS stores.  The next brick's loads are issued before the current
+// brick's MFMAs so that their latency hides behind the compute.  A tap's x
+// fragment starts dx + 1 elements into an aligned 16-byte LDS read: for
+// dx = 0 and +1 the eight elements are realigned from that read and the next
+// dword.  Row strides are padded so that the 16 rows of a fragment read fall
+// on distinct bank groups.  Wave w accumulates the 2 x 2 blocks of 16 x 16
+// for taps w, w + 8, w + 16, w + 24; the dy fragments of a K step are read
+// once and serve all of them.
 
 constexpr int kDyStride = 256 + 8;        // bf16 per co row of staged dy
-constexpr int kXStride = 36 * 16 + 8;     // bf16 per ci row of one staged x copy
-constexpr int kXCopy = 32 * kXStride;     // bf16 per copy
+constexpr int kXRow = 24;                 // bf16 per staged halo row (18 used)
+constexpr int kXStride = 36 * kXRow + 8;  // bf16 per ci row of staged x
+constexpr int kXTasks = 36 * 3 * 4;       // (halo row, octet, channel group) blocks of x
+constexpr int kDyTasks = 32 * 4;          // (x octet, channel group) blocks of dy
+constexpr int kBwThreads = 512;
 
 __device__ __forceinline__ void transpose8x8(const u4 (&in)[8], u4 (&out)[8])
 {
@@ -341,17 +347,14 @@ __device__ __forceinline__ void transpose8x8(const u4 (&in)[8], u4 (&out)[8])
     }
 }
 
-__global__ __launch_bounds__(256) void k_conv_bwd_w_tile(G g, const bf16* __restrict__ x, int cin,
-                                                         const bf16* __restrict__ dy, int cout, int bricks_per_chunk,
-                                                         float* __restrict__ part, float* __restrict__ bpart)
+__global__ __launch_bounds__(kBwThreads) void k_conv_bwd_w_tile(G g, const bf16* __restrict__ x, int cin,
+                                                                const bf16* __restrict__ dy, int cout,
+                                                                int bricks_per_chunk, float* __restrict__ part,
+                                                                float* __restrict__ bpart)
 {
     __shared__ __attribute__((aligned(16))) bf16 sdy[32 * kDyStride];
-    __shared__ __attribute__((aligned(16))) bf16 sxc[3 * kXCopy];
-    __shared__ float sbias[256];
-    // bias gradient (column sums of dy) from the staged dy, by the ci-tile-0 workgroups:
-    // thread (co = tid / 8, segment tid % 8) sums 32 voxels of each brick
-    const bool do_bias = bpart != nullptr && blockIdx.x % (cin / 32) == 0;
-    float bsum = 0.f;
+    __shared__ __attribute__((aligned(16))) bf16 sx[32 * kXStride];
+    __shared__ float sbias[kBwThreads];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ct = cout / 32, it = cin / 32;
     int bid = blockIdx.x;
@@ -359,18 +362,20 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w_tile(G g, const bf16* __rest
     bid /= it;
     const int cot = bid % ct;
     const int ch = bid / ct;
+    // bias gradient (column sums of dy) from the staged dy, by the ci-tile-0 workgroups:
+    // thread (co = tid / 16, segment tid % 16) sums 16 voxels of each brick
+    const bool do_bias = bpart != nullptr && cit == 0;
+    float bsum = 0.f;
     const int nbw = g.w / kTW, nbh = g.h / kTH, nbd = g.d / kTD;
     const long long nbricks = (long long)g.n * nbd * nbh * nbw;
-    f4 acc[7][2][2];
-#pragma unroll
-    for (int k = 0; k < 7; ++k)
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b) acc[k][a][b] = f4{0.f, 0.f, 0.f, 0.f};
     const long long b0 = (long long)ch * bricks_per_chunk;
     const long long b1 = b0 + bricks_per_chunk < nbricks ? b0 + bricks_per_chunk : nbricks;
-    for (long long br = b0; br < b1; ++br) {
+    // staging roles: x block tid (tid < 432), dy block tid - 384 (tid >= 384)
+    const bool has_x = tid < kXTasks, has_dy = tid >= kBwThreads - kDyTasks;
+    const int xcg = tid & 3, xoct = (tid >> 2) % 3, xhr = tid / 12;
+    const int dyt = tid - (kBwThreads - kDyTasks), dcg = dyt & 3, drow = (dyt >> 2) >> 1, dxo = ((dyt >> 2) & 1) * 8;
+    u4 xin[8], dyin[8];
+    auto load = [&](long long br) {
         long long r = br;
         const int x0 = (int)(r % nbw) * kTW;
         r /= nbw;
@@ -378,48 +383,60 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w_tile(G g, const bf16* __rest
         r /= nbh;
         const int d0 = (int)(r % nbd) * kTD;
         const long long n = r / nbd;
-        __syncthreads();
-        // dy: 32 x-octets (16 rows x 2) x 4 channel groups = 128 blocks
-        if (tid < 128) {
-            const int oc = tid >> 2, cg = tid & 3;
-            const int row = oc >> 1, xo = (oc & 1) * 8;
-            const long long v = ((n * g.d + d0 + (row >> 2)) * g.h + h0 + (row & 3)) * g.w + x0 + xo;
-            const bf16* src = dy + v * cout + cot * 32 + cg * 8;
-            u4 in[8], out[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) in[i] = *(const u4*)(src + (long long)i * cout);
-            transpose8x8(in, out);
-#pragma unroll
-            for (int c = 0; c < 8; ++c) *(u4*)&sdy[(cg * 8 + c) * kDyStride + row * 16 + xo] = out[c];
-        }
-        // x: 3 copies x 36 halo rows x 2 octets x 4 channel groups = 864 blocks
-        for (int p = tid; p < 864; p += 256) {
-            const int cg = p & 3, oc = (p >> 2) % 72, cx = p / 288;
-            const int hr = oc >> 1, xo = (oc & 1) * 8;
-            const int hd = hr / 6, hh = hr % 6;
+        if (has_x) {
             int sd = 0, sh = 0;
-            const bool rok = shift_axis(d0, hd - 1, g.d, g.per[0], sd) && shift_axis(h0, hh - 1, g.h, g.per[1], sh);
+            const bool rok = shift_axis(d0, xhr / 6 - 1, g.d, g.per[0], sd) &&
+                             shift_axis(h0, xhr % 6 - 1, g.h, g.per[1], sh);
             const long long rowbase = ((n * g.d + sd) * g.h + sh) * g.w;
-            u4 in[8], out[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
+                const int pos = xoct * 8 + i;  // halo position: x = x0 - 1 + pos
                 int sw = 0;
-                in[i] = u4{0u, 0u, 0u, 0u};
-                if (rok && shift_axis(x0, cx - 1 + xo + i, g.w, g.per[2], sw))
-                    in[i] = *(const u4*)(x + (rowbase + sw) * cin + cit * 32 + cg * 8);
+                xin[i] = u4{0u, 0u, 0u, 0u};
+                if (rok && pos < kTW + 2 && shift_axis(x0, pos - 1, g.w, g.per[2], sw))
+                    xin[i] = *(const u4*)(x + (rowbase + sw) * cin + cit * 32 + xcg * 8);
             }
-            transpose8x8(in, out);
+        }
+        if (has_dy) {
+            const long long v = ((n * g.d + d0 + (drow >> 2)) * g.h + h0 + (drow & 3)) * g.w + x0 + dxo;
+            const bf16* src = dy + v * cout + cot * 32 + dcg * 8;
 #pragma unroll
-            for (int c = 0; c < 8; ++c) *(u4*)&sxc[cx * kXCopy + (cg * 8 + c) * kXStride + hr * 16 + xo] = out[c];
+            for (int i = 0; i < 8; ++i) dyin[i] = *(const u4*)(src + (long long)i * cout);
         }
+    };
+    auto store = [&]() {
+        u4 out[8];
+        if (has_x) {
+            transpose8x8(xin, out);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) *(u4*)&sx[(xcg * 8 + c) * kXStride + xhr * kXRow + xoct * 8] = out[c];
+        }
+        if (has_dy) {
+            transpose8x8(dyin, out);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) *(u4*)&sdy[(dcg * 8 + c) * kDyStride + drow * 16 + dxo] = out[c];
+        }
+    };
+    f4 acc[4][2][2];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) acc[k][a][b] = f4{0.f, 0.f, 0.f, 0.f};
+    if (b0 < b1) load(b0);
+    const int j = lane >> 4, l16 = lane & 15;
+    for (long long br = b0; br < b1; ++br) {
         __syncthreads();
+        store();
+        __syncthreads();
+        if (br + 1 < b1) load(br + 1);
         if (do_bias) {
-            const bf16* q = &sdy[(tid >> 3) * kDyStride + (tid & 7) * 32];
-#pragma unroll 8
-            for (int k = 0; k < 32; ++k) bsum += (float)q[k];
+            const bf16* q = &sdy[(tid >> 4) * kDyStride + (tid & 15) * 16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) bsum += (float)q[k];
         }
-        // 8 K steps of 32 voxels (two brick rows); lane group j = lane / 16 takes voxels 8j..8j+7
-        const int j = lane >> 4, l16 = lane & 15;
+        // 8 K steps of 32 voxels (two brick rows); lane group j takes voxels 8j..8j+7
 #pragma unroll 2
         for (int ks = 0; ks < 8; ++ks) {
             const int row = ks * 2 + (j >> 1), xo = (j & 1) * 8;
@@ -428,15 +445,25 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w_tile(G g, const bf16* __rest
             for (int cb = 0; cb < 2; ++cb) a[cb] = *(const bf16x8*)&sdy[(cb * 16 + l16) * kDyStride + row * 16 + xo];
             const int dd = row >> 2, hh = row & 3;
 #pragma unroll
-            for (int k = 0; k < 7; ++k) {
-                const int t = wave + 4 * k;
+            for (int k = 0; k < 4; ++k) {
+                const int t = wave + 8 * k;
                 if (t < 27) {
                     const int dz = t / 9 - 1, dyy = (t / 3) % 3 - 1, cx = t % 3;
                     const int hr = (dd + 1 + dz) * 6 + hh + 1 + dyy;
 #pragma unroll
                     for (int ib = 0; ib < 2; ++ib) {
-                        const bf16x8 b =
-                            *(const bf16x8*)&sxc[cx * kXCopy + (ib * 16 + l16) * kXStride + hr * 16 + xo];
+                        const bf16* q = &sx[(ib * 16 + l16) * kXStride + hr * kXRow + xo];
+                        const u4 lo = *(const u4*)q;
+                        u4 f = lo;
+                        if (cx != 0) {
+                            const unsigned hi = *(const unsigned*)(q + 8);
+                            if (cx == 1)
+                                f = u4{__builtin_amdgcn_alignbyte(lo[1], lo[0], 2), __builtin_amdgcn_alignbyte(lo[2], lo[1], 2),
+                                       __builtin_amdgcn_alignbyte(lo[3], lo[2], 2), __builtin_amdgcn_alignbyte(hi, lo[3], 2)};
+                            else
+                                f = u4{lo[1], lo[2], lo[3], hi};
+                        }
+                        const bf16x8 b = __builtin_bit_cast(bf16x8, f);
 #pragma unroll
                         for (int cb = 0; cb < 2; ++cb)
                             acc[k][cb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[cb], b, acc[k][cb][ib], 0, 0, 0);
@@ -451,14 +478,14 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w_tile(G g, const bf16* __rest
         if (tid < 32) {
             float b = 0.f;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) b += sbias[tid * 8 + k];
+            for (int k = 0; k < 16; ++k) b += sbias[tid * 16 + k];
             bpart[(long long)ch * cout + cot * 32 + tid] = b;
         }
     }
     // D[co][ci]: row (lane / 16) * 4 + i, column lane % 16
 #pragma unroll
-    for (int k = 0; k < 7; ++k) {
-        const int t = wave + 4 * k;
+    for (int k = 0; k < 4; ++k) {
+        const int t = wave + 8 * k;
         if (t >= 27) continue;
         float* p = part + (((long long)ch * 27 + t) * cout) * cin;
 #pragma unroll
@@ -1034,8 +1061,8 @@ dim3 grid_for(long long n)
 bool brick_ok(const G& g) { return g.d % kTD == 0 && g.h % kTH == 0 && g.w % kTW == 0; }
 
 // Voxel chunks of the weight gradient (partials summed in a fixed order).
-// Brick path: about 256 workgroups (one per CU: the staging takes 128 KB of
-// LDS), whole bricks per chunk.  Generic path: >= 4096 voxels per chunk.
+// Brick path: about 256 workgroups of 8 waves (one per CU), whole bricks
+// per chunk.  Generic path: >= 4096 voxels per chunk.
 int bwd_w_chunks(const G& g, int cin, int cout)
 {
     if (brick_ok(g)) {
@@ -1134,7 +1161,7 @@ int cmnn_conv3d_bwd_weight(const cmnn_geom* g, const void* x, int32_t cin, const
         const long long bricks = gg.nvox / (kTD * kTH * kTW);
         const int per_chunk = (int)((bricks + nc - 1) / nc);
         const unsigned nblk = (unsigned)(nc * (cout / 32) * (cin / 32));
-        k_conv_bwd_w_tile<<<nblk, 256, 0, s>>>(gg, (const bf16*)x, cin, (const bf16*)dy, cout, per_chunk, part,
+        k_conv_bwd_w_tile<<<nblk, kBwThreads, 0, s>>>(gg, (const bf16*)x, cin, (const bf16*)dy, cout, per_chunk, part,
                                                dbias ? bpart : nullptr);
         if (launched()) return CMNN_EHIP;
         k_sum_chunks<<<(unsigned)((per + 63) / 64), 256, 0, s>>>(part, per, nc, dw);
