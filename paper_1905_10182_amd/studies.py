@@ -2,6 +2,7 @@
 
     python -m paper_1905_10182_amd.studies precision [--n 512] [--steps 2000] [--every 100]
     python -m paper_1905_10182_amd.studies kolmogorov [--n 384] [--steps 5000] [--every 500]
+    python -m paper_1905_10182_amd.studies four-rolls [--storage fp64]
 
 ``precision``: the 3D Taylor-Green vortex (u0 = 0.05, Re = 1600) advanced in
 lockstep with FP64, FP32, FP16 and BF16 population storage (16-bit both with
@@ -13,7 +14,14 @@ FP32 runs.
 ``kolmogorov``: Kolmogorov flow (F_x = F0 sin(2 pi 4 y / N), tau = 0.5005)
 with FP64, FP32 and FP16 (both roundings) storage, same report.
 
-Both print one JSON object per checkpoint.  Error norms are taken with torch
+``four-rolls``: convergence of the two-dimensional four-rolls mill (Re = 100,
+one node in z, per-node force field) to its analytic steady state for
+N = 8..256 at u0 = 1e-3 and 1e-2: relative L2 velocity error per grid and the
+observed order between successive grids (the paper prints 1.998 for
+u0 = 1e-3).  Each grid starts from the analytic field and runs for three
+relaxation times of the box, 3 / (nu psi^2).
+
+All print one JSON object per checkpoint or grid.  Error norms are taken with torch
 on device-resident moments (diagnostics only; the solver runs in libcmlbm).
 """
 import argparse
@@ -90,9 +98,42 @@ def kolmogorov_study(n=384, steps=5000, every=500, storages=("fp64", "fp32", "fp
     return lockstep(lats, steps, every, f"kolmogorov_{n}")
 
 
+def four_rolls_study(ns=(8, 16, 32, 64, 128, 256), u0s=(1e-3, 1e-2), relax=3.0, storage="fp64", out=sys.stdout):
+    import math
+
+    import numpy as np
+    import torch
+
+    rows = []
+    for u0 in u0s:
+        prev = None
+        for n in ns:
+            wl = workloads.four_rolls_mill(n, u0=u0)
+            lat = Lattice(n, n, 1, tau=wl["tau"], storage=storage, device="cuda:0")
+            lat.set_force("field", field=wl["force"])
+            lat.init(np.ones(wl["shape"]), wl["u_exact"])
+            steps = int(relax * wl["t_relax"])
+            t0 = time.perf_counter()
+            lat.step(steps)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            u = lat.moments()[1].double().cpu().numpy()
+            ex = wl["u_exact"][:2]
+            err = float(np.linalg.norm(u[:2] - ex) / np.linalg.norm(ex))
+            row = {"study": "four_rolls_mill", "storage": storage, "u0": u0, "n": n, "tau": wl["tau"],
+                   "steps": steps, "error": err, "order": None if prev is None else math.log2(prev / err),
+                   "seconds": round(dt, 2)}
+            print(json.dumps(row), file=out, flush=True)
+            rows.append(row)
+            prev = err
+            del lat
+    return rows
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["precision", "kolmogorov"])
+    ap.add_argument("study", choices=["precision", "kolmogorov", "four-rolls"])
+    ap.add_argument("--storage", default="fp64")
     ap.add_argument("--n", type=int)
     ap.add_argument("--steps", type=int)
     ap.add_argument("--every", type=int)
@@ -100,8 +141,10 @@ def main(argv=None):
     kw = {k: v for k, v in (("n", a.n), ("steps", a.steps), ("every", a.every)) if v is not None}
     if a.study == "precision":
         precision_study(**kw)
-    else:
+    elif a.study == "kolmogorov":
         kolmogorov_study(**kw)
+    else:
+        four_rolls_study(storage=a.storage)
 
 
 if __name__ == "__main__":

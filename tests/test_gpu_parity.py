@@ -178,6 +178,46 @@ def test_fp64_kolmogorov_profile_force(torch):
     assert err < 1e-12
 
 
+def test_fp64_four_rolls_mill_nz1_field_force(torch):
+    """Four-rolls mill 16 x 16 x 1 (one node in z, periodic), per-node force
+    field, 2000 steps from the analytic field."""
+    log("fp64 four-rolls mill 16x16x1, 2000 steps")
+    wl = W.four_rolls_mill(16)
+    ref = O.Lattice(16, 16, 1, tau=wl["tau"], force=wl["force"], extended=True)
+    ref.init(np.ones(wl["shape"]), wl["u_exact"])
+    ref.step(2000)
+    lat = Lat(nx=16, ny=16, nz=1, tau=wl["tau"], storage="fp64")
+    lat.set_force("field", field=wl["force"])
+    lat.init(np.ones(wl["shape"]), wl["u_exact"])
+    lat.step(2000)
+    _, u = lat.moments()
+    _, ur = ref.moments()
+    err = rel(u.cpu().numpy(), ur)
+    log(f"  velocity {err:.3e}")
+    assert err < 1e-12
+
+
+def test_four_rolls_mill_convergence_fp64(torch):
+    """Four-rolls mill at Re = 100, u0 = 1e-3 on the GPU (FP64): relative L2
+    error of the steady velocity against the analytic field for N = 8..64,
+    each grid run for two relaxation times from the analytic field.  The
+    observed order between successive grids must be 2 within 0.1 (the paper
+    prints 1.998)."""
+    errs = []
+    for n in (8, 16, 32, 64):
+        wl = W.four_rolls_mill(n)
+        lat = Lat(nx=n, ny=n, nz=1, tau=wl["tau"], storage="fp64")
+        lat.set_force("field", field=wl["force"])
+        lat.init(np.ones(wl["shape"]), wl["u_exact"])
+        lat.step(int(2 * wl["t_relax"]))
+        u = lat.moments()[1].cpu().numpy()
+        errs.append(rel(u[:2], wl["u_exact"][:2]))
+        log(f"  N={n}: error {errs[-1]:.4e}")
+    rates = [math.log2(errs[k] / errs[k + 1]) for k in range(3)]
+    log(f"  observed orders {rates}")
+    assert all(1.9 < r < 2.1 for r in rates)
+
+
 def test_fp64_sphere_channels_batch_force(torch):
     log("fp64 sphere channels 3x(40x20x16), 60 steps")
     wl = W.sphere_channels(3, nx=40, ny=20, nz=16, seed=77, rmin=2.0, rmax=4.0)

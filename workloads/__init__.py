@@ -73,6 +73,29 @@ def kolmogorov(n, f0=1e-5, tau=0.5005, kf=4, noise=1e-4, seed=2, steps=5000):
                 force_profile_y=prof, steps=steps)
 
 
+def four_rolls_mill(n, u0=1e-3, re=100.0):
+    """Two-dimensional four-rolls mill (Sec. III): an n x n periodic box, one
+    node in z, driven by the body-force density
+    F = 2 nu u0 psi^2 [sin(psi x) sin(psi y), cos(psi x) cos(psi y)], psi = 2 pi / n,
+    on the integer node coordinates, with Re = u0 n / nu.  Its steady state is
+    u = u0 [sin(psi x) sin(psi y), cos(psi x) cos(psi y)] (returned as u_exact,
+    z component zero).  Arrays have the batch shape (1, 1, n, n)."""
+    nu = u0 * n / re
+    psi = 2.0 * math.pi / n
+    c = np.arange(n, dtype=np.float64)
+    sx, cx = np.sin(psi * c)[None, :], np.cos(psi * c)[None, :]  # varies along x (last axis)
+    sy, cy = np.sin(psi * c)[:, None], np.cos(psi * c)[:, None]  # varies along y
+    shape = (1, 1, n, n)
+    u = np.zeros((3,) + shape)
+    u[0] = (u0 * sx * sy).reshape(shape)
+    u[1] = (u0 * cx * cy).reshape(shape)
+    force = 2.0 * nu * psi * psi * u
+    return dict(name=f"four_rolls_mill_{n}", shape=shape, tau=0.5 + 3.0 * nu, nu=nu, u0=u0, re=re, rho0=1.0,
+                wall=(0, 0, 0), force=force, u_exact=u,
+                # slowest relaxation time of the box (wavenumber psi): 1 / (nu psi^2)
+                t_relax=1.0 / (nu * psi * psi))
+
+
 def sphere_channels(nb, nx=64, ny=32, nz=32, seed=1000, rmin=3.0, rmax=8.0, nmin=1, nmax=4, fmin=1e-6, fmax=1e-5,
                     tau=0.8):
     """Batch of nb forced channels (periodic x, z; walls in y) with 1-4 solid
