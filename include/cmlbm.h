@@ -82,6 +82,11 @@ extern "C" {
 #define CMLBM_FLAG_STOCHASTIC 4u /* 16-bit storage: stochastic (unbiased) instead of nearest-even rounding
                                     of the post-collision populations; bits from a counter-based hash
                                     of (cell, step), so runs are reproducible */
+/* Comparison models of Sec. III (FP64 and FP32 storage only): the same
+ * central-moment relaxation with a truncated equilibrium and/or forcing term.
+ * Neither flag: the method itself (complete equilibrium and forcing, M1). */
+#define CMLBM_FLAG_FORCE_GUO 8u  /* second-order (H1 + H2, Guo et al.) forcing term: M4 */
+#define CMLBM_FLAG_EQ_SECOND 16u /* second-order equilibrium; with CMLBM_FLAG_FORCE_GUO: M5 */
 
 /* cmlbm_reduce: `what` bits and the layout of one row of its output */
 #define CMLBM_REDUCE_RESIDUAL 1u /* compare u with the last snapshot */

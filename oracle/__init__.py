@@ -34,6 +34,10 @@ def _load(extended=False):
         lib.orc_lattice_constants.argtypes = [_ip, _ip, _ip, _dp, _ip]
         lib.orc_feq.argtypes = [_real, _dp, _dp]
         lib.orc_forcing.argtypes = [_dp, _dp, _dp]
+        lib.orc_feq_order.argtypes = [_real, _dp, ctypes.c_int, _dp]
+        lib.orc_forcing_order.argtypes = [_dp, _dp, ctypes.c_int, _dp]
+        lib.orc_collide_model.argtypes = [_dp, _dp, _real, ctypes.c_int, ctypes.c_int, _dp]
+        lib.orc_collide_model.restype = ctypes.c_int
         lib.orc_basis.argtypes = [_dp, _dp]
         lib.orc_central_moments.argtypes = [_dp, _dp, _dp]
         lib.orc_macroscopic.argtypes = [_dp, _dp, _dp, _dp]
@@ -96,6 +100,29 @@ def forcing(u, F):
     """Complete Hermite forcing term (eq. forcing), F a force density."""
     out = np.zeros(27)
     _load().orc_forcing(_d(_vec(u, 3)), _d(_vec(F, 3)), _d(out))
+    return out
+
+
+def feq_order(rho, u, order):
+    """Equilibrium of eq. eq:truncation keeping Hermite tensors up to `order` (2 or 6)."""
+    out = np.zeros(27)
+    _load().orc_feq_order(float(rho), _d(_vec(u, 3)), int(order), _d(out))
+    return out
+
+
+def forcing_order(u, F, order):
+    """Forcing term of eq. forcing keeping Hermite tensors up to `order` (2 = Guo, 6 = complete)."""
+    out = np.zeros(27)
+    _load().orc_forcing_order(_d(_vec(u, 3)), _d(_vec(F, 3)), int(order), _d(out))
+    return out
+
+
+def collide_model(f, F, omega, eq_order, force_order):
+    """Literal collision with a truncated equilibrium / forcing (the comparison models of Sec. III)."""
+    out = np.zeros(27)
+    if _load().orc_collide_model(_d(_vec(f, 27)), _d(_vec(F, 3)), float(omega), int(eq_order), int(force_order),
+                                 _d(out)) != 0:
+        raise ArithmeticError("singular central-moment matrix")
     return out
 
 
@@ -188,7 +215,10 @@ class Lattice:
     oracle in 80-bit long double (arrays np.longdouble).
     """
 
-    VARIANTS = {"closed": 0, "literal": 1}
+    # closed form and literal route of the method (M1); literal routes of the
+    # comparison models M4 (second-order forcing), M5 (second-order equilibrium
+    # and forcing) and a second-order equilibrium with the complete forcing
+    VARIANTS = {"closed": 0, "literal": 1, "m4": 2, "m5": 3, "eq2": 4}
 
     def __init__(self, nx, ny, nz, nb=1, tau=0.8, wall=(0, 0, 0), solid=None, force=None, extended=False):
         self.extended = bool(extended)

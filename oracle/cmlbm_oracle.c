@@ -152,8 +152,10 @@ static void hermite_tensors(int i, hermite_set* h)
     h->xxyyzz = Hxx * Hyy * Hzz;
 }
 
-/* Complete 27-Hermite equilibrium, eq. "eq:truncation", term by term. */
-void orc_feq(real rho, const real u[3], real out[Q])
+/* 27-Hermite equilibrium, eq. "eq:truncation", term by term, keeping the
+ * Hermite tensors up to the given order (2: the classical second-order
+ * equilibrium the text mentions; 6: the complete expansion). */
+void orc_feq_order(real rho, const real u[3], int order, real out[Q])
 {
     const real ux = u[0], uy = u[1], uz = u[2];
     const real cs4 = CS2 * CS2, cs6 = cs4 * CS2, cs8 = cs4 * cs4, cs10 = cs8 * CS2, cs12 = cs6 * cs6;
@@ -165,6 +167,10 @@ void orc_feq(real rho, const real u[3], real out[Q])
         s += (H.xx * ux * ux + H.yy * uy * uy + H.zz * uz * uz +
               2.0 * (H.xy * ux * uy + H.xz * ux * uz + H.yz * uy * uz)) /
              (2.0 * cs4);
+        if (order < 3) {
+            out[i] = weight(i) * rho * s;
+            continue;
+        }
         s += (H.xxy * ux * ux * uy + H.xxz * ux * ux * uz + H.xyy * ux * uy * uy + H.xzz * ux * uz * uz +
               H.yzz * uy * uz * uz + H.yyz * uy * uy * uz + 2.0 * H.xyz * ux * uy * uz) /
              (2.0 * cs6);
@@ -179,9 +185,14 @@ void orc_feq(real rho, const real u[3], real out[Q])
     }
 }
 
-/* Complete Hermite forcing term, eq. "forcing", term by term, under reading R1
- * (F is a force density, so the rho prefactor of the printed formula is 1). */
-void orc_forcing(const real u[3], const real F[3], real out[Q])
+/* Complete 27-Hermite equilibrium. */
+void orc_feq(real rho, const real u[3], real out[Q]) { orc_feq_order(rho, u, 6, out); }
+
+/* Hermite forcing term, eq. "forcing", term by term, under reading R1 (F is a
+ * force density, so the rho prefactor of the printed formula is 1), keeping
+ * the Hermite tensors up to the given order (2: H1 + H2, the Guo form the
+ * text names; 6: the complete expansion). */
+void orc_forcing_order(const real u[3], const real F[3], int order, real out[Q])
 {
     const real ux = u[0], uy = u[1], uz = u[2];
     const real Fx = F[0], Fy = F[1], Fz = F[2];
@@ -193,6 +204,10 @@ void orc_forcing(const real u[3], const real F[3], real out[Q])
         s += (H.xx * (2 * ux * Fx) + H.yy * (2 * uy * Fy) + H.zz * (2 * uz * Fz) +
               2 * H.xy * (ux * Fy + uy * Fx) + 2 * H.xz * (ux * Fz + uz * Fx) + 2 * H.yz * (uy * Fz + uz * Fy)) /
              (2 * cs4);
+        if (order < 3) {
+            out[i] = weight(i) * s;
+            continue;
+        }
         s += (H.xxy * (2 * ux * uy * Fx + ux * ux * Fy) + H.xxz * (2 * ux * uz * Fx + ux * ux * Fz) +
               H.xyy * (2 * ux * uy * Fy + uy * uy * Fx) + H.xzz * (2 * ux * uz * Fz + uz * uz * Fx) +
               H.yzz * (2 * uy * uz * Fz + uz * uz * Fy) + H.yyz * (2 * uy * uz * Fy + uy * uy * Fz) +
@@ -215,6 +230,9 @@ void orc_forcing(const real u[3], const real F[3], real out[Q])
         out[i] = weight(i) * s;
     }
 }
+
+/* Complete Hermite forcing term. */
+void orc_forcing(const real u[3], const real F[3], real out[Q]) { orc_forcing_order(u, F, 6, out); }
 
 /* The 27 basis polynomials of eq. "basis" evaluated at one shifted velocity. */
 static void basis_polys(real X, real Y, real Z, real T[Q])
@@ -339,13 +357,16 @@ int orc_reconstruct_literal(const real u[3], const real k[Q], real f[Q])
 
 /* Literal collision: every central-moment vector is formed by the matrix
  * products of Sec. II; k^eq and R come from eqs. "eq:truncation" and "forcing". */
-int orc_collide_literal(const real f[Q], const real F[3], real omega, real fstar[Q])
+/* Literal collision of a comparison model of Sec. III: the same central-moment
+ * relaxation (eq. "eq:relaxationMatrix") with the equilibrium truncated at
+ * eq_order and the forcing term at force_order (M1: 6, 6; M4: 6, 2; M5: 2, 2). */
+int orc_collide_model(const real f[Q], const real F[3], real omega, int eq_order, int force_order, real fstar[Q])
 {
     real rho, u[3];
     orc_macroscopic(f, F, &rho, u);
     real feq[Q], ff[Q], k[Q], keq[Q], R[Q], ks[Q];
-    orc_feq(rho, u, feq);
-    orc_forcing(u, F, ff);
+    orc_feq_order(rho, u, eq_order, feq);
+    orc_forcing_order(u, F, force_order, ff);
     orc_central_moments(u, f, k);
     orc_central_moments(u, feq, keq);
     orc_central_moments(u, ff, R);
@@ -354,6 +375,28 @@ int orc_collide_literal(const real f[Q], const real F[3], real omega, real fstar
         ks[j] = (1.0 - L) * k[j] + L * keq[j] + (1.0 - 0.5 * L) * R[j];
     }
     return orc_reconstruct_literal(u, ks, fstar);
+}
+
+void orc_collide_closed(const real f[Q], const real F[3], real omega, real fstar[Q]);
+
+int orc_collide_literal(const real f[Q], const real F[3], real omega, real fstar[Q])
+{
+    return orc_collide_model(f, F, omega, 6, 6, fstar);
+}
+
+/* Collision by variant code: 0 closed form (M1), 1 literal M1, 2 literal M4
+ * (second-order forcing), 3 literal M5 (second-order equilibrium and
+ * forcing), 4 literal with a second-order equilibrium and the complete
+ * forcing.  Returns non-zero on a singular literal solve. */
+static int collide_variant(const real f[Q], const real F[3], real omega, int variant, real fstar[Q])
+{
+    switch (variant) {
+        case 0: orc_collide_closed(f, F, omega, fstar); return 0;
+        case 1: return orc_collide_model(f, F, omega, 6, 6, fstar);
+        case 2: return orc_collide_model(f, F, omega, 6, 2, fstar);
+        case 3: return orc_collide_model(f, F, omega, 2, 2, fstar);
+        default: return orc_collide_model(f, F, omega, 2, 6, fstar);
+    }
 }
 
 /* Eq. "pre_collision": k_4..k_8 as direct sums with the shifted velocities. */
@@ -556,7 +599,7 @@ void orc_lattice_init(int nx, int ny, int nz, int nb, const uint8_t* solid, cons
 
 /* Advance nsteps: collide every fluid cell (eq. "collision" in central-moment
  * form), then stream (eq. "streaming") with periodic wrap or halfway
- * bounce-back (reading R3).  variant 0 = closed form, 1 = literal.
+ * bounce-back (reading R3).  variant: see collide_variant.
  * tmp is caller scratch of the same size as f.  Returns 0, or -1 if a literal
  * solve met a singular matrix. */
 int orc_lattice_step(int nx, int ny, int nz, int nb, const int* wall, const uint8_t* solid,
@@ -573,13 +616,9 @@ int orc_lattice_step(int nx, int ny, int nz, int nb, const int* wall, const uint
             real fc[Q], fs[Q], F[3];
             for (int i = 0; i < Q; ++i) fc[i] = f[i * N + n];
             cell_force(&g, n, F);
-            if (variant == 1) {
-                if (orc_collide_literal(fc, F, omega, fs) != 0) {
+            if (collide_variant(fc, F, omega, variant, fs) != 0) {
 #pragma omp atomic write
-                    status = -1;
-                }
-            } else {
-                orc_collide_closed(fc, F, omega, fs);
+                status = -1;
             }
             for (int i = 0; i < Q; ++i) tmp[i * N + n] = fs[i];
         }
@@ -625,7 +664,7 @@ void orc_lattice_moments(int nx, int ny, int nz, int nb, const uint8_t* solid, c
 }
 
 /* Collide n independent cells (sampled checks): f, out are [27][n], F is
- * [3][n] or NULL.  variant 0 = closed form, 1 = literal. */
+ * [3][n] or NULL.  variant: see collide_variant. */
 int orc_collide_cells(long n, const real* f, const real* F, real omega, int variant, real* out)
 {
     int status = 0;
@@ -634,13 +673,9 @@ int orc_collide_cells(long n, const real* f, const real* F, real omega, int vari
         real fc[Q], fs[Q], Fc[3];
         for (int i = 0; i < Q; ++i) fc[i] = f[i * n + c];
         for (int a = 0; a < 3; ++a) Fc[a] = F ? F[a * n + c] : 0.0;
-        if (variant == 1) {
-            if (orc_collide_literal(fc, Fc, omega, fs) != 0) {
+        if (collide_variant(fc, Fc, omega, variant, fs) != 0) {
 #pragma omp atomic write
-                status = -1;
-            }
-        } else {
-            orc_collide_closed(fc, Fc, omega, fs);
+            status = -1;
         }
         for (int i = 0; i < Q; ++i) out[i * n + c] = fs[i];
     }

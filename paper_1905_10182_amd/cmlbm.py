@@ -18,7 +18,9 @@ STORAGE = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16}
 STORAGE_BYTES = {FP64: 8, FP32: 4, FP16: 2, BF16: 2}
 PERIODIC, BOUNCEBACK = 0, 1
 FORCE_NONE, FORCE_UNIFORM, FORCE_BATCH, FORCE_PROFILE_Y, FORCE_FIELD = 0, 1, 2, 3, 4
-FLAG_SOLID, FLAG_RESIDUAL, FLAG_STOCHASTIC = 1, 2, 4
+FLAG_SOLID, FLAG_RESIDUAL, FLAG_STOCHASTIC, FLAG_FORCE_GUO, FLAG_EQ_SECOND = 1, 2, 4, 8, 16
+# collision models: the method (M1) and the comparison models of Sec. III
+MODELS = {"m1": 0, "m4": FLAG_FORCE_GUO, "m5": FLAG_FORCE_GUO | FLAG_EQ_SECOND, "eq2": FLAG_EQ_SECOND}
 REDUCE_RESIDUAL, REDUCE_SNAPSHOT = 1, 2
 RED = {"mass": 0, "momx": 1, "momy": 2, "momz": 3, "ke": 4, "umax": 5, "nonfinite": 6, "fluid": 7,
        "du2": 8, "u2": 9, "residual": 10}
@@ -122,13 +124,13 @@ class Lattice:
     """
 
     def __init__(self, nx, ny, nz, nbatch=1, tau=0.8, rho0=1.0, storage="fp32", wall=(0, 0, 0),
-                 solid=False, residual=False, stochastic=False, device="cuda"):
+                 solid=False, residual=False, stochastic=False, model="m1", device="cuda"):
         import torch
 
         self.torch = torch
         self.lib = load_library()
         flags = (FLAG_SOLID if solid else 0) | (FLAG_RESIDUAL if residual else 0) | \
-            (FLAG_STOCHASTIC if stochastic else 0)
+            (FLAG_STOCHASTIC if stochastic else 0) | MODELS[model]
         self.params = make_params(nx, ny, nz, nbatch, tau, rho0, storage, wall, flags)
         self.shape = (int(nbatch), int(nz), int(ny), int(nx))
         self.N = int(np.prod(self.shape))

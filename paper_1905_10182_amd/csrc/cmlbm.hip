@@ -32,6 +32,9 @@ namespace {
 
 constexpr int kBlock = 256;   // threads per workgroup of every kernel
 constexpr int kNPart = 10;    // partial-sum slots of k_reduce
+// collision model bits of k_step (0: the method's closed-form collision)
+constexpr int kModelGuo = 1;  // second-order forcing term
+constexpr int kModelEq2 = 2;  // second-order equilibrium
 constexpr int kMaxRedBlocks = 256;  // reduce workgroups per batch member
 constexpr uint32_t kSolidBit = 1u << 27;
 
@@ -274,7 +277,7 @@ __device__ __forceinline__ void st_off(void* base, uint32_t byte_off, X v)
     }
 }
 
-template <int ST, int V, bool MASK, bool FIELD, bool NT>
+template <int ST, int V, bool MASK, bool FIELD, bool NT, int MODEL>
 __global__ __launch_bounds__(kBlock) void k_step(const typename storage<ST>::S* __restrict__ src,
                                                   typename storage<ST>::S* __restrict__ dst, Geom g, int segs,
                                                   typename storage<ST>::T omega, typename storage<ST>::T rho0,
@@ -283,6 +286,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename storage<ST>::S* 
                                                   const uint32_t* __restrict__ mask, int sr, uint32_t step)
 {
     static_assert(V == 1 || !MASK, "bounce-back masks use one cell per lane");
+    static_assert(MODEL == 0 || V == 1, "comparison models use one cell per lane");
     using SS = storage<ST>;
     using S = typename SS::S;
     using T = typename SS::T;
@@ -392,7 +396,11 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename storage<ST>::S* 
 #pragma unroll
     for (int c = 0; c < V; ++c) {
         T rho, ux, uy, uz;
-        collide<T>(h[c], Fx[c], Fy[c], Fz[c], omega, rho0, rho, ux, uy, uz);
+        if constexpr (MODEL == 0)
+            collide<T>(h[c], Fx[c], Fy[c], Fz[c], omega, rho0, rho, ux, uy, uz);
+        else
+            collide_model<T, (MODEL & kModelEq2) != 0, (MODEL & kModelGuo) != 0>(h[c], Fx[c], Fy[c], Fz[c], omega,
+                                                                                   rho0, rho, ux, uy, uz);
     }
     const uint32_t bst = (uint32_t)x0 * (uint32_t)sizeof(S);
     if constexpr (sizeof(S) == 2) {
@@ -763,7 +771,12 @@ int validate(const cmlbm_params* p)
     if (p->storage < CMLBM_FP64 || p->storage > CMLBM_BF16) return CMLBM_EINVAL;
     for (int a = 0; a < 3; ++a)
         if (p->wall[a] != CMLBM_PERIODIC && p->wall[a] != CMLBM_BOUNCEBACK) return CMLBM_EINVAL;
-    if (p->flags & ~(CMLBM_FLAG_SOLID | CMLBM_FLAG_RESIDUAL | CMLBM_FLAG_STOCHASTIC)) return CMLBM_EINVAL;
+    if (p->flags & ~(CMLBM_FLAG_SOLID | CMLBM_FLAG_RESIDUAL | CMLBM_FLAG_STOCHASTIC | CMLBM_FLAG_FORCE_GUO |
+                     CMLBM_FLAG_EQ_SECOND))
+        return CMLBM_EINVAL;
+    if ((p->flags & (CMLBM_FLAG_FORCE_GUO | CMLBM_FLAG_EQ_SECOND)) && p->storage != CMLBM_FP64 &&
+        p->storage != CMLBM_FP32)
+        return CMLBM_EINVAL;
     // an axis of extent 1 with walls would bounce everything; periodic is required there
     const int dims[3] = {p->nx, p->ny, p->nz};
     for (int a = 0; a < 3; ++a)
@@ -872,7 +885,12 @@ int step_lanes(const cmlbm_lattice* lat)
     return 1;
 }
 
-template <int ST, int V, bool MASK, bool FIELD>
+int lat_model(const cmlbm_lattice* lat)
+{
+    return ((lat->p.flags & CMLBM_FLAG_FORCE_GUO) ? kModelGuo : 0) | ((lat->p.flags & CMLBM_FLAG_EQ_SECOND) ? kModelEq2 : 0);
+}
+
+template <int ST, int V, bool MASK, bool FIELD, int MODEL = 0>
 void launch_step_v(cmlbm_lattice* lat, hipStream_t s)
 {
     using SS = storage<ST>;
@@ -882,10 +900,27 @@ void launch_step_v(cmlbm_lattice* lat, hipStream_t s)
     const uint64_t waves = (uint64_t)g.rows * (uint64_t)segs;
     const dim3 grid((unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64)));
     const T* ftab = (const T*)(lat->scratch + (ST == CMLBM_FP64 ? lat->off_ftab64 : lat->off_ftab32));
-    k_step<ST, V, MASK, FIELD, true><<<grid, dim3(kBlock), 0, s>>>(
+    k_step<ST, V, MASK, FIELD, true, MODEL><<<grid, dim3(kBlock), 0, s>>>(
         (const typename SS::S*)lat->pop[lat->cur], (typename SS::S*)lat->pop[1 - lat->cur], g, segs,
         (T)(1.0 / lat->p.tau), (T)lat->p.rho0, ftab, (const T*)lat->field, mask_ptr(lat),
         (lat->p.flags & CMLBM_FLAG_STOCHASTIC) ? 1 : 0, (uint32_t)lat->t);
+}
+
+template <int ST, int MODEL>
+void launch_step_model(cmlbm_lattice* lat, hipStream_t s)
+{
+    const bool F = lat->force_mode == CMLBM_FORCE_FIELD;
+    if (lat->needs_mask) {
+        if (F)
+            launch_step_v<ST, 1, true, true, MODEL>(lat, s);
+        else
+            launch_step_v<ST, 1, true, false, MODEL>(lat, s);
+    } else {
+        if (F)
+            launch_step_v<ST, 1, false, true, MODEL>(lat, s);
+        else
+            launch_step_v<ST, 1, false, false, MODEL>(lat, s);
+    }
 }
 
 template <int ST>
@@ -893,6 +928,18 @@ int launch_step_st(cmlbm_lattice* lat, hipStream_t s)
 {
     const bool F = lat->force_mode == CMLBM_FORCE_FIELD;
     const int V = step_lanes(lat);
+    if constexpr (ST == CMLBM_FP64 || ST == CMLBM_FP32) {
+        const int model = lat_model(lat);
+        if (model) {
+            if (model == kModelGuo)
+                launch_step_model<ST, kModelGuo>(lat, s);
+            else if (model == kModelEq2)
+                launch_step_model<ST, kModelEq2>(lat, s);
+            else
+                launch_step_model<ST, kModelGuo | kModelEq2>(lat, s);
+            return launch_check(lat, "step");
+        }
+    }
     if (lat->needs_mask) {
         if (F)
             launch_step_v<ST, 1, true, true>(lat, s);

@@ -181,4 +181,179 @@ __device__ __forceinline__ void collide(T h[27], T Fx, T Fy, T Fz, T omega, T rh
                   h[vel_index(1, b - 1, c - 1)]);
 }
 
+// Forward 1D central-moment map on {-1, 0, +1} shifted by u:
+// (g-, g0, g+) -> (sum g, sum g (c - u), sum g (c - u)^2).
+template <typename T>
+__device__ __forceinline__ void fwd1d(T gm, T g0, T gp, T u, T& m0, T& m1, T& m2)
+{
+    m0 = gm + g0 + gp;
+    const T odd = gp - gm, even = gp + gm;
+    m1 = odd - u * m0;
+    m2 = even - T(2) * u * odd + u * u * m0;
+}
+
+// Central monomial moments M[p][q][r] = sum_i g_i (cx-ux)^p (cy-uy)^q (cz-uz)^r,
+// by three 1D maps (x, then y, then z).
+template <typename T>
+__device__ __forceinline__ void central_monomials(const T g[27], T ux, T uy, T uz, T M[3][3][3])
+{
+    T A[3][3][3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            fwd1d(g[vel_index(-1, b - 1, c - 1)], g[vel_index(0, b - 1, c - 1)], g[vel_index(1, b - 1, c - 1)], ux,
+                  A[0][b][c], A[1][b][c], A[2][b][c]);
+    T B[3][3][3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) fwd1d(A[p][0][c], A[p][1][c], A[p][2][c], uy, B[p][0][c], B[p][1][c], B[p][2][c]);
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) fwd1d(B[p][q][0], B[p][q][1], B[p][q][2], uz, M[p][q][0], M[p][q][1], M[p][q][2]);
+}
+
+// Collision of the comparison models of Sec. III: the same central-moment
+// relaxation (omega on k4..k8, 1 on every other moment) with the equilibrium
+// and the forcing term truncated in Hermite order.  EQ2: second-order
+// equilibrium instead of the complete one; GUO: second-order (H1 + H2, Guo)
+// forcing instead of the complete one.  (GUO: M4; EQ2 + GUO: M5.)
+//
+// The truncated equilibrium and forcing have velocity-dependent central
+// moments, so instead of a closed table this route builds both as
+// populations (the equilibrium in deviation form, f^eq_i - w_i rho0), takes
+// their central monomial moments, and relaxes:
+//   rate-1 moments:  K* = K^eq + R / 2
+//   k4..k8:          k* = (1 - omega) k + omega k^eq + (1 - omega / 2) R
+// with k7 = K200 - K020, k8 = K200 - K002 and the trace K200 + K020 + K002
+// relaxing at rate 1.  Everything is carried minus the rest state's central
+// moments, as in collide().
+template <typename T, bool EQ2, bool GUO>
+__device__ __forceinline__ void collide_model(T h[27], T Fx, T Fy, T Fz, T omega, T rho0, T& rho_out, T& ux_out,
+                                              T& uy_out, T& uz_out)
+{
+    // density, velocity and the pre-collision second-order central moments, as in collide()
+    T X[3][3][3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const T hm = h[vel_index(-1, b - 1, c - 1)];
+            const T h0 = h[vel_index(0, b - 1, c - 1)];
+            const T hp = h[vel_index(1, b - 1, c - 1)];
+            X[0][b][c] = hm + h0 + hp;
+            X[1][b][c] = hp - hm;
+            X[2][b][c] = hp + hm;
+        }
+    T Y[3][3][3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Y[p][0][c] = X[p][0][c] + X[p][1][c] + X[p][2][c];
+            Y[p][1][c] = X[p][2][c] - X[p][0][c];
+            Y[p][2][c] = X[p][2][c] + X[p][0][c];
+        }
+    auto zsum = [&](int p, int q, int r) -> T {
+        if (r == 0) return Y[p][q][0] + Y[p][q][1] + Y[p][q][2];
+        if (r == 1) return Y[p][q][2] - Y[p][q][0];
+        return Y[p][q][2] + Y[p][q][0];
+    };
+    const T drho = zsum(0, 0, 0);
+    const T jx = zsum(1, 0, 0), jy = zsum(0, 1, 0), jz = zsum(0, 0, 1);
+    const T Sxx = zsum(2, 0, 0), Syy = zsum(0, 2, 0), Szz = zsum(0, 0, 2);
+    const T Sxy = zsum(1, 1, 0), Sxz = zsum(1, 0, 1), Syz = zsum(0, 1, 1);
+    const T rho = rho0 + drho;
+    const T inv_rho = T(1) / rho;
+    const T ux = (jx + T(0.5) * Fx) * inv_rho;
+    const T uy = (jy + T(0.5) * Fy) * inv_rho;
+    const T uz = (jz + T(0.5) * Fz) * inv_rho;
+    rho_out = rho;
+    ux_out = ux;
+    uy_out = uy;
+    uz_out = uz;
+    const T k4 = Sxy - rho * ux * uy + T(0.5) * (ux * Fy + uy * Fx);
+    const T k5 = Sxz - rho * ux * uz + T(0.5) * (ux * Fz + uz * Fx);
+    const T k6 = Syz - rho * uy * uz + T(0.5) * (uy * Fz + uz * Fy);
+    const T k7 = (Sxx - Syy) - rho * (ux * ux - uy * uy) + (ux * Fx - uy * Fy);
+    const T k8 = (Sxx - Szz) - rho * (ux * ux - uz * uz) + (ux * Fx - uz * Fz);
+
+    // equilibrium (deviation form) and forcing populations of the model
+    const T ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz, usq = ux2 + uy2 + uz2;
+    const T uF = ux * Fx + uy * Fy + uz * Fz;
+    T e[27], g[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        constexpr T third = T(1.0 / 3.0);
+        const int cx = vel_x(i), cy = vel_y(i), cz = vel_z(i);
+        const T w = T(weight(i));
+        // 1D factors of the complete equilibrium, phi(c, u) = 1 + 3 c u + (9/2)(c^2 - 1/3) u^2, minus 1
+        const T ax = T(3 * cx) * ux + T(4.5) * (T(cx * cx) - third) * ux2;
+        const T ay = T(3 * cy) * uy + T(4.5) * (T(cy * cy) - third) * uy2;
+        const T az = T(3 * cz) * uz + T(4.5) * (T(cz * cz) - third) * uz2;
+        const T cu = T(cx) * ux + T(cy) * uy + T(cz) * uz;
+        T sm1;  // f^eq_i / (w_i rho) - 1
+        if (EQ2)
+            sm1 = T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq;
+        else
+            sm1 = ax + ay + az + ax * ay + ax * az + ay * az + ax * ay * az;
+        e[i] = w * (drho + rho * sm1);
+        const T cF = T(cx) * Fx + T(cy) * Fy + T(cz) * Fz;
+        if (GUO) {
+            g[i] = w * (T(3) * (cF - uF) + T(9) * cu * cF);
+        } else {
+            // F . grad_u of the complete (product-form) equilibrium at rho = 1
+            const T dx = T(3 * cx) + T(9) * (T(cx * cx) - third) * ux;
+            const T dy = T(3 * cy) + T(9) * (T(cy * cy) - third) * uy;
+            const T dz = T(3 * cz) + T(9) * (T(cz * cz) - third) * uz;
+            g[i] = w * (Fx * dx * (T(1) + ay) * (T(1) + az) + Fy * (T(1) + ax) * dy * (T(1) + az) +
+                        Fz * (T(1) + ax) * (T(1) + ay) * dz);
+        }
+    }
+    T De[3][3][3], R[3][3][3];
+    central_monomials(e, ux, uy, uz, De);
+    central_monomials(g, ux, uy, uz, R);
+
+    T D[3][3][3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int r = 0; r < 3; ++r) D[p][q][r] = De[p][q][r] + T(0.5) * R[p][q][r];
+    // second-order block; the rest state's central moments are rho0 (ux uy, ..., 1/3 + ux^2, ...)
+    const T om1 = T(1) - omega, hf = T(1) - T(0.5) * omega, third = T(1.0 / 3.0);
+    const T r110 = rho0 * ux * uy, r101 = rho0 * ux * uz, r011 = rho0 * uy * uz;
+    D[1][1][0] = om1 * (k4 - r110) + omega * De[1][1][0] + hf * R[1][1][0];
+    D[1][0][1] = om1 * (k5 - r101) + omega * De[1][0][1] + hf * R[1][0][1];
+    D[0][1][1] = om1 * (k6 - r011) + omega * De[0][1][1] + hf * R[0][1][1];
+    const T keq7 = De[2][0][0] - De[0][2][0] + rho0 * (ux2 - uy2);
+    const T keq8 = De[2][0][0] - De[0][0][2] + rho0 * (ux2 - uz2);
+    const T k7s = om1 * k7 + omega * keq7 + hf * (R[2][0][0] - R[0][2][0]);
+    const T k8s = om1 * k8 + omega * keq8 + hf * (R[2][0][0] - R[0][0][2]);
+    const T d9 = De[2][0][0] + De[0][2][0] + De[0][0][2] + T(0.5) * (R[2][0][0] + R[0][2][0] + R[0][0][2]);
+    D[2][0][0] = (d9 + k7s + k8s) * third + rho0 * (uy2 + uz2 - T(2) * ux2) * third;
+    D[0][2][0] = (d9 - T(2) * k7s + k8s) * third + rho0 * (ux2 + uz2 - T(2) * uy2) * third;
+    D[0][0][2] = (d9 + k7s - T(2) * k8s) * third + rho0 * (ux2 + uy2 - T(2) * uz2) * third;
+
+    T A[3][3][3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) inv1d(D[p][q][0], D[p][q][1], D[p][q][2], uz, A[p][q][0], A[p][q][1], A[p][q][2]);
+    T B[3][3][3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) inv1d(A[p][0][c], A[p][1][c], A[p][2][c], uy, B[p][0][c], B[p][1][c], B[p][2][c]);
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            inv1d(B[0][b][c], B[1][b][c], B[2][b][c], ux, h[vel_index(-1, b - 1, c - 1)], h[vel_index(0, b - 1, c - 1)],
+                  h[vel_index(1, b - 1, c - 1)]);
+}
+
 }  // namespace cmlbm

@@ -2,7 +2,7 @@
 
     python -m paper_1905_10182_amd.studies precision [--n 512] [--steps 2000] [--every 100]
     python -m paper_1905_10182_amd.studies kolmogorov [--n 384] [--steps 5000] [--every 500]
-    python -m paper_1905_10182_amd.studies four-rolls [--storage fp64]
+    python -m paper_1905_10182_amd.studies four-rolls [--storage fp64] [--models m1,m4,m5]
 
 ``precision``: the 3D Taylor-Green vortex (u0 = 0.05, Re = 1600) advanced in
 lockstep with FP64, FP32, FP16 and BF16 population storage (16-bit both with
@@ -18,8 +18,10 @@ with FP64, FP32 and FP16 (both roundings) storage, same report.
 one node in z, per-node force field) to its analytic steady state for
 N = 8..256 at u0 = 1e-3 and 1e-2: relative L2 velocity error per grid and the
 observed order between successive grids (the paper prints 1.998 for
-u0 = 1e-3).  Each grid starts from the analytic field and runs for three
-relaxation times of the box, 3 / (nu psi^2).
+u0 = 1e-3), for the method (m1) and optionally the comparison models m4
+(second-order forcing) and m5 (second-order equilibrium and forcing).  Each
+grid starts from the analytic field and runs for three relaxation times of
+the box, 3 / (nu psi^2).
 
 All print one JSON object per checkpoint or grid.  Error norms are taken with torch
 on device-resident moments (diagnostics only; the solver runs in libcmlbm).
@@ -98,18 +100,19 @@ def kolmogorov_study(n=384, steps=5000, every=500, storages=("fp64", "fp32", "fp
     return lockstep(lats, steps, every, f"kolmogorov_{n}")
 
 
-def four_rolls_study(ns=(8, 16, 32, 64, 128, 256), u0s=(1e-3, 1e-2), relax=3.0, storage="fp64", out=sys.stdout):
+def four_rolls_study(ns=(8, 16, 32, 64, 128, 256), u0s=(1e-3, 1e-2), relax=3.0, storage="fp64", models=("m1",),
+                     out=sys.stdout):
     import math
 
     import numpy as np
     import torch
 
     rows = []
-    for u0 in u0s:
+    for model, u0 in ((m, u) for m in models for u in u0s):
         prev = None
         for n in ns:
             wl = workloads.four_rolls_mill(n, u0=u0)
-            lat = Lattice(n, n, 1, tau=wl["tau"], storage=storage, device="cuda:0")
+            lat = Lattice(n, n, 1, tau=wl["tau"], storage=storage, model=model, device="cuda:0")
             lat.set_force("field", field=wl["force"])
             lat.init(np.ones(wl["shape"]), wl["u_exact"])
             steps = int(relax * wl["t_relax"])
@@ -120,7 +123,7 @@ def four_rolls_study(ns=(8, 16, 32, 64, 128, 256), u0s=(1e-3, 1e-2), relax=3.0, 
             u = lat.moments()[1].double().cpu().numpy()
             ex = wl["u_exact"][:2]
             err = float(np.linalg.norm(u[:2] - ex) / np.linalg.norm(ex))
-            row = {"study": "four_rolls_mill", "storage": storage, "u0": u0, "n": n, "tau": wl["tau"],
+            row = {"study": "four_rolls_mill", "model": model, "storage": storage, "u0": u0, "n": n, "tau": wl["tau"],
                    "steps": steps, "error": err, "order": None if prev is None else math.log2(prev / err),
                    "seconds": round(dt, 2)}
             print(json.dumps(row), file=out, flush=True)
@@ -134,6 +137,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("study", choices=["precision", "kolmogorov", "four-rolls"])
     ap.add_argument("--storage", default="fp64")
+    ap.add_argument("--models", default="m1", help="comma-separated: m1 (the method), m4, m5, eq2")
     ap.add_argument("--n", type=int)
     ap.add_argument("--steps", type=int)
     ap.add_argument("--every", type=int)
@@ -144,7 +148,7 @@ def main(argv=None):
     elif a.study == "kolmogorov":
         kolmogorov_study(**kw)
     else:
-        four_rolls_study(storage=a.storage)
+        four_rolls_study(storage=a.storage, models=tuple(a.models.split(",")))
 
 
 if __name__ == "__main__":

@@ -74,7 +74,8 @@ def test_plane_size_limit():
 
 @pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=0.3), dict(tau=float("nan")), dict(nx=0), dict(ny=-1),
                                 dict(nbatch=0), dict(rho0=0.0), dict(storage=7), dict(wall=(2, 0, 0)),
-                                dict(flags=8), dict(nz=1, wall=(0, 0, 1))])
+                                dict(flags=32), dict(flags=8, storage="fp16"), dict(flags=16, storage="bf16"),
+                                dict(nz=1, wall=(0, 0, 1))])
 def test_invalid_params(kw):
     with pytest.raises(B.CmlbmError) as e:
         B.required_bytes(req(**kw))

@@ -178,6 +178,54 @@ def test_fp64_kolmogorov_profile_force(torch):
     assert err < 1e-12
 
 
+@pytest.mark.parametrize("model", ["m4", "m5", "eq2"])
+def test_fp64_comparison_models_random_state(torch, model):
+    """The comparison models of Sec. III (truncated equilibrium / forcing,
+    same relaxation) against the oracle's literal route of the same model:
+    random non-equilibrium populations, per-cell force field, walls, solids,
+    a ragged batch of two, 5 steps, every population."""
+    log(f"fp64 {model} random state 37x13x11 nb=2, 5 steps")
+    shape = (2, 11, 13, 37)
+    g = W.generator(41)
+    solid = (g.uniform(size=shape) < 0.08).astype(np.uint8)
+    f0 = W.random_populations(shape, seed=42)
+    f0[:, solid.astype(bool)] = 0.0
+    force = g.uniform(-1e-3, 1e-3, size=(3,) + shape)
+    ref = O.Lattice(37, 13, 11, nb=2, tau=0.73, wall=(0, 1, 1), solid=solid, force=force, extended=True)
+    ref.load_populations(f0)
+    ref.step(5, variant=model)
+    lat = Lat(nx=37, ny=13, nz=11, nbatch=2, tau=0.73, storage="fp64", wall=(0, 1, 1), solid=True, model=model)
+    lat.set_solid(solid)
+    lat.set_force("field", field=force)
+    lat.load_populations(f0)
+    lat.step(5)
+    out = lat.populations().cpu().numpy()
+    fr = ref.f.astype(np.float64)
+    err = np.abs(out - fr).max() / np.abs(fr).max()
+    log(f"  max population error {err:.3e}")
+    assert err < 1e-13
+    # and the model differs from the method on this state (the switch is live)
+    m1 = O.Lattice(37, 13, 11, nb=2, tau=0.73, wall=(0, 1, 1), solid=solid, force=force)
+    m1.load_populations(f0)
+    m1.step(5)
+    assert np.abs(out - m1.f).max() > 1e3 * err * np.abs(fr).max()
+
+
+@pytest.mark.parametrize("model", ["m4", "m5"])
+def test_fp32_comparison_models_taylor_green(torch, model):
+    log(f"fp32 {model} TGV 32^3, 100 steps")
+    wl = W.taylor_green(32, seed=1)
+    ref = O.Lattice(32, 32, 32, tau=wl["tau"])
+    ref.init(wl["rho"], wl["u"])
+    ref.step(100, variant=model)
+    lat = Lat(nx=32, ny=32, nz=32, tau=wl["tau"], storage="fp32", model=model)
+    lat.init(wl["rho"], wl["u"])
+    lat.step(100)
+    err = rel(lat.moments()[1].cpu().numpy(), ref.moments()[1])
+    log(f"  velocity {err:.3e}")
+    assert err < 1e-5
+
+
 def test_fp64_four_rolls_mill_nz1_field_force(torch):
     """Four-rolls mill 16 x 16 x 1 (one node in z, periodic), per-node force
     field, 2000 steps from the analytic field."""

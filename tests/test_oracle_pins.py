@@ -477,3 +477,75 @@ def test_four_rolls_mill_second_order():
     rate = math.log2(errs[8] / errs[16])
     assert 1.9 < rate < 2.1, (errs, rate)
     assert errs[16] < 0.03
+
+
+# ---------------------------------------------------------------------------
+# comparison models of Sec. III: truncated equilibrium (M5) and forcing (M4, M5)
+
+def test_second_order_equilibrium_is_textbook_form():
+    g = W.generator(31)
+    for _ in range(5):
+        rho, u = g.uniform(0.9, 1.1), g.uniform(-0.2, 0.2, 3)
+        cu = C @ u
+        ref = WGT * rho * (1 + cu / CS2 + cu ** 2 / (2 * CS2 ** 2) - (u @ u) / (2 * CS2))
+        np.testing.assert_allclose(O.feq_order(rho, u, 2), ref, atol=1e-15)
+        np.testing.assert_allclose(O.feq_order(rho, u, 6), O.feq(rho, u), atol=0)
+
+
+def test_second_order_forcing_is_guo_form_and_printed_table():
+    """H1 + H2 of eq. forcing is the Guo et al. forcing w_i [(c - u).F/cs2 +
+    (c.u)(c.F)/cs4], and its central moments are the first truncation table of
+    the forcing discussion in Sec. II, entry by entry (R0 and R4..R9 zero)."""
+    g = W.generator(32)
+    for _ in range(5):
+        u, F = g.uniform(-0.2, 0.2, 3), g.uniform(-1e-2, 1e-2, 3)
+        cu, cF = C @ u, C @ F
+        guo = WGT * ((cF - u @ F) / CS2 + cu * cF / CS2 ** 2)
+        f2 = O.forcing_order(u, F, 2)
+        np.testing.assert_allclose(f2, guo, atol=1e-17)
+        R = O.central_moments(u, f2)
+        ux, uy, uz = u
+        Fx, Fy, Fz = F
+        cs2, cs4 = CS2, CS2 ** 2
+        table = {
+            1: Fx, 2: Fy, 3: Fz,
+            10: 2 * Fx * cs2 - Fx * uy ** 2 - 2 * Fy * ux * uy - Fx * uz ** 2 - 2 * Fz * ux * uz,
+            11: 2 * Fy * cs2 - Fy * ux ** 2 - 2 * Fx * uy * ux - Fy * uz ** 2 - 2 * Fz * uy * uz,
+            12: 2 * Fz * cs2 - Fz * ux ** 2 - 2 * Fx * uz * ux - Fz * uy ** 2 - 2 * Fy * uz * uy,
+            13: -Fx * uy ** 2 - 2 * Fy * ux * uy + Fx * uz ** 2 + 2 * Fz * ux * uz,
+            14: -Fy * ux ** 2 - 2 * Fx * uy * ux + Fy * uz ** 2 + 2 * Fz * uy * uz,
+            15: -Fz * ux ** 2 - 2 * Fx * uz * ux + Fz * uy ** 2 + 2 * Fy * uz * uy,
+            16: -Fz * ux * uy - Fy * ux * uz - Fx * uy * uz,
+            17: 4 * (Fy * ux ** 2 * uy + Fz * ux ** 2 * uz + Fx * ux * uy ** 2 + Fx * ux * uz ** 2
+                     + Fz * uy ** 2 * uz + Fy * uy * uz ** 2),
+            18: 4 * (Fy * ux ** 2 * uy + Fz * ux ** 2 * uz + Fx * ux * uy ** 2 + Fx * ux * uz ** 2
+                     - Fz * uy ** 2 * uz - Fy * uy * uz ** 2),
+            19: 4 * ux * (Fx * uy ** 2 + Fy * ux * uy - Fx * uz ** 2 - Fz * ux * uz),
+            20: 2 * ux * (Fz * ux * uy + Fy * ux * uz + 2 * Fx * uy * uz),
+            21: 2 * uy * (Fz * ux * uy + 2 * Fy * ux * uz + Fx * uy * uz),
+            22: 2 * uz * (2 * Fz * ux * uy + Fy * ux * uz + Fx * uy * uz),
+            23: Fx * cs4 - 3 * Fx * uy ** 2 * uz ** 2 - 6 * Fz * ux * uy ** 2 * uz - Fx * uy ** 2 / 3
+                - 6 * Fy * ux * uy * uz ** 2 - 2 * Fy * ux * uy / 3 - Fx * uz ** 2 / 3 - 2 * Fz * ux * uz / 3,
+            24: Fy * cs4 - 3 * Fy * ux ** 2 * uz ** 2 - 6 * Fz * uy * ux ** 2 * uz - Fy * ux ** 2 / 3
+                - 6 * Fx * uy * ux * uz ** 2 - 2 * Fx * uy * ux / 3 - Fy * uz ** 2 / 3 - 2 * Fz * uy * uz / 3,
+            25: Fz * cs4 - 3 * Fz * ux ** 2 * uy ** 2 - 6 * Fy * uz * ux ** 2 * uy - Fz * ux ** 2 / 3
+                - 6 * Fx * uz * ux * uy ** 2 - 2 * Fx * uz * ux / 3 - Fz * uy ** 2 / 3 - 2 * Fy * uz * uy / 3,
+            26: 8 * (Fz * ux ** 2 * uy ** 2 * uz + Fy * ux ** 2 * uy * uz ** 2 + Fx * ux * uy ** 2 * uz ** 2)
+                + 4 * cs2 * (Fy * ux ** 2 * uy + Fz * ux ** 2 * uz + Fx * ux * uy ** 2 + Fx * ux * uz ** 2
+                             + Fz * uy ** 2 * uz + Fy * uy * uz ** 2),
+        }
+        for j in range(27):
+            assert abs(R[j] - table.get(j, 0.0)) < 1e-15, (j, R[j], table.get(j, 0.0))
+
+
+@pytest.mark.parametrize("eq_order,force_order", [(6, 2), (2, 2), (2, 6)])
+def test_comparison_models_conserve_mass_and_add_force(eq_order, force_order):
+    g = W.generator(33)
+    F = g.uniform(-1e-3, 1e-3, 3)
+    for _ in range(5):
+        f = W.random_populations((1,), seed=int(g.integers(1 << 30)))[:, 0]
+        fs = O.collide_model(f, F, 1 / 0.7, eq_order, force_order)
+        assert abs(fs.sum() - f.sum()) < 1e-15
+        np.testing.assert_allclose(C.T @ fs - C.T @ f, F, atol=1e-15)
+    # with the complete equilibrium and forcing the model route is the method itself
+    np.testing.assert_allclose(O.collide_model(f, F, 1 / 0.7, 6, 6), O.collide_closed(f, F, 1 / 0.7), atol=2e-15)
