@@ -64,6 +64,18 @@ extern "C" {
 #define CMLBM_FP32 1
 #define CMLBM_FP16 2
 #define CMLBM_BF16 3
+/* Moment representation (FP32): instead of 27 populations a cell keeps the
+ * nine numbers its post-collision state is made of -- rho - rho0, the
+ * half-force-corrected u and the relaxed shear moments (1 - omega) k4..k8
+ * (eq. "post_collision_central_moments_forcing") -- 36 bytes per cell per
+ * buffer instead of 108.  The stored state is the post-collision state of
+ * the current time t; a step rebuilds the neighbours' post-collision
+ * populations in on-chip memory, streams and collides.  Restrictions:
+ * periodic axes only, no solid mask, no stochastic rounding, no comparison
+ * model; cmlbm_populations and cmlbm_load_populations are not available
+ * (the pre-collision populations are not part of the state), and since the
+ * first collision happens in cmlbm_init, set the force before cmlbm_init. */
+#define CMLBM_MOM32 4
 
 /* per-axis boundary kinds */
 #define CMLBM_PERIODIC 0

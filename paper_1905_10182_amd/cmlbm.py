@@ -13,9 +13,10 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libcmlbm.so")
 
 OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
-FP64, FP32, FP16, BF16 = 0, 1, 2, 3
-STORAGE = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16}
-STORAGE_BYTES = {FP64: 8, FP32: 4, FP16: 2, BF16: 2}
+FP64, FP32, FP16, BF16, MOM32 = 0, 1, 2, 3, 4
+# population storage types, and the moment representation (nine FP32 numbers per cell)
+STORAGE = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16, "mom32": MOM32}
+STORAGE_BYTES = {FP64: 8, FP32: 4, FP16: 2, BF16: 2, MOM32: 4}
 PERIODIC, BOUNCEBACK = 0, 1
 FORCE_NONE, FORCE_UNIFORM, FORCE_BATCH, FORCE_PROFILE_Y, FORCE_FIELD = 0, 1, 2, 3, 4
 FLAG_SOLID, FLAG_RESIDUAL, FLAG_STOCHASTIC, FLAG_FORCE_GUO, FLAG_EQ_SECOND = 1, 2, 4, 8, 16

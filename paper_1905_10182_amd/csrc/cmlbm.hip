@@ -91,6 +91,13 @@ struct storage<CMLBM_BF16> {
     }
 };
 
+// moment representation: nine FP32 planes (rho - rho0, u, (1 - omega) k4..k8)
+template <>
+struct storage<CMLBM_MOM32> {
+    typedef float S;
+    typedef float T;
+};
+
 // Counter-based random bits for stochastic rounding: one hashed 32-bit seed
 // per (cell, step) -- a 32-bit integer finaliser (xor-shift / multiply
 // rounds) -- then an xorshift32 stream, 8 bits per population.
@@ -111,7 +118,8 @@ __device__ __forceinline__ uint32_t xorshift32(uint32_t x)
     return x;
 }
 
-size_t storage_bytes(int st) { return st == CMLBM_FP64 ? 8 : st == CMLBM_FP32 ? 4 : 2; }
+size_t storage_bytes(int st) { return st == CMLBM_FP64 ? 8 : (st == CMLBM_FP32 || st == CMLBM_MOM32) ? 4 : 2; }
+int planes_of(int st) { return st == CMLBM_MOM32 ? 9 : 27; }
 
 // ---------------------------------------------------------------------------
 // geometry passed to every kernel
@@ -450,6 +458,29 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename storage<ST>::S* 
 
 enum InitSrc { INIT_EQ_F64 = 0, INIT_EQ_F32 = 1, INIT_POPS_F64 = 2 };
 
+// Complete 27-Hermite equilibrium (eq. "eq:truncation") in deviation form,
+// e_i = f^eq_i - w_i rho0.  It factors over the axes as
+// w_i rho prod_a (1 + c_a u_a / cs^2 + (c_a^2 - cs^2) u_a^2 / (2 cs^4)), evaluated
+// as w_i [drho P_i + rho0 (P_i - 1)] to keep the deviation small.
+template <typename T>
+__device__ __forceinline__ void feq_dev(T drho, const T u[3], T rho0, T e[27])
+{
+    T am[3][3];  // am[axis][c+1] = P_axis(c) - 1
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const T uu = u[a];
+        am[a][0] = T(-3) * uu + T(3) * uu * uu;
+        am[a][1] = T(-1.5) * uu * uu;
+        am[a][2] = T(3) * uu + T(3) * uu * uu;
+    }
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const T ax = am[0][vel_x(i) + 1], ay = am[1][vel_y(i) + 1], az = am[2][vel_z(i) + 1];
+        const T pm1 = ax + ay + az + ax * ay + ax * az + ay * az + ax * ay * az;
+        e[i] = (T)weight(i) * (drho * (T(1) + pm1) + rho0 * pm1);
+    }
+}
+
 template <int ST, bool MASK, int SRC>
 __global__ __launch_bounds__(kBlock) void k_init(typename storage<ST>::S* __restrict__ dst, Geom g, double rho0,
                                                  const void* __restrict__ rho_in, const void* __restrict__ u_in,
@@ -469,9 +500,7 @@ __global__ __launch_bounds__(kBlock) void k_init(typename storage<ST>::S* __rest
 #pragma unroll
         for (int i = 0; i < 27; ++i) e[i] = (T)(pops[(uint64_t)i * g.ncell + c.lin] - weight(i) * rho0);
     } else {
-        // complete 27-Hermite equilibrium (eq. "eq:truncation"); it factors over
-        // the axes as w_i rho prod_a (1 + c_a u_a / cs^2 + (c_a^2 - cs^2) u_a^2 / (2 cs^4)),
-        // evaluated here as w_i [drho P_i + rho0 (P_i - 1)] to keep the deviation small.
+        // complete 27-Hermite equilibrium
         T drho, u[3];
         if (SRC == INIT_EQ_F64) {
             const double* R = (const double*)rho_in;
@@ -484,20 +513,7 @@ __global__ __launch_bounds__(kBlock) void k_init(typename storage<ST>::S* __rest
             drho = R ? (T)((double)R[c.lin] - rho0) : T(0);
             for (int a = 0; a < 3; ++a) u[a] = U ? (T)U[a * g.ncell + c.lin] : T(0);
         }
-        T am[3][3];  // am[axis][c+1] = P_axis(c) - 1
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const T uu = u[a];
-            am[a][0] = T(-3) * uu + T(3) * uu * uu;
-            am[a][1] = T(-1.5) * uu * uu;
-            am[a][2] = T(3) * uu + T(3) * uu * uu;
-        }
-#pragma unroll
-        for (int i = 0; i < 27; ++i) {
-            const T ax = am[0][vel_x(i) + 1], ay = am[1][vel_y(i) + 1], az = am[2][vel_z(i) + 1];
-            const T pm1 = ax + ay + az + ax * ay + ax * az + ay * az + ax * ay * az;
-            e[i] = (T)weight(i) * (drho * (T(1) + pm1) + (T)rho0 * pm1);
-        }
+        feq_dev<T>(drho, u, (T)rho0, e);
     }
     const Pull p = make_pull(g, c);
 #pragma unroll
@@ -507,6 +523,199 @@ __global__ __launch_bounds__(kBlock) void k_init(typename storage<ST>::S* __rest
         const uint64_t d = bounce ? (uint64_t)opposite(i) * g.pstride + c.own : (uint64_t)i * g.pstride + off;
         dst[d] = SS::pack(e[i]);
     }
+}
+
+// ---------------------------------------------------------------------------
+// moment-representation storage (CMLBM_MOM32)
+//
+// The state is the post-collision state of the current time t, kept as the
+// nine numbers it is made of: m = (rho - rho0, u, s4..s8 = (1 - omega) k4..k8),
+// FP32 planes [9][nb][nz][ny][nxp].  With the force density they determine the
+// post-collision populations (reconstruct()), so a step moves 9 values per
+// cell instead of 27 each way:
+//   reconstruct f*(t) for a tile and a one-cell halo in LDS, pull
+//   f(x, t + 1) = f*(x - c_i, t) from there, collide (pre_collision()) and
+//   store m of t + 1.
+// Workgroup: a 64 x 6 (x, y) tile marching up a chunk of kMomZC planes.  The
+// 66 x 8 halo tile of a plane is reconstructed by 9 waves (waves 0-7 rows
+// 0-7, columns 1-64; wave 8 the two edge columns of the 8 rows), one cell per
+// lane.  LDS keeps populations by their c_z class: c_z = +1 of the two
+// previous planes, c_z = 0 of the current plane, c_z = -1 of the next one, so
+// every plane of the chunk (and the two halo planes) is reconstructed once.
+// Waves 1-6 then collide the 64 x 6 interior cells of the current plane.
+
+constexpr int kMomTX = 64, kMomTY = 6, kMomHX = kMomTX + 2, kMomHY = kMomTY + 2;
+constexpr int kMomZC = 16;                     // planes per workgroup
+constexpr int kMomThreads = 9 * 64;
+constexpr int kMomSlot = 9 * kMomHY * kMomHX;  // floats: one c_z class of one halo plane
+
+__device__ __forceinline__ int mom_lds(int j, int hy, int hx) { return (j * kMomHY + hy) * kMomHX + hx; }
+
+template <bool FIELD>
+__device__ __forceinline__ void mom_force(const Geom& g, uint64_t lin, int b, int y, const float* __restrict__ ftab,
+                                          const float* __restrict__ field, float F[3])
+{
+    if (FIELD) {
+        F[0] = field[lin];
+        F[1] = field[g.ncell + lin];
+        F[2] = field[2 * g.ncell + lin];
+    } else {
+        const float* fr = ftab + 3 * (b * g.ny + y);
+        F[0] = fr[0];
+        F[1] = fr[1];
+        F[2] = fr[2];
+    }
+}
+
+__device__ __forceinline__ void mom_store(float* __restrict__ dst, uint64_t pstride, uint64_t off, float drho,
+                                          float ux, float uy, float uz, const float k[5], float om1)
+{
+    __builtin_nontemporal_store(drho, dst + off);
+    __builtin_nontemporal_store(ux, dst + pstride + off);
+    __builtin_nontemporal_store(uy, dst + 2 * pstride + off);
+    __builtin_nontemporal_store(uz, dst + 3 * pstride + off);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) __builtin_nontemporal_store(om1 * k[j], dst + (4 + j) * pstride + off);
+}
+
+template <bool FIELD>
+__global__ __launch_bounds__(kMomThreads) void k_step_mom(const float* __restrict__ src, float* __restrict__ dst,
+                                                          Geom g, float omega, float rho0,
+                                                          const float* __restrict__ ftab,
+                                                          const float* __restrict__ field)
+{
+    __shared__ float sp[2][kMomSlot];  // c_z = +1 populations, by plane parity
+    __shared__ float s0[kMomSlot];     // c_z = 0 populations of the current plane
+    __shared__ float sm[kMomSlot];     // c_z = -1 populations of the next plane
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int x0 = blockIdx.x * kMomTX, y0 = blockIdx.y * kMomTY;
+    const int nzc = (g.nz + kMomZC - 1) / kMomZC;
+    const int b = blockIdx.z / nzc;
+    const int zs = (blockIdx.z % nzc) * kMomZC;
+    const int ze = zs + kMomZC < g.nz ? zs + kMomZC : g.nz;
+    const int nxi = g.nx - x0 < kMomTX ? g.nx - x0 : kMomTX;
+    const int nyi = g.ny - y0 < kMomTY ? g.ny - y0 : kMomTY;
+    // reconstruction role: halo cell (hy, hx) of the 66 x 8 tile; the right and
+    // bottom halo follow the last interior column / row of a partial tile
+    int hy, hx;
+    bool rec;
+    if (wave < 8) {
+        hy = wave;
+        hx = lane + 1;
+        rec = lane < nxi && hy <= nyi + 1;
+    } else {
+        hy = lane & 7;
+        hx = (lane & 8) ? nxi + 1 : 0;
+        rec = lane < 16 && hy <= nyi + 1;
+    }
+    const int gx = wrap(x0 + hx - 1, g.nx), gy = wrap(y0 + hy - 1, g.ny);
+    // collision role: interior cell (wave, lane + 1), waves 1..6
+    const bool inter = wave >= 1 && wave <= nyi && lane < nxi;
+    const int iy = y0 + wave - 1, ix = x0 + lane;
+    const float om1 = 1.f - omega;
+    auto row_of = [&](int z, int y) -> uint64_t { return ((uint64_t)(b * g.nz + z) * g.ny + y) * g.nxp; };
+    auto lin_of = [&](int z, int y, int x) -> uint64_t { return ((uint64_t)(b * g.nz + z) * g.ny + y) * g.nx + x; };
+
+    float mreg[9], freg[3] = {0.f, 0.f, 0.f};
+    auto load_m = [&](int zu) {
+        if (!rec) return;
+        const int z = wrap(zu, g.nz);
+        const uint64_t o = row_of(z, gy) + gx;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) mreg[k] = src[k * g.pstride + o];
+        if (FIELD) mom_force<true>(g, lin_of(z, gy, gx), b, gy, ftab, field, freg);
+    };
+    float h[27];
+    auto recon = [&]() {
+        float F[3];
+        if (FIELD) {
+            F[0] = freg[0];
+            F[1] = freg[1];
+            F[2] = freg[2];
+        } else {
+            mom_force<false>(g, 0, b, gy, ftab, field, F);
+        }
+        const float sh[5] = {mreg[4], mreg[5], mreg[6], mreg[7], mreg[8]};
+        reconstruct<float>(mreg[0], mreg[1], mreg[2], mreg[3], F[0], F[1], F[2], sh, rho0, h);
+    };
+    auto put = [&](float* slot, int cz) {
+#pragma unroll
+        for (int i = 0; i < 27; ++i)
+            if (vel_z(i) == cz) slot[mom_lds((vel_y(i) + 1) * 3 + vel_x(i) + 1, hy, hx)] = h[i];
+    };
+
+    // prologue: c_z = +1 populations of plane zs - 1, c_z = +1 and 0 of plane zs
+    load_m(zs - 1);
+    if (rec) {
+        recon();
+        put(sp[(zs - 1) & 1], 1);
+    }
+    load_m(zs);
+    if (rec) {
+        recon();
+        put(sp[zs & 1], 1);
+        put(s0, 0);
+    }
+    load_m(zs + 1);
+    for (int z = zs; z < ze; ++z) {
+        // plane z + 1 from the prefetched numbers; then prefetch plane z + 2
+        if (rec) recon();
+        if (z + 2 <= ze) load_m(z + 2);
+        if (rec) put(sm, -1);
+        __syncthreads();
+        if (inter) {
+            float f[27];
+#pragma unroll
+            for (int i = 0; i < 27; ++i) {
+                const int cx = vel_x(i), cy = vel_y(i), cz = vel_z(i);
+                const float* slot = cz > 0 ? sp[(z - 1) & 1] : (cz == 0 ? s0 : sm);
+                f[i] = slot[mom_lds((cy + 1) * 3 + cx + 1, wave - cy, lane + 1 - cx)];
+            }
+            float F[3];
+            mom_force<FIELD>(g, lin_of(z, iy, ix), b, iy, ftab, field, F);
+            float drho, ux, uy, uz, k[5];
+            pre_collision<float>(f, F[0], F[1], F[2], rho0, drho, ux, uy, uz, k);
+            mom_store(dst, g.pstride, row_of(z, iy) + ix, drho, ux, uy, uz, k, om1);
+        }
+        __syncthreads();
+        if (rec) {
+            put(sp[(z + 1) & 1], 1);
+            put(s0, 0);
+        }
+    }
+}
+
+// First collision of a moment-representation state: f(x, 0) = f^eq(rho, u)
+// at every cell, collided in place (cell-local), the nine numbers stored.
+template <int SRC>
+__global__ __launch_bounds__(kBlock) void k_init_mom(float* __restrict__ dst, Geom g, float omega, float rho0,
+                                                     const void* __restrict__ rho_in, const void* __restrict__ u_in,
+                                                     const float* __restrict__ ftab, const float* __restrict__ field)
+{
+    const Cell c = locate(g);
+    if (!c.valid) return;
+    float drho0, u[3];
+    if (SRC == INIT_EQ_F64) {
+        const double* R = (const double*)rho_in;
+        const double* U = (const double*)u_in;
+        drho0 = R ? (float)(R[c.lin] - rho0) : 0.f;
+        for (int a = 0; a < 3; ++a) u[a] = U ? (float)U[a * g.ncell + c.lin] : 0.f;
+    } else {
+        const float* R = (const float*)rho_in;
+        const float* U = (const float*)u_in;
+        drho0 = R ? (float)((double)R[c.lin] - rho0) : 0.f;
+        for (int a = 0; a < 3; ++a) u[a] = U ? U[a * g.ncell + c.lin] : 0.f;
+    }
+    float e[27];
+    feq_dev<float>(drho0, u, rho0, e);
+    float F[3];
+    if (field)
+        mom_force<true>(g, c.lin, c.b, c.y, ftab, field, F);
+    else
+        mom_force<false>(g, c.lin, c.b, c.y, ftab, field, F);
+    float drho, ux, uy, uz, k[5];
+    pre_collision<float>(e, F[0], F[1], F[2], rho0, drho, ux, uy, uz, k);
+    mom_store(dst, g.pstride, c.own, drho, ux, uy, uz, k, 1.f - omega);
 }
 
 // ---------------------------------------------------------------------------
@@ -575,18 +784,24 @@ __global__ __launch_bounds__(kBlock) void k_gather(const typename storage<ST>::S
 {
     const Cell c = locate(g);
     if (!c.valid) return;
-    double h[27];
-    const bool fluid = gather_f64<ST, MASK>(src, g, c, mask, h);
-    if (pops_out) {
-#pragma unroll
-        for (int i = 0; i < 27; ++i) pops_out[(uint64_t)i * g.ncell + c.lin] = fluid ? h[i] + weight(i) * rho0 : 0.0;
-    }
-    if (!rho_out && !u_out) return;
     double rho = rho0, u[3] = {0, 0, 0};
-    if (fluid) {
-        double F[3], j[3], drho;
-        cell_force64(g, c, ftab, field, field_f64, F);
-        macro64(h, rho0, F, rho, u, j, drho);
+    if constexpr (ST == CMLBM_MOM32) {
+        // the stored numbers of the post-collision state are its density and velocity
+        rho = rho0 + (double)src[c.own];
+        for (int a = 0; a < 3; ++a) u[a] = (double)src[(1 + a) * g.pstride + c.own];
+    } else {
+        double h[27];
+        const bool fluid = gather_f64<ST, MASK>(src, g, c, mask, h);
+        if (pops_out) {
+#pragma unroll
+            for (int i = 0; i < 27; ++i) pops_out[(uint64_t)i * g.ncell + c.lin] = fluid ? h[i] + weight(i) * rho0 : 0.0;
+        }
+        if (!rho_out && !u_out) return;
+        if (fluid) {
+            double F[3], j[3], drho;
+            cell_force64(g, c, ftab, field, field_f64, F);
+            macro64(h, rho0, F, rho, u, j, drho);
+        }
     }
     if (out_f64) {
         if (rho_out) ((double*)rho_out)[c.lin] = rho;
@@ -628,11 +843,21 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const typename storage<ST>::S
         c.own = (uint32_t)row * (uint32_t)g.nxp + (uint32_t)x;
         c.lin = (uint64_t)row * g.nx + x;
         c.valid = true;
-        double h[27];
-        if (!gather_f64<ST, MASK>(src, g, c, mask, h)) continue;
         double F[3], rho, u[3], j[3], drho;
-        cell_force64(g, c, ftab, field, field_f64, F);
-        macro64(h, rho0, F, rho, u, j, drho);
+        if constexpr (ST == CMLBM_MOM32) {
+            cell_force64(g, c, ftab, field, field_f64, F);
+            drho = (double)src[c.own];
+            rho = rho0 + drho;
+            for (int a = 0; a < 3; ++a) {
+                u[a] = (double)src[(1 + a) * g.pstride + c.own];
+                j[a] = rho * u[a] - 0.5 * F[a];  // sum_i f_i c_i
+            }
+        } else {
+            double h[27];
+            if (!gather_f64<ST, MASK>(src, g, c, mask, h)) continue;
+            cell_force64(g, c, ftab, field, field_f64, F);
+            macro64(h, rho0, F, rho, u, j, drho);
+        }
         const double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
         const bool finite = isfinite(rho) && isfinite(u2);
         acc[7] += 1.0;
@@ -768,7 +993,10 @@ int validate(const cmlbm_params* p)
     if (p->nx < 1 || p->ny < 1 || p->nz < 1 || p->nbatch < 1) return CMLBM_EINVAL;
     if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return CMLBM_EINVAL;
     if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return CMLBM_EINVAL;
-    if (p->storage < CMLBM_FP64 || p->storage > CMLBM_BF16) return CMLBM_EINVAL;
+    if (p->storage < CMLBM_FP64 || p->storage > CMLBM_MOM32) return CMLBM_EINVAL;
+    if (p->storage == CMLBM_MOM32 && (p->wall[0] || p->wall[1] || p->wall[2] ||
+                                      (p->flags & ~(uint32_t)CMLBM_FLAG_RESIDUAL)))
+        return CMLBM_EINVAL;
     for (int a = 0; a < 3; ++a)
         if (p->wall[a] != CMLBM_PERIODIC && p->wall[a] != CMLBM_BOUNCEBACK) return CMLBM_EINVAL;
     if (p->flags & ~(CMLBM_FLAG_SOLID | CMLBM_FLAG_RESIDUAL | CMLBM_FLAG_STOCHASTIC | CMLBM_FLAG_FORCE_GUO |
@@ -809,7 +1037,7 @@ int make_layout(const cmlbm_params* p, Layout* L)
     const uint64_t nblocks = (uint64_t)g.xblocks * ((rows + g.by - 1) / g.by);
     if (nblocks > 0x7fffffffULL) return CMLBM_EINVAL;
 
-    L->pop_bytes = align256(27 * g.pstride * sb);
+    L->pop_bytes = align256((uint64_t)planes_of(p->storage) * g.pstride * sb);
     L->needs_mask = (p->flags & CMLBM_FLAG_SOLID) || p->wall[0] || p->wall[1] || p->wall[2];
     const uint64_t per = (uint64_t)p->nz * p->ny * p->nx;
     uint64_t gpb = (per + kBlock - 1) / kBlock;
@@ -971,9 +1199,27 @@ int launch_step_st(cmlbm_lattice* lat, hipStream_t s)
     return launch_check(lat, "step");
 }
 
+int launch_step_mom(cmlbm_lattice* lat, hipStream_t s)
+{
+    const Geom& g = lat->g;
+    const int nzc = (g.nz + kMomZC - 1) / kMomZC;
+    const dim3 grid((unsigned)((g.nx + kMomTX - 1) / kMomTX), (unsigned)((g.ny + kMomTY - 1) / kMomTY),
+                    (unsigned)(g.nb * nzc));
+    const float* ftab = (const float*)(lat->scratch + lat->off_ftab32);
+    const float* src = (const float*)lat->pop[lat->cur];
+    float* dst = (float*)lat->pop[1 - lat->cur];
+    const float om = (float)(1.0 / lat->p.tau), r0 = (float)lat->p.rho0;
+    if (lat->force_mode == CMLBM_FORCE_FIELD)
+        k_step_mom<true><<<grid, dim3(kMomThreads), 0, s>>>(src, dst, g, om, r0, ftab, (const float*)lat->field);
+    else
+        k_step_mom<false><<<grid, dim3(kMomThreads), 0, s>>>(src, dst, g, om, r0, ftab, nullptr);
+    return launch_check(lat, "step");
+}
+
 int launch_step(cmlbm_lattice* lat, hipStream_t s)
 {
     switch (lat->p.storage) {
+        case CMLBM_MOM32: return launch_step_mom(lat, s);
         case CMLBM_FP64: return launch_step_st<CMLBM_FP64>(lat, s);
         case CMLBM_FP32: return launch_step_st<CMLBM_FP32>(lat, s);
         case CMLBM_FP16: return launch_step_st<CMLBM_FP16>(lat, s);
@@ -1008,9 +1254,24 @@ int launch_init_st(cmlbm_lattice* lat, int src_kind, const void* rho, const void
     return launch_check(lat, "init");
 }
 
+int launch_init_mom(cmlbm_lattice* lat, int src_kind, const void* rho, const void* u, hipStream_t s)
+{
+    const Geom& g = lat->g;
+    const float* ftab = (const float*)(lat->scratch + lat->off_ftab32);
+    const float* field = lat->force_mode == CMLBM_FORCE_FIELD ? (const float*)lat->field : nullptr;
+    float* dst = (float*)lat->pop[lat->cur];
+    const float om = (float)(1.0 / lat->p.tau), r0 = (float)lat->p.rho0;
+    if (src_kind == INIT_EQ_F64)
+        k_init_mom<INIT_EQ_F64><<<grid_of(g), block_of(g), 0, s>>>(dst, g, om, r0, rho, u, ftab, field);
+    else
+        k_init_mom<INIT_EQ_F32><<<grid_of(g), block_of(g), 0, s>>>(dst, g, om, r0, rho, u, ftab, field);
+    return launch_check(lat, "init");
+}
+
 int launch_init(cmlbm_lattice* lat, int src_kind, const void* rho, const void* u, const double* pops, hipStream_t s)
 {
     switch (lat->p.storage) {
+        case CMLBM_MOM32: return launch_init_mom(lat, src_kind, rho, u, s);
         case CMLBM_FP64: return launch_init_st<CMLBM_FP64>(lat, src_kind, rho, u, pops, s);
         case CMLBM_FP32: return launch_init_st<CMLBM_FP32>(lat, src_kind, rho, u, pops, s);
         case CMLBM_FP16: return launch_init_st<CMLBM_FP16>(lat, src_kind, rho, u, pops, s);
@@ -1047,6 +1308,7 @@ int launch_gather_st(cmlbm_lattice* lat, void* rho, void* u, int out_f64, double
 int launch_gather(cmlbm_lattice* lat, void* rho, void* u, int out_f64, double* pops, hipStream_t s)
 {
     switch (lat->p.storage) {
+        case CMLBM_MOM32: launch_gather_m<CMLBM_MOM32, false>(lat, rho, u, out_f64, pops, s); return launch_check(lat, "gather");
         case CMLBM_FP64: return launch_gather_st<CMLBM_FP64>(lat, rho, u, out_f64, pops, s);
         case CMLBM_FP32: return launch_gather_st<CMLBM_FP32>(lat, rho, u, out_f64, pops, s);
         case CMLBM_FP16: return launch_gather_st<CMLBM_FP16>(lat, rho, u, out_f64, pops, s);
@@ -1078,6 +1340,7 @@ void launch_reduce_st(cmlbm_lattice* lat, int residual, int snapshot, hipStream_
 int launch_reduce(cmlbm_lattice* lat, int residual, int snapshot, hipStream_t s)
 {
     switch (lat->p.storage) {
+        case CMLBM_MOM32: launch_reduce_m<CMLBM_MOM32, false>(lat, residual, snapshot, s); break;
         case CMLBM_FP64: launch_reduce_st<CMLBM_FP64>(lat, residual, snapshot, s); break;
         case CMLBM_FP32: launch_reduce_st<CMLBM_FP32>(lat, residual, snapshot, s); break;
         case CMLBM_FP16: launch_reduce_st<CMLBM_FP16>(lat, residual, snapshot, s); break;
@@ -1240,6 +1503,8 @@ int cmlbm_init(cmlbm_lattice* lat, const void* dev_rho, const void* dev_u, int i
 int cmlbm_load_populations(cmlbm_lattice* lat, const double* dev_in, void* hip_stream)
 {
     if (!lat || !dev_in) return CMLBM_EINVAL;
+    if (lat->p.storage == CMLBM_MOM32)
+        return fail(lat, CMLBM_EINVAL, "moment storage keeps nine numbers per cell: populations cannot be loaded");
     hipStream_t s = (hipStream_t)hip_stream;
     int rc = ensure_mask(lat, s);
     if (rc) return rc;
@@ -1278,6 +1543,8 @@ int cmlbm_moments(cmlbm_lattice* lat, void* dev_rho, void* dev_u, int io_dtype, 
 int cmlbm_populations(cmlbm_lattice* lat, double* dev_out, void* hip_stream)
 {
     if (!lat || !dev_out) return CMLBM_EINVAL;
+    if (lat->p.storage == CMLBM_MOM32)
+        return fail(lat, CMLBM_ESTATE, "moment storage keeps the post-collision state: no pre-collision populations");
     if (!lat->initialized) return fail(lat, CMLBM_ESTATE, "populations before init");
     return launch_gather(lat, nullptr, nullptr, 1, dev_out, (hipStream_t)hip_stream);
 }

@@ -58,15 +58,12 @@ __device__ __forceinline__ void inv1d(T m0, T m1, T m2, T u, T& gm, T& g0, T& gp
     gp = T(0.5) * (even + odd);
 }
 
-// Collide one cell in place.
-//   h[27]   in: pre-collision h_i = f_i - w_i rho0; out: post-collision h*_i
-//   F       force density at the cell
-//   omega   1/tau
-//   rho0    reference density of the shift
-// Outputs the density and the half-force-corrected velocity as well.
+// First half of the collision: density, half-force-corrected velocity
+// (eq. "macroscopic") and the five pre-collision central moments k4..k8
+// (eq. "pre_collision") of the pre-collision h_i = f_i - w_i rho0.
 template <typename T>
-__device__ __forceinline__ void collide(T h[27], T Fx, T Fy, T Fz, T omega, T rho0, T& rho_out, T& ux_out,
-                                        T& uy_out, T& uz_out)
+__device__ __forceinline__ void pre_collision(const T h[27], T Fx, T Fy, T Fz, T rho0, T& drho, T& ux, T& uy, T& uz,
+                                              T k[5])
 {
     // Raw moments of h up to second order, by three 1D sums (x, then y, then z).
     T X[3][3][3];  // X[p][b][c] = sum_a h(a,b,c) a^p
@@ -95,7 +92,7 @@ __device__ __forceinline__ void collide(T h[27], T Fx, T Fy, T Fz, T omega, T rh
         if (r == 1) return Y[p][q][2] - Y[p][q][0];
         return Y[p][q][2] + Y[p][q][0];
     };
-    const T drho = zsum(0, 0, 0);
+    drho = zsum(0, 0, 0);
     const T jx = zsum(1, 0, 0), jy = zsum(0, 1, 0), jz = zsum(0, 0, 1);
     const T Sxx = zsum(2, 0, 0), Syy = zsum(0, 2, 0), Szz = zsum(0, 0, 2);
     const T Sxy = zsum(1, 1, 0), Sxz = zsum(1, 0, 1), Syz = zsum(0, 1, 1);
@@ -103,28 +100,31 @@ __device__ __forceinline__ void collide(T h[27], T Fx, T Fy, T Fz, T omega, T rh
     // Macroscopic variables with the half-force correction (eq. "macroscopic").
     const T rho = rho0 + drho;
     const T inv_rho = T(1) / rho;
-    const T ux = (jx + T(0.5) * Fx) * inv_rho;
-    const T uy = (jy + T(0.5) * Fy) * inv_rho;
-    const T uz = (jz + T(0.5) * Fz) * inv_rho;
-    rho_out = rho;
-    ux_out = ux;
-    uy_out = uy;
-    uz_out = uz;
+    ux = (jx + T(0.5) * Fx) * inv_rho;
+    uy = (jy + T(0.5) * Fy) * inv_rho;
+    uz = (jz + T(0.5) * Fz) * inv_rho;
 
-    // The five pre-collision central moments k4..k8 (eq. "pre_collision"),
-    // from raw moments: sum f (cx-ux)(cy-uy) = Pxy - rho ux uy + (ux Fy + uy Fx)/2,
-    // where the rest state contributes nothing to Pxy or Pxx - Pyy.
-    const T k4 = Sxy - rho * ux * uy + T(0.5) * (ux * Fy + uy * Fx);
-    const T k5 = Sxz - rho * ux * uz + T(0.5) * (ux * Fz + uz * Fx);
-    const T k6 = Syz - rho * uy * uz + T(0.5) * (uy * Fz + uz * Fy);
-    const T k7 = (Sxx - Syy) - rho * (ux * ux - uy * uy) + (ux * Fx - uy * Fy);
-    const T k8 = (Sxx - Szz) - rho * (ux * ux - uz * uz) + (ux * Fx - uz * Fz);
+    // The five pre-collision central moments k4..k8 from raw moments:
+    // sum f (cx-ux)(cy-uy) = Pxy - rho ux uy + (ux Fy + uy Fx)/2, where the
+    // rest state contributes nothing to Pxy or Pxx - Pyy.
+    k[0] = Sxy - rho * ux * uy + T(0.5) * (ux * Fy + uy * Fx);
+    k[1] = Sxz - rho * ux * uz + T(0.5) * (ux * Fz + uz * Fx);
+    k[2] = Syz - rho * uy * uz + T(0.5) * (uy * Fz + uz * Fy);
+    k[3] = (Sxx - Syy) - rho * (ux * ux - uy * uy) + (ux * Fx - uy * Fy);
+    k[4] = (Sxx - Szz) - rho * (ux * ux - uz * uz) + (ux * Fx - uz * Fz);
+}
 
-    // Post-collision central moments (eq. "post_collision_central_moments_forcing")
-    // rewritten on the monomials (cx-ux)^p (cy-uy)^q (cz-uz)^r, minus the central
-    // moments of the rest state rho0 w_i, which factor as rho0 M_p(ux) M_q(uy) M_r(uz)
-    // with M_0 = 1, M_1(u) = -u, M_2(u) = 1/3 + u^2.
-    const T om1 = T(1) - omega;
+// Second half: the post-collision populations h*_i = f*_i - w_i rho0 from
+// the density deviation, the velocity, the force density and the relaxed
+// shear moments s = (1 - omega) k4..k8, i.e. the nineteen non-zero
+// post-collision central moments (eq. "post_collision_central_moments_forcing")
+// and their inverse transform (eq. "system").
+template <typename T>
+__device__ __forceinline__ void reconstruct(T drho, T ux, T uy, T uz, T Fx, T Fy, T Fz, const T s[5], T rho0, T h[27])
+{
+    // Post-collision central moments on the monomials (cx-ux)^p (cy-uy)^q (cz-uz)^r,
+    // minus the central moments of the rest state rho0 w_i, which factor as
+    // rho0 M_p(ux) M_q(uy) M_r(uz) with M_0 = 1, M_1(u) = -u, M_2(u) = 1/3 + u^2.
     const T third = T(1.0 / 3.0);
     const T ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz;
     const T ax = third + ux2, ay = third + uy2, az = third + uz2;
@@ -133,12 +133,12 @@ __device__ __forceinline__ void collide(T h[27], T Fx, T Fy, T Fz, T omega, T rh
     D[1][0][0] = T(0.5) * Fx + rho0 * ux;
     D[0][1][0] = T(0.5) * Fy + rho0 * uy;
     D[0][0][1] = T(0.5) * Fz + rho0 * uz;
-    D[1][1][0] = om1 * k4 - rho0 * ux * uy;
-    D[1][0][1] = om1 * k5 - rho0 * ux * uz;
-    D[0][1][1] = om1 * k6 - rho0 * uy * uz;
-    D[2][0][0] = (om1 * (k7 + k8) + drho) * third - rho0 * ux2;
-    D[0][2][0] = (om1 * (k8 - T(2) * k7) + drho) * third - rho0 * uy2;
-    D[0][0][2] = (om1 * (k7 - T(2) * k8) + drho) * third - rho0 * uz2;
+    D[1][1][0] = s[0] - rho0 * ux * uy;
+    D[1][0][1] = s[1] - rho0 * ux * uz;
+    D[0][1][1] = s[2] - rho0 * uy * uz;
+    D[2][0][0] = (s[3] + s[4] + drho) * third - rho0 * ux2;
+    D[0][2][0] = (s[4] - T(2) * s[3] + drho) * third - rho0 * uy2;
+    D[0][0][2] = (s[3] - T(2) * s[4] + drho) * third - rho0 * uz2;
     const T sixth = T(1.0 / 6.0);
     D[1][2][0] = sixth * Fx + rho0 * ux * ay;
     D[1][0][2] = sixth * Fx + rho0 * ux * az;
@@ -179,6 +179,29 @@ __device__ __forceinline__ void collide(T h[27], T Fx, T Fy, T Fz, T omega, T rh
         for (int c = 0; c < 3; ++c)
             inv1d(B[0][b][c], B[1][b][c], B[2][b][c], ux, h[vel_index(-1, b - 1, c - 1)], h[vel_index(0, b - 1, c - 1)],
                   h[vel_index(1, b - 1, c - 1)]);
+}
+
+// Collide one cell in place.
+//   h[27]   in: pre-collision h_i = f_i - w_i rho0; out: post-collision h*_i
+//   F       force density at the cell
+//   omega   1/tau
+//   rho0    reference density of the shift
+// Outputs the density and the half-force-corrected velocity as well.
+template <typename T>
+__device__ __forceinline__ void collide(T h[27], T Fx, T Fy, T Fz, T omega, T rho0, T& rho_out, T& ux_out,
+                                        T& uy_out, T& uz_out)
+{
+    T drho, ux, uy, uz, k[5];
+    pre_collision(h, Fx, Fy, Fz, rho0, drho, ux, uy, uz, k);
+    rho_out = rho0 + drho;
+    ux_out = ux;
+    uy_out = uy;
+    uz_out = uz;
+    const T om1 = T(1) - omega;
+    T s[5];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) s[j] = om1 * k[j];
+    reconstruct(drho, ux, uy, uz, Fx, Fy, Fz, s, rho0, h);
 }
 
 // Forward 1D central-moment map on {-1, 0, +1} shifted by u:

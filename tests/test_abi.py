@@ -75,7 +75,9 @@ def test_plane_size_limit():
 @pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=0.3), dict(tau=float("nan")), dict(nx=0), dict(ny=-1),
                                 dict(nbatch=0), dict(rho0=0.0), dict(storage=7), dict(wall=(2, 0, 0)),
                                 dict(flags=32), dict(flags=8, storage="fp16"), dict(flags=16, storage="bf16"),
-                                dict(nz=1, wall=(0, 0, 1))])
+                                dict(nz=1, wall=(0, 0, 1)), dict(storage="mom32", wall=(0, 1, 0)),
+                                dict(storage="mom32", flags=1), dict(storage="mom32", flags=4),
+                                dict(storage="mom32", flags=8), dict(storage=5)])
 def test_invalid_params(kw):
     with pytest.raises(B.CmlbmError) as e:
         B.required_bytes(req(**kw))
@@ -132,3 +134,12 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(OSError):
         B.load_library()
+
+
+def test_moment_storage_bytes():
+    """The moment representation keeps nine FP32 planes per buffer."""
+    pop, _ = B.required_bytes(req(nx=64, ny=8, nz=8, storage="mom32"))
+    assert pop == 9 * 8 * 8 * 64 * 4
+    pop32, _ = B.required_bytes(req(nx=64, ny=8, nz=8, storage="fp32"))
+    assert pop32 == 3 * pop
+    B.required_bytes(req(storage="mom32", flags=B.FLAG_RESIDUAL))  # residual snapshots are allowed
