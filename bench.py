@@ -22,7 +22,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-BYTES_PER_CELL = {"fp64": 432, "fp32": 216, "fp16": 108, "bf16": 108}  # 27 reads + 27 writes
+BYTES_PER_CELL = {"fp64": 432, "fp32": 216, "fp16": 108, "bf16": 108,  # 27 reads + 27 writes
+                  "mom32": 72}  # moment representation: 9 FP32 numbers read + 9 written
 # template arguments: storage, cells per lane, solid mask, force field, non-temporal stores, collision model
 STEP_KERNEL = {"fp32": "k_step<1, 1, false, false, true, 0>", "fp16": "k_step<2, 4, false, false, true, 0>",
                "bf16": "k_step<3, 4, false, false, true, 0>", "fp64": "k_step<0, 1, false, false, true, 0>"}
@@ -154,6 +155,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp16", action="store_true")
     ap.add_argument("--no-warmstart", action="store_true")
+    ap.add_argument("--no-mom", action="store_true")
     ap.add_argument("--n", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -185,6 +187,20 @@ def main():
             "hbm_frac": round(r16s["bytes_per_launch"] / r16s["launch_s"] / 1e9 / HBM_PEAK_GBS, 4),
             "speedup_vs_fp32_glups": round(r16s["glups"] / main_run["glups"], 3)}
         print(f"[bench] fp16 stochastic rounding {r16s['glups']:.2f} GLUPS", file=sys.stderr, flush=True)
+    if not args.no_mom:
+        for nm in sorted({args.n, 512 if args.n == 256 else args.n}):
+            print(f"[bench] TGV {nm}^3 moment storage (FP32)", file=sys.stderr, flush=True)
+            rm = run_gpu(nm, "mom32", args.steps if nm == args.n else max(args.steps // 4, 10),
+                         args.warmup if nm == args.n else max(args.warmup // 4, 5))
+            extra[f"moment_storage_{nm}"] = {
+                "workload": f"taylor_green_{nm}, nine FP32 numbers per cell (rho - rho0, u, (1 - omega) k4..k8), "
+                            "neighbour populations rebuilt in LDS",
+                "glups": round(rm["glups"], 3), "ms_per_step": round(rm["ms_per_step"], 4),
+                "bytes_per_cell": BYTES_PER_CELL["mom32"],
+                "hbm_gbs": round(rm["bytes_per_launch"] / rm["launch_s"] / 1e9, 1),
+                "speedup_vs_fp32_populations_256": round(rm["glups"] / main_run["glups"], 3),
+                "mass_drift": rm["mass_drift"]}
+            print(f"[bench] moment storage {nm}^3: {rm['glups']:.2f} GLUPS", file=sys.stderr, flush=True)
     extra["device_copy_gbs"] = round(copy_bandwidth(), 1)
     if not args.no_warmstart:
         print("[bench] warm start: 64 sphere channels 64x32x32, cold vs U-Net init", file=sys.stderr, flush=True)

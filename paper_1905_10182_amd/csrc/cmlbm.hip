@@ -544,12 +544,11 @@ __global__ __launch_bounds__(kBlock) void k_init(typename storage<ST>::S* __rest
 // every plane of the chunk (and the two halo planes) is reconstructed once.
 // Waves 1-6 then collide the 64 x 6 interior cells of the current plane.
 
-constexpr int kMomTX = 64, kMomTY = 6, kMomHX = kMomTX + 2, kMomHY = kMomTY + 2;
-constexpr int kMomZC = 16;                     // planes per workgroup
-constexpr int kMomThreads = 9 * 64;
-constexpr int kMomSlot = 9 * kMomHY * kMomHX;  // floats: one c_z class of one halo plane
+constexpr int kMomTX = 64, kMomHX = kMomTX + 2;
+constexpr int kMomZC = 32;  // planes per workgroup
 
-__device__ __forceinline__ int mom_lds(int j, int hy, int hx) { return (j * kMomHY + hy) * kMomHX + hx; }
+template <int HY>
+__device__ __forceinline__ int mom_lds(int j, int hy, int hx) { return (j * HY + hy) * kMomHX + hx; }
 
 template <bool FIELD>
 __device__ __forceinline__ void mom_force(const Geom& g, uint64_t lin, int b, int y, const float* __restrict__ ftab,
@@ -578,38 +577,42 @@ __device__ __forceinline__ void mom_store(float* __restrict__ dst, uint64_t pstr
     for (int j = 0; j < 5; ++j) __builtin_nontemporal_store(om1 * k[j], dst + (4 + j) * pstride + off);
 }
 
-template <bool FIELD>
-__global__ __launch_bounds__(kMomThreads) void k_step_mom(const float* __restrict__ src, float* __restrict__ dst,
-                                                          Geom g, float omega, float rho0,
-                                                          const float* __restrict__ ftab,
-                                                          const float* __restrict__ field)
+// TY interior rows per tile: TY + 2 halo rows reconstructed by waves 0..TY+1,
+// the two edge columns of those rows by wave TY + 2.
+template <bool FIELD, int TY>
+__global__ __launch_bounds__((TY + 3) * 64) void k_step_mom(const float* __restrict__ src, float* __restrict__ dst,
+                                                            Geom g, float omega, float rho0,
+                                                            const float* __restrict__ ftab,
+                                                            const float* __restrict__ field)
 {
-    __shared__ float sp[2][kMomSlot];  // c_z = +1 populations, by plane parity
-    __shared__ float s0[kMomSlot];     // c_z = 0 populations of the current plane
-    __shared__ float sm[kMomSlot];     // c_z = -1 populations of the next plane
+    constexpr int HY = TY + 2;
+    constexpr int SLOT = 9 * HY * kMomHX;  // floats: one c_z class of one halo plane
+    __shared__ float sp[2][SLOT];          // c_z = +1 populations, by plane parity
+    __shared__ float s0[SLOT];             // c_z = 0 populations of the current plane
+    __shared__ float sm[SLOT];             // c_z = -1 populations of the next plane
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int x0 = blockIdx.x * kMomTX, y0 = blockIdx.y * kMomTY;
+    const int x0 = blockIdx.x * kMomTX, y0 = blockIdx.y * TY;
     const int nzc = (g.nz + kMomZC - 1) / kMomZC;
     const int b = blockIdx.z / nzc;
     const int zs = (blockIdx.z % nzc) * kMomZC;
     const int ze = zs + kMomZC < g.nz ? zs + kMomZC : g.nz;
     const int nxi = g.nx - x0 < kMomTX ? g.nx - x0 : kMomTX;
-    const int nyi = g.ny - y0 < kMomTY ? g.ny - y0 : kMomTY;
-    // reconstruction role: halo cell (hy, hx) of the 66 x 8 tile; the right and
+    const int nyi = g.ny - y0 < TY ? g.ny - y0 : TY;
+    // reconstruction role: halo cell (hy, hx) of the 66 x HY tile; the right and
     // bottom halo follow the last interior column / row of a partial tile
     int hy, hx;
     bool rec;
-    if (wave < 8) {
+    if (wave < HY) {
         hy = wave;
         hx = lane + 1;
         rec = lane < nxi && hy <= nyi + 1;
     } else {
-        hy = lane & 7;
-        hx = (lane & 8) ? nxi + 1 : 0;
-        rec = lane < 16 && hy <= nyi + 1;
+        hy = lane >> 1;
+        hx = (lane & 1) ? nxi + 1 : 0;
+        rec = lane < 2 * HY && hy <= nyi + 1;
     }
     const int gx = wrap(x0 + hx - 1, g.nx), gy = wrap(y0 + hy - 1, g.ny);
-    // collision role: interior cell (wave, lane + 1), waves 1..6
+    // collision role: interior cell (wave, lane + 1), waves 1..TY
     const bool inter = wave >= 1 && wave <= nyi && lane < nxi;
     const int iy = y0 + wave - 1, ix = x0 + lane;
     const float om1 = 1.f - omega;
@@ -641,7 +644,7 @@ __global__ __launch_bounds__(kMomThreads) void k_step_mom(const float* __restric
     auto put = [&](float* slot, int cz) {
 #pragma unroll
         for (int i = 0; i < 27; ++i)
-            if (vel_z(i) == cz) slot[mom_lds((vel_y(i) + 1) * 3 + vel_x(i) + 1, hy, hx)] = h[i];
+            if (vel_z(i) == cz) slot[mom_lds<HY>((vel_y(i) + 1) * 3 + vel_x(i) + 1, hy, hx)] = h[i];
     };
 
     // prologue: c_z = +1 populations of plane zs - 1, c_z = +1 and 0 of plane zs
@@ -669,7 +672,7 @@ __global__ __launch_bounds__(kMomThreads) void k_step_mom(const float* __restric
             for (int i = 0; i < 27; ++i) {
                 const int cx = vel_x(i), cy = vel_y(i), cz = vel_z(i);
                 const float* slot = cz > 0 ? sp[(z - 1) & 1] : (cz == 0 ? s0 : sm);
-                f[i] = slot[mom_lds((cy + 1) * 3 + cx + 1, wave - cy, lane + 1 - cx)];
+                f[i] = slot[mom_lds<HY>((cy + 1) * 3 + cx + 1, wave - cy, lane + 1 - cx)];
             }
             float F[3];
             mom_force<FIELD>(g, lin_of(z, iy, ix), b, iy, ftab, field, F);
@@ -684,6 +687,10 @@ __global__ __launch_bounds__(kMomThreads) void k_step_mom(const float* __restric
         }
     }
 }
+
+// interior tile rows of the moment kernel: 12 when the lattice is tall enough
+// (halo overhead 14/12 in y, one workgroup of 15 waves per CU), else 6
+int mom_rows(const Geom& g) { return g.ny >= 24 ? 12 : 6; }
 
 // First collision of a moment-representation state: f(x, 0) = f^eq(rho, u)
 // at every cell, collided in place (cell-local), the nine numbers stored.
@@ -1199,20 +1206,30 @@ int launch_step_st(cmlbm_lattice* lat, hipStream_t s)
     return launch_check(lat, "step");
 }
 
-int launch_step_mom(cmlbm_lattice* lat, hipStream_t s)
+template <int TY>
+void launch_step_mom_t(cmlbm_lattice* lat, hipStream_t s)
 {
     const Geom& g = lat->g;
     const int nzc = (g.nz + kMomZC - 1) / kMomZC;
-    const dim3 grid((unsigned)((g.nx + kMomTX - 1) / kMomTX), (unsigned)((g.ny + kMomTY - 1) / kMomTY),
+    const dim3 grid((unsigned)((g.nx + kMomTX - 1) / kMomTX), (unsigned)((g.ny + TY - 1) / TY),
                     (unsigned)(g.nb * nzc));
     const float* ftab = (const float*)(lat->scratch + lat->off_ftab32);
     const float* src = (const float*)lat->pop[lat->cur];
     float* dst = (float*)lat->pop[1 - lat->cur];
     const float om = (float)(1.0 / lat->p.tau), r0 = (float)lat->p.rho0;
+    const dim3 block((TY + 3) * 64);
     if (lat->force_mode == CMLBM_FORCE_FIELD)
-        k_step_mom<true><<<grid, dim3(kMomThreads), 0, s>>>(src, dst, g, om, r0, ftab, (const float*)lat->field);
+        k_step_mom<true, TY><<<grid, block, 0, s>>>(src, dst, g, om, r0, ftab, (const float*)lat->field);
     else
-        k_step_mom<false><<<grid, dim3(kMomThreads), 0, s>>>(src, dst, g, om, r0, ftab, nullptr);
+        k_step_mom<false, TY><<<grid, block, 0, s>>>(src, dst, g, om, r0, ftab, nullptr);
+}
+
+int launch_step_mom(cmlbm_lattice* lat, hipStream_t s)
+{
+    if (mom_rows(lat->g) == 12)
+        launch_step_mom_t<12>(lat, s);
+    else
+        launch_step_mom_t<6>(lat, s);
     return launch_check(lat, "step");
 }
 
