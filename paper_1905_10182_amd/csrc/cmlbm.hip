@@ -591,10 +591,19 @@ __global__ __launch_bounds__((TY + 3) * 64) void k_step_mom(const float* __restr
     __shared__ float s0[SLOT];             // c_z = 0 populations of the current plane
     __shared__ float sm[SLOT];             // c_z = -1 populations of the next plane
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int x0 = blockIdx.x * kMomTX, y0 = blockIdx.y * TY;
+    // tiles are numbered x fastest, then y, then (batch member, z chunk);
+    // workgroups are dealt round-robin to the 8 XCDs, so give each XCD a
+    // contiguous run of tiles: neighbours share halo cache lines in one L2
+    const int ntx = (g.nx + kMomTX - 1) / kMomTX, nty = (g.ny + TY - 1) / TY;
     const int nzc = (g.nz + kMomZC - 1) / kMomZC;
-    const int b = blockIdx.z / nzc;
-    const int zs = (blockIdx.z % nzc) * kMomZC;
+    const unsigned total = gridDim.x;
+    unsigned tile = blockIdx.x;
+    if (total % 8 == 0) tile = (tile & 7u) * (total >> 3) + (tile >> 3);
+    const int x0 = (int)(tile % ntx) * kMomTX;
+    const int y0 = (int)((tile / ntx) % nty) * TY;
+    const int bzc = (int)(tile / (ntx * nty));
+    const int b = bzc / nzc;
+    const int zs = (bzc % nzc) * kMomZC;
     const int ze = zs + kMomZC < g.nz ? zs + kMomZC : g.nz;
     const int nxi = g.nx - x0 < kMomTX ? g.nx - x0 : kMomTX;
     const int nyi = g.ny - y0 < TY ? g.ny - y0 : TY;
@@ -1043,6 +1052,10 @@ int make_layout(const cmlbm_params* p, Layout* L)
     g.xblocks = (p->nx + g.bx - 1) / g.bx;
     const uint64_t nblocks = (uint64_t)g.xblocks * ((rows + g.by - 1) / g.by);
     if (nblocks > 0x7fffffffULL) return CMLBM_EINVAL;
+    if (p->storage == CMLBM_MOM32) {  // one-dimensional grid of moment tiles (6-row tiles: the most work-items)
+        const uint64_t tiles = (uint64_t)((p->nx + 63) / 64) * ((p->ny + 5) / 6) * p->nbatch * ((p->nz + 31) / 32);
+        if (tiles * 9 * 64 > 0xffffffffULL) return CMLBM_EINVAL;
+    }
 
     L->pop_bytes = align256((uint64_t)planes_of(p->storage) * g.pstride * sb);
     L->needs_mask = (p->flags & CMLBM_FLAG_SOLID) || p->wall[0] || p->wall[1] || p->wall[2];
@@ -1211,8 +1224,7 @@ void launch_step_mom_t(cmlbm_lattice* lat, hipStream_t s)
 {
     const Geom& g = lat->g;
     const int nzc = (g.nz + kMomZC - 1) / kMomZC;
-    const dim3 grid((unsigned)((g.nx + kMomTX - 1) / kMomTX), (unsigned)((g.ny + TY - 1) / TY),
-                    (unsigned)(g.nb * nzc));
+    const dim3 grid((unsigned)(((g.nx + kMomTX - 1) / kMomTX) * ((g.ny + TY - 1) / TY) * g.nb * nzc));
     const float* ftab = (const float*)(lat->scratch + lat->off_ftab32);
     const float* src = (const float*)lat->pop[lat->cur];
     float* dst = (float*)lat->pop[1 - lat->cur];
