@@ -99,6 +99,9 @@ extern "C" {
  * Neither flag: the method itself (complete equilibrium and forcing, M1). */
 #define CMLBM_FLAG_FORCE_GUO 8u  /* second-order (H1 + H2, Guo et al.) forcing term: M4 */
 #define CMLBM_FLAG_EQ_SECOND 16u /* second-order equilibrium; with CMLBM_FLAG_FORCE_GUO: M5 */
+#define CMLBM_FLAG_BGK 32u       /* stability control: every moment relaxes with omega (single relaxation
+                                    time), with either both flags above (the classical BGK scheme with
+                                    Guo forcing) or neither (the complete equilibrium and forcing) */
 
 /* cmlbm_reduce: `what` bits and the layout of one row of its output */
 #define CMLBM_REDUCE_RESIDUAL 1u /* compare u with the last snapshot */

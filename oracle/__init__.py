@@ -38,6 +38,8 @@ def _load(extended=False):
         lib.orc_forcing_order.argtypes = [_dp, _dp, ctypes.c_int, _dp]
         lib.orc_collide_model.argtypes = [_dp, _dp, _real, ctypes.c_int, ctypes.c_int, _dp]
         lib.orc_collide_model.restype = ctypes.c_int
+        lib.orc_collide_model_bgk.argtypes = [_dp, _dp, _real, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp]
+        lib.orc_collide_model_bgk.restype = ctypes.c_int
         lib.orc_basis.argtypes = [_dp, _dp]
         lib.orc_central_moments.argtypes = [_dp, _dp, _dp]
         lib.orc_macroscopic.argtypes = [_dp, _dp, _dp, _dp]
@@ -117,11 +119,12 @@ def forcing_order(u, F, order):
     return out
 
 
-def collide_model(f, F, omega, eq_order, force_order):
-    """Literal collision with a truncated equilibrium / forcing (the comparison models of Sec. III)."""
+def collide_model(f, F, omega, eq_order, force_order, bgk=False):
+    """Literal collision with a truncated equilibrium / forcing (the comparison models of Sec. III);
+    bgk=True relaxes every central moment with omega (single-relaxation-time control)."""
     out = np.zeros(27)
-    if _load().orc_collide_model(_d(_vec(f, 27)), _d(_vec(F, 3)), float(omega), int(eq_order), int(force_order),
-                                 _d(out)) != 0:
+    if _load().orc_collide_model_bgk(_d(_vec(f, 27)), _d(_vec(F, 3)), float(omega), int(eq_order),
+                                     int(force_order), int(bool(bgk)), _d(out)) != 0:
         raise ArithmeticError("singular central-moment matrix")
     return out
 
@@ -217,8 +220,10 @@ class Lattice:
 
     # closed form and literal route of the method (M1); literal routes of the
     # comparison models M4 (second-order forcing), M5 (second-order equilibrium
-    # and forcing) and a second-order equilibrium with the complete forcing
-    VARIANTS = {"closed": 0, "literal": 1, "m4": 2, "m5": 3, "eq2": 4}
+    # and forcing), a second-order equilibrium with the complete forcing, and
+    # the single-relaxation-time (BGK) controls with the second-order or the
+    # complete equilibrium and forcing
+    VARIANTS = {"closed": 0, "literal": 1, "m4": 2, "m5": 3, "eq2": 4, "bgk": 5, "bgk6": 6}
 
     def __init__(self, nx, ny, nz, nb=1, tau=0.8, wall=(0, 0, 0), solid=None, force=None, extended=False):
         self.extended = bool(extended)

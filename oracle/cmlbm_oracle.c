@@ -360,7 +360,19 @@ int orc_reconstruct_literal(const real u[3], const real k[Q], real f[Q])
 /* Literal collision of a comparison model of Sec. III: the same central-moment
  * relaxation (eq. "eq:relaxationMatrix") with the equilibrium truncated at
  * eq_order and the forcing term at force_order (M1: 6, 6; M4: 6, 2; M5: 2, 2). */
+int orc_collide_model_bgk(const real f[Q], const real F[3], real omega, int eq_order, int force_order, int bgk,
+                          real fstar[Q]);
+
 int orc_collide_model(const real f[Q], const real F[3], real omega, int eq_order, int force_order, real fstar[Q])
+{
+    return orc_collide_model_bgk(f, F, omega, eq_order, force_order, 0, fstar);
+}
+
+/* As orc_collide_model; bgk != 0 relaxes every central moment with omega
+ * (Lambda = omega I, the single-relaxation-time control), which in population
+ * space is f* = f - omega (f - f^eq) + (1 - omega / 2) F. */
+int orc_collide_model_bgk(const real f[Q], const real F[3], real omega, int eq_order, int force_order, int bgk,
+                          real fstar[Q])
 {
     real rho, u[3];
     orc_macroscopic(f, F, &rho, u);
@@ -371,7 +383,7 @@ int orc_collide_model(const real f[Q], const real F[3], real omega, int eq_order
     orc_central_moments(u, feq, keq);
     orc_central_moments(u, ff, R);
     for (int j = 0; j < Q; ++j) {
-        const real L = relax_rate(j, omega);
+        const real L = bgk ? omega : relax_rate(j, omega);
         ks[j] = (1.0 - L) * k[j] + L * keq[j] + (1.0 - 0.5 * L) * R[j];
     }
     return orc_reconstruct_literal(u, ks, fstar);
@@ -387,7 +399,9 @@ int orc_collide_literal(const real f[Q], const real F[3], real omega, real fstar
 /* Collision by variant code: 0 closed form (M1), 1 literal M1, 2 literal M4
  * (second-order forcing), 3 literal M5 (second-order equilibrium and
  * forcing), 4 literal with a second-order equilibrium and the complete
- * forcing.  Returns non-zero on a singular literal solve. */
+ * forcing, 5 BGK with the second-order equilibrium and forcing (the classical
+ * single-relaxation-time scheme with Guo forcing), 6 BGK with the complete
+ * ones.  Returns non-zero on a singular literal solve. */
 static int collide_variant(const real f[Q], const real F[3], real omega, int variant, real fstar[Q])
 {
     switch (variant) {
@@ -395,7 +409,9 @@ static int collide_variant(const real f[Q], const real F[3], real omega, int var
         case 1: return orc_collide_model(f, F, omega, 6, 6, fstar);
         case 2: return orc_collide_model(f, F, omega, 6, 2, fstar);
         case 3: return orc_collide_model(f, F, omega, 2, 2, fstar);
-        default: return orc_collide_model(f, F, omega, 2, 6, fstar);
+        case 4: return orc_collide_model(f, F, omega, 2, 6, fstar);
+        case 5: return orc_collide_model_bgk(f, F, omega, 2, 2, 1, fstar);
+        default: return orc_collide_model_bgk(f, F, omega, 6, 6, 1, fstar);
     }
 }
 

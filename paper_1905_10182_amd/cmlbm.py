@@ -19,9 +19,12 @@ STORAGE = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16, "mom32": MOM3
 STORAGE_BYTES = {FP64: 8, FP32: 4, FP16: 2, BF16: 2, MOM32: 4}
 PERIODIC, BOUNCEBACK = 0, 1
 FORCE_NONE, FORCE_UNIFORM, FORCE_BATCH, FORCE_PROFILE_Y, FORCE_FIELD = 0, 1, 2, 3, 4
-FLAG_SOLID, FLAG_RESIDUAL, FLAG_STOCHASTIC, FLAG_FORCE_GUO, FLAG_EQ_SECOND = 1, 2, 4, 8, 16
-# collision models: the method (M1) and the comparison models of Sec. III
-MODELS = {"m1": 0, "m4": FLAG_FORCE_GUO, "m5": FLAG_FORCE_GUO | FLAG_EQ_SECOND, "eq2": FLAG_EQ_SECOND}
+FLAG_SOLID, FLAG_RESIDUAL, FLAG_STOCHASTIC, FLAG_FORCE_GUO, FLAG_EQ_SECOND, FLAG_BGK = 1, 2, 4, 8, 16, 32
+# collision models: the method (M1), the comparison models of Sec. III, and the
+# single-relaxation-time controls (classical BGK with Guo forcing; BGK with the
+# complete equilibrium and forcing)
+MODELS = {"m1": 0, "m4": FLAG_FORCE_GUO, "m5": FLAG_FORCE_GUO | FLAG_EQ_SECOND, "eq2": FLAG_EQ_SECOND,
+          "bgk": FLAG_BGK | FLAG_FORCE_GUO | FLAG_EQ_SECOND, "bgk6": FLAG_BGK}
 REDUCE_RESIDUAL, REDUCE_SNAPSHOT = 1, 2
 RED = {"mass": 0, "momx": 1, "momy": 2, "momz": 3, "ke": 4, "umax": 5, "nonfinite": 6, "fluid": 7,
        "du2": 8, "u2": 9, "residual": 10}

@@ -35,6 +35,7 @@ constexpr int kNPart = 10;    // partial-sum slots of k_reduce
 // collision model bits of k_step (0: the method's closed-form collision)
 constexpr int kModelGuo = 1;  // second-order forcing term
 constexpr int kModelEq2 = 2;  // second-order equilibrium
+constexpr int kModelBgk = 4;  // single relaxation time
 constexpr int kMaxRedBlocks = 256;  // reduce workgroups per batch member
 constexpr uint32_t kSolidBit = 1u << 27;
 
@@ -407,8 +408,8 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename storage<ST>::S* 
         if constexpr (MODEL == 0)
             collide<T>(h[c], Fx[c], Fy[c], Fz[c], omega, rho0, rho, ux, uy, uz);
         else
-            collide_model<T, (MODEL & kModelEq2) != 0, (MODEL & kModelGuo) != 0>(h[c], Fx[c], Fy[c], Fz[c], omega,
-                                                                                   rho0, rho, ux, uy, uz);
+            collide_model<T, (MODEL & kModelEq2) != 0, (MODEL & kModelGuo) != 0, (MODEL & kModelBgk) != 0>(
+                h[c], Fx[c], Fy[c], Fz[c], omega, rho0, rho, ux, uy, uz);
     }
     const uint32_t bst = (uint32_t)x0 * (uint32_t)sizeof(S);
     if constexpr (sizeof(S) == 2) {
@@ -1016,10 +1017,12 @@ int validate(const cmlbm_params* p)
     for (int a = 0; a < 3; ++a)
         if (p->wall[a] != CMLBM_PERIODIC && p->wall[a] != CMLBM_BOUNCEBACK) return CMLBM_EINVAL;
     if (p->flags & ~(CMLBM_FLAG_SOLID | CMLBM_FLAG_RESIDUAL | CMLBM_FLAG_STOCHASTIC | CMLBM_FLAG_FORCE_GUO |
-                     CMLBM_FLAG_EQ_SECOND))
+                     CMLBM_FLAG_EQ_SECOND | CMLBM_FLAG_BGK))
         return CMLBM_EINVAL;
-    if ((p->flags & (CMLBM_FLAG_FORCE_GUO | CMLBM_FLAG_EQ_SECOND)) && p->storage != CMLBM_FP64 &&
-        p->storage != CMLBM_FP32)
+    const uint32_t model = p->flags & (CMLBM_FLAG_FORCE_GUO | CMLBM_FLAG_EQ_SECOND | CMLBM_FLAG_BGK);
+    if (model && p->storage != CMLBM_FP64 && p->storage != CMLBM_FP32) return CMLBM_EINVAL;
+    if ((model & CMLBM_FLAG_BGK) && model != CMLBM_FLAG_BGK &&
+        model != (CMLBM_FLAG_BGK | CMLBM_FLAG_FORCE_GUO | CMLBM_FLAG_EQ_SECOND))
         return CMLBM_EINVAL;
     // an axis of extent 1 with walls would bounce everything; periodic is required there
     const int dims[3] = {p->nx, p->ny, p->nz};
@@ -1135,7 +1138,8 @@ int step_lanes(const cmlbm_lattice* lat)
 
 int lat_model(const cmlbm_lattice* lat)
 {
-    return ((lat->p.flags & CMLBM_FLAG_FORCE_GUO) ? kModelGuo : 0) | ((lat->p.flags & CMLBM_FLAG_EQ_SECOND) ? kModelEq2 : 0);
+    return ((lat->p.flags & CMLBM_FLAG_FORCE_GUO) ? kModelGuo : 0) | ((lat->p.flags & CMLBM_FLAG_EQ_SECOND) ? kModelEq2 : 0) |
+           ((lat->p.flags & CMLBM_FLAG_BGK) ? kModelBgk : 0);
 }
 
 template <int ST, int V, bool MASK, bool FIELD, int MODEL = 0>
@@ -1183,8 +1187,12 @@ int launch_step_st(cmlbm_lattice* lat, hipStream_t s)
                 launch_step_model<ST, kModelGuo>(lat, s);
             else if (model == kModelEq2)
                 launch_step_model<ST, kModelEq2>(lat, s);
-            else
+            else if (model == (kModelGuo | kModelEq2))
                 launch_step_model<ST, kModelGuo | kModelEq2>(lat, s);
+            else if (model == kModelBgk)
+                launch_step_model<ST, kModelBgk>(lat, s);
+            else
+                launch_step_model<ST, kModelBgk | kModelGuo | kModelEq2>(lat, s);
             return launch_check(lat, "step");
         }
     }

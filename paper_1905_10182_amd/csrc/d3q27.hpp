@@ -242,7 +242,9 @@ __device__ __forceinline__ void central_monomials(const T g[27], T ux, T uy, T u
 // relaxation (omega on k4..k8, 1 on every other moment) with the equilibrium
 // and the forcing term truncated in Hermite order.  EQ2: second-order
 // equilibrium instead of the complete one; GUO: second-order (H1 + H2, Guo)
-// forcing instead of the complete one.  (GUO: M4; EQ2 + GUO: M5.)
+// forcing instead of the complete one.  (GUO: M4; EQ2 + GUO: M5.)  BGK:
+// every moment relaxes with omega instead (the single-relaxation-time
+// stability control), done directly on the populations.
 //
 // The truncated equilibrium and forcing have velocity-dependent central
 // moments, so instead of a closed table this route builds both as
@@ -253,7 +255,7 @@ __device__ __forceinline__ void central_monomials(const T g[27], T ux, T uy, T u
 // with k7 = K200 - K020, k8 = K200 - K002 and the trace K200 + K020 + K002
 // relaxing at rate 1.  Everything is carried minus the rest state's central
 // moments, as in collide().
-template <typename T, bool EQ2, bool GUO>
+template <typename T, bool EQ2, bool GUO, bool BGK>
 __device__ __forceinline__ void collide_model(T h[27], T Fx, T Fy, T Fz, T omega, T rho0, T& rho_out, T& ux_out,
                                               T& uy_out, T& uz_out)
 {
@@ -334,6 +336,13 @@ __device__ __forceinline__ void collide_model(T h[27], T Fx, T Fy, T Fz, T omega
             g[i] = w * (Fx * dx * (T(1) + ay) * (T(1) + az) + Fy * (T(1) + ax) * dy * (T(1) + az) +
                         Fz * (T(1) + ax) * (T(1) + ay) * dz);
         }
+    }
+    if (BGK) {
+        // every moment relaxes with omega: in population space h* = h - omega (h - e) + (1 - omega / 2) g
+        const T hf = T(1) - T(0.5) * omega;
+#pragma unroll
+        for (int i = 0; i < 27; ++i) h[i] = h[i] - omega * (h[i] - e[i]) + hf * g[i];
+        return;
     }
     T De[3][3][3], R[3][3][3];
     central_monomials(e, ux, uy, uz, De);

@@ -3,6 +3,7 @@
     python -m paper_1905_10182_amd.studies precision [--n 512] [--steps 2000] [--every 100]
     python -m paper_1905_10182_amd.studies kolmogorov [--n 384] [--steps 5000] [--every 500]
     python -m paper_1905_10182_amd.studies four-rolls [--storage fp64] [--models m1,m4,m5]
+    python -m paper_1905_10182_amd.studies stability [--n 128] [--steps 4000] [--every 200]
 
 ``precision``: the 3D Taylor-Green vortex (u0 = 0.05, Re = 1600) advanced in
 lockstep with FP64, FP32, FP16 and BF16 population storage (16-bit both with
@@ -22,6 +23,12 @@ u0 = 1e-3), for the method (m1) and optionally the comparison models m4
 (second-order forcing) and m5 (second-order equilibrium and forcing).  Each
 grid starts from the analytic field and runs for three relaxation times of
 the box, 3 / (nu psi^2).
+
+``stability``: the Taylor-Green vortex (u0 = 0.05) at Re = 1600, 10^4 and
+10^5 with the method (m1) and the single-relaxation-time controls (bgk: the
+classical BGK scheme with second-order equilibrium and Guo forcing; bgk6:
+BGK with the complete equilibrium and forcing), FP32 storage: kinetic energy
+at every checkpoint until the run ends or turns non-finite.
 
 All print one JSON object per checkpoint or grid.  Error norms are taken with torch
 on device-resident moments (diagnostics only; the solver runs in libcmlbm).
@@ -133,9 +140,38 @@ def four_rolls_study(ns=(8, 16, 32, 64, 128, 256), u0s=(1e-3, 1e-2), relax=3.0, 
     return rows
 
 
+def stability_study(n=128, res=(1600.0, 1e4, 1e5), models=("m1", "bgk", "bgk6"), steps=4000, every=200,
+                    storage="fp32", out=sys.stdout):
+    rows = []
+    for re in res:
+        wl = workloads.taylor_green(n, re=re, seed=1)
+        for model in models:
+            lat = Lattice(n, n, n, tau=wl["tau"], storage=storage, model=model, device="cuda:0")
+            lat.init(wl["rho"], wl["u"])
+            t, blew = 0, None
+            while True:
+                r = lat.reduce(allow_unstable=True)[0]
+                row = {"study": "stability", "n": n, "re": re, "tau": wl["tau"], "model": model, "step": t,
+                       "ke": float(r[RED["ke"]]), "umax": float(r[RED["umax"]]),
+                       "nonfinite": int(r[RED["nonfinite"]])}
+                print(json.dumps(row), file=out, flush=True)
+                rows.append(row)
+                if row["nonfinite"] > 0 or not row["umax"] < 1.0:
+                    blew = t
+                    break
+                if t >= steps:
+                    break
+                lat.step(every)
+                t += every
+            print(f"[stability] n={n} Re={re:g} {model}: " + (f"blew up by step {blew}" if blew is not None
+                  else f"stable for {steps} steps"), file=sys.stderr, flush=True)
+            del lat
+    return rows
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["precision", "kolmogorov", "four-rolls"])
+    ap.add_argument("study", choices=["precision", "kolmogorov", "four-rolls", "stability"])
     ap.add_argument("--storage", default="fp64")
     ap.add_argument("--models", default="m1", help="comma-separated: m1 (the method), m4, m5, eq2")
     ap.add_argument("--n", type=int)
@@ -147,6 +183,8 @@ def main(argv=None):
         precision_study(**kw)
     elif a.study == "kolmogorov":
         kolmogorov_study(**kw)
+    elif a.study == "stability":
+        stability_study(**kw)
     else:
         four_rolls_study(storage=a.storage, models=tuple(a.models.split(",")))
 

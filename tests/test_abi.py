@@ -74,10 +74,11 @@ def test_plane_size_limit():
 
 @pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=0.3), dict(tau=float("nan")), dict(nx=0), dict(ny=-1),
                                 dict(nbatch=0), dict(rho0=0.0), dict(storage=7), dict(wall=(2, 0, 0)),
-                                dict(flags=32), dict(flags=8, storage="fp16"), dict(flags=16, storage="bf16"),
+                                dict(flags=8, storage="fp16"), dict(flags=16, storage="bf16"),
                                 dict(nz=1, wall=(0, 0, 1)), dict(storage="mom32", wall=(0, 1, 0)),
                                 dict(storage="mom32", flags=1), dict(storage="mom32", flags=4),
-                                dict(storage="mom32", flags=8), dict(storage=5)])
+                                dict(storage="mom32", flags=8), dict(storage=5), dict(flags=32 | 8),
+                                dict(flags=32, storage="fp16"), dict(flags=64)])
 def test_invalid_params(kw):
     with pytest.raises(B.CmlbmError) as e:
         B.required_bytes(req(**kw))

@@ -178,7 +178,7 @@ def test_fp64_kolmogorov_profile_force(torch):
     assert err < 1e-12
 
 
-@pytest.mark.parametrize("model", ["m4", "m5", "eq2"])
+@pytest.mark.parametrize("model", ["m4", "m5", "eq2", "bgk", "bgk6"])
 def test_fp64_comparison_models_random_state(torch, model):
     """The comparison models of Sec. III (truncated equilibrium / forcing,
     same relaxation) against the oracle's literal route of the same model:

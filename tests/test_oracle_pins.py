@@ -549,3 +549,19 @@ def test_comparison_models_conserve_mass_and_add_force(eq_order, force_order):
         np.testing.assert_allclose(C.T @ fs - C.T @ f, F, atol=1e-15)
     # with the complete equilibrium and forcing the model route is the method itself
     np.testing.assert_allclose(O.collide_model(f, F, 1 / 0.7, 6, 6), O.collide_closed(f, F, 1 / 0.7), atol=2e-15)
+
+
+@pytest.mark.parametrize("order", [2, 6])
+def test_bgk_control_is_population_space_bgk(order):
+    """Relaxing every central moment with omega is the population-space BGK
+    collision f* = f - omega (f - f^eq) + (1 - omega / 2) F (T-bar is
+    invertible), with the equilibrium and forcing of the given order."""
+    g = W.generator(34)
+    F = g.uniform(-1e-3, 1e-3, 3)
+    omega = 1 / 0.62
+    for _ in range(5):
+        f = W.random_populations((1,), seed=int(g.integers(1 << 30)))[:, 0]
+        rho = f.sum()
+        u = (C.T @ f + F / 2) / rho
+        ref = f - omega * (f - O.feq_order(rho, u, order)) + (1 - omega / 2) * O.forcing_order(u, F, order)
+        np.testing.assert_allclose(O.collide_model(f, F, omega, order, order, bgk=True), ref, atol=2e-15)
