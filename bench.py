@@ -147,6 +147,40 @@ def cpu_baseline():
             "sample": f"taylor_green {n}^3 fp64, {steps} steps ({s:.1f} s)"}
 
 
+def cpu_detail():
+    """The oracle on the host cores in more detail (not part of the default run):
+    closed-form route at 64^3 and 256^3 with one thread and with all threads,
+    and the literal route (matrix algebra per cell) at 32^3."""
+    import subprocess
+    code = r"""
+import json, os, sys, time
+sys.path.insert(0, %r)
+import oracle, workloads
+def run(n, steps, variant):
+    wl = workloads.taylor_green(n, seed=1)
+    L = oracle.Lattice(n, n, n, tau=wl["tau"])
+    L.init(wl["rho"], wl["u"])
+    L.step(1, variant=variant)
+    t0 = time.perf_counter()
+    L.step(steps, variant=variant)
+    s = time.perf_counter() - t0
+    return {"n": n, "steps": steps, "route": variant, "threads": oracle.num_threads(), "mlups": round(n ** 3 * steps / s / 1e6, 3)}
+for n, steps, v in ((64, 20, "closed"), (256, 3, "closed"), (32, 3, "literal")):
+    print(json.dumps(run(n, steps, v)), flush=True)
+""" % ROOT
+    rows = []
+    for threads in (1, os.cpu_count()):
+        env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+        out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, check=True)
+        rows += [json.loads(l) for l in out.stdout.splitlines() if l.startswith("{")]
+    model = ""
+    try:
+        model = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    return {"cpu_model": model, "cpu_count": os.cpu_count(), "runs": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,8 +190,12 @@ def main():
     ap.add_argument("--no-fp16", action="store_true")
     ap.add_argument("--no-warmstart", action="store_true")
     ap.add_argument("--no-mom", action="store_true")
+    ap.add_argument("--cpu-detail", action="store_true", help="only time the oracle on the host in detail")
     ap.add_argument("--n", type=int, default=256)
     args = ap.parse_args()
+    if args.cpu_detail:
+        print(json.dumps(cpu_detail()), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}): the solver is single-GPU; "
               "a z-slab decomposition over several GPUs is not built.", file=sys.stderr)

@@ -178,3 +178,17 @@ def test_shipped_model_warm_start():
     assert s["prediction_rel_error_u"] < 0.05
     assert s["speedup_steps_warm"] > 1.2
     assert s["warm_vs_cold_final_rel"] < 2e-5
+
+
+def test_warm_and_cold_starts_reach_the_same_state():
+    """Run the shipped network's warm start and the cold start of 4 held-out
+    channels to a residual of 1e-10: the converged velocity fields agree to
+    1e-6 relative (at 1e-8 they agree only to a few 1e-6, the residual times
+    the ~10^3-step relaxation time)."""
+    from paper_1905_10182_amd import warmstart as WS
+
+    log("warm vs cold start to residual 1e-10, 4 channels")
+    s = WS.evaluate(WS.load_model(), first_seed=1_000_100, nb=4, tol=1e-10, max_steps=60000, log=log)
+    log(f"  warm vs cold final {s['warm_vs_cold_final_rel']:.3e}")
+    assert all(r["all_converged"] for r in s["results"].values())
+    assert s["warm_vs_cold_final_rel"] < 1e-6
