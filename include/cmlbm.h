@@ -177,6 +177,17 @@ int cmlbm_step(cmlbm_lattice* lat, int32_t nsteps, void* hip_stream);
  * (either may be NULL), io_dtype CMLBM_FP64 or CMLBM_FP32. */
 int cmlbm_moments(cmlbm_lattice* lat, void* dev_rho, void* dev_u, int io_dtype, void* hip_stream);
 
+/* Shan-Chen pseudo-potential interaction force of the static-droplet test
+ * (Sec. III): field[a][n] = -G psi(x_n) sum_i w_i c_ia psi(x_n + c_i), with
+ * psi = 1 - exp(-rho), from a density field in the cell order of
+ * cmlbm_moments (dev_rho [N], dev_field [3][N], both FP64 for FP64 storage
+ * and FP32 otherwise, device pointers).  Periodic lattices without solids
+ * only.  To drive a step with it, register dev_field once with
+ * cmlbm_set_force(CMLBM_FORCE_FIELD) and refresh it from cmlbm_moments before
+ * every cmlbm_step. */
+int cmlbm_pseudopotential_force(cmlbm_lattice* lat, double G, const void* dev_rho, int io_dtype, void* dev_field,
+                                void* hip_stream);
+
 /* FP64 reductions over fluid cells, one row of CMLBM_NRED doubles per batch
  * member into host_out[nbatch][CMLBM_NRED] (layout CMLBM_RED_*).  The sums
  * use a fixed order, so results are bitwise reproducible.  RESIDUAL and

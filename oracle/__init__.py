@@ -57,6 +57,7 @@ def _load(extended=False):
         lib.orc_lattice_step.restype = ctypes.c_int
         lib.orc_lattice_moments.argtypes = [ctypes.c_int] * 4 + [_u8p, _dp, _dp, _dp, _dp]
         lib.orc_num_threads.restype = ctypes.c_int
+        lib.orc_pseudopotential_force.argtypes = [ctypes.c_int] * 4 + [_real, _dp, _dp]
         lib.orc_collide_cells.argtypes = [ctypes.c_long, _dp, _dp, _real, ctypes.c_int, _dp]
         lib.orc_collide_cells.restype = ctypes.c_int
         _libs[extended] = lib
@@ -117,6 +118,17 @@ def forcing_order(u, F, order):
     out = np.zeros(27)
     _load().orc_forcing_order(_d(_vec(u, 3)), _d(_vec(F, 3)), int(order), _d(out))
     return out
+
+
+def pseudopotential_force(rho, G, extended=False):
+    """Shan-Chen force -G psi(x) sum_i w_i c_i psi(x + c_i), psi = 1 - exp(-rho), periodic;
+    rho (nb, nz, ny, nx) -> F (3, nb, nz, ny, nx)."""
+    dt = np.longdouble if extended else np.float64
+    rho = np.ascontiguousarray(np.asarray(rho, dt))
+    nb, nz, ny, nx = rho.shape
+    F = np.zeros((3,) + rho.shape, dt)
+    _load(extended).orc_pseudopotential_force(nx, ny, nz, nb, dt(G), _d(rho), _d(F))
+    return F
 
 
 def collide_model(f, F, omega, eq_order, force_order, bgk=False):

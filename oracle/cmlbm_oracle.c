@@ -698,6 +698,39 @@ int orc_collide_cells(long n, const real* f, const real* F, real omega, int vari
     return status;
 }
 
+/* Shan-Chen pseudo-potential interaction force of the static-droplet test
+ * (Sec. III): F(x) = -G psi(x) sum_i w_i c_i psi(x + c_i), psi = 1 - exp(-rho),
+ * on a periodic lattice.  rho is [N], F is [3][N]. */
+static real real_exp(real v)
+{
+#ifdef ORC_EXTENDED
+    return expl(v);
+#else
+    return exp(v);
+#endif
+}
+
+void orc_pseudopotential_force(int nx, int ny, int nz, int nb, real G, const real* rho, real* F)
+{
+    grid_t g;
+    const int wall[3] = {0, 0, 0};
+    make_grid(&g, nx, ny, nz, nb, wall, NULL, NULL);
+    const long N = ncells(&g);
+#pragma omp parallel for schedule(static)
+    for (long n = 0; n < N; ++n) {
+        real s[3] = {0, 0, 0};
+        for (int i = 1; i < Q; ++i) {
+            const long m = neighbour(&g, n, i);
+            const real psi = 1.0 - real_exp(-rho[m]);
+            s[0] += weight(i) * CX[i] * psi;
+            s[1] += weight(i) * CY[i] * psi;
+            s[2] += weight(i) * CZ[i] * psi;
+        }
+        const real psi0 = 1.0 - real_exp(-rho[n]);
+        for (int a = 0; a < 3; ++a) F[a * N + n] = -G * psi0 * s[a];
+    }
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

@@ -34,7 +34,7 @@ NRED = 11
 EXPORTS = ["cmlbm_required_bytes", "cmlbm_create", "cmlbm_set_solid", "cmlbm_set_force", "cmlbm_init",
            "cmlbm_step", "cmlbm_moments", "cmlbm_reduce", "cmlbm_populations", "cmlbm_load_populations",
            "cmlbm_save_state", "cmlbm_restore_state", "cmlbm_get_time", "cmlbm_set_time", "cmlbm_destroy",
-           "cmlbm_last_error", "cmlbm_status_string"]
+           "cmlbm_last_error", "cmlbm_status_string", "cmlbm_pseudopotential_force"]
 
 
 class Params(ctypes.Structure):
@@ -70,6 +70,7 @@ def load_library():
     lib.cmlbm_step.argtypes = [vp, i32, vp]
     lib.cmlbm_moments.argtypes = [vp, vp, vp, ctypes.c_int, vp]
     lib.cmlbm_reduce.argtypes = [vp, u32, ctypes.POINTER(ctypes.c_double), vp]
+    lib.cmlbm_pseudopotential_force.argtypes = [vp, ctypes.c_double, vp, ctypes.c_int, vp, vp]
     lib.cmlbm_populations.argtypes = [vp, dp, vp]
     lib.cmlbm_load_populations.argtypes = [vp, dp, vp]
     lib.cmlbm_save_state.argtypes = [vp, vp, sz, vp]
@@ -256,6 +257,20 @@ class Lattice:
                     "restore_state")
         if t is not None:
             self.time = t
+
+    def pseudopotential_force(self, G, rho, out=None):
+        """Shan-Chen force -G psi sum_i w_i c_i psi(x + c_i), psi = 1 - exp(-rho), from a
+        device density field (as returned by moments(); FP64 for FP64 storage, FP32
+        otherwise); returns (or fills) the force field (3, nbatch, nz, ny, nx)."""
+        dt = self.torch.float64 if self.storage == FP64 else self.torch.float32
+        io = FP64 if self.storage == FP64 else FP32
+        r = self._dev(rho, dt, self.shape)
+        if out is None:
+            out = self.torch.empty((3,) + self.shape, dtype=dt, device=self.device)
+        assert out.dtype == dt and out.is_contiguous() and tuple(out.shape) == (3,) + self.shape
+        self._check(self.lib.cmlbm_pseudopotential_force(self.handle, float(G), _ptr(r), io, _ptr(out),
+                                                         self._stream()), "pseudopotential_force")
+        return out
 
     def reduce(self, residual=False, snapshot=False, allow_unstable=False):
         """FP64 reductions, numpy array (nbatch, NRED) laid out as RED."""

@@ -736,6 +736,34 @@ __global__ __launch_bounds__(kBlock) void k_init_mom(float* __restrict__ dst, Ge
 }
 
 // ---------------------------------------------------------------------------
+// Shan-Chen pseudo-potential force (static-droplet test of Sec. III):
+// F(x) = -G psi(x) sum_i w_i c_i psi(x + c_i), psi = 1 - exp(-rho), periodic.
+// rho [N] and F [3][N] in the unpadded cell order of cmlbm_moments.
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pseudopotential(Geom g, T G, const T* __restrict__ rho, T* __restrict__ F)
+{
+    const Cell c = locate(g);
+    if (!c.valid) return;
+    T s[3] = {T(0), T(0), T(0)};
+    const uint64_t plane = (uint64_t)g.nx * g.ny;
+    const uint64_t base = (uint64_t)c.b * g.nz * plane;
+#pragma unroll
+    for (int i = 1; i < 27; ++i) {
+        const int x = wrap(c.x + vel_x(i), g.nx), y = wrap(c.y + vel_y(i), g.ny), z = wrap(c.z + vel_z(i), g.nz);
+        const T r = rho[base + (uint64_t)z * plane + (uint64_t)y * g.nx + x];
+        const T psi = T(1) - exp(-r);
+        const T w = T(weight(i));
+        s[0] += w * T(vel_x(i)) * psi;
+        s[1] += w * T(vel_y(i)) * psi;
+        s[2] += w * T(vel_z(i)) * psi;
+    }
+    const T psi0 = T(1) - exp(-rho[c.lin]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) F[a * g.ncell + c.lin] = -G * psi0 * s[a];
+}
+
+// ---------------------------------------------------------------------------
 // diagnostics: gather in FP64
 
 template <int ST, bool MASK>
@@ -1584,6 +1612,25 @@ int cmlbm_populations(cmlbm_lattice* lat, double* dev_out, void* hip_stream)
         return fail(lat, CMLBM_ESTATE, "moment storage keeps the post-collision state: no pre-collision populations");
     if (!lat->initialized) return fail(lat, CMLBM_ESTATE, "populations before init");
     return launch_gather(lat, nullptr, nullptr, 1, dev_out, (hipStream_t)hip_stream);
+}
+
+int cmlbm_pseudopotential_force(cmlbm_lattice* lat, double G, const void* dev_rho, int io_dtype, void* dev_field,
+                                void* hip_stream)
+{
+    if (!lat || !dev_rho || !dev_field || !std::isfinite(G)) return CMLBM_EINVAL;
+    if (lat->p.wall[0] || lat->p.wall[1] || lat->p.wall[2] || (lat->p.flags & CMLBM_FLAG_SOLID))
+        return fail(lat, CMLBM_EINVAL, "the pseudo-potential force needs a periodic lattice without solids");
+    const int need = lat->p.storage == CMLBM_FP64 ? CMLBM_FP64 : CMLBM_FP32;
+    if (io_dtype != need)
+        return fail(lat, CMLBM_EINVAL, "pseudo-potential dtype must be FP64 for FP64 storage, FP32 otherwise");
+    const Geom& g = lat->g;
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (need == CMLBM_FP64)
+        k_pseudopotential<double><<<grid_of(g), block_of(g), 0, s>>>(g, G, (const double*)dev_rho, (double*)dev_field);
+    else
+        k_pseudopotential<float><<<grid_of(g), block_of(g), 0, s>>>(g, (float)G, (const float*)dev_rho,
+                                                                   (float*)dev_field);
+    return launch_check(lat, "pseudo-potential force");
 }
 
 int cmlbm_reduce(cmlbm_lattice* lat, uint32_t what, double* host_out, void* hip_stream)

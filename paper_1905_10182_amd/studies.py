@@ -4,6 +4,7 @@
     python -m paper_1905_10182_amd.studies kolmogorov [--n 384] [--steps 5000] [--every 500]
     python -m paper_1905_10182_amd.studies four-rolls [--storage fp64] [--models m1,m4,m5]
     python -m paper_1905_10182_amd.studies stability [--n 128] [--steps 4000] [--every 200]
+    python -m paper_1905_10182_amd.studies droplet [--n 200] [--steps 3000]
 
 ``precision``: the 3D Taylor-Green vortex (u0 = 0.05, Re = 1600) advanced in
 lockstep with FP64, FP32, FP16 and BF16 population storage (16-bit both with
@@ -30,6 +31,12 @@ classical BGK scheme with second-order equilibrium and Guo forcing; bgk6:
 BGK with the complete equilibrium and forcing), FP32 storage: kinetic energy
 at every checkpoint until the run ends or turns non-finite.
 
+``droplet``: the static droplet of the pseudo-potential test (Shan-Chen force,
+G = -6, 200^3, radius 40, tau = 2, tanh interface of width 8) with the
+method (m1) and the comparison
+models m4 and m5: mean kinetic energy over time, the force refreshed from the
+density before every step (cmlbm_pseudopotential_force).
+
 All print one JSON object per checkpoint or grid.  Error norms are taken with torch
 on device-resident moments (diagnostics only; the solver runs in libcmlbm).
 """
@@ -37,6 +44,8 @@ import argparse
 import json
 import sys
 import time
+
+import numpy as np
 
 import workloads
 from paper_1905_10182_amd.cmlbm import RED, Lattice
@@ -169,9 +178,53 @@ def stability_study(n=128, res=(1600.0, 1e4, 1e5), models=("m1", "bgk", "bgk6"),
     return rows
 
 
+def droplet_run(lat, wl, steps, out=sys.stdout, label="", every=lambda t: 10 if t < 500 else 50):
+    """Advance a pseudo-potential lattice, refreshing the force field from the
+    density before every step; report the mean kinetic energy at checkpoints.
+    Returns (rows, step of blow-up or None)."""
+    import torch
+
+    dt = torch.float64 if lat.storage == 0 else torch.float32
+    field = torch.zeros((3,) + lat.shape, dtype=dt, device=lat.device)
+    lat.set_force("field", field=field)
+    lat.init(wl["rho"], wl["u"])
+    n = float(np.prod(lat.shape))
+    rows, t, nxt = [], 0, 0
+    while True:
+        rho = lat.moments(dtype=dt)[0]
+        lat.pseudopotential_force(wl["g"], rho, out=field)
+        if t == nxt:
+            r = lat.reduce(allow_unstable=True)[0]
+            row = {"study": "droplet", "label": label, "step": t, "ke_mean": float(r[RED["ke"]]) / n,
+                   "umax": float(r[RED["umax"]]), "nonfinite": int(r[RED["nonfinite"]])}
+            print(json.dumps(row), file=out, flush=True)
+            rows.append(row)
+            if row["nonfinite"] > 0 or not row["umax"] < 1.0:
+                return rows, t
+            nxt = t + every(t)
+        if t >= steps:
+            return rows, None
+        lat.step(1)
+        t += 1
+
+
+def droplet_study(n=200, radius=40.0, models=("m1", "m4", "m5"), steps=3000, storage="fp64", out=sys.stdout):
+    res = {}
+    for model in models:
+        wl = workloads.static_droplet(n, radius)
+        lat = Lattice(n, n, n, tau=wl["tau"], storage=storage, model=model, device="cuda:0")
+        rows, blew = droplet_run(lat, wl, steps, out=out, label=model)
+        res[model] = (rows, blew)
+        peak = max(r["ke_mean"] for r in rows if r["nonfinite"] == 0)
+        print(f"[droplet] {model}: " + (f"non-finite by step {blew}" if blew is not None else f"stable to {steps}")
+              + f", peak mean KE {peak:.3e}, final {rows[-1]['ke_mean']:.3e}", file=sys.stderr, flush=True)
+        del lat
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["precision", "kolmogorov", "four-rolls", "stability"])
+    ap.add_argument("study", choices=["precision", "kolmogorov", "four-rolls", "stability", "droplet"])
     ap.add_argument("--storage", default="fp64")
     ap.add_argument("--models", default="m1", help="comma-separated: m1 (the method), m4, m5, eq2")
     ap.add_argument("--n", type=int)
@@ -185,6 +238,8 @@ def main(argv=None):
         kolmogorov_study(**kw)
     elif a.study == "stability":
         stability_study(**kw)
+    elif a.study == "droplet":
+        droplet_study(storage=a.storage, **{k: v for k, v in kw.items() if k in ("n", "steps")})
     else:
         four_rolls_study(storage=a.storage, models=tuple(a.models.split(",")))
 

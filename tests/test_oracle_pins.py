@@ -565,3 +565,27 @@ def test_bgk_control_is_population_space_bgk(order):
         u = (C.T @ f + F / 2) / rho
         ref = f - omega * (f - O.feq_order(rho, u, order)) + (1 - omega / 2) * O.forcing_order(u, F, order)
         np.testing.assert_allclose(O.collide_model(f, F, omega, order, order, bgk=True), ref, atol=2e-15)
+
+
+# ---------------------------------------------------------------------------
+# Shan-Chen pseudo-potential force of the static-droplet test (Sec. III)
+
+def test_pseudopotential_force_properties():
+    """Uniform density: no force.  Any density: the forces sum to zero (each
+    pair interaction appears with both signs, Newton's third law).  Density
+    varying along x only: the 27-velocity sum collapses to the 1D weights
+    (1/6 for c_x = +-1), F_x = -G psi(x) (psi(x+1) - psi(x-1)) / 6 and
+    F_y = F_z = 0."""
+    G = -6.0
+    assert np.abs(O.pseudopotential_force(np.full((1, 4, 5, 6), 0.7), G)).max() < 1e-15
+    rho = W.generator(35).uniform(0.1, 2.0, size=(2, 5, 6, 7))
+    F = O.pseudopotential_force(rho, G)
+    assert np.abs(F.sum(axis=(1, 2, 3, 4))).max() < 1e-12
+    x = np.arange(12)
+    r1 = 1.0 + 0.5 * np.sin(2 * np.pi * x / 12) + 0.2 * np.cos(4 * np.pi * x / 12)
+    rho = np.broadcast_to(r1, (1, 3, 4, 12)).copy()
+    F = O.pseudopotential_force(rho, G)
+    psi = 1 - np.exp(-r1)
+    fx = -G * psi * (np.roll(psi, -1) - np.roll(psi, 1)) / 6
+    np.testing.assert_allclose(F[0][0, 1, 2], fx, atol=1e-15)
+    assert np.abs(F[1:]).max() < 1e-15

@@ -96,6 +96,26 @@ def four_rolls_mill(n, u0=1e-3, re=100.0):
                 t_relax=1.0 / (nu * psi * psi))
 
 
+def static_droplet(n=200, radius=40.0, rho_in=1.0, rho_out=0.125, g=-6.0, tau=2.0, width=8.0):
+    """Static droplet of the pseudo-potential test (Sec. III): a periodic n^3 box,
+    a sphere of radius `radius` about the box centre at density rho_in in a
+    vapour at rho_out = rho_in / 8, at rest; Shan-Chen interaction strength g.
+    The paper states neither the radius, the relaxation time nor the interface
+    profile; this workload uses radius n / 5, tau = 2 and a tanh interface
+    rho(r) = (rho_in + rho_out) / 2 - (rho_in - rho_out) / 2 tanh(2 (r - R) / width)
+    (width = 0: a sharp step, cells with r <= R inside)."""
+    c = (np.arange(n) - (n - 1) / 2.0) ** 2
+    r = np.sqrt(c[:, None, None] + c[None, :, None] + c[None, None, :])
+    if width > 0:
+        rho = 0.5 * (rho_in + rho_out) - 0.5 * (rho_in - rho_out) * np.tanh(2.0 * (r - radius) / width)
+    else:
+        rho = np.where(r <= radius, rho_in, rho_out)
+    rho = rho[None].astype(np.float64)
+    shape = (1, n, n, n)
+    return dict(name=f"static_droplet_{n}_r{radius:g}", shape=shape, tau=tau, rho0=1.0, wall=(0, 0, 0), rho=rho,
+                u=np.zeros((3,) + shape), g=g, radius=radius)
+
+
 def sphere_channels(nb, nx=64, ny=32, nz=32, seed=1000, rmin=3.0, rmax=8.0, nmin=1, nmax=4, fmin=1e-6, fmax=1e-5,
                     tau=0.8):
     """Batch of nb forced channels (periodic x, z; walls in y) with 1-4 solid
