@@ -1,4 +1,5 @@
-"""Compile the FP64 CPU oracle (test infrastructure) into oracle/liboracle.so.
+"""Compile the FP64 CPU oracle (test infrastructure) into oracle/liboracle.so
+(the D3Q27 model and the D2Q9 model of App. B).
 
 Plain gcc, OpenMP, no fused multiply-add contraction, no fast-math: the oracle
 rounds every operation as written.  Built for x86-64-v3 (AVX2/FMA class hosts)
@@ -9,7 +10,8 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "cmlbm_oracle.c")
+SRCS = [os.path.join(HERE, "cmlbm_oracle.c"),  # D3Q27 model of Sec. II
+        os.path.join(HERE, "d2q9_oracle.c")]   # D2Q9 model of App. B
 LIB = os.path.join(HERE, "liboracle.so")
 LIB_EXT = os.path.join(HERE, "liboracle_ext.so")  # same source in 80-bit long double
 
@@ -18,10 +20,10 @@ CFLAGS = ["-O3", "-march=x86-64-v3", "-fopenmp", "-ffp-contract=off", "-fno-fast
 
 
 def build_one(lib, defines, force):
-    if not force and os.path.exists(lib) and os.path.getmtime(lib) >= os.path.getmtime(SRC):
+    if not force and os.path.exists(lib) and os.path.getmtime(lib) >= max(os.path.getmtime(s) for s in SRCS):
         return lib
     tmp = lib + ".tmp"
-    subprocess.run(["gcc", *CFLAGS, *defines, "-o", tmp, SRC, "-lm"], check=True)
+    subprocess.run(["gcc", *CFLAGS, *defines, "-o", tmp, *SRCS, "-lm"], check=True)
     os.replace(tmp, lib)
     return lib
 

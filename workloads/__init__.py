@@ -96,6 +96,20 @@ def four_rolls_mill(n, u0=1e-3, re=100.0):
                 t_relax=1.0 / (nu * psi * psi))
 
 
+def four_rolls_mill_2d(n, u0=1e-3, re=100.0):
+    """The four-rolls mill above on a genuinely two-dimensional n x n lattice
+    (the D2Q9 model of App. B): the same force and steady state with the z
+    axis dropped; arrays have the shape (ny, nx) = (n, n), vectors (2, n, n)."""
+    wl = four_rolls_mill(n, u0, re)
+    wl = dict(wl)
+    wl["name"] = f"four_rolls_mill_2d_{n}"
+    wl["shape"] = (n, n)
+    wl["force"] = np.ascontiguousarray(wl["force"][:2, 0, 0])
+    wl["u_exact"] = np.ascontiguousarray(wl["u_exact"][:2, 0, 0])
+    del wl["wall"]
+    return wl
+
+
 def static_droplet(n=200, radius=40.0, rho_in=1.0, rho_out=0.125, g=-6.0, tau=2.0, width=8.0):
     """Static droplet of the pseudo-potential test (Sec. III): a periodic n^3 box,
     a sphere of radius `radius` about the box centre at density rho_in in a
@@ -150,10 +164,11 @@ def sphere_channels(nb, nx=64, ny=32, nz=32, seed=1000, rmin=3.0, rmax=8.0, nmin
                 wall=(0, 1, 0), solid=solid, fx=fx, spheres=spheres)
 
 
-def random_populations(shape, seed, lo=0.8, hi=1.2):
-    """Positive populations f_i = U(lo, hi) / 27, array (27,) + shape: an
-    arbitrary (non-equilibrium) pre-collision state for parity tests."""
-    return generator(seed).uniform(lo, hi, size=(27,) + tuple(shape)) / 27.0
+def random_populations(shape, seed, lo=0.8, hi=1.2, q=27):
+    """Positive populations f_i = U(lo, hi) / q, array (q,) + shape: an
+    arbitrary (non-equilibrium) pre-collision state for parity tests (q = 27
+    for D3Q27, 9 for D2Q9)."""
+    return generator(seed).uniform(lo, hi, size=(q,) + tuple(shape)) / float(q)
 
 
 def random_cells(n, seed, umax=0.1, rho_lo=0.9, rho_hi=1.1):
