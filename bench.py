@@ -88,6 +88,38 @@ def run_gpu(n, storage, steps, warmup, stochastic=False):
                 umax=float(r1[0, 5]))
 
 
+# D2Q9 (App. B model): nine populations read + nine written, plus the force
+# field (two components) read, per cell
+BYTES_PER_CELL_2D = {"fp64": 144 + 16, "fp32": 72 + 8, "fp16": 36 + 8, "bf16": 36 + 8}
+STEP_KERNEL_2D = {"fp64": "k2_step<0, 1, true>", "fp32": "k2_step<1, 2, true>", "fp16": "k2_step<2, 4, true>",
+                  "bf16": "k2_step<3, 4, true>"}
+
+
+def run_gpu_2d(n, storage, steps, warmup):
+    """The four-rolls mill (App. B model, per-cell force field) on an n x n lattice."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1905_10182_amd.cmlbm2d import Lattice2D
+
+    wl = workloads.four_rolls_mill_2d(n, dtype=np.float32)
+    lat = Lattice2D(n, n, tau=wl["tau"], storage=storage, device="cuda:0")
+    lat.set_force("field", field=wl["force"])
+    lat.init(np.ones(1, np.float32), wl["u_exact"], dtype=torch.float32)
+    del wl
+    secs, wall = time_steps(lat, steps, warmup)
+    rho, u = lat.moments()
+    finite = bool(torch.isfinite(u).all()) and bool(torch.isfinite(rho).all())
+    assert finite, "non-finite state"
+    mass_drift = abs(float(rho.sum()) / (n * n) - 1)
+    del rho, u, lat
+    torch.cuda.empty_cache()
+    ncell = n * n
+    return dict(secs=secs, wall=wall, glups=ncell * steps / secs / 1e9, ms_per_step=secs / steps * 1e3,
+                launch_s=secs / steps, bytes_per_launch=BYTES_PER_CELL_2D[storage] * ncell, mass_drift=mass_drift)
+
+
 def copy_bandwidth():
     import torch
     n = 1 << 30  # 4 GiB of float32
@@ -190,6 +222,7 @@ def main():
     ap.add_argument("--no-fp16", action="store_true")
     ap.add_argument("--no-warmstart", action="store_true")
     ap.add_argument("--no-mom", action="store_true")
+    ap.add_argument("--no-d2q9", action="store_true")
     ap.add_argument("--cpu-detail", action="store_true", help="only time the oracle on the host in detail")
     ap.add_argument("--n", type=int, default=256)
     args = ap.parse_args()
@@ -239,6 +272,20 @@ def main():
                 "speedup_vs_fp32_populations_256": round(rm["glups"] / main_run["glups"], 3),
                 "mass_drift": rm["mass_drift"]}
             print(f"[bench] moment storage {nm}^3: {rm['glups']:.2f} GLUPS", file=sys.stderr, flush=True)
+    if not args.no_d2q9:
+        n2 = 8192
+        res2 = {}
+        for st in ("fp32", "fp16", "fp64"):
+            print(f"[bench] D2Q9 four-rolls mill {n2}^2 {st}", file=sys.stderr, flush=True)
+            r2 = run_gpu_2d(n2, st, max(args.steps // 2, 10), max(args.warmup // 2, 5))
+            bw = r2["bytes_per_launch"] / r2["launch_s"] / 1e9
+            res2[st] = {"glups": round(r2["glups"], 3), "ms_per_step": round(r2["ms_per_step"], 4),
+                        "kernel": STEP_KERNEL_2D[st], "bytes_per_cell": BYTES_PER_CELL_2D[st],
+                        "hbm_gbs": round(bw, 1), "hbm_frac": round(bw / HBM_PEAK_GBS, 4),
+                        "mass_drift": r2["mass_drift"]}
+            print(f"[bench] D2Q9 {st} {r2['glups']:.2f} GLUPS", file=sys.stderr, flush=True)
+        extra["d2q9"] = {"workload": f"four_rolls_mill_2d_{n2} (App. B model, Re 100, u0 1e-3, per-cell force field)",
+                         **res2}
     extra["device_copy_gbs"] = round(copy_bandwidth(), 1)
     if not args.no_warmstart:
         print("[bench] warm start: 64 sphere channels 64x32x32, cold vs U-Net init", file=sys.stderr, flush=True)

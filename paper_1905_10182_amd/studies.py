@@ -2,7 +2,7 @@
 
     python -m paper_1905_10182_amd.studies precision [--n 512] [--steps 2000] [--every 100]
     python -m paper_1905_10182_amd.studies kolmogorov [--n 384] [--steps 5000] [--every 500]
-    python -m paper_1905_10182_amd.studies four-rolls [--storage fp64] [--models m1,m4,m5]
+    python -m paper_1905_10182_amd.studies four-rolls [--storage fp64] [--models m1,m4,m5] [--lattice d2q9]
     python -m paper_1905_10182_amd.studies stability [--n 128] [--steps 4000] [--every 200]
     python -m paper_1905_10182_amd.studies droplet [--n 200] [--steps 3000]
 
@@ -23,7 +23,8 @@ observed order between successive grids (the paper prints 1.998 for
 u0 = 1e-3), for the method (m1) and optionally the comparison models m4
 (second-order forcing) and m5 (second-order equilibrium and forcing).  Each
 grid starts from the analytic field and runs for three relaxation times of
-the box, 3 / (nu psi^2).
+the box, 3 / (nu psi^2).  ``--lattice d2q9`` runs the same study on the
+two-dimensional D2Q9 model of App. B (libcmlbm2d, the method only).
 
 ``stability``: the Taylor-Green vortex (u0 = 0.05) at Re = 1600, 10^4 and
 10^5 with the method (m1) and the single-relaxation-time controls (bgk: the
@@ -49,6 +50,7 @@ import numpy as np
 
 import workloads
 from paper_1905_10182_amd.cmlbm import RED, Lattice
+from paper_1905_10182_amd.cmlbm2d import Lattice2D
 
 
 def _rel(a, b, torch):
@@ -149,6 +151,38 @@ def four_rolls_study(ns=(8, 16, 32, 64, 128, 256), u0s=(1e-3, 1e-2), relax=3.0, 
     return rows
 
 
+def four_rolls_study_2d(ns=(8, 16, 32, 64, 128, 256), u0s=(1e-3, 1e-2), relax=3.0, storage="fp64",
+                        out=sys.stdout):
+    import math
+
+    import torch
+
+    rows = []
+    for u0 in u0s:
+        prev = None
+        for n in ns:
+            wl = workloads.four_rolls_mill_2d(n, u0=u0)
+            lat = Lattice2D(n, n, tau=wl["tau"], storage=storage, device="cuda:0")
+            lat.set_force("field", field=wl["force"])
+            lat.init(np.ones(wl["shape"]), wl["u_exact"])
+            steps = int(relax * wl["t_relax"])
+            t0 = time.perf_counter()
+            lat.step(steps)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            u = lat.moments()[1].double().cpu().numpy()
+            ex = wl["u_exact"]
+            err = float(np.linalg.norm(u - ex) / np.linalg.norm(ex))
+            row = {"study": "four_rolls_mill", "lattice": "d2q9", "model": "m1", "storage": storage, "u0": u0, "n": n,
+                   "tau": wl["tau"], "steps": steps, "error": err,
+                   "order": None if prev is None else math.log2(prev / err), "seconds": round(dt, 2)}
+            print(json.dumps(row), file=out, flush=True)
+            rows.append(row)
+            prev = err
+            del lat
+    return rows
+
+
 def stability_study(n=128, res=(1600.0, 1e4, 1e5), models=("m1", "bgk", "bgk6"), steps=4000, every=200,
                     storage="fp32", out=sys.stdout):
     rows = []
@@ -227,6 +261,7 @@ def main(argv=None):
     ap.add_argument("study", choices=["precision", "kolmogorov", "four-rolls", "stability", "droplet"])
     ap.add_argument("--storage", default="fp64")
     ap.add_argument("--models", default="m1", help="comma-separated: m1 (the method), m4, m5, eq2")
+    ap.add_argument("--lattice", default="d3q27", choices=["d3q27", "d2q9"])
     ap.add_argument("--n", type=int)
     ap.add_argument("--steps", type=int)
     ap.add_argument("--every", type=int)
@@ -240,6 +275,8 @@ def main(argv=None):
         stability_study(**kw)
     elif a.study == "droplet":
         droplet_study(storage=a.storage, **{k: v for k, v in kw.items() if k in ("n", "steps")})
+    elif a.lattice == "d2q9":
+        four_rolls_study_2d(storage=a.storage)
     else:
         four_rolls_study(storage=a.storage, models=tuple(a.models.split(",")))
 

@@ -1,0 +1,135 @@
+"""CPU-side checks of the D2Q9 C ABI (include/cmlbm2d.h): the library loads,
+exports every declared entry point, and rejects invalid arguments on the host
+before any device work.  No call here reaches the GPU (cmlbm2d_create,
+cmlbm2d_set_force and the argument checks of the other entry points are
+host-only; the fake device addresses below are never dereferenced)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1905_10182_amd import cmlbm2d as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cmlbm2d.h")
+FAKE_A, FAKE_B = 0x7F0000000000, 0x7F0100000000  # 256-byte aligned, never touched
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return B.load_library()
+
+
+def declared_functions(path):
+    text = re.sub(r"/\*.*?\*/", "", open(path).read(), flags=re.S)
+    return sorted(set(re.findall(r"\b(cmlbm2d_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions(HEADER) == sorted(B.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions(HEADER):
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    assert lib.cmlbm2d_status_string(0) == b"CMLBM2D_OK"
+    assert lib.cmlbm2d_status_string(-5) == b"CMLBM2D_ESTATE"
+    assert lib.cmlbm2d_status_string(3) == b"CMLBM2D_UNKNOWN"
+    assert lib.cmlbm2d_last_error(None) == b""
+
+
+def test_required_bytes_padding():
+    # nine planes of ny rows, rows padded to 256 bytes
+    assert B.required_bytes(B.make_params(32, 16, storage="fp32")) == 9 * 16 * 64 * 4
+    assert B.required_bytes(B.make_params(8192, 8192, storage="fp32")) == 9 * 8192 * 8192 * 4
+    assert B.required_bytes(B.make_params(37, 13, storage="fp64")) == 9 * 13 * 64 * 8
+    assert B.required_bytes(B.make_params(100, 3, storage="fp16")) == 9 * 3 * 128 * 2
+    assert B.required_bytes(B.make_params(1, 1, storage="bf16")) == 9 * 128 * 2
+
+
+def test_plane_size_limit():
+    # per-plane byte offsets are 32-bit: a 32768^2 FP32 plane (4 GiB) is refused, FP16 accepted
+    with pytest.raises(B.Cmlbm2dError):
+        B.required_bytes(B.make_params(32768, 32768, storage="fp32"))
+    assert B.required_bytes(B.make_params(32768, 32768, storage="fp16")) == 9 * 32768 ** 2 * 2
+
+
+@pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=float("nan")), dict(nx=0), dict(ny=-3), dict(rho0=0.0),
+                                dict(rho0=float("inf")), dict(storage=4), dict(storage=-1), dict(flags=1)])
+def test_invalid_params(lib, kw):
+    base = dict(nx=16, ny=8, tau=0.8, rho0=1.0, storage="fp32", flags=0)
+    base.update(kw)
+    p = B.make_params(**base)
+    n = ctypes.c_size_t()
+    assert lib.cmlbm2d_required_bytes(ctypes.byref(p), ctypes.byref(n)) == B.EINVAL
+    h = ctypes.c_void_p()
+    assert lib.cmlbm2d_create(ctypes.byref(p), FAKE_A, 1 << 20, FAKE_B, 1 << 20, ctypes.byref(h)) == B.EINVAL
+    assert h.value is None
+
+
+def create(lib, storage="fp32", nx=16, ny=8):
+    p = B.make_params(nx, ny, storage=storage)
+    need = B.required_bytes(p)
+    h = ctypes.c_void_p()
+    assert lib.cmlbm2d_create(ctypes.byref(p), FAKE_A, need, FAKE_B, need, ctypes.byref(h)) == B.OK
+    return h, need, p
+
+
+def test_create_checks_buffers(lib):
+    p = B.make_params(16, 8)
+    need = B.required_bytes(p)
+    h = ctypes.c_void_p()
+    assert lib.cmlbm2d_create(ctypes.byref(p), FAKE_A, need - 1, FAKE_B, need, ctypes.byref(h)) == B.ENOMEM
+    assert lib.cmlbm2d_create(ctypes.byref(p), FAKE_A + 64, need, FAKE_B, need, ctypes.byref(h)) == B.EINVAL
+    assert lib.cmlbm2d_create(ctypes.byref(p), FAKE_A, need, FAKE_A, need, ctypes.byref(h)) == B.EINVAL
+    assert lib.cmlbm2d_create(ctypes.byref(p), None, need, FAKE_B, need, ctypes.byref(h)) == B.EINVAL
+    h, _, _ = create(lib)
+    assert lib.cmlbm2d_destroy(h) == B.OK
+    assert lib.cmlbm2d_destroy(None) == B.OK
+
+
+def test_state_and_argument_errors_before_any_launch(lib):
+    h, _, _ = create(lib)
+    try:
+        assert lib.cmlbm2d_step(h, 1, None) == B.ESTATE  # not initialised
+        assert b"init" in lib.cmlbm2d_last_error(h)
+        assert lib.cmlbm2d_step(h, -1, None) == B.EINVAL
+        assert lib.cmlbm2d_moments(h, FAKE_A, None, B.FP32, None) == B.ESTATE
+        assert lib.cmlbm2d_moments(h, FAKE_A, None, B.FP16, None) == B.EINVAL
+        assert lib.cmlbm2d_populations(h, FAKE_A, None) == B.ESTATE
+        assert lib.cmlbm2d_populations(h, None, None) == B.EINVAL
+        assert lib.cmlbm2d_init(h, None, None, 7, None) == B.EINVAL
+        assert lib.cmlbm2d_load_populations(h, None, None) == B.EINVAL
+        t = ctypes.c_int64(-1)
+        assert lib.cmlbm2d_get_time(h, ctypes.byref(t)) == B.OK and t.value == 0
+    finally:
+        lib.cmlbm2d_destroy(h)
+
+
+def test_set_force_validation(lib):
+    dp = ctypes.POINTER(ctypes.c_double)
+    h, _, _ = create(lib, "fp32")
+    try:
+        good = (ctypes.c_double * 2)(1e-5, -2e-5)
+        bad = (ctypes.c_double * 2)(float("nan"), 0.0)
+        assert lib.cmlbm2d_set_force(h, B.FORCE_UNIFORM, ctypes.cast(good, dp), None, B.FP64, None) == B.OK
+        assert lib.cmlbm2d_set_force(h, B.FORCE_UNIFORM, ctypes.cast(bad, dp), None, B.FP64, None) == B.EINVAL
+        assert lib.cmlbm2d_set_force(h, B.FORCE_UNIFORM, None, None, B.FP64, None) == B.EINVAL
+        assert lib.cmlbm2d_set_force(h, B.FORCE_FIELD, None, FAKE_A, B.FP32, None) == B.OK
+        assert lib.cmlbm2d_set_force(h, B.FORCE_FIELD, None, FAKE_A, B.FP64, None) == B.EINVAL  # FP32 storage
+        assert lib.cmlbm2d_set_force(h, B.FORCE_FIELD, None, FAKE_A + 2, B.FP32, None) == B.EINVAL
+        assert lib.cmlbm2d_set_force(h, B.FORCE_FIELD, None, None, B.FP32, None) == B.EINVAL
+        assert lib.cmlbm2d_set_force(h, 9, None, None, B.FP32, None) == B.EINVAL
+        assert lib.cmlbm2d_set_force(h, B.FORCE_NONE, None, None, B.FP64, None) == B.OK
+    finally:
+        lib.cmlbm2d_destroy(h)
+    h, _, _ = create(lib, "fp64")
+    try:
+        assert lib.cmlbm2d_set_force(h, B.FORCE_FIELD, None, FAKE_A, B.FP64, None) == B.OK
+        assert lib.cmlbm2d_set_force(h, B.FORCE_FIELD, None, FAKE_A + 4, B.FP64, None) == B.EINVAL
+    finally:
+        lib.cmlbm2d_destroy(h)

@@ -1,0 +1,230 @@
+"""Parity of the HIP D2Q9 solver (App. B model, through the C ABI of
+include/cmlbm2d.h) with the CPU oracle of oracle/d2q9_oracle.c.
+
+Tolerances: FP64 storage 1e-12 relative against the oracle built in 80-bit
+long double; FP32 storage 1e-5 relative in velocity (and 1e-6 absolute per
+population); 16-bit storage within one unit in the last place of the stored
+format per population after one step.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import d2q9 as D
+
+pytestmark = pytest.mark.gpu
+
+CX, CY, WGT, OPP = D.constants()
+
+# (nx, ny): ragged rows, a row of exactly one wave at two cells per lane,
+# rows spanning several wave segments with a one-cell last segment, rows
+# shorter than a wave, and the degenerate one-cell axes
+SHAPES = [(37, 13), (64, 8), (128, 5), (200, 7), (130, 4), (256, 3), (1, 9), (9, 1), (1, 1)]
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+def Lat(nx, ny, **kw):
+    from paper_1905_10182_amd.cmlbm2d import Lattice2D
+    return Lattice2D(nx, ny, device="cuda:0", **kw)
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def near_eq_state(shape, seed, amp=0.05):
+    """Populations f_i = w_i (1 + amp * U(-1, 1)): an arbitrary
+    non-equilibrium state near rest."""
+    g = W.generator(seed)
+    return WGT.reshape(9, 1, 1) * (1.0 + amp * g.uniform(-1, 1, size=(9,) + tuple(shape)))
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+@pytest.mark.parametrize("nx,ny", SHAPES)
+def test_steps_match_oracle(torch, storage, nx, ny):
+    log(f"d2q9 {storage} {nx}x{ny}: 7 steps with a force field")
+    shape = (ny, nx)
+    f0 = near_eq_state(shape, seed=nx * 131 + ny)
+    force = W.generator(nx + 7 * ny).uniform(-1e-3, 1e-3, size=(2,) + shape)
+    ref = D.Lattice2D(nx, ny, tau=0.7, force=force, extended=storage == "fp64")
+    ref.load_populations(f0)
+    ref.step(7)
+    lat = Lat(nx, ny, tau=0.7, storage=storage)
+    lat.set_force("field", field=force)
+    lat.load_populations(f0)
+    lat.step(7)
+    assert lat.time == 7
+    f = lat.populations().cpu().numpy()
+    rho, u = (t.cpu().numpy() for t in lat.moments())
+    rho_r, u_r = (np.asarray(a, np.float64) for a in ref.moments())
+    fr = np.asarray(ref.f, np.float64)
+    if storage == "fp64":
+        assert np.abs(f - fr).max() < 1e-12 * np.abs(fr).max()
+        assert rel(u, u_r) < 1e-12 and rel(rho, rho_r) < 1e-13
+    else:
+        assert np.abs(f - fr).max() < 1e-6
+        assert rel(u, u_r) < 1e-5
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_init_is_complete_equilibrium(torch, storage):
+    nx, ny = 45, 11
+    g = W.generator(5)
+    rho = g.uniform(0.9, 1.1, size=(ny, nx))
+    u = g.uniform(-0.1, 0.1, size=(2, ny, nx))
+    ref = D.Lattice2D(nx, ny)
+    ref.init(rho, u)
+    lat = Lat(nx, ny, storage=storage)
+    lat.init(rho, u)
+    f = lat.populations().cpu().numpy()
+    tol = 1e-15 if storage == "fp64" else 3e-8
+    assert np.abs(f - ref.f).max() < tol
+    r, v = (t.cpu().numpy() for t in lat.moments())
+    assert np.abs(r - rho).max() < (1e-14 if storage == "fp64" else 1e-6)
+    assert np.abs(v - u).max() < (1e-15 if storage == "fp64" else 1e-7)
+
+
+def test_population_roundtrip_bit_exact(torch):
+    nx, ny = 37, 13
+    f0 = near_eq_state((ny, nx), seed=9, amp=0.3)
+    lat = Lat(nx, ny, storage="fp64")
+    lat.load_populations(f0)
+    assert np.array_equal(lat.populations().cpu().numpy(), f0)
+
+
+def test_uniform_force_equals_constant_field(torch):
+    nx, ny = 96, 10
+    f0 = near_eq_state((ny, nx), seed=11)
+    F = np.array([2e-4, -1e-4])
+    out = []
+    for mode in ("uniform", "field"):
+        lat = Lat(nx, ny, tau=0.65, storage="fp64")
+        if mode == "uniform":
+            lat.set_force("uniform", F)
+        else:
+            lat.set_force("field", field=np.broadcast_to(F.reshape(2, 1, 1), (2, ny, nx)))
+        lat.load_populations(f0)
+        lat.step(5)
+        out.append(lat.populations().cpu().numpy())
+    assert np.array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+@pytest.mark.parametrize("nx,ny", [(256, 3), (200, 7), (130, 4), (37, 5)])
+def test_16bit_step_within_one_ulp(torch, storage, nx, ny):
+    """One step from a state exactly representable in the storage: every
+    stored post-collision population is within one unit in the last place of
+    the oracle's value (round-to-nearest of an FP32 result)."""
+    log(f"d2q9 {storage} {nx}x{ny}: one step")
+    shape = (ny, nx)
+    lat = Lat(nx, ny, tau=0.8, storage=storage)
+    force = W.generator(3).uniform(-1e-3, 1e-3, size=(2,) + shape)
+    lat.set_force("field", field=force)
+    lat.load_populations(near_eq_state(shape, seed=12))
+    f0 = lat.populations().cpu().numpy()  # the rounded state, exactly
+    ref = D.Lattice2D(nx, ny, tau=0.8, force=force.astype(np.float32).astype(np.float64))
+    ref.load_populations(f0)
+    ref.step(1)
+    lat.step(1)
+    f1 = lat.populations().cpu().numpy()
+    s_ref = ref.f - WGT.reshape(9, 1, 1)  # shifted values, as stored
+    if storage == "fp16":
+        ulp = 2.0 ** (np.floor(np.log2(np.maximum(np.abs(s_ref) * 256, 2.0 ** -14))) - 10) / 256
+    else:
+        ulp = 2.0 ** (np.floor(np.log2(np.maximum(np.abs(s_ref), 1e-30))) - 7)
+    assert np.all(np.abs(f1 - ref.f) <= ulp * 1.01 + 1e-8)
+
+
+def test_four_rolls_mill_matches_oracle_and_converges(torch):
+    """Four-rolls mill (Re = 100, u0 = 1e-3) on the GPU in FP64: at N = 16
+    the steady velocity agrees with the oracle's; over N = 8..64 the error
+    against the analytic field falls at second order (the paper prints
+    1.998)."""
+    errs = []
+    for n in (8, 16, 32, 64):
+        wl = W.four_rolls_mill_2d(n)
+        lat = Lat(n, n, tau=wl["tau"], storage="fp64")
+        lat.set_force("field", field=wl["force"])
+        lat.init(np.ones(wl["shape"]), wl["u_exact"])
+        lat.step(int(2 * wl["t_relax"]))
+        u = lat.moments()[1].cpu().numpy()
+        errs.append(rel(u, wl["u_exact"]))
+        log(f"  N={n}: error {errs[-1]:.4e}")
+        if n == 16:
+            ref = D.Lattice2D(n, n, tau=wl["tau"], force=wl["force"])
+            ref.init(np.ones(wl["shape"]), wl["u_exact"])
+            ref.step(int(2 * wl["t_relax"]))
+            # 81k steps: the FP64 oracle's own rounding drift is about 1.5e-11 here
+            assert rel(u, ref.moments()[1]) < 1e-10
+    rates = [math.log2(errs[k] / errs[k + 1]) for k in range(3)]
+    log(f"  observed orders {rates}")
+    assert all(1.9 < r < 2.1 for r in rates)
+
+
+def test_four_rolls_mill_short_run_fp64_bar(torch):
+    # 300 steps of the four-rolls mill at N = 16 from rest: FP64 bar against the 80-bit oracle
+    n = 16
+    wl = W.four_rolls_mill_2d(n)
+    ref = D.Lattice2D(n, n, tau=wl["tau"], force=wl["force"], extended=True)
+    ref.init(np.ones(wl["shape"]), np.zeros((2, n, n)))
+    ref.step(300)
+    lat = Lat(n, n, tau=wl["tau"], storage="fp64")
+    lat.set_force("field", field=wl["force"])
+    lat.init(None, None)
+    lat.step(300)
+    assert rel(lat.moments()[1].cpu().numpy(), np.asarray(ref.moments()[1], np.float64)) < 1e-12
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+def test_bench_size_sampled_step(torch, storage):
+    """At the benchmark workload (the four-rolls mill at N = 8192 with its
+    force field, in the launch configuration the benchmark times), one step on
+    sampled cells equals the oracle's collision of the exported pre-step
+    populations of each sampled cell's upstream neighbours (edges and corners
+    included)."""
+    n = 8192
+    log(f"d2q9 {storage} {n}x{n}: sampled one-step check")
+    wl = W.four_rolls_mill_2d(n, dtype=np.float32)
+    lat = Lat(n, n, tau=wl["tau"], storage=storage)
+    lat.set_force("field", field=wl["force"])
+    lat.init(np.ones(1, np.float32), wl["u_exact"], dtype=torch.float32)
+    lat.step(3)
+    f_t = lat.populations().reshape(9, -1)
+    g = W.generator(4)
+    ys = np.concatenate([[0, 0, n - 1, n - 1, 0, n // 2], g.integers(0, n, 2042)])
+    xs = np.concatenate([[0, n - 1, 0, n - 1, n // 2, 0], g.integers(0, n, 2042)])
+    K = ys.size
+    pre = np.empty((9, 9, K))  # [direction j][population i][sample]: f_i at the cell upstream along c_j
+    Fpre = np.empty((9, 2, K))
+    for j in range(9):
+        sy, sx = (ys - CY[j]) % n, (xs - CX[j]) % n
+        pre[j] = f_t[:, torch.as_tensor(sy * n + sx, device=f_t.device)].cpu().numpy()
+        Fpre[j] = wl["force"][:, sy, sx].astype(np.float64)
+    del f_t
+    lat.step(1)
+    f_t1 = lat.populations().reshape(9, -1)[:, torch.as_tensor(ys * n + xs, device="cuda:0")].cpu().numpy()
+    expect = np.empty((9, K))
+    for j in range(9):
+        expect[j] = D.collide_cells(pre[j], Fpre[j], 1.0 / wl["tau"])[j]
+    if storage == "fp32":
+        assert np.abs(f_t1 - expect).max() < 1e-6
+    else:
+        s = np.abs(expect - WGT.reshape(9, 1)) * 256
+        ulp = 2.0 ** (np.floor(np.log2(np.maximum(s, 2.0 ** -14))) - 10) / 256
+        assert np.all(np.abs(f_t1 - expect) <= ulp * 1.01 + 1e-8)
