@@ -11,7 +11,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRCS = [os.path.join(HERE, "cmlbm_oracle.c"),  # D3Q27 model of Sec. II
-        os.path.join(HERE, "d2q9_oracle.c")]   # D2Q9 model of App. B
+        os.path.join(HERE, "d2q9_oracle.c"),   # D2Q9 model of App. B
+        os.path.join(HERE, "mhd_oracle.c")]    # magnetic lattice of App. C and the Lorentz force
 LIB = os.path.join(HERE, "liboracle.so")
 LIB_EXT = os.path.join(HERE, "liboracle_ext.so")  # same source in 80-bit long double
 
