@@ -4,7 +4,8 @@
 
 produces paper_1905_10182_amd/libcmlbm.so (the D3Q27 solver, C ABI in
 include/cmlbm.h), libcmlbm2d.so (the D2Q9 model of App. B, C ABI in
-include/cmlbm2d.h) and libcmnn.so (the warm-start network kernels, C ABI in
+include/cmlbm2d.h), libcmlbm_mhd.so (the magnetic lattice of App. C and the
+Lorentz force, C ABI in include/cmlbm_mhd.h) and libcmnn.so (the warm-start network kernels, C ABI in
 include/cmnn.h).  Cross-compiles on a machine without a GPU.
 """
 import os
@@ -25,6 +26,7 @@ HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
 LIBS = {
     "libcmlbm.so": ["cmlbm.hip"],
     "libcmlbm2d.so": ["cmlbm2d.hip"],
+    "libcmlbm_mhd.so": ["cmlbm_mhd.hip"],
     "libcmnn.so": ["cmnn.hip"],
 }
 

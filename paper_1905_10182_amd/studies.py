@@ -5,6 +5,7 @@
     python -m paper_1905_10182_amd.studies four-rolls [--storage fp64] [--models m1,m4,m5] [--lattice d2q9]
     python -m paper_1905_10182_amd.studies stability [--n 128] [--steps 4000] [--every 200]
     python -m paper_1905_10182_amd.studies droplet [--n 200] [--steps 3000]
+    python -m paper_1905_10182_amd.studies orszag-tang [--n 256] [--models m1,m5] [--current populations]
 
 ``precision``: the 3D Taylor-Green vortex (u0 = 0.05, Re = 1600) advanced in
 lockstep with FP64, FP32, FP16 and BF16 population storage (16-bit both with
@@ -37,6 +38,14 @@ G = -6, 200^3, radius 40, tau = 2, tanh interface of width 8) with the
 method (m1) and the comparison
 models m4 and m5: mean kinetic energy over time, the force refreshed from the
 density before every step (cmlbm_pseudopotential_force).
+
+``orszag-tang``: the two-dimensional Orszag-Tang vortex of the MHD tests
+(Sec. III): the D3Q27 fluid with one node in z coupled to the magnetic lattice
+of App. C through the Lorentz force (libcmlbm_mhd), u = u0 (-sin y, sin x),
+b = u0 (-sin y, sin 2x) on a 2 pi box, Ma = u0 / cs in {0.07, 0.14, 0.28},
+Re = u0 (N / 2 pi) / nu = 1600, eta = nu, FP64.  Every 0.1 time units (in
+units of (N / 2 pi) / u0 steps) it reports the kinetic energy relative to its
+initial value and the peak current and vorticity in the same units.
 
 All print one JSON object per checkpoint or grid.  Error norms are taken with torch
 on device-resident moments (diagnostics only; the solver runs in libcmlbm).
@@ -183,6 +192,58 @@ def four_rolls_study_2d(ns=(8, 16, 32, 64, 128, 256), u0s=(1e-3, 1e-2), relax=3.
     return rows
 
 
+def orszag_tang_study(ns=(256,), mas=(0.07, 0.14, 0.28), models=("m1", "m5"), current="populations", re=1600.0,
+                      tmax=2.0, every=0.1, storage="fp64", out=sys.stdout):
+    import math
+
+    import torch
+
+    from paper_1905_10182_amd.mhd import CoupledMHD
+
+    def ddx(f, axis):  # central difference on the periodic lattice
+        return 0.5 * (torch.roll(f, -1, axis) - torch.roll(f, 1, axis))
+
+    rows = []
+    for n in ns:
+        for ma in mas:
+            u0 = ma / math.sqrt(3.0)
+            nu = u0 * n / (2 * math.pi * re)
+            tau, tau_m = 0.5 + 3 * nu, 0.5 + 4 * nu
+            k = 2 * math.pi / n
+            X, Y = np.meshgrid(np.arange(n), np.arange(n))
+            u = np.zeros((3, 1, n, n))
+            b = np.zeros((3, 1, n, n))
+            u[0, 0], u[1, 0] = -u0 * np.sin(k * Y), u0 * np.sin(k * X)
+            b[0, 0], b[1, 0] = -u0 * np.sin(k * Y), u0 * np.sin(2 * k * X)
+            unit = n / (2 * math.pi * u0)  # steps per time unit
+            for model in models:
+                S = CoupledMHD(n, n, 1, tau, tau_m, storage=storage, model=model, current=current)
+                S.init(np.ones((1, n, n)), u, b)
+                ke0 = None
+                t0 = time.perf_counter()
+                for i in range(int(round(tmax / every)) + 1):
+                    t = i * every
+                    S.step(int(round(t * unit)) - S.time)
+                    rho, uu, bb, jj = S.state()
+                    ke = float((uu[:2] ** 2).sum())
+                    ke0 = ke if ke0 is None else ke0
+                    zeta = ddx(uu[1, 0], 1) - ddx(uu[0, 0], 0)
+                    jst = ddx(bb[1, 0], 1) - ddx(bb[0, 0], 0)
+                    finite = bool(torch.isfinite(uu).all())
+                    row = {"study": "orszag_tang", "n": n, "ma": ma, "model": model, "current": current, "tau": tau,
+                           "tau_m": tau_m, "t": round(t, 4), "step": S.time, "ke_rel": ke / ke0,
+                           "jmax": float(jj[2].abs().max()) * unit, "jmax_stencil": float(jst.abs().max()) * unit,
+                           "zeta_max": float(zeta.abs().max()) * unit, "finite": finite}
+                    print(json.dumps(row), file=out, flush=True)
+                    rows.append(row)
+                    if not finite:
+                        break
+                print(f"[orszag-tang] N={n} Ma={ma} {model}: {S.time} steps in {time.perf_counter() - t0:.1f} s",
+                      file=sys.stderr, flush=True)
+                del S
+    return rows
+
+
 def stability_study(n=128, res=(1600.0, 1e4, 1e5), models=("m1", "bgk", "bgk6"), steps=4000, every=200,
                     storage="fp32", out=sys.stdout):
     rows = []
@@ -258,10 +319,13 @@ def droplet_study(n=200, radius=40.0, models=("m1", "m4", "m5"), steps=3000, sto
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["precision", "kolmogorov", "four-rolls", "stability", "droplet"])
+    ap.add_argument("study", choices=["precision", "kolmogorov", "four-rolls", "stability", "droplet",
+                                      "orszag-tang"])
     ap.add_argument("--storage", default="fp64")
     ap.add_argument("--models", default="m1", help="comma-separated: m1 (the method), m4, m5, eq2")
     ap.add_argument("--lattice", default="d3q27", choices=["d3q27", "d2q9"])
+    ap.add_argument("--current", default="populations", choices=["populations", "stencil"])
+    ap.add_argument("--tmax", type=float, default=2.0)
     ap.add_argument("--n", type=int)
     ap.add_argument("--steps", type=int)
     ap.add_argument("--every", type=int)
@@ -273,6 +337,8 @@ def main(argv=None):
         kolmogorov_study(**kw)
     elif a.study == "stability":
         stability_study(**kw)
+    elif a.study == "orszag-tang":
+        orszag_tang_study(ns=(a.n or 256,), models=tuple(a.models.split(",")), current=a.current, tmax=a.tmax)
     elif a.study == "droplet":
         droplet_study(storage=a.storage, **{k: v for k, v in kw.items() if k in ("n", "steps")})
     elif a.lattice == "d2q9":
