@@ -6,6 +6,7 @@
     python -m paper_1905_10182_amd.studies stability [--n 128] [--steps 4000] [--every 200]
     python -m paper_1905_10182_amd.studies droplet [--n 200] [--steps 3000]
     python -m paper_1905_10182_amd.studies orszag-tang [--n 256] [--models m1,m5] [--current populations]
+    python -m paper_1905_10182_amd.studies orszag-tang-3d [--n 64] [--models m1,m4,m5] [--re 100]
 
 ``precision``: the 3D Taylor-Green vortex (u0 = 0.05, Re = 1600) advanced in
 lockstep with FP64, FP32, FP16 and BF16 population storage (16-bit both with
@@ -46,6 +47,10 @@ b = u0 (-sin y, sin 2x) on a 2 pi box, Ma = u0 / cs in {0.07, 0.14, 0.28},
 Re = u0 (N / 2 pi) / nu = 1600, eta = nu, FP64.  Every 0.1 time units (in
 units of (N / 2 pi) / u0 steps) it reports the kinetic energy relative to its
 initial value and the peak current and vorticity in the same units.
+
+``orszag-tang-3d``: the three-dimensional Orszag-Tang vortex of Sec. III
+(u0 = b0 = 0.0203, Re = 100 by default), peak current magnitude over time for
+N = 32, 64, 128 (or the given N), stencil current.
 
 All print one JSON object per checkpoint or grid.  Error norms are taken with torch
 on device-resident moments (diagnostics only; the solver runs in libcmlbm).
@@ -244,6 +249,61 @@ def orszag_tang_study(ns=(256,), mas=(0.07, 0.14, 0.28), models=("m1", "m5"), cu
     return rows
 
 
+def orszag_tang_3d_study(ns=(32, 64, 128), re=100.0, models=("m1",), current="stencil", tmax=2.0, every=0.1,
+                         storage="fp64", out=sys.stdout):
+    """Three-dimensional Orszag-Tang vortex (Sec. III): u = u0 (-2 sin y,
+    2 sin x, 0), b = 0.8 u0 (-2 sin 2y + sin z, 2 sin x + sin z, sin x + sin y)
+    on a 2 pi box, u0 = 0.0203, Re = u0 (N / 2 pi) / nu, eta = nu; peak
+    current magnitude and kinetic energy every `every` time units."""
+    import math
+
+    import torch
+
+    from paper_1905_10182_amd.mhd import CoupledMHD
+
+    def ddx(f, axis):
+        return 0.5 * (torch.roll(f, -1, axis) - torch.roll(f, 1, axis))
+
+    rows = []
+    u0 = 0.0203
+    for n in ns:
+        nu = u0 * n / (2 * math.pi * re)
+        tau, tau_m = 0.5 + 3 * nu, 0.5 + 4 * nu
+        c = 2 * math.pi * np.arange(n) / n
+        Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+        u = np.stack([-2 * u0 * np.sin(Y), 2 * u0 * np.sin(X), 0 * X])
+        b = 0.8 * u0 * np.stack([-2 * np.sin(2 * Y) + np.sin(Z), 2 * np.sin(X) + np.sin(Z), np.sin(X) + np.sin(Y)])
+        unit = n / (2 * math.pi * u0)
+        for model in models:
+            S = CoupledMHD(n, n, n, tau, tau_m, storage=storage, model=model, current=current)
+            S.init(np.ones((1, n, n, n)), u[:, None], b[:, None])
+            t_start = time.perf_counter()
+            ke0 = None
+            for i in range(int(round(tmax / every)) + 1):
+                t = i * every
+                S.step(int(round(t * unit)) - S.time)
+                rho, uu, bb, jj = S.state()
+                ke = float((uu ** 2).sum())
+                ke0 = ke if ke0 is None else ke0
+                # |curl b| by central differences (axes of bb: component, z, y, x)
+                jx = ddx(bb[2], 1) - ddx(bb[1], 0)
+                jy = ddx(bb[0], 0) - ddx(bb[2], 2)
+                jz = ddx(bb[1], 2) - ddx(bb[0], 1)
+                jmag = torch.sqrt(jx * jx + jy * jy + jz * jz)
+                finite = bool(torch.isfinite(uu).all())
+                row = {"study": "orszag_tang_3d", "n": n, "re": re, "model": model, "current": current, "tau": tau,
+                       "t": round(t, 4), "step": S.time, "ke_rel": ke / ke0, "jmax": float(jmag.max()) * unit,
+                       "finite": finite}
+                print(json.dumps(row), file=out, flush=True)
+                rows.append(row)
+                if not finite:
+                    break
+            print(f"[orszag-tang-3d] N={n} Re={re} {model}: {S.time} steps in {time.perf_counter() - t_start:.1f} s",
+                  file=sys.stderr, flush=True)
+            del S
+    return rows
+
+
 def stability_study(n=128, res=(1600.0, 1e4, 1e5), models=("m1", "bgk", "bgk6"), steps=4000, every=200,
                     storage="fp32", out=sys.stdout):
     rows = []
@@ -320,12 +380,13 @@ def droplet_study(n=200, radius=40.0, models=("m1", "m4", "m5"), steps=3000, sto
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("study", choices=["precision", "kolmogorov", "four-rolls", "stability", "droplet",
-                                      "orszag-tang"])
+                                      "orszag-tang", "orszag-tang-3d"])
     ap.add_argument("--storage", default="fp64")
     ap.add_argument("--models", default="m1", help="comma-separated: m1 (the method), m4, m5, eq2")
     ap.add_argument("--lattice", default="d3q27", choices=["d3q27", "d2q9"])
     ap.add_argument("--current", default="populations", choices=["populations", "stencil"])
     ap.add_argument("--tmax", type=float, default=2.0)
+    ap.add_argument("--re", type=float)
     ap.add_argument("--n", type=int)
     ap.add_argument("--steps", type=int)
     ap.add_argument("--every", type=int)
@@ -339,6 +400,9 @@ def main(argv=None):
         stability_study(**kw)
     elif a.study == "orszag-tang":
         orszag_tang_study(ns=(a.n or 256,), models=tuple(a.models.split(",")), current=a.current, tmax=a.tmax)
+    elif a.study == "orszag-tang-3d":
+        orszag_tang_3d_study(ns=(a.n,) if a.n else (32, 64, 128), re=a.re or 100.0,
+                             models=tuple(a.models.split(",")), tmax=a.tmax)
     elif a.study == "droplet":
         droplet_study(storage=a.storage, **{k: v for k, v in kw.items() if k in ("n", "steps")})
     elif a.lattice == "d2q9":
