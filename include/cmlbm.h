@@ -135,8 +135,9 @@ typedef struct {
 /* Bytes the caller must provide for each of the two population buffers and for
  * the scratch buffer.  Pure host computation.  EINVAL on invalid params,
  * including a population plane (one population over all cells, rows padded to
- * 256 bytes) of 4 GiB or more: the kernels address within a plane with 32-bit
- * byte offsets (FP32 up to ~1.07e9 cells, 16-bit up to ~2.1e9 cells). */
+ * 256 bytes, planes 4 KiB apart beyond that) of 4 GiB or more: the kernels
+ * address within a plane with 32-bit byte offsets (FP32 up to ~1.07e9 cells,
+ * 16-bit up to ~2.1e9 cells). */
 int cmlbm_required_bytes(const cmlbm_params* params, size_t* pop_buffer_bytes, size_t* scratch_bytes);
 
 /* Create a handle over caller-allocated device buffers (borrowed; each must be

@@ -74,7 +74,8 @@ typedef struct {
 } cmlbm2d_params;
 
 /* Bytes the caller must provide for each of the two population buffers (nine
- * planes of ny rows, each row padded to 256 bytes).  Pure host computation.
+ * planes of ny rows, each row padded to 256 bytes; FP64 planes 4 KiB apart
+ * beyond that).  Pure host computation.
  * EINVAL on invalid params, including a plane of 4 GiB or more (the kernels
  * address within a plane with 32-bit byte offsets). */
 int cmlbm2d_required_bytes(const cmlbm2d_params* params, size_t* pop_buffer_bytes);

@@ -12,7 +12,8 @@
 //
 // Memory layout in HBM (structure of arrays): population plane i holds one
 // value per cell, rows of nxp elements (nx rounded up to 256 bytes), cells
-// ordered [nbatch][nz][ny][nxp]; two such buffers alternate between steps.
+// ordered [nbatch][nz][ny][nxp], consecutive planes kPlanePad bytes apart
+// beyond their rows; two such buffers alternate between steps.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -38,6 +39,7 @@ constexpr int kModelEq2 = 2;  // second-order equilibrium
 constexpr int kModelBgk = 4;  // single relaxation time
 constexpr int kMaxRedBlocks = 256;  // reduce workgroups per batch member
 constexpr uint32_t kSolidBit = 1u << 27;
+constexpr size_t kPlanePad = 4096;  // bytes between consecutive population planes (a multiple of 256)
 
 // ---------------------------------------------------------------------------
 // storage types
@@ -1074,7 +1076,9 @@ int make_layout(const cmlbm_params* p, Layout* L)
     const uint64_t rows = (uint64_t)p->ny * p->nz * p->nbatch;
     if (rows > 0x7fffffffULL) return CMLBM_EINVAL;
     g.rows = (int)rows;
-    g.pstride = rows * (uint64_t)g.nxp;
+    // planes are kPlanePad bytes apart beyond their rows: at power-of-two plane sizes the 27
+    // concurrent plane streams would otherwise map onto the same HBM channels
+    g.pstride = rows * (uint64_t)g.nxp + kPlanePad / sb;
     if (g.pstride * sb >= (1ULL << 32)) return CMLBM_EINVAL;  // per-plane byte offsets are 32-bit
     g.ncell = rows * (uint64_t)p->nx;
     const int nx64 = (p->nx + 63) / 64 * 64;

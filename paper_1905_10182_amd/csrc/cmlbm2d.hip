@@ -4,7 +4,8 @@
 // d2q9.hpp; this file holds the kernels and the host side.
 //
 // Data layout in HBM: nine population planes of ny rows, each row padded to
-// 256 bytes, stored shifted (f_i - w_i rho0) in the storage type; two such
+// 256 bytes (FP64 planes also kPlanePad bytes apart beyond their rows),
+// stored shifted (f_i - w_i rho0) in the storage type; two such
 // buffers alternate (read one, write the other).  The stored array A_i(y)
 // holds the population that the next pull gather moves to y + c_i, so
 // f_i(x, t) = A_i(x - c_i): a step is gather (streaming), collision and a
@@ -34,7 +35,8 @@ using namespace cmlbm2d;
 
 namespace {
 
-constexpr int kBlock = 256;  // threads per workgroup
+constexpr int kBlock = 256;         // threads per workgroup
+constexpr size_t kPlanePad = 4096;  // bytes between consecutive FP64 population planes (a multiple of 256)
 
 // ---------------------------------------------------------------------------
 // storage types: S is stored, T is the arithmetic type
@@ -397,7 +399,11 @@ int make_geom(const cmlbm2d_params* p, Geom2* g, size_t* pop_bytes)
     g->nx = p->nx;
     g->ny = p->ny;
     g->nxp = (int)(align256((size_t)p->nx * sb) / sb);
-    g->pstride = (uint64_t)p->ny * (uint64_t)g->nxp;
+    // FP64 planes kPlanePad bytes apart beyond their rows (at power-of-two plane sizes the
+    // nine plane streams otherwise share HBM channels); measured on 8192^2 it raises FP64 by
+    // 6% and lowers FP16/BF16 by 6%, FP32 unchanged, so the other storages keep dense planes
+    const size_t pad = p->storage == CMLBM2D_FP64 ? kPlanePad : 0;
+    g->pstride = (uint64_t)p->ny * (uint64_t)g->nxp + pad / sb;
     if (g->pstride * sb >= (1ULL << 32)) return CMLBM2D_EINVAL;  // per-plane byte offsets are 32-bit
     g->ncell = (uint64_t)p->ny * (uint64_t)p->nx;
     g->V = lanes_for(p->storage, p->nx);

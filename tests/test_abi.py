@@ -46,16 +46,19 @@ def req(**kw):
     return B.make_params(**base)
 
 
+PLANE_PAD = 4096  # bytes between consecutive population planes
+
+
 def test_required_bytes_padding():
-    # rows padded to 256 bytes; 27 planes of rows * padded row length
+    # rows padded to 256 bytes; 27 planes of rows * padded row length, planes 4 KiB apart
     pop, scratch = B.required_bytes(req(nx=32, storage="fp32"))
-    assert pop == 27 * 16 * 16 * 64 * 4
+    assert pop == 27 * (16 * 16 * 64 * 4 + PLANE_PAD)
     pop, _ = B.required_bytes(req(nx=256, ny=256, nz=256, storage="fp32"))
-    assert pop == 27 * 256 ** 3 * 4
+    assert pop == 27 * (256 ** 3 * 4 + PLANE_PAD)
     pop, _ = B.required_bytes(req(nx=512, ny=512, nz=512, storage="fp16"))
-    assert pop == 27 * 512 ** 3 * 2
+    assert pop == 27 * (512 ** 3 * 2 + PLANE_PAD)
     pop, _ = B.required_bytes(req(nx=37, ny=13, nz=11, nbatch=2, storage="fp64"))
-    assert pop == 27 * 13 * 11 * 2 * 64 * 8
+    assert pop == 27 * (13 * 11 * 2 * 64 * 8 + PLANE_PAD)
     # a mask (walls/solid) and the residual snapshot enlarge the scratch
     _, s0 = B.required_bytes(req())
     _, s1 = B.required_bytes(req(wall=(0, 1, 0)))
@@ -69,7 +72,7 @@ def test_plane_size_limit():
     with pytest.raises(B.CmlbmError):
         B.required_bytes(req(nx=1024, ny=1024, nz=1024, storage="fp32"))
     pop, _ = B.required_bytes(req(nx=1024, ny=1024, nz=1024, storage="fp16"))
-    assert pop == 27 * 1024 ** 3 * 2
+    assert pop == 27 * (1024 ** 3 * 2 + PLANE_PAD)
 
 
 @pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=0.3), dict(tau=float("nan")), dict(nx=0), dict(ny=-1),
@@ -140,7 +143,7 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
 def test_moment_storage_bytes():
     """The moment representation keeps nine FP32 planes per buffer."""
     pop, _ = B.required_bytes(req(nx=64, ny=8, nz=8, storage="mom32"))
-    assert pop == 9 * 8 * 8 * 64 * 4
+    assert pop == 9 * (8 * 8 * 64 * 4 + PLANE_PAD)
     pop32, _ = B.required_bytes(req(nx=64, ny=8, nz=8, storage="fp32"))
     assert pop32 == 3 * pop
     B.required_bytes(req(storage="mom32", flags=B.FLAG_RESIDUAL))  # residual snapshots are allowed

@@ -42,11 +42,14 @@ def test_status_strings(lib):
     assert lib.cmlbm2d_last_error(None) == b""
 
 
+PLANE_PAD = 4096  # bytes between consecutive FP64 population planes
+
+
 def test_required_bytes_padding():
-    # nine planes of ny rows, rows padded to 256 bytes
+    # nine planes of ny rows, rows padded to 256 bytes, FP64 planes 4 KiB apart
     assert B.required_bytes(B.make_params(32, 16, storage="fp32")) == 9 * 16 * 64 * 4
     assert B.required_bytes(B.make_params(8192, 8192, storage="fp32")) == 9 * 8192 * 8192 * 4
-    assert B.required_bytes(B.make_params(37, 13, storage="fp64")) == 9 * 13 * 64 * 8
+    assert B.required_bytes(B.make_params(37, 13, storage="fp64")) == 9 * (13 * 64 * 8 + PLANE_PAD)
     assert B.required_bytes(B.make_params(100, 3, storage="fp16")) == 9 * 3 * 128 * 2
     assert B.required_bytes(B.make_params(1, 1, storage="bf16")) == 9 * 128 * 2
 
