@@ -195,6 +195,12 @@ class Lattice:
         t = None if solid is None else self._dev(solid, self.torch.uint8, self.shape)
         self._check(self.lib.cmlbm_set_solid(self.handle, _ptr(t), self._stream()), "set_solid")
 
+    @property
+    def force_field(self):
+        """The device tensor the solver borrows in FIELD mode (writing into it
+        changes the force of later steps and moments), else None."""
+        return self._field
+
     def set_force(self, mode, values=None, field=None):
         """mode: 'none' | 'uniform' (values[3]) | 'batch' (values[nbatch][3]) |
         'profile_y' (values[ny][3]) | 'field' (field (3, nbatch, nz, ny, nx))."""

@@ -214,7 +214,7 @@ class CoupledMHD:
         self.fluid.init(np.asarray(rho, np.float64).reshape((1,) + self.shape), u.reshape((3, 1) + self.shape))
         self.F.zero_()
         self.fluid.set_force("field", field=self.F)
-        self.F = self.fluid._field  # the buffer the fluid solver borrows
+        self.F = self.fluid.force_field  # the buffer the fluid solver borrows
         self.mag.init(b, u)
 
     def velocity(self):
