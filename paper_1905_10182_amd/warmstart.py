@@ -44,8 +44,8 @@ from .unet import UNet3D
 import os
 
 NX, NY, NZ = 64, 32, 32
-# trained network shipped with the package (64000 Adam steps on 4096 steady
-# states, seeds 0..4095); evaluation seeds start at 1000000
+# trained network shipped with the package (96000 Adam steps at batch 16 on
+# 8192 steady states, seeds 0..8191); evaluation seeds start at 1000000
 DEFAULT_MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "unet_warmstart.npz")
 TAU = 0.8
 NU = (TAU - 0.5) / 3.0
