@@ -29,6 +29,8 @@ def _load(extended=False):
         lib.orc_mhd_heq.argtypes = [dp, dp, dp]
         lib.orc_mhd_init.argtypes = [ci, ci, ci, dp, dp, dp]
         lib.orc_mhd_step.argtypes = [ci, ci, ci, dp, real, dp, dp]
+        lib.orc_mhd_step_walls.argtypes = [ci, ci, ci, _ip, dp, dp, real, dp, dp]
+        lib.orc_curl_fd_walls.argtypes = [ci, ci, ci, _ip, dp, dp, dp]
         lib.orc_mhd_fields.argtypes = [ci, ci, ci, dp, real, dp, dp, dp]
         lib.orc_curl_fd.argtypes = [ci, ci, ci, dp, dp]
         lib.orc_lorentz.argtypes = [ctypes.c_long, dp, dp, dp]
@@ -52,12 +54,18 @@ def heq(b, u):
     return out
 
 
-def curl_fd(b):
-    """Central-difference curl of a periodic field b (3, nz, ny, nx)."""
+def curl_fd(b, wall=None, b_wall=None):
+    """Central-difference curl of b (3, nz, ny, nx): periodic axes, or the
+    ghost value 2 b_wall - b beyond the walls flagged in `wall` (x, y, z)."""
     b = np.ascontiguousarray(b, np.float64)
     nz, ny, nx = b.shape[1:]
     j = np.zeros_like(b)
-    _load().orc_curl_fd(nx, ny, nz, _d(b), _d(j))
+    if wall is None:
+        _load().orc_curl_fd(nx, ny, nz, _d(b), _d(j))
+    else:
+        w = np.ascontiguousarray(wall, np.int32)
+        bw = np.ascontiguousarray(np.zeros(3) if b_wall is None else b_wall, np.float64)
+        _load().orc_curl_fd_walls(nx, ny, nz, w.ctypes.data_as(_ip), _d(bw), _d(b), _d(j))
     return j
 
 
@@ -70,11 +78,12 @@ def lorentz(j, b):
 
 
 class MagneticLattice:
-    """The D3Q7 magnetic lattice alone on a periodic nx * ny * nz box.
-    State h (7, 3, nz, ny, nx); tau_m the magnetic relaxation time,
-    eta = (tau_m - 1/2) / 4."""
+    """The D3Q7 magnetic lattice alone on an nx * ny * nz box: periodic axes,
+    or walls halfway between nodes on the axes flagged in `wall` (x, y, z)
+    where b takes the value b_wall (reading C3).  State h (7, 3, nz, ny, nx);
+    tau_m the magnetic relaxation time, eta = (tau_m - 1/2) / 4."""
 
-    def __init__(self, nx, ny, nz, tau_m, extended=False):
+    def __init__(self, nx, ny, nz, tau_m, extended=False, wall=(0, 0, 0), b_wall=(0.0, 0.0, 0.0)):
         self.extended = bool(extended)
         self.dtype = np.longdouble if self.extended else np.float64
         self.lib = _load(self.extended)
@@ -85,6 +94,8 @@ class MagneticLattice:
         self.tau_m = self.dtype(tau_m)
         self.h = np.zeros((Q, 3) + self.shape, self.dtype)
         self._tmp = np.zeros_like(self.h)
+        self.wall = np.ascontiguousarray(wall, np.int32)
+        self.b_wall = np.ascontiguousarray(b_wall, self.dtype)
 
     def _vec(self, v):
         return None if v is None else np.ascontiguousarray(np.broadcast_to(np.asarray(v, self.dtype),
@@ -96,8 +107,8 @@ class MagneticLattice:
 
     def step(self, u=None):
         u = self._vec(u)
-        self.lib.orc_mhd_step(self.nx, self.ny, self.nz, None if u is None else _d(u), 1 / self.tau_m,
-                              _d(self.h), _d(self._tmp))
+        self.lib.orc_mhd_step_walls(self.nx, self.ny, self.nz, self.wall.ctypes.data_as(_ip), _d(self.b_wall),
+                                    None if u is None else _d(u), 1 / self.tau_m, _d(self.h), _d(self._tmp))
 
     def fields(self, u=None, current="populations"):
         """(b, j), each (3, nz, ny, nx); the current from the populations
@@ -108,13 +119,17 @@ class MagneticLattice:
         self.lib.orc_mhd_fields(self.nx, self.ny, self.nz, None if u is None else _d(u), self.tau_m, _d(self.h),
                                 _d(b), _d(j) if current == "populations" else None)
         if current != "populations":
-            j = curl_fd(b.astype(np.float64)).astype(self.dtype)
+            j = curl_fd(b.astype(np.float64), self.wall, self.b_wall.astype(np.float64)).astype(self.dtype)
         return b, j
 
 
 class MHD:
     """Fluid (D3Q27 oracle, `variant` as in oracle.Lattice) coupled to the
-    magnetic lattice through the Lorentz force, one box (nbatch = 1).
+    magnetic lattice through the Lorentz force, one box (nbatch = 1).  With
+    `wall` both lattices have walls on the flagged axes (fluid: halfway
+    bounce-back; field: b = b_wall there).  `body_force` (3 values, set after
+    construction) is added to the Lorentz force (the driving of the Hartmann
+    channel).
 
     One step:
       (a) u_lag = fluid velocity with the force in effect (the previous step's);
@@ -125,9 +140,11 @@ class MHD:
       (e) fluid collision with F and streaming.
     """
 
-    def __init__(self, nx, ny, nz, tau, tau_m, variant="closed", current="populations", extended=False):
-        self.fluid = Lattice(nx, ny, nz, tau=tau, extended=extended)
-        self.mag = MagneticLattice(nx, ny, nz, tau_m, extended=extended)
+    def __init__(self, nx, ny, nz, tau, tau_m, variant="closed", current="populations", extended=False,
+                 wall=(0, 0, 0), b_wall=(0.0, 0.0, 0.0)):
+        self.fluid = Lattice(nx, ny, nz, tau=tau, wall=wall, extended=extended)
+        self.mag = MagneticLattice(nx, ny, nz, tau_m, extended=extended, wall=wall, b_wall=b_wall)
+        self.body_force = None
         self.variant, self.current = variant, current
         self.shape = (nz, ny, nx)
         self.t = 0
@@ -146,6 +163,8 @@ class MHD:
             u_lag = self.velocity()
             b, j = self.mag.fields(u_lag, self.current)
             F = lorentz(j.astype(np.float64), b.astype(np.float64))
+            if self.body_force is not None:
+                F = F + np.asarray(self.body_force, np.float64).reshape(3, 1, 1, 1)
             self.fluid.set_force(F.reshape((3, 1) + self.shape))
             u = self.velocity()
             self.mag.step(u)

@@ -23,7 +23,13 @@
  *       difference curl of b is the alternative ("stencil") current.
  *   C2  The Lorentz force F = j x b is a force density (b in units where the
  *       magnetic pressure is |b|^2/2).
- *   C3  Periodic boundaries (the Orszag-Tang and Alfven-wave cases).
+ *   C3  Periodic axes, or walls halfway between nodes on the axes flagged in
+ *       `wall`: the magnetic field takes a given value b_w at the wall (the
+ *       Hartmann test imposes it there).  A population that would stream into
+ *       the wall comes back as h_opp(l)(x, t+1) = -h*_l(x, t) + 2 w_l b_w
+ *       (anti-bounce-back, which places the Dirichlet value at the half-way
+ *       point); the central-difference curl uses the ghost value 2 b_w - b(x)
+ *       beyond a wall.
  *
  * Layout: h[(l*3 + a)*N + n], N = nz*ny*nx, n = (z*ny + y)*nx + x; vector
  * fields [3][N].
@@ -92,8 +98,21 @@ static void cell_b(const real* h, long N, long n, real b[3])
 }
 
 /* One step: collide every cell towards h^eq(b, u) with rate omega_m, then
- * stream periodically, h_l(x + xi_l) = h*_l(x).  u is [3][N] or NULL. */
+ * stream, h_l(x + xi_l) = h*_l(x), periodic or through the wall rule of
+ * reading C3 (wall[3] flags per axis, b_wall[3]; both may be NULL = periodic).
+ * u is [3][N] or NULL. */
+void orc_mhd_step_walls(int nx, int ny, int nz, const int* wall, const real* b_wall, const real* u, real omega_m,
+                        real* h, real* tmp);
+
 void orc_mhd_step(int nx, int ny, int nz, const real* u, real omega_m, real* h, real* tmp)
+{
+    orc_mhd_step_walls(nx, ny, nz, NULL, NULL, u, omega_m, h, tmp);
+}
+
+static int opp_m(int l) { return l == 0 ? 0 : (l % 2 ? l + 1 : l - 1); }
+
+void orc_mhd_step_walls(int nx, int ny, int nz, const int* wall, const real* b_wall, const real* u, real omega_m,
+                        real* h, real* tmp)
 {
     const long N = (long)nx * ny * nz;
     for (long n = 0; n < N; ++n) {
@@ -104,11 +123,26 @@ void orc_mhd_step(int nx, int ny, int nz, const real* u, real omega_m, real* h, 
         orc_mhd_heq(b, uu, e);
         for (int k = 0; k < QM * 3; ++k) tmp[k * N + n] = h[k * N + n] + omega_m * (e[k] - h[k * N + n]);
     }
+    const long dim[3] = {nx, ny, nz};
     for (long n = 0; n < N; ++n) {
-        const long x = n % nx, y = (n / nx) % ny, z = n / ((long)nx * ny);
+        const long c[3] = {n % nx, (n / nx) % ny, n / ((long)nx * ny)};
         for (int l = 0; l < QM; ++l) {
-            const long xd = (x + XI[l][0] + nx) % nx, yd = (y + XI[l][1] + ny) % ny, zd = (z + XI[l][2] + nz) % nz;
-            const long m = (zd * ny + yd) * nx + xd;
+            long d[3];
+            int into_wall = 0;
+            for (int a = 0; a < 3; ++a) {
+                d[a] = c[a] + XI[l][a];
+                if (d[a] < 0 || d[a] >= dim[a]) {
+                    if (wall && wall[a]) into_wall = 1;
+                    d[a] = (d[a] + dim[a]) % dim[a];
+                }
+            }
+            if (into_wall) {
+                const int o = opp_m(l);
+                for (int a = 0; a < 3; ++a)
+                    h[(3 * o + a) * N + n] = -tmp[(3 * l + a) * N + n] + 2.0 * wm(l) * (b_wall ? b_wall[a] : 0.0);
+                continue;
+            }
+            const long m = (d[2] * ny + d[1]) * nx + d[0];
             for (int a = 0; a < 3; ++a) h[(3 * l + a) * N + m] = tmp[(3 * l + a) * N + n];
         }
     }
@@ -142,26 +176,41 @@ void orc_mhd_fields(int nx, int ny, int nz, const real* u, real tau_m, const rea
     }
 }
 
-/* Central-difference curl of a periodic field b ([3][N]) into j. */
-void orc_curl_fd(int nx, int ny, int nz, const real* b, real* j)
+/* Central-difference curl of b ([3][N]) into j: periodic axes, or (wall[a]
+ * set) the ghost value 2 b_wall - b(x) beyond a wall (reading C3).  wall and
+ * b_wall may be NULL (periodic). */
+void orc_curl_fd_walls(int nx, int ny, int nz, const int* wall, const real* b_wall, const real* b, real* j)
 {
     const long N = (long)nx * ny * nz;
+    const long dim[3] = {nx, ny, nz};
+    const long stride[3] = {1, nx, (long)nx * ny};
     for (long n = 0; n < N; ++n) {
-        const long x = n % nx, y = (n / nx) % ny, z = n / ((long)nx * ny);
-        const long xp = (z * ny + y) * nx + (x + 1) % nx, xm = (z * ny + y) * nx + (x + nx - 1) % nx;
-        const long yp = (z * ny + (y + 1) % ny) * nx + x, ym = (z * ny + (y + ny - 1) % ny) * nx + x;
-        const long zp = (((z + 1) % nz) * ny + y) * nx + x, zm = (((z + nz - 1) % nz) * ny + y) * nx + x;
-        /* d_a of component c: (b_c(+) - b_c(-)) / 2; an axis of extent 1 has no derivative */
-#define D(c, pp, mm, ext) ((ext) > 1 ? 0.5 * (b[(c) * N + (pp)] - b[(c) * N + (mm)]) : 0.0)
-        const real dyBz = D(2, yp, ym, ny), dzBy = D(1, zp, zm, nz);
-        const real dzBx = D(0, zp, zm, nz), dxBz = D(2, xp, xm, nx);
-        const real dxBy = D(1, xp, xm, nx), dyBx = D(0, yp, ym, ny);
-#undef D
-        j[n] = dyBz - dzBy;
-        j[N + n] = dzBx - dxBz;
-        j[2 * N + n] = dxBy - dyBx;
+        const long c[3] = {n % nx, (n / nx) % ny, n / ((long)nx * ny)};
+        real D[3][3]; /* D[a][comp] = d_a b_comp */
+        for (int a = 0; a < 3; ++a) {
+            for (int q = 0; q < 3; ++q) D[a][q] = 0.0;
+            if (dim[a] < 2) continue; /* an axis of extent 1 has no derivative */
+            for (int q = 0; q < 3; ++q) {
+                real vp, vm;
+                const real here = b[q * N + n];
+                if (c[a] + 1 < dim[a])
+                    vp = b[q * N + n + stride[a]];
+                else
+                    vp = (wall && wall[a]) ? 2.0 * (b_wall ? b_wall[q] : 0.0) - here : b[q * N + n - (dim[a] - 1) * stride[a]];
+                if (c[a] > 0)
+                    vm = b[q * N + n - stride[a]];
+                else
+                    vm = (wall && wall[a]) ? 2.0 * (b_wall ? b_wall[q] : 0.0) - here : b[q * N + n + (dim[a] - 1) * stride[a]];
+                D[a][q] = 0.5 * (vp - vm);
+            }
+        }
+        j[n] = D[1][2] - D[2][1];
+        j[N + n] = D[2][0] - D[0][2];
+        j[2 * N + n] = D[0][1] - D[1][0];
     }
 }
+
+void orc_curl_fd(int nx, int ny, int nz, const real* b, real* j) { orc_curl_fd_walls(nx, ny, nz, NULL, NULL, b, j); }
 
 /* Lorentz force density F = j x b (reading C2). */
 void orc_lorentz(long N, const real* j, const real* b, real* F)

@@ -178,3 +178,75 @@ def test_coupled_step_conserves_mass_and_mean_field():
     assert abs(S.fluid.f.sum() / m0 - 1) < 1e-14
     np.testing.assert_allclose(bb.sum(axis=(1, 2, 3)), b.sum(axis=(1, 2, 3)), atol=1e-14)
     assert abs(uu[2]).max() < 1e-15 and abs(bb[2]).max() < 1e-15  # planar fields stay planar
+
+
+# ---------------------------------------------------------------------------
+# walls (reading C3) and the Hartmann flow (Sec. III)
+
+def test_field_diffusion_between_walls():
+    """With b = 0 imposed at walls halfway outside nodes 0 and n - 1, the
+    mode sin(pi (y + 1/2) / n) decays at eta (pi / n)^2: the Dirichlet value
+    sits at the half-way wall, to second order."""
+    rates = []
+    for n in (8, 16, 32):
+        L = M.MagneticLattice(1, n, 1, 0.8, wall=(0, 1, 0))
+        s = np.sin(math.pi * (np.arange(n) + 0.5) / n)
+        b = np.zeros((3, 1, n, 1))
+        b[0, 0, :, 0] = 1e-3 * s
+        L.init(b)
+        for _ in range(50):
+            L.step()
+        a = L.fields()[0][0, 0, :, 0] @ s
+        for _ in range(200):
+            L.step()
+        c = L.fields()[0][0, 0, :, 0] @ s
+        eta = 0.3 * CSM2
+        rates.append(-math.log(c / a) / 200 / (eta * (math.pi / n) ** 2) - 1)
+    assert abs(rates[2]) < 5e-3
+    assert 3.5 < rates[0] / rates[1] < 4.5 and 3.5 < rates[1] / rates[2] < 4.5, rates
+
+
+def test_wall_value_is_reached_at_steady_state():
+    # a uniform field equal to the wall value is a steady state at rest
+    n = 10
+    bw = np.array([0.01, -0.02, 0.005])
+    L = M.MagneticLattice(1, n, 1, 0.7, wall=(0, 1, 0), b_wall=bw)
+    L.init(np.broadcast_to(bw.reshape(3, 1, 1, 1), (3, 1, n, 1)))
+    for _ in range(20):
+        L.step()
+    np.testing.assert_allclose(L.fields()[0][:, 0, :, 0], np.broadcast_to(bw[:, None], (3, n)), atol=1e-16)
+
+
+def hartmann_error(L, Ha, current, nu=0.1, umax=1e-3, relax=4.0):
+    """Relative L2 error of the steady Hartmann profile in a channel of width
+    L (walls at y = -1/2 and L - 1/2, the field (0, B0, 0) imposed there,
+    eta = nu, driven by a uniform force G).  With b_x = 0 at both walls the
+    one-dimensional MHD equations give
+    u(s) = G a^2 / (nu Ha tanh Ha) [1 - cosh(Ha s / a) / cosh Ha],
+    a = L / 2, Ha = B0 a / sqrt(nu eta) (the Hartmann number as the paper
+    defines it, B0 L / sqrt(4 rho nu eta))."""
+    a = L / 2.0
+    B0 = Ha * nu / a
+    G = umax * nu * Ha * math.tanh(Ha) / (a * a)
+    S = M.MHD(1, L, 1, 0.5 + 3 * nu, 0.5 + 4 * nu, current=current, wall=(0, 1, 0), b_wall=(0.0, B0, 0.0))
+    b = np.zeros((3, 1, L, 1))
+    b[1] = B0
+    S.init(np.ones((1, L, 1)), np.zeros((3, 1, L, 1)), b)
+    S.body_force = (G, 0.0, 0.0)
+    S.step(int(relax * a * a / nu))
+    u = S.state()[1][0, 0, :, 0]
+    s = np.arange(L) - (L - 1) / 2.0
+    ua = G * a * a / (nu * Ha * math.tanh(Ha)) * (1 - np.cosh(Ha * s / a) / math.cosh(Ha))
+    return float(np.linalg.norm(u - ua) / np.linalg.norm(ua))
+
+
+@pytest.mark.parametrize("current", ["populations", "stencil"])
+def test_hartmann_profile_converges(current):
+    """Hartmann flow (Sec. III) at Ha = 3: the steady velocity converges to the
+    analytic profile, at second order for the population current and close to
+    it for the stencil current (whose ghost value at the wall is one-sided)."""
+    e = [hartmann_error(L, 3.0, current) for L in (8, 16, 32)]
+    rates = [math.log2(e[k] / e[k + 1]) for k in range(2)]
+    assert e[2] < (5e-3 if current == "populations" else 1e-2), e
+    lo = 1.8 if current == "populations" else 1.5
+    assert all(r > lo for r in rates), (e, rates)
