@@ -30,7 +30,7 @@
  * - Cells: N = nz * ny * nx, x fastest; vector fields are [3][N] (component
  *   slowest), the layout of cmlbm_moments and cmlbm_set_force FIELD for one
  *   batch member.  Population arrays are [7][3][N] (velocity, component, cell).
- *   All axes are periodic.
+ *   Axes are periodic or carry walls (CMLBM_MHD_WALL).
  * - The two population buffers are caller-allocated (size from
  *   cmlbm_mhd_required_bytes, 256-byte aligned) and borrowed for the life of
  *   the handle; every other array is caller-owned.  No entry point allocates
@@ -60,6 +60,12 @@ extern "C" {
 #define CMLBM_MHD_FP64 0
 #define CMLBM_MHD_FP32 1
 
+/* per-axis boundary kinds */
+#define CMLBM_MHD_PERIODIC 0
+#define CMLBM_MHD_WALL 1 /* walls halfway outside the first and last node, where b takes the value set by
+                            cmlbm_mhd_set_wall_field (the Hartmann test); use the fluid's CMLBM_BOUNCEBACK
+                            on the same axes */
+
 /* current kinds of cmlbm_mhd_fields */
 #define CMLBM_MHD_CURRENT_POPULATIONS 0 /* from the non-equilibrium electric tensor */
 #define CMLBM_MHD_CURRENT_STENCIL 1     /* central differences of b (needs dev_b) */
@@ -67,9 +73,10 @@ extern "C" {
 typedef struct cmlbm_mhd_lattice cmlbm_mhd_lattice; /* opaque handle */
 
 typedef struct {
-    int32_t nx, ny, nz; /* lattice extent, each >= 1 */
+    int32_t nx, ny, nz; /* lattice extent, each >= 1 (>= 2 on a wall axis) */
     double tau_m;       /* magnetic relaxation time, > 1/2: eta = (tau_m - 1/2) / 4 */
     int32_t storage;    /* CMLBM_MHD_FP64 | CMLBM_MHD_FP32 */
+    int32_t wall[3];    /* x, y, z: CMLBM_MHD_PERIODIC or CMLBM_MHD_WALL */
     uint32_t flags;     /* reserved, must be 0 */
 } cmlbm_mhd_params;
 
@@ -83,11 +90,25 @@ int cmlbm_mhd_required_bytes(const cmlbm_mhd_params* params, size_t* pop_buffer_
 int cmlbm_mhd_create(const cmlbm_mhd_params* params, void* pop_a, size_t pop_a_bytes, void* pop_b,
                      size_t pop_b_bytes, cmlbm_mhd_lattice** out);
 
+/* The field b_w (host_b_wall[3]) imposed at every wall: a population that
+ * would stream into a wall returns as h_opp(x, t+1) = -h*_l(x, t) + 2 w_l b_w
+ * (anti-bounce-back: the Dirichlet value sits at the half-way wall), and the
+ * stencil current takes the ghost value 2 b_w - b beyond it.  The paper
+ * assigns the missing wall population from b = sum h instead (App. C); this
+ * halfway form matches the fluid's halfway bounce-back walls.  Host-only;
+ * default 0.  Set it before cmlbm_mhd_init. */
+int cmlbm_mhd_set_wall_field(cmlbm_mhd_lattice* lat, const double* host_b_wall);
+
+/* A uniform force density host_f0[3] added to every Lorentz force that
+ * cmlbm_mhd_fields writes (F = j x b + f0: the driving force of a channel such
+ * as the Hartmann test).  Host-only; default 0. */
+int cmlbm_mhd_set_body_force(cmlbm_mhd_lattice* lat, const double* host_f0);
+
 /* h = h^eq(b, u) from dev_b[3][N] (required) and dev_u[3][N] (NULL = rest). */
 int cmlbm_mhd_init(cmlbm_mhd_lattice* lat, const void* dev_b, const void* dev_u, void* hip_stream);
 
 /* From the current populations: b into dev_b[3][N], j into dev_j[3][N] and
- * the Lorentz force density F = j x b into dev_F[3][N] (each may be NULL;
+ * the Lorentz force density F = j x b (+ f0) into dev_F[3][N] (each may be NULL;
  * the STENCIL current needs dev_b, which it reads back).  dev_u[3][N] is the
  * fluid velocity for Lambda^eq (POPULATIONS current only; NULL = rest). */
 int cmlbm_mhd_fields(cmlbm_mhd_lattice* lat, const void* dev_u, int current, void* dev_b, void* dev_j, void* dev_F,

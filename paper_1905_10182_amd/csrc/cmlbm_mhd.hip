@@ -35,7 +35,24 @@ struct GeomM {
     int nxp;           // padded row length (elements)
     uint64_t pstride;  // elements per plane
     uint64_t ncell;    // nz * ny * nx
+    int wall[3];       // per axis: 0 periodic, 1 walls halfway outside the first and last node
+    double bw[3];      // field imposed at the walls
+    double f0[3];      // uniform force density added to the Lorentz force
 };
+
+// opposite D3Q7 direction: rest, then the pairs (+x, -x), (+y, -y), (+z, -z)
+__host__ __device__ constexpr int opp(int l) { return l == 0 ? 0 : ((l & 1) ? l + 1 : l - 1); }
+
+// Does the link from (x, y, z) against xi_l leave the box through a wall?
+__device__ __forceinline__ bool from_wall(const GeomM& g, int x, int y, int z, int l)
+{
+    const int s[3] = {x - xi(l, 0), y - xi(l, 1), z - xi(l, 2)};
+    const int n[3] = {g.nx, g.ny, g.nz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if (g.wall[a] && (s[a] < 0 || s[a] >= n[a])) return true;
+    return false;
+}
 
 __device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
@@ -52,12 +69,22 @@ __device__ __forceinline__ uint64_t plane_off(const GeomM& g, int x, int y, int 
     return ((uint64_t)z * (uint64_t)g.ny + (uint64_t)y) * (uint64_t)g.nxp + (uint64_t)x;
 }
 
-// Pull gather: h_l(x) = A_l(x - xi_l), periodic.
+// Pull gather: h_l(x) = A_l(x - xi_l) across periodic axes.  A link coming
+// in through a wall (the field is imposed there) is the anti-bounce-back of
+// the population that left towards it: h_l(x) = -h*_opp(l)(x) + 2 w_l b_w,
+// which puts the Dirichlet value at the half-way wall.
 template <typename T>
 __device__ __forceinline__ void gather(const T* __restrict__ A, const GeomM& g, int x, int y, int z, T h[7][3])
 {
 #pragma unroll
     for (int l = 0; l < 7; ++l) {
+        if (l > 0 && from_wall(g, x, y, z, l)) {
+            const uint64_t own = plane_off(g, x, y, z);
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                h[l][a] = -A[(uint64_t)(3 * opp(l) + a) * g.pstride + own] + T(2.0 * wm(l) * g.bw[a]);
+            continue;
+        }
         const uint64_t s = plane_off(g, wrap(x - xi(l, 0), g.nx), wrap(y - xi(l, 1), g.ny), wrap(z - xi(l, 2), g.nz));
 #pragma unroll
         for (int a = 0; a < 3; ++a) h[l][a] = A[(uint64_t)(3 * l + a) * g.pstride + s];
@@ -109,7 +136,8 @@ __device__ __forceinline__ void store_nt(T* p, T v)
 }
 
 // h = h^eq(b, u) or imported FP64 populations, written through the inverse
-// of the pull gather: A_l(x - xi_l) = h_l(x).
+// of the pull gather: A_l(x - xi_l) = h_l(x), or for a link coming in through
+// a wall A_opp(l)(x) = 2 w_l b_w - h_l(x).
 template <typename T, bool POPS>
 __global__ __launch_bounds__(kBlock) void k_mhd_init(T* __restrict__ dst, GeomM g, const T* __restrict__ b_in,
                                                      const T* __restrict__ u_in, const double* __restrict__ pops)
@@ -132,6 +160,13 @@ __global__ __launch_bounds__(kBlock) void k_mhd_init(T* __restrict__ dst, GeomM 
     }
 #pragma unroll
     for (int l = 0; l < 7; ++l) {
+        if (l > 0 && from_wall(g, x, y, z, l)) {
+            const uint64_t own = plane_off(g, x, y, z);
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                dst[(uint64_t)(3 * opp(l) + a) * g.pstride + own] = T(2.0 * wm(l) * g.bw[a]) - e[l][a];
+            continue;
+        }
         const uint64_t d = plane_off(g, wrap(x - xi(l, 0), g.nx), wrap(y - xi(l, 1), g.ny), wrap(z - xi(l, 2), g.nz));
 #pragma unroll
         for (int a = 0; a < 3; ++a) dst[(uint64_t)(3 * l + a) * g.pstride + d] = e[l][a];
@@ -160,12 +195,13 @@ __global__ __launch_bounds__(kBlock) void k_mhd_step(const T* __restrict__ src, 
             store_nt(dst + (uint64_t)(3 * l + a) * g.pstride + own, h[l][a] + omega * (e[l][a] - h[l][a]));
 }
 
+// F = j x b + f0
 template <typename T>
-__device__ __forceinline__ void cross(const T j[3], const T b[3], T F[3])
+__device__ __forceinline__ void lorentz(const GeomM& g, const T j[3], const T b[3], T F[3])
 {
-    F[0] = j[1] * b[2] - j[2] * b[1];
-    F[1] = j[2] * b[0] - j[0] * b[2];
-    F[2] = j[0] * b[1] - j[1] * b[0];
+    F[0] = j[1] * b[2] - j[2] * b[1] + T(g.f0[0]);
+    F[1] = j[2] * b[0] - j[0] * b[2] + T(g.f0[1]);
+    F[2] = j[0] * b[1] - j[1] * b[0] + T(g.f0[2]);
 }
 
 template <typename T>
@@ -177,7 +213,7 @@ __device__ __forceinline__ void store_vec(T* __restrict__ v, const GeomM& g, uin
 }
 
 // b = sum_l h_l and, with POP, the population current
-// j_c = -eps_cba (Lambda - Lambda^eq)_ba / (tau_m cs^2) and F = j x b.
+// j_c = -eps_cba (Lambda - Lambda^eq)_ba / (tau_m cs^2) and F = j x b + f0.
 template <typename T, bool POP>
 __global__ __launch_bounds__(kBlock) void k_mhd_fields(const T* __restrict__ src, GeomM g, T tau_m,
                                                        const T* __restrict__ u_in, T* __restrict__ b_out,
@@ -205,14 +241,15 @@ __global__ __launch_bounds__(kBlock) void k_mhd_fields(const T* __restrict__ src
         store_vec(j_out, g, n, j);
         if (F_out) {
             T F[3];
-            cross(j, b, F);
+            lorentz(g, j, b, F);
             store_vec(F_out, g, n, F);
         }
     }
 }
 
-// Central-difference curl of b ([3][N], periodic; an axis of extent 1 has no
-// derivative) and F = j x b.
+// Central-difference curl of b ([3][N]; periodic axes, beyond a wall the
+// ghost value 2 b_w - b(x); an axis of extent 1 has no derivative) and
+// F = j x b.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_mhd_curl(GeomM g, const T* __restrict__ b, T* __restrict__ j_out,
                                                      T* __restrict__ F_out)
@@ -223,19 +260,33 @@ __global__ __launch_bounds__(kBlock) void k_mhd_curl(GeomM g, const T* __restric
     coords(g, n, x, y, z);
     const uint64_t row = (uint64_t)g.nx, sl = (uint64_t)g.nx * (uint64_t)g.ny;
     auto at = [&](int xx, int yy, int zz) { return (uint64_t)zz * sl + (uint64_t)yy * row + (uint64_t)xx; };
-    const uint64_t xp = at(wrap(x + 1, g.nx), y, z), xm = at(wrap(x - 1, g.nx), y, z);
-    const uint64_t yp = at(x, wrap(y + 1, g.ny), z), ym = at(x, wrap(y - 1, g.ny), z);
-    const uint64_t zp = at(x, y, wrap(z + 1, g.nz)), zm = at(x, y, wrap(z - 1, g.nz));
-    auto d = [&](int c, uint64_t p, uint64_t m, int ext) {
-        return ext > 1 ? T(0.5) * (b[(uint64_t)c * g.ncell + p] - b[(uint64_t)c * g.ncell + m]) : T(0);
+    const int c[3] = {x, y, z}, ext[3] = {g.nx, g.ny, g.nz};
+    // derivative along axis a of component q
+    auto d = [&](int a, int q) -> T {
+        if (ext[a] < 2) return T(0);
+        const T here = b[(uint64_t)q * g.ncell + n];
+        T v[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            int p[3] = {x, y, z};
+            p[a] = c[a] + (k == 0 ? 1 : -1);
+            if (p[a] < 0 || p[a] >= ext[a]) {
+                if (g.wall[a]) {
+                    v[k] = T(2.0 * g.bw[q]) - here;
+                    continue;
+                }
+                p[a] = wrap(p[a], ext[a]);
+            }
+            v[k] = b[(uint64_t)q * g.ncell + at(p[0], p[1], p[2])];
+        }
+        return T(0.5) * (v[0] - v[1]);
     };
-    const T j[3] = {d(2, yp, ym, g.ny) - d(1, zp, zm, g.nz), d(0, zp, zm, g.nz) - d(2, xp, xm, g.nx),
-                    d(1, xp, xm, g.nx) - d(0, yp, ym, g.ny)};
+    const T j[3] = {d(1, 2) - d(2, 1), d(2, 0) - d(0, 2), d(0, 1) - d(1, 0)};
     store_vec(j_out, g, n, j);
     if (F_out) {
         T bb[3], F[3];
         load_vec(b, g, n, bb);
-        cross(j, bb, F);
+        lorentz(g, j, bb, F);
         store_vec(F_out, g, n, F);
     }
 }
@@ -278,6 +329,14 @@ int make_geom(const cmlbm_mhd_params* p, GeomM* g, size_t* bytes)
     if (!(p->tau_m > 0.5) || !std::isfinite(p->tau_m)) return CMLBM_MHD_EINVAL;
     if (p->storage != CMLBM_MHD_FP64 && p->storage != CMLBM_MHD_FP32) return CMLBM_MHD_EINVAL;
     if (p->flags != 0) return CMLBM_MHD_EINVAL;
+    const int dims[3] = {p->nx, p->ny, p->nz};
+    for (int a = 0; a < 3; ++a) {
+        if (p->wall[a] != CMLBM_MHD_PERIODIC && p->wall[a] != CMLBM_MHD_WALL) return CMLBM_MHD_EINVAL;
+        if (p->wall[a] == CMLBM_MHD_WALL && dims[a] < 2) return CMLBM_MHD_EINVAL;
+        g->wall[a] = p->wall[a];
+        g->bw[a] = 0.0;
+        g->f0[a] = 0.0;
+    }
     const size_t sb = p->storage == CMLBM_MHD_FP64 ? 8 : 4;
     g->nx = p->nx;
     g->ny = p->ny;
@@ -368,6 +427,24 @@ int cmlbm_mhd_create(const cmlbm_mhd_params* params, void* pop_a, size_t pop_a_b
     lat->initialized = false;
     lat->t = 0;
     *out = lat;
+    return CMLBM_MHD_OK;
+}
+
+int cmlbm_mhd_set_wall_field(cmlbm_mhd_lattice* lat, const double* host_b_wall)
+{
+    if (!lat || !host_b_wall) return CMLBM_MHD_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(host_b_wall[a])) return fail(lat, CMLBM_MHD_EINVAL, "non-finite wall field");
+    for (int a = 0; a < 3; ++a) lat->g.bw[a] = host_b_wall[a];
+    return CMLBM_MHD_OK;
+}
+
+int cmlbm_mhd_set_body_force(cmlbm_mhd_lattice* lat, const double* host_f0)
+{
+    if (!lat || !host_f0) return CMLBM_MHD_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(host_f0[a])) return fail(lat, CMLBM_MHD_EINVAL, "non-finite body force");
+    for (int a = 0; a < 3; ++a) lat->g.f0[a] = host_f0[a];
     return CMLBM_MHD_OK;
 }
 

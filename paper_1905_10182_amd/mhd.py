@@ -17,17 +17,19 @@ LIB_PATH = os.path.join(_PKG, "libcmlbm_mhd.so")
 OK, EINVAL, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -5
 FP64, FP32 = 0, 1
 STORAGE = {"fp64": FP64, "fp32": FP32}
+PERIODIC, WALL = 0, 1
 CURRENT = {"populations": 0, "stencil": 1}
 
 # Every entry point declared in include/cmlbm_mhd.h.
-EXPORTS = ["cmlbm_mhd_required_bytes", "cmlbm_mhd_create", "cmlbm_mhd_init", "cmlbm_mhd_fields", "cmlbm_mhd_step",
-           "cmlbm_mhd_populations", "cmlbm_mhd_load_populations", "cmlbm_mhd_get_time", "cmlbm_mhd_destroy",
-           "cmlbm_mhd_last_error", "cmlbm_mhd_status_string"]
+EXPORTS = ["cmlbm_mhd_required_bytes", "cmlbm_mhd_create", "cmlbm_mhd_set_wall_field", "cmlbm_mhd_set_body_force",
+           "cmlbm_mhd_init", "cmlbm_mhd_fields", "cmlbm_mhd_step", "cmlbm_mhd_populations",
+           "cmlbm_mhd_load_populations", "cmlbm_mhd_get_time", "cmlbm_mhd_destroy", "cmlbm_mhd_last_error",
+           "cmlbm_mhd_status_string"]
 
 
 class Params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("tau_m", ctypes.c_double),
-                ("storage", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("storage", ctypes.c_int32), ("wall", ctypes.c_int32 * 3), ("flags", ctypes.c_uint32)]
 
 
 class MhdError(RuntimeError):
@@ -51,6 +53,8 @@ def load_library():
     P = ctypes.POINTER(Params)
     lib.cmlbm_mhd_required_bytes.argtypes = [P, ctypes.POINTER(sz)]
     lib.cmlbm_mhd_create.argtypes = [P, vp, sz, vp, sz, ctypes.POINTER(vp)]
+    lib.cmlbm_mhd_set_wall_field.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    lib.cmlbm_mhd_set_body_force.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     lib.cmlbm_mhd_init.argtypes = [vp, vp, vp, vp]
     lib.cmlbm_mhd_fields.argtypes = [vp, vp, ctypes.c_int, vp, vp, vp, vp]
     lib.cmlbm_mhd_step.argtypes = [vp, vp, vp]
@@ -76,13 +80,20 @@ def _status_string(code):
         return str(code)
 
 
-def make_params(nx, ny, nz, tau_m=0.8, storage="fp64", flags=0):
+def make_params(nx, ny, nz, tau_m=0.8, storage="fp64", wall=(0, 0, 0), flags=0):
     p = Params()
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
     p.tau_m = float(tau_m)
     p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    for a in range(3):
+        p.wall[a] = int(wall[a])
     p.flags = int(flags)
     return p
+
+
+def _host3(v):
+    a = (ctypes.c_double * 3)(*[float(x) for x in np.asarray(v, np.float64).ravel()])
+    return a
 
 
 def required_bytes(params):
@@ -99,14 +110,15 @@ def _ptr(t):
 
 class MagneticLattice:
     """One magnetic-lattice handle over torch-allocated device buffers.
-    Vector fields are (3, nz, ny, nx) tensors of the storage dtype."""
+    Vector fields are (3, nz, ny, nx) tensors of the storage dtype.  `wall`
+    flags axes (x, y, z) with walls, where b takes the value b_wall."""
 
-    def __init__(self, nx, ny, nz, tau_m, storage="fp64", device="cuda"):
+    def __init__(self, nx, ny, nz, tau_m, storage="fp64", device="cuda", wall=(0, 0, 0), b_wall=None):
         import torch
 
         self.torch = torch
         self.lib = load_library()
-        self.params = make_params(nx, ny, nz, tau_m, storage)
+        self.params = make_params(nx, ny, nz, tau_m, storage, wall)
         self.shape = (int(nz), int(ny), int(nx))
         self.dtype = torch.float64 if self.params.storage == FP64 else torch.float32
         self.device = torch.device(device)
@@ -119,6 +131,15 @@ class MagneticLattice:
         if rc != OK:
             raise MhdError(rc, "cmlbm_mhd_create failed")
         self.handle = h
+        if b_wall is not None:
+            self.set_wall_field(b_wall)
+
+    def set_wall_field(self, b_wall):
+        self._check(self.lib.cmlbm_mhd_set_wall_field(self.handle, _host3(b_wall)), "set_wall_field")
+
+    def set_body_force(self, f0):
+        """Uniform force density added to the Lorentz force that fields() writes."""
+        self._check(self.lib.cmlbm_mhd_set_body_force(self.handle, _host3(f0)), "set_body_force")
 
     def _stream(self):
         return ctypes.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
@@ -196,13 +217,19 @@ class CoupledMHD:
       (c) u = fluid velocity with F;
       (d) magnetic collision towards h^eq(b, u) and streaming;
       (e) fluid step with F.
-    `model` is a fluid collision model of cmlbm.MODELS (m1, m4, m5, ...)."""
+    `model` is a fluid collision model of cmlbm.MODELS (m1, m4, m5, ...).
+    `wall` flags axes with walls for both lattices (fluid: halfway
+    bounce-back; field: b = b_wall there); `body_force` is a uniform force
+    density added to the Lorentz force (the driving of a channel)."""
 
-    def __init__(self, nx, ny, nz, tau, tau_m, storage="fp64", model="m1", current="populations", device="cuda:0"):
+    def __init__(self, nx, ny, nz, tau, tau_m, storage="fp64", model="m1", current="populations", device="cuda:0",
+                 wall=(0, 0, 0), b_wall=None, body_force=None):
         from .cmlbm import Lattice
 
-        self.fluid = Lattice(nx, ny, nz, tau=tau, storage=storage, model=model, device=device)
-        self.mag = MagneticLattice(nx, ny, nz, tau_m, storage=storage, device=device)
+        self.fluid = Lattice(nx, ny, nz, tau=tau, storage=storage, model=model, wall=wall, device=device)
+        self.mag = MagneticLattice(nx, ny, nz, tau_m, storage=storage, device=device, wall=wall, b_wall=b_wall)
+        if body_force is not None:
+            self.mag.set_body_force(body_force)
         self.torch = self.mag.torch
         self.current = current
         self.shape = (int(nz), int(ny), int(nx))

@@ -7,6 +7,7 @@
     python -m paper_1905_10182_amd.studies droplet [--n 200] [--steps 3000]
     python -m paper_1905_10182_amd.studies orszag-tang [--n 256] [--models m1,m5] [--current populations]
     python -m paper_1905_10182_amd.studies orszag-tang-3d [--n 64] [--models m1,m4,m5] [--re 100]
+    python -m paper_1905_10182_amd.studies hartmann [--current populations|stencil]
 
 ``precision``: the 3D Taylor-Green vortex (u0 = 0.05, Re = 1600) advanced in
 lockstep with FP64, FP32, FP16 and BF16 population storage (16-bit both with
@@ -47,6 +48,10 @@ b = u0 (-sin y, sin 2x) on a 2 pi box, Ma = u0 / cs in {0.07, 0.14, 0.28},
 Re = u0 (N / 2 pi) / nu = 1600, eta = nu, FP64.  Every 0.1 time units (in
 units of (N / 2 pi) / u0 steps) it reports the kinetic energy relative to its
 initial value and the peak current and vorticity in the same units.
+
+``hartmann``: the Hartmann flow of the MHD tests (Sec. III) for Ha = 1, 3,
+10, 20 and channel widths L = 8..128: error of the steady velocity against
+the analytic profile and the observed order.
 
 ``orszag-tang-3d``: the three-dimensional Orszag-Tang vortex of Sec. III
 (u0 = b0 = 0.0203, Re = 100 by default), peak current magnitude over time for
@@ -304,6 +309,48 @@ def orszag_tang_3d_study(ns=(32, 64, 128), re=100.0, models=("m1",), current="st
     return rows
 
 
+def hartmann_study(Ls=(8, 16, 32, 64, 128), has=(1.0, 3.0, 10.0, 20.0), current="populations", nu=0.1, umax=1e-3,
+                   storage="fp64", out=sys.stdout):
+    """Hartmann flow (Sec. III): a channel of width L between halfway walls at
+    which the field (0, B0, 0) is imposed, eta = nu, driven by a uniform force;
+    relative L2 error of the steady velocity against
+    u(s) = G a^2 / (nu Ha tanh Ha) [1 - cosh(Ha s / a) / cosh Ha] (a = L / 2,
+    b_x = 0 at both walls), and the observed order between successive L."""
+    import math
+
+    from paper_1905_10182_amd.mhd import CoupledMHD
+
+    rows = []
+    for ha in has:
+        prev = None
+        for L in Ls:
+            a = L / 2.0
+            B0 = ha * nu / a
+            G = umax * nu * ha * math.tanh(ha) / (a * a)
+            b = np.zeros((3, 1, L, 1))
+            b[1] = B0
+            S = CoupledMHD(1, L, 1, 0.5 + 3 * nu, 0.5 + 4 * nu, storage=storage, current=current, wall=(0, 1, 0),
+                           b_wall=(0.0, B0, 0.0), body_force=(G, 0.0, 0.0))
+            S.init(np.ones((1, L, 1)), np.zeros((3, 1, L, 1)), b)
+            # twelve e-foldings of the slowest mode: with eta = nu the Elsasser variables u +- b are
+            # advected at +-B0 and diffuse with nu, rate nu (pi^2 + Ha^2) / (4 a^2)
+            steps = int(48 * a * a / (nu * (math.pi ** 2 + ha * ha))) + 200
+            t0 = time.perf_counter()
+            S.step(steps)
+            u = S.state()[1][0, 0, :, 0].double().cpu().numpy()
+            s = np.arange(L) - (L - 1) / 2.0
+            ua = G * a * a / (nu * ha * math.tanh(ha)) * (1 - np.cosh(ha * s / a) / math.cosh(ha))
+            err = float(np.linalg.norm(u - ua) / np.linalg.norm(ua))
+            row = {"study": "hartmann", "ha": ha, "L": L, "current": current, "steps": steps, "error": err,
+                   "order": None if prev is None else math.log2(prev / err),
+                   "seconds": round(time.perf_counter() - t0, 2)}
+            print(json.dumps(row), file=out, flush=True)
+            rows.append(row)
+            prev = err
+            del S
+    return rows
+
+
 def stability_study(n=128, res=(1600.0, 1e4, 1e5), models=("m1", "bgk", "bgk6"), steps=4000, every=200,
                     storage="fp32", out=sys.stdout):
     rows = []
@@ -380,7 +427,7 @@ def droplet_study(n=200, radius=40.0, models=("m1", "m4", "m5"), steps=3000, sto
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("study", choices=["precision", "kolmogorov", "four-rolls", "stability", "droplet",
-                                      "orszag-tang", "orszag-tang-3d"])
+                                      "orszag-tang", "orszag-tang-3d", "hartmann"])
     ap.add_argument("--storage", default="fp64")
     ap.add_argument("--models", default="m1", help="comma-separated: m1 (the method), m4, m5, eq2")
     ap.add_argument("--lattice", default="d3q27", choices=["d3q27", "d2q9"])
@@ -400,6 +447,8 @@ def main(argv=None):
         stability_study(**kw)
     elif a.study == "orszag-tang":
         orszag_tang_study(ns=(a.n or 256,), models=tuple(a.models.split(",")), current=a.current, tmax=a.tmax)
+    elif a.study == "hartmann":
+        hartmann_study(current=a.current)
     elif a.study == "orszag-tang-3d":
         orszag_tang_3d_study(ns=(a.n,) if a.n else (32, 64, 128), re=a.re or 100.0,
                              models=tuple(a.models.split(",")), tmax=a.tmax)

@@ -49,9 +49,9 @@ def test_required_bytes_padding():
 
 
 @pytest.mark.parametrize("kw", [dict(tau_m=0.5), dict(tau_m=float("nan")), dict(nx=0), dict(nz=-1),
-                                dict(storage=2), dict(flags=1)])
+                                dict(storage=2), dict(flags=1), dict(wall=(0, 2, 0)), dict(wall=(0, 0, 1))])
 def test_invalid_params(lib, kw):
-    base = dict(nx=16, ny=8, nz=1, tau_m=0.8, storage="fp64", flags=0)
+    base = dict(nx=16, ny=8, nz=1, tau_m=0.8, storage="fp64", wall=(0, 0, 0), flags=0)
     base.update(kw)
     p = B.make_params(**base)
     n = ctypes.c_size_t()
@@ -79,3 +79,20 @@ def test_create_and_state_errors(lib):
         assert lib.cmlbm_mhd_get_time(h, ctypes.byref(t)) == B.OK and t.value == 0
     finally:
         assert lib.cmlbm_mhd_destroy(h) == B.OK
+
+
+def test_wall_field_and_body_force_validation(lib):
+    p = B.make_params(4, 8, 1, wall=(0, 1, 0))
+    need = B.required_bytes(p)
+    h = ctypes.c_void_p()
+    assert lib.cmlbm_mhd_create(ctypes.byref(p), FAKE_A, need, FAKE_B, need, ctypes.byref(h)) == B.OK
+    try:
+        good = (ctypes.c_double * 3)(0.0, 0.05, 0.0)
+        bad = (ctypes.c_double * 3)(0.0, float("inf"), 0.0)
+        assert lib.cmlbm_mhd_set_wall_field(h, good) == B.OK
+        assert lib.cmlbm_mhd_set_wall_field(h, bad) == B.EINVAL
+        assert lib.cmlbm_mhd_set_wall_field(h, None) == B.EINVAL
+        assert lib.cmlbm_mhd_set_body_force(h, good) == B.OK
+        assert lib.cmlbm_mhd_set_body_force(h, bad) == B.EINVAL
+    finally:
+        lib.cmlbm_mhd_destroy(h)
