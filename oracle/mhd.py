@@ -80,7 +80,7 @@ def lorentz(j, b):
 class MagneticLattice:
     """The D3Q7 magnetic lattice alone on an nx * ny * nz box: periodic axes,
     or walls halfway between nodes on the axes flagged in `wall` (x, y, z)
-    where b takes the value b_wall (reading C3).  State h (7, 3, nz, ny, nx);
+    where b takes the value b_wall (reading C6).  State h (7, 3, nz, ny, nx);
     tau_m the magnetic relaxation time, eta = (tau_m - 1/2) / 4."""
 
     def __init__(self, nx, ny, nz, tau_m, extended=False, wall=(0, 0, 0), b_wall=(0.0, 0.0, 0.0)):

@@ -23,7 +23,9 @@
  *       difference curl of b is the alternative ("stencil") current.
  *   C2  The Lorentz force F = j x b is a force density (b in units where the
  *       magnetic pressure is |b|^2/2).
- *   C3  Periodic axes, or walls halfway between nodes on the axes flagged in
+ *   (C3, the order of the stages within a coupled step, is sequenced by the
+ *   Python wrapper mhd.py.)
+ *   C6  Periodic axes, or walls halfway between nodes on the axes flagged in
  *       `wall`: the magnetic field takes a given value b_w at the wall (the
  *       Hartmann test imposes it there).  A population that would stream into
  *       the wall comes back as h_opp(l)(x, t+1) = -h*_l(x, t) + 2 w_l b_w
@@ -99,7 +101,7 @@ static void cell_b(const real* h, long N, long n, real b[3])
 
 /* One step: collide every cell towards h^eq(b, u) with rate omega_m, then
  * stream, h_l(x + xi_l) = h*_l(x), periodic or through the wall rule of
- * reading C3 (wall[3] flags per axis, b_wall[3]; both may be NULL = periodic).
+ * reading C6 (wall[3] flags per axis, b_wall[3]; both may be NULL = periodic).
  * u is [3][N] or NULL. */
 void orc_mhd_step_walls(int nx, int ny, int nz, const int* wall, const real* b_wall, const real* u, real omega_m,
                         real* h, real* tmp);
@@ -177,7 +179,7 @@ void orc_mhd_fields(int nx, int ny, int nz, const real* u, real tau_m, const rea
 }
 
 /* Central-difference curl of b ([3][N]) into j: periodic axes, or (wall[a]
- * set) the ghost value 2 b_wall - b(x) beyond a wall (reading C3).  wall and
+ * set) the ghost value 2 b_wall - b(x) beyond a wall (reading C6).  wall and
  * b_wall may be NULL (periodic). */
 void orc_curl_fd_walls(int nx, int ny, int nz, const int* wall, const real* b_wall, const real* b, real* j)
 {
