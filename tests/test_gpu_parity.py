@@ -559,14 +559,15 @@ def ulp16(h, storage):
 
 
 @pytest.mark.parametrize("storage", ["fp16", "bf16"])
-@pytest.mark.parametrize("nx", [40, 42, 37, 264])
+@pytest.mark.parametrize("nx", [40, 42, 37, 264, 128])
 def test_16bit_one_step_every_cell_is_rounded_oracle(torch, storage, nx):
     """Every post-collision population of one step equals the oracle's value
     rounded to nearest in the 16-bit format: |error| <= half a unit in the
     last place plus the FP32 arithmetic error (bounded by 2e-7 w_i; the FP32
-    path itself stays below 1e-7 w_i).  nx = 40 and 264 run the
-    4-cells-per-lane kernel (one partial wave per row / a row over several
-    waves), 42 the 2-cell one, 37 the one-cell one."""
+    path itself stays below 1e-7 w_i).  nx = 40, 42 and 264 run the
+    2-cells-per-lane kernel (one partial wave per row / a row over several
+    waves), 128 it with a row of exactly one wave (the lane rotation is the
+    periodic wrap), 37 the one-cell one."""
     log(f"{storage} one step, every cell, {nx}x12x10")
     got, ref = sampled_one_step(torch, max(nx, 64), storage, None, 0, dims=(nx, 12, 10), re=200.0)
     h_ref = ref - WGT[:, None]
