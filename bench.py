@@ -120,6 +120,45 @@ def run_gpu_2d(n, storage, steps, warmup):
                 launch_s=secs / steps, bytes_per_launch=BYTES_PER_CELL_2D[storage] * ncell, mass_drift=mass_drift)
 
 
+# magnetic lattice (FP32): 21 populations read + 21 written, u (3 values) read
+BYTES_PER_CELL_MHD = 21 * 4 * 2 + 12
+
+
+def run_gpu_mhd(n, steps, warmup):
+    """The magnetic lattice alone (FP32, n^3, periodic) stepped with a fixed
+    velocity field: 21 populations read and written per cell plus u read."""
+    import numpy as np
+    import torch
+
+    from paper_1905_10182_amd.mhd import MagneticLattice
+
+    lat = MagneticLattice(n, n, n, 0.8, storage="fp32", device="cuda:0")
+    c = torch.arange(n, device="cuda:0", dtype=torch.float32) * (2 * math.pi / n)
+    z, y, x = torch.meshgrid(c, c, c, indexing="ij")
+    b = torch.stack([torch.sin(y), torch.sin(z), torch.sin(x)]) * 0.01
+    u = (torch.stack([torch.sin(z), torch.sin(x), torch.sin(y)]) * 0.02).contiguous()
+    lat.init(b, u)
+    del b, x, y, z
+    for _ in range(warmup):
+        lat.step(u)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        lat.step(u)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    secs = e0.elapsed_time(e1) / 1e3
+    bf, _ = lat.fields()
+    assert bool(torch.isfinite(bf).all()), "non-finite magnetic field"
+    del lat, u, bf
+    torch.cuda.empty_cache()
+    ncell = n ** 3
+    return dict(glups=ncell * steps / secs / 1e9, ms_per_step=secs / steps * 1e3,
+                bytes_per_launch=BYTES_PER_CELL_MHD * ncell, launch_s=secs / steps)
+
+
 def copy_bandwidth():
     import torch
     n = 1 << 30  # 4 GiB of float32
@@ -223,6 +262,7 @@ def main():
     ap.add_argument("--no-warmstart", action="store_true")
     ap.add_argument("--no-mom", action="store_true")
     ap.add_argument("--no-d2q9", action="store_true")
+    ap.add_argument("--no-mhd", action="store_true")
     ap.add_argument("--cpu-detail", action="store_true", help="only time the oracle on the host in detail")
     ap.add_argument("--n", type=int, default=256)
     args = ap.parse_args()
@@ -286,6 +326,15 @@ def main():
             print(f"[bench] D2Q9 {st} {r2['glups']:.2f} GLUPS", file=sys.stderr, flush=True)
         extra["d2q9"] = {"workload": f"four_rolls_mill_2d_{n2} (App. B model, Re 100, u0 1e-3, per-cell force field)",
                          **res2}
+    if not args.no_mhd:
+        print("[bench] magnetic lattice 256^3 fp32", file=sys.stderr, flush=True)
+        rmag = run_gpu_mhd(256, max(args.steps // 10, 10), 3)
+        bw = rmag["bytes_per_launch"] / rmag["launch_s"] / 1e9
+        extra["mhd_magnetic_lattice"] = {
+            "workload": "D3Q7 vector populations (App. C), 256^3 periodic, fp32, fixed velocity field",
+            "kernel": "k_mhd_step<float>", "glups": round(rmag["glups"], 3), "ms_per_step": round(rmag["ms_per_step"], 4),
+            "bytes_per_cell": BYTES_PER_CELL_MHD, "hbm_gbs": round(bw, 1), "hbm_frac": round(bw / HBM_PEAK_GBS, 4)}
+        print(f"[bench] magnetic lattice {rmag['glups']:.2f} GLUPS, {bw:.0f} GB/s", file=sys.stderr, flush=True)
     extra["device_copy_gbs"] = round(copy_bandwidth(), 1)
     if not args.no_warmstart:
         print("[bench] warm start: 64 sphere channels 64x32x32, cold vs U-Net init", file=sys.stderr, flush=True)
