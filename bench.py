@@ -258,7 +258,7 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-fp16", action="store_true")
+    ap.add_argument("--no-fp16", action="store_true", help="skip the FP16, BF16 and FP64 storage legs")
     ap.add_argument("--no-warmstart", action="store_true")
     ap.add_argument("--no-mom", action="store_true")
     ap.add_argument("--no-d2q9", action="store_true")
@@ -298,6 +298,23 @@ def main():
             "hbm_frac": round(r16s["bytes_per_launch"] / r16s["launch_s"] / 1e9 / HBM_PEAK_GBS, 4),
             "speedup_vs_fp32_glups": round(r16s["glups"] / main_run["glups"], 3)}
         print(f"[bench] fp16 stochastic rounding {r16s['glups']:.2f} GLUPS", file=sys.stderr, flush=True)
+        print(f"[bench] TGV {n16}^3 bf16 storage", file=sys.stderr, flush=True)
+        rb = run_gpu(n16, "bf16", max(args.steps // 4, 10), max(args.warmup // 4, 5))
+        extra["bf16_storage"] = {
+            "kernel": STEP_KERNEL["bf16"], "glups": round(rb["glups"], 3), "ms_per_step": round(rb["ms_per_step"], 4),
+            "hbm_gbs": round(rb["bytes_per_launch"] / rb["launch_s"] / 1e9, 1),
+            "hbm_frac": round(rb["bytes_per_launch"] / rb["launch_s"] / 1e9 / HBM_PEAK_GBS, 4),
+            "speedup_vs_fp32_glups": round(rb["glups"] / main_run["glups"], 3)}
+        print(f"[bench] bf16 {rb['glups']:.2f} GLUPS", file=sys.stderr, flush=True)
+        print(f"[bench] TGV {args.n}^3 fp64 storage", file=sys.stderr, flush=True)
+        r64 = run_gpu(args.n, "fp64", max(args.steps // 4, 10), max(args.warmup // 4, 5))
+        extra["fp64_storage"] = {
+            "workload": f"taylor_green_{args.n}, fp64 populations and arithmetic",
+            "kernel": STEP_KERNEL["fp64"], "glups": round(r64["glups"], 3), "ms_per_step": round(r64["ms_per_step"], 4),
+            "bytes_per_cell": BYTES_PER_CELL["fp64"],
+            "hbm_gbs": round(r64["bytes_per_launch"] / r64["launch_s"] / 1e9, 1),
+            "hbm_frac": round(r64["bytes_per_launch"] / r64["launch_s"] / 1e9 / HBM_PEAK_GBS, 4)}
+        print(f"[bench] fp64 {r64['glups']:.2f} GLUPS", file=sys.stderr, flush=True)
     if not args.no_mom:
         for nm in sorted({args.n, 512 if args.n == 256 else args.n}):
             print(f"[bench] TGV {nm}^3 moment storage (FP32)", file=sys.stderr, flush=True)

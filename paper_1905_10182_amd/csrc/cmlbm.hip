@@ -37,7 +37,7 @@ constexpr int kNPart = 10;    // partial-sum slots of k_reduce
 constexpr int kModelGuo = 1;  // second-order forcing term
 constexpr int kModelEq2 = 2;  // second-order equilibrium
 constexpr int kModelBgk = 4;  // single relaxation time
-constexpr int kMaxRedBlocks = 256;  // reduce workgroups per batch member
+constexpr int kMaxRedBlocks = 2048;  // reduce workgroups per batch member (half that for FP64 storage)
 constexpr uint32_t kSolidBit = 1u << 27;
 constexpr size_t kPlanePad = 4096;  // bytes between consecutive population planes (a multiple of 256)
 
@@ -861,9 +861,10 @@ __global__ __launch_bounds__(kBlock) void k_gather(const typename storage<ST>::S
     }
 }
 
-// FP64 reductions.  Each batch member is split into `gpb` workgroups that
-// stride over its cells; every workgroup writes kNPart partial values, summed
-// in a fixed tree order, so results are reproducible bit for bit.
+// FP64 reductions.  Each batch member is split into `gpb` workgroups whose
+// waves stride over its 64-cell row segments (wave-uniform row arithmetic, as
+// in k_step); every workgroup writes kNPart partial values, summed in a fixed
+// tree order, so results are reproducible bit for bit.
 template <int ST, bool MASK>
 __global__ __launch_bounds__(kBlock) void k_reduce(const typename storage<ST>::S* __restrict__ src, Geom g,
                                                    double rho0, const double* __restrict__ ftab,
@@ -875,18 +876,24 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const typename storage<ST>::S
     const int b = blockIdx.x / gpb;
     const int gblk = blockIdx.x % gpb;
     const int tid = threadIdx.x;
-    const uint64_t per = (uint64_t)g.nz * g.ny * g.nx;
+    const int lane = tid & 63;
+    const int segs = (g.nx + 63) >> 6;
+    const int rows = g.nz * g.ny;  // rows of one batch member
+    const int nseg = rows * segs;
+    const int nwaves = gpb * (kBlock / 64);
+    const int wave0 = __builtin_amdgcn_readfirstlane(gblk * (kBlock / 64) + (tid >> 6));
     double acc[kNPart];
     for (int k = 0; k < kNPart; ++k) acc[k] = 0.0;
-    for (uint64_t k = (uint64_t)gblk * kBlock + tid; k < per; k += (uint64_t)gpb * kBlock) {
-        const int x = (int)(k % g.nx);
-        const uint64_t r = k / g.nx;
+    for (int sg = wave0; sg < nseg; sg += nwaves) {
+        const int r = sg / segs;
+        const int x = (sg - r * segs) * 64 + lane;
+        if (x >= g.nx) continue;
         Cell c;
         c.x = x;
-        c.y = (int)(r % g.ny);
-        c.z = (int)(r / g.ny);
+        c.y = r % g.ny;
+        c.z = r / g.ny;
         c.b = b;
-        const int row = (b * g.nz + c.z) * g.ny + c.y;
+        const int row = b * rows + r;
         c.own = (uint32_t)row * (uint32_t)g.nxp + (uint32_t)x;
         c.lin = (uint64_t)row * g.nx + x;
         c.valid = true;
@@ -940,16 +947,32 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const typename storage<ST>::S
     if (tid < kNPart) part[(uint64_t)blockIdx.x * kNPart + tid] = sh[tid][0];
 }
 
-__global__ void k_reduce_final(const double* __restrict__ part, int gpb, double rho0, double* __restrict__ out)
+// One workgroup per batch member: thread t sums the partials t, t + kBlock,
+// ... in order, then the same fixed tree as k_reduce.
+__global__ __launch_bounds__(kBlock) void k_reduce_final(const double* __restrict__ part, int gpb, double rho0,
+                                                         double* __restrict__ out)
 {
+    __shared__ double sh[kNPart][kBlock];
     const int b = blockIdx.x;
-    const int k = threadIdx.x;
-    if (k >= kNPart) return;
-    double s = 0.0;
-    for (int i = 0; i < gpb; ++i) {
-        const double v = part[((uint64_t)b * gpb + i) * kNPart + k];
-        s = (k == 5) ? fmax(s, v) : s + v;
+    const int tid = threadIdx.x;
+    double acc[kNPart];
+    for (int k = 0; k < kNPart; ++k) acc[k] = 0.0;
+    for (int i = tid; i < gpb; i += kBlock)
+        for (int k = 0; k < kNPart; ++k) {
+            const double v = part[((uint64_t)b * gpb + i) * kNPart + k];
+            acc[k] = (k == 5) ? fmax(acc[k], v) : acc[k] + v;
+        }
+    for (int k = 0; k < kNPart; ++k) sh[k][tid] = acc[k];
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (tid < s)
+            for (int k = 0; k < kNPart; ++k)
+                sh[k][tid] = (k == 5) ? fmax(sh[k][tid], sh[k][tid + s]) : sh[k][tid] + sh[k][tid + s];
+        __syncthreads();
     }
+    if (tid >= kNPart) return;
+    const int k = tid;
+    const double s = sh[k][0];
     double* o = out + (uint64_t)b * CMLBM_NRED;
     switch (k) {
         case 0: o[CMLBM_RED_MASS] = s; break;  // completed on the host with rho0 * fluid
@@ -1096,7 +1119,8 @@ int make_layout(const cmlbm_params* p, Layout* L)
     L->needs_mask = (p->flags & CMLBM_FLAG_SOLID) || p->wall[0] || p->wall[1] || p->wall[2];
     const uint64_t per = (uint64_t)p->nz * p->ny * p->nx;
     uint64_t gpb = (per + kBlock - 1) / kBlock;
-    if (gpb > (uint64_t)kMaxRedBlocks) gpb = kMaxRedBlocks;
+    const uint64_t max_gpb = p->storage == CMLBM_FP64 ? kMaxRedBlocks / 2 : kMaxRedBlocks;
+    if (gpb > max_gpb) gpb = max_gpb;
     L->gpb = (int)gpb;
     size_t off = 0;
     L->off_ftab64 = off;
@@ -1410,7 +1434,7 @@ int launch_reduce(cmlbm_lattice* lat, int residual, int snapshot, hipStream_t s)
     }
     int rc = launch_check(lat, "reduce");
     if (rc) return rc;
-    k_reduce_final<<<dim3(lat->g.nb), dim3(64), 0, s>>>((const double*)(lat->scratch + lat->off_part), lat->gpb,
+    k_reduce_final<<<dim3(lat->g.nb), dim3(kBlock), 0, s>>>((const double*)(lat->scratch + lat->off_part), lat->gpb,
                                                        lat->p.rho0, (double*)(lat->scratch + lat->off_final));
     return launch_check(lat, "reduce final");
 }
