@@ -620,6 +620,59 @@ def test_full_size_taylor_green_512_fp16_sampled(torch):
     assert np.all(err <= 0.5 * ulp + 2e-7 * WGT[:, None])
 
 
+def test_full_size_taylor_green_512_bf16_sampled(torch):
+    """BF16 storage at 512^3, the benchmark's 16-bit launch: every sampled
+    post-collision population is the oracle's value rounded to nearest BF16."""
+    log("bf16 TGV 512^3 one step, 4096 sampled cells")
+    got, ref = sampled_one_step(torch, 512, "bf16", 4096, seed=33)
+    h_ref = ref - WGT[:, None]
+    err = np.abs((got - WGT[:, None]) - h_ref)
+    ulp = ulp16(h_ref, "bf16")
+    log(f"  max error in BF16 ulps {(err / ulp).max():.3f}")
+    assert np.all(err <= 0.5 * ulp + 2e-7 * WGT[:, None])
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+def test_full_size_kolmogorov_384_sampled(torch, storage):
+    """Kolmogorov flow at its full size, 384^3 (not a power of two: six waves per
+    row in FP32, three in FP16), with the y-profile force: after three steps
+    from the seeded state, one more step on 4096 sampled cells against the
+    oracle's collision with each cell's force."""
+    log(f"{storage} Kolmogorov 384^3, 3 + 1 steps, 4096 sampled cells")
+    n = 384
+    wl = W.kolmogorov(n)
+    prof = wl["force_profile_y"]
+    lat = Lat(nx=n, ny=n, nz=n, tau=wl["tau"], storage=storage)
+    lat.set_force("profile_y", prof)
+    lat.init(wl["rho"], wl["u"])
+    del wl
+    lat.step(3)
+    g = W.generator(34)
+    s = np.stack([g.integers(0, n, 4096), g.integers(0, n, 4096), g.integers(0, n, 4096)], 1)
+    P0 = lat.populations().reshape(27, -1)
+    f0 = P0[:, torch.as_tensor((s[:, 2] * n + s[:, 1]) * n + s[:, 0], device=P0.device)].cpu().numpy()
+    del P0
+    lat.step(1)
+    P1 = lat.populations().reshape(27, -1)
+    got = np.empty((27, len(s)))
+    for i in range(27):
+        d = (s + np.array([CX[i], CY[i], CZ[i]])) % n
+        got[i] = P1[i, torch.as_tensor((d[:, 2] * n + d[:, 1]) * n + d[:, 0], device=P1.device)].cpu().numpy()
+    del P1
+    ref = O.collide_cells(f0, prof[s[:, 1]].T, 1.0 / lat.params.tau)
+    lat.close()
+    if storage == "fp32":
+        err = np.abs(got - ref) / WGT[:, None]
+        log(f"  max |f* - oracle| / w = {err.max():.3e}")
+        assert err.max() < 1e-6
+    else:
+        h_ref = ref - WGT[:, None]
+        err = np.abs((got - WGT[:, None]) - h_ref)
+        ulp = ulp16(h_ref, storage)
+        log(f"  max error in FP16 ulps {(err / ulp).max():.3f}")
+        assert np.all(err <= 0.5 * ulp + 2e-7 * WGT[:, None])
+
+
 # ---------------------------------------------------------------------------
 # reductions, residual, checkpoint, failure detection
 
