@@ -161,17 +161,64 @@ __global__ __launch_bounds__(256) void k_conv_fwd(G g, const bf16* __restrict__ 
 // Workgroup = one brick of 256 output voxels x (16 * NB) output channels.
 // Per 32-channel input chunk the brick's 6 x 6 x 18 halo is staged once in LDS
 // (voxel stride 80 bytes: 16 consecutive voxels of a 16-byte fragment read
-// land on distinct bank groups), and every one of the 27 taps reads its A
+// land on distinct bank groups), and every one of the 27 taps takes its A
 // fragments from there: each input value is fetched from memory once per
-// brick instead of once per tap.  Wave w owns the 4 brick rows (d, h) =
+// brick instead of once per tap, and each halo row is read from LDS once for
+// its three x taps (the x - 1 and x + 1 fragments are lane shifts of it).  Wave w owns the 4 brick rows (d, h) =
 // (w, 0..3), i.e. 4 MFMA row blocks of 16 x-consecutive voxels, and keeps
 // 4 x NB accumulator tiles: each B fragment (weights, through L1) feeds 4
 // MFMAs and each A fragment (LDS) feeds NB.
+
+// The A operand of v_mfma_f32_16x16x32_bf16 holds voxel row (lane % 16), so
+// the fragment of the neighbouring x tap is the same fragment shifted by one
+// lane within each 16-lane DPP row; the lane left without a source keeps
+// `edge` (update_dpp with bound_ctrl off leaves it unwritten).
+// rows_from_lower: lane l takes lane l - 1 (voxel x - 1), lane 0 keeps edge.
+// rows_from_upper: lane l takes lane l + 1 (voxel x + 1), lane 15 keeps edge.
+__device__ __forceinline__ bf16x8 rows_from_lower(bf16x8 edge, bf16x8 v)
+{
+    const u4 e = __builtin_bit_cast(u4, edge), a = __builtin_bit_cast(u4, v);
+    u4 r;
+    r.x = (unsigned)__builtin_amdgcn_update_dpp((int)e.x, (int)a.x, 0x111, 0xF, 0xF, false);  // row_shr:1
+    r.y = (unsigned)__builtin_amdgcn_update_dpp((int)e.y, (int)a.y, 0x111, 0xF, 0xF, false);
+    r.z = (unsigned)__builtin_amdgcn_update_dpp((int)e.z, (int)a.z, 0x111, 0xF, 0xF, false);
+    r.w = (unsigned)__builtin_amdgcn_update_dpp((int)e.w, (int)a.w, 0x111, 0xF, 0xF, false);
+    return __builtin_bit_cast(bf16x8, r);
+}
+
+__device__ __forceinline__ bf16x8 rows_from_upper(bf16x8 edge, bf16x8 v)
+{
+    const u4 e = __builtin_bit_cast(u4, edge), a = __builtin_bit_cast(u4, v);
+    u4 r;
+    r.x = (unsigned)__builtin_amdgcn_update_dpp((int)e.x, (int)a.x, 0x101, 0xF, 0xF, false);  // row_shl:1
+    r.y = (unsigned)__builtin_amdgcn_update_dpp((int)e.y, (int)a.y, 0x101, 0xF, 0xF, false);
+    r.z = (unsigned)__builtin_amdgcn_update_dpp((int)e.z, (int)a.z, 0x101, 0xF, 0xF, false);
+    r.w = (unsigned)__builtin_amdgcn_update_dpp((int)e.w, (int)a.w, 0x101, 0xF, 0xF, false);
+    return __builtin_bit_cast(bf16x8, r);
+}
 
 constexpr int kTD = 4, kTH = 4, kTW = 16;
 constexpr int kHD = kTD + 2, kHH = kTH + 2, kHW = kTW + 2;
 constexpr int kHalo = kHD * kHH * kHW;  // 648 voxels
 constexpr int kVStride = 40;            // bf16 per staged voxel (32 channels + 8 pad)
+
+constexpr int kStageIters = (kHalo * 4 + 255) / 256;
+
+__device__ __forceinline__ void stage_halo_load(const G& g, const bf16* __restrict__ x, int cin, int c0, long long n,
+                                                int d0, int h0, int x0, int tid, u4 stage[kStageIters])
+{
+#pragma unroll
+    for (int it = 0; it < kStageIters; ++it) {
+        const int p = tid + it * 256;
+        const int hv = p >> 2, part = p & 3;
+        const int hx = hv % kHW, hh = (hv / kHW) % kHH, hd = hv / (kHW * kHH);
+        int sd = 0, sh = 0, sw = 0;
+        stage[it] = u4{0u, 0u, 0u, 0u};
+        if (p < kHalo * 4 && shift_axis(d0, hd - 1, g.d, g.per[0], sd) && shift_axis(h0, hh - 1, g.h, g.per[1], sh) &&
+            shift_axis(x0, hx - 1, g.w, g.per[2], sw))
+            stage[it] = *(const u4*)(x + (((n * g.d + sd) * g.h + sh) * g.w + sw) * cin + c0 + part * 8);
+    }
+}
 
 template <int NB, int SIGN, int ACT>
 __global__ __launch_bounds__(256) void k_conv_tile(G g, const bf16* __restrict__ x, int cin,
@@ -199,31 +246,45 @@ __global__ __launch_bounds__(256) void k_conv_tile(G g, const bf16* __restrict__
 #pragma unroll
         for (int b = 0; b < NB; ++b) acc[m][b] = f4{0.f, 0.f, 0.f, 0.f};
     const bf16* wl = wt + (long long)(co0 + (lane & 15)) * cin + (lane >> 4) * 8;
+    // halo staging: thread tid moves the 16-byte parts tid, tid + 256, ... of
+    // the 648 x 4; all its loads are in flight together, and the next chunk's
+    // are issued before the current chunk's MFMAs
+    u4 stage[kStageIters];
     for (int c0 = 0; c0 < cin; c0 += 32) {
+        stage_halo_load(g, x, cin, c0, n, d0, h0, x0, tid, stage);
         __syncthreads();
-        for (int p = tid; p < kHalo * 4; p += 256) {
-            const int hv = p >> 2, part = p & 3;
-            const int hx = hv % kHW, hh = (hv / kHW) % kHH, hd = hv / (kHW * kHH);
-            int sd = 0, sh = 0, sw = 0;
-            u4 v = u4{0u, 0u, 0u, 0u};
-            if (shift_axis(d0, hd - 1, g.d, g.per[0], sd) && shift_axis(h0, hh - 1, g.h, g.per[1], sh) &&
-                shift_axis(x0, hx - 1, g.w, g.per[2], sw))
-                v = *(const u4*)(x + (((n * g.d + sd) * g.h + sh) * g.w + sw) * cin + c0 + part * 8);
-            *(u4*)&sx[hv * kVStride + part * 8] = v;
+#pragma unroll
+        for (int it = 0; it < kStageIters; ++it) {
+            const int p = tid + it * 256;
+            if (p < kHalo * 4) *(u4*)&sx[(p >> 2) * kVStride + (p & 3) * 8] = stage[it];
         }
         __syncthreads();
-#pragma unroll 3
-        for (int t = 0; t < 27; ++t) {
-            const int dz = SIGN * (t / 9 - 1), dy = SIGN * ((t / 3) % 3 - 1), dx = SIGN * (t % 3 - 1);
-            bf16x8 bw[NB];
-#pragma unroll
-            for (int b = 0; b < NB; ++b) bw[b] = ld8(wl + ((long long)t * cout + 16 * b) * cin + c0);
+#pragma unroll 1
+        for (int t9 = 0; t9 < 9; ++t9) {
+            const int dz = SIGN * (t9 / 3 - 1), dy = SIGN * (t9 % 3 - 1);
+            // A fragments of the three x taps (index dx + 1) of each brick row
+            bf16x8 af[4][3];
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-                const int hv = ((wave + 1 + dz) * kHH + (m + 1 + dy)) * kHW + (lane & 15) + 1 + dx;
-                const bf16x8 a = *(const bf16x8*)&sx[hv * kVStride + (lane >> 4) * 8];
+                const int hrow = ((wave + 1 + dz) * kHH + (m + 1 + dy)) * kHW;
+                const bf16x8 a0 = *(const bf16x8*)&sx[(hrow + (lane & 15) + 1) * kVStride + (lane >> 4) * 8];
+                const bf16x8 e = *(const bf16x8*)&sx[(hrow + ((lane & 15) < 8 ? 0 : kHW - 1)) * kVStride + (lane >> 4) * 8];
+                af[m][0] = rows_from_lower(e, a0);
+                af[m][1] = a0;
+                af[m][2] = rows_from_upper(e, a0);
+            }
 #pragma unroll
-                for (int b = 0; b < NB; ++b) acc[m][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[b], acc[m][b], 0, 0, 0);
+            for (int j = 0; j < 3; ++j) {
+                const int t = t9 * 3 + j;
+                const int k = SIGN > 0 ? j : 2 - j;  // dx = SIGN * (j - 1)
+                bf16x8 bw[NB];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) bw[b] = ld8(wl + ((long long)t * cout + 16 * b) * cin + c0);
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+                        acc[m][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[m][k], bw[b], acc[m][b], 0, 0, 0);
             }
         }
     }
