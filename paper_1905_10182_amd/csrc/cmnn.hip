@@ -381,7 +381,9 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(G g, const bf16* __restrict_
 // fragment starts dx + 1 elements into an aligned 16-byte LDS read: for
 // dx = 0 and +1 the eight elements are realigned from that read and the next
 // dword.  Row strides are padded so that the 16 rows of a fragment read fall
-// on distinct bank groups.  Wave w accumulates the 2 x 2 blocks of 16 x 16
+// on distinct bank groups.  Two LDS buffers alternate: a wave stores brick
+// br + 1 as soon as its MFMAs on brick br are done, so the stores of one
+// wave overlap the MFMAs of another, with one barrier per brick.  Wave w accumulates the 2 x 2 blocks of 16 x 16
 // for taps w, w + 8, w + 16, w + 24; the dy fragments of a K step are read
 // once and serve all of them.
 
@@ -413,8 +415,8 @@ __global__ __launch_bounds__(kBwThreads) void k_conv_bwd_w_tile(G g, const bf16*
                                                                 int bricks_per_chunk, float* __restrict__ part,
                                                                 float* __restrict__ bpart)
 {
-    __shared__ __attribute__((aligned(16))) bf16 sdy[32 * kDyStride];
-    __shared__ __attribute__((aligned(16))) bf16 sx[32 * kXStride];
+    __shared__ __attribute__((aligned(16))) bf16 sdy2[2][32 * kDyStride];
+    __shared__ __attribute__((aligned(16))) bf16 sx2[2][32 * kXStride];
     __shared__ float sbias[kBwThreads];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ct = cout / 32, it = cin / 32;
@@ -465,7 +467,9 @@ __global__ __launch_bounds__(kBwThreads) void k_conv_bwd_w_tile(G g, const bf16*
             for (int i = 0; i < 8; ++i) dyin[i] = *(const u4*)(src + (long long)i * cout);
         }
     };
-    auto store = [&]() {
+    auto store = [&](int buf) {
+        bf16* sdy = sdy2[buf];
+        bf16* sx = sx2[buf];
         u4 out[8];
         if (has_x) {
             transpose8x8(xin, out);
@@ -485,20 +489,26 @@ __global__ __launch_bounds__(kBwThreads) void k_conv_bwd_w_tile(G g, const bf16*
         for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b) acc[k][a][b] = f4{0.f, 0.f, 0.f, 0.f};
-    if (b0 < b1) load(b0);
     const int j = lane >> 4, l16 = lane & 15;
+    // two LDS buffers: brick br + 1 is stored while brick br's MFMAs run in
+    // other waves; one barrier per brick
+    if (b0 < b1) {
+        load(b0);
+        store(0);
+        if (b0 + 1 < b1) load(b0 + 1);
+    }
+    __syncthreads();
+    int cur = 0;
     for (long long br = b0; br < b1; ++br) {
-        __syncthreads();
-        store();
-        __syncthreads();
-        if (br + 1 < b1) load(br + 1);
+        const bf16* sdy = sdy2[cur];
+        const bf16* sx = sx2[cur];
         if (do_bias) {
             const bf16* q = &sdy[(tid >> 4) * kDyStride + (tid & 15) * 16];
 #pragma unroll
             for (int k = 0; k < 16; ++k) bsum += (float)q[k];
         }
         // 8 K steps of 32 voxels (two brick rows); lane group j takes voxels 8j..8j+7
-#pragma unroll 2
+#pragma unroll 8
         for (int ks = 0; ks < 8; ++ks) {
             const int row = ks * 2 + (j >> 1), xo = (j & 1) * 8;
             bf16x8 a[2];
@@ -532,6 +542,12 @@ __global__ __launch_bounds__(kBwThreads) void k_conv_bwd_w_tile(G g, const bf16*
                 }
             }
         }
+        if (br + 1 < b1) {
+            store(cur ^ 1);
+            if (br + 2 < b1) load(br + 2);
+        }
+        __syncthreads();
+        cur ^= 1;
     }
     if (do_bias) {
         sbias[tid] = bsum;
