@@ -21,6 +21,8 @@
  * - Every function enqueues on hip_stream (NULL = null stream), returns 0 or
  *   a negative CMNN_E* code, checks its arguments on the host first and
  *   never allocates: buffers are caller-owned device memory, 16-byte aligned.
+ * - A geometry needs positive extents and at most 2^31 - 1 voxels (EINVAL
+ *   otherwise).
  */
 #ifndef CMNN_H
 #define CMNN_H
@@ -59,8 +61,8 @@ int cmnn_conv3d_bwd_data(const cmnn_geom* g, const void* dy, int32_t cout, const
 int cmnn_conv3d_bwd_weight_workspace(const cmnn_geom* g, int32_t cin, int32_t cout, size_t* bytes);
 
 /* dw[t][co][ci] = sum_v dy[v][co] x[v + off(t)][ci] and dbias[co] = sum_v dy[v][co]
- * (dbias may be NULL), FP32, overwritten.  Deterministic: per-chunk partials
- * in the workspace are summed in a fixed order. */
+ * (dbias may be NULL), FP32, overwritten; cout <= 256.  Deterministic:
+ * per-chunk partials in the workspace are summed in a fixed order. */
 int cmnn_conv3d_bwd_weight(const cmnn_geom* g, const void* x, int32_t cin, const void* dy, int32_t cout, float* dw,
                            float* dbias, void* workspace, size_t workspace_bytes, void* hip_stream);
 
@@ -75,14 +77,15 @@ int cmnn_pool2_bwd(const cmnn_geom* g, const void* dy, int32_t c, void* dx, void
 int cmnn_up2_fwd(const cmnn_geom* g, const void* x, int32_t c, void* y, void* hip_stream);
 int cmnn_up2_bwd(const cmnn_geom* g, const void* dy, int32_t c, void* dx, void* hip_stream);
 
-/* Channel concatenation y = [a | b] over nvox voxels, and its split. */
+/* Channel concatenation y = [a | b] over nvox voxels, and its split (da or
+ * db may be NULL: that part is not written). */
 int cmnn_concat_fwd(size_t nvox, const void* a, int32_t ca, const void* b, int32_t cb, void* y, void* hip_stream);
 int cmnn_concat_bwd(size_t nvox, const void* dy, int32_t ca, int32_t cb, void* da, void* db, void* hip_stream);
 
 /* Per-sample channel mean broadcast over the voxels (global context):
  * y[n][v][c] = (1/V) sum_v' x[n][v'][c], V = d*h*w, c <= 256.  The map is a
  * symmetric projection, so the same call on dy gives the gradient.
- * workspace: cmnn_channel_mean_workspace bytes. */
+ * workspace: cmnn_channel_mean_workspace bytes; n <= 2^25. */
 int cmnn_channel_mean_workspace(const cmnn_geom* g, int32_t c, size_t* bytes);
 int cmnn_channel_mean(const cmnn_geom* g, const void* x, int32_t c, void* y, void* workspace, size_t workspace_bytes,
                       void* hip_stream);

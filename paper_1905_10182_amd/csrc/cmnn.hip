@@ -46,9 +46,12 @@ G make_g(const cmnn_geom* g)
     return r;
 }
 
+// Positive extents and at most 2^31 - 1 voxels, so that every launch grid and
+// per-voxel index fits the kernels' arithmetic.
 bool geom_ok(const cmnn_geom* g)
 {
-    return g && g->n > 0 && g->d > 0 && g->h > 0 && g->w > 0;
+    if (!g || g->n <= 0 || g->d <= 0 || g->h <= 0 || g->w <= 0) return false;
+    return (long long)g->n * g->d * g->h * g->w <= 0x7fffffffLL;
 }
 bool chan_ok(int c) { return c > 0 && c % CMNN_CALIGN == 0; }
 bool al16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
@@ -1363,7 +1366,7 @@ int cmnn_add(size_t n, const void* a, const void* b, void* y, void* hip_stream)
 
 int cmnn_channel_mean_workspace(const cmnn_geom* g, int32_t c, size_t* bytes)
 {
-    if (!geom_ok(g) || c <= 0 || c > 256 || !bytes) return CMNN_EINVAL;
+    if (!geom_ok(g) || c <= 0 || c > 256 || !bytes || (long long)g->n * kMeanParts > 0x7fffffffLL) return CMNN_EINVAL;
     *bytes = (size_t)g->n * (kMeanParts + 1) * c * sizeof(float);
     return CMNN_OK;
 }

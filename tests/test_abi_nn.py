@@ -1,0 +1,127 @@
+"""CPU-side checks of the C ABI of the warm-start network kernels
+(include/cmnn.h): the library loads, exports every declared entry point, and
+rejects invalid arguments on the host before any device work.  Every call
+here is invalid, so none reaches a kernel launch."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1905_10182_amd import cmnn as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cmnn.h")
+EINVAL = -1
+
+P = ctypes.c_void_p(1 << 20)        # stand-in device pointers: never dereferenced (validation fails first)
+P2 = ctypes.c_void_p((1 << 20) + 256)
+ODD = ctypes.c_void_p((1 << 20) + 8)  # not 16-byte aligned
+NULL = None
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return N.load_library()
+
+
+def declared_functions(path):
+    text = re.sub(r"/\*.*?\*/", "", open(path).read(), flags=re.S)
+    return sorted(set(re.findall(r"\b(cmnn_[a-z0-9_]+)\s*\(", text)))
+
+
+def g(n=2, d=8, h=8, w=16, periodic=(1, 0, 1)):
+    return ctypes.byref(N.geom(n, d, h, w, periodic))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions(HEADER) == sorted(N.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions(HEADER):
+        assert hasattr(lib, name), name
+
+
+def test_conv_forward_and_data_gradient_validation(lib):
+    ok = dict(x=P, cin=32, w=P2, b=NULL, cout=32, act=1, y=P)
+    def fwd(geom=None, **kw):
+        a = dict(ok, **kw)
+        return lib.cmnn_conv3d_fwd(geom if geom is not None else g(n=0), a["x"], a["cin"], a["w"], a["b"], a["cout"],
+                                   a["act"], a["y"], NULL)
+    assert fwd() == EINVAL  # empty batch
+    for kw in (dict(cin=48), dict(cout=0), dict(cin=-32), dict(x=NULL), dict(w=NULL), dict(y=NULL), dict(x=ODD),
+               dict(w=ODD), dict(act=2), dict(act=-1)):
+        assert fwd(g(), **kw) == EINVAL, kw
+    for geom in (g(d=0), g(h=-1), g(n=1024, d=1024, h=1024, w=2)):  # the last has 2^31 voxels
+        assert fwd(geom) == EINVAL
+    assert lib.cmnn_conv3d_fwd(None, P, 32, P2, NULL, 32, 1, P, NULL) == EINVAL
+    assert lib.cmnn_conv3d_bwd_data(g(), P, 32, P2, 40, P, NULL) == EINVAL
+    assert lib.cmnn_conv3d_bwd_data(g(), ODD, 32, P2, 32, P, NULL) == EINVAL
+    assert lib.cmnn_conv3d_bwd_data(g(), P, 32, NULL, 32, P, NULL) == EINVAL
+    assert lib.cmnn_conv3d_bwd_data(g(w=0), P, 32, P2, 32, P, NULL) == EINVAL
+
+
+def test_weight_gradient_workspace_and_validation(lib):
+    n = ctypes.c_size_t()
+    # brick geometry 16 x 32 x 32 x 64, 32 x 32 channels: 4096 bricks in 256
+    # chunks, 27 x 32 x 32 FP32 partials each, plus the bias column partials
+    assert lib.cmnn_conv3d_bwd_weight_workspace(ctypes.byref(N.geom(16, 32, 32, 64)), 32, 32, ctypes.byref(n)) == 0
+    assert n.value == 256 * 27 * 32 * 32 * 4 + 1024 * 32 * 4
+    # four 32 x 32 channel tiles: 64 chunks
+    assert lib.cmnn_conv3d_bwd_weight_workspace(ctypes.byref(N.geom(16, 32, 32, 64)), 64, 64, ctypes.byref(n)) == 0
+    assert n.value == 64 * 27 * 64 * 64 * 4 + 1024 * 64 * 4
+    assert lib.cmnn_conv3d_bwd_weight_workspace(g(), 33, 32, ctypes.byref(n)) == EINVAL
+    assert lib.cmnn_conv3d_bwd_weight_workspace(g(), 32, 32, None) == EINVAL
+    assert lib.cmnn_conv3d_bwd_weight_workspace(g(n=0), 32, 32, ctypes.byref(n)) == EINVAL
+    assert lib.cmnn_conv3d_bwd_weight_workspace(g(), 32, 32, ctypes.byref(n)) == 0
+    need = n.value
+    call = lambda **kw: lib.cmnn_conv3d_bwd_weight(g(), kw.get("x", P), 32, kw.get("dy", P2), kw.get("cout", 32),
+                                                   kw.get("dw", P), NULL, kw.get("ws", P), kw.get("wsb", need), NULL)
+    for kw in (dict(wsb=need - 1), dict(ws=NULL), dict(x=NULL), dict(dy=NULL), dict(dw=NULL), dict(x=ODD),
+               dict(dy=ODD), dict(cout=288)):
+        assert call(**kw) == EINVAL, kw
+
+
+def test_elementwise_validation(lib):
+    assert lib.cmnn_act_bwd(P, P, NULL, 64, 1, NULL) == EINVAL
+    assert lib.cmnn_act_bwd(P, P, P, 64, 3, NULL) == EINVAL
+    assert lib.cmnn_pool2_fwd(g(d=7), P, 32, P2, NULL) == EINVAL  # odd extent
+    assert lib.cmnn_pool2_fwd(g(), P, 0, P2, NULL) == EINVAL
+    assert lib.cmnn_pool2_bwd(g(w=15), P, 32, P2, NULL) == EINVAL
+    assert lib.cmnn_up2_fwd(g(), NULL, 32, P2, NULL) == EINVAL
+    assert lib.cmnn_up2_bwd(g(h=0), P, 32, P2, NULL) == EINVAL
+    assert lib.cmnn_concat_fwd(10, P, 0, P, 32, P2, NULL) == EINVAL
+    assert lib.cmnn_concat_fwd(10, P, 32, NULL, 32, P2, NULL) == EINVAL
+    assert lib.cmnn_concat_bwd(10, NULL, 32, 32, P, P2, NULL) == EINVAL
+    assert lib.cmnn_concat_bwd(10, P, 32, -8, P, P2, NULL) == EINVAL
+    assert lib.cmnn_add(10, P, NULL, P2, NULL) == EINVAL
+    assert lib.cmnn_pack_weights(P, 0, 32, P, P2, NULL) == EINVAL
+    assert lib.cmnn_pack_weights(P, 32, 32, P, NULL, NULL) == EINVAL
+    assert lib.cmnn_pack_channels(10, P, 4, P2, 3, NULL) == EINVAL  # fewer slots than channels
+    assert lib.cmnn_unpack_channels(10, P, 32, NULL, 4, NULL) == EINVAL
+    assert lib.cmnn_adam(10, P, P, P, P, ctypes.c_float(1e-3), ctypes.c_float(0.9), ctypes.c_float(0.999),
+                         ctypes.c_float(1e-8), ctypes.c_float(0.0), 0, NULL) == EINVAL  # step counts from 1
+
+
+def test_reduction_workspaces_and_validation(lib):
+    n = ctypes.c_size_t()
+    assert lib.cmnn_channel_mean_workspace(g(n=3), 96, ctypes.byref(n)) == 0
+    assert n.value == 3 * 65 * 96 * 4  # 64 partial sums and the mean per sample and channel
+    assert lib.cmnn_channel_mean_workspace(g(), 288, ctypes.byref(n)) == EINVAL
+    assert lib.cmnn_channel_mean_workspace(g(n=1 << 26, d=1, h=1, w=1), 32, ctypes.byref(n)) == EINVAL
+    assert lib.cmnn_channel_mean(g(), P, 32, P2, P, 10, NULL) == EINVAL  # workspace too small
+    assert lib.cmnn_mse_workspace(0, ctypes.byref(n)) == EINVAL
+    assert lib.cmnn_mse_workspace(100, ctypes.byref(n)) == 0
+    need = n.value
+    mse = lambda c=32, creal=3, wsb=need, ws=P: lib.cmnn_mse(100, P, c, creal, P2, P2, P, NULL, ws, wsb, NULL)
+    assert mse(creal=33) == EINVAL
+    assert mse(creal=0) == EINVAL
+    assert mse(wsb=need - 4) == EINVAL
+    assert mse(ws=NULL) == EINVAL
+    assert lib.cmnn_clip_grad_norm_workspace(0, ctypes.byref(n)) == EINVAL
+    assert lib.cmnn_clip_grad_norm_workspace(1000, ctypes.byref(n)) == 0
+    cl = lambda mx, wsb: lib.cmnn_clip_grad_norm(1000, P, ctypes.c_float(mx), P2, P, wsb, NULL)
+    assert cl(-1.0, n.value) == EINVAL
+    assert cl(float("nan"), n.value) == EINVAL
+    assert cl(1.0, n.value - 4) == EINVAL
