@@ -44,8 +44,9 @@ from .unet import UNet3D
 import os
 
 NX, NY, NZ = 64, 32, 32
-# trained network shipped with the package (96000 Adam steps at batch 16 on
-# 8192 steady states, seeds 0..8191); evaluation seeds start at 1000000
+# trained network shipped with the package: 96000 Adam steps at batch 16 on
+# the 8192 steady states of seeds 0..8191, then 80000 more on seeds
+# 8192..16383 (train --init); evaluation seeds start at 1000000
 DEFAULT_MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "unet_warmstart.npz")
 TAU = 0.8
 NU = (TAU - 0.5) / 3.0
@@ -249,10 +250,13 @@ class Trainer:
         return tot / max(cnt, 1)
 
 
-def train(data, steps=3000, batch=8, lr=4e-4, lr_min=4e-6, seed=0, log=print, test=None):
+def train(data, steps=3000, batch=8, lr=4e-4, lr_min=4e-6, seed=0, log=print, test=None, init=None):
+    """Adam on the fluid-masked MSE with a cosine learning rate from lr to
+    lr_min; `init` (a UNet3D) continues training that network instead of a
+    fresh one (fresh Adam moments)."""
     import torch
 
-    net = UNet3D((NZ, NY, NX), out_ch=NOUT, seed=seed)
+    net = init if init is not None else UNet3D((NZ, NY, NX), out_ch=NOUT, seed=seed)
     tr = Trainer(net, data, batch)
     log(f"U-Net: {net.nparams_real} parameters ({net.nparams} with channel padding), "
         f"{net.flops_per_sample() / 1e9:.1f} GFLOP per sample forward")
@@ -414,6 +418,8 @@ def main(argv=None):
     t.add_argument("--steps", type=int, default=3000)
     t.add_argument("--batch", type=int, default=8)
     t.add_argument("--lr", type=float, default=4e-4)
+    t.add_argument("--lr-min", type=float, default=4e-6)
+    t.add_argument("--init", help="continue training this model")
     t.add_argument("--out", required=True)
     e = sub.add_parser("evaluate")
     e.add_argument("--model")
@@ -427,7 +433,8 @@ def main(argv=None):
     elif a.cmd == "train":
         z = dict(np.load(a.data, allow_pickle=False))
         test = dict(np.load(a.test, allow_pickle=False)) if a.test else None
-        net, info = train(z, steps=a.steps, batch=a.batch, lr=a.lr, log=log, test=test)
+        net, info = train(z, steps=a.steps, batch=a.batch, lr=a.lr, lr_min=a.lr_min, log=log, test=test,
+                          init=load_model(a.init) if a.init else None)
         save_model(net, a.out, info)
         print(json.dumps({k: v for k, v in info.items() if k != "loss_history"}))
     else:
