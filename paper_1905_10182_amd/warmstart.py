@@ -46,7 +46,8 @@ import os
 NX, NY, NZ = 64, 32, 32
 # trained network shipped with the package: 96000 Adam steps at batch 16 on
 # the 8192 steady states of seeds 0..8191, then 80000 more on seeds
-# 8192..16383 (train --init); evaluation seeds start at 1000000
+# 8192..16383 and 80000 more on seeds 16384..24575 (train --init);
+# evaluation seeds start at 1000000
 DEFAULT_MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "unet_warmstart.npz")
 TAU = 0.8
 NU = (TAU - 0.5) / 3.0
