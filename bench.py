@@ -24,9 +24,10 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 BYTES_PER_CELL = {"fp64": 432, "fp32": 216, "fp16": 108, "bf16": 108,  # 27 reads + 27 writes
                   "mom32": 72}  # moment representation: 9 FP32 numbers read + 9 written
-# template arguments: storage, cells per lane, solid mask, force field, non-temporal stores, collision model
-STEP_KERNEL = {"fp32": "k_step<1, 1, false, false, true, 0>", "fp16": "k_step<2, 2, false, false, true, 0>",
-               "bf16": "k_step<3, 2, false, false, true, 0>", "fp64": "k_step<0, 1, false, false, true, 0>"}
+# template arguments: storage, cells per lane, solid mask, force field, non-temporal stores, collision model,
+# fused reductions
+STEP_KERNEL = {"fp32": "k_step<1, 1, false, false, true, 0, false>", "fp16": "k_step<2, 2, false, false, true, 0, false>",
+               "bf16": "k_step<3, 2, false, false, true, 0, false>", "fp64": "k_step<0, 1, false, false, true, 0, false>"}
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_step_tgv256_fp32_counters.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1905_10182_amd", "csrc", f) for f in ("cmlbm.hip", "d3q27.hpp")]
 

@@ -102,6 +102,9 @@ extern "C" {
 #define CMLBM_FLAG_BGK 32u       /* stability control: every moment relaxes with omega (single relaxation
                                     time), with either both flags above (the classical BGK scheme with
                                     Guo forcing) or neither (the complete equilibrium and forcing) */
+#define CMLBM_FLAG_FUSED_REDUCE 64u /* reserve room for cmlbm_step_reduce's per-wave partial sums (10 doubles
+                                       per 64 x 1 or 64 x 2 cell row segment); population storage and the
+                                       method's collision only (EINVAL with a comparison model or MOM32) */
 
 /* cmlbm_reduce: `what` bits and the layout of one row of its output */
 #define CMLBM_REDUCE_RESIDUAL 1u /* compare u with the last snapshot */
@@ -196,6 +199,23 @@ int cmlbm_pseudopotential_force(cmlbm_lattice* lat, double G, const void* dev_rh
  * ESTATE.  Waits for the stream.  Returns CMLBM_EUNSTABLE (output still
  * filled) if any fluid cell has a non-finite rho or u. */
 int cmlbm_reduce(cmlbm_lattice* lat, uint32_t what, double* host_out, void* hip_stream);
+
+/* One time step (cmlbm_step with nsteps = 1) whose kernel also forms the FP64
+ * reductions of the state it reads, the state at the current step t (the
+ * global sums that the per-step kinetic-energy and mass monitoring of the
+ * method's validation needs), without a second pass over the populations.
+ * Output as cmlbm_reduce without RESIDUAL (DU2 and RESIDUAL are 0).  The
+ * per-cell density and velocity come from the step's own arithmetic (FP32 for
+ * FP32 and 16-bit storage, FP64 for FP64) and are summed in FP64 in a fixed
+ * order: bitwise reproducible, and within the FP32 rounding of the per-cell
+ * values of cmlbm_reduce's sums.  The step runs in a separately compiled
+ * kernel whose arithmetic may round differently in the last unit of the
+ * stored format (measured: 99.97% or more of the populations bitwise equal to
+ * cmlbm_step's, the rest one unit apart).  Needs CMLBM_FLAG_FUSED_REDUCE
+ * (ESTATE otherwise).  The step is taken in every case; waits for the stream;
+ * returns CMLBM_EUNSTABLE (output filled, step taken) if a fluid cell of the
+ * state at t has a non-finite rho or u. */
+int cmlbm_step_reduce(cmlbm_lattice* lat, double* host_out, void* hip_stream);
 
 /* Export the pre-collision populations f_i(x, t) (unshifted, FP64) into
  * dev_out[27][N], paper order.  Solid cells are written as 0. */

@@ -20,6 +20,7 @@ STORAGE_BYTES = {FP64: 8, FP32: 4, FP16: 2, BF16: 2, MOM32: 4}
 PERIODIC, BOUNCEBACK = 0, 1
 FORCE_NONE, FORCE_UNIFORM, FORCE_BATCH, FORCE_PROFILE_Y, FORCE_FIELD = 0, 1, 2, 3, 4
 FLAG_SOLID, FLAG_RESIDUAL, FLAG_STOCHASTIC, FLAG_FORCE_GUO, FLAG_EQ_SECOND, FLAG_BGK = 1, 2, 4, 8, 16, 32
+FLAG_FUSED_REDUCE = 64
 # collision models: the method (M1), the comparison models of Sec. III, and the
 # single-relaxation-time controls (classical BGK with Guo forcing; BGK with the
 # complete equilibrium and forcing)
@@ -32,7 +33,8 @@ NRED = 11
 
 # Every entry point declared in include/cmlbm.h.
 EXPORTS = ["cmlbm_required_bytes", "cmlbm_create", "cmlbm_set_solid", "cmlbm_set_force", "cmlbm_init",
-           "cmlbm_step", "cmlbm_moments", "cmlbm_reduce", "cmlbm_populations", "cmlbm_load_populations",
+           "cmlbm_step", "cmlbm_moments", "cmlbm_reduce", "cmlbm_step_reduce", "cmlbm_populations",
+           "cmlbm_load_populations",
            "cmlbm_save_state", "cmlbm_restore_state", "cmlbm_get_time", "cmlbm_set_time", "cmlbm_destroy",
            "cmlbm_last_error", "cmlbm_status_string", "cmlbm_pseudopotential_force"]
 
@@ -70,6 +72,7 @@ def load_library():
     lib.cmlbm_step.argtypes = [vp, i32, vp]
     lib.cmlbm_moments.argtypes = [vp, vp, vp, ctypes.c_int, vp]
     lib.cmlbm_reduce.argtypes = [vp, u32, ctypes.POINTER(ctypes.c_double), vp]
+    lib.cmlbm_step_reduce.argtypes = [vp, ctypes.POINTER(ctypes.c_double), vp]
     lib.cmlbm_pseudopotential_force.argtypes = [vp, ctypes.c_double, vp, ctypes.c_int, vp, vp]
     lib.cmlbm_populations.argtypes = [vp, dp, vp]
     lib.cmlbm_load_populations.argtypes = [vp, dp, vp]
@@ -129,13 +132,13 @@ class Lattice:
     """
 
     def __init__(self, nx, ny, nz, nbatch=1, tau=0.8, rho0=1.0, storage="fp32", wall=(0, 0, 0),
-                 solid=False, residual=False, stochastic=False, model="m1", device="cuda"):
+                 solid=False, residual=False, stochastic=False, model="m1", fused_reduce=False, device="cuda"):
         import torch
 
         self.torch = torch
         self.lib = load_library()
         flags = (FLAG_SOLID if solid else 0) | (FLAG_RESIDUAL if residual else 0) | \
-            (FLAG_STOCHASTIC if stochastic else 0) | MODELS[model]
+            (FLAG_STOCHASTIC if stochastic else 0) | MODELS[model] | (FLAG_FUSED_REDUCE if fused_reduce else 0)
         self.params = make_params(nx, ny, nz, nbatch, tau, rho0, storage, wall, flags)
         self.shape = (int(nbatch), int(nz), int(ny), int(nx))
         self.N = int(np.prod(self.shape))
@@ -276,6 +279,18 @@ class Lattice:
         assert out.dtype == dt and out.is_contiguous() and tuple(out.shape) == (3,) + self.shape
         self._check(self.lib.cmlbm_pseudopotential_force(self.handle, float(G), _ptr(r), io, _ptr(out),
                                                          self._stream()), "pseudopotential_force")
+        return out
+
+    def step_reduce(self, allow_unstable=False):
+        """One step that also returns the FP64 reductions of the state it
+        started from (numpy (nbatch, NRED), as reduce()); needs
+        fused_reduce=True."""
+        out = np.zeros((self.shape[0], NRED), np.float64)
+        rc = self.lib.cmlbm_step_reduce(self.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        self._stream())
+        if rc == EUNSTABLE and allow_unstable:
+            return out
+        self._check(rc, "step_reduce")
         return out
 
     def reduce(self, residual=False, snapshot=False, allow_unstable=False):

@@ -3,7 +3,9 @@
 // Sec. II).  C ABI in include/cmlbm.h.
 //
 // Kernels
-//   k_step       fused pull-stream gather + collision + store (the hot path)
+//   k_step       fused pull-stream gather + collision + store (the hot path);
+//                with RED also the FP64 partial sums of the state it reads
+//   k_red_waves  second level of those sums
 //   k_init       inverse of the gather: writes a given pre-collision state
 //   k_gather     rho/u or FP64 populations from the current state
 //   k_reduce     per-block FP64 partial sums; k_reduce_final finishes them
@@ -292,16 +294,43 @@ __device__ __forceinline__ void st_off(void* base, uint32_t byte_off, X v)
 // best for each; the grid is rows x segments of waves either way).
 constexpr int step_block(int st) { return st == CMLBM_FP32 ? 1024 : 256; }
 
-template <int ST, int V, bool MASK, bool FIELD, bool NT, int MODEL>
+// FP64 sum over the 64 lanes of a wave by a butterfly of lane exchanges: every
+// lane ends with the same value (each level adds the same two operands), so
+// the result does not depend on which lane writes it.
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v = fmax(v, __shfl_xor(v, m));
+    return v;
+}
+
+// One time step, one wave per 64 x V cell row segment.  With RED the step
+// also forms, from the same gather, the FP64 partial sums of the state it
+// reads (the quantities of k_reduce, from the per-cell values of the step's
+// own arithmetic) and writes them for this wave to wpart[wave][kNPart]; every
+// lane then stays live until that wave-wide sum, and lanes without a fluid
+// cell only skip their contributions and stores.  (RED is a template flag of
+// the kernel itself: a shared device function changed the register
+// allocation of the RED = false kernels.)
+template <int ST, int V, bool MASK, bool FIELD, bool NT, int MODEL, bool RED>
 __global__ __launch_bounds__(step_block(ST)) void k_step(const typename storage<ST>::S* __restrict__ src,
                                                   typename storage<ST>::S* __restrict__ dst, Geom g, int segs,
                                                   typename storage<ST>::T omega, typename storage<ST>::T rho0,
                                                   const typename storage<ST>::T* __restrict__ ftab,
                                                   const typename storage<ST>::T* __restrict__ field,
-                                                  const uint32_t* __restrict__ mask, int sr, uint32_t step)
+                                                  const uint32_t* __restrict__ mask, int sr, uint32_t step,
+                                                  double* __restrict__ wpart)
 {
     static_assert(V == 1 || !MASK, "bounce-back masks use one cell per lane");
     static_assert(MODEL == 0 || V == 1, "comparison models use one cell per lane");
+    static_assert(!RED || MODEL == 0, "fused reductions are for the method's collision");
     using SS = storage<ST>;
     using S = typename SS::S;
     using T = typename SS::T;
@@ -329,12 +358,17 @@ __global__ __launch_bounds__(step_block(ST)) void k_step(const typename storage<
         }
     const uint32_t own_row = (uint32_t)row * (uint32_t)g.nxp;
     T h[V][27];
+    bool live = active;  // this lane holds fluid cells (RED: a lane without one stays for the wave sum)
     if constexpr (V == 1) {
-        const uint32_t bx[3] = {(uint32_t)wrap(x0 + 1, g.nx) * (uint32_t)sizeof(S), (uint32_t)x0 * (uint32_t)sizeof(S),
-                                (uint32_t)wrap(x0 - 1, g.nx) * (uint32_t)sizeof(S)};
+        const int xa = RED && !active ? 0 : x0;  // RED: in-bounds addresses for lanes past the row end
+        const uint32_t bx[3] = {(uint32_t)wrap(xa + 1, g.nx) * (uint32_t)sizeof(S), (uint32_t)xa * (uint32_t)sizeof(S),
+                                (uint32_t)wrap(xa - 1, g.nx) * (uint32_t)sizeof(S)};
         uint32_t m = 0;
         if (MASK) m = active ? mask[own_row + x0] : kSolidBit;
-        if (!active || (m & kSolidBit)) return;
+        if constexpr (RED)
+            live = active && !(m & kSolidBit);
+        else if (!active || (m & kSolidBit))
+            return;
 #pragma unroll
         for (int i = 0; i < 27; ++i) {
             const S* plane_row = srow[vel_y(i) + 1][vel_z(i) + 1] + (uint64_t)i * g.pstride;
@@ -388,11 +422,12 @@ __global__ __launch_bounds__(step_block(ST)) void k_step(const typename storage<
                 h[c][i] = SS::load(&e);
             }
         }
-        if (!active) return;
+        if constexpr (!RED)
+            if (!active) return;
     }
     T Fx[V], Fy[V], Fz[V];
     if (FIELD) {
-        const uint64_t lin = (uint64_t)row * (uint64_t)g.nx + (uint64_t)x0;
+        const uint64_t lin = (uint64_t)row * (uint64_t)g.nx + (uint64_t)(RED && !live ? 0 : x0);
 #pragma unroll
         for (int c = 0; c < V; ++c) {
             Fx[c] = field[lin + c];
@@ -408,14 +443,110 @@ __global__ __launch_bounds__(step_block(ST)) void k_step(const typename storage<
             Fz[c] = fr[2];
         }
     }
+    T mq[RED ? V : 1][4];  // RED: each cell's drho, ux, uy, uz
 #pragma unroll
     for (int c = 0; c < V; ++c) {
         T rho, ux, uy, uz;
-        if constexpr (MODEL == 0)
+        if constexpr (RED) {
+            // collide() with its density deviation kept for the mass sum
+            T drho, k5[5], s5[5];
+            pre_collision(h[c], Fx[c], Fy[c], Fz[c], rho0, drho, ux, uy, uz, k5);
+#pragma unroll
+            for (int j = 0; j < 5; ++j) s5[j] = (T(1) - omega) * k5[j];
+            reconstruct(drho, ux, uy, uz, Fx[c], Fy[c], Fz[c], s5, rho0, h[c]);
+            mq[c][0] = drho;
+            mq[c][1] = ux;
+            mq[c][2] = uy;
+            mq[c][3] = uz;
+        } else if constexpr (MODEL == 0) {
             collide<T>(h[c], Fx[c], Fy[c], Fz[c], omega, rho0, rho, ux, uy, uz);
-        else
+        } else {
             collide_model<T, (MODEL & kModelEq2) != 0, (MODEL & kModelGuo) != 0, (MODEL & kModelBgk) != 0>(
                 h[c], Fx[c], Fy[c], Fz[c], omega, rho0, rho, ux, uy, uz);
+        }
+    }
+    if constexpr (RED) {
+        // the stores below, as a lambda so that the sums can follow them (a
+        // `return` inside leaves only the stores); the plain kernels keep the
+        // stores inline: routed through the lambda they were allocated more
+        // registers (FP16: 76 -> 81)
+        auto store_all = [&]() {
+            const uint32_t bst = (uint32_t)x0 * (uint32_t)sizeof(S);
+            if constexpr (sizeof(S) == 2) {
+                if (sr) {  // wave-uniform
+                    // stochastic rounding: 7 words of random bits per cell, byte (i % 4) of word i / 4
+                    uint32_t rw[V][7];
+#pragma unroll
+                    for (int c = 0; c < V; ++c) {
+                        const uint32_t lin = (uint32_t)((uint64_t)row * (uint64_t)g.nx + (uint64_t)(x0 + c));
+                        uint32_t w = mix32(lin ^ mix32(step * 0x9E3779B9u + 0x632BE5ABu));
+#pragma unroll
+                        for (int k = 0; k < 7; ++k) {
+                            w = xorshift32(w | 1u);
+                            rw[c][k] = w;
+                        }
+                    }
+#pragma unroll
+                    for (int i = 0; i < 27; ++i) {
+                        S* plane_row = dst + (uint64_t)i * g.pstride + own_row;
+                        vt o;
+#pragma unroll
+                        for (int c = 0; c < V; ++c) o[c] = SS::pack_sr(h[c][i], (rw[c][i / 4] >> (8 * (i % 4))) & 0xFFu);
+                        if constexpr (V == 1)
+                            st_off<NT>(plane_row, bst, o[0]);
+                        else
+                            st_off<NT>(plane_row, bst, o);
+                    }
+                    return;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 27; ++i) {
+                S* plane_row = dst + (uint64_t)i * g.pstride + own_row;
+                if constexpr (V == 1) {
+                    st_off<NT>(plane_row, bst, SS::pack(h[0][i]));
+                } else {
+                    vt o;
+#pragma unroll
+                    for (int c = 0; c < V; ++c) o[c] = SS::pack(h[c][i]);
+                    st_off<NT>(plane_row, bst, o);
+                }
+            }
+        };
+        if (live) store_all();
+        // FP64 sums of this lane's cells, then over the wave; after the stores,
+        // so that the post-collision populations are not held across them
+        double acc[kNPart];
+#pragma unroll
+        for (int k = 0; k < kNPart; ++k) acc[k] = 0.0;
+#pragma unroll
+        for (int c = 0; c < V; ++c) {
+            if (!live || (V > 1 && x0 + c >= g.nx)) continue;
+            const double r = (double)rho0 + (double)mq[c][0];
+            const double u[3] = {(double)mq[c][1], (double)mq[c][2], (double)mq[c][3]};
+            const double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+            acc[7] += 1.0;
+            if (!(isfinite(r) && isfinite(u2))) {
+                acc[6] += 1.0;
+                continue;
+            }
+            acc[0] += (double)mq[c][0];
+            acc[1] += r * u[0] - 0.5 * (double)Fx[c];  // sum_i f_i c_i
+            acc[2] += r * u[1] - 0.5 * (double)Fy[c];
+            acc[3] += r * u[2] - 0.5 * (double)Fz[c];
+            acc[4] += 0.5 * r * u2;
+            acc[5] = fmax(acc[5], sqrt(u2));
+            acc[9] += u2;
+        }
+#pragma unroll
+        for (int k = 0; k < kNPart; ++k) acc[k] = k == 5 ? wave_max(acc[k]) : wave_sum(acc[k]);
+        if (lane < kNPart) {
+            double v = acc[0];
+#pragma unroll
+            for (int k = 1; k < kNPart; ++k) v = lane == k ? acc[k] : v;
+            wpart[(uint64_t)wave * kNPart + lane] = v;
+        }
+        return;
     }
     const uint32_t bst = (uint32_t)x0 * (uint32_t)sizeof(S);
     if constexpr (sizeof(S) == 2) {
@@ -992,6 +1123,34 @@ __global__ __launch_bounds__(kBlock) void k_reduce_final(const double* __restric
     }
 }
 
+// Second level of the fused reductions: workgroup (b, k) sums, in a fixed
+// order and tree, chunk k of the per-wave partials of batch member b (waves
+// [b * wpm, (b + 1) * wpm)) into part[b][k], the layout k_reduce writes.
+__global__ __launch_bounds__(kBlock) void k_red_waves(const double* __restrict__ wpart, int wpm, int nchunk,
+                                                      double* __restrict__ part)
+{
+    __shared__ double sh[kNPart][kBlock];
+    const int b = blockIdx.x / nchunk, k = blockIdx.x % nchunk, tid = threadIdx.x;
+    const int per = (wpm + nchunk - 1) / nchunk;
+    const int w0 = k * per, w1 = w0 + per < wpm ? w0 + per : wpm;
+    double acc[kNPart];
+    for (int q = 0; q < kNPart; ++q) acc[q] = 0.0;
+    for (int w = w0 + tid; w < w1; w += kBlock)
+        for (int q = 0; q < kNPart; ++q) {
+            const double v = wpart[((uint64_t)b * wpm + w) * kNPart + q];
+            acc[q] = q == 5 ? fmax(acc[q], v) : acc[q] + v;
+        }
+    for (int q = 0; q < kNPart; ++q) sh[q][tid] = acc[q];
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+        if (tid < st)
+            for (int q = 0; q < kNPart; ++q)
+                sh[q][tid] = q == 5 ? fmax(sh[q][tid], sh[q][tid + st]) : sh[q][tid] + sh[q][tid + st];
+        __syncthreads();
+    }
+    if (tid < kNPart) part[((uint64_t)b * nchunk + k) * kNPart + tid] = sh[tid][0];
+}
+
 // Per-cell link mask: bit i set if the node x - c_i lies beyond a wall or is
 // solid (the population pulled along c_i then comes from the opposite
 // direction at x itself), bit 27 set if x is solid.
@@ -1039,7 +1198,7 @@ struct cmlbm_lattice {
     void* pop[2];
     int cur;  // buffer holding the state
     uint8_t* scratch;
-    size_t off_ftab64, off_ftab32, off_mask, off_part, off_final, off_snap;
+    size_t off_ftab64, off_ftab32, off_mask, off_part, off_final, off_snap, off_wpart;
     int gpb;
     bool needs_mask, mask_ready, initialized, snap_valid;
     int force_mode;
@@ -1056,10 +1215,19 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct Layout {
     Geom g;
     size_t pop_bytes, scratch_bytes;
-    size_t off_ftab64, off_ftab32, off_mask, off_part, off_final, off_snap;
+    size_t off_ftab64, off_ftab32, off_mask, off_part, off_final, off_snap, off_wpart;
     int gpb;
     bool needs_mask;
 };
+
+// Cells per lane of k_step: two for 16-bit storage on rows of even length
+// without a bounce-back mask, otherwise one.
+int lanes_rule(int storage, int nx, bool needs_mask)
+{
+    if (needs_mask) return 1;
+    if ((storage == CMLBM_FP16 || storage == CMLBM_BF16) && nx % 2 == 0) return 2;
+    return 1;
+}
 
 int validate(const cmlbm_params* p)
 {
@@ -1074,9 +1242,11 @@ int validate(const cmlbm_params* p)
     for (int a = 0; a < 3; ++a)
         if (p->wall[a] != CMLBM_PERIODIC && p->wall[a] != CMLBM_BOUNCEBACK) return CMLBM_EINVAL;
     if (p->flags & ~(CMLBM_FLAG_SOLID | CMLBM_FLAG_RESIDUAL | CMLBM_FLAG_STOCHASTIC | CMLBM_FLAG_FORCE_GUO |
-                     CMLBM_FLAG_EQ_SECOND | CMLBM_FLAG_BGK))
+                     CMLBM_FLAG_EQ_SECOND | CMLBM_FLAG_BGK | CMLBM_FLAG_FUSED_REDUCE))
         return CMLBM_EINVAL;
     const uint32_t model = p->flags & (CMLBM_FLAG_FORCE_GUO | CMLBM_FLAG_EQ_SECOND | CMLBM_FLAG_BGK);
+    // fused reductions run in the kernel of the method's own collision on population storage
+    if ((p->flags & CMLBM_FLAG_FUSED_REDUCE) && (model || p->storage == CMLBM_MOM32)) return CMLBM_EINVAL;
     if (model && p->storage != CMLBM_FP64 && p->storage != CMLBM_FP32) return CMLBM_EINVAL;
     if ((model & CMLBM_FLAG_BGK) && model != CMLBM_FLAG_BGK &&
         model != (CMLBM_FLAG_BGK | CMLBM_FLAG_FORCE_GUO | CMLBM_FLAG_EQ_SECOND))
@@ -1139,6 +1309,13 @@ int make_layout(const cmlbm_params* p, Layout* L)
     off = align256(off + (size_t)p->nbatch * CMLBM_NRED * sizeof(double));
     L->off_snap = off;
     if (p->flags & CMLBM_FLAG_RESIDUAL) off = align256(off + 3 * g.ncell * sizeof(double));
+    L->off_wpart = off;
+    if (p->flags & CMLBM_FLAG_FUSED_REDUCE) {  // one partial row per k_step wave
+        const int V = lanes_rule(p->storage, p->nx, L->needs_mask);
+        const uint64_t segs = (uint64_t)(p->nx + 64 * V - 1) / (64 * V);
+        if (segs * p->ny * p->nz > 0x7fffffffULL) return CMLBM_EINVAL;
+        off = align256(off + rows * segs * kNPart * sizeof(double));
+    }
     L->scratch_bytes = off;
     return CMLBM_OK;
 }
@@ -1187,12 +1364,7 @@ int ensure_mask(cmlbm_lattice* lat, hipStream_t s)
 // Cells per lane of k_step: 16-bit storage reads 2 cells (4 bytes) per lane
 // where the row length allows, everything else one cell per lane.  (With the
 // population planes spaced, 2 cells beat 4 by 2-5% at 512^3.)
-int step_lanes(const cmlbm_lattice* lat)
-{
-    if (lat->needs_mask) return 1;
-    if ((lat->p.storage == CMLBM_FP16 || lat->p.storage == CMLBM_BF16) && lat->g.nx % 2 == 0) return 2;
-    return 1;
-}
+int step_lanes(const cmlbm_lattice* lat) { return lanes_rule(lat->p.storage, lat->g.nx, lat->needs_mask); }
 
 int lat_model(const cmlbm_lattice* lat)
 {
@@ -1211,10 +1383,10 @@ void launch_step_v(cmlbm_lattice* lat, hipStream_t s)
     constexpr int wpb = step_block(ST) / 64;
     const dim3 grid((unsigned)((waves + wpb - 1) / wpb));
     const T* ftab = (const T*)(lat->scratch + (ST == CMLBM_FP64 ? lat->off_ftab64 : lat->off_ftab32));
-    k_step<ST, V, MASK, FIELD, true, MODEL><<<grid, dim3(step_block(ST)), 0, s>>>(
+    k_step<ST, V, MASK, FIELD, true, MODEL, false><<<grid, dim3(step_block(ST)), 0, s>>>(
         (const typename SS::S*)lat->pop[lat->cur], (typename SS::S*)lat->pop[1 - lat->cur], g, segs,
         (T)(1.0 / lat->p.tau), (T)lat->p.rho0, ftab, (const T*)lat->field, mask_ptr(lat),
-        (lat->p.flags & CMLBM_FLAG_STOCHASTIC) ? 1 : 0, (uint32_t)lat->t);
+        (lat->p.flags & CMLBM_FLAG_STOCHASTIC) ? 1 : 0, (uint32_t)lat->t, nullptr);
 }
 
 template <int ST, int MODEL>
@@ -1279,6 +1451,74 @@ int launch_step_st(cmlbm_lattice* lat, hipStream_t s)
             launch_step_v<ST, 1, false, false>(lat, s);
     }
     return launch_check(lat, "step");
+}
+
+// One step with fused reductions: k_step with RED, then the two reduction levels
+// into the final row of each batch member.
+template <int ST, int V, bool MASK, bool FIELD>
+void launch_step_red_v(cmlbm_lattice* lat, hipStream_t s)
+{
+    using SS = storage<ST>;
+    using T = typename SS::T;
+    const Geom& g = lat->g;
+    const int segs = (g.nx + 64 * V - 1) / (64 * V);
+    const uint64_t waves = (uint64_t)g.rows * (uint64_t)segs;
+    constexpr int wpb = step_block(ST) / 64;
+    const dim3 grid((unsigned)((waves + wpb - 1) / wpb));
+    const T* ftab = (const T*)(lat->scratch + (ST == CMLBM_FP64 ? lat->off_ftab64 : lat->off_ftab32));
+    k_step<ST, V, MASK, FIELD, true, 0, true><<<grid, dim3(step_block(ST)), 0, s>>>(
+        (const typename SS::S*)lat->pop[lat->cur], (typename SS::S*)lat->pop[1 - lat->cur], g, segs,
+        (T)(1.0 / lat->p.tau), (T)lat->p.rho0, ftab, (const T*)lat->field, mask_ptr(lat),
+        (lat->p.flags & CMLBM_FLAG_STOCHASTIC) ? 1 : 0, (uint32_t)lat->t, (double*)(lat->scratch + lat->off_wpart));
+}
+
+template <int ST>
+int launch_step_red_st(cmlbm_lattice* lat, hipStream_t s)
+{
+    const bool F = lat->force_mode == CMLBM_FORCE_FIELD;
+    const int V = step_lanes(lat);
+    if (lat->needs_mask) {
+        if (F)
+            launch_step_red_v<ST, 1, true, true>(lat, s);
+        else
+            launch_step_red_v<ST, 1, true, false>(lat, s);
+    } else if (V == 2) {
+        if constexpr (ST == CMLBM_FP16 || ST == CMLBM_BF16) {
+            if (F)
+                launch_step_red_v<ST, 2, false, true>(lat, s);
+            else
+                launch_step_red_v<ST, 2, false, false>(lat, s);
+        }
+    } else {
+        if (F)
+            launch_step_red_v<ST, 1, false, true>(lat, s);
+        else
+            launch_step_red_v<ST, 1, false, false>(lat, s);
+    }
+    int rc = launch_check(lat, "step (fused reductions)");
+    if (rc) return rc;
+    const Geom& g = lat->g;
+    const int segs = (g.nx + 64 * V - 1) / (64 * V);
+    const int wpm = (g.rows / g.nb) * segs;  // waves per batch member
+    int nchunk = (wpm + 1023) / 1024;
+    if (nchunk > lat->gpb) nchunk = lat->gpb;
+    k_red_waves<<<dim3(g.nb * nchunk), dim3(kBlock), 0, s>>>((const double*)(lat->scratch + lat->off_wpart), wpm,
+                                                            nchunk, (double*)(lat->scratch + lat->off_part));
+    rc = launch_check(lat, "reduce waves");
+    if (rc) return rc;
+    k_reduce_final<<<dim3(g.nb), dim3(kBlock), 0, s>>>((const double*)(lat->scratch + lat->off_part), nchunk,
+                                                      lat->p.rho0, (double*)(lat->scratch + lat->off_final));
+    return launch_check(lat, "reduce final");
+}
+
+int launch_step_red(cmlbm_lattice* lat, hipStream_t s)
+{
+    switch (lat->p.storage) {
+        case CMLBM_FP64: return launch_step_red_st<CMLBM_FP64>(lat, s);
+        case CMLBM_FP32: return launch_step_red_st<CMLBM_FP32>(lat, s);
+        case CMLBM_FP16: return launch_step_red_st<CMLBM_FP16>(lat, s);
+        default: return launch_step_red_st<CMLBM_BF16>(lat, s);
+    }
 }
 
 template <int TY>
@@ -1446,6 +1686,22 @@ int launch_reduce(cmlbm_lattice* lat, int residual, int snapshot, hipStream_t s)
 
 bool aligned256(const void* p) { return ((uintptr_t)p & 255u) == 0; }
 
+// Host completion of the FP64 reductions: the mass gets rho0 per finite fluid
+// cell (the sums hold deviations), the residual its square root.
+int finish_reduce(cmlbm_lattice* lat, bool residual, double* host_out)
+{
+    bool unstable = false;
+    for (size_t b = 0; b < (size_t)lat->g.nb; ++b) {
+        double* o = host_out + b * CMLBM_NRED;
+        o[CMLBM_RED_MASS] += lat->p.rho0 * (o[CMLBM_RED_FLUID] - o[CMLBM_RED_NONFINITE]);
+        o[CMLBM_RED_RESIDUAL] = residual && o[CMLBM_RED_U2] > 0 ? std::sqrt(o[CMLBM_RED_DU2] / o[CMLBM_RED_U2]) : 0.0;
+        if (!residual) o[CMLBM_RED_DU2] = 0.0;
+        if (o[CMLBM_RED_NONFINITE] > 0) unstable = true;
+    }
+    if (unstable) return fail(lat, CMLBM_EUNSTABLE, "non-finite density or velocity");
+    return CMLBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1486,6 +1742,7 @@ int cmlbm_create(const cmlbm_params* params, void* pop_a, size_t pop_a_bytes, vo
     lat->off_part = L.off_part;
     lat->off_final = L.off_final;
     lat->off_snap = L.off_snap;
+    lat->off_wpart = L.off_wpart;
     lat->gpb = L.gpb;
     lat->needs_mask = L.needs_mask;
     lat->mask_ready = false;
@@ -1680,16 +1937,28 @@ int cmlbm_reduce(cmlbm_lattice* lat, uint32_t what, double* host_out, void* hip_
     rc = hip_check(lat, hipStreamSynchronize(s), "reduce sync");
     if (rc) return rc;
     if (snapshot) lat->snap_valid = true;
-    bool unstable = false;
-    for (size_t b = 0; b < nb; ++b) {
-        double* o = host_out + b * CMLBM_NRED;
-        o[CMLBM_RED_MASS] += lat->p.rho0 * (o[CMLBM_RED_FLUID] - o[CMLBM_RED_NONFINITE]);
-        o[CMLBM_RED_RESIDUAL] = residual && o[CMLBM_RED_U2] > 0 ? std::sqrt(o[CMLBM_RED_DU2] / o[CMLBM_RED_U2]) : 0.0;
-        if (!residual) o[CMLBM_RED_DU2] = 0.0;
-        if (o[CMLBM_RED_NONFINITE] > 0) unstable = true;
-    }
-    if (unstable) return fail(lat, CMLBM_EUNSTABLE, "non-finite density or velocity");
-    return CMLBM_OK;
+    return finish_reduce(lat, residual, host_out);
+}
+
+int cmlbm_step_reduce(cmlbm_lattice* lat, double* host_out, void* hip_stream)
+{
+    if (!lat || !host_out) return CMLBM_EINVAL;
+    if (!(lat->p.flags & CMLBM_FLAG_FUSED_REDUCE))
+        return fail(lat, CMLBM_ESTATE, "step_reduce needs CMLBM_FLAG_FUSED_REDUCE");
+    if (!lat->initialized) return fail(lat, CMLBM_ESTATE, "step_reduce before init");
+    hipStream_t s = (hipStream_t)hip_stream;
+    int rc = launch_step_red(lat, s);
+    if (rc) return rc;
+    lat->cur = 1 - lat->cur;
+    lat->t += 1;
+    rc = hip_check(lat,
+                   hipMemcpyAsync(host_out, lat->scratch + lat->off_final, lat->g.nb * CMLBM_NRED * sizeof(double),
+                                  hipMemcpyDeviceToHost, s),
+                   "step_reduce copy");
+    if (rc) return rc;
+    rc = hip_check(lat, hipStreamSynchronize(s), "step_reduce sync");
+    if (rc) return rc;
+    return finish_reduce(lat, false, host_out);
 }
 
 int cmlbm_save_state(cmlbm_lattice* lat, void* dev_blob, size_t blob_bytes, void* hip_stream)

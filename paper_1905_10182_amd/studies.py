@@ -76,7 +76,12 @@ def _rel(a, b, torch):
     return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
 
 
-def lockstep(lattices, steps, every, label, out=sys.stdout):
+def lockstep(lattices, steps, every, label, out=sys.stdout, per_step_ke=False):
+    """Advance the lattices together; every `every` steps print their velocity
+    errors against the FP64 (and FP32) run and their FP64-reduced kinetic
+    energy.  With per_step_ke (lattices created with fused reductions) the
+    steps go through step_reduce and a row of every lattice's kinetic energy
+    is printed for every step, at no extra pass over the populations."""
     import torch
 
     names = list(lattices)
@@ -100,8 +105,13 @@ def lockstep(lattices, steps, every, label, out=sys.stdout):
             break
         n = min(every, steps - t)
         t0 = time.perf_counter()
-        for k in names:
-            lattices[k].step(n)
+        if per_step_ke:
+            for j in range(n):
+                ke = {k: float(lattices[k].step_reduce(allow_unstable=True)[0][RED["ke"]]) for k in names}
+                print(json.dumps({"study": label, "step": t + j, "ke": ke}), file=out, flush=True)
+        else:
+            for k in names:
+                lattices[k].step(n)
         torch.cuda.synchronize()
         t += n
         print(f"[{label}] step {t} ({time.perf_counter() - t0:.2f} s for {n} steps x {len(names)} runs)",
@@ -109,32 +119,34 @@ def lockstep(lattices, steps, every, label, out=sys.stdout):
     return rows
 
 
-def _make(st, n, tau):
+def _make(st, n, tau, fused=False):
     """Storage names: fp64, fp32, fp16, bf16, and fp16sr / bf16sr for stochastic rounding."""
-    return Lattice(n, n, n, tau=tau, storage=st[:4], stochastic=st.endswith("sr"), device="cuda:0")
+    return Lattice(n, n, n, tau=tau, storage=st[:4], stochastic=st.endswith("sr"), fused_reduce=fused,
+                   device="cuda:0")
 
 
-def precision_study(n=512, steps=2000, every=100, storages=("fp64", "fp32", "fp16", "fp16sr", "bf16", "bf16sr")):
+def precision_study(n=512, steps=2000, every=100, storages=("fp64", "fp32", "fp16", "fp16sr", "bf16", "bf16sr"),
+                    per_step_ke=False):
     wl = workloads.taylor_green(n, seed=1)
     lats = {}
     for st in storages:
-        lat = _make(st, n, wl["tau"])
+        lat = _make(st, n, wl["tau"], per_step_ke)
         lat.init(wl["rho"], wl["u"])
         lats[st] = lat
     del wl
-    return lockstep(lats, steps, every, f"taylor_green_{n}")
+    return lockstep(lats, steps, every, f"taylor_green_{n}", per_step_ke=per_step_ke)
 
 
-def kolmogorov_study(n=384, steps=5000, every=500, storages=("fp64", "fp32", "fp16", "fp16sr")):
+def kolmogorov_study(n=384, steps=5000, every=500, storages=("fp64", "fp32", "fp16", "fp16sr"), per_step_ke=False):
     wl = workloads.kolmogorov(n)
     lats = {}
     for st in storages:
-        lat = _make(st, n, wl["tau"])
+        lat = _make(st, n, wl["tau"], per_step_ke)
         lat.set_force("profile_y", wl["force_profile_y"])
         lat.init(wl["rho"], wl["u"])
         lats[st] = lat
     del wl
-    return lockstep(lats, steps, every, f"kolmogorov_{n}")
+    return lockstep(lats, steps, every, f"kolmogorov_{n}", per_step_ke=per_step_ke)
 
 
 def four_rolls_study(ns=(8, 16, 32, 64, 128, 256), u0s=(1e-3, 1e-2), relax=3.0, storage="fp64", models=("m1",),
@@ -437,12 +449,14 @@ def main(argv=None):
     ap.add_argument("--n", type=int)
     ap.add_argument("--steps", type=int)
     ap.add_argument("--every", type=int)
+    ap.add_argument("--per-step-ke", action="store_true",
+                    help="precision / kolmogorov: kinetic energy of every run at every step (fused reductions)")
     a = ap.parse_args(argv)
     kw = {k: v for k, v in (("n", a.n), ("steps", a.steps), ("every", a.every)) if v is not None}
     if a.study == "precision":
-        precision_study(**kw)
+        precision_study(per_step_ke=a.per_step_ke, **kw)
     elif a.study == "kolmogorov":
-        kolmogorov_study(**kw)
+        kolmogorov_study(per_step_ke=a.per_step_ke, **kw)
     elif a.study == "stability":
         stability_study(**kw)
     elif a.study == "orszag-tang":

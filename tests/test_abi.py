@@ -81,7 +81,7 @@ def test_plane_size_limit():
                                 dict(nz=1, wall=(0, 0, 1)), dict(storage="mom32", wall=(0, 1, 0)),
                                 dict(storage="mom32", flags=1), dict(storage="mom32", flags=4),
                                 dict(storage="mom32", flags=8), dict(storage=5), dict(flags=32 | 8),
-                                dict(flags=32, storage="fp16"), dict(flags=64)])
+                                dict(flags=32, storage="fp16"), dict(flags=128)])
 def test_invalid_params(kw):
     with pytest.raises(B.CmlbmError) as e:
         B.required_bytes(req(**kw))
@@ -147,3 +147,19 @@ def test_moment_storage_bytes():
     pop32, _ = B.required_bytes(req(nx=64, ny=8, nz=8, storage="fp32"))
     assert pop32 == 3 * pop
     B.required_bytes(req(storage="mom32", flags=B.FLAG_RESIDUAL))  # residual snapshots are allowed
+
+
+def test_fused_reduce_flag():
+    # the per-wave partials: 10 doubles per 64-cell (16-bit: 128-cell) row segment
+    _, base = B.required_bytes(req(nx=100, ny=8, nz=4, storage="fp32"))
+    _, fused = B.required_bytes(req(nx=100, ny=8, nz=4, storage="fp32", flags=B.FLAG_FUSED_REDUCE))
+    assert fused - base >= 2 * 8 * 4 * 10 * 8
+    _, f16 = B.required_bytes(req(nx=256, ny=8, nz=4, storage="fp16", flags=B.FLAG_FUSED_REDUCE))
+    _, b16 = B.required_bytes(req(nx=256, ny=8, nz=4, storage="fp16"))
+    assert f16 - b16 >= 2 * 8 * 4 * 10 * 8
+    # only with the method's collision on population storage
+    for kw in (dict(storage="mom32"), dict(flags=B.FLAG_FUSED_REDUCE | B.FLAG_FORCE_GUO)):
+        p = req(**kw)
+        p.flags |= B.FLAG_FUSED_REDUCE
+        with pytest.raises(B.CmlbmError):
+            B.required_bytes(p)
