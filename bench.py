@@ -160,6 +160,42 @@ def run_gpu_mhd(n, steps, warmup):
                 bytes_per_launch=BYTES_PER_CELL_MHD * ncell, launch_s=secs / steps)
 
 
+def run_fused(n, calls):
+    """cmlbm_step_reduce (a step whose kernel also forms the FP64 reductions of
+    the state it reads) against cmlbm_reduce + cmlbm_step, wall clock per call
+    (both wait for the stream), FP32 TGV n^3."""
+    import torch
+    import workloads
+    from paper_1905_10182_amd import Lattice
+
+    wl = workloads.taylor_green(n, seed=1)
+    lat = Lattice(n, n, n, tau=wl["tau"], storage="fp32", fused_reduce=True, device="cuda:0")
+    lat.init(wl["rho"], wl["u"])
+    del wl
+    lat.step(5)
+    lat.step_reduce()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        lat.step(1)
+        torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / calls
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        r = lat.step_reduce()
+    t_fused = (time.perf_counter() - t0) / calls
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        lat.reduce()
+        lat.step(1)
+        torch.cuda.synchronize()
+    t_sep = (time.perf_counter() - t0) / calls
+    lat.close()
+    return {"workload": f"taylor_green_{n} fp32, one call per step, wall clock incl. the stream sync",
+            "step_ms": round(t_step * 1e3, 4), "step_reduce_ms": round(t_fused * 1e3, 4),
+            "reduce_then_step_ms": round(t_sep * 1e3, 4), "ke": float(r[0, 4])}
+
+
 def copy_bandwidth():
     import torch
     n = 1 << 30  # 4 GiB of float32
@@ -353,6 +389,8 @@ def main():
             "kernel": "k_mhd_step<float>", "glups": round(rmag["glups"], 3), "ms_per_step": round(rmag["ms_per_step"], 4),
             "bytes_per_cell": BYTES_PER_CELL_MHD, "hbm_gbs": round(bw, 1), "hbm_frac": round(bw / HBM_PEAK_GBS, 4)}
         print(f"[bench] magnetic lattice {rmag['glups']:.2f} GLUPS, {bw:.0f} GB/s", file=sys.stderr, flush=True)
+    print(f"[bench] fused reductions, TGV {args.n}^3 fp32", file=sys.stderr, flush=True)
+    extra["fused_reduce"] = run_fused(args.n, 20)
     extra["device_copy_gbs"] = round(copy_bandwidth(), 1)
     if not args.no_warmstart:
         print("[bench] warm start: 64 sphere channels 64x32x32, cold vs U-Net init", file=sys.stderr, flush=True)

@@ -50,7 +50,7 @@ def torch():
     return t
 
 
-def pair(storage, nx, ny, nz, nbatch=1, wall=(0, 0, 0), solid=None, field=None, steps=3, seed=5):
+def pair(storage, nx, ny, nz, nbatch=1, wall=(0, 0, 0), solid=None, field=None, steps=3, seed=5, stochastic=False):
     from paper_1905_10182_amd import Lattice
     g = W.generator(seed)
     u = g.uniform(-0.04, 0.04, size=(3, nbatch, nz, ny, nx))
@@ -58,7 +58,7 @@ def pair(storage, nx, ny, nz, nbatch=1, wall=(0, 0, 0), solid=None, field=None, 
     lats = []
     for fused in (True, False):
         lat = Lattice(nx, ny, nz, nbatch=nbatch, tau=0.6, storage=storage, wall=wall, solid=solid is not None,
-                      fused_reduce=fused, device="cuda:0")
+                      stochastic=stochastic, fused_reduce=fused, device="cuda:0")
         if solid is not None:
             lat.set_solid(solid)
         if field is not None:
@@ -108,6 +108,16 @@ def test_fused_reduce_periodic(torch, storage, nx):
     37: odd, one cell per lane; 128: a row of exactly one or two waves)."""
     log(f"{storage} fused reductions, {nx}x12x10 periodic")
     a, b = pair(storage, nx, 12, 10)
+    check(torch, a, b, storage)
+
+
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+@pytest.mark.parametrize("nx", [40, 37])
+def test_fused_reduce_stochastic_rounding(torch, storage, nx):
+    """16-bit storage with stochastic rounding: the fused kernel draws the same
+    counter-based bits for each (cell, step) as the plain one."""
+    log(f"{storage} stochastic rounding, fused reductions, {nx}x12x10")
+    a, b = pair(storage, nx, 12, 10, stochastic=True)
     check(torch, a, b, storage)
 
 
