@@ -290,9 +290,13 @@ __device__ __forceinline__ void st_off(void* base, uint32_t byte_off, X v)
     }
 }
 
-// Threads per k_step workgroup: 1024 for FP32 storage, 256 otherwise (measured
-// best for each; the grid is rows x segments of waves either way).
-constexpr int step_block(int st) { return st == CMLBM_FP32 ? 1024 : 256; }
+// Threads per k_step workgroup: 1024 for FP32 storage, 512 for FP64 without a
+// bounce-back mask, 256 otherwise (measured best for each; the grid is rows x
+// segments of waves either way).
+constexpr int step_block(int st, bool mask)
+{
+    return st == CMLBM_FP32 ? 1024 : (st == CMLBM_FP64 && !mask) ? 512 : 256;
+}
 
 // FP64 sum over the 64 lanes of a wave by a butterfly of lane exchanges: every
 // lane ends with the same value (each level adds the same two operands), so
@@ -320,7 +324,7 @@ __device__ __forceinline__ double wave_max(double v)
 // the kernel itself: a shared device function changed the register
 // allocation of the RED = false kernels.)
 template <int ST, int V, bool MASK, bool FIELD, bool NT, int MODEL, bool RED>
-__global__ __launch_bounds__(step_block(ST)) void k_step(const typename storage<ST>::S* __restrict__ src,
+__global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename storage<ST>::S* __restrict__ src,
                                                   typename storage<ST>::S* __restrict__ dst, Geom g, int segs,
                                                   typename storage<ST>::T omega, typename storage<ST>::T rho0,
                                                   const typename storage<ST>::T* __restrict__ ftab,
@@ -336,7 +340,7 @@ __global__ __launch_bounds__(step_block(ST)) void k_step(const typename storage<
     using T = typename SS::T;
     typedef S vt __attribute__((ext_vector_type(V == 1 ? 2 : V)));
     const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (step_block(ST) / 64) + (threadIdx.x >> 6)));
+    const int wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (step_block(ST, MASK) / 64) + (threadIdx.x >> 6)));
     const int row = wave / segs;
     if (row >= g.rows) return;  // whole wave
     const int seg = wave - row * segs;
@@ -1380,10 +1384,10 @@ void launch_step_v(cmlbm_lattice* lat, hipStream_t s)
     const Geom& g = lat->g;
     const int segs = (g.nx + 64 * V - 1) / (64 * V);
     const uint64_t waves = (uint64_t)g.rows * (uint64_t)segs;
-    constexpr int wpb = step_block(ST) / 64;
+    constexpr int wpb = step_block(ST, MASK) / 64;
     const dim3 grid((unsigned)((waves + wpb - 1) / wpb));
     const T* ftab = (const T*)(lat->scratch + (ST == CMLBM_FP64 ? lat->off_ftab64 : lat->off_ftab32));
-    k_step<ST, V, MASK, FIELD, true, MODEL, false><<<grid, dim3(step_block(ST)), 0, s>>>(
+    k_step<ST, V, MASK, FIELD, true, MODEL, false><<<grid, dim3(step_block(ST, MASK)), 0, s>>>(
         (const typename SS::S*)lat->pop[lat->cur], (typename SS::S*)lat->pop[1 - lat->cur], g, segs,
         (T)(1.0 / lat->p.tau), (T)lat->p.rho0, ftab, (const T*)lat->field, mask_ptr(lat),
         (lat->p.flags & CMLBM_FLAG_STOCHASTIC) ? 1 : 0, (uint32_t)lat->t, nullptr);
@@ -1463,10 +1467,10 @@ void launch_step_red_v(cmlbm_lattice* lat, hipStream_t s)
     const Geom& g = lat->g;
     const int segs = (g.nx + 64 * V - 1) / (64 * V);
     const uint64_t waves = (uint64_t)g.rows * (uint64_t)segs;
-    constexpr int wpb = step_block(ST) / 64;
+    constexpr int wpb = step_block(ST, MASK) / 64;
     const dim3 grid((unsigned)((waves + wpb - 1) / wpb));
     const T* ftab = (const T*)(lat->scratch + (ST == CMLBM_FP64 ? lat->off_ftab64 : lat->off_ftab32));
-    k_step<ST, V, MASK, FIELD, true, 0, true><<<grid, dim3(step_block(ST)), 0, s>>>(
+    k_step<ST, V, MASK, FIELD, true, 0, true><<<grid, dim3(step_block(ST, MASK)), 0, s>>>(
         (const typename SS::S*)lat->pop[lat->cur], (typename SS::S*)lat->pop[1 - lat->cur], g, segs,
         (T)(1.0 / lat->p.tau), (T)lat->p.rho0, ftab, (const T*)lat->field, mask_ptr(lat),
         (lat->p.flags & CMLBM_FLAG_STOCHASTIC) ? 1 : 0, (uint32_t)lat->t, (double*)(lat->scratch + lat->off_wpart));
