@@ -24,7 +24,7 @@ s + b).
 - evaluate: steps to residual 1e-8 for the same channels from three
   initial states -- rest (cold), the analytic Poiseuille profile of the empty
   channel (a non-learned control), and the network prediction (warm) --
-  with the solver itself as the judge of convergence.  A prediction that is
+  with the solver itself deciding convergence.  A prediction that is
   non-finite or exceeds |u| = 0.1 falls back to rest.  The converged fields
   of the warm and cold runs are compared.
 """
