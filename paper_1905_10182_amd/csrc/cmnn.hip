@@ -383,12 +383,14 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(G g, const bf16* __restrict_
 // brick's MFMAs so that their latency hides behind the compute.  A tap's x
 // fragment starts dx + 1 elements into an aligned 16-byte LDS read: for
 // dx = 0 and +1 the eight elements are realigned from that read and the next
-// dword.  Row strides are padded so that the 16 rows of a fragment read fall
-// on distinct bank groups.  Two LDS buffers alternate: a wave stores brick
-// br + 1 as soon as its MFMAs on brick br are done, so the stores of one
-// wave overlap the MFMAs of another, with one barrier per brick.  Wave w accumulates the 2 x 2 blocks of 16 x 16
-// for taps w, w + 8, w + 16, w + 24; the dy fragments of a K step are read
-// once and serve all of them.
+// dword, and the three x taps of one (dz, dy) share that read.  Row strides
+// are padded so that the 16 rows of a fragment read fall on distinct bank
+// groups.  Two LDS buffers alternate: a wave stores brick br + 1 as soon as
+// its MFMAs on brick br are done, so the stores of one wave overlap the MFMAs
+// of another, with one barrier per brick.  The work units are the 18 pairs
+// (tap group (dz, dy), 16-channel ci block); wave w takes units w, w + 8 and
+// w + 16 and accumulates, for each, the three x taps times two 16-channel co
+// blocks.  The dy fragments of a K step are read once and serve all of them.
 
 constexpr int kDyStride = 256 + 8;        // bf16 per co row of staged dy
 constexpr int kXRow = 24;                 // bf16 per staged halo row (18 used)
@@ -485,11 +487,14 @@ __global__ __launch_bounds__(kBwThreads) void k_conv_bwd_w_tile(G g, const bf16*
             for (int c = 0; c < 8; ++c) *(u4*)&sdy[(dcg * 8 + c) * kDyStride + drow * 16 + dxo] = out[c];
         }
     };
-    f4 acc[4][2][2];
+    // work units: (tap group g = (dz, dy), ci block ib), 18 of them; wave w
+    // takes units w, w + 8, w + 16.  The three x taps of a group share one
+    // 20-byte B read per lane (their K windows are byte shifts of it).
+    f4 acc[3][3][2];  // [unit of this wave][x tap][co block]
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < 3; ++k)
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 3; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b) acc[k][a][b] = f4{0.f, 0.f, 0.f, 0.f};
     const int j = lane >> 4, l16 = lane & 15;
@@ -519,28 +524,26 @@ __global__ __launch_bounds__(kBwThreads) void k_conv_bwd_w_tile(G g, const bf16*
             for (int cb = 0; cb < 2; ++cb) a[cb] = *(const bf16x8*)&sdy[(cb * 16 + l16) * kDyStride + row * 16 + xo];
             const int dd = row >> 2, hh = row & 3;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int t = wave + 8 * k;
-                if (t < 27) {
-                    const int dz = t / 9 - 1, dyy = (t / 3) % 3 - 1, cx = t % 3;
+            for (int k = 0; k < 3; ++k) {
+                const int u = wave + 8 * k;
+                if (u < 18) {
+                    const int g = u >> 1, ib = u & 1;
+                    const int dz = g / 3 - 1, dyy = g % 3 - 1;
                     const int hr = (dd + 1 + dz) * 6 + hh + 1 + dyy;
+                    const bf16* q = &sx[(ib * 16 + l16) * kXStride + hr * kXRow + xo];
+                    const u4 lo = *(const u4*)q;
+                    const unsigned hi = *(const unsigned*)(q + 8);
+                    // x taps cx = 0, 1, 2 start 0, 1, 2 elements into the read
+                    const u4 f[3] = {lo,
+                                     u4{__builtin_amdgcn_alignbyte(lo[1], lo[0], 2), __builtin_amdgcn_alignbyte(lo[2], lo[1], 2),
+                                        __builtin_amdgcn_alignbyte(lo[3], lo[2], 2), __builtin_amdgcn_alignbyte(hi, lo[3], 2)},
+                                     u4{lo[1], lo[2], lo[3], hi}};
 #pragma unroll
-                    for (int ib = 0; ib < 2; ++ib) {
-                        const bf16* q = &sx[(ib * 16 + l16) * kXStride + hr * kXRow + xo];
-                        const u4 lo = *(const u4*)q;
-                        u4 f = lo;
-                        if (cx != 0) {
-                            const unsigned hi = *(const unsigned*)(q + 8);
-                            if (cx == 1)
-                                f = u4{__builtin_amdgcn_alignbyte(lo[1], lo[0], 2), __builtin_amdgcn_alignbyte(lo[2], lo[1], 2),
-                                       __builtin_amdgcn_alignbyte(lo[3], lo[2], 2), __builtin_amdgcn_alignbyte(hi, lo[3], 2)};
-                            else
-                                f = u4{lo[1], lo[2], lo[3], hi};
-                        }
-                        const bf16x8 b = __builtin_bit_cast(bf16x8, f);
+                    for (int cx = 0; cx < 3; ++cx) {
+                        const bf16x8 b = __builtin_bit_cast(bf16x8, f[cx]);
 #pragma unroll
                         for (int cb = 0; cb < 2; ++cb)
-                            acc[k][cb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[cb], b, acc[k][cb][ib], 0, 0, 0);
+                            acc[k][cx][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[cb], b, acc[k][cx][cb], 0, 0, 0);
                     }
                 }
             }
@@ -564,20 +567,23 @@ __global__ __launch_bounds__(kBwThreads) void k_conv_bwd_w_tile(G g, const bf16*
     }
     // D[co][ci]: row (lane / 16) * 4 + i, column lane % 16
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int t = wave + 8 * k;
-        if (t >= 27) continue;
-        float* p = part + (((long long)ch * 27 + t) * cout) * cin;
+    for (int k = 0; k < 3; ++k) {
+        const int u = wave + 8 * k;
+        if (u >= 18) continue;
+        const int g = u >> 1, ib = u & 1;
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
+        for (int cx = 0; cx < 3; ++cx) {
+            const int t = g * 3 + cx;
+            float* p = part + (((long long)ch * 27 + t) * cout) * cin;
 #pragma unroll
-            for (int ib = 0; ib < 2; ++ib)
+            for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int co = cot * 32 + cb * 16 + (lane >> 4) * 4 + i;
                     const int ci = cit * 32 + ib * 16 + (lane & 15);
-                    p[(long long)co * cin + ci] = acc[k][cb][ib][i];
+                    p[(long long)co * cin + ci] = acc[k][cx][cb][i];
                 }
+        }
     }
 }
 
