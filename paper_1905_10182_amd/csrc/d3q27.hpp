@@ -58,6 +58,21 @@ __device__ __forceinline__ void inv1d(T m0, T m1, T m2, T u, T& gm, T& g0, T& gp
     gp = T(0.5) * (even + odd);
 }
 
+// inv1d with its first- and second-order inputs given at half scale
+// (m1h = m1 / 2, m2h = m2 / 2) and hu = u / 2: with o = (g+ - g-) / 2 and
+// e = (g+ + g-) / 2, o = m1h + hu m0, e = m2h + u (m1h + o), g-+ = e -+ o,
+// g0 = m0 - 2 e.  Six operations instead of nine; the halving is folded into
+// the construction of the moments (see reconstruct).
+template <typename T>
+__device__ __forceinline__ void inv1d_half(T m0, T m1h, T m2h, T u, T hu, T& gm, T& g0, T& gp)
+{
+    const T o = m1h + hu * m0;
+    const T e = m2h + u * (m1h + o);
+    gm = e - o;
+    gp = e + o;
+    g0 = m0 - T(2) * e;
+}
+
 // First half of the collision: density, half-force-corrected velocity
 // (eq. "macroscopic") and the five pre-collision central moments k4..k8
 // (eq. "pre_collision") of the pre-collision h_i = f_i - w_i rho0.
@@ -125,60 +140,69 @@ __device__ __forceinline__ void reconstruct(T drho, T ux, T uy, T uz, T Fx, T Fy
     // Post-collision central moments on the monomials (cx-ux)^p (cy-uy)^q (cz-uz)^r,
     // minus the central moments of the rest state rho0 w_i, which factor as
     // rho0 M_p(ux) M_q(uy) M_r(uz) with M_0 = 1, M_1(u) = -u, M_2(u) = 1/3 + u^2.
+    // D[p][q][r] is held at scale 2^-(number of non-zero p, q, r): each of the
+    // three 1D passes below then receives its first- and second-order inputs
+    // at half scale (inv1d_half), and by linearity the populations come out
+    // unscaled.  The scale factors are powers of two, so they round nothing.
     const T third = T(1.0 / 3.0);
     const T ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz;
     const T ax = third + ux2, ay = third + uy2, az = third + uz2;
+    const T r1 = T(0.5) * rho0, r2 = T(0.25) * rho0, r3 = T(0.125) * rho0;
     T D[3][3][3];
     D[0][0][0] = drho;
-    D[1][0][0] = T(0.5) * Fx + rho0 * ux;
-    D[0][1][0] = T(0.5) * Fy + rho0 * uy;
-    D[0][0][1] = T(0.5) * Fz + rho0 * uz;
-    D[1][1][0] = s[0] - rho0 * ux * uy;
-    D[1][0][1] = s[1] - rho0 * ux * uz;
-    D[0][1][1] = s[2] - rho0 * uy * uz;
-    D[2][0][0] = (s[3] + s[4] + drho) * third - rho0 * ux2;
-    D[0][2][0] = (s[4] - T(2) * s[3] + drho) * third - rho0 * uy2;
-    D[0][0][2] = (s[3] - T(2) * s[4] + drho) * third - rho0 * uz2;
+    D[1][0][0] = T(0.25) * Fx + r1 * ux;
+    D[0][1][0] = T(0.25) * Fy + r1 * uy;
+    D[0][0][1] = T(0.25) * Fz + r1 * uz;
+    D[1][1][0] = T(0.25) * s[0] - r2 * ux * uy;
+    D[1][0][1] = T(0.25) * s[1] - r2 * ux * uz;
+    D[0][1][1] = T(0.25) * s[2] - r2 * uy * uz;
     const T sixth = T(1.0 / 6.0);
-    D[1][2][0] = sixth * Fx + rho0 * ux * ay;
-    D[1][0][2] = sixth * Fx + rho0 * ux * az;
-    D[2][1][0] = sixth * Fy + rho0 * uy * ax;
-    D[0][1][2] = sixth * Fy + rho0 * uy * az;
-    D[2][0][1] = sixth * Fz + rho0 * uz * ax;
-    D[0][2][1] = sixth * Fz + rho0 * uz * ay;
-    D[1][1][1] = rho0 * ux * uy * uz;
-    const T ninth = T(1.0 / 9.0);
-    D[2][2][0] = ninth * drho - rho0 * ((ux2 + uy2) * third + ux2 * uy2);
-    D[2][0][2] = ninth * drho - rho0 * ((ux2 + uz2) * third + ux2 * uz2);
-    D[0][2][2] = ninth * drho - rho0 * ((uy2 + uz2) * third + uy2 * uz2);
-    D[2][1][1] = -rho0 * ax * uy * uz;
-    D[1][2][1] = -rho0 * ay * ux * uz;
-    D[1][1][2] = -rho0 * az * ux * uy;
-    const T f18 = T(1.0 / 18.0);
-    D[1][2][2] = f18 * Fx + rho0 * ux * ay * az;
-    D[2][1][2] = f18 * Fy + rho0 * uy * ax * az;
-    D[2][2][1] = f18 * Fz + rho0 * uz * ax * ay;
-    D[2][2][2] = T(1.0 / 27.0) * drho -
-                 rho0 * ((ux2 + uy2 + uz2) * ninth + (ux2 * uy2 + ux2 * uz2 + uy2 * uz2) * third + ux2 * uy2 * uz2);
+    D[2][0][0] = (s[3] + s[4] + drho) * sixth - r1 * ux2;
+    D[0][2][0] = (s[4] - T(2) * s[3] + drho) * sixth - r1 * uy2;
+    D[0][0][2] = (s[3] - T(2) * s[4] + drho) * sixth - r1 * uz2;
+    const T f24 = T(1.0 / 24.0);
+    D[1][2][0] = f24 * Fx + r2 * ux * ay;
+    D[1][0][2] = f24 * Fx + r2 * ux * az;
+    D[2][1][0] = f24 * Fy + r2 * uy * ax;
+    D[0][1][2] = f24 * Fy + r2 * uy * az;
+    D[2][0][1] = f24 * Fz + r2 * uz * ax;
+    D[0][2][1] = f24 * Fz + r2 * uz * ay;
+    D[1][1][1] = r3 * ux * uy * uz;
+    const T f36 = T(1.0 / 36.0);
+    D[2][2][0] = f36 * drho - r2 * ((ux2 + uy2) * third + ux2 * uy2);
+    D[2][0][2] = f36 * drho - r2 * ((ux2 + uz2) * third + ux2 * uz2);
+    D[0][2][2] = f36 * drho - r2 * ((uy2 + uz2) * third + uy2 * uz2);
+    D[2][1][1] = -r3 * ax * uy * uz;
+    D[1][2][1] = -r3 * ay * ux * uz;
+    D[1][1][2] = -r3 * az * ux * uy;
+    const T f144 = T(1.0 / 144.0);
+    D[1][2][2] = f144 * Fx + r3 * ux * ay * az;
+    D[2][1][2] = f144 * Fy + r3 * uy * ax * az;
+    D[2][2][1] = f144 * Fz + r3 * uz * ax * ay;
+    D[2][2][2] = T(1.0 / 216.0) * drho -
+                 r3 * ((ux2 + uy2 + uz2) * (T(1.0 / 9.0)) + (ux2 * uy2 + ux2 * uz2 + uy2 * uz2) * third + ux2 * uy2 * uz2);
 
     // Reconstruction (eq. "system") by the factorised inverse transform:
     // along z, then y, then x.
+    const T hx = T(0.5) * ux, hy = T(0.5) * uy, hz = T(0.5) * uz;
     T A[3][3][3];
 #pragma unroll
     for (int p = 0; p < 3; ++p)
 #pragma unroll
-        for (int q = 0; q < 3; ++q) inv1d(D[p][q][0], D[p][q][1], D[p][q][2], uz, A[p][q][0], A[p][q][1], A[p][q][2]);
+        for (int q = 0; q < 3; ++q)
+            inv1d_half(D[p][q][0], D[p][q][1], D[p][q][2], uz, hz, A[p][q][0], A[p][q][1], A[p][q][2]);
     T B[3][3][3];
 #pragma unroll
     for (int p = 0; p < 3; ++p)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) inv1d(A[p][0][c], A[p][1][c], A[p][2][c], uy, B[p][0][c], B[p][1][c], B[p][2][c]);
+        for (int c = 0; c < 3; ++c)
+            inv1d_half(A[p][0][c], A[p][1][c], A[p][2][c], uy, hy, B[p][0][c], B[p][1][c], B[p][2][c]);
 #pragma unroll
     for (int b = 0; b < 3; ++b)
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-            inv1d(B[0][b][c], B[1][b][c], B[2][b][c], ux, h[vel_index(-1, b - 1, c - 1)], h[vel_index(0, b - 1, c - 1)],
-                  h[vel_index(1, b - 1, c - 1)]);
+            inv1d_half(B[0][b][c], B[1][b][c], B[2][b][c], ux, hx, h[vel_index(-1, b - 1, c - 1)],
+                       h[vel_index(0, b - 1, c - 1)], h[vel_index(1, b - 1, c - 1)]);
 }
 
 // Collide one cell in place.
