@@ -78,28 +78,33 @@ __device__ __forceinline__ void pre_collision(const T h[9], T Fx, T Fy, T rho0, 
 // k7* = Fx cs^2/2, k8* = rho cs^4) on the monomials (cx-ux)^p (cy-uy)^q, minus
 // the rest-state moments rho0 M_p(ux) M_q(uy) (M_0 = 1, M_1(u) = -u,
 // M_2(u) = 1/3 + u^2), then the inverse transform along y and along x.
+// As in the D3Q27 reconstruction, D[p][q] is held at scale 2^-(number of
+// non-zero p, q) so that both 1D passes take their first- and second-order
+// inputs at half scale (cmlbm::inv1d_half); the populations come out unscaled.
 template <typename T>
 __device__ __forceinline__ void reconstruct(T drho, T ux, T uy, T Fx, T Fy, T s4, T s5, T rho0, T h[9])
 {
     const T third = T(1.0 / 3.0);
     const T ux2 = ux * ux, uy2 = uy * uy;
+    const T r1 = T(0.5) * rho0, r2 = T(0.25) * rho0;
     T D[3][3];
     D[0][0] = drho;
-    D[1][0] = T(0.5) * Fx + rho0 * ux;
-    D[0][1] = T(0.5) * Fy + rho0 * uy;
-    D[2][0] = drho * third + T(0.5) * s4 - rho0 * ux2;
-    D[0][2] = drho * third - T(0.5) * s4 - rho0 * uy2;
-    D[1][1] = s5 - rho0 * ux * uy;
-    D[2][1] = Fy * T(1.0 / 6.0) + rho0 * uy * (third + ux2);
-    D[1][2] = Fx * T(1.0 / 6.0) + rho0 * ux * (third + uy2);
-    D[2][2] = drho * T(1.0 / 9.0) - rho0 * ((ux2 + uy2) * third + ux2 * uy2);
-    T G[3][3];  // G[p][cy + 1]: x-moment p of the populations with that cy
+    D[1][0] = T(0.25) * Fx + r1 * ux;
+    D[0][1] = T(0.25) * Fy + r1 * uy;
+    D[2][0] = drho * T(1.0 / 6.0) + T(0.25) * s4 - r1 * ux2;
+    D[0][2] = drho * T(1.0 / 6.0) - T(0.25) * s4 - r1 * uy2;
+    D[1][1] = T(0.25) * s5 - r2 * ux * uy;
+    D[2][1] = Fy * T(1.0 / 24.0) + r2 * uy * (third + ux2);
+    D[1][2] = Fx * T(1.0 / 24.0) + r2 * ux * (third + uy2);
+    D[2][2] = drho * T(1.0 / 36.0) - r2 * ((ux2 + uy2) * third + ux2 * uy2);
+    const T hx = T(0.5) * ux, hy = T(0.5) * uy;
+    T G[3][3];  // G[p][cy + 1]: x-moment p of the populations with that cy (at scale 2^-[p > 0])
 #pragma unroll
-    for (int p = 0; p < 3; ++p) cmlbm::inv1d<T>(D[p][0], D[p][1], D[p][2], uy, G[p][0], G[p][1], G[p][2]);
+    for (int p = 0; p < 3; ++p) cmlbm::inv1d_half<T>(D[p][0], D[p][1], D[p][2], uy, hy, G[p][0], G[p][1], G[p][2]);
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
         T gm, g0, gp;
-        cmlbm::inv1d<T>(G[0][b], G[1][b], G[2][b], ux, gm, g0, gp);
+        cmlbm::inv1d_half<T>(G[0][b], G[1][b], G[2][b], ux, hx, gm, g0, gp);
         h[vel_index(-1, b - 1)] = gm;
         h[vel_index(0, b - 1)] = g0;
         h[vel_index(1, b - 1)] = gp;
