@@ -216,6 +216,29 @@ def copy_bandwidth():
     return 2 * 4 * n * reps / s / 1e9
 
 
+def kernel_copy_bandwidth():
+    """Rate of the library's plain 16-byte non-temporal copy kernel on 4 GiB:
+    the practical read + write ceiling of the device."""
+    import torch
+    from paper_1905_10182_amd.cmlbm import device_copy
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    device_copy(b, a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    reps = 10
+    for _ in range(reps):
+        device_copy(b, a)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * 4 * n * reps / s / 1e9
+
+
 def warm_start():
     """Steps to the 1e-8 residual for 64 held-out sphere channels (FP64
     solver) from rest and from the shipped U-Net's prediction."""
@@ -391,7 +414,8 @@ def main():
         print(f"[bench] magnetic lattice {rmag['glups']:.2f} GLUPS, {bw:.0f} GB/s", file=sys.stderr, flush=True)
     print(f"[bench] fused reductions, TGV {args.n}^3 fp32", file=sys.stderr, flush=True)
     extra["fused_reduce"] = run_fused(args.n, 20)
-    extra["device_copy_gbs"] = round(copy_bandwidth(), 1)
+    extra["device_copy_gbs"] = round(copy_bandwidth(), 1)  # torch's copy
+    extra["kernel_copy_gbs"] = round(kernel_copy_bandwidth(), 1)  # 16-byte non-temporal copy kernel
     if not args.no_warmstart:
         print("[bench] warm start: 64 sphere channels 64x32x32, cold vs U-Net init", file=sys.stderr, flush=True)
         extra["warm_start"] = warm_start()

@@ -248,6 +248,14 @@ const char* cmlbm_last_error(const cmlbm_lattice* lat);
 /* Static name of a status code. */
 const char* cmlbm_status_string(int status);
 
+/* Measurement aid, not part of the method: copy `bytes` (a multiple of 16)
+ * from dev_src to dev_dst (16-byte aligned, not overlapping) with 16-byte
+ * non-temporal loads and stores, four loads in flight per thread, a
+ * grid-stride loop over at most 1024 workgroups per 64 MiB.  Its rate is the practical read + write bandwidth of the device,
+ * the ceiling that the HBM-bound steps are compared with.  EINVAL on NULL,
+ * misaligned or odd-sized arguments; nothing is enqueued then. */
+int cmlbm_device_copy(void* dev_dst, const void* dev_src, size_t bytes, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

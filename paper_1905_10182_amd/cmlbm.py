@@ -36,7 +36,7 @@ EXPORTS = ["cmlbm_required_bytes", "cmlbm_create", "cmlbm_set_solid", "cmlbm_set
            "cmlbm_step", "cmlbm_moments", "cmlbm_reduce", "cmlbm_step_reduce", "cmlbm_populations",
            "cmlbm_load_populations",
            "cmlbm_save_state", "cmlbm_restore_state", "cmlbm_get_time", "cmlbm_set_time", "cmlbm_destroy",
-           "cmlbm_last_error", "cmlbm_status_string", "cmlbm_pseudopotential_force"]
+           "cmlbm_last_error", "cmlbm_status_string", "cmlbm_pseudopotential_force", "cmlbm_device_copy"]
 
 
 class Params(ctypes.Structure):
@@ -83,6 +83,7 @@ def load_library():
     lib.cmlbm_destroy.argtypes = [vp]
     lib.cmlbm_last_error.argtypes = [vp]
     lib.cmlbm_last_error.restype = ctypes.c_char_p
+    lib.cmlbm_device_copy.argtypes = [vp, vp, sz, vp]
     lib.cmlbm_status_string.argtypes = [ctypes.c_int]
     lib.cmlbm_status_string.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -97,6 +98,19 @@ def _status_string(code):
         return load_library().cmlbm_status_string(code).decode()
     except OSError:
         return str(code)
+
+
+def device_copy(dst, src, stream=None):
+    """Copy tensor src into dst (same byte size, 16-byte aligned) with the
+    library's 16-byte non-temporal copy kernel (a bandwidth measurement aid)."""
+    import torch
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    s = torch.cuda.current_stream().cuda_stream if stream is None else stream
+    rc = load_library().cmlbm_device_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes,
+                                          ctypes.c_void_p(s))
+    if rc != OK:
+        raise CmlbmError(rc, "device_copy")
 
 
 def make_params(nx, ny, nz, nbatch=1, tau=0.8, rho0=1.0, storage="fp32", wall=(0, 0, 0), flags=0):

@@ -163,3 +163,15 @@ def test_fused_reduce_flag():
         p.flags |= B.FLAG_FUSED_REDUCE
         with pytest.raises(B.CmlbmError):
             B.required_bytes(p)
+
+
+def test_device_copy_validation(lib):
+    base = 1 << 24  # stand-in device addresses: every call below fails validation before any launch
+    P = lambda off: ctypes.c_void_p(base + off)
+    assert lib.cmlbm_device_copy(None, P(0), 16, None) == B.EINVAL
+    assert lib.cmlbm_device_copy(P(4096), None, 16, None) == B.EINVAL
+    assert lib.cmlbm_device_copy(P(4096), P(8), 16, None) == B.EINVAL     # misaligned source
+    assert lib.cmlbm_device_copy(P(4096 + 4), P(0), 16, None) == B.EINVAL  # misaligned destination
+    assert lib.cmlbm_device_copy(P(4096), P(0), 24, None) == B.EINVAL     # not a multiple of 16 bytes
+    assert lib.cmlbm_device_copy(P(4096), P(0), 0, None) == B.EINVAL
+    assert lib.cmlbm_device_copy(P(64), P(0), 128, None) == B.EINVAL      # overlapping
