@@ -759,3 +759,16 @@ def test_nonfinite_state_reports_unstable(torch):
     assert e.value.code == B.EUNSTABLE
     r = lat.reduce(allow_unstable=True)
     assert r[0, 6] == 1 and r[0, 7] == 64 * 16
+
+
+def test_device_copy_bitwise(torch):
+    """The copy probe copies every byte, including a tail that is not a whole
+    number of its 4 x 16-byte thread groups."""
+    from paper_1905_10182_amd.cmlbm import device_copy
+    g = torch.Generator(device="cuda:0").manual_seed(3)
+    for n in (16 * 1024 * 4 + 12, 1000004 * 4):  # int32 counts: whole 16-byte units with ragged tails
+        a = torch.randint(-2**31, 2**31 - 1, (n,), dtype=torch.int32, device="cuda:0", generator=g)
+        b = torch.zeros_like(a)
+        device_copy(b, a)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
