@@ -606,6 +606,17 @@ def test_full_size_taylor_green_256_fp32_sampled(torch):
     assert err.max() < 1e-6
 
 
+def test_full_size_taylor_green_256_fp64_sampled(torch):
+    """FP64 storage in the benchmark's configuration (TGV 256^3, 512-thread
+    workgroups): every sampled post-collision population within 1e-12 of the
+    oracle's collision of the exported state."""
+    log("fp64 TGV 256^3 one step, 4096 sampled cells")
+    got, ref = sampled_one_step(torch, 256, "fp64", 4096, seed=35)
+    err = np.abs(got - ref) / WGT[:, None]
+    log(f"  max |f* - oracle| / w = {err.max():.3e}")
+    assert err.max() < 1e-12
+
+
 def test_full_size_taylor_green_512_fp16_sampled(torch):
     """16-bit storage at 512^3: every sampled post-collision population is the
     oracle's value rounded to nearest FP16 (half an ulp plus the FP32
