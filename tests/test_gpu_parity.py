@@ -348,18 +348,19 @@ def test_mom32_state_semantics(torch):
     assert e.value.code == EINVAL
 
 
-def test_mom32_full_size_matches_fp32_populations(torch):
-    """TGV 256^3 in the benchmark configuration: after 20 steps the moment
-    storage and the FP32 population storage agree to 1e-6 in velocity (two
-    independent data paths of the same arithmetic)."""
-    log("mom32 vs fp32 populations, TGV 256^3, 20 steps")
-    wl = W.taylor_green(256, seed=1, dtype=np.float32)
-    a = Lat(nx=256, ny=256, nz=256, tau=wl["tau"], storage="mom32")
+@pytest.mark.parametrize("n", [256, 512])
+def test_mom32_full_size_matches_fp32_populations(torch, n):
+    """TGV 256^3 and 512^3 in the benchmark configurations: after 20 steps the
+    moment storage and the FP32 population storage agree to 1e-6 in velocity
+    (two independent data paths of the same arithmetic)."""
+    log(f"mom32 vs fp32 populations, TGV {n}^3, 20 steps")
+    wl = W.taylor_green(n, seed=1, dtype=np.float32)
+    a = Lat(nx=n, ny=n, nz=n, tau=wl["tau"], storage="mom32")
     a.init(wl["rho"], wl["u"], dtype=torch.float32)
     a.step(20)
     ua = a.moments(dtype=torch.float32)[1]
     del a
-    b = Lat(nx=256, ny=256, nz=256, tau=wl["tau"], storage="fp32")
+    b = Lat(nx=n, ny=n, nz=n, tau=wl["tau"], storage="fp32")
     b.init(wl["rho"], wl["u"], dtype=torch.float32)
     b.step(20)
     ub = b.moments(dtype=torch.float32)[1]
