@@ -222,3 +222,42 @@ def test_hartmann_steady_profile_on_gpu(torch):
         errs.append(rel(u, ua))
         log(f"  L={L}: error {errs[-1]:.3e}")
     assert errs[1] < 6e-3 and math.log2(errs[0] / errs[1]) > 1.8, errs
+
+
+def test_bench_size_magnetic_step_sampled(torch):
+    """The magnetic lattice in the benchmark's configuration (256^3, FP32,
+    periodic, a fixed velocity field, 256-thread workgroups): one step on 2048
+    sampled cells against the oracle's collision (App. C equilibrium) of the
+    exported populations at x - xi_l, streamed to x."""
+    from paper_1905_10182_amd.mhd import MagneticLattice
+    n, tau_m = 256, 0.8
+    log(f"magnetic lattice {n}^3 fp32, one step, 2048 sampled cells")
+    lat = MagneticLattice(n, n, n, tau_m, storage="fp32", device="cuda:0")
+    c = torch.arange(n, device="cuda:0", dtype=torch.float32) * (2 * math.pi / n)
+    z, y, x = torch.meshgrid(c, c, c, indexing="ij")
+    b = torch.stack([torch.sin(y), torch.sin(z), torch.sin(x)]) * 0.01
+    u = (torch.stack([torch.sin(z), torch.sin(x), torch.sin(y)]) * 0.02).contiguous()
+    lat.init(b, u)
+    lat.step(u)  # leave equilibrium
+    del b, x, y, z
+    xi, _ = M.constants()
+    g = W.generator(41)
+    s = np.stack([g.integers(0, n, 2048), g.integers(0, n, 2048), g.integers(0, n, 2048)], 1)  # (x, y, z)
+    lin = lambda q: torch.as_tensor((q[:, 2] * n + q[:, 1]) * n + q[:, 0], device="cuda:0")
+    P0 = lat.populations().reshape(7, 3, -1)
+    src = {l: (s - xi[l]) % n for l in range(7)}
+    h0 = {l: P0[:, :, lin(src[l])].cpu().numpy() for l in range(7)}  # (7, 3, 2048) at x - xi_l
+    u0 = {l: u.reshape(3, -1)[:, lin(src[l])].double().cpu().numpy() for l in range(7)}
+    del P0
+    lat.step(u)
+    P1 = lat.populations().reshape(7, 3, -1)[:, :, lin(s)].cpu().numpy()
+    om = 1.0 / tau_m
+    err = 0.0
+    for l in range(7):
+        for k in range(len(s)):
+            hp = h0[l][:, :, k]
+            e = M.heq(hp.sum(axis=0), u0[l][:, k])
+            want = hp[l] + om * (e[l] - hp[l])
+            err = max(err, float(np.abs(P1[l, :, k] - want).max()))
+    log(f"  max |h - oracle| = {err:.3e}")
+    assert err < 2e-9  # FP32 arithmetic on populations of order 1e-3
