@@ -151,3 +151,25 @@ def test_fused_reduce_reproducible_and_needs_flag(torch):
     plain.init(wl["rho"], wl["u"])
     with pytest.raises(CmlbmError, match="ESTATE"):
         plain.step_reduce()
+
+
+def test_fused_reduce_bench_size(torch):
+    """The benchmark's fused-reduction leg (FP32 TGV 256^3, 1024-thread
+    workgroups): step_reduce's sums of the state against reduce() of the same
+    state."""
+    from paper_1905_10182_amd import Lattice
+    wl = W.taylor_green(256, seed=1)
+    lat = Lattice(256, 256, 256, tau=wl["tau"], storage="fp32", fused_reduce=True, device="cuda:0")
+    lat.init(wl["rho"], wl["u"])
+    del wl
+    lat.step(3)
+    ref = lat.reduce()
+    got = lat.step_reduce()
+    log(f"  fp32 256^3: ke {got[0, 4]:.10e} vs {ref[0, 4]:.10e}, mass {got[0, 0]:.10e} vs {ref[0, 0]:.10e}")
+    assert got[0, KEYS["fluid"]] == ref[0, KEYS["fluid"]] == 256 ** 3
+    for key in ("ke", "u2"):
+        assert abs(got[0, KEYS[key]] / ref[0, KEYS[key]] - 1) < 2e-6
+    assert abs(got[0, KEYS["umax"]] / ref[0, KEYS["umax"]] - 1) < 1e-5
+    n = 256 ** 3
+    for key in ("mass", "momx", "momy", "momz"):
+        assert abs(got[0, KEYS[key]] - ref[0, KEYS[key]]) < 2e-7 * n
