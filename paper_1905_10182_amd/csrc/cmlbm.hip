@@ -48,19 +48,28 @@ constexpr size_t kPlanePad = 4096;  // bytes between consecutive population plan
 
 template <int ST>
 struct storage;
+// Every storage type also offers load_raw / pack_raw (/ pack_sr_raw): the
+// stored number itself, which for FP16 is 256 h (kScale); the step kernel
+// computes on that scale.
 template <>
 struct storage<CMLBM_FP64> {
     typedef double S;
     typedef double T;
+    static constexpr T kScale = 1;
     static __device__ __forceinline__ T load(const S* p) { return *p; }
     static __device__ __forceinline__ S pack(T v) { return v; }
+    static __device__ __forceinline__ T load_raw(const S* p) { return *p; }
+    static __device__ __forceinline__ S pack_raw(T v) { return v; }
 };
 template <>
 struct storage<CMLBM_FP32> {
     typedef float S;
     typedef float T;
+    static constexpr T kScale = 1;
     static __device__ __forceinline__ T load(const S* p) { return *p; }
     static __device__ __forceinline__ S pack(T v) { return v; }
+    static __device__ __forceinline__ T load_raw(const S* p) { return *p; }
+    static __device__ __forceinline__ S pack_raw(T v) { return v; }
 };
 // 16-bit formats.  pack() rounds to nearest even; pack_sr() rounds
 // stochastically: r8 (8 random bits) is added to the top 8 of the discarded
@@ -75,11 +84,15 @@ template <>
 struct storage<CMLBM_FP16> {
     typedef _Float16 S;
     typedef float T;
+    static constexpr T kScale = 256;
     static __device__ __forceinline__ T load(const S* p) { return (float)*p * 0.00390625f; }
     static __device__ __forceinline__ S pack(T v) { return (_Float16)(v * 256.0f); }
-    static __device__ __forceinline__ S pack_sr(T v, uint32_t r8)
+    static __device__ __forceinline__ S pack_sr(T v, uint32_t r8) { return pack_sr_raw(v * 256.0f, r8); }
+    static __device__ __forceinline__ T load_raw(const S* p) { return (float)*p; }
+    static __device__ __forceinline__ S pack_raw(T v) { return (_Float16)v; }
+    static __device__ __forceinline__ S pack_sr_raw(T v, uint32_t r8)
     {
-        const uint32_t b = (__builtin_bit_cast(uint32_t, v * 256.0f) + (r8 << 5) + 16u) & 0xFFFFE000u;
+        const uint32_t b = (__builtin_bit_cast(uint32_t, v) + (r8 << 5) + 16u) & 0xFFFFE000u;
         return (_Float16)__builtin_bit_cast(float, b);  // exact: b has an FP16 significand
     }
 };
@@ -87,6 +100,7 @@ template <>
 struct storage<CMLBM_BF16> {
     typedef __bf16 S;
     typedef float T;
+    static constexpr T kScale = 1;
     static __device__ __forceinline__ T load(const S* p) { return (float)*p; }
     static __device__ __forceinline__ S pack(T v) { return (__bf16)v; }
     static __device__ __forceinline__ S pack_sr(T v, uint32_t r8)
@@ -94,6 +108,9 @@ struct storage<CMLBM_BF16> {
         const uint32_t b = (__builtin_bit_cast(uint32_t, v) + (r8 << 8) + 128u) & 0xFFFF0000u;
         return __builtin_bit_cast(__bf16, (unsigned short)(b >> 16));
     }
+    static __device__ __forceinline__ T load_raw(const S* p) { return load(p); }
+    static __device__ __forceinline__ S pack_raw(T v) { return pack(v); }
+    static __device__ __forceinline__ S pack_sr_raw(T v, uint32_t r8) { return pack_sr(v, r8); }
 };
 
 // moment representation: nine FP32 planes (rho - rho0, u, (1 - omega) k4..k8)
@@ -338,6 +355,14 @@ __global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename st
     using SS = storage<ST>;
     using S = typename SS::S;
     using T = typename SS::T;
+    // FP16 stores 256 h: the step computes on that scale, with the force
+    // density and rho0 scaled alike, so its loads and stores need no
+    // rescaling.  The collision is homogeneous of degree one in (h, F, rho0)
+    // at fixed u and a power-of-two scale is exact, so only the compiler's
+    // different choice of fused multiply-adds separates this from computing on
+    // h: about one stored value in 10^5 moves by one unit in the last place.
+    constexpr T kS = SS::kScale;
+    const T rho0s = rho0 * kS;
     typedef S vt __attribute__((ext_vector_type(V == 1 ? 2 : V)));
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (step_block(ST, MASK) / 64) + (threadIdx.x >> 6)));
@@ -381,7 +406,7 @@ __global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename st
                 e = ld_off<S>(src + (uint64_t)opposite(i) * g.pstride + own_row, bx[1]);
             else
                 e = ld_off<S>(plane_row, bx[vel_x(i) + 1]);
-            h[0][i] = SS::load(&e);
+            h[0][i] = SS::load_raw(&e);
         }
     } else {
         const bool whole = g.nx == 64 * V;
@@ -414,7 +439,7 @@ __global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename st
                     src_e = c == 0 ? e : v[i][c - 1];
                 else
                     src_e = c == V - 1 ? e : v[i][c + 1];
-                h[c][i] = SS::load(&src_e);
+                h[c][i] = SS::load_raw(&src_e);
             }
         }
 #pragma unroll
@@ -423,7 +448,7 @@ __global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename st
 #pragma unroll
             for (int c = 0; c < V; ++c) {
                 S e = v[i][c];
-                h[c][i] = SS::load(&e);
+                h[c][i] = SS::load_raw(&e);
             }
         }
         if constexpr (!RED)
@@ -447,6 +472,13 @@ __global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename st
             Fz[c] = fr[2];
         }
     }
+    if constexpr (kS != T(1))
+#pragma unroll
+        for (int c = 0; c < V; ++c) {
+            Fx[c] *= kS;
+            Fy[c] *= kS;
+            Fz[c] *= kS;
+        }
     T mq[RED ? V : 1][4];  // RED: each cell's drho, ux, uy, uz
 #pragma unroll
     for (int c = 0; c < V; ++c) {
@@ -454,19 +486,19 @@ __global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename st
         if constexpr (RED) {
             // collide() with its density deviation kept for the mass sum
             T drho, k5[5], s5[5];
-            pre_collision(h[c], Fx[c], Fy[c], Fz[c], rho0, drho, ux, uy, uz, k5);
+            pre_collision(h[c], Fx[c], Fy[c], Fz[c], rho0s, drho, ux, uy, uz, k5);
 #pragma unroll
             for (int j = 0; j < 5; ++j) s5[j] = (T(1) - omega) * k5[j];
-            reconstruct(drho, ux, uy, uz, Fx[c], Fy[c], Fz[c], s5, rho0, h[c]);
+            reconstruct(drho, ux, uy, uz, Fx[c], Fy[c], Fz[c], s5, rho0s, h[c]);
             mq[c][0] = drho;
             mq[c][1] = ux;
             mq[c][2] = uy;
             mq[c][3] = uz;
         } else if constexpr (MODEL == 0) {
-            collide<T>(h[c], Fx[c], Fy[c], Fz[c], omega, rho0, rho, ux, uy, uz);
+            collide<T>(h[c], Fx[c], Fy[c], Fz[c], omega, rho0s, rho, ux, uy, uz);
         } else {
             collide_model<T, (MODEL & kModelEq2) != 0, (MODEL & kModelGuo) != 0, (MODEL & kModelBgk) != 0>(
-                h[c], Fx[c], Fy[c], Fz[c], omega, rho0, rho, ux, uy, uz);
+                h[c], Fx[c], Fy[c], Fz[c], omega, rho0s, rho, ux, uy, uz);
         }
     }
     if constexpr (RED) {
@@ -495,7 +527,7 @@ __global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename st
                         S* plane_row = dst + (uint64_t)i * g.pstride + own_row;
                         vt o;
 #pragma unroll
-                        for (int c = 0; c < V; ++c) o[c] = SS::pack_sr(h[c][i], (rw[c][i / 4] >> (8 * (i % 4))) & 0xFFu);
+                        for (int c = 0; c < V; ++c) o[c] = SS::pack_sr_raw(h[c][i], (rw[c][i / 4] >> (8 * (i % 4))) & 0xFFu);
                         if constexpr (V == 1)
                             st_off<NT>(plane_row, bst, o[0]);
                         else
@@ -508,11 +540,11 @@ __global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename st
             for (int i = 0; i < 27; ++i) {
                 S* plane_row = dst + (uint64_t)i * g.pstride + own_row;
                 if constexpr (V == 1) {
-                    st_off<NT>(plane_row, bst, SS::pack(h[0][i]));
+                    st_off<NT>(plane_row, bst, SS::pack_raw(h[0][i]));
                 } else {
                     vt o;
 #pragma unroll
-                    for (int c = 0; c < V; ++c) o[c] = SS::pack(h[c][i]);
+                    for (int c = 0; c < V; ++c) o[c] = SS::pack_raw(h[c][i]);
                     st_off<NT>(plane_row, bst, o);
                 }
             }
@@ -526,7 +558,8 @@ __global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename st
 #pragma unroll
         for (int c = 0; c < V; ++c) {
             if (!live || (V > 1 && x0 + c >= g.nx)) continue;
-            const double r = (double)rho0 + (double)mq[c][0];
+            const double dr = (double)mq[c][0] / (double)kS;  // the density deviation, unscaled
+            const double r = (double)rho0 + dr;
             const double u[3] = {(double)mq[c][1], (double)mq[c][2], (double)mq[c][3]};
             const double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
             acc[7] += 1.0;
@@ -534,10 +567,10 @@ __global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename st
                 acc[6] += 1.0;
                 continue;
             }
-            acc[0] += (double)mq[c][0];
-            acc[1] += r * u[0] - 0.5 * (double)Fx[c];  // sum_i f_i c_i
-            acc[2] += r * u[1] - 0.5 * (double)Fy[c];
-            acc[3] += r * u[2] - 0.5 * (double)Fz[c];
+            acc[0] += dr;
+            acc[1] += r * u[0] - 0.5 * (double)Fx[c] / (double)kS;  // sum_i f_i c_i
+            acc[2] += r * u[1] - 0.5 * (double)Fy[c] / (double)kS;
+            acc[3] += r * u[2] - 0.5 * (double)Fz[c] / (double)kS;
             acc[4] += 0.5 * r * u2;
             acc[5] = fmax(acc[5], sqrt(u2));
             acc[9] += u2;
@@ -572,7 +605,7 @@ __global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename st
                 S* plane_row = dst + (uint64_t)i * g.pstride + own_row;
                 vt o;
 #pragma unroll
-                for (int c = 0; c < V; ++c) o[c] = SS::pack_sr(h[c][i], (rw[c][i / 4] >> (8 * (i % 4))) & 0xFFu);
+                for (int c = 0; c < V; ++c) o[c] = SS::pack_sr_raw(h[c][i], (rw[c][i / 4] >> (8 * (i % 4))) & 0xFFu);
                 if constexpr (V == 1)
                     st_off<NT>(plane_row, bst, o[0]);
                 else
@@ -585,11 +618,11 @@ __global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename st
     for (int i = 0; i < 27; ++i) {
         S* plane_row = dst + (uint64_t)i * g.pstride + own_row;
         if constexpr (V == 1) {
-            st_off<NT>(plane_row, bst, SS::pack(h[0][i]));
+            st_off<NT>(plane_row, bst, SS::pack_raw(h[0][i]));
         } else {
             vt o;
 #pragma unroll
-            for (int c = 0; c < V; ++c) o[c] = SS::pack(h[c][i]);
+            for (int c = 0; c < V; ++c) o[c] = SS::pack_raw(h[c][i]);
             st_off<NT>(plane_row, bst, o);
         }
     }
