@@ -210,6 +210,13 @@ __device__ __forceinline__ Pull make_pull(const Geom& g, const Cell& c)
     return p;
 }
 
+// load of the X at byte_off from base
+template <typename X>
+__device__ __forceinline__ X ld_off(const void* base, uint32_t byte_off)
+{
+    return *(const X*)((const char*)base + byte_off);
+}
+
 // Gather the 27 shifted pre-collision populations of one cell.
 template <int ST, bool MASK>
 __device__ __forceinline__ void gather(const typename storage<ST>::S* __restrict__ src, const Geom& g,
@@ -225,8 +232,11 @@ __device__ __forceinline__ void gather(const typename storage<ST>::S* __restrict
             const uint64_t e = bounce ? (uint64_t)opposite(i) * g.pstride + c.own : (uint64_t)i * g.pstride + off;
             h[i] = SS::load(src + e);
         } else {
-            const typename SS::S* plane = src + (uint64_t)i * g.pstride;
-            h[i] = SS::load(plane + off);
+            // wave-uniform source row plus a 32-bit per-lane byte offset (the
+            // "saddr + voffset" load form; the row arithmetic stays scalar)
+            const typename SS::S* row = src + (uint64_t)i * g.pstride + p.rowoff[vel_y(i) + 1][vel_z(i) + 1];
+            typename SS::S e = ld_off<typename SS::S>(row, p.xs[vel_x(i) + 1] * (uint32_t)sizeof(typename SS::S));
+            h[i] = SS::load(&e);
         }
     }
 }
@@ -280,12 +290,6 @@ __device__ __forceinline__ S lane_shift(S v, bool from_prev)
 // offset (one of three x offsets for the loads, one for every store), which
 // maps onto the global_load/store "saddr + voffset" form.  Needs per-plane
 // byte offsets below 4 GiB.
-
-template <typename X>
-__device__ __forceinline__ X ld_off(const void* base, uint32_t byte_off)
-{
-    return *(const X*)((const char*)base + byte_off);
-}
 
 template <bool NT, typename X>
 __device__ __forceinline__ void st_off(void* base, uint32_t byte_off, X v)
