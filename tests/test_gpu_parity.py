@@ -514,16 +514,23 @@ def test_16bit_taylor_green_32_error(torch, storage, bound):
 # ---------------------------------------------------------------------------
 # full-size configurations, sampled
 
-def sampled_one_step(torch, n, storage, nsample, seed, dims=None, re=1600.0, stochastic=False):
+def sampled_one_step(torch, n, storage, nsample, seed, dims=None, re=1600.0, stochastic=False, force_amp=0.0):
     """One fused step; at nsample random cells s (every cell if nsample is
     None) the oracle collides the exported pre-collision populations P0[:, s]
-    and each result f*_i must appear at P1[i, s + c_i]."""
+    and each result f*_i must appear at P1[i, s + c_i].  force_amp > 0 adds a
+    seeded per-cell force field, uniform in [-force_amp, force_amp] (FP32
+    values, given to the oracle as they are)."""
     nx, ny, nz = dims or (n, n, n)
     wl = W.taylor_green(n, seed=1, re=re)
     rho, u = wl["rho"], wl["u"]
     if dims is not None:  # a periodic box cut from a larger vortex: still a valid state
         rho, u = rho[:, :nz, :ny, :nx], u[:, :, :nz, :ny, :nx]
     lat = Lat(nx=nx, ny=ny, nz=nz, tau=wl["tau"], storage=storage, stochastic=stochastic)
+    field = None
+    if force_amp > 0:
+        dt = np.float64 if storage == "fp64" else np.float32
+        field = W.generator(seed + 1000).uniform(-force_amp, force_amp, size=(3, 1, nz, ny, nx)).astype(dt)
+        lat.set_force("field", field=field)
     lat.init(rho, u)
     del wl, rho, u
     if nsample is None:
@@ -545,7 +552,8 @@ def sampled_one_step(torch, n, storage, nsample, seed, dims=None, re=1600.0, sto
         lin = torch.as_tensor((d[:, 2] * ny + d[:, 1]) * nx + d[:, 0], device=P1.device)
         got[i] = P1[i, lin].cpu().numpy()
     del P1
-    ref = O.collide_cells(f0, None, 1.0 / lat.params.tau)
+    F = None if field is None else field[:, 0, s[:, 2], s[:, 1], s[:, 0]].astype(np.float64)
+    ref = O.collide_cells(f0, F, 1.0 / lat.params.tau)
     lat.close()
     return got, ref
 
@@ -571,6 +579,22 @@ def test_16bit_one_step_every_cell_is_rounded_oracle(torch, storage, nx):
     periodic wrap), 37 the one-cell one."""
     log(f"{storage} one step, every cell, {nx}x12x10")
     got, ref = sampled_one_step(torch, max(nx, 64), storage, None, 0, dims=(nx, 12, 10), re=200.0)
+    h_ref = ref - WGT[:, None]
+    err = np.abs((got - WGT[:, None]) - h_ref)
+    ulp = ulp16(h_ref, storage)
+    log(f"  max error in ulps {(err / ulp).max():.3f}")
+    assert np.all(err <= 0.5 * ulp + 2e-7 * WGT[:, None])
+
+
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+@pytest.mark.parametrize("nx", [40, 128, 37])
+def test_16bit_one_step_strong_force_field_is_rounded_oracle(torch, storage, nx):
+    """As the force-free case, with a per-cell force field of up to 2e-3 per
+    component.  FP16 computes on its stored scale (256 h, with the force
+    scaled alike), so a force term off by that scale, or dropped, moves
+    populations by many units in the last place here."""
+    log(f"{storage} one step, every cell, {nx}x12x10, force field |F| <= 2e-3")
+    got, ref = sampled_one_step(torch, max(nx, 64), storage, None, 7, dims=(nx, 12, 10), re=200.0, force_amp=2e-3)
     h_ref = ref - WGT[:, None]
     err = np.abs((got - WGT[:, None]) - h_ref)
     ulp = ulp16(h_ref, storage)
