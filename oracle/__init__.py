@@ -294,3 +294,57 @@ class Lattice:
         self.lib.orc_lattice_moments(self.nx, self.ny, self.nz, self.nb, self._solid_p(), self._force_p(),
                                     _d(self.f), _d(rho), _d(u))
         return rho, u
+
+    def reductions(self, u_snapshot=None):
+        """Global monitors of the current state (time t, force in effect):
+        the module-level reductions() of moments()."""
+        rho, u = self.moments()
+        return reductions(rho, u, self.solid, self.force, u_snapshot)
+
+
+# ---------------------------------------------------------------------------
+# global monitors of a lattice state
+
+def reductions(rho, u, solid=None, force=None, u_snapshot=None):
+    """Global sums over the fluid cells of each batch member, from the
+    macroscopic fields of eq. macroscopic (rho, and the half-force-corrected
+    u, as Lattice.moments() returns them).
+
+    rho (nb, ...), u (3, nb, ...), solid (nb, ...) or None, force (3, nb, ...)
+    or None (the force density in effect), u_snapshot (3, nb, ...) or None.
+    Returns one dict per member:
+      mass      sum rho                                   (eq. macroscopic)
+      mom       sum_x sum_i f_i c_i = sum (rho u - F/2)   (eq. macroscopic: rho u = sum f c + F/2)
+      ke        sum rho |u|^2 / 2   (the kinetic energy whose mean is the
+                stability monitor of the Orszag-Tang and static-droplet tests, Sec. III)
+      umax      max |u|
+      u2        sum |u|^2
+      du2       sum |u - u_snapshot|^2 (0 without a snapshot)
+      residual  sqrt(du2 / u2): the relative L2 norm of eq. error applied to
+                two velocity fields (0 without a snapshot)
+      fluid     number of fluid cells
+      nonfinite number of fluid cells whose rho or u is not finite
+    Sums are taken in the arrays' precision (FP64, or 80-bit for the
+    extended oracle)."""
+    rho = np.asarray(rho)
+    u = np.asarray(u)
+    nb = rho.shape[0]
+    fl = np.ones(rho.shape, bool) if solid is None else ~np.asarray(solid, bool).reshape(rho.shape)
+    out = []
+    for b in range(nb):
+        m = fl[b]
+        r = rho[b][m]
+        ub = u[:, b][:, m]
+        fin = np.isfinite(r) & np.isfinite(ub).all(axis=0)
+        mom = (r * ub).sum(axis=1)
+        if force is not None:
+            mom = mom - np.asarray(force, u.dtype)[:, b][:, m].sum(axis=1) / 2
+        usq = (ub * ub).sum(axis=0)
+        d = {"mass": r.sum(), "mom": mom, "ke": (r * usq).sum() / 2, "umax": np.sqrt(usq.max()) if usq.size else 0.0,
+             "u2": usq.sum(), "du2": 0.0, "residual": 0.0, "fluid": int(m.sum()), "nonfinite": int((~fin).sum())}
+        if u_snapshot is not None:
+            dv = ub - np.asarray(u_snapshot, u.dtype)[:, b][:, m]
+            d["du2"] = (dv * dv).sum()
+            d["residual"] = np.sqrt(d["du2"] / d["u2"])
+        out.append(d)
+    return out

@@ -76,12 +76,13 @@ def _rel(a, b, torch):
     return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
 
 
-def lockstep(lattices, steps, every, label, out=sys.stdout, per_step_ke=False):
+def lockstep(lattices, steps, every, label, out=sys.stdout, per_step_ke=False, ke_rows=None):
     """Advance the lattices together; every `every` steps print their velocity
     errors against the FP64 (and FP32) run and their FP64-reduced kinetic
     energy.  With per_step_ke (lattices created with fused reductions) the
     steps go through step_reduce and a row of every lattice's kinetic energy
-    is printed for every step, at no extra pass over the populations."""
+    is printed for every step, at no extra pass over the populations (and
+    appended to ke_rows if a list is given)."""
     import torch
 
     names = list(lattices)
@@ -109,6 +110,8 @@ def lockstep(lattices, steps, every, label, out=sys.stdout, per_step_ke=False):
             for j in range(n):
                 ke = {k: float(lattices[k].step_reduce(allow_unstable=True)[0][RED["ke"]]) for k in names}
                 print(json.dumps({"study": label, "step": t + j, "ke": ke}), file=out, flush=True)
+                if ke_rows is not None:
+                    ke_rows.append({"step": t + j, **ke})
         else:
             for k in names:
                 lattices[k].step(n)
@@ -126,8 +129,8 @@ def _make(st, n, tau, fused=False):
 
 
 def precision_study(n=512, steps=2000, every=100, storages=("fp64", "fp32", "fp16", "fp16sr", "bf16", "bf16sr"),
-                    per_step_ke=False):
-    wl = workloads.taylor_green(n, seed=1)
+                    per_step_ke=False, re=1600.0):
+    wl = workloads.taylor_green(n, re=re, seed=1)
     lats = {}
     for st in storages:
         lat = _make(st, n, wl["tau"], per_step_ke)

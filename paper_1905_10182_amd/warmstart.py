@@ -24,9 +24,22 @@ s + b).
 - evaluate: steps to residual 1e-8 for the same channels from three
   initial states -- rest (cold), the analytic Poiseuille profile of the empty
   channel (a non-learned control), and the network prediction (warm) --
-  with the solver itself deciding convergence.  A prediction that is
-  non-finite or exceeds |u| = 0.1 falls back to rest.  The converged fields
-  of the warm and cold runs are compared.
+  with the solver itself deciding convergence.  The converged fields of the
+  warm and cold runs are compared.
+
+Fallback (warm_solve): the method is the judge of every prediction.  A
+member falls back to the cold start (rest) when
+  - its prediction is non-finite, has a velocity component above 0.1 or a
+    density more than 0.1 from 1 (screened before the run), or
+  - its residual at the first check is worse than (or not finite, or above)
+    the residual a cold start of the same channel has at that check -- a
+    cold twin of the batch runs alongside for that first interval, and the
+    member continues from the twin's state, exactly as a cold start, or
+  - its state turns non-finite at a later check (restarted from rest).
+Every member is charged every step taken for it, including the steps of an
+abandoned warm attempt; a member that never reaches the tolerance is
+charged max_steps and marked unconverged, and no speed-up is reported
+unless every member converged.
 """
 import argparse
 import json
@@ -107,30 +120,55 @@ def new_lattice(nb):
                    device="cuda:0")
 
 
-def run_to_residual(lat, tol, max_steps, check=100, log=None):
-    """Advance until every member's residual is <= tol.  The residual is the
-    per-step change measured over two steps, ||u_t - u_{t-2}|| / (2 ||u_t||):
-    halfway bounce-back around obstacles excites a non-decaying period-2
-    (staggered) oscillation of the lattice, which a single-step difference
-    would report as a floor (about 2e-6 in these channels) and which cancels
-    over two steps.  Returns (steps-to-tol per member (-1 if never), final
-    residuals)."""
+def advance_check(lat, check=100):
+    """Advance `check` steps and return (residual, non-finite flag) per
+    member.  The residual is the per-step change measured over two steps,
+    ||u_t - u_{t-2}|| / (2 ||u_t||): halfway bounce-back around obstacles
+    excites a non-decaying period-2 (staggered) oscillation of the lattice,
+    which a single-step difference would report as a floor (about 2e-6 in
+    these channels) and which cancels over two steps."""
+    lat.step(check - 2)
+    lat.reduce(snapshot=True, allow_unstable=True)
+    lat.step(2)
+    r = lat.reduce(residual=True, allow_unstable=True)
+    bad = r[:, RED["nonfinite"]] > 0
+    res = np.where(bad, np.inf, r[:, RED["residual"]] / 2.0)
+    return res, bad
+
+
+def replace_members(lat, members, source):
+    """Overwrite the state of the given batch members with their state in
+    `source` (FP64 populations (27, nb, nz, ny, nx) on the device, e.g. an
+    export of a lattice of the same geometry): a device copy, no arithmetic."""
+    P = lat.populations()
+    idx = lat.torch.as_tensor(np.nonzero(members)[0], device=P.device)
+    P[:, idx] = source[:, idx]
+    lat.load_populations(P)
+
+
+def run_to_residual(lat, tol, max_steps, check=100, log=None, t0=0, reached=None, restart=None, reason=None):
+    """Advance until every member's residual is <= tol, or max_steps (the
+    lattice's own step count, starting at t0).  Returns (steps-to-tol per
+    member (-1 if never), final residuals).  A member whose state turns
+    non-finite raises, unless `restart` (rest-state populations, as for
+    replace_members) is given: then it starts again from rest, keeps being
+    charged from step 0, and `reason` (if given) records "blowup"."""
     import torch
 
     nb = lat.shape[0]
-    reached = np.full(nb, -1, np.int64)
+    reached = np.full(nb, -1, np.int64) if reached is None else reached
     res = np.full(nb, np.inf)
-    t = 0
+    t = t0
     while t < max_steps:
-        lat.step(check - 2)
-        lat.reduce(snapshot=True)
-        lat.step(2)
+        res, bad = advance_check(lat, check)
         t += check
-        r = lat.reduce(residual=True, allow_unstable=True)
-        res = r[:, RED["residual"]] / 2.0
-        bad = r[:, RED["nonfinite"]] > 0
         if bad.any():
-            raise RuntimeError(f"solver blew up in members {np.nonzero(bad)[0].tolist()}")
+            if restart is None:
+                raise RuntimeError(f"solver blew up in members {np.nonzero(bad)[0].tolist()}")
+            replace_members(lat, bad, restart)
+            reached[bad] = -1
+            if reason is not None:
+                reason[bad] = "blowup"
         newly = (res <= tol) & (reached < 0)
         reached[newly] = t
         if log and t % (20 * check) == 0:
@@ -139,6 +177,59 @@ def run_to_residual(lat, tol, max_steps, check=100, log=None):
             break
     torch.cuda.synchronize()
     return reached, res
+
+
+def screen(rho, u, umax=0.1, drho=0.1):
+    """Members whose predicted state is unusable: non-finite, a velocity
+    component above umax in magnitude, or a density further than drho from 1."""
+    with np.errstate(invalid="ignore"):
+        bad = ~np.isfinite(u).all(axis=(0, 2, 3, 4)) | ~np.isfinite(rho).all(axis=(1, 2, 3))
+        bad |= np.nan_to_num(np.abs(u), nan=0.0).max(axis=(0, 2, 3, 4)) > umax
+        bad |= np.nan_to_num(np.abs(rho - 1.0), nan=0.0).max(axis=(1, 2, 3)) > drho
+    return bad
+
+
+def warm_solve(solid, force, rho_pred, u_pred, tol, max_steps, check=100, log=None):
+    """Solve the channels from a predicted state, with the method as judge
+    (see the module notes on fallback).  Returns a dict: the lattice at the
+    end, reached (absolute step of convergence per member, -1 if never),
+    charged (steps charged per member: reached, plus the abandoned first
+    interval for a residual fallback, max_steps if never converged), final
+    residuals, and the fallback reason per member ("" = warm start kept)."""
+    nb = solid.shape[0]
+    reason = np.array([""] * nb, dtype=object)
+    bad = screen(rho_pred, u_pred)
+    reason[bad] = "screen"
+    rho0 = np.where(bad[:, None, None, None], 1.0, rho_pred)
+    u0 = np.where(bad[None, :, None, None, None], 0.0, u_pred)
+
+    def lattice(r, u):
+        lat = new_lattice(nb)
+        lat.set_solid(solid)
+        lat.set_force("batch", force)
+        lat.init(r, u)
+        return lat
+
+    warm = lattice(rho0, u0)
+    cold = lattice(None, None)
+    rest = cold.populations()  # the cold start's state at t = 0
+    res_w, nonfin = advance_check(warm, check)
+    res_c, _ = advance_check(cold, check)
+    worse = ~bad & (nonfin | ~(res_w <= res_c))
+    reason[worse] = "residual"
+    if worse.any():
+        replace_members(warm, worse, cold.populations())
+        res_w[worse] = res_c[worse]
+    if log:
+        log(f"  first check: warm residual median {np.median(res_w):.2e}, cold {np.median(res_c):.2e}; "
+            f"fallbacks {[(int(i), reason[i]) for i in np.nonzero(reason != '')[0]]}")
+    del cold
+    reached = np.where(res_w <= tol, check, -1).astype(np.int64)
+    if not (reached >= 0).all():
+        reached, res_w = run_to_residual(warm, tol, max_steps, check, log=log, t0=check, reached=reached,
+                                         restart=rest, reason=reason)
+    charged = np.where(reached < 0, max_steps, reached) + np.where(worse, check, 0)
+    return dict(lattice=warm, reached=reached, charged=charged, residual=res_w, reason=reason)
 
 
 def steady_moments(lat):
@@ -318,7 +409,13 @@ def predict(net, solid, fx, batch=8):
     return rho, u
 
 
-def evaluate(net, first_seed=1_000_000, nb=64, tol=1e-8, max_steps=40000, ablation=False, log=print):
+def evaluate(net, first_seed=1_000_000, nb=64, tol=1e-8, max_steps=40000, ablation=False, log=print,
+             corrupt=None):
+    """Steps to the residual tol from rest (cold), from the empty-channel
+    Poiseuille profile, from the network's prediction (warm, through
+    warm_solve and its fallback) and from the converged cold moments
+    (exact).  corrupt(rho, u) -> (rho, u), if given, alters the prediction on
+    the host before the solve (used to exercise the fallback)."""
     import torch
 
     wl = workloads.sphere_channels(nb, NX, NY, NZ, seed=first_seed)
@@ -330,19 +427,15 @@ def evaluate(net, first_seed=1_000_000, nb=64, tol=1e-8, max_steps=40000, ablati
     rho_warm, u_warm = predict(net, solid, fx) if net is not None else (None, None)
     torch.cuda.synchronize()
     t_infer = time.perf_counter() - t0
-    fallback = np.zeros(nb, bool)
-    if u_warm is not None:
-        bad = ~np.isfinite(u_warm).all(axis=(0, 2, 3, 4)) | (np.abs(u_warm).max(axis=(0, 2, 3, 4)) > 0.1)
-        bad |= ~np.isfinite(rho_warm).all(axis=(1, 2, 3)) | (np.abs(rho_warm - 1).max(axis=(1, 2, 3)) > 0.1)
-        u_warm[:, bad] = 0.0
-        rho_warm[bad] = 1.0
-        fallback = bad
+    if u_warm is not None and corrupt is not None:
+        rho_warm, u_warm = corrupt(rho_warm, u_warm)
     inits = {"cold": (None, None), "poiseuille": (None, poiseuille_field(solid, fx))}
     if u_warm is not None:
         inits["warm"] = (rho_warm, u_warm)
     names = list(inits) + ["exact"]
     if ablation and u_warm is not None:
         names += ["warm_u_exact_rho", "exact_u_warm_rho"]
+    reason = np.array([""] * nb, dtype=object)
     for name in names:
         # "exact": the converged cold-start moments themselves, the best any
         # moment-based initialisation can do (the non-equilibrium parts of
@@ -356,37 +449,48 @@ def evaluate(net, first_seed=1_000_000, nb=64, tol=1e-8, max_steps=40000, ablati
             r0, u0 = rho_warm, fields["cold"][1]
         else:
             r0, u0 = inits[name]
-        lat = new_lattice(nb)
-        lat.set_solid(solid)
-        lat.set_force("batch", force)
-        lat.init(r0, u0)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        reached, res = run_to_residual(lat, tol, max_steps)
+        if name == "warm":
+            out = warm_solve(solid, force, r0, u0, tol, max_steps, log=log)
+            lat, reached, charged, reason = out["lattice"], out["reached"], out["charged"], out["reason"]
+        else:
+            lat = new_lattice(nb)
+            lat.set_solid(solid)
+            lat.set_force("batch", force)
+            lat.init(r0, u0)
+            reached, _ = run_to_residual(lat, tol, max_steps)
+            charged = np.where(reached < 0, max_steps, reached)
         dt = time.perf_counter() - t1
         fields[name] = steady_moments(lat)
-        results[name] = {"steps": reached.tolist(), "median_steps": float(np.median(reached)),
-                         "mean_steps": float(np.mean(reached)), "solve_seconds": dt,
-                         "all_converged": bool((reached >= 0).all())}
-        log(f"{name}: steps to {tol:g} median {np.median(reached):.0f} mean {np.mean(reached):.0f} "
-            f"max {reached.max()} ({dt:.1f} s)")
+        conv = bool((reached >= 0).all())
+        results[name] = {"steps": charged.tolist(), "reached": reached.tolist(),
+                         "median_steps": float(np.median(charged)), "mean_steps": float(np.mean(charged)),
+                         "solve_seconds": dt, "all_converged": conv, "unconverged": int((reached < 0).sum())}
+        log(f"{name}: steps to {tol:g} median {np.median(charged):.0f} mean {np.mean(charged):.0f} "
+            f"max {charged.max()}{'' if conv else f' ({int((reached < 0).sum())} unconverged)'} ({dt:.1f} s)")
         del lat
         torch.cuda.empty_cache()
     fl = ~solid.astype(bool)
     rho_ref, u_ref_field = fields["cold"][0][fl], fields["cold"][1][:, fl]
     summary = {"tol": tol, "nb": nb, "first_seed": first_seed, "results": results, "inference_seconds": t_infer,
-               "fallbacks": int(fallback.sum())}
+               "fallbacks": int((reason != "").sum()),
+               "fallback_reasons": {int(i): str(reason[i]) for i in np.nonzero(reason != "")[0]}}
     for name in fields:
         if name != "cold":
             summary[f"{name}_vs_cold_final_rel"] = float(
                 np.linalg.norm(fields[name][1][:, fl] - u_ref_field) / np.linalg.norm(u_ref_field))
-            summary[f"speedup_steps_{name}"] = results["cold"]["mean_steps"] / results[name]["mean_steps"]
+            ok = results["cold"]["all_converged"] and results[name]["all_converged"]
+            summary[f"speedup_steps_{name}"] = (results["cold"]["mean_steps"] / results[name]["mean_steps"]
+                                                if ok else None)
     if u_warm is not None:
         summary["prediction_rel_error_u"] = float(np.linalg.norm(u_warm[:, fl] - u_ref_field) /
                                                   np.linalg.norm(u_ref_field))
         summary["prediction_rel_error_rho"] = float(np.linalg.norm(rho_warm[fl] - rho_ref) /
                                                     np.linalg.norm(rho_ref - 1.0))
-        summary["speedup_wall_warm"] = results["cold"]["solve_seconds"] / (results["warm"]["solve_seconds"] + t_infer)
+        ok = results["cold"]["all_converged"] and results["warm"]["all_converged"]
+        summary["speedup_wall_warm"] = (results["cold"]["solve_seconds"] / (results["warm"]["solve_seconds"] + t_infer)
+                                        if ok else None)
     summary["poiseuille_rel_error_u"] = float(np.linalg.norm(inits["poiseuille"][1][:, fl] - u_ref_field) /
                                               np.linalg.norm(u_ref_field))
     return summary

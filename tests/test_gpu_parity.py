@@ -53,12 +53,12 @@ def fluid_rel(u, ref, solid=None):
     return rel(np.asarray(u)[:, m], np.asarray(ref)[:, m])
 
 
-def tgv_pair(n, storage, steps, re=1600.0):
+def tgv_pair(n, storage, steps, re=1600.0, stochastic=False):
     wl = W.taylor_green(n, re=re, seed=1)
     ref = O.Lattice(n, n, n, tau=wl["tau"], extended=storage == "fp64")
     ref.init(wl["rho"], wl["u"])
     ref.step(steps)
-    lat = Lat(nx=n, ny=n, nz=n, tau=wl["tau"], storage=storage)
+    lat = Lat(nx=n, ny=n, nz=n, tau=wl["tau"], storage=storage, stochastic=stochastic)
     lat.init(wl["rho"], wl["u"])
     lat.step(steps)
     return ref, lat
@@ -500,10 +500,14 @@ def test_fp32_poiseuille_config(torch):
     assert err < 1e-5
 
 
-@pytest.mark.parametrize("storage,bound", [("fp16", 5e-3), ("bf16", 5e-2)])
-def test_16bit_taylor_green_32_error(torch, storage, bound):
-    log(f"{storage} TGV 32^3, 200 steps")
-    ref, lat = tgv_pair(32, storage, 200)
+@pytest.mark.parametrize("storage,stochastic,bound", [("fp16", False, 1e-3), ("fp16", True, 1e-3),
+                                                      ("bf16", False, 1e-2), ("bf16", True, 1e-2)])
+def test_16bit_taylor_green_32_error(torch, storage, stochastic, bound):
+    """Velocity error of 16-bit storage after 200 steps of TGV 32^3 (Re 1600)
+    against the FP64 oracle: FP16 within the 1e-3 target with either
+    rounding; BF16 (8-bit significand) within 1e-2."""
+    log(f"{storage}{' stochastic rounding' if stochastic else ''} TGV 32^3, 200 steps")
+    ref, lat = tgv_pair(32, storage, 200, stochastic=stochastic)
     _, u = lat.moments()
     _, ur = ref.moments()
     err = rel(u.cpu().numpy(), ur)

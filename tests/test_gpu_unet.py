@@ -192,3 +192,58 @@ def test_warm_and_cold_starts_reach_the_same_state():
     log(f"  warm vs cold final {s['warm_vs_cold_final_rel']:.3e}")
     assert all(r["all_converged"] for r in s["results"].values())
     assert s["warm_vs_cold_final_rel"] < 1e-6
+
+
+def test_warm_start_fallback_on_corrupted_predictions():
+    """The method judges every prediction.  Three of 8 held-out channels get
+    a corrupted prediction on the host: a non-finite velocity (member 1) and
+    a velocity component of 0.2 (member 3) are screened out before the run
+    and start from rest; member 5 gets a scrambled field (i.i.d. velocity
+    and density noise of up to 0.09 per cell, inside the screen) whose
+    residual at the first check is worse than the cold start's, so it
+    continues from the cold start's state.  No other member falls back.
+    Every member converges to the cold start's state (residual 1e-10,
+    velocity within 1e-6), and the fallback members are charged the cold
+    start's steps, plus the abandoned first interval (100 steps) for
+    member 5."""
+    from paper_1905_10182_amd import warmstart as WS
+
+    def corrupt(rho, u):
+        rho, u = rho.copy(), u.copy()
+        u[0, 1, 3, 4, 5] = np.nan
+        u[0, 3, 10, 15, 20] = 0.2
+        g = W.generator(77)
+        u[:, 5] = g.uniform(-0.09, 0.09, size=u[:, 5].shape)
+        rho[5] = 1.0 + g.uniform(-0.09, 0.09, size=rho[5].shape)
+        return rho, u
+
+    log("warm start with corrupted predictions, 8 channels, residual 1e-10")
+    s = WS.evaluate(WS.load_model(), first_seed=1_000_200, nb=8, tol=1e-10, max_steps=60000, log=log,
+                    corrupt=corrupt)
+    log(f"  fallbacks {s['fallback_reasons']}, warm vs cold final {s['warm_vs_cold_final_rel']:.3e}")
+    assert s["fallback_reasons"] == {1: "screen", 3: "screen", 5: "residual"}
+    cold, warm = s["results"]["cold"], s["results"]["warm"]
+    assert cold["all_converged"] and warm["all_converged"]
+    log(f"  steps cold {cold['steps']}\n  steps warm {warm['steps']}")
+    # a fallback member follows the cold start's trajectory (to the ~1e-16
+    # rounding of the population export / import that swaps members' states)
+    for m in (1, 3):
+        assert abs(warm["steps"][m] - cold["steps"][m]) <= 100
+    assert abs(warm["steps"][5] - (cold["steps"][5] + 100)) <= 100 and warm["steps"][5] > cold["steps"][5]
+    assert s["warm_vs_cold_final_rel"] < 1e-6
+    kept = [m for m in range(8) if m not in (1, 3, 5)]
+    assert np.mean([warm["steps"][m] for m in kept]) < np.mean([cold["steps"][m] for m in kept])
+
+
+def test_warm_start_counts_unconverged_members():
+    """A member that does not reach the tolerance within max_steps is
+    charged max_steps and reported unconverged, and no speed-up is computed
+    from an incomplete run."""
+    from paper_1905_10182_amd import warmstart as WS
+
+    log("warm start with a step budget too small to converge, 4 channels")
+    s = WS.evaluate(WS.load_model(), first_seed=1_000_300, nb=4, tol=1e-8, max_steps=300, log=log)
+    cold = s["results"]["cold"]
+    assert not cold["all_converged"] and cold["unconverged"] > 0
+    assert all(st == 300 for st, r in zip(cold["steps"], cold["reached"]) if r < 0)
+    assert s["speedup_steps_warm"] is None and s["speedup_wall_warm"] is None

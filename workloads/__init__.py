@@ -174,6 +174,26 @@ def random_populations(shape, seed, lo=0.8, hi=1.2, q=27):
     return generator(seed).uniform(lo, hi, size=(q,) + tuple(shape)) / float(q)
 
 
+def representable(x, storage):
+    """x (FP64 array) moved to a nearby value that the storage format holds
+    exactly, so that both sides of a parity test start from the same numbers:
+    FP64 unchanged; FP32 rounded to float32; FP16 as the solver stores it
+    (256 x rounded to binary16, divided by 256); BF16 x in float32 with the
+    low 16 bits cleared (truncated to an 8-bit significand).  Input
+    preparation only."""
+    x = np.asarray(x, np.float64)
+    if storage == "fp64":
+        return x.copy()
+    if storage == "fp32":
+        return x.astype(np.float32).astype(np.float64)
+    if storage == "fp16":
+        return (x * 256.0).astype(np.float16).astype(np.float64) / 256.0
+    if storage == "bf16":
+        b = np.ascontiguousarray(x.astype(np.float32)).view(np.uint32) & np.uint32(0xFFFF0000)
+        return b.view(np.float32).astype(np.float64)
+    raise ValueError(storage)
+
+
 def random_cells(n, seed, umax=0.1, rho_lo=0.9, rho_hi=1.1):
     """n random (rho, u) pairs: rho ~ U[rho_lo, rho_hi], u_a ~ U[-umax, umax]."""
     g = generator(seed)
