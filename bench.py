@@ -1,19 +1,34 @@
 """Benchmark of the fused D3Q27 CM-LBM step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp16]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--repeats R] [--legs LIST] [--error-steps E]
+                    [--no-cpu] [--no-fp16] [--no-warmstart] [--no-mom] [--no-d2q9] [--no-mhd]
+    python bench.py --cpu-detail
 
 Headline workload: 3D Taylor-Green vortex, 256^3 periodic, FP32 populations,
 u0 = 0.05, Re = 1600, zero force.  A step is one pass of the whole hot path
-(one fused pull-stream + collide launch over every cell).  Prints one JSON line:
-value = GLUPS (10^9 lattice-cell updates per second) of the timed K steps,
-plus the HBM roofline of the step kernel, the FP16-storage variant at 512^3,
-and the FP64 CPU oracle timed on the host cores on a bounded sample.
+(one fused pull-stream + collide launch over every cell).  Every leg runs W
+untimed warmup steps and then R timed windows of exactly K steps (HIP events
+on the solver's stream, synchronised on both sides); its figure is the
+median window.  Prints one JSON line: value = GLUPS (10^9 lattice-cell
+updates per second) of the headline leg, the HBM roofline of its step
+kernel, the FP64 CPU oracle timed on the host cores on a bounded sample,
+and the other legs:
+  - precision legs, Taylor-Green 512^3 (the same vortex, Re = 1600): FP64,
+    FP32, FP16 and BF16 storage (16-bit with nearest and with stochastic
+    rounding), each run first for E steps from the initial state with the
+    fused reductions -- its kinetic energy at every step -- and compared
+    after E steps with the FP64 run (relative L2 velocity error, eq. error
+    of the paper) and with the FP32 run; then timed.  The 16-bit speed-ups
+    are given against FP32 at the same size;
+  - FP64 storage at 256^3, moment storage, the D2Q9 model, the magnetic
+    lattice, the fused reductions, copy kernels and the learned warm start.
 """
 import argparse
 import json
 import math
 import os
 import re
+import statistics
 import sys
 import time
 
@@ -25,11 +40,21 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 BYTES_PER_CELL = {"fp64": 432, "fp32": 216, "fp16": 108, "bf16": 108,  # 27 reads + 27 writes
                   "mom32": 72}  # moment representation: 9 FP32 numbers read + 9 written
 # template arguments: storage, cells per lane, solid mask, force field, non-temporal stores, collision model,
-# fused reductions
-STEP_KERNEL = {"fp32": "k_step<1, 1, false, false, true, 0, false>", "fp16": "k_step<2, 2, false, false, true, 0, false>",
-               "bf16": "k_step<3, 2, false, false, true, 0, false>", "fp64": "k_step<0, 1, false, false, true, 0, false>"}
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_step_tgv256_fp32_counters.md")
+# fused reductions, stochastic rounding
+STEP_KERNEL = {"fp32": "k_step<1, 1, false, false, true, 0, false, false>",
+               "fp16": "k_step<2, 2, false, false, true, 0, false, false>",
+               "fp16sr": "k_step<2, 2, false, false, true, 0, false, true>",
+               "bf16": "k_step<3, 2, false, false, true, 0, false, false>",
+               "bf16sr": "k_step<3, 2, false, false, true, 0, false, true>",
+               "fp64": "k_step<0, 1, false, false, true, 0, false, false>"}
+# committed rocprofv3 counter summaries (FETCH_SIZE, WRITE_SIZE) per step configuration
+COUNTERS_FILE = {k: os.path.join(ROOT, "profiles", f"k_step_{k}_counters.md") for k in STEP_KERNEL}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1905_10182_amd", "csrc", f) for f in ("cmlbm.hip", "d3q27.hpp")]
+ALL_LEGS = ("fp32", "precision", "fp64", "mom", "d2q9", "mhd", "fused", "copy", "warmstart", "cpu")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def source_digest():
@@ -40,12 +65,14 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None if there is none or the kernel sources changed since it was taken."""
-    if not os.path.exists(COUNTERS_FILE):
+def measured_traffic(key):
+    """HBM bytes per launch of the step configuration `key` from its committed
+    rocprofv3 counter summary, or None if there is none or the kernel sources
+    changed since it was taken."""
+    path = COUNTERS_FILE.get(key)
+    if not path or not os.path.exists(path):
         return None
-    text = open(COUNTERS_FILE).read()
+    text = open(path).read()
     m = re.search(r"source_digest:\s*([0-9a-f]+)", text)
     t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
     if not m or not t or m.group(1) != source_digest():
@@ -53,40 +80,112 @@ def measured_traffic():
     return float(t.group(1))
 
 
-def time_steps(lat, steps, warmup):
+def time_steps(lat, steps, warmup, repeats):
+    """warmup untimed steps, then `repeats` windows of exactly `steps` steps,
+    each bracketed by a device synchronisation and timed with HIP events on the
+    stream the solver launches on.  Returns the seconds of each window."""
     import torch
     lat.step(warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    lat.step(steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    return e0.elapsed_time(e1) / 1e3, wall
+    out = []
+    for _ in range(repeats):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        lat.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1) / 1e3)
+    return out
 
 
-def run_gpu(n, storage, steps, warmup, stochastic=False):
+def rate(ncell, steps, windows, bytes_per_cell):
+    """Figures of a timed leg from its windows (median window)."""
+    secs = statistics.median(windows)
+    launch = secs / steps
+    gbs = bytes_per_cell * ncell / launch / 1e9
+    return {"glups": round(ncell * steps / secs / 1e9, 4), "ms_per_step": round(launch * 1e3, 5),
+            "window_ms_per_step": [round(w / steps * 1e3, 5) for w in windows],
+            "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def run_gpu(n, storage, steps, warmup, repeats, stochastic=False, fields=None):
+    """Time the step on the Taylor-Green vortex n^3 (FP32/FP64/16-bit/moment storage)."""
     import workloads
     from paper_1905_10182_amd import Lattice
 
-    wl = workloads.taylor_green(n, seed=1)
+    wl = fields or workloads.taylor_green(n, seed=1)
     lat = Lattice(n, n, n, tau=wl["tau"], storage=storage, stochastic=stochastic, device="cuda:0")
     lat.init(wl["rho"], wl["u"])
     del wl
     r0 = lat.reduce()
-    secs, wall = time_steps(lat, steps, warmup)
+    windows = time_steps(lat, steps, warmup, repeats)
     r1 = lat.reduce()
-    ncell = n ** 3
-    mass_drift = abs(r1[0, 0] / r0[0, 0] - 1)
     assert r1[0, 6] == 0, "non-finite state"
     lat.close()
-    return dict(secs=secs, wall=wall, glups=ncell * steps / secs / 1e9, ms_per_step=secs / steps * 1e3,
-                launch_s=secs / steps, bytes_per_launch=BYTES_PER_CELL[storage] * ncell, mass_drift=mass_drift,
-                umax=float(r1[0, 5]))
+    out = rate(n ** 3, steps, windows, BYTES_PER_CELL[storage])
+    out["mass_drift"] = abs(r1[0, 0] / r0[0, 0] - 1)
+    return out
+
+
+def device_fields(n):
+    """The Taylor-Green n^3 initial state uploaded once (FP64 on the device), reused by every leg."""
+    import torch
+    import workloads
+    wl = workloads.taylor_green(n, seed=1)
+    return {"tau": wl["tau"], "rho": torch.as_tensor(wl["rho"], device="cuda:0"),
+            "u": torch.as_tensor(wl["u"], device="cuda:0")}
+
+
+def precision_legs(n, names, steps, warmup, repeats, error_steps, fields):
+    """Each configuration from the same initial state: error_steps steps through
+    cmlbm_step_reduce (kinetic energy of every step), velocity after them
+    compared with the FP64 and FP32 runs, then the timed windows."""
+    import torch
+    from paper_1905_10182_amd import Lattice
+
+    ref = {}
+    ke_ref = {}
+    out = {}
+    for name in names:
+        st, sr = name[:4], name.endswith("sr")
+        log(f"TGV {n}^3 {name}: {error_steps} steps with per-step kinetic energy")
+        lat = Lattice(n, n, n, tau=fields["tau"], storage=st, stochastic=sr, fused_reduce=True, device="cuda:0")
+        lat.init(fields["rho"], fields["u"])
+        t0 = time.perf_counter()
+        ke = [float(lat.step_reduce(allow_unstable=True)[0, 4]) for _ in range(error_steps)]
+        t_err = time.perf_counter() - t0
+        u = lat.moments(dtype=torch.float64)[1]
+        finite = bool(torch.isfinite(u).all())
+        row = {"kernel": STEP_KERNEL[name], "rounding": "stochastic" if sr else ("nearest" if st in ("fp16", "bf16")
+                                                                                  else None)}
+        err = {"steps": error_steps, "finite": finite}
+        for rk in ("fp64", "fp32"):
+            if rk in ref and rk != name:
+                err[f"rel_l2_u_vs_{rk}"] = float(torch.linalg.vector_norm(u - ref[rk]) /
+                                                 torch.linalg.vector_norm(ref[rk]))
+                err[f"max_rel_ke_dev_vs_{rk}"] = max(abs(a / b - 1) for a, b in zip(ke, ke_ref[rk]))
+        err["ke_final"] = ke[-1]
+        row["error"] = err
+        if name in ("fp64", "fp32"):
+            ref[name] = u
+            ke_ref[name] = ke
+        else:
+            del u
+        log(f"  {name}: {err} ({t_err:.1f} s)")
+        if name != "fp64":  # FP64 storage is timed at the headline size
+            windows = time_steps(lat, steps, warmup, repeats)
+            row.update(rate(n ** 3, steps, windows, BYTES_PER_CELL[st]))
+            row["traffic"] = measured_traffic(name)
+            log(f"  {name}: {row['glups']:.2f} GLUPS, {row['hbm_gbs']:.0f} GB/s")
+        lat.close()
+        torch.cuda.empty_cache()
+        out[name] = row
+    del ref
+    torch.cuda.empty_cache()
+    return out
 
 
 # D2Q9 (App. B model): nine populations read + nine written, plus the force
@@ -96,7 +195,7 @@ STEP_KERNEL_2D = {"fp64": "k2_step<0, 1, true>", "fp32": "k2_step<1, 2, true>", 
                   "bf16": "k2_step<3, 4, true>"}
 
 
-def run_gpu_2d(n, storage, steps, warmup):
+def run_gpu_2d(n, storage, steps, warmup, repeats):
     """The four-rolls mill (App. B model, per-cell force field) on an n x n lattice."""
     import numpy as np
     import torch
@@ -109,26 +208,25 @@ def run_gpu_2d(n, storage, steps, warmup):
     lat.set_force("field", field=wl["force"])
     lat.init(np.ones(1, np.float32), wl["u_exact"], dtype=torch.float32)
     del wl
-    secs, wall = time_steps(lat, steps, warmup)
+    windows = time_steps(lat, steps, warmup, repeats)
     rho, u = lat.moments()
     finite = bool(torch.isfinite(u).all()) and bool(torch.isfinite(rho).all())
     assert finite, "non-finite state"
     mass_drift = abs(float(rho.sum()) / (n * n) - 1)
     del rho, u, lat
     torch.cuda.empty_cache()
-    ncell = n * n
-    return dict(secs=secs, wall=wall, glups=ncell * steps / secs / 1e9, ms_per_step=secs / steps * 1e3,
-                launch_s=secs / steps, bytes_per_launch=BYTES_PER_CELL_2D[storage] * ncell, mass_drift=mass_drift)
+    out = rate(n * n, steps, windows, BYTES_PER_CELL_2D[storage])
+    out.update(kernel=STEP_KERNEL_2D[storage], bytes_per_cell=BYTES_PER_CELL_2D[storage], mass_drift=mass_drift)
+    return out
 
 
 # magnetic lattice (FP32): 21 populations read + 21 written, u (3 values) read
 BYTES_PER_CELL_MHD = 21 * 4 * 2 + 12
 
 
-def run_gpu_mhd(n, steps, warmup):
+def run_gpu_mhd(n, steps, warmup, repeats):
     """The magnetic lattice alone (FP32, n^3, periodic) stepped with a fixed
     velocity field: 21 populations read and written per cell plus u read."""
-    import numpy as np
     import torch
 
     from paper_1905_10182_amd.mhd import MagneticLattice
@@ -144,34 +242,33 @@ def run_gpu_mhd(n, steps, warmup):
         lat.step(u)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(steps):
-        lat.step(u)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    secs = e0.elapsed_time(e1) / 1e3
+    windows = []
+    for _ in range(repeats):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            lat.step(u)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        windows.append(e0.elapsed_time(e1) / 1e3)
     bf, _ = lat.fields()
     assert bool(torch.isfinite(bf).all()), "non-finite magnetic field"
     del lat, u, bf
     torch.cuda.empty_cache()
-    ncell = n ** 3
-    return dict(glups=ncell * steps / secs / 1e9, ms_per_step=secs / steps * 1e3,
-                bytes_per_launch=BYTES_PER_CELL_MHD * ncell, launch_s=secs / steps)
+    out = rate(n ** 3, steps, windows, BYTES_PER_CELL_MHD)
+    out.update(kernel="k_mhd_step<float>", bytes_per_cell=BYTES_PER_CELL_MHD)
+    return out
 
 
-def run_fused(n, calls):
+def run_fused(n, calls, fields):
     """cmlbm_step_reduce (a step whose kernel also forms the FP64 reductions of
     the state it reads) against cmlbm_reduce + cmlbm_step, wall clock per call
     (both wait for the stream), FP32 TGV n^3."""
     import torch
-    import workloads
     from paper_1905_10182_amd import Lattice
 
-    wl = workloads.taylor_green(n, seed=1)
-    lat = Lattice(n, n, n, tau=wl["tau"], storage="fp32", fused_reduce=True, device="cuda:0")
-    lat.init(wl["rho"], wl["u"])
-    del wl
+    lat = Lattice(n, n, n, tau=fields["tau"], storage="fp32", fused_reduce=True, device="cuda:0")
+    lat.init(fields["rho"], fields["u"])
     lat.step(5)
     lat.step_reduce()
     torch.cuda.synchronize()
@@ -196,47 +293,25 @@ def run_fused(n, calls):
             "reduce_then_step_ms": round(t_sep * 1e3, 4), "ke": float(r[0, 4])}
 
 
-def copy_bandwidth():
+def copy_bandwidth(fn):
+    """Read + write rate of fn(dst, src) on 4 GiB, median of 10 calls."""
     import torch
-    n = 1 << 30  # 4 GiB of float32
-    a = torch.empty(n, dtype=torch.float32, device="cuda:0")
-    b = torch.empty_like(a)
-    b.copy_(a)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    reps = 10
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    s = e0.elapsed_time(e1) / 1e3
-    del a, b
-    torch.cuda.empty_cache()
-    return 2 * 4 * n * reps / s / 1e9
-
-
-def kernel_copy_bandwidth():
-    """Rate of the library's plain 16-byte non-temporal copy kernel on 4 GiB:
-    the practical read + write ceiling of the device."""
-    import torch
-    from paper_1905_10182_amd.cmlbm import device_copy
     n = 1 << 30
     a = torch.empty(n, dtype=torch.float32, device="cuda:0")
     b = torch.empty_like(a)
-    device_copy(b, a)
+    fn(b, a)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    reps = 10
-    for _ in range(reps):
-        device_copy(b, a)
-    e1.record()
-    torch.cuda.synchronize()
-    s = e0.elapsed_time(e1) / 1e3
+    ts = []
+    for _ in range(10):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn(b, a)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
     del a, b
     torch.cuda.empty_cache()
-    return 2 * 4 * n * reps / s / 1e9
+    return 2 * 4 * n / statistics.median(ts) / 1e9
 
 
 def warm_start():
@@ -245,65 +320,73 @@ def warm_start():
     from paper_1905_10182_amd import warmstart as ws
 
     net = ws.load_model()
-    s = ws.evaluate(net, first_seed=1_000_000, nb=64, tol=1e-8, log=lambda m: print(f"[bench]   {m}", file=sys.stderr,
-                                                                                    flush=True))
+    s = ws.evaluate(net, first_seed=1_000_000, nb=64, tol=1e-8, log=lambda m: log(f"  {m}"))
     r = s["results"]
+    rnd = lambda v, k=3: None if v is None else round(v, k)  # noqa: E731
     return {"workload": "64 channels 64x32x32, 1-4 spheres r 3-8, F_x ~ U[1e-6, 1e-5], tau 0.8, fp64, "
                         "seeds 1000000..1000063",
             "mean_steps_cold": r["cold"]["mean_steps"], "mean_steps_warm": r["warm"]["mean_steps"],
             "mean_steps_exact_moments": r["exact"]["mean_steps"],
-            "speedup_steps": round(s["speedup_steps_warm"], 3), "speedup_wall": round(s["speedup_wall_warm"], 3),
-            "speedup_steps_exact_moments": round(s["speedup_steps_exact"], 3),
+            "all_converged": all(v["all_converged"] for v in r.values()),
+            "speedup_steps": rnd(s["speedup_steps_warm"]), "speedup_wall": rnd(s["speedup_wall_warm"]),
+            "speedup_steps_exact_moments": rnd(s["speedup_steps_exact"]),
             "prediction_rel_error_u": round(s["prediction_rel_error_u"], 5),
             "prediction_rel_error_rho": round(s["prediction_rel_error_rho"], 5),
             "warm_vs_cold_final_rel": s["warm_vs_cold_final_rel"], "inference_s": round(s["inference_seconds"], 4),
-            "fallbacks": s["fallbacks"]}
+            "fallbacks": s["fallbacks"], "fallback_reasons": s["fallback_reasons"]}
+
+
+_ORACLE_RUN = r"""
+import json, sys, time
+sys.path.insert(0, %r)
+import oracle, workloads
+n, steps, variant = %d, %d, %r
+wl = workloads.taylor_green(n, seed=1)
+L = oracle.Lattice(n, n, n, tau=wl["tau"])
+L.init(wl["rho"], wl["u"])
+del wl
+L.step(1, variant=variant)
+t0 = time.perf_counter()
+L.step(steps, variant=variant)
+s = time.perf_counter() - t0
+print(json.dumps({"n": n, "steps": steps, "route": variant, "threads": oracle.num_threads(), "seconds": s,
+                  "glups": n ** 3 * steps / s / 1e9}), flush=True)
+"""
+
+
+def oracle_rate(n, steps, threads=None, variant="closed"):
+    """The FP64 oracle (closed-form route, OpenMP) timed in a child process
+    (its thread count is fixed when the OpenMP runtime starts)."""
+    import subprocess
+    env = dict(os.environ)
+    if threads:
+        env["OMP_NUM_THREADS"] = str(threads)
+    res = subprocess.run([sys.executable, "-c", _ORACLE_RUN % (ROOT, n, steps, variant)], env=env,
+                         capture_output=True, text=True, check=True)
+    return json.loads([l for l in res.stdout.splitlines() if l.startswith("{")][-1])
 
 
 def cpu_baseline():
-    """The FP64 oracle (closed-form route, OpenMP) on a bounded sample of the
-    same workload: Taylor-Green 128^3, 400 steps."""
-    import oracle
-    import workloads
-
-    n, steps = 128, 400
-    wl = workloads.taylor_green(n, seed=1)
-    L = oracle.Lattice(n, n, n, tau=wl["tau"])
-    L.init(wl["rho"], wl["u"])
-    L.step(1)
-    t0 = time.perf_counter()
-    L.step(steps)
-    s = time.perf_counter() - t0
-    return {"value": n ** 3 * steps / s / 1e9, "unit": "GLUPS", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"taylor_green {n}^3 fp64, {steps} steps ({s:.1f} s)"}
+    """The FP64 oracle on the headline workload itself (Taylor-Green 256^3): a
+    bounded sample of 8 steps on all host threads and 1 step on one thread."""
+    allc = oracle_rate(256, 8)
+    one = oracle_rate(256, 1, threads=1)
+    return {"value": round(allc["glups"], 5), "unit": "GLUPS", "cores": allc["threads"], "kind": "oracle",
+            "sample": f"taylor_green 256^3 fp64 closed-form route: {allc['steps']} steps on {allc['threads']} "
+                      f"threads ({allc['seconds']:.1f} s); 1 step on 1 thread ({one['seconds']:.1f} s)",
+            "one_thread_glups": round(one["glups"], 5)}
 
 
 def cpu_detail():
     """The oracle on the host cores in more detail (not part of the default run):
     closed-form route at 64^3 and 256^3 with one thread and with all threads,
     and the literal route (matrix algebra per cell) at 32^3."""
-    import subprocess
-    code = r"""
-import json, os, sys, time
-sys.path.insert(0, %r)
-import oracle, workloads
-def run(n, steps, variant):
-    wl = workloads.taylor_green(n, seed=1)
-    L = oracle.Lattice(n, n, n, tau=wl["tau"])
-    L.init(wl["rho"], wl["u"])
-    L.step(1, variant=variant)
-    t0 = time.perf_counter()
-    L.step(steps, variant=variant)
-    s = time.perf_counter() - t0
-    return {"n": n, "steps": steps, "route": variant, "threads": oracle.num_threads(), "mlups": round(n ** 3 * steps / s / 1e6, 3)}
-for n, steps, v in ((64, 20, "closed"), (256, 3, "closed"), (32, 3, "literal")):
-    print(json.dumps(run(n, steps, v)), flush=True)
-""" % ROOT
     rows = []
     for threads in (1, os.cpu_count()):
-        env = dict(os.environ, OMP_NUM_THREADS=str(threads))
-        out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, check=True)
-        rows += [json.loads(l) for l in out.stdout.splitlines() if l.startswith("{")]
+        for n, steps, v in ((64, 20, "closed"), (256, 3, "closed"), (32, 3, "literal")):
+            r = oracle_rate(n, steps, threads, v)
+            r["mlups"] = round(r.pop("glups") * 1e3, 3)
+            rows.append(r)
     model = ""
     try:
         model = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name"))
@@ -315,16 +398,22 @@ for n, steps, v in ((64, 20, "closed"), (256, 3, "closed"), (32, 3, "literal")):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--repeats", type=int, default=3)
+    ap.add_argument("--legs", default=",".join(ALL_LEGS), help=f"comma-separated subset of {','.join(ALL_LEGS)}")
+    ap.add_argument("--precision", default="fp64,fp32,fp16,fp16sr,bf16,bf16sr",
+                    help="configurations of the precision legs")
+    ap.add_argument("--error-steps", type=int, default=2000)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--n16", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-fp16", action="store_true", help="skip the FP16, BF16 and FP64 storage legs")
+    ap.add_argument("--no-fp16", action="store_true", help="skip the precision legs and the FP64 storage leg")
     ap.add_argument("--no-warmstart", action="store_true")
     ap.add_argument("--no-mom", action="store_true")
     ap.add_argument("--no-d2q9", action="store_true")
     ap.add_argument("--no-mhd", action="store_true")
     ap.add_argument("--cpu-detail", action="store_true", help="only time the oracle on the host in detail")
-    ap.add_argument("--n", type=int, default=256)
     args = ap.parse_args()
     if args.cpu_detail:
         print(json.dumps(cpu_detail()), flush=True)
@@ -333,119 +422,126 @@ def main():
         print(f"bench.py measures one GPU only (asked for {args.gpus}): the solver is single-GPU; "
               "a z-slab decomposition over several GPUs is not built.", file=sys.stderr)
         sys.exit(2)
+    legs = set(args.legs.split(","))
+    for flag, leg in (("no_cpu", "cpu"), ("no_warmstart", "warmstart"), ("no_mom", "mom"), ("no_d2q9", "d2q9"),
+                      ("no_mhd", "mhd")):
+        if getattr(args, flag):
+            legs.discard(leg)
+    if args.no_fp16:
+        legs -= {"precision", "fp64"}
+    K, W, R = args.steps, args.warmup, args.repeats
 
     import torch
     assert torch.cuda.is_available(), "no GPU"
-    print(f"[bench] TGV {args.n}^3 fp32: {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr,
-          flush=True)
-    main_run = run_gpu(args.n, "fp32", args.steps, args.warmup)
-    print(f"[bench] fp32 {main_run['glups']:.2f} GLUPS", file=sys.stderr, flush=True)
+    n = args.n
+    fields = device_fields(n)
+    main_run = None
     extra = {}
-    if not args.no_fp16:
-        n16 = 512 if args.n == 256 else args.n
-        print(f"[bench] TGV {n16}^3 fp16 storage", file=sys.stderr, flush=True)
-        r16 = run_gpu(n16, "fp16", max(args.steps // 4, 10), max(args.warmup // 4, 5))
-        extra["fp16_storage"] = {
-            "workload": f"taylor_green_{n16} fp16-stored shifted populations, fp32 compute",
-            "glups": round(r16["glups"], 3), "ms_per_step": round(r16["ms_per_step"], 4),
-            "hbm_gbs": round(r16["bytes_per_launch"] / r16["launch_s"] / 1e9, 1),
-            "hbm_frac": round(r16["bytes_per_launch"] / r16["launch_s"] / 1e9 / HBM_PEAK_GBS, 4),
-            "speedup_vs_fp32_glups": round(r16["glups"] / main_run["glups"], 3)}
-        print(f"[bench] fp16 {r16['glups']:.2f} GLUPS", file=sys.stderr, flush=True)
-        r16s = run_gpu(n16, "fp16", max(args.steps // 4, 10), max(args.warmup // 4, 5), stochastic=True)
-        extra["fp16_storage_stochastic_rounding"] = {
-            "glups": round(r16s["glups"], 3), "ms_per_step": round(r16s["ms_per_step"], 4),
-            "hbm_frac": round(r16s["bytes_per_launch"] / r16s["launch_s"] / 1e9 / HBM_PEAK_GBS, 4),
-            "speedup_vs_fp32_glups": round(r16s["glups"] / main_run["glups"], 3)}
-        print(f"[bench] fp16 stochastic rounding {r16s['glups']:.2f} GLUPS", file=sys.stderr, flush=True)
-        print(f"[bench] TGV {n16}^3 bf16 storage", file=sys.stderr, flush=True)
-        rb = run_gpu(n16, "bf16", max(args.steps // 4, 10), max(args.warmup // 4, 5))
-        extra["bf16_storage"] = {
-            "kernel": STEP_KERNEL["bf16"], "glups": round(rb["glups"], 3), "ms_per_step": round(rb["ms_per_step"], 4),
-            "hbm_gbs": round(rb["bytes_per_launch"] / rb["launch_s"] / 1e9, 1),
-            "hbm_frac": round(rb["bytes_per_launch"] / rb["launch_s"] / 1e9 / HBM_PEAK_GBS, 4),
-            "speedup_vs_fp32_glups": round(rb["glups"] / main_run["glups"], 3)}
-        print(f"[bench] bf16 {rb['glups']:.2f} GLUPS", file=sys.stderr, flush=True)
-        print(f"[bench] TGV {args.n}^3 fp64 storage", file=sys.stderr, flush=True)
-        r64 = run_gpu(args.n, "fp64", max(args.steps // 4, 10), max(args.warmup // 4, 5))
-        extra["fp64_storage"] = {
-            "workload": f"taylor_green_{args.n}, fp64 populations and arithmetic",
-            "kernel": STEP_KERNEL["fp64"], "glups": round(r64["glups"], 3), "ms_per_step": round(r64["ms_per_step"], 4),
-            "bytes_per_cell": BYTES_PER_CELL["fp64"],
-            "hbm_gbs": round(r64["bytes_per_launch"] / r64["launch_s"] / 1e9, 1),
-            "hbm_frac": round(r64["bytes_per_launch"] / r64["launch_s"] / 1e9 / HBM_PEAK_GBS, 4)}
-        print(f"[bench] fp64 {r64['glups']:.2f} GLUPS", file=sys.stderr, flush=True)
-    if not args.no_mom:
-        for nm in sorted({args.n, 512 if args.n == 256 else args.n}):
-            print(f"[bench] TGV {nm}^3 moment storage (FP32)", file=sys.stderr, flush=True)
-            rm = run_gpu(nm, "mom32", args.steps if nm == args.n else max(args.steps // 4, 10),
-                         args.warmup if nm == args.n else max(args.warmup // 4, 5))
-            extra[f"moment_storage_{nm}"] = {
-                "workload": f"taylor_green_{nm}, nine FP32 numbers per cell (rho - rho0, u, (1 - omega) k4..k8), "
-                            "neighbour populations rebuilt in LDS",
-                "glups": round(rm["glups"], 3), "ms_per_step": round(rm["ms_per_step"], 4),
-                "bytes_per_cell": BYTES_PER_CELL["mom32"],
-                "hbm_gbs": round(rm["bytes_per_launch"] / rm["launch_s"] / 1e9, 1),
-                "speedup_vs_fp32_populations_256": round(rm["glups"] / main_run["glups"], 3),
-                "mass_drift": rm["mass_drift"]}
-            print(f"[bench] moment storage {nm}^3: {rm['glups']:.2f} GLUPS", file=sys.stderr, flush=True)
-    if not args.no_d2q9:
+    if "fp32" in legs:
+        log(f"TGV {n}^3 fp32: {W} warmup + {R} x {K} timed steps")
+        main_run = run_gpu(n, "fp32", K, W, R, fields=fields)
+        log(f"fp32 {main_run['glups']:.2f} GLUPS ({main_run['window_ms_per_step']} ms per step)")
+    if "fp64" in legs:
+        log(f"TGV {n}^3 fp64 storage")
+        r64 = run_gpu(n, "fp64", K, W, R, fields=fields)
+        extra["fp64_storage"] = {"workload": f"taylor_green_{n}, fp64 populations and arithmetic",
+                                 "kernel": STEP_KERNEL["fp64"], "bytes_per_cell": BYTES_PER_CELL["fp64"],
+                                 "traffic": measured_traffic("fp64"), **r64}
+        log(f"fp64 {r64['glups']:.2f} GLUPS")
+    if "fused" in legs:
+        log(f"fused reductions, TGV {n}^3 fp32")
+        extra["fused_reduce"] = run_fused(n, 20, fields)
+    if "mom" in legs:
+        log(f"TGV {n}^3 moment storage (FP32)")
+        rm = run_gpu(n, "mom32", K, W, R, fields=fields)
+        extra[f"moment_storage_{n}"] = {
+            "workload": f"taylor_green_{n}, nine FP32 numbers per cell (rho - rho0, u, (1 - omega) k4..k8), "
+                        "neighbour populations rebuilt in LDS", "bytes_per_cell": BYTES_PER_CELL["mom32"], **rm}
+        log(f"moment storage {n}^3: {rm['glups']:.2f} GLUPS")
+    del fields
+    torch.cuda.empty_cache()
+    n16 = args.n16
+    if "precision" in legs or ("mom" in legs and n16 != n):
+        f16 = device_fields(n16)
+        if "precision" in legs:
+            names = [s for s in args.precision.split(",") if s]
+            prec = precision_legs(n16, names, K, W, R, args.error_steps, f16)
+            ref32 = prec.get("fp32", {}).get("glups")
+            for name, row in prec.items():
+                if ref32 and name != "fp32" and "glups" in row:
+                    row["speedup_vs_fp32_same_size"] = round(row["glups"] / ref32, 3)
+                if main_run and "glups" in row:
+                    row[f"speedup_vs_fp32_{n}"] = round(row["glups"] / main_run["glups"], 3)
+            extra["precision"] = {
+                "workload": f"taylor_green_{n16} periodic, u0=0.05, Re=1600, seeded 1e-6 density noise; every "
+                            f"configuration from the same initial state; errors after {args.error_steps} steps",
+                **prec}
+            target = prec.get("fp16sr")
+            if target and "speedup_vs_fp32_same_size" in target:
+                e = target["error"].get("rel_l2_u_vs_fp64")
+                extra["fp16_target"] = {
+                    "configuration": "fp16 storage, stochastic rounding",
+                    "speedup_vs_fp32_same_size": target["speedup_vs_fp32_same_size"],
+                    "rel_l2_u_vs_fp64": e, "steps": args.error_steps,
+                    "meets_1.7x_at_1e-3": bool(target["speedup_vs_fp32_same_size"] >= 1.7 and e is not None
+                                               and e <= 1e-3)}
+        if "mom" in legs and n16 != n:
+            log(f"TGV {n16}^3 moment storage (FP32)")
+            rm = run_gpu(n16, "mom32", K, W, R, fields=f16)
+            extra[f"moment_storage_{n16}"] = {"bytes_per_cell": BYTES_PER_CELL["mom32"], **rm}
+            log(f"moment storage {n16}^3: {rm['glups']:.2f} GLUPS")
+        del f16
+        torch.cuda.empty_cache()
+    if "d2q9" in legs:
         n2 = 8192
         res2 = {}
         for st in ("fp32", "fp16", "fp64"):
-            print(f"[bench] D2Q9 four-rolls mill {n2}^2 {st}", file=sys.stderr, flush=True)
-            r2 = run_gpu_2d(n2, st, max(args.steps // 2, 10), max(args.warmup // 2, 5))
-            bw = r2["bytes_per_launch"] / r2["launch_s"] / 1e9
-            res2[st] = {"glups": round(r2["glups"], 3), "ms_per_step": round(r2["ms_per_step"], 4),
-                        "kernel": STEP_KERNEL_2D[st], "bytes_per_cell": BYTES_PER_CELL_2D[st],
-                        "hbm_gbs": round(bw, 1), "hbm_frac": round(bw / HBM_PEAK_GBS, 4),
-                        "mass_drift": r2["mass_drift"]}
-            print(f"[bench] D2Q9 {st} {r2['glups']:.2f} GLUPS", file=sys.stderr, flush=True)
+            log(f"D2Q9 four-rolls mill {n2}^2 {st}")
+            res2[st] = run_gpu_2d(n2, st, K, W, R)
+            log(f"D2Q9 {st} {res2[st]['glups']:.2f} GLUPS")
         extra["d2q9"] = {"workload": f"four_rolls_mill_2d_{n2} (App. B model, Re 100, u0 1e-3, per-cell force field)",
                          **res2}
-    if not args.no_mhd:
-        print("[bench] magnetic lattice 256^3 fp32", file=sys.stderr, flush=True)
-        rmag = run_gpu_mhd(256, max(args.steps // 10, 10), 3)
-        bw = rmag["bytes_per_launch"] / rmag["launch_s"] / 1e9
+    if "mhd" in legs:
+        log("magnetic lattice 256^3 fp32")
+        rmag = run_gpu_mhd(256, K, W, R)
         extra["mhd_magnetic_lattice"] = {
-            "workload": "D3Q7 vector populations (App. C), 256^3 periodic, fp32, fixed velocity field",
-            "kernel": "k_mhd_step<float>", "glups": round(rmag["glups"], 3), "ms_per_step": round(rmag["ms_per_step"], 4),
-            "bytes_per_cell": BYTES_PER_CELL_MHD, "hbm_gbs": round(bw, 1), "hbm_frac": round(bw / HBM_PEAK_GBS, 4)}
-        print(f"[bench] magnetic lattice {rmag['glups']:.2f} GLUPS, {bw:.0f} GB/s", file=sys.stderr, flush=True)
-    print(f"[bench] fused reductions, TGV {args.n}^3 fp32", file=sys.stderr, flush=True)
-    extra["fused_reduce"] = run_fused(args.n, 20)
-    extra["device_copy_gbs"] = round(copy_bandwidth(), 1)  # torch's copy
-    extra["kernel_copy_gbs"] = round(kernel_copy_bandwidth(), 1)  # 16-byte non-temporal copy kernel
-    if not args.no_warmstart:
-        print("[bench] warm start: 64 sphere channels 64x32x32, cold vs U-Net init", file=sys.stderr, flush=True)
+            "workload": "D3Q7 vector populations (App. C), 256^3 periodic, fp32, fixed velocity field", **rmag}
+        log(f"magnetic lattice {rmag['glups']:.2f} GLUPS")
+    if "copy" in legs:
+        from paper_1905_10182_amd.cmlbm import device_copy
+        extra["device_copy_gbs"] = round(copy_bandwidth(lambda b, a: b.copy_(a)), 1)  # torch's copy
+        extra["kernel_copy_gbs"] = round(copy_bandwidth(device_copy), 1)  # 16-byte non-temporal copy kernel
+    if "warmstart" in legs:
+        log("warm start: 64 sphere channels 64x32x32, cold vs U-Net init")
         extra["warm_start"] = warm_start()
-    achieved = main_run["bytes_per_launch"] / main_run["launch_s"] / 1e9
-    traffic = measured_traffic()
     cpu = None
-    if not args.no_cpu:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+    if "cpu" in legs:
+        log("cpu baseline (oracle, taylor_green 256^3)")
         cpu = cpu_baseline()
     out = {
         "metric": "D3Q27 CM-LBM GLUPS & %HBM peak, FP32 vs FP16-store; warm-start speedup",
-        "value": round(main_run["glups"], 4),
+        "value": main_run["glups"] if main_run else None,
         "unit": "GLUPS",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(main_run["ms_per_step"], 5),
+        "steps": K,
+        "warmup": W,
+        "repeats": R,
+        "ms_per_step": main_run["ms_per_step"] if main_run else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"taylor_green_{args.n} periodic, fp32 populations, u0=0.05, Re=1600, "
-                               f"zero force, seeded 1e-6 density noise", "cells": args.n ** 3,
-                   "tau": round(3 * 0.05 * args.n / (2 * math.pi * 1600) + 0.5, 6)},
-        "roofline": {"bound": "hbm", "kernel": STEP_KERNEL["fp32"], "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "bytes_per_cell": BYTES_PER_CELL["fp32"]},
+        "config": {"workload": f"taylor_green_{n} periodic, fp32 populations, u0=0.05, Re=1600, "
+                               f"zero force, seeded 1e-6 density noise", "cells": n ** 3,
+                   "tau": round(3 * 0.05 * n / (2 * math.pi * 1600) + 0.5, 6)},
+        "roofline": None if main_run is None else {
+            "bound": "hbm", "kernel": STEP_KERNEL["fp32"], "achieved": main_run["hbm_gbs"], "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": main_run["hbm_frac"], "traffic": measured_traffic("fp32"),
+            "bytes_per_cell": BYTES_PER_CELL["fp32"], "window_ms_per_step": main_run["window_ms_per_step"],
+            "source_digest": source_digest()},
         "cpu_baseline": cpu,
-        "mass_drift": main_run["mass_drift"],
+        "mass_drift": main_run["mass_drift"] if main_run else None,
     }
     out.update(extra)
     print(json.dumps(out), flush=True)

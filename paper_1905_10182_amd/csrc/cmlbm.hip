@@ -24,6 +24,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "cmlbm.h"
@@ -71,15 +72,21 @@ struct storage<CMLBM_FP32> {
     static __device__ __forceinline__ T load_raw(const S* p) { return *p; }
     static __device__ __forceinline__ S pack_raw(T v) { return v; }
 };
-// 16-bit formats.  pack() rounds to nearest even; pack_sr() rounds
-// stochastically: r8 (8 random bits) is added to the top 8 of the discarded
-// FP32 significand bits, together with half a step of the remaining ones
-// (so the truncation of those is unbiased on average), and the discarded bits
-// are cleared.  The value then rounds away from zero with probability equal
-// to its fractional position (resolved to 1/256 of an ulp): an unbiased
-// rounding.  FP16 values carry a factor 2^8 (h * 256 is
+// 16-bit formats.  pack() rounds to nearest even.  pack_sr_raw() rounds
+// stochastically with gfx950's conversion instructions (v_cvt_sr_f16_f32,
+// v_cvt_sr_bf16_f32): the value goes to the 16-bit neighbour further from
+// zero with probability equal to its fractional position between the two
+// neighbours, the position being compared with the top bits of the 32-bit
+// random operand -- the 13 (FP16) or 16 (BF16) discarded significand bits'
+// worth (checked on the hardware: a value half-way between two neighbours
+// rounds up exactly when bit 31 is set, and over random operands a value at
+// 0.3 / 0.7 of the way rounds up with frequency 0.300 / 0.702).  An unbiased
+// rounding.  pack2_sr_raw() converts two values into one packed pair, each
+// with its own random operand.  FP16 values carry a factor 2^8 (h * 256 is
 // stored) so that even the smallest shifted populations stay in FP16's
-// normal range, where the bit-level rounding above is exact.
+// normal range.
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf162_t __attribute__((ext_vector_type(2)));
 template <>
 struct storage<CMLBM_FP16> {
     typedef _Float16 S;
@@ -87,13 +94,19 @@ struct storage<CMLBM_FP16> {
     static constexpr T kScale = 256;
     static __device__ __forceinline__ T load(const S* p) { return (float)*p * 0.00390625f; }
     static __device__ __forceinline__ S pack(T v) { return (_Float16)(v * 256.0f); }
-    static __device__ __forceinline__ S pack_sr(T v, uint32_t r8) { return pack_sr_raw(v * 256.0f, r8); }
     static __device__ __forceinline__ T load_raw(const S* p) { return (float)*p; }
     static __device__ __forceinline__ S pack_raw(T v) { return (_Float16)v; }
-    static __device__ __forceinline__ S pack_sr_raw(T v, uint32_t r8)
+    static __device__ __forceinline__ S pack_sr_raw(T v, uint32_t rnd)
     {
-        const uint32_t b = (__builtin_bit_cast(uint32_t, v) + (r8 << 5) + 16u) & 0xFFFFE000u;
-        return (_Float16)__builtin_bit_cast(float, b);  // exact: b has an FP16 significand
+        half2_t x = {};
+        x = __builtin_amdgcn_cvt_sr_f16_f32(x, v, rnd, false);
+        return x[0];
+    }
+    static __device__ __forceinline__ half2_t pack2_sr_raw(T a, T b, uint32_t ra, uint32_t rb)
+    {
+        half2_t x = {};
+        x = __builtin_amdgcn_cvt_sr_f16_f32(x, a, ra, false);
+        return __builtin_amdgcn_cvt_sr_f16_f32(x, b, rb, true);
     }
 };
 template <>
@@ -103,14 +116,20 @@ struct storage<CMLBM_BF16> {
     static constexpr T kScale = 1;
     static __device__ __forceinline__ T load(const S* p) { return (float)*p; }
     static __device__ __forceinline__ S pack(T v) { return (__bf16)v; }
-    static __device__ __forceinline__ S pack_sr(T v, uint32_t r8)
-    {
-        const uint32_t b = (__builtin_bit_cast(uint32_t, v) + (r8 << 8) + 128u) & 0xFFFF0000u;
-        return __builtin_bit_cast(__bf16, (unsigned short)(b >> 16));
-    }
     static __device__ __forceinline__ T load_raw(const S* p) { return load(p); }
     static __device__ __forceinline__ S pack_raw(T v) { return pack(v); }
-    static __device__ __forceinline__ S pack_sr_raw(T v, uint32_t r8) { return pack_sr(v, r8); }
+    static __device__ __forceinline__ S pack_sr_raw(T v, uint32_t rnd)
+    {
+        bf162_t x = {};
+        x = __builtin_amdgcn_cvt_sr_bf16_f32(x, v, rnd, false);
+        return x[0];
+    }
+    static __device__ __forceinline__ bf162_t pack2_sr_raw(T a, T b, uint32_t ra, uint32_t rb)
+    {
+        bf162_t x = {};
+        x = __builtin_amdgcn_cvt_sr_bf16_f32(x, a, ra, false);
+        return __builtin_amdgcn_cvt_sr_bf16_f32(x, b, rb, true);
+    }
 };
 
 // moment representation: nine FP32 planes (rho - rho0, u, (1 - omega) k4..k8)
@@ -121,8 +140,13 @@ struct storage<CMLBM_MOM32> {
 };
 
 // Counter-based random bits for stochastic rounding: one hashed 32-bit seed
-// per (cell, step) -- a 32-bit integer finaliser (xor-shift / multiply
-// rounds) -- then an xorshift32 stream, 8 bits per population.
+// per (lane, step) -- a 32-bit integer finaliser (xor-shift / multiply
+// rounds) of the linear index of the lane's first cell and the step -- then an
+// xorshift32 stream of 7 words per cell (sr_words); population i of a cell
+// takes word i / 4 rotated so that its byte i % 4 is on top (sr_operand).
+// The conversion reads the top 13 or 16 bits, so the bits below that byte are
+// the top bits of the word's next-lower byte: two populations of a cell share
+// only the low-order bits of their rounding thresholds.
 __device__ __forceinline__ uint32_t mix32(uint32_t x)
 {
     x ^= x >> 16;
@@ -138,6 +162,24 @@ __device__ __forceinline__ uint32_t xorshift32(uint32_t x)
     x ^= x >> 17;
     x ^= x << 5;
     return x;
+}
+
+template <int V>
+__device__ __forceinline__ void sr_words(uint32_t lin0, uint32_t step, uint32_t rw[V][7])
+{
+    uint32_t w = mix32(lin0 ^ mix32(step * 0x9E3779B9u + 0x632BE5ABu)) | 1u;  // xorshift32 keeps a non-zero state
+#pragma unroll
+    for (int c = 0; c < V; ++c)
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+            w = xorshift32(w);
+            rw[c][k] = w;
+        }
+}
+
+__device__ __forceinline__ uint32_t sr_operand(const uint32_t rw[7], int i)
+{
+    return __builtin_rotateright32(rw[i / 4], (uint32_t)(8 * (i % 4) + 8) & 31u);
 }
 
 size_t storage_bytes(int st) { return st == CMLBM_FP64 ? 8 : (st == CMLBM_FP32 || st == CMLBM_MOM32) ? 4 : 2; }
@@ -208,6 +250,19 @@ __device__ __forceinline__ Pull make_pull(const Geom& g, const Cell& c)
 #pragma unroll
     for (int a = 0; a < 3; ++a) p.xs[a] = (uint32_t)wrap(c.x - (a - 1), g.nx);
     return p;
+}
+
+// A wave-uniform global pointer made opaque to the optimiser: it stays a
+// scalar base of the "saddr + voffset" access form instead of being folded
+// with the per-lane offset into a 64-bit vector address.
+typedef __attribute__((address_space(1))) char gchar;
+template <typename P>
+__device__ __forceinline__ gchar* uniform_ptr(P* p)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (gchar*)(((uint64_t)hi << 32) | lo);
 }
 
 // load of the X at byte_off from base
@@ -292,22 +347,26 @@ __device__ __forceinline__ S lane_shift(S v, bool from_prev)
 // byte offsets below 4 GiB.
 
 template <bool NT, typename X>
-__device__ __forceinline__ void st_off(void* base, uint32_t byte_off, X v)
+__device__ __forceinline__ void st_off(gchar* base, uint32_t byte_off, X v)
 {
-    X* p = (X*)((char*)base + byte_off);
+    gchar* p = base + byte_off;
+    typedef __attribute__((address_space(1))) X gX;
     if constexpr (NT) {
         if constexpr (sizeof(X) == 16) {
             typedef int i4 __attribute__((ext_vector_type(4)));
-            __builtin_nontemporal_store(__builtin_bit_cast(i4, v), (i4*)p);
+            typedef __attribute__((address_space(1))) i4 gi4;
+            __builtin_nontemporal_store(__builtin_bit_cast(i4, v), (gi4*)p);
         } else if constexpr (sizeof(X) == 8) {
-            __builtin_nontemporal_store(__builtin_bit_cast(unsigned long long, v), (unsigned long long*)p);
+            __builtin_nontemporal_store(__builtin_bit_cast(unsigned long long, v),
+                                        (__attribute__((address_space(1))) unsigned long long*)p);
         } else if constexpr (sizeof(X) == 4) {
-            __builtin_nontemporal_store(__builtin_bit_cast(unsigned, v), (unsigned*)p);
+            __builtin_nontemporal_store(__builtin_bit_cast(unsigned, v), (__attribute__((address_space(1))) unsigned*)p);
         } else {
-            __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, v), (unsigned short*)p);
+            __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, v),
+                                        (__attribute__((address_space(1))) unsigned short*)p);
         }
     } else {
-        *p = v;
+        *(gX*)p = v;
     }
 }
 
@@ -344,13 +403,13 @@ __device__ __forceinline__ double wave_max(double v)
 // cell only skip their contributions and stores.  (RED is a template flag of
 // the kernel itself: a shared device function changed the register
 // allocation of the RED = false kernels.)
-template <int ST, int V, bool MASK, bool FIELD, bool NT, int MODEL, bool RED>
+template <int ST, int V, bool MASK, bool FIELD, bool NT, int MODEL, bool RED, bool SR>
 __global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename storage<ST>::S* __restrict__ src,
                                                   typename storage<ST>::S* __restrict__ dst, Geom g, int segs,
                                                   typename storage<ST>::T omega, typename storage<ST>::T rho0,
                                                   const typename storage<ST>::T* __restrict__ ftab,
                                                   const typename storage<ST>::T* __restrict__ field,
-                                                  const uint32_t* __restrict__ mask, int sr, uint32_t step,
+                                                  const uint32_t* __restrict__ mask, uint32_t step,
                                                   double* __restrict__ wpart)
 {
     static_assert(V == 1 || !MASK, "bounce-back masks use one cell per lane");
@@ -359,6 +418,7 @@ __global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename st
     using SS = storage<ST>;
     using S = typename SS::S;
     using T = typename SS::T;
+    static_assert(!SR || sizeof(S) == 2, "stochastic rounding is for 16-bit storage");
     // FP16 stores 256 h: the step computes on that scale, with the force
     // density and rho0 scaled alike, so its loads and stores need no
     // rescaling.  The collision is homogeneous of degree one in (h, F, rho0)
@@ -418,6 +478,9 @@ __global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename st
         const bool next_in_reg = whole || (lane < 63 && x0 + V < g.nx);
         const uint32_t bxm = (uint32_t)(x0 == 0 ? g.nx - 1 : x0 - 1) * (uint32_t)sizeof(S);
         const uint32_t bxp = (uint32_t)(x0 + V >= g.nx ? 0 : x0 + V) * (uint32_t)sizeof(S);
+        // (Unconditional loads -- lanes past the row end reading the row's first
+        // vector -- compile to one burst of 27 loads with fewer instructions, but
+        // measured 2-5% slower at 512^3 than these predicated ones.)
         const uint32_t bx0 = (uint32_t)x0 * (uint32_t)sizeof(S);
         vt v[27];
 #pragma unroll
@@ -513,36 +576,24 @@ __global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename st
         auto store_all = [&]() {
             const uint32_t bst = (uint32_t)x0 * (uint32_t)sizeof(S);
             if constexpr (sizeof(S) == 2) {
-                if (sr) {  // wave-uniform
-                    // stochastic rounding: 7 words of random bits per cell, byte (i % 4) of word i / 4
+                if constexpr (SR) {
                     uint32_t rw[V][7];
-#pragma unroll
-                    for (int c = 0; c < V; ++c) {
-                        const uint32_t lin = (uint32_t)((uint64_t)row * (uint64_t)g.nx + (uint64_t)(x0 + c));
-                        uint32_t w = mix32(lin ^ mix32(step * 0x9E3779B9u + 0x632BE5ABu));
-#pragma unroll
-                        for (int k = 0; k < 7; ++k) {
-                            w = xorshift32(w | 1u);
-                            rw[c][k] = w;
-                        }
-                    }
+                    sr_words<V>((uint32_t)((uint64_t)row * (uint64_t)g.nx + (uint64_t)x0), step, rw);
 #pragma unroll
                     for (int i = 0; i < 27; ++i) {
-                        S* plane_row = dst + (uint64_t)i * g.pstride + own_row;
-                        vt o;
-#pragma unroll
-                        for (int c = 0; c < V; ++c) o[c] = SS::pack_sr_raw(h[c][i], (rw[c][i / 4] >> (8 * (i % 4))) & 0xFFu);
+                        gchar* plane_row = uniform_ptr(dst + (uint64_t)i * g.pstride + own_row);
                         if constexpr (V == 1)
-                            st_off<NT>(plane_row, bst, o[0]);
+                            st_off<NT>(plane_row, bst, SS::pack_sr_raw(h[0][i], sr_operand(rw[0], i)));
                         else
-                            st_off<NT>(plane_row, bst, o);
+                            st_off<NT>(plane_row, bst,
+                                       SS::pack2_sr_raw(h[0][i], h[1][i], sr_operand(rw[0], i), sr_operand(rw[1], i)));
                     }
                     return;
                 }
             }
 #pragma unroll
             for (int i = 0; i < 27; ++i) {
-                S* plane_row = dst + (uint64_t)i * g.pstride + own_row;
+                gchar* plane_row = uniform_ptr(dst + (uint64_t)i * g.pstride + own_row);
                 if constexpr (V == 1) {
                     st_off<NT>(plane_row, bst, SS::pack_raw(h[0][i]));
                 } else {
@@ -591,36 +642,24 @@ __global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename st
     }
     const uint32_t bst = (uint32_t)x0 * (uint32_t)sizeof(S);
     if constexpr (sizeof(S) == 2) {
-        if (sr) {  // wave-uniform
-            // stochastic rounding: 7 words of random bits per cell, byte (i % 4) of word i / 4
+        if constexpr (SR) {
             uint32_t rw[V][7];
-#pragma unroll
-            for (int c = 0; c < V; ++c) {
-                const uint32_t lin = (uint32_t)((uint64_t)row * (uint64_t)g.nx + (uint64_t)(x0 + c));
-                uint32_t w = mix32(lin ^ mix32(step * 0x9E3779B9u + 0x632BE5ABu));
-#pragma unroll
-                for (int k = 0; k < 7; ++k) {
-                    w = xorshift32(w | 1u);
-                    rw[c][k] = w;
-                }
-            }
+            sr_words<V>((uint32_t)((uint64_t)row * (uint64_t)g.nx + (uint64_t)x0), step, rw);
 #pragma unroll
             for (int i = 0; i < 27; ++i) {
-                S* plane_row = dst + (uint64_t)i * g.pstride + own_row;
-                vt o;
-#pragma unroll
-                for (int c = 0; c < V; ++c) o[c] = SS::pack_sr_raw(h[c][i], (rw[c][i / 4] >> (8 * (i % 4))) & 0xFFu);
+                gchar* plane_row = uniform_ptr(dst + (uint64_t)i * g.pstride + own_row);
                 if constexpr (V == 1)
-                    st_off<NT>(plane_row, bst, o[0]);
+                    st_off<NT>(plane_row, bst, SS::pack_sr_raw(h[0][i], sr_operand(rw[0], i)));
                 else
-                    st_off<NT>(plane_row, bst, o);
+                    st_off<NT>(plane_row, bst,
+                               SS::pack2_sr_raw(h[0][i], h[1][i], sr_operand(rw[0], i), sr_operand(rw[1], i)));
             }
             return;
         }
     }
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
-        S* plane_row = dst + (uint64_t)i * g.pstride + own_row;
+        gchar* plane_row = uniform_ptr(dst + (uint64_t)i * g.pstride + own_row);
         if constexpr (V == 1) {
             st_off<NT>(plane_row, bst, SS::pack_raw(h[0][i]));
         } else {
@@ -1443,10 +1482,20 @@ void launch_step_v(cmlbm_lattice* lat, hipStream_t s)
     constexpr int wpb = step_block(ST, MASK) / 64;
     const dim3 grid((unsigned)((waves + wpb - 1) / wpb));
     const T* ftab = (const T*)(lat->scratch + (ST == CMLBM_FP64 ? lat->off_ftab64 : lat->off_ftab32));
-    k_step<ST, V, MASK, FIELD, true, MODEL, false><<<grid, dim3(step_block(ST, MASK)), 0, s>>>(
-        (const typename SS::S*)lat->pop[lat->cur], (typename SS::S*)lat->pop[1 - lat->cur], g, segs,
-        (T)(1.0 / lat->p.tau), (T)lat->p.rho0, ftab, (const T*)lat->field, mask_ptr(lat),
-        (lat->p.flags & CMLBM_FLAG_STOCHASTIC) ? 1 : 0, (uint32_t)lat->t, nullptr);
+    auto go = [&](auto sr) {
+        k_step<ST, V, MASK, FIELD, true, MODEL, false, decltype(sr)::value><<<grid, dim3(step_block(ST, MASK)), 0, s>>>(
+            (const typename SS::S*)lat->pop[lat->cur], (typename SS::S*)lat->pop[1 - lat->cur], g, segs,
+            (T)(1.0 / lat->p.tau), (T)lat->p.rho0, ftab, (const T*)lat->field, mask_ptr(lat), (uint32_t)lat->t,
+            nullptr);
+    };
+    if constexpr (sizeof(typename SS::S) == 2 && MODEL == 0) {
+        if (lat->p.flags & CMLBM_FLAG_STOCHASTIC)
+            go(std::true_type{});
+        else
+            go(std::false_type{});
+    } else {
+        go(std::false_type{});
+    }
 }
 
 template <int ST, int MODEL>
@@ -1526,10 +1575,20 @@ void launch_step_red_v(cmlbm_lattice* lat, hipStream_t s)
     constexpr int wpb = step_block(ST, MASK) / 64;
     const dim3 grid((unsigned)((waves + wpb - 1) / wpb));
     const T* ftab = (const T*)(lat->scratch + (ST == CMLBM_FP64 ? lat->off_ftab64 : lat->off_ftab32));
-    k_step<ST, V, MASK, FIELD, true, 0, true><<<grid, dim3(step_block(ST, MASK)), 0, s>>>(
-        (const typename SS::S*)lat->pop[lat->cur], (typename SS::S*)lat->pop[1 - lat->cur], g, segs,
-        (T)(1.0 / lat->p.tau), (T)lat->p.rho0, ftab, (const T*)lat->field, mask_ptr(lat),
-        (lat->p.flags & CMLBM_FLAG_STOCHASTIC) ? 1 : 0, (uint32_t)lat->t, (double*)(lat->scratch + lat->off_wpart));
+    auto go = [&](auto sr) {
+        k_step<ST, V, MASK, FIELD, true, 0, true, decltype(sr)::value><<<grid, dim3(step_block(ST, MASK)), 0, s>>>(
+            (const typename SS::S*)lat->pop[lat->cur], (typename SS::S*)lat->pop[1 - lat->cur], g, segs,
+            (T)(1.0 / lat->p.tau), (T)lat->p.rho0, ftab, (const T*)lat->field, mask_ptr(lat), (uint32_t)lat->t,
+            (double*)(lat->scratch + lat->off_wpart));
+    };
+    if constexpr (sizeof(typename SS::S) == 2) {
+        if (lat->p.flags & CMLBM_FLAG_STOCHASTIC)
+            go(std::true_type{});
+        else
+            go(std::false_type{});
+    } else {
+        go(std::false_type{});
+    }
 }
 
 template <int ST>
