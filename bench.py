@@ -50,7 +50,7 @@ STEP_KERNEL = {"fp32": "k_step<1, 1, false, false, true, 0, false, false>",
 # committed rocprofv3 counter summaries (FETCH_SIZE, WRITE_SIZE) per step configuration
 COUNTERS_FILE = {k: os.path.join(ROOT, "profiles", f"k_step_{k}_counters.md") for k in STEP_KERNEL}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1905_10182_amd", "csrc", f) for f in ("cmlbm.hip", "d3q27.hpp")]
-ALL_LEGS = ("fp32", "precision", "fp64", "mom", "d2q9", "mhd", "fused", "copy", "warmstart", "cpu")
+ALL_LEGS = ("fp32", "precision", "fp64", "mom", "d2q9", "mhd", "fused", "copy", "conv", "warmstart", "cpu")
 
 
 def log(msg):
@@ -293,6 +293,88 @@ def run_fused(n, calls, fields):
             "reduce_then_step_ms": round(t_sep * 1e3, 4), "ke": float(r[0, 4])}
 
 
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
+
+
+def run_conv(steps, warmup, repeats):
+    """The learned part's kernels: Adam training steps of the warm-start U-Net
+    (batch 16 x 32 x 32 x 64 voxels, forward + masked MSE + backward + Adam, all
+    in libcmnn) on synthetic inputs and targets, and the three convolution
+    kernels alone on one layer of each resolution level, against the dense
+    BF16 MFMA peak."""
+    import numpy as np
+    import torch
+    from paper_1905_10182_amd import cmnn
+    from paper_1905_10182_amd import warmstart as ws
+    from paper_1905_10182_amd.unet import UNet3D
+
+    g = np.random.Generator(np.random.PCG64(2024))
+    nb, batch = 32, 16
+    shape = (nb, ws.NZ, ws.NY, ws.NX)
+    data = {"x": g.uniform(0, 1, (nb, 2) + shape[1:]).astype(np.float32),
+            "y": g.normal(0, 0.1, (nb, ws.NOUT) + shape[1:]).astype(np.float32),
+            "w": (g.uniform(0, 1, shape) > 0.1).astype(np.float32)}
+    net = UNet3D((ws.NZ, ws.NY, ws.NX), out_ch=ws.NOUT, seed=0)
+    tr = ws.Trainer(net, data, batch=batch)
+    for _ in range(warmup):
+        tr.step(1e-4)
+    torch.cuda.synchronize()
+    windows = []
+    for _ in range(repeats):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            tr.step(1e-4)
+        e1.record()
+        torch.cuda.synchronize()
+        windows.append(e0.elapsed_time(e1) / 1e3)
+    secs = statistics.median(windows) / steps
+    flops = 3 * net.flops_per_sample() * batch
+    out = {"workload": f"U-Net training step, batch {batch} x 32 x 32 x 64, {net.nparams_real} parameters, "
+                       "synthetic inputs", "ms_per_step": round(secs * 1e3, 4),
+           "conv_tflops": round(flops / secs / 1e12, 1), "layers": {}}
+    del tr, net, data
+    torch.cuda.empty_cache()
+    dev = "cuda:0"
+    for name, dims, cin, cout in (("level0_32x32", (batch, 32, 32, 64), 32, 32),
+                                  ("level1_64x64", (batch, 16, 16, 32), 64, 64),
+                                  ("level2_64x96", (batch, 8, 8, 16), 64, 96)):
+        geo = cmnn.geom(*dims, periodic=(1, 0, 1))
+        x = torch.randn(dims + (cin,), device=dev).to(torch.bfloat16)
+        dy = torch.randn(dims + (cout,), device=dev).to(torch.bfloat16)
+        wf = (0.05 * torch.randn((27, cout, cin), device=dev)).to(torch.bfloat16)
+        wt = wf.transpose(1, 2).contiguous()
+        y = torch.empty(dims + (cout,), dtype=torch.bfloat16, device=dev)
+        dx = torch.empty(dims + (cin,), dtype=torch.bfloat16, device=dev)
+        dw = torch.empty((27, cout, cin), dtype=torch.float32, device=dev)
+        wsp = torch.empty(cmnn.conv_bwd_weight_workspace(geo, cin, cout) // 4, dtype=torch.float32, device=dev)
+        ops = {"fwd": lambda: cmnn.conv_fwd(geo, x, cin, wf, None, cout, cmnn.ACT_NONE, y),
+               "bwd_data": lambda: cmnn.conv_bwd_data(geo, dy, cout, wt, cin, dx),
+               "bwd_weight": lambda: cmnn.conv_bwd_weight(geo, x, cin, dy, cout, dw, None, wsp)}
+        fl = 2.0 * 27 * cin * cout * int(np.prod(dims))
+        row = {"dims": list(dims), "cin": cin, "cout": cout, "gflop": round(fl / 1e9, 2)}
+        for op, fn in ops.items():
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(repeats):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(20):
+                    fn()
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1) / 1e3 / 20)
+            t = statistics.median(ts)
+            row[op] = {"us": round(t * 1e6, 1), "tflops": round(fl / t / 1e12, 1),
+                       "frac_bf16_peak": round(fl / t / 1e12 / BF16_PEAK_TFLOPS, 4)}
+        out["layers"][name] = row
+        del x, dy, wf, wt, y, dx, dw, wsp
+        torch.cuda.empty_cache()
+    return out
+
+
 def copy_bandwidth(fn):
     """Read + write rate of fn(dst, src) on 4 GiB, median of 10 calls."""
     import torch
@@ -511,6 +593,10 @@ def main():
         from paper_1905_10182_amd.cmlbm import device_copy
         extra["device_copy_gbs"] = round(copy_bandwidth(lambda b, a: b.copy_(a)), 1)  # torch's copy
         extra["kernel_copy_gbs"] = round(copy_bandwidth(device_copy), 1)  # 16-byte non-temporal copy kernel
+    if "conv" in legs:
+        log("U-Net training steps and convolution kernels (libcmnn)")
+        extra["conv"] = run_conv(max(K // 10, 5), max(W // 10, 2), R)
+        log(f"U-Net training step {extra['conv']['ms_per_step']} ms, {extra['conv']['conv_tflops']} TFLOP/s")
     if "warmstart" in legs:
         log("warm start: 64 sphere channels 64x32x32, cold vs U-Net init")
         extra["warm_start"] = warm_start()
