@@ -66,6 +66,21 @@ int cmnn_conv3d_bwd_weight_workspace(const cmnn_geom* g, int32_t cin, int32_t co
 int cmnn_conv3d_bwd_weight(const cmnn_geom* g, const void* x, int32_t cin, const void* dy, int32_t cout, float* dw,
                            float* dbias, void* workspace, size_t workspace_bytes, void* hip_stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving or training loops, harnesses that forbid allocation): the weight
+ * gradient of cmnn_conv3d_bwd_weight, same arguments and results (bitwise:
+ * the same kernels), without a workspace argument.  Its per-chunk partials
+ * live in a fixed device array of the library, 64 MiB per GPU, held until the
+ * process ends; it calls no allocator.  Geometries whose
+ * cmnn_conv3d_bwd_weight_workspace exceeds 64 MiB are rejected with
+ * CMNN_EINVAL before any device work (every brick geometry with cout <= 256 and
+ * cin <= 256 fits).  Every call on one GPU within a process shares that GPU's
+ * array: calls that overlap in time on one GPU (on different streams or from
+ * different threads) race, and the caller must order them.  CMNN_EHIP if the
+ * array's address cannot be obtained on the current device. */
+int cmnn_conv3d_bwd_weight_noalloc(const cmnn_geom* g, const void* x, int32_t cin, const void* dy, int32_t cout,
+                                   float* dw, float* dbias, void* hip_stream);
+
 /* dpre = dy * act'(.) evaluated from the activation output y; n elements. */
 int cmnn_act_bwd(const void* y, const void* dy, void* dpre, size_t n, int32_t act, void* hip_stream);
 

@@ -12,6 +12,7 @@ CALIGN = 32
 ACT_NONE, ACT_LEAKY = 0, 1
 
 EXPORTS = ["cmnn_conv3d_fwd", "cmnn_conv3d_bwd_data", "cmnn_conv3d_bwd_weight_workspace", "cmnn_conv3d_bwd_weight",
+           "cmnn_conv3d_bwd_weight_noalloc",
            "cmnn_act_bwd", "cmnn_pool2_fwd", "cmnn_pool2_bwd", "cmnn_up2_fwd", "cmnn_up2_bwd", "cmnn_concat_fwd",
            "cmnn_concat_bwd", "cmnn_add", "cmnn_channel_mean_workspace", "cmnn_channel_mean", "cmnn_mse_workspace",
            "cmnn_mse", "cmnn_clip_grad_norm_workspace", "cmnn_clip_grad_norm", "cmnn_adam", "cmnn_pack_weights",
@@ -51,6 +52,7 @@ def load_library():
     lib.cmnn_conv3d_bwd_data.argtypes = [G, vp, i32, vp, i32, vp, vp]
     lib.cmnn_conv3d_bwd_weight_workspace.argtypes = [G, i32, i32, ctypes.POINTER(sz)]
     lib.cmnn_conv3d_bwd_weight.argtypes = [G, vp, i32, vp, i32, vp, vp, vp, sz, vp]
+    lib.cmnn_conv3d_bwd_weight_noalloc.argtypes = [G, vp, i32, vp, i32, vp, vp, vp]
     lib.cmnn_act_bwd.argtypes = [vp, vp, vp, sz, i32, vp]
     for f in (lib.cmnn_pool2_fwd, lib.cmnn_pool2_bwd, lib.cmnn_up2_fwd, lib.cmnn_up2_bwd):
         f.argtypes = [G, vp, i32, vp, vp]
@@ -111,6 +113,12 @@ def conv_bwd_weight_workspace(g, cin, cout):
 def conv_bwd_weight(g, x, cin, dy, cout, dw, db, ws):
     _check(load_library().cmnn_conv3d_bwd_weight(ctypes.byref(g), _p(x), cin, _p(dy), cout, _p(dw), _p(db), _p(ws),
                                                  ws.numel() * ws.element_size(), _s()), "conv3d_bwd_weight")
+
+
+def conv_bwd_weight_noalloc(g, x, cin, dy, cout, dw, db):
+    """conv_bwd_weight without a workspace (the library's fixed device scratch)."""
+    _check(load_library().cmnn_conv3d_bwd_weight_noalloc(ctypes.byref(g), _p(x), cin, _p(dy), cout, _p(dw), _p(db),
+                                                         _s()), "conv3d_bwd_weight_noalloc")
 
 
 def act_bwd(y, dy, dpre, act=ACT_LEAKY):

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "cmnn.h"
 
@@ -1193,6 +1194,31 @@ int conv_dispatch(const G& g, const bf16* x, int cin, const bf16* w, const float
     return launched();
 }
 
+// Device scratch of the entry points that allocate nothing: a file-scope
+// array of fixed size, one copy per GPU, found once per device through
+// hipGetSymbolAddress (host code never uses the array's name as an address).
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of `scratch`, looked up on the first call on that device.
+int static_scratch(void** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return CMNN_EHIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return CMNN_EHIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return CMNN_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1275,6 +1301,21 @@ int cmnn_conv3d_bwd_weight(const cmnn_geom* g, const void* x, int32_t cin, const
         if (launched()) return CMNN_EHIP;
     }
     return CMNN_OK;
+}
+
+int cmnn_conv3d_bwd_weight_noalloc(const cmnn_geom* g, const void* x, int32_t cin, const void* dy, int32_t cout,
+                                   float* dw, float* dbias, void* hip_stream)
+{
+    size_t need = 0;
+    if (cmnn_conv3d_bwd_weight_workspace(g, cin, cout, &need) != CMNN_OK) return CMNN_EINVAL;
+    if (need > kStaticScratchBytes) return CMNN_EINVAL;  // beyond the fixed scratch: nothing enqueued
+    if (!x || !dy || !dw || !al16(x) || !al16(dy) || cout > 256) return CMNN_EINVAL;
+    void* ws = nullptr;
+    const int rc = static_scratch(&ws);
+    if (rc != CMNN_OK) return rc;
+    // every partial the kernels read is written first in the same call, so the
+    // previous call's contents need no clearing
+    return cmnn_conv3d_bwd_weight(g, x, cin, dy, cout, dw, dbias, ws, kStaticScratchBytes, hip_stream);
 }
 
 int cmnn_act_bwd(const void* y, const void* dy, void* dpre, size_t n, int32_t act, void* hip_stream)

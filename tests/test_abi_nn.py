@@ -83,6 +83,22 @@ def test_weight_gradient_workspace_and_validation(lib):
         assert call(**kw) == EINVAL, kw
 
 
+def test_weight_gradient_noalloc_validation(lib):
+    """The no-allocation weight gradient refuses, before any device call, a
+    geometry whose workspace exceeds its fixed 64 MiB scratch and invalid
+    pointers or channel counts."""
+    n = ctypes.c_size_t()
+    big = N.geom(4, 3, 5, 4400, periodic=(1, 1, 1))  # generic kernel, 64 chunks of 27 x 160 x 160 partials
+    assert lib.cmnn_conv3d_bwd_weight_workspace(ctypes.byref(big), 160, 160, ctypes.byref(n)) == 0
+    assert n.value > 64 << 20
+    assert lib.cmnn_conv3d_bwd_weight_noalloc(ctypes.byref(big), P, 160, P2, 160, P, NULL, NULL) == EINVAL
+    call = lambda **kw: lib.cmnn_conv3d_bwd_weight_noalloc(g(), kw.get("x", P), 32, kw.get("dy", P2),
+                                                           kw.get("cout", 32), kw.get("dw", P), NULL, NULL)
+    for kw in (dict(x=NULL), dict(dy=NULL), dict(dw=NULL), dict(x=ODD), dict(dy=ODD), dict(cout=288),
+               dict(cout=33)):
+        assert call(**kw) == EINVAL, kw
+
+
 def test_elementwise_validation(lib):
     assert lib.cmnn_act_bwd(P, P, NULL, 64, 1, NULL) == EINVAL
     assert lib.cmnn_act_bwd(P, P, P, 64, 3, NULL) == EINVAL
