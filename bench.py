@@ -47,8 +47,8 @@ STEP_KERNEL = {"fp32": "k_step<1, 1, false, false, true, 0, false, false>",
                "bf16": "k_step<3, 2, false, false, true, 0, false, false>",
                "bf16sr": "k_step<3, 2, false, false, true, 0, false, true>",
                "fp64": "k_step<0, 1, false, false, true, 0, false, false>"}
-# committed rocprofv3 counter summaries (FETCH_SIZE, WRITE_SIZE) per step configuration
-COUNTERS_FILE = {k: os.path.join(ROOT, "profiles", f"k_step_{k}_counters.md") for k in STEP_KERNEL}
+# committed rocprofv3 counter summary (FETCH_SIZE, WRITE_SIZE) of every step configuration
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_step_counters.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1905_10182_amd", "csrc", f) for f in ("cmlbm.hip", "d3q27.hpp")]
 ALL_LEGS = ("fp32", "precision", "fp64", "mom", "d2q9", "mhd", "fused", "copy", "conv", "warmstart", "cpu")
 
@@ -69,12 +69,11 @@ def measured_traffic(key):
     """HBM bytes per launch of the step configuration `key` from its committed
     rocprofv3 counter summary, or None if there is none or the kernel sources
     changed since it was taken."""
-    path = COUNTERS_FILE.get(key)
-    if not path or not os.path.exists(path):
+    if not os.path.exists(COUNTERS_FILE):
         return None
-    text = open(path).read()
+    text = open(COUNTERS_FILE).read()
     m = re.search(r"source_digest:\s*([0-9a-f]+)", text)
-    t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    t = re.search(r"hbm_bytes_per_launch\[" + re.escape(key) + r"\]:\s*([0-9.eE+]+)", text)
     if not m or not t or m.group(1) != source_digest():
         return None
     return float(t.group(1))
