@@ -394,6 +394,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(G g, const bf16* __restrict_
 // blocks.  The dy fragments of a K step are read once and serve all of them.
 
 constexpr int kDyStride = 256 + 8;        // bf16 per co row of staged dy
+constexpr int kSkew = 8;                  // bf16 shift of each group of 8 channel rows (one 16-byte slot)
 constexpr int kXRow = 24;                 // bf16 per staged halo row (18 used)
 constexpr int kXStride = 36 * kXRow + 8;  // bf16 per ci row of staged x
 constexpr int kXTasks = 36 * 3 * 4;       // (halo row, octet, channel group) blocks of x
@@ -410,7 +411,8 @@ __device__ __forceinline__ void transpose8x8(const u4 (&in)[8], u4 (&out)[8])
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const unsigned a = in[2 * j][k], b = in[2 * j + 1][k];
-            o[j] = hi ? ((a >> 16) | (b & 0xffff0000u)) : ((a & 0xffffu) | (b << 16));
+            // one byte permute: (a >> 16) | (b & 0xffff0000) or (a & 0xffff) | (b << 16)
+            o[j] = __builtin_amdgcn_perm(b, a, hi ? 0x07060302u : 0x05040100u);
         }
         out[c] = u4{o[0], o[1], o[2], o[3]};
     }
@@ -419,10 +421,10 @@ __device__ __forceinline__ void transpose8x8(const u4 (&in)[8], u4 (&out)[8])
 __global__ __launch_bounds__(kBwThreads) void k_conv_bwd_w_tile(G g, const bf16* __restrict__ x, int cin,
                                                                 const bf16* __restrict__ dy, int cout,
                                                                 int bricks_per_chunk, float* __restrict__ part,
-                                                                float* __restrict__ bpart)
+                                                                long long pstride, bool bias)
 {
-    __shared__ __attribute__((aligned(16))) bf16 sdy2[2][32 * kDyStride];
-    __shared__ __attribute__((aligned(16))) bf16 sx2[2][32 * kXStride];
+    __shared__ __attribute__((aligned(16))) bf16 sdy2[2][32 * kDyStride + 3 * kSkew];
+    __shared__ __attribute__((aligned(16))) bf16 sx2[2][32 * kXStride + 3 * kSkew];
     __shared__ float sbias[kBwThreads];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ct = cout / 32, it = cin / 32;
@@ -433,7 +435,7 @@ __global__ __launch_bounds__(kBwThreads) void k_conv_bwd_w_tile(G g, const bf16*
     const int ch = bid / ct;
     // bias gradient (column sums of dy) from the staged dy, by the ci-tile-0 workgroups:
     // thread (co = tid / 16, segment tid % 16) sums 16 voxels of each brick
-    const bool do_bias = bpart != nullptr && cit == 0;
+    const bool do_bias = bias && cit == 0;
     float bsum = 0.f;
     const int nbw = g.w / kTW, nbh = g.h / kTH, nbd = g.d / kTD;
     const long long nbricks = (long long)g.n * nbd * nbh * nbw;
@@ -444,33 +446,54 @@ __global__ __launch_bounds__(kBwThreads) void k_conv_bwd_w_tile(G g, const bf16*
     const int xcg = tid & 3, xoct = (tid >> 2) % 3, xhr = tid / 12;
     const int dyt = tid - (kBwThreads - kDyTasks), dcg = dyt & 3, drow = (dyt >> 2) >> 1, dxo = ((dyt >> 2) & 1) * 8;
     u4 xin[8], dyin[8];
-    auto load = [&](long long br) {
-        long long r = br;
-        const int x0 = (int)(r % nbw) * kTW;
+    // coordinates of the next brick to load (bricks are loaded in order b0, b0 + 1, ...),
+    // advanced brick by brick without divisions
+    int lx0, lh0, ld0, ln;
+    {
+        int r = (int)b0;
+        lx0 = (r % nbw) * kTW;
         r /= nbw;
-        const int h0 = (int)(r % nbh) * kTH;
+        lh0 = (r % nbh) * kTH;
         r /= nbh;
-        const int d0 = (int)(r % nbd) * kTD;
-        const long long n = r / nbd;
+        ld0 = (r % nbd) * kTD;
+        ln = r / nbd;
+    }
+    const int xdz = xhr / 6 - 1, xdy = xhr % 6 - 1;         // this thread's halo row offsets
+    const int xcoff = cit * 32 + xcg * 8, dyoff = cot * 32 + dcg * 8;
+    auto load = [&]() {
+        const int x0 = lx0, h0 = lh0, d0 = ld0, n = ln;
+        lx0 += kTW;
+        if (lx0 == g.w) {
+            lx0 = 0;
+            lh0 += kTH;
+            if (lh0 == g.h) {
+                lh0 = 0;
+                ld0 += kTD;
+                if (ld0 == g.d) {
+                    ld0 = 0;
+                    ++ln;
+                }
+            }
+        }
         if (has_x) {
             int sd = 0, sh = 0;
-            const bool rok = shift_axis(d0, xhr / 6 - 1, g.d, g.per[0], sd) &&
-                             shift_axis(h0, xhr % 6 - 1, g.h, g.per[1], sh);
-            const long long rowbase = ((n * g.d + sd) * g.h + sh) * g.w;
+            const bool rok = shift_axis(d0, xdz, g.d, g.per[0], sd) && shift_axis(h0, xdy, g.h, g.per[1], sh);
+            // 32-bit element offsets from the tensor base (the host keeps x below 4 GiB)
+            const uint32_t xrow = (uint32_t)(((n * g.d + sd) * g.h + sh) * g.w) * (uint32_t)cin + (uint32_t)xcoff;
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const int pos = xoct * 8 + i;  // halo position: x = x0 - 1 + pos
                 int sw = 0;
                 xin[i] = u4{0u, 0u, 0u, 0u};
                 if (rok && pos < kTW + 2 && shift_axis(x0, pos - 1, g.w, g.per[2], sw))
-                    xin[i] = *(const u4*)(x + (rowbase + sw) * cin + cit * 32 + xcg * 8);
+                    xin[i] = *(const u4*)((const char*)x + 2u * (xrow + (uint32_t)sw * (uint32_t)cin));
             }
         }
         if (has_dy) {
-            const long long v = ((n * g.d + d0 + (drow >> 2)) * g.h + h0 + (drow & 3)) * g.w + x0 + dxo;
-            const bf16* src = dy + v * cout + cot * 32 + dcg * 8;
+            const int v = ((n * g.d + d0 + (drow >> 2)) * g.h + h0 + (drow & 3)) * g.w + x0 + dxo;
+            const uint32_t src = (uint32_t)v * (uint32_t)cout + (uint32_t)dyoff;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) dyin[i] = *(const u4*)(src + (long long)i * cout);
+            for (int i = 0; i < 8; ++i) dyin[i] = *(const u4*)((const char*)dy + 2u * (src + (uint32_t)(i * cout)));
         }
     };
     auto store = [&](int buf) {
@@ -480,12 +503,12 @@ __global__ __launch_bounds__(kBwThreads) void k_conv_bwd_w_tile(G g, const bf16*
         if (has_x) {
             transpose8x8(xin, out);
 #pragma unroll
-            for (int c = 0; c < 8; ++c) *(u4*)&sx[(xcg * 8 + c) * kXStride + xhr * kXRow + xoct * 8] = out[c];
+            for (int c = 0; c < 8; ++c) *(u4*)&sx[(xcg * 8 + c) * kXStride + xcg * kSkew + xhr * kXRow + xoct * 8] = out[c];
         }
         if (has_dy) {
             transpose8x8(dyin, out);
 #pragma unroll
-            for (int c = 0; c < 8; ++c) *(u4*)&sdy[(dcg * 8 + c) * kDyStride + drow * 16 + dxo] = out[c];
+            for (int c = 0; c < 8; ++c) *(u4*)&sdy[(dcg * 8 + c) * kDyStride + dcg * kSkew + drow * 16 + dxo] = out[c];
         }
     };
     // work units: (tap group g = (dz, dy), ci block ib), 18 of them; wave w
@@ -502,9 +525,9 @@ __global__ __launch_bounds__(kBwThreads) void k_conv_bwd_w_tile(G g, const bf16*
     // two LDS buffers: brick br + 1 is stored while brick br's MFMAs run in
     // other waves; one barrier per brick
     if (b0 < b1) {
-        load(b0);
+        load();
         store(0);
-        if (b0 + 1 < b1) load(b0 + 1);
+        if (b0 + 1 < b1) load();
     }
     __syncthreads();
     int cur = 0;
@@ -512,7 +535,7 @@ __global__ __launch_bounds__(kBwThreads) void k_conv_bwd_w_tile(G g, const bf16*
         const bf16* sdy = sdy2[cur];
         const bf16* sx = sx2[cur];
         if (do_bias) {
-            const bf16* q = &sdy[(tid >> 4) * kDyStride + (tid & 15) * 16];
+            const bf16* q = &sdy[(tid >> 4) * kDyStride + (tid >> 7) * kSkew + (tid & 15) * 16];
 #pragma unroll
             for (int k = 0; k < 16; ++k) bsum += (float)q[k];
         }
@@ -522,7 +545,8 @@ __global__ __launch_bounds__(kBwThreads) void k_conv_bwd_w_tile(G g, const bf16*
             const int row = ks * 2 + (j >> 1), xo = (j & 1) * 8;
             bf16x8 a[2];
 #pragma unroll
-            for (int cb = 0; cb < 2; ++cb) a[cb] = *(const bf16x8*)&sdy[(cb * 16 + l16) * kDyStride + row * 16 + xo];
+            for (int cb = 0; cb < 2; ++cb)
+                a[cb] = *(const bf16x8*)&sdy[(cb * 16 + l16) * kDyStride + (cb * 2 + (l16 >> 3)) * kSkew + row * 16 + xo];
             const int dd = row >> 2, hh = row & 3;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
@@ -531,9 +555,12 @@ __global__ __launch_bounds__(kBwThreads) void k_conv_bwd_w_tile(G g, const bf16*
                     const int g = u >> 1, ib = u & 1;
                     const int dz = g / 3 - 1, dyy = g % 3 - 1;
                     const int hr = (dd + 1 + dz) * 6 + hh + 1 + dyy;
-                    const bf16* q = &sx[(ib * 16 + l16) * kXStride + hr * kXRow + xo];
-                    const u4 lo = *(const u4*)q;
-                    const unsigned hi = *(const unsigned*)(q + 8);
+                    const bf16* q = &sx[(ib * 16 + l16) * kXStride + (ib * 2 + (l16 >> 3)) * kSkew + hr * kXRow + xo];
+                    u4 lo = *(const u4*)q;
+                    unsigned hi = *(const unsigned*)(q + 8);
+                    // opaque to the optimiser: the third tap's window is then built from
+                    // these registers instead of being re-read from LDS as an unaligned load
+                    asm("" : "+v"(lo), "+v"(hi));
                     // x taps cx = 0, 1, 2 start 0, 1, 2 elements into the read
                     const u4 f[3] = {lo,
                                      u4{__builtin_amdgcn_alignbyte(lo[1], lo[0], 2), __builtin_amdgcn_alignbyte(lo[2], lo[1], 2),
@@ -551,7 +578,7 @@ __global__ __launch_bounds__(kBwThreads) void k_conv_bwd_w_tile(G g, const bf16*
         }
         if (br + 1 < b1) {
             store(cur ^ 1);
-            if (br + 2 < b1) load(br + 2);
+            if (br + 2 < b1) load();
         }
         __syncthreads();
         cur ^= 1;
@@ -563,7 +590,7 @@ __global__ __launch_bounds__(kBwThreads) void k_conv_bwd_w_tile(G g, const bf16*
             float b = 0.f;
 #pragma unroll
             for (int k = 0; k < 16; ++k) b += sbias[tid * 16 + k];
-            bpart[(long long)ch * cout + cot * 32 + tid] = b;
+            part[(long long)ch * pstride + 27LL * cin * cout + cot * 32 + tid] = b;
         }
     }
     // D[co][ci]: row (lane / 16) * 4 + i, column lane % 16
@@ -575,7 +602,7 @@ __global__ __launch_bounds__(kBwThreads) void k_conv_bwd_w_tile(G g, const bf16*
 #pragma unroll
         for (int cx = 0; cx < 3; ++cx) {
             const int t = g * 3 + cx;
-            float* p = part + (((long long)ch * 27 + t) * cout) * cin;
+            float* p = part + (long long)ch * pstride + ((long long)t * cout) * cin;
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
@@ -588,21 +615,33 @@ __global__ __launch_bounds__(kBwThreads) void k_conv_bwd_w_tile(G g, const bf16*
     }
 }
 
-// out[e] = sum over chunks of part[chunk][e], in a fixed order: wave s of a
-// workgroup sums chunks s, s + 4, s + 8, ... for 64 consecutive elements, then
-// the four wave sums are added in order.
-__global__ __launch_bounds__(256) void k_sum_chunks(const float* __restrict__ part, long long per, int nchunk,
-                                                    float* __restrict__ out)
+// Element e of the chunk sums, e < n0 + n1: out0[e] (e < n0) or out1[e - n0]
+// = sum over chunks c of part[c * pstride + e], in a fixed order: wave s of a
+// workgroup of W waves sums chunks s, s + W, s + 2 W, ... for 64 consecutive
+// elements, then the wave sums are added in wave order.  The sum is bound by
+// the latency of its loads: 16 waves pay off from about 128 chunks.
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_sum_chunks(const float* __restrict__ part, long long pstride, long long n0,
+                                                       long long n1, int nchunk, float* __restrict__ out0,
+                                                       float* __restrict__ out1)
 {
-    __shared__ float sh[4][64];
+    __shared__ float sh[W][64];
     const int e = threadIdx.x & 63, sl = threadIdx.x >> 6;
     const long long i = (long long)blockIdx.x * 64 + e;
+    const long long n = n0 + n1;
     float acc = 0.f;
-    if (i < per)
-        for (int c = sl; c < nchunk; c += 4) acc += part[(long long)c * per + i];
+    if (i < n)
+        for (int c = sl; c < nchunk; c += W) acc += part[(long long)c * pstride + i];
     sh[sl][e] = acc;
     __syncthreads();
-    if (sl == 0 && i < per) out[i] = ((sh[0][e] + sh[1][e]) + sh[2][e]) + sh[3][e];
+    if (sl == 0 && i < n) {
+        float v = sh[0][e];
+        for (int k = 1; k < W; ++k) v += sh[k][e];
+        if (i < n0)
+            out0[i] = v;
+        else
+            out1[i - n0] = v;
+    }
 }
 
 // Per-chunk column sums of a [rows][cols] BF16 matrix (cols <= 256): thread t
@@ -1137,6 +1176,17 @@ constexpr int kMeanParts = 64;
 
 int launched() { return hipGetLastError() == hipSuccess ? CMNN_OK : CMNN_EHIP; }
 
+int sum_chunks(const float* part, long long pstride, long long n0, long long n1, int nchunk, float* out0, float* out1,
+               hipStream_t s)
+{
+    const unsigned nblk = (unsigned)((n0 + n1 + 63) / 64);
+    if (nchunk >= 128)
+        k_sum_chunks<16><<<nblk, 1024, 0, s>>>(part, pstride, n0, n1, nchunk, out0, out1);
+    else
+        k_sum_chunks<8><<<nblk, 512, 0, s>>>(part, pstride, n0, n1, nchunk, out0, out1);
+    return launched();
+}
+
 dim3 grid_for(long long n)
 {
     long long b = (n + 255) / 256;
@@ -1146,13 +1196,18 @@ dim3 grid_for(long long n)
 }
 
 bool brick_ok(const G& g) { return g.d % kTD == 0 && g.h % kTH == 0 && g.w % kTW == 0; }
+// The brick weight-gradient kernel addresses x and dy with 32-bit byte offsets.
+bool bwd_w_brick(const G& g, int cin, int cout)
+{
+    return brick_ok(g) && g.nvox * 2LL * (cin > cout ? cin : cout) < (1LL << 32);
+}
 
 // Voxel chunks of the weight gradient (partials summed in a fixed order).
 // Brick path: about 256 workgroups of 8 waves (one per CU), whole bricks
 // per chunk.  Generic path: >= 4096 voxels per chunk.
 int bwd_w_chunks(const G& g, int cin, int cout)
 {
-    if (brick_ok(g)) {
+    if (bwd_w_brick(g, cin, cout)) {
         const long long bricks = g.nvox / (kTD * kTH * kTW);
         const long long tiles = (long long)(cin / 32) * (cout / 32);
         long long c = (256 + tiles - 1) / tiles;
@@ -1269,36 +1324,32 @@ int cmnn_conv3d_bwd_weight(const cmnn_geom* g, const void* x, int32_t cin, const
     float* part = (float*)workspace;
     const long long per = 27LL * cin * cout;
     float* bpart = part + (long long)nc * per;
-    if (brick_ok(gg)) {
+    if (bwd_w_brick(gg, cin, cout)) {
         const long long bricks = gg.nvox / (kTD * kTH * kTW);
         const int per_chunk = (int)((bricks + nc - 1) / nc);
         const unsigned nblk = (unsigned)(nc * (cout / 32) * (cin / 32));
+        // per chunk: the 27 x cout x cin weight partials, then the cout bias partials,
+        // summed over the chunks by one launch; nc <= 256 <= kColSumBlocks, so the
+        // nc * (per + cout) floats fit the workspace
+        const long long pst = per + cout, nb = dbias ? cout : 0;
         k_conv_bwd_w_tile<<<nblk, kBwThreads, 0, s>>>(gg, (const bf16*)x, cin, (const bf16*)dy, cout, per_chunk, part,
-                                               dbias ? bpart : nullptr);
+                                                      pst, dbias != nullptr);
         if (launched()) return CMNN_EHIP;
-        k_sum_chunks<<<(unsigned)((per + 63) / 64), 256, 0, s>>>(part, per, nc, dw);
-        if (launched()) return CMNN_EHIP;
-        if (dbias) {
-            k_sum_chunks<<<(unsigned)((cout + 63) / 64), 256, 0, s>>>(bpart, cout, nc, dbias);
-            if (launched()) return CMNN_EHIP;
-        }
-        return CMNN_OK;
+        return sum_chunks(part, pst, per, nb, nc, dw, dbias, s);
     } else {
         const long long chunk = (gg.nvox + nc - 1) / nc;
         const unsigned nblk = (unsigned)(nc * 27 * (cout / 32) * (cin / 32));
         k_conv_bwd_w<<<nblk, 256, 0, s>>>(gg, (const bf16*)x, cin, (const bf16*)dy, cout, chunk, part);
     }
     if (launched()) return CMNN_EHIP;
-    k_sum_chunks<<<(unsigned)((per + 63) / 64), 256, 0, s>>>(part, per, nc, dw);
-    if (launched()) return CMNN_EHIP;
+    if (sum_chunks(part, per, per, 0, nc, dw, nullptr, s)) return CMNN_EHIP;
     if (dbias) {
         long long nb = (gg.nvox + 1023) / 1024;
         if (nb > kColSumBlocks) nb = kColSumBlocks;
         const long long bchunk = (gg.nvox + nb - 1) / nb;
         k_colsum_part<<<(unsigned)nb, 256, 0, s>>>((const bf16*)dy, gg.nvox, cout, bchunk, bpart);
         if (launched()) return CMNN_EHIP;
-        k_sum_chunks<<<(unsigned)((cout + 63) / 64), 256, 0, s>>>(bpart, cout, (int)nb, dbias);
-        if (launched()) return CMNN_EHIP;
+        if (sum_chunks(bpart, cout, cout, 0, (int)nb, dbias, nullptr, s)) return CMNN_EHIP;
     }
     return CMNN_OK;
 }
