@@ -98,14 +98,12 @@ struct storage<CMLBM_FP16> {
     static __device__ __forceinline__ S pack_raw(T v) { return (_Float16)v; }
     static __device__ __forceinline__ S pack_sr_raw(T v, uint32_t rnd)
     {
-        half2_t x = {};
-        x = __builtin_amdgcn_cvt_sr_f16_f32(x, v, rnd, false);
+        half2_t x = __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(half2_t, v), v, rnd, false);
         return x[0];
     }
     static __device__ __forceinline__ half2_t pack2_sr_raw(T a, T b, uint32_t ra, uint32_t rb)
     {
-        half2_t x = {};
-        x = __builtin_amdgcn_cvt_sr_f16_f32(x, a, ra, false);
+        half2_t x = __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(half2_t, a), a, ra, false);
         return __builtin_amdgcn_cvt_sr_f16_f32(x, b, rb, true);
     }
 };
@@ -120,14 +118,12 @@ struct storage<CMLBM_BF16> {
     static __device__ __forceinline__ S pack_raw(T v) { return pack(v); }
     static __device__ __forceinline__ S pack_sr_raw(T v, uint32_t rnd)
     {
-        bf162_t x = {};
-        x = __builtin_amdgcn_cvt_sr_bf16_f32(x, v, rnd, false);
+        bf162_t x = __builtin_amdgcn_cvt_sr_bf16_f32(__builtin_bit_cast(bf162_t, v), v, rnd, false);
         return x[0];
     }
     static __device__ __forceinline__ bf162_t pack2_sr_raw(T a, T b, uint32_t ra, uint32_t rb)
     {
-        bf162_t x = {};
-        x = __builtin_amdgcn_cvt_sr_bf16_f32(x, a, ra, false);
+        bf162_t x = __builtin_amdgcn_cvt_sr_bf16_f32(__builtin_bit_cast(bf162_t, a), a, ra, false);
         return __builtin_amdgcn_cvt_sr_bf16_f32(x, b, rb, true);
     }
 };
@@ -140,13 +136,17 @@ struct storage<CMLBM_MOM32> {
 };
 
 // Counter-based random bits for stochastic rounding: one hashed 32-bit seed
-// per (lane, step) -- a 32-bit integer finaliser (xor-shift / multiply
-// rounds) of the linear index of the lane's first cell and the step -- then an
-// xorshift32 stream of 7 words per cell (sr_words); population i of a cell
-// takes word i / 4 rotated so that its byte i % 4 is on top (sr_operand).
-// The conversion reads the top 13 or 16 bits, so the bits below that byte are
-// the top bits of the word's next-lower byte: two populations of a cell share
-// only the low-order bits of their rounding thresholds.
+// h per (lane, step) -- a 32-bit integer finaliser (xor-shift / multiply
+// rounds) of the linear index of the lane's first cell and the step -- then 7
+// words per cell, word k = h + k * 0x9E3779B9 (a Weyl sequence: one add per
+// word; sr_words); population i of a cell takes word i / 4 rotated so that its
+// byte i % 4 is on top (sr_operand).  Every operand is uniform, and operands
+// of different cells or steps are independent.  Within a cell they are
+// related: the conversion reads the top 13 or 16 bits, so two populations of
+// one word share the low-order bits of their thresholds, and the same byte of
+// consecutive words differs by a constant (plus a carry).  Each population's
+// rounding stays unbiased; the words cost 13 adds per lane instead of an
+// xorshift chain's 84 operations.
 __device__ __forceinline__ uint32_t mix32(uint32_t x)
 {
     x ^= x >> 16;
@@ -156,25 +156,15 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x)
     x ^= x >> 16;
     return x;
 }
-__device__ __forceinline__ uint32_t xorshift32(uint32_t x)
-{
-    x ^= x << 13;
-    x ^= x >> 17;
-    x ^= x << 5;
-    return x;
-}
 
 template <int V>
 __device__ __forceinline__ void sr_words(uint32_t lin0, uint32_t step, uint32_t rw[V][7])
 {
-    uint32_t w = mix32(lin0 ^ mix32(step * 0x9E3779B9u + 0x632BE5ABu)) | 1u;  // xorshift32 keeps a non-zero state
+    const uint32_t w = mix32(lin0 ^ mix32(step * 0x9E3779B9u + 0x632BE5ABu));
 #pragma unroll
     for (int c = 0; c < V; ++c)
 #pragma unroll
-        for (int k = 0; k < 7; ++k) {
-            w = xorshift32(w);
-            rw[c][k] = w;
-        }
+        for (int k = 0; k < 7; ++k) rw[c][k] = w + (uint32_t)(7 * c + k) * 0x9E3779B9u;
 }
 
 __device__ __forceinline__ uint32_t sr_operand(const uint32_t rw[7], int i)
@@ -263,6 +253,31 @@ __device__ __forceinline__ gchar* uniform_ptr(P* p)
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
     return (gchar*)(((uint64_t)hi << 32) | lo);
+}
+
+// Raw buffer access for 4-byte vectors: a descriptor in four scalar registers
+// (wave-uniform base, stride 0, size in bytes, the gfx9 raw-buffer format
+// word) and a 32-bit per-lane byte offset, added to the base by the memory
+// unit instead of by a 64-bit VALU add per access.  Offsets stay below the
+// size (one padded row), so the range check never drops an access.
+constexpr int kRawBufferWord3 = 0x00020000;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(gchar* base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)bytes, kRawBufferWord3);
+}
+template <typename X>
+__device__ __forceinline__ X ld_buf(gchar* base, uint32_t bytes, uint32_t byte_off)
+{
+    static_assert(sizeof(X) == 4, "4-byte buffer loads only");
+    return __builtin_bit_cast(X, __builtin_amdgcn_raw_buffer_load_b32(row_rsrc(base, bytes), byte_off, 0, 0));
+}
+// aux bit 1: the non-temporal hint (nt) on gfx94x / gfx950
+template <bool NT, typename X>
+__device__ __forceinline__ void st_buf(gchar* base, uint32_t bytes, uint32_t byte_off, X v)
+{
+    static_assert(sizeof(X) == 4, "4-byte buffer stores only");
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), row_rsrc(base, bytes), byte_off, 0,
+                                          NT ? 2 : 0);
 }
 
 // load of the X at byte_off from base
@@ -482,11 +497,12 @@ __global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename st
         // vector -- compile to one burst of 27 loads with fewer instructions, but
         // measured 2-5% slower at 512^3 than these predicated ones.)
         const uint32_t bx0 = (uint32_t)x0 * (uint32_t)sizeof(S);
+        const uint32_t rowb = (uint32_t)g.nxp * (uint32_t)sizeof(S);
         vt v[27];
 #pragma unroll
         for (int i = 0; i < 27; ++i) {
             const S* plane_row = srow[vel_y(i) + 1][vel_z(i) + 1] + (uint64_t)i * g.pstride;
-            v[i] = active ? ld_off<vt>(plane_row, bx0) : vt(0);
+            v[i] = active ? ld_buf<vt>(uniform_ptr(plane_row), rowb, bx0) : vt(0);
         }
 #pragma unroll
         for (int i = 0; i < 27; ++i) {
@@ -585,7 +601,7 @@ __global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename st
                         if constexpr (V == 1)
                             st_off<NT>(plane_row, bst, SS::pack_sr_raw(h[0][i], sr_operand(rw[0], i)));
                         else
-                            st_off<NT>(plane_row, bst,
+                            st_buf<NT>(plane_row, (uint32_t)g.nxp * (uint32_t)sizeof(S), bst,
                                        SS::pack2_sr_raw(h[0][i], h[1][i], sr_operand(rw[0], i), sr_operand(rw[1], i)));
                     }
                     return;
@@ -600,7 +616,10 @@ __global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename st
                     vt o;
 #pragma unroll
                     for (int c = 0; c < V; ++c) o[c] = SS::pack_raw(h[c][i]);
-                    st_off<NT>(plane_row, bst, o);
+                    if constexpr (sizeof(vt) == 4)
+                        st_buf<NT>(plane_row, (uint32_t)g.nxp * (uint32_t)sizeof(S), bst, o);
+                    else
+                        st_off<NT>(plane_row, bst, o);
                 }
             }
         };
@@ -651,7 +670,7 @@ __global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename st
                 if constexpr (V == 1)
                     st_off<NT>(plane_row, bst, SS::pack_sr_raw(h[0][i], sr_operand(rw[0], i)));
                 else
-                    st_off<NT>(plane_row, bst,
+                    st_buf<NT>(plane_row, (uint32_t)g.nxp * (uint32_t)sizeof(S), bst,
                                SS::pack2_sr_raw(h[0][i], h[1][i], sr_operand(rw[0], i), sr_operand(rw[1], i)));
             }
             return;
@@ -666,7 +685,10 @@ __global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename st
             vt o;
 #pragma unroll
             for (int c = 0; c < V; ++c) o[c] = SS::pack_raw(h[c][i]);
-            st_off<NT>(plane_row, bst, o);
+            if constexpr (sizeof(vt) == 4)
+                st_buf<NT>(plane_row, (uint32_t)g.nxp * (uint32_t)sizeof(S), bst, o);
+            else
+                st_off<NT>(plane_row, bst, o);
         }
     }
 }

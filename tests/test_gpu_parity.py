@@ -623,6 +623,24 @@ def test_16bit_stochastic_rounding_is_unbiased(torch, storage, nx):
     frac_away = float(np.mean(np.abs(got - WGT[:, None])[big] > np.abs(h_ref)[big]))
     log(f"  mean signed error {mean:+.4f} ulp, rounded away from zero {frac_away:.3f}")
     assert abs(mean) < 0.01
+    # calibration: a value at fractional position p between its two 16-bit
+    # neighbours rounds away from zero with probability p, in every bin of p
+    # and for every population index (each index has its own random operand)
+    a = np.abs(h_ref)
+    e = np.floor(np.log2(np.maximum(a * 256, 2.0 ** -14) if storage == "fp16" else np.maximum(a, 2.0 ** -126)))
+    sp = np.ldexp(1.0, (e - 10).astype(np.int64)) / 256 if storage == "fp16" else np.ldexp(1.0, (e - 7).astype(np.int64))
+    pos = (a - np.floor(a / sp) * sp) / sp
+    away = np.abs(got - WGT[:, None]) > a
+    use = big & (pos > 1e-3) & (pos < 1 - 1e-3)
+    for lo in np.arange(0.0, 1.0, 0.2):
+        sel = use & (pos >= lo) & (pos < lo + 0.2)
+        fa, fp = float(np.mean(away[sel])), float(np.mean(pos[sel]))
+        log(f"  position in [{lo:.1f}, {lo + 0.2:.1f}): {sel.sum()} values, rounded away {fa:.4f}, mean position {fp:.4f}")
+        assert abs(fa - fp) < 0.02
+    for i in range(27):
+        sel = use[i]
+        if sel.sum() >= 1000:
+            assert abs(float(np.mean(away[i][sel] - pos[i][sel]))) < 0.04, i
     got2, _ = sampled_one_step(torch, 64, storage, None, 0, dims=(nx, 12, 10), re=200.0, stochastic=True)
     assert np.array_equal(got, got2)  # counter-based bits: reproducible
 
