@@ -817,6 +817,17 @@ __device__ __forceinline__ void mom_store(float* __restrict__ dst, uint64_t pstr
     for (int j = 0; j < 5; ++j) __builtin_nontemporal_store(om1 * k[j], dst + (4 + j) * pstride + off);
 }
 
+// The same nine stores into one z plane of each moment: plane_k = dst + k *
+// pstride (+ the plane's wave-uniform start), a 32-bit byte offset within it.
+__device__ __forceinline__ void mom_store_plane(float* __restrict__ plane0, uint64_t pstride, uint32_t bytes,
+                                                uint32_t byte_off, float drho, float ux, float uy, float uz,
+                                                const float k[5], float om1)
+{
+    const float v[9] = {drho, ux, uy, uz, om1 * k[0], om1 * k[1], om1 * k[2], om1 * k[3], om1 * k[4]};
+#pragma unroll
+    for (int j = 0; j < 9; ++j) st_buf<true>((gchar*)(plane0 + j * pstride), bytes, byte_off, v[j]);
+}
+
 // TY interior rows per tile: TY + 2 halo rows reconstructed by waves 0..TY+1,
 // the two edge columns of those rows by wave TY + 2.
 template <bool FIELD, int TY>
@@ -867,15 +878,29 @@ __global__ __launch_bounds__((TY + 3) * 64) void k_step_mom(const float* __restr
     const float om1 = 1.f - omega;
     auto row_of = [&](int z, int y) -> uint64_t { return ((uint64_t)(b * g.nz + z) * g.ny + y) * g.nxp; };
     auto lin_of = [&](int z, int y, int x) -> uint64_t { return ((uint64_t)(b * g.nz + z) * g.ny + y) * g.nx + x; };
+    // loads and stores address one z plane of a moment (wave-uniform start,
+    // ny * nxp floats) with a loop-invariant 32-bit lane offset
+    const uint32_t plane_bytes = (uint32_t)g.ny * (uint32_t)g.nxp * 4u;
+    const uint32_t rec_off = ((uint32_t)gy * (uint32_t)g.nxp + (uint32_t)gx) * 4u;
+    const uint32_t int_off = ((uint32_t)(inter ? iy : 0) * (uint32_t)g.nxp + (uint32_t)ix) * 4u;
+    // the force field the same way, in its unpadded [3][cells] layout
+    const uint32_t fplane_bytes = (uint32_t)g.ny * (uint32_t)g.nx * 4u;
+    const uint32_t rec_foff = ((uint32_t)gy * (uint32_t)g.nx + (uint32_t)gx) * 4u;
+    const uint32_t int_foff = ((uint32_t)(inter ? iy : 0) * (uint32_t)g.nx + (uint32_t)ix) * 4u;
+    auto field_at = [&](int z, uint32_t off, float F[3]) {
+        const float* p0 = field + lin_of(z, 0, 0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) F[a] = ld_buf<float>((gchar*)(p0 + a * g.ncell), fplane_bytes, off);
+    };
 
     float mreg[9], freg[3] = {0.f, 0.f, 0.f};
     auto load_m = [&](int zu) {
         if (!rec) return;
         const int z = wrap(zu, g.nz);
-        const uint64_t o = row_of(z, gy) + gx;
+        const float* plane0 = src + row_of(z, 0);
 #pragma unroll
-        for (int k = 0; k < 9; ++k) mreg[k] = src[k * g.pstride + o];
-        if (FIELD) mom_force<true>(g, lin_of(z, gy, gx), b, gy, ftab, field, freg);
+        for (int k = 0; k < 9; ++k) mreg[k] = ld_buf<float>((gchar*)(plane0 + k * g.pstride), plane_bytes, rec_off);
+        if (FIELD) field_at(z, rec_foff, freg);
     };
     float h[27];
     auto recon = [&]() {
@@ -924,10 +949,13 @@ __global__ __launch_bounds__((TY + 3) * 64) void k_step_mom(const float* __restr
                 f[i] = slot[mom_lds<HY>((cy + 1) * 3 + cx + 1, wave - cy, lane + 1 - cx)];
             }
             float F[3];
-            mom_force<FIELD>(g, lin_of(z, iy, ix), b, iy, ftab, field, F);
+            if (FIELD)
+                field_at(z, int_foff, F);
+            else
+                mom_force<false>(g, 0, b, iy, ftab, field, F);
             float drho, ux, uy, uz, k[5];
             pre_collision<float>(f, F[0], F[1], F[2], rho0, drho, ux, uy, uz, k);
-            mom_store(dst, g.pstride, row_of(z, iy) + ix, drho, ux, uy, uz, k, om1);
+            mom_store_plane(dst + row_of(z, 0), g.pstride, plane_bytes, int_off, drho, ux, uy, uz, k, om1);
         }
         __syncthreads();
         if (rec) {

@@ -38,6 +38,22 @@ __host__ __device__ constexpr int vel_index(int a, int b, int c)
 }
 __host__ __device__ constexpr int opposite(int i) { return vel_index(-vel_x(i), -vel_y(i), -vel_z(i)); }
 
+// 1 / x.  FP32: the hardware reciprocal (about one ulp) refined by one Newton
+// step, e = 1 - x r, r + r e (within an ulp of the quotient; the density is
+// near 1, far from FP32's range limits), in place of the correctly rounded
+// division's scale / fix-up sequence.  FP64: the division.
+template <typename T>
+__device__ __forceinline__ T reciprocal(T x)
+{
+    return T(1) / x;
+}
+template <>
+__device__ __forceinline__ float reciprocal<float>(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return __builtin_fmaf(__builtin_fmaf(-x, r, 1.0f), r, r);
+}
+
 // Lattice weight: the tensor product of the 1D weights (1/6, 2/3, 1/6),
 // equal to 8/27, 2/27, 1/54, 1/216 for |c|^2 = 0, 1, 2, 3.
 __host__ __device__ constexpr double weight(int i)
@@ -114,7 +130,7 @@ __device__ __forceinline__ void pre_collision(const T h[27], T Fx, T Fy, T Fz, T
 
     // Macroscopic variables with the half-force correction (eq. "macroscopic").
     const T rho = rho0 + drho;
-    const T inv_rho = T(1) / rho;
+    const T inv_rho = reciprocal(rho);
     ux = (jx + T(0.5) * Fx) * inv_rho;
     uy = (jy + T(0.5) * Fy) * inv_rho;
     uz = (jz + T(0.5) * Fz) * inv_rho;
@@ -315,7 +331,7 @@ __device__ __forceinline__ void collide_model(T h[27], T Fx, T Fy, T Fz, T omega
     const T Sxx = zsum(2, 0, 0), Syy = zsum(0, 2, 0), Szz = zsum(0, 0, 2);
     const T Sxy = zsum(1, 1, 0), Sxz = zsum(1, 0, 1), Syz = zsum(0, 1, 1);
     const T rho = rho0 + drho;
-    const T inv_rho = T(1) / rho;
+    const T inv_rho = reciprocal(rho);
     const T ux = (jx + T(0.5) * Fx) * inv_rho;
     const T uy = (jy + T(0.5) * Fy) * inv_rho;
     const T uz = (jz + T(0.5) * Fz) * inv_rho;
