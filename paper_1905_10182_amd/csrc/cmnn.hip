@@ -1208,9 +1208,12 @@ bool bwd_w_brick(const G& g, int cin, int cout)
 int bwd_w_chunks(const G& g, int cin, int cout)
 {
     if (bwd_w_brick(g, cin, cout)) {
+        // one workgroup per CU (147 KB of LDS): at most 256 (chunk, tile)
+        // workgroups, so that none waits for a second round
         const long long bricks = g.nvox / (kTD * kTH * kTW);
         const long long tiles = (long long)(cin / 32) * (cout / 32);
-        long long c = (256 + tiles - 1) / tiles;
+        long long c = 256 / tiles;
+        if (c < 1) c = 1;
         if (c > bricks) c = bricks;
         const long long per = (bricks + c - 1) / c;
         return (int)((bricks + per - 1) / per);
