@@ -374,6 +374,36 @@ def run_conv(steps, warmup, repeats):
     return out
 
 
+def plane_copy_rate(n=256, repeats=5, launches=20):
+    """The FP32 step's memory traffic without its arithmetic on the headline
+    lattice's layout (27 planes of n^3 cells, the library's plane stride):
+    median of `repeats` windows of `launches` plane copies."""
+    import torch
+    from paper_1905_10182_amd import cmlbm
+    assert (4 * n) % 256 == 0  # rows are whole 256-byte lines, so the plane is n^3 values
+    cells = n ** 3
+    stride = cells + 1024  # planes 4 KiB apart beyond their rows, as the library lays them out
+    a = torch.zeros(27 * stride, dtype=torch.float32, device="cuda:0")
+    b = torch.zeros_like(a)
+    for _ in range(3):
+        cmlbm.plane_copy(b, a, 27, cells, stride)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(repeats):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(launches):
+            cmlbm.plane_copy(b, a, 27, cells, stride)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) / launches)
+    ms = statistics.median(ts)
+    del a, b
+    torch.cuda.empty_cache()
+    return {"workload": f"27 FP32 planes of {n}^3 cells in, 27 out, one cell per lane, no arithmetic",
+            "ms_per_launch": round(ms, 5), "gbs": round(2 * 27 * 4 * cells / (ms * 1e-3) / 1e9, 1)}
+
+
 def copy_bandwidth(fn):
     """Read + write rate of fn(dst, src) on 4 GiB, median of 10 calls."""
     import torch
@@ -592,6 +622,7 @@ def main():
         from paper_1905_10182_amd.cmlbm import device_copy
         extra["device_copy_gbs"] = round(copy_bandwidth(lambda b, a: b.copy_(a)), 1)  # torch's copy
         extra["kernel_copy_gbs"] = round(copy_bandwidth(device_copy), 1)  # 16-byte non-temporal copy kernel
+        extra["plane_copy"] = plane_copy_rate()  # the FP32 step's access pattern without arithmetic
     if "conv" in legs:
         log("U-Net training steps and convolution kernels (libcmnn)")
         extra["conv"] = run_conv(max(K // 10, 5), max(W // 10, 2), R)
@@ -624,7 +655,9 @@ def main():
             "bound": "hbm", "kernel": STEP_KERNEL["fp32"], "achieved": main_run["hbm_gbs"], "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": main_run["hbm_frac"], "traffic": measured_traffic("fp32"),
             "bytes_per_cell": BYTES_PER_CELL["fp32"], "window_ms_per_step": main_run["window_ms_per_step"],
-            "source_digest": source_digest()},
+            "source_digest": source_digest(),
+            # the same 27-plane access pattern with no arithmetic, timed in this run (copy leg)
+            "pattern_copy_gbs": extra["plane_copy"]["gbs"] if "plane_copy" in extra else None},
         "cpu_baseline": cpu,
         "mass_drift": main_run["mass_drift"] if main_run else None,
     }

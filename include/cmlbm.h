@@ -256,6 +256,20 @@ const char* cmlbm_status_string(int status);
  * misaligned or odd-sized arguments; nothing is enqueued then. */
 int cmlbm_device_copy(void* dev_dst, const void* dev_src, size_t bytes, void* hip_stream);
 
+/* Measurement aid, not part of the method: the FP32 step's memory traffic
+ * without its arithmetic.  For every plane p < planes and cell c < cells,
+ * dev_dst[p * plane_stride + c] = dev_src[p * plane_stride + c] (FP32
+ * elements; both device pointers 4-byte aligned, the two spans not
+ * overlapping), one cell per lane in 1024-thread workgroups: each lane loads
+ * its cell of every plane, then stores them non-temporally -- the access
+ * pattern of the FP32 population step (planes = 27) or of the moment
+ * storage's nine numbers (planes = 9) with no collision.  Its rate is the
+ * ceiling of that pattern.  EINVAL on NULL or misaligned pointers, planes
+ * other than 9 or 27, cells < 1, plane_stride < cells, or overlapping spans;
+ * nothing is enqueued then. */
+int cmlbm_plane_copy(void* dev_dst, const void* dev_src, int32_t planes, int64_t cells, int64_t plane_stride,
+                     void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

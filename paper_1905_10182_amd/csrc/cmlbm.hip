@@ -1354,6 +1354,22 @@ __global__ __launch_bounds__(kBlock) void k_copy16(const v4i* __restrict__ src, 
     }
 }
 
+// The FP32 step's memory traffic without its arithmetic (a measurement aid):
+// one cell per lane in 1024-thread workgroups, each lane loads its cell of
+// every plane, then stores them with non-temporal stores.
+template <int NP>
+__global__ __launch_bounds__(1024) void k_copy_planes(const float* __restrict__ src, float* __restrict__ dst,
+                                                      uint64_t cells, uint64_t pstride)
+{
+    const uint64_t c = (uint64_t)blockIdx.x * 1024 + threadIdx.x;
+    if (c >= cells) return;
+    float v[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) v[p] = src[p * pstride + c];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) __builtin_nontemporal_store(v[p], dst + p * pstride + c);
+}
+
 __global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v)
 {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
@@ -2244,6 +2260,27 @@ int cmlbm_device_copy(void* dev_dst, const void* dev_src, size_t bytes, void* hi
     const uint64_t need = (n + kBlock * 4 - 1) / (kBlock * 4);
     if (blocks > need) blocks = need;
     k_copy16<<<dim3((unsigned)blocks), dim3(kBlock), 0, (hipStream_t)hip_stream>>>((const v4i*)dev_src, (v4i*)dev_dst, n);
+    return hipGetLastError() == hipSuccess ? CMLBM_OK : CMLBM_EHIP;
+}
+
+int cmlbm_plane_copy(void* dev_dst, const void* dev_src, int32_t planes, int64_t cells, int64_t plane_stride,
+                     void* hip_stream)
+{
+    if (!dev_dst || !dev_src || (planes != 9 && planes != 27) || cells < 1 || plane_stride < cells ||
+        ((uintptr_t)dev_dst | (uintptr_t)dev_src) % 4)
+        return CMLBM_EINVAL;
+    const uint64_t span = ((uint64_t)(planes - 1) * (uint64_t)plane_stride + (uint64_t)cells) * 4;
+    const char *d = (const char*)dev_dst, *sp = (const char*)dev_src;
+    if (d < sp + span && sp < d + span) return CMLBM_EINVAL;  // overlapping
+    const uint64_t blocks = ((uint64_t)cells + 1023) / 1024;
+    if (blocks > 0x7fffffffULL) return CMLBM_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (planes == 27)
+        k_copy_planes<27><<<dim3((unsigned)blocks), dim3(1024), 0, s>>>((const float*)dev_src, (float*)dev_dst,
+                                                                       (uint64_t)cells, (uint64_t)plane_stride);
+    else
+        k_copy_planes<9><<<dim3((unsigned)blocks), dim3(1024), 0, s>>>((const float*)dev_src, (float*)dev_dst,
+                                                                      (uint64_t)cells, (uint64_t)plane_stride);
     return hipGetLastError() == hipSuccess ? CMLBM_OK : CMLBM_EHIP;
 }
 

@@ -175,3 +175,17 @@ def test_device_copy_validation(lib):
     assert lib.cmlbm_device_copy(P(4096), P(0), 24, None) == B.EINVAL     # not a multiple of 16 bytes
     assert lib.cmlbm_device_copy(P(4096), P(0), 0, None) == B.EINVAL
     assert lib.cmlbm_device_copy(P(64), P(0), 128, None) == B.EINVAL      # overlapping
+
+
+def test_plane_copy_validation(lib):
+    """Argument checks of the plane copy, all before any GPU call."""
+    P = ctypes.c_void_p
+    lib.cmlbm_plane_copy.argtypes = [P, P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, P]
+    far = 1 << 40
+    assert lib.cmlbm_plane_copy(None, P(0x1000), 27, 64, 64, None) == B.EINVAL
+    assert lib.cmlbm_plane_copy(P(far), None, 27, 64, 64, None) == B.EINVAL
+    assert lib.cmlbm_plane_copy(P(far), P(0x1000), 8, 64, 64, None) == B.EINVAL     # planes: 9 or 27
+    assert lib.cmlbm_plane_copy(P(far), P(0x1000), 27, 0, 64, None) == B.EINVAL     # no cells
+    assert lib.cmlbm_plane_copy(P(far), P(0x1000), 27, 64, 63, None) == B.EINVAL    # stride below the cells
+    assert lib.cmlbm_plane_copy(P(far + 2), P(0x1000), 27, 64, 64, None) == B.EINVAL  # misaligned
+    assert lib.cmlbm_plane_copy(P(0x1000 + 256), P(0x1000), 9, 64, 64, None) == B.EINVAL  # overlapping

@@ -859,3 +859,19 @@ def test_device_copy_bitwise(torch):
         device_copy(b, a)
         torch.cuda.synchronize()
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("planes", [27, 9])
+def test_plane_copy_bitwise(torch, planes):
+    """The plane copy copies every cell of every plane (a ragged last
+    workgroup, planes spaced beyond their cells) and leaves the gaps between
+    planes untouched."""
+    from paper_1905_10182_amd.cmlbm import plane_copy
+    g = torch.Generator(device="cuda:0").manual_seed(5)
+    cells, stride = 1024 * 37 + 5, 1024 * 37 + 5 + 1031
+    a = torch.randn((planes, stride), device="cuda:0", generator=g)
+    b = torch.full_like(a, -7.0)
+    plane_copy(b, a, planes, cells, stride)
+    torch.cuda.synchronize()
+    assert torch.equal(a[:, :cells], b[:, :cells])
+    assert torch.all(b[:, cells:] == -7.0)
