@@ -107,6 +107,20 @@ __device__ __forceinline__ u4 pack8(const float (&f)[8])
 
 __device__ __forceinline__ bf16x8 ld8(const bf16* p) { return __builtin_bit_cast(bf16x8, *(const u4*)p); }
 
+// Raw buffer loads of 16 bytes: a descriptor in four scalar registers
+// (wave-uniform base, stride 0, size in bytes, the gfx9 raw-buffer format
+// word) plus a 32-bit per-lane offset and a wave-uniform offset, added by the
+// memory unit instead of by 64-bit VALU arithmetic.
+constexpr int kRawBufferWord3 = 0x00020000;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kRawBufferWord3);
+}
+__device__ __forceinline__ bf16x8 ldb8(__amdgpu_buffer_rsrc_t r, uint32_t lane_off, uint32_t uniform_off)
+{
+    return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(r, lane_off, uniform_off, 0));
+}
+
 // ---------------------------------------------------------------------------
 // forward convolution (and, with SIGN = -1, the data gradient)
 //
@@ -171,7 +185,11 @@ __global__ __launch_bounds__(256) void k_conv_fwd(G g, const bf16* __restrict__ 
 // its three x taps (the x - 1 and x + 1 fragments are lane shifts of it).  Wave w owns the 4 brick rows (d, h) =
 // (w, 0..3), i.e. 4 MFMA row blocks of 16 x-consecutive voxels, and keeps
 // 4 x NB accumulator tiles: each B fragment (weights, through L1) feeds 4
-// MFMAs and each A fragment (LDS) feeds NB.
+// MFMAs and each A fragment (LDS) feeds NB.  The weight fragments are raw
+// buffer loads (a loop-invariant lane offset plus a wave-uniform tap offset,
+// no per-load address arithmetic); a tap group's second and third taps are
+// loaded before its LDS reads and the next group's first tap during its first
+// tap's MFMAs, so the load latency overlaps work.
 
 // The A operand of v_mfma_f32_16x16x32_bf16 holds voxel row (lane % 16), so
 // the fragment of the neighbouring x tap is the same fragment shifted by one
@@ -205,6 +223,7 @@ constexpr int kTD = 4, kTH = 4, kTW = 16;
 constexpr int kHD = kTD + 2, kHH = kTH + 2, kHW = kTW + 2;
 constexpr int kHalo = kHD * kHH * kHW;  // 648 voxels
 constexpr int kVStride = 40;            // bf16 per staged voxel (32 channels + 8 pad)
+constexpr uint32_t kVBytes = kVStride * 2;
 
 constexpr int kStageIters = (kHalo * 4 + 255) / 256;
 
@@ -249,11 +268,20 @@ __global__ __launch_bounds__(256) void k_conv_tile(G g, const bf16* __restrict__
     for (int m = 0; m < 4; ++m)
 #pragma unroll
         for (int b = 0; b < NB; ++b) acc[m][b] = f4{0.f, 0.f, 0.f, 0.f};
-    const bf16* wl = wt + (long long)(co0 + (lane & 15)) * cin + (lane >> 4) * 8;
+    // weights: one descriptor over the [27][cout][cin] tensor, this lane's
+    // row / channel part as a loop-invariant lane offset, the tap, output
+    // block and channel chunk as a wave-uniform offset
+    const __amdgpu_buffer_rsrc_t wr = buf_rsrc(wt, 27u * (uint32_t)cout * (uint32_t)cin * 2u);
+    const uint32_t wlane = ((uint32_t)(co0 + (lane & 15)) * (uint32_t)cin + (uint32_t)(lane >> 4) * 8u) * 2u;
     // halo staging: thread tid moves the 16-byte parts tid, tid + 256, ... of
-    // the 648 x 4; all its loads are in flight together, and the next chunk's
-    // are issued before the current chunk's MFMAs
+    // the 648 x 4; all its loads are in flight together
     u4 stage[kStageIters];
+    // LDS fragment reads: lane part of the centre row (voxel x = lane % 16 + 1
+    // of the halo row) and of its edge voxel, 16-byte channel group lane / 16
+    const char* sxb = (const char*)sx;
+    const uint32_t lane_a = ((uint32_t)(lane & 15) + 1u) * kVBytes + (uint32_t)(lane >> 4) * 16u;
+    const uint32_t lane_e = ((lane & 15) < 8 ? 0u : (uint32_t)(kHW - 1) * kVBytes) + (uint32_t)(lane >> 4) * 16u;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
     for (int c0 = 0; c0 < cin; c0 += 32) {
         stage_halo_load(g, x, cin, c0, n, d0, h0, x0, tid, stage);
         __syncthreads();
@@ -263,32 +291,46 @@ __global__ __launch_bounds__(256) void k_conv_tile(G g, const bf16* __restrict__
             if (p < kHalo * 4) *(u4*)&sx[(p >> 2) * kVStride + (p & 3) * 8] = stage[it];
         }
         __syncthreads();
+        // weight fragments of tap t (NB output blocks); the first tap of the
+        // next group is loaded one group ahead
+        auto wload = [&](int t, bf16x8 bw[NB]) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                bw[b] = ldb8(wr, wlane, (((uint32_t)t * (uint32_t)cout + 16u * b) * (uint32_t)cin + (uint32_t)c0) * 2u);
+        };
+        bf16x8 bnext[NB];
+        wload(0, bnext);
 #pragma unroll 1
         for (int t9 = 0; t9 < 9; ++t9) {
             const int dz = SIGN * (t9 / 3 - 1), dy = SIGN * (t9 % 3 - 1);
-            // A fragments of the three x taps (index dx + 1) of each brick row
+            bf16x8 bw[3][NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) bw[0][b] = bnext[b];
+            wload(t9 * 3 + 1, bw[1]);
+            wload(t9 * 3 + 2, bw[2]);
+            // A fragments of the three x taps (index dx + 1) of each brick row:
+            // 32-bit LDS byte offsets, the tap's row wave-uniform, the brick row
+            // m an immediate
+            const uint32_t trow = (uint32_t)(((wv + 1 + dz) * kHH + 1 + dy) * kHW) * kVBytes;
             bf16x8 af[4][3];
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-                const int hrow = ((wave + 1 + dz) * kHH + (m + 1 + dy)) * kHW;
-                const bf16x8 a0 = *(const bf16x8*)&sx[(hrow + (lane & 15) + 1) * kVStride + (lane >> 4) * 8];
-                const bf16x8 e = *(const bf16x8*)&sx[(hrow + ((lane & 15) < 8 ? 0 : kHW - 1)) * kVStride + (lane >> 4) * 8];
+                const uint32_t mrow = trow + (uint32_t)(m * kHW) * kVBytes;
+                const bf16x8 a0 = *(const bf16x8*)(sxb + lane_a + mrow);
+                const bf16x8 e = *(const bf16x8*)(sxb + lane_e + mrow);
                 af[m][0] = rows_from_lower(e, a0);
                 af[m][1] = a0;
                 af[m][2] = rows_from_upper(e, a0);
             }
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                const int t = t9 * 3 + j;
                 const int k = SIGN > 0 ? j : 2 - j;  // dx = SIGN * (j - 1)
-                bf16x8 bw[NB];
-#pragma unroll
-                for (int b = 0; b < NB; ++b) bw[b] = ld8(wl + ((long long)t * cout + 16 * b) * cin + c0);
 #pragma unroll
                 for (int m = 0; m < 4; ++m)
 #pragma unroll
                     for (int b = 0; b < NB; ++b)
-                        acc[m][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[m][k], bw[b], acc[m][b], 0, 0, 0);
+                        acc[m][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[m][k], bw[j][b], acc[m][b], 0, 0, 0);
+                if (j == 0 && t9 < 8) wload(t9 * 3 + 3, bnext);
             }
         }
     }
@@ -1236,7 +1278,8 @@ template <int SIGN, int ACT>
 int conv_dispatch(const G& g, const bf16* x, int cin, const bf16* w, const float* bias, int cout, bf16* y,
                   hipStream_t s)
 {
-    if (brick_ok(g)) {
+    // the brick kernel addresses the weights with 32-bit byte offsets
+    if (brick_ok(g) && 27LL * cout * cin * 2 < (1LL << 32)) {
         // widest output tile that still leaves >= 512 workgroups (two per CU)
         const long long bricks = g.nvox / (kTD * kTH * kTW);
         const int c16 = cout / 16;
