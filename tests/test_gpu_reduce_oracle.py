@@ -198,3 +198,50 @@ def test_members_are_reduced_apart(torch, storage):
     got = lat.step_reduce(allow_unstable=True)
     compare(got, rr, tol, 1e-13 if storage == "fp64" else 1e-7, tol, "step_reduce")
     lat.close()
+
+
+def oracle_blow_up_step(n=32, u0=0.3, tau=0.5005, every=5, limit=400):
+    """First multiple of `every` at which the oracle's state has a non-finite
+    cell (the unstable Taylor-Green run of the oracle's blow-up test)."""
+    wl = W.taylor_green(n, seed=1, u0=u0)
+    ref = O.Lattice(n, n, n, tau=tau)
+    ref.init(wl["rho"], wl["u"])
+    for k in range(every, limit + 1, every):
+        ref.step(every)
+        with np.errstate(invalid="ignore", over="ignore"):
+            if ref.reductions()[0]["nonfinite"]:
+                return k
+    return None
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_blow_up_reports_unstable(torch, storage):
+    """The unstable run (TGV 32^3, u0 = 0.3, tau = 0.5005) through the
+    library: cmlbm_reduce raises EUNSTABLE once the state turns non-finite
+    and not before (both sides checked every 5 steps); in FP64 it fires
+    within 20 steps of the oracle's detector."""
+    from paper_1905_10182_amd import Lattice
+    from paper_1905_10182_amd import cmlbm as B
+    k_ref = oracle_blow_up_step()
+    assert k_ref is not None
+    log(f"{storage} blow-up run, TGV 32^3 u0 = 0.3 tau = 0.5005; oracle fires at step {k_ref}")
+    wl = W.taylor_green(32, seed=1, u0=0.3)
+    lat = Lattice(32, 32, 32, tau=0.5005, storage=storage, device="cuda:0")
+    lat.init(wl["rho"], wl["u"])
+    fired = None
+    for k in range(5, 401, 5):
+        lat.step(5)
+        try:
+            r = lat.reduce()
+        except B.CmlbmError as e:
+            assert e.code == B.EUNSTABLE
+            fired = k
+            break
+        assert np.isfinite(r[0, RED["ke"]]) and r[0, RED["nonfinite"]] == 0
+    log(f"  library fires at step {fired}")
+    assert fired is not None
+    r = lat.reduce(allow_unstable=True)
+    assert r[0, RED["nonfinite"]] > 0 and r[0, RED["fluid"]] == 32 ** 3
+    if storage == "fp64":
+        assert abs(fired - k_ref) <= 20
+    lat.close()

@@ -22,6 +22,7 @@ import math
 import numpy as np
 
 import oracle as O
+import workloads as W
 
 SHAPE = (2, 4, 5, 6)  # nb, nz, ny, nx
 N = 4 * 5 * 6
@@ -138,3 +139,22 @@ def test_kinetic_energy_decay_of_taylor_green_2d():
     # and the kinetic energy of the initial field is the closed form sum rho |u|^2 / 2
     L.init(rho, u)
     close(L.reductions()[0]["ke"], (rho[0] * (u[:2, 0] ** 2).sum(axis=0)).sum() / 2, rtol=1e-12)
+
+
+def test_blow_up_is_detected():
+    """A Taylor-Green vortex at u0 = 0.3 (Mach 0.52) and tau = 0.5005 on 32^3
+    is unstable: the oracle's state turns non-finite, and the reductions'
+    non-finite count fires then and not before (checked every 5 steps)."""
+    wl = W.taylor_green(32, seed=1, u0=0.3)
+    lat = O.Lattice(32, 32, 32, tau=0.5005)
+    lat.init(wl["rho"], wl["u"])
+    fired = None
+    for k in range(5, 401, 5):
+        lat.step(5)
+        with np.errstate(invalid="ignore", over="ignore"):  # sums over the non-finite cells
+            r = lat.reductions()[0]
+        if r["nonfinite"]:
+            fired = k
+            break
+        assert np.isfinite(r["ke"]) and r["fluid"] == 32 ** 3
+    assert fired is not None and 100 < fired <= 400, fired
