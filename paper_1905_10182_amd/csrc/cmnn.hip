@@ -1285,6 +1285,8 @@ int conv_dispatch(const G& g, const bf16* x, int cin, const bf16* w, const float
         const int c16 = cout / 16;
         if (c16 % 6 == 0 && bricks * (c16 / 6) >= 512) return conv_tile_launch<6, SIGN, ACT>(g, x, cin, w, bias, cout, y, s);
         if (c16 % 4 == 0 && bricks * (c16 / 4) >= 512) return conv_tile_launch<4, SIGN, ACT>(g, x, cin, w, bias, cout, y, s);
+        // a grid of fewer workgroups than CUs takes 16-channel tiles (twice the workgroups)
+        if (bricks * (c16 / 2) < 256) return conv_tile_launch<1, SIGN, ACT>(g, x, cin, w, bias, cout, y, s);
         return conv_tile_launch<2, SIGN, ACT>(g, x, cin, w, bias, cout, y, s);
     }
     const unsigned mb = (unsigned)((g.nvox + 63) / 64);
