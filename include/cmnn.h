@@ -57,6 +57,17 @@ int cmnn_conv3d_fwd(const cmnn_geom* g, const void* x, int32_t cin, const void* 
 int cmnn_conv3d_bwd_data(const cmnn_geom* g, const void* dy, int32_t cout, const void* w_t, int32_t cin, void* dx,
                          void* hip_stream);
 
+/* The data gradient of cmnn_conv3d_bwd_data with the activation gradient of
+ * the layer that produced this layer's input fused in: dx as above, then,
+ * for act = CMNN_ACT_LEAKY, each element multiplied by 0.1 where the same
+ * element of gate (that layer's activation output, [..][cin] BF16, i.e. this
+ * layer's input) is <= 0 -- the rule of cmnn_act_bwd, applied to the FP32
+ * accumulator before the one BF16 rounding.  dx is then that layer's
+ * pre-activation gradient.  act = CMNN_ACT_NONE is cmnn_conv3d_bwd_data
+ * (gate ignored).  EINVAL on a NULL or misaligned gate, or gate == dx. */
+int cmnn_conv3d_bwd_data_act(const cmnn_geom* g, const void* dy, int32_t cout, const void* w_t, int32_t cin,
+                             const void* gate, int32_t act, void* dx, void* hip_stream);
+
 /* Workspace bytes needed by cmnn_conv3d_bwd_weight. */
 int cmnn_conv3d_bwd_weight_workspace(const cmnn_geom* g, int32_t cin, int32_t cout, size_t* bytes);
 

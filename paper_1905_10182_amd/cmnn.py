@@ -11,8 +11,8 @@ OK, EINVAL, EHIP = 0, -1, -3
 CALIGN = 32
 ACT_NONE, ACT_LEAKY = 0, 1
 
-EXPORTS = ["cmnn_conv3d_fwd", "cmnn_conv3d_bwd_data", "cmnn_conv3d_bwd_weight_workspace", "cmnn_conv3d_bwd_weight",
-           "cmnn_conv3d_bwd_weight_noalloc",
+EXPORTS = ["cmnn_conv3d_fwd", "cmnn_conv3d_bwd_data", "cmnn_conv3d_bwd_data_act", "cmnn_conv3d_bwd_weight_workspace",
+           "cmnn_conv3d_bwd_weight", "cmnn_conv3d_bwd_weight_noalloc",
            "cmnn_act_bwd", "cmnn_pool2_fwd", "cmnn_pool2_bwd", "cmnn_up2_fwd", "cmnn_up2_bwd", "cmnn_concat_fwd",
            "cmnn_concat_bwd", "cmnn_add", "cmnn_channel_mean_workspace", "cmnn_channel_mean", "cmnn_mse_workspace",
            "cmnn_mse", "cmnn_clip_grad_norm_workspace", "cmnn_clip_grad_norm", "cmnn_adam", "cmnn_pack_weights",
@@ -50,6 +50,7 @@ def load_library():
     G = ctypes.POINTER(Geom)
     lib.cmnn_conv3d_fwd.argtypes = [G, vp, i32, vp, vp, i32, i32, vp, vp]
     lib.cmnn_conv3d_bwd_data.argtypes = [G, vp, i32, vp, i32, vp, vp]
+    lib.cmnn_conv3d_bwd_data_act.argtypes = [G, vp, i32, vp, i32, vp, i32, vp, vp]
     lib.cmnn_conv3d_bwd_weight_workspace.argtypes = [G, i32, i32, ctypes.POINTER(sz)]
     lib.cmnn_conv3d_bwd_weight.argtypes = [G, vp, i32, vp, i32, vp, vp, vp, sz, vp]
     lib.cmnn_conv3d_bwd_weight_noalloc.argtypes = [G, vp, i32, vp, i32, vp, vp, vp]
@@ -96,6 +97,13 @@ def nvox(g):
 def conv_fwd(g, x, cin, w, b, cout, act, y):
     _check(load_library().cmnn_conv3d_fwd(ctypes.byref(g), _p(x), cin, _p(w), _p(b), cout, act, _p(y), _s()),
            "conv3d_fwd")
+
+
+def conv_bwd_data_act(g, dy, cout, w_t, cin, gate, act, dx):
+    """Data gradient with the producing layer's activation gradient fused in:
+    dx = conv_bwd_data(dy) times the slope of `act` at its output `gate`."""
+    _check(load_library().cmnn_conv3d_bwd_data_act(ctypes.byref(g), _p(dy), cout, _p(w_t), cin, _p(gate), act,
+                                                   _p(dx), _s()), "conv3d_bwd_data_act")
 
 
 def conv_bwd_data(g, dy, cout, w_t, cin, dx):

@@ -127,9 +127,27 @@ __device__ __forceinline__ bf16x8 ldb8(__amdgpu_buffer_rsrc_t r, uint32_t lane_o
 // Workgroup = 4 waves = 64 consecutive voxels x (16 * NB) output channels;
 // wave w owns voxels [16w, 16w + 16) and NB 16-channel output blocks.
 
+// Epilogue of the convolution kernels.  SIGN = +1 (forward): v + bias, then
+// the activation.  SIGN = -1 (data gradient) with ACT = LEAKY: the gradient is
+// multiplied by the leaky-ReLU slope at the activation output `gate` (0.1
+// where gate <= 0), i.e. it leaves as the producing layer's pre-activation
+// gradient (the rule of k_act_bwd, applied before the BF16 rounding).
+template <int SIGN, int ACT>
+__device__ __forceinline__ float conv_out(float v, float bias, const bf16* __restrict__ gate, long long idx)
+{
+    if (SIGN > 0) {
+        v += bias;
+        if (ACT == CMNN_ACT_LEAKY) v = v > 0.f ? v : kLeak * v;
+    } else if (ACT == CMNN_ACT_LEAKY) {
+        if ((float)gate[idx] <= 0.f) v *= kLeak;
+    }
+    return v;
+}
+
 template <int NB, int SIGN, int ACT>
 __global__ __launch_bounds__(256) void k_conv_fwd(G g, const bf16* __restrict__ x, int cin, const bf16* __restrict__ wt,
-                                                  const float* __restrict__ bias, int cout, bf16* __restrict__ y)
+                                                  const float* __restrict__ bias, int cout, bf16* __restrict__ y,
+                                                  const bf16* __restrict__ gate)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const long long m0 = (long long)blockIdx.x * 64 + wave * 16;
@@ -165,9 +183,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(G g, const bf16* __restrict__ 
         for (int i = 0; i < 4; ++i) {
             const long long m = m0 + kq * 4 + i;
             if (m >= g.nvox) continue;
-            float v = acc[b][i] + bb;
-            if (ACT == CMNN_ACT_LEAKY) v = v > 0.f ? v : kLeak * v;
-            y[m * cout + co] = (bf16)v;
+            y[m * cout + co] = (bf16)conv_out<SIGN, ACT>(acc[b][i], bb, gate, m * cout + co);
         }
     }
 }
@@ -246,7 +262,8 @@ __device__ __forceinline__ void stage_halo_load(const G& g, const bf16* __restri
 template <int NB, int SIGN, int ACT>
 __global__ __launch_bounds__(256) void k_conv_tile(G g, const bf16* __restrict__ x, int cin,
                                                    const bf16* __restrict__ wt, const float* __restrict__ bias,
-                                                   int cout, bf16* __restrict__ y, unsigned xcd_span)
+                                                   int cout, bf16* __restrict__ y, unsigned xcd_span,
+                                                   const bf16* __restrict__ gate)
 {
     __shared__ __attribute__((aligned(16))) bf16 sx[kHalo * kVStride];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -344,9 +361,8 @@ __global__ __launch_bounds__(256) void k_conv_tile(G g, const bf16* __restrict__
             const float bb = bias ? bias[co] : 0.f;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                float v = acc[m][b][i] + bb;
-                if (ACT == CMNN_ACT_LEAKY) v = v > 0.f ? v : kLeak * v;
-                y[(vrow + (lane >> 4) * 4 + i) * cout + co] = (bf16)v;
+                const long long idx = (vrow + (lane >> 4) * 4 + i) * cout + co;
+                y[idx] = (bf16)conv_out<SIGN, ACT>(acc[m][b][i], bb, gate, idx);
             }
         }
     }
@@ -1266,34 +1282,34 @@ int bwd_w_chunks(const G& g, int cin, int cout)
 
 template <int NB, int SIGN, int ACT>
 int conv_tile_launch(const G& g, const bf16* x, int cin, const bf16* w, const float* bias, int cout, bf16* y,
-                     hipStream_t s)
+                     const bf16* gate, hipStream_t s)
 {
     const unsigned bricks = (unsigned)(g.nvox / (kTD * kTH * kTW));
     const unsigned span = bricks % 8 == 0 ? bricks / 8 : 0;
-    k_conv_tile<NB, SIGN, ACT><<<dim3(bricks, cout / (16 * NB)), 256, 0, s>>>(g, x, cin, w, bias, cout, y, span);
+    k_conv_tile<NB, SIGN, ACT><<<dim3(bricks, cout / (16 * NB)), 256, 0, s>>>(g, x, cin, w, bias, cout, y, span, gate);
     return launched();
 }
 
 template <int SIGN, int ACT>
 int conv_dispatch(const G& g, const bf16* x, int cin, const bf16* w, const float* bias, int cout, bf16* y,
-                  hipStream_t s)
+                  const bf16* gate, hipStream_t s)
 {
     // the brick kernel addresses the weights with 32-bit byte offsets
     if (brick_ok(g) && 27LL * cout * cin * 2 < (1LL << 32)) {
         // widest output tile that still leaves >= 512 workgroups (two per CU)
         const long long bricks = g.nvox / (kTD * kTH * kTW);
         const int c16 = cout / 16;
-        if (c16 % 6 == 0 && bricks * (c16 / 6) >= 512) return conv_tile_launch<6, SIGN, ACT>(g, x, cin, w, bias, cout, y, s);
-        if (c16 % 4 == 0 && bricks * (c16 / 4) >= 512) return conv_tile_launch<4, SIGN, ACT>(g, x, cin, w, bias, cout, y, s);
+        if (c16 % 6 == 0 && bricks * (c16 / 6) >= 512) return conv_tile_launch<6, SIGN, ACT>(g, x, cin, w, bias, cout, y, gate, s);
+        if (c16 % 4 == 0 && bricks * (c16 / 4) >= 512) return conv_tile_launch<4, SIGN, ACT>(g, x, cin, w, bias, cout, y, gate, s);
         // a grid of fewer workgroups than CUs takes 16-channel tiles (twice the workgroups)
-        if (bricks * (c16 / 2) < 256) return conv_tile_launch<1, SIGN, ACT>(g, x, cin, w, bias, cout, y, s);
-        return conv_tile_launch<2, SIGN, ACT>(g, x, cin, w, bias, cout, y, s);
+        if (bricks * (c16 / 2) < 256) return conv_tile_launch<1, SIGN, ACT>(g, x, cin, w, bias, cout, y, gate, s);
+        return conv_tile_launch<2, SIGN, ACT>(g, x, cin, w, bias, cout, y, gate, s);
     }
     const unsigned mb = (unsigned)((g.nvox + 63) / 64);
     if (cout % 64 == 0)
-        k_conv_fwd<4, SIGN, ACT><<<dim3(mb, cout / 64), 256, 0, s>>>(g, x, cin, w, bias, cout, y);
+        k_conv_fwd<4, SIGN, ACT><<<dim3(mb, cout / 64), 256, 0, s>>>(g, x, cin, w, bias, cout, y, gate);
     else
-        k_conv_fwd<2, SIGN, ACT><<<dim3(mb, cout / 32), 256, 0, s>>>(g, x, cin, w, bias, cout, y);
+        k_conv_fwd<2, SIGN, ACT><<<dim3(mb, cout / 32), 256, 0, s>>>(g, x, cin, w, bias, cout, y, gate);
     return launched();
 }
 
@@ -1334,8 +1350,9 @@ int cmnn_conv3d_fwd(const cmnn_geom* g, const void* x, int32_t cin, const void* 
     const G gg = make_g(g);
     hipStream_t s = (hipStream_t)hip_stream;
     if (act == CMNN_ACT_LEAKY)
-        return conv_dispatch<1, CMNN_ACT_LEAKY>(gg, (const bf16*)x, cin, (const bf16*)w, bias, cout, (bf16*)y, s);
-    return conv_dispatch<1, CMNN_ACT_NONE>(gg, (const bf16*)x, cin, (const bf16*)w, bias, cout, (bf16*)y, s);
+        return conv_dispatch<1, CMNN_ACT_LEAKY>(gg, (const bf16*)x, cin, (const bf16*)w, bias, cout, (bf16*)y, nullptr,
+                                                s);
+    return conv_dispatch<1, CMNN_ACT_NONE>(gg, (const bf16*)x, cin, (const bf16*)w, bias, cout, (bf16*)y, nullptr, s);
 }
 
 int cmnn_conv3d_bwd_data(const cmnn_geom* g, const void* dy, int32_t cout, const void* w_t, int32_t cin, void* dx,
@@ -1347,7 +1364,21 @@ int cmnn_conv3d_bwd_data(const cmnn_geom* g, const void* dy, int32_t cout, const
     // the data gradient is the forward kernel with negated tap offsets, input dy
     // (cout channels), transposed weights [27][cin][cout] and cin outputs
     return conv_dispatch<-1, CMNN_ACT_NONE>(gg, (const bf16*)dy, cout, (const bf16*)w_t, nullptr, cin, (bf16*)dx,
-                                            (hipStream_t)hip_stream);
+                                            nullptr, (hipStream_t)hip_stream);
+}
+
+int cmnn_conv3d_bwd_data_act(const cmnn_geom* g, const void* dy, int32_t cout, const void* w_t, int32_t cin,
+                             const void* gate, int32_t act, void* dx, void* hip_stream)
+{
+    if (!geom_ok(g) || !chan_ok(cin) || !chan_ok(cout) || !dy || !w_t || !dx) return CMNN_EINVAL;
+    if (!al16(dy) || !al16(w_t) || act < CMNN_ACT_NONE || act > CMNN_ACT_LEAKY) return CMNN_EINVAL;
+    if (act == CMNN_ACT_LEAKY && (!gate || !al16(gate) || gate == dx)) return CMNN_EINVAL;
+    const G gg = make_g(g);
+    if (act == CMNN_ACT_NONE)
+        return conv_dispatch<-1, CMNN_ACT_NONE>(gg, (const bf16*)dy, cout, (const bf16*)w_t, nullptr, cin, (bf16*)dx,
+                                                nullptr, (hipStream_t)hip_stream);
+    return conv_dispatch<-1, CMNN_ACT_LEAKY>(gg, (const bf16*)dy, cout, (const bf16*)w_t, nullptr, cin, (bf16*)dx,
+                                             (const bf16*)gate, (hipStream_t)hip_stream);
 }
 
 int cmnn_conv3d_bwd_weight_workspace(const cmnn_geom* g, int32_t cin, int32_t cout, size_t* bytes)

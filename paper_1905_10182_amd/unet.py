@@ -170,10 +170,14 @@ class UNet3D:
             self._mws = self.torch.empty((need + 3) // 4, dtype=self.torch.float32, device=self.device)
         return self._mws
 
-    def _conv_bwd(self, name, g, x, y, dy, level, need_dx=True):
-        """dy: gradient w.r.t. the layer output y; returns the gradient w.r.t. x."""
+    def _conv_bwd(self, name, g, x, y, dy, level, need_dx=True, pre=False, into=None):
+        """dy: gradient w.r.t. the layer output y, or with pre=True already
+        w.r.t. its pre-activation.  Returns the gradient w.r.t. x; with into =
+        the name of the layer whose activation output x is, the data-gradient
+        kernel applies that activation's gradient too and returns the gradient
+        w.r.t. that layer's pre-activation."""
         L = self.layers[name]
-        if L["act"] != cmnn.ACT_NONE:
+        if L["act"] != cmnn.ACT_NONE and not pre:
             dpre = self.torch.empty_like(dy)
             cmnn.act_bwd(y, dy, dpre, L["act"])
         else:
@@ -182,7 +186,10 @@ class UNet3D:
         if not need_dx:
             return None
         dx = self._t(g.n, level, L["cin"])
-        cmnn.conv_bwd_data(g, dpre, L["cout"], L["wt"], L["cin"], dx)
+        if into is not None:
+            cmnn.conv_bwd_data_act(g, dpre, L["cout"], L["wt"], L["cin"], x, self.layers[into]["act"], dx)
+        else:
+            cmnn.conv_bwd_data(g, dpre, L["cout"], L["wt"], L["cin"], dx)
         return dx
 
     def backward(self, dy):
@@ -192,15 +199,19 @@ class UNet3D:
         g0, g1, g2 = self.geoms(n)
         w0, w1, w2 = self.widths
         self._workspace(n)
-        d = self._conv_bwd("head", g0, A["d0b"], A["y"], dy, 0)
-        d = self._conv_bwd("d0b", g0, A["d0a"], A["d0b"], d, 0)
-        d = self._conv_bwd("d0a", g0, A["c0"], A["d0a"], d, 0)
+        # where a layer's input is the activation output of the layer below
+        # (not a concatenation, pooling or sum), its data gradient also applies
+        # that activation's gradient ("into"), and the layer below takes it as
+        # its pre-activation gradient (pre=True)
+        d = self._conv_bwd("head", g0, A["d0b"], A["y"], dy, 0, into="d0b")
+        d = self._conv_bwd("d0b", g0, A["d0a"], A["d0b"], d, 0, pre=True, into="d0a")
+        d = self._conv_bwd("d0a", g0, A["c0"], A["d0a"], d, 0, pre=True)
         ds0c, du0 = self._t(n, 0, w0), self._t(n, 0, w1)
         cmnn.concat_bwd(cmnn.nvox(g0), d, w0, w1, ds0c, du0)
         d = self._t(n, 1, w1)
         cmnn.up2_bwd(g1, du0, w1, d)
-        d = self._conv_bwd("d1b", g1, A["d1a"], A["d1b"], d, 1)
-        d = self._conv_bwd("d1a", g1, A["c1"], A["d1a"], d, 1)
+        d = self._conv_bwd("d1b", g1, A["d1a"], A["d1b"], d, 1, into="d1a")
+        d = self._conv_bwd("d1a", g1, A["c1"], A["d1a"], d, 1, pre=True)
         ds1c, du1 = self._t(n, 1, w1), self._t(n, 1, w2)
         cmnn.concat_bwd(cmnn.nvox(g1), d, w1, w2, ds1c, du1)
         d = self._t(n, 2, w2)
@@ -217,14 +228,14 @@ class UNet3D:
         cmnn.pool2_bwd(g1, d, w1, ds1p)
         ds1 = self._t(n, 1, w1)
         cmnn.add(ds1c, ds1p, ds1)
-        d = self._conv_bwd("e1b", g1, A["e1a"], A["s1"], ds1, 1)
-        d = self._conv_bwd("e1a", g1, A["p0"], A["e1a"], d, 1)
+        d = self._conv_bwd("e1b", g1, A["e1a"], A["s1"], ds1, 1, into="e1a")
+        d = self._conv_bwd("e1a", g1, A["p0"], A["e1a"], d, 1, pre=True)
         ds0p = self._t(n, 0, w0)
         cmnn.pool2_bwd(g0, d, w0, ds0p)
         ds0 = self._t(n, 0, w0)
         cmnn.add(ds0c, ds0p, ds0)
-        d = self._conv_bwd("e0b", g0, A["e0a"], A["s0"], ds0, 0)
-        self._conv_bwd("e0a", g0, A["x"], A["e0a"], d, 0, need_dx=False)
+        d = self._conv_bwd("e0b", g0, A["e0a"], A["s0"], ds0, 0, into="e0a")
+        self._conv_bwd("e0a", g0, A["x"], A["e0a"], d, 0, need_dx=False, pre=True)
 
     def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0, clip=None):
         """One Adam update from self.grads.  clip: global gradient-norm limit

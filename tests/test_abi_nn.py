@@ -61,6 +61,16 @@ def test_conv_forward_and_data_gradient_validation(lib):
     assert lib.cmnn_conv3d_bwd_data(g(), P, 32, NULL, 32, P, NULL) == EINVAL
     assert lib.cmnn_conv3d_bwd_data(g(w=0), P, 32, P2, 32, P, NULL) == EINVAL
 
+    # the data gradient with the activation gradient fused in
+    L = lib.cmnn_conv3d_bwd_data_act
+    assert L(g(), P, 32, P2, 40, P2, 1, P, NULL) == EINVAL        # channels not a multiple of 32
+    assert L(g(), ODD, 32, P2, 32, P2, 1, P, NULL) == EINVAL      # misaligned dy
+    assert L(g(), P, 32, P2, 32, NULL, 1, P, NULL) == EINVAL      # leaky needs its gate
+    assert L(g(), P, 32, P2, 32, ODD, 1, P, NULL) == EINVAL       # misaligned gate
+    assert L(g(), P, 32, P2, 32, P, 1, P, NULL) == EINVAL         # gate aliasing dx
+    assert L(g(), P, 32, P2, 32, P2, 2, P, NULL) == EINVAL        # unknown activation
+    assert L(g(w=0), P, 32, P2, 32, P2, 1, P, NULL) == EINVAL
+
 
 def test_weight_gradient_workspace_and_validation(lib):
     n = ctypes.c_size_t()

@@ -98,6 +98,20 @@ def test_conv_backward(torch, nn, dims, cin, cout, per):
     r = close_bf16(dx.float().cpu().numpy(), rdx, magx)
     log(f"  dx: max error / bound = {r:.3f}")
     assert r <= 1.0
+    # the same with the producing layer's activation gradient fused in: gate is
+    # that layer's leaky-ReLU output (mixed signs, some exact zeros)
+    gv = randn(dims + (cin,), 9)
+    gv[np.abs(gv) < 0.1] = 0.0
+    gate, gr = bf16_tensor(torch, gv)
+    dxa = torch.empty_like(dx)
+    nn.conv_bwd_data_act(g, dy, cout, wt, cin, gate, nn.ACT_LEAKY, dxa)
+    rdxa = C.leaky_grad_from_output(gr, rdx)
+    magxa = C.leaky_grad_from_output(gr, magx)
+    r = close_bf16(dxa.float().cpu().numpy(), rdxa, magxa)
+    log(f"  dx with the activation gradient: max error / bound = {r:.3f}")
+    assert r <= 1.0
+    nn.conv_bwd_data_act(g, dy, cout, wt, cin, gate, nn.ACT_NONE, dxa)
+    assert torch.equal(dxa, dx)  # no activation: the plain data gradient, bitwise
     ws = torch.empty(nn.conv_bwd_weight_workspace(g, cin, cout) // 4, dtype=torch.float32, device="cuda:0")
     dw = torch.empty((27, cout, cin), dtype=torch.float32, device="cuda:0")
     db = torch.empty((cout,), dtype=torch.float32, device="cuda:0")
