@@ -1045,16 +1045,32 @@ __global__ __launch_bounds__(256) void k_mse_part(long long nvox, const bf16* __
     }
 }
 
-__global__ void k_mse_final(const float* __restrict__ part, int nb, int creal, float* __restrict__ out)
+// One workgroup of 256: thread t adds partials t, t + 256, ... in order, then
+// the 256 sums are added pairwise in LDS (a fixed order: deterministic).
+__global__ __launch_bounds__(256) void k_mse_final(const float* __restrict__ part, int nb, int creal,
+                                                   float* __restrict__ out)
 {
-    if (threadIdx.x != 0) return;
+    __shared__ float sa[256], sb[256];
+    const int t = threadIdx.x;
     float a = 0.f, b = 0.f;
-    for (int i = 0; i < nb; ++i) {
+    for (int i = t; i < nb; i += 256) {
         a += part[2 * i];
         b += part[2 * i + 1];
     }
-    out[0] = b > 0.f ? a / (b * creal) : 0.f;  // loss
-    out[1] = b * creal;                        // normaliser, read by k_mse_grad
+    sa[t] = a;
+    sb[t] = b;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) {
+            sa[t] += sa[t + h];
+            sb[t] += sb[t + h];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        out[0] = sb[0] > 0.f ? sa[0] / (sb[0] * creal) : 0.f;  // loss
+        out[1] = sb[0] * creal;                                 // normaliser, read by k_mse_grad
+    }
 }
 
 __global__ void k_mse_grad(long long nvox, const bf16* __restrict__ pred, int c, int creal,
@@ -1086,8 +1102,8 @@ __global__ void k_adam(long long n, float* __restrict__ p, const float* __restri
     }
 }
 
-// Global gradient-norm clipping: per-block partial sums of g^2, a single
-// thread that forms the norm and the scale min(1, max_norm / norm) (0 for a
+// Global gradient-norm clipping: per-block partial sums of g^2, one workgroup
+// that sums them and forms the norm and the scale min(1, max_norm / norm) (0 for a
 // non-finite norm, which turns the update into a no-gradient step), then an
 // in-place scale read from device memory (no host round trip).
 constexpr int kClipBlocks = 512;
@@ -1109,12 +1125,22 @@ __global__ __launch_bounds__(256) void k_sumsq_part(long long n, const float* __
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-__global__ void k_clip_final(const float* __restrict__ part, int nb, float max_norm, float* __restrict__ out)
+// One workgroup of 256, FP64 sums in a fixed order (as k_mse_final).
+__global__ __launch_bounds__(256) void k_clip_final(const float* __restrict__ part, int nb, float max_norm,
+                                                    float* __restrict__ out)
 {
-    if (threadIdx.x != 0) return;
+    __shared__ double sh[256];
+    const int t = threadIdx.x;
     double a = 0.0;
-    for (int i = 0; i < nb; ++i) a += part[i];
-    const float norm = (float)sqrt(a);
+    for (int i = t; i < nb; i += 256) a += part[i];
+    sh[t] = a;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) sh[t] += sh[t + h];
+        __syncthreads();
+    }
+    if (t != 0) return;
+    const float norm = (float)sqrt(sh[0]);
     float scale = 1.f;
     if (!(norm < INFINITY)) scale = 0.f;
     else if (max_norm > 0.f && norm > max_norm) scale = max_norm / norm;
@@ -1196,7 +1222,8 @@ __global__ void k_chmean_final(const float* __restrict__ part, long long vps, in
         const long long n = i / c;
         const int ch = (int)(i % c);
         float s = 0.f;
-        for (int p = 0; p < parts; ++p) s += part[(n * parts + p) * c + ch];
+#pragma unroll 16
+        for (int p = 0; p < parts; ++p) s += part[(n * parts + p) * c + ch];  // loads in flight together
         mean[i] = s / (float)vps;
     }
 }
@@ -1588,7 +1615,7 @@ int cmnn_mse(size_t nvox, const void* pred, int32_t c, int32_t creal, const floa
     k_mse_part<<<kMseBlocks, 256, 0, s>>>((long long)nvox, (const bf16*)pred, c, creal, target, weight, part);
     if (launched()) return CMNN_EHIP;
     // loss_out[0] = loss, loss_out[1] = normaliser (callers pass two floats)
-    k_mse_final<<<1, 64, 0, s>>>(part, kMseBlocks, creal, loss_out);
+    k_mse_final<<<1, 256, 0, s>>>(part, kMseBlocks, creal, loss_out);
     if (launched()) return CMNN_EHIP;
     if (dpred) {
         k_mse_grad<<<grid_for((long long)nvox * c), 256, 0, s>>>((long long)nvox, (const bf16*)pred, c, creal, target,
@@ -1615,7 +1642,7 @@ int cmnn_clip_grad_norm(size_t n, float* grad, float max_norm, float* norm_out, 
     float* part = (float*)workspace;
     k_sumsq_part<<<kClipBlocks, 256, 0, s>>>((long long)n, grad, part);
     if (launched()) return CMNN_EHIP;
-    k_clip_final<<<1, 64, 0, s>>>(part, kClipBlocks, max_norm, norm_out);
+    k_clip_final<<<1, 256, 0, s>>>(part, kClipBlocks, max_norm, norm_out);
     if (launched()) return CMNN_EHIP;
     k_scale<<<grid_for((long long)n), 256, 0, s>>>((long long)n, grad, norm_out);
     return launched();
