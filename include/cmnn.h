@@ -108,6 +108,40 @@ int cmnn_up2_bwd(const cmnn_geom* g, const void* dy, int32_t c, void* dx, void* 
 int cmnn_concat_fwd(size_t nvox, const void* a, int32_t ca, const void* b, int32_t cb, void* y, void* hip_stream);
 int cmnn_concat_bwd(size_t nvox, const void* dy, int32_t ca, int32_t cb, void* da, void* db, void* hip_stream);
 
+/* Skip-connection joins of the U-Net, each one pass in place of the separate
+ * upsampling or pooling, concatenation, sum and activation-gradient calls it
+ * replaces.  Channel counts are multiples of 32; a channel stride ld (the
+ * distance in elements between two voxels' rows, >= the channel count, a
+ * multiple of 8) lets a part of a concatenation be read in place: pass the
+ * pointer to its first channel.  Outputs must not overlap inputs.  act is
+ * CMNN_ACT_NONE (gate ignored) or CMNN_ACT_LEAKY (gate: the activation output
+ * of the layer whose gradient this is; the FP32 result is multiplied by 0.1
+ * where gate <= 0 before the one BF16 rounding).  EINVAL on a NULL or
+ * misaligned pointer, a bad channel count or stride, or more than 2^31 - 1
+ * fine voxels. */
+
+/* Decoder join, forward: y = [skip | up2(x)].  g is the coarse geometry of x
+ * [..][cx]; skip [..][cs] and y [..][cs + cx] are at the fine level (2d, 2h,
+ * 2w).  Bitwise cmnn_up2_fwd then cmnn_concat_fwd, without the upsampled
+ * tensor in between. */
+int cmnn_up2_concat_fwd(const cmnn_geom* g, const void* skip, int32_t cs, const void* x, int32_t cx, void* y,
+                        void* hip_stream);
+
+/* Decoder join, backward of its upsampled part: dx [..][c] (coarse) = the sum
+ * over each coarse voxel's 8 fine children of dy, channel stride ldy (the
+ * upsampled part of the concatenation's gradient), times act'(gate), gate
+ * coarse [..][c].  g is the coarse geometry. */
+int cmnn_up2_bwd_act(const cmnn_geom* g, const void* dy, int32_t ldy, int32_t c, const void* gate, int32_t act,
+                     void* dx, void* hip_stream);
+
+/* Encoder join, backward: dx [..][c] (fine) = act'(gate) * (dy / 8 + skip),
+ * dy coarse [..][c] the gradient of the 2x2x2 average pool of this level's
+ * output, skip (channel stride ldskip; NULL: no term) the skip part of the
+ * decoder concatenation's gradient, gate fine [..][c].  g is the fine
+ * geometry (d, h, w even). */
+int cmnn_pool2_bwd_add_act(const cmnn_geom* g, const void* dy, int32_t c, const void* skip, int32_t ldskip,
+                           const void* gate, int32_t act, void* dx, void* hip_stream);
+
 /* Per-sample channel mean broadcast over the voxels (global context):
  * y[n][v][c] = (1/V) sum_v' x[n][v'][c], V = d*h*w, c <= 256.  The map is a
  * symmetric projection, so the same call on dy gives the gradient.
@@ -115,6 +149,23 @@ int cmnn_concat_bwd(size_t nvox, const void* dy, int32_t ca, int32_t cb, void* d
 int cmnn_channel_mean_workspace(const cmnn_geom* g, int32_t c, size_t* bytes);
 int cmnn_channel_mean(const cmnn_geom* g, const void* x, int32_t c, void* y, void* workspace, size_t workspace_bytes,
                       void* hip_stream);
+
+/* Global-context join of the U-Net bottleneck, forward: y [..][2c] =
+ * [x | the per-sample channel means of x broadcast over the voxels], bitwise
+ * cmnn_channel_mean then cmnn_concat_fwd.  c a multiple of 32, <= 256;
+ * workspace: cmnn_channel_mean_workspace(g, c) bytes. */
+int cmnn_channel_mean_concat(const cmnn_geom* g, const void* x, int32_t c, void* y, void* workspace,
+                             size_t workspace_bytes, void* hip_stream);
+
+/* Its backward: dx [..][c] = act'(gate) * (skip + the broadcast per-sample
+ * channel means of dy) -- the mean map is its own adjoint -- where dy and
+ * skip are the two parts of the concatenation's gradient, read in place with
+ * channel strides ldy and ldskip, and gate [..][c] is the activation output of
+ * the layer that produced x (rules of the skip-connection joins above).
+ * workspace: cmnn_channel_mean_workspace(g, c) bytes. */
+int cmnn_channel_mean_add_act(const cmnn_geom* g, const void* dy, int32_t ldy, int32_t c, const void* skip,
+                              int32_t ldskip, const void* gate, int32_t act, void* dx, void* workspace,
+                              size_t workspace_bytes, void* hip_stream);
 
 /* y = a + b elementwise (BF16), n elements. */
 int cmnn_add(size_t n, const void* a, const void* b, void* y, void* hip_stream);

@@ -14,7 +14,9 @@ ACT_NONE, ACT_LEAKY = 0, 1
 EXPORTS = ["cmnn_conv3d_fwd", "cmnn_conv3d_bwd_data", "cmnn_conv3d_bwd_data_act", "cmnn_conv3d_bwd_weight_workspace",
            "cmnn_conv3d_bwd_weight", "cmnn_conv3d_bwd_weight_noalloc",
            "cmnn_act_bwd", "cmnn_pool2_fwd", "cmnn_pool2_bwd", "cmnn_up2_fwd", "cmnn_up2_bwd", "cmnn_concat_fwd",
-           "cmnn_concat_bwd", "cmnn_add", "cmnn_channel_mean_workspace", "cmnn_channel_mean", "cmnn_mse_workspace",
+           "cmnn_concat_bwd", "cmnn_up2_concat_fwd", "cmnn_up2_bwd_act", "cmnn_pool2_bwd_add_act",
+           "cmnn_add", "cmnn_channel_mean_workspace", "cmnn_channel_mean",
+           "cmnn_channel_mean_concat", "cmnn_channel_mean_add_act", "cmnn_mse_workspace",
            "cmnn_mse", "cmnn_clip_grad_norm_workspace", "cmnn_clip_grad_norm", "cmnn_adam", "cmnn_pack_weights",
            "cmnn_pack_channels", "cmnn_unpack_channels"]
 
@@ -59,9 +61,14 @@ def load_library():
         f.argtypes = [G, vp, i32, vp, vp]
     lib.cmnn_concat_fwd.argtypes = [sz, vp, i32, vp, i32, vp, vp]
     lib.cmnn_concat_bwd.argtypes = [sz, vp, i32, i32, vp, vp, vp]
+    lib.cmnn_up2_concat_fwd.argtypes = [G, vp, i32, vp, i32, vp, vp]
+    lib.cmnn_up2_bwd_act.argtypes = [G, vp, i32, i32, vp, i32, vp, vp]
+    lib.cmnn_pool2_bwd_add_act.argtypes = [G, vp, i32, vp, i32, vp, i32, vp, vp]
     lib.cmnn_add.argtypes = [sz, vp, vp, vp, vp]
     lib.cmnn_channel_mean_workspace.argtypes = [G, i32, ctypes.POINTER(sz)]
     lib.cmnn_channel_mean.argtypes = [G, vp, i32, vp, vp, sz, vp]
+    lib.cmnn_channel_mean_concat.argtypes = [G, vp, i32, vp, vp, sz, vp]
+    lib.cmnn_channel_mean_add_act.argtypes = [G, vp, i32, i32, vp, i32, vp, i32, vp, vp, sz, vp]
     lib.cmnn_mse_workspace.argtypes = [sz, ctypes.POINTER(sz)]
     lib.cmnn_mse.argtypes = [sz, vp, i32, i32, vp, vp, vp, vp, vp, sz, vp]
     lib.cmnn_clip_grad_norm_workspace.argtypes = [sz, ctypes.POINTER(sz)]
@@ -157,6 +164,31 @@ def concat_bwd(nv, dy, ca, cb, da, db):
     _check(load_library().cmnn_concat_bwd(nv, _p(dy), ca, cb, _p(da), _p(db), _s()), "concat_bwd")
 
 
+def _part(t, off):
+    """Pointer to channel `off` of every voxel row of t (a channel part read in place)."""
+    return None if t is None else ctypes.c_void_p(t.data_ptr() + off * t.element_size())
+
+
+def up2_concat_fwd(g, skip, cs, x, cx, y):
+    """y = [skip | up2(x)] at the fine level; g is the coarse geometry of x."""
+    _check(load_library().cmnn_up2_concat_fwd(ctypes.byref(g), _p(skip), cs, _p(x), cx, _p(y), _s()),
+           "up2_concat_fwd")
+
+
+def up2_bwd_act(g, dy, off, ldy, c, gate, act, dx):
+    """dx (coarse) = act'(gate) * up2 gradient of channels [off, off + c) of
+    dy (fine, ldy channels per voxel); g is the coarse geometry."""
+    _check(load_library().cmnn_up2_bwd_act(ctypes.byref(g), _part(dy, off), ldy, c, _p(gate), act, _p(dx), _s()),
+           "up2_bwd_act")
+
+
+def pool2_bwd_add_act(g, dy, c, skip, off, ldskip, gate, act, dx):
+    """dx (fine) = act'(gate) * (pool2 gradient of dy + channels [off, off + c)
+    of skip, ldskip channels per voxel; skip None: no term); g is the fine geometry."""
+    _check(load_library().cmnn_pool2_bwd_add_act(ctypes.byref(g), _p(dy), c, _part(skip, off), ldskip, _p(gate),
+                                                 act, _p(dx), _s()), "pool2_bwd_add_act")
+
+
 def add(a, b, y):
     _check(load_library().cmnn_add(a.numel(), _p(a), _p(b), _p(y), _s()), "add")
 
@@ -170,6 +202,20 @@ def channel_mean_workspace(g, c):
 def channel_mean(g, x, c, y, ws):
     _check(load_library().cmnn_channel_mean(ctypes.byref(g), _p(x), c, _p(y), _p(ws), ws.numel() * ws.element_size(),
                                             _s()), "channel_mean")
+
+
+def channel_mean_concat(g, x, c, y, ws):
+    """y = [x | per-sample channel means of x, broadcast]."""
+    _check(load_library().cmnn_channel_mean_concat(ctypes.byref(g), _p(x), c, _p(y), _p(ws),
+                                                   ws.numel() * ws.element_size(), _s()), "channel_mean_concat")
+
+
+def channel_mean_add_act(g, dy, off, ldy, c, skip, skip_off, ldskip, gate, act, dx, ws):
+    """dx = act'(gate) * (channels [skip_off, +c) of skip + the broadcast channel
+    means of channels [off, +c) of dy); ldy, ldskip: channels per voxel row."""
+    _check(load_library().cmnn_channel_mean_add_act(ctypes.byref(g), _part(dy, off), ldy, c, _part(skip, skip_off),
+                                                    ldskip, _p(gate), act, _p(dx), _p(ws),
+                                                    ws.numel() * ws.element_size(), _s()), "channel_mean_add_act")
 
 
 def mse_workspace(nv):

@@ -1010,6 +1010,108 @@ __global__ void k_add8(long long n8, const u4* __restrict__ a, const u4* __restr
     }
 }
 
+// Skip-connection joins of the U-Net: one pass over the fine level each, in
+// place of the separate upsampling or pooling, concatenation, sum and
+// activation-gradient passes.  Channel counts are multiples of 32 and channel
+// strides multiples of 8, so every thread moves 8 channels (16 bytes).
+
+// y = [skip | up2(x)] at the fine level; g is the coarse geometry of x.
+__global__ void k_up2_concat_fwd8(G g, const bf16* __restrict__ skip, int cs, const bf16* __restrict__ x, int cx,
+                                  bf16* __restrict__ y)
+{
+    const int D = 2 * g.d, H = 2 * g.h, W = 2 * g.w, qs = cs / 8, q8 = (cs + cx) / 8;
+    GRID_STRIDE(i, 8 * g.nvox * q8)
+    {
+        const int q = (int)(i % q8);
+        const long long v = i / q8;
+        u4 e;
+        if (q < qs) {
+            e = *(const u4*)(skip + v * cs + 8 * q);
+        } else {
+            const int w = (int)(v % W);
+            long long r = v / W;
+            const int h = (int)(r % H);
+            r /= H;
+            const int d = (int)(r % D);
+            const long long n = r / D;
+            const long long p = ((n * g.d + d / 2) * g.h + h / 2) * g.w + w / 2;
+            e = *(const u4*)(x + p * cx + 8 * (q - qs));
+        }
+        *(u4*)(y + i * 8) = e;
+    }
+}
+
+// Leaky-ReLU slope at the activation output, applied to an FP32 gradient.
+__device__ __forceinline__ void act_grad8(const bf16* __restrict__ gate, int act, float (&f)[8])
+{
+    if (act != CMNN_ACT_LEAKY) return;
+    float t[8];
+    unpack8(*(const u4*)gate, t);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) f[e] = t[e] <= 0.f ? kLeak * f[e] : f[e];
+}
+
+// dx = act'(gate) * (up2 gradient of dy): dy is the upsampled part of a
+// concatenation's gradient (channel stride ldy), g the coarse geometry.
+__global__ void k_up2_bwd_act8(G g, const bf16* __restrict__ dy, int ldy, int c, const bf16* __restrict__ gate,
+                               int act, bf16* __restrict__ dx)
+{
+    const int H = 2 * g.h, W = 2 * g.w, q8 = c / 8;
+    GRID_STRIDE(i, g.nvox * q8)
+    {
+        const int q = (int)(i % q8);
+        long long r = i / q8;
+        const int w = (int)(r % g.w);
+        r /= g.w;
+        const int h = (int)(r % g.h);
+        r /= g.h;
+        const int d = (int)(r % g.d);
+        const long long n = r / g.d;
+        float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, f[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const long long v = ((n * (2 * g.d) + 2 * d + (k >> 2)) * H + 2 * h + ((k >> 1) & 1)) * W + 2 * w + (k & 1);
+            unpack8(*(const u4*)(dy + v * ldy + 8 * q), f);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) s[e] += f[e];
+        }
+        act_grad8(gate + i * 8, act, s);
+        *(u4*)(dx + i * 8) = pack8(s);
+    }
+}
+
+// dx = act'(gate) * (pool2 gradient of dy + skip): g is the fine geometry, dy
+// coarse, skip the skip part of a concatenation's gradient (channel stride
+// ldskip) or NULL.
+__global__ void k_pool2_bwd_add_act8(G g, const bf16* __restrict__ dy, int c, const bf16* __restrict__ skip,
+                                     int ldskip, const bf16* __restrict__ gate, int act, bf16* __restrict__ dx)
+{
+    const int q8 = c / 8;
+    GRID_STRIDE(i, g.nvox * q8)
+    {
+        const int q = (int)(i % q8);
+        const long long v = i / q8;
+        const int w = (int)(v % g.w);
+        long long r = v / g.w;
+        const int h = (int)(r % g.h);
+        r /= g.h;
+        const int d = (int)(r % g.d);
+        const long long n = r / g.d;
+        const long long p = ((n * (g.d / 2) + d / 2) * (g.h / 2) + h / 2) * (g.w / 2) + w / 2;
+        float f[8], t[8];
+        unpack8(*(const u4*)(dy + p * c + 8 * q), f);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) f[e] *= 0.125f;
+        if (skip) {
+            unpack8(*(const u4*)(skip + v * ldskip + 8 * q), t);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) f[e] += t[e];
+        }
+        act_grad8(gate + i * 8, act, f);
+        *(u4*)(dx + i * 8) = pack8(f);
+    }
+}
+
 // masked MSE: per-block partial (sum wt * sq, sum wt), then a single-block final
 constexpr int kMseBlocks = 1024;
 
@@ -1193,10 +1295,11 @@ __global__ void k_unpack_ch(long long nvox, const bf16* __restrict__ src, int c,
 // Per-sample channel means broadcast back over the voxels:
 // y[n][v][c] = (1/V) sum_v' x[n][v'][c].  The operator is a symmetric
 // projection, so the same two kernels also give its gradient.
-__global__ __launch_bounds__(256) void k_chmean_part(const bf16* __restrict__ x, long long vps, int c,
+__global__ __launch_bounds__(256) void k_chmean_part(const bf16* __restrict__ x, int ldx, long long vps, int c,
                                                      int parts, float* __restrict__ part)
 {
     // block (n, p): voxels [p * chunk, (p + 1) * chunk) of sample n; thread t sums channel t % c
+    // (voxel rows ldx channels apart)
     __shared__ float sh[256];
     const int n = blockIdx.x / parts, p = blockIdx.x % parts;
     const long long chunk = (vps + parts - 1) / parts;
@@ -1204,7 +1307,7 @@ __global__ __launch_bounds__(256) void k_chmean_part(const bf16* __restrict__ x,
     const int t = threadIdx.x, rpi = 256 / c, ch = t % c, roff = t / c;
     float s = 0.f;
     if (roff < rpi)
-        for (long long v = v0 + roff; v < v1; v += rpi) s += (float)x[((long long)n * vps + v) * c + ch];
+        for (long long v = v0 + roff; v < v1; v += rpi) s += (float)x[((long long)n * vps + v) * ldx + ch];
     sh[t] = s;
     __syncthreads();
     if (t < c) {
@@ -1239,6 +1342,47 @@ __global__ void k_chmean_bcast8(const float* __restrict__ mean, long long vps, i
         float f[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) f[e] = mean[n * c + 8 * q + e];
+        *(u4*)(y + i * 8) = pack8(f);
+    }
+}
+
+// Joins of the U-Net bottleneck's global context (channel counts multiples of
+// 32): y = [x | broadcast mean] for the forward concatenation, and
+// y = act'(gate) * (skip + broadcast mean) for its gradient.
+__global__ void k_chmean_concat8(const float* __restrict__ mean, long long vps, int c, const bf16* __restrict__ x,
+                                 bf16* __restrict__ y, long long total8)
+{
+    const int qc = c / 8, q8 = 2 * qc;
+    GRID_STRIDE(i, total8)
+    {
+        const int q = (int)(i % q8);
+        const long long v = i / q8;
+        if (q < qc) {
+            *(u4*)(y + i * 8) = *(const u4*)(x + v * c + 8 * q);
+        } else {
+            const long long n = v / vps;
+            float f[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) f[e] = mean[n * c + 8 * (q - qc) + e];
+            *(u4*)(y + i * 8) = pack8(f);
+        }
+    }
+}
+
+__global__ void k_chmean_add_act8(const float* __restrict__ mean, long long vps, int c,
+                                  const bf16* __restrict__ skip, int ldskip, const bf16* __restrict__ gate, int act,
+                                  bf16* __restrict__ y, long long total8)
+{
+    const int q8 = c / 8;
+    GRID_STRIDE(i, total8)
+    {
+        const int q = (int)(i % q8);
+        const long long v = i / q8, n = v / vps;
+        float f[8], t[8];
+        unpack8(*(const u4*)(skip + v * ldskip + 8 * q), t);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) f[e] = mean[n * c + 8 * q + e] + t[e];
+        act_grad8(gate + i * 8, act, f);
         *(u4*)(y + i * 8) = pack8(f);
     }
 }
@@ -1363,6 +1507,29 @@ int static_scratch(void** out)
     }
     *out = g_scratch_ptr[dev];
     return CMNN_OK;
+}
+
+// the fine level of a coarse geometry must fit the voxel limit too
+bool coarse_ok(const cmnn_geom* g) { return geom_ok(g) && 8LL * g->n * g->d * g->h * g->w <= 0x7fffffffLL; }
+bool ld_ok(int ld, int c) { return ld >= c && ld % 8 == 0; }
+bool gate_ok(const void* gate, int act)
+{
+    if (act == CMNN_ACT_NONE) return true;
+    return act == CMNN_ACT_LEAKY && gate && al16(gate);
+}
+
+// Per-sample channel means of x (voxel rows ldx channels apart) into
+// workspace: partial sums, then the means after them; returns the means.
+const float* channel_means(const cmnn_geom* g, const void* x, int ldx, int c, void* workspace, hipStream_t s)
+{
+    const long long vps = (long long)g->d * g->h * g->w;
+    k_chmean_part<<<(unsigned)(g->n * kMeanParts), 256, 0, s>>>((const bf16*)x, ldx, vps, c, kMeanParts,
+                                                                 (float*)workspace);
+    if (launched()) return nullptr;
+    float* mean = (float*)workspace + (size_t)g->n * kMeanParts * c;
+    k_chmean_final<<<grid_for((long long)g->n * c), 256, 0, s>>>((const float*)workspace, vps, c, g->n, kMeanParts,
+                                                                 mean);
+    return launched() ? nullptr : mean;
 }
 
 }  // namespace
@@ -1556,6 +1723,41 @@ int cmnn_concat_bwd(size_t nvox, const void* dy, int32_t ca, int32_t cb, void* d
     return launched();
 }
 
+int cmnn_up2_concat_fwd(const cmnn_geom* g, const void* skip, int32_t cs, const void* x, int32_t cx, void* y,
+                        void* hip_stream)
+{
+    if (!coarse_ok(g) || !chan_ok(cs) || !chan_ok(cx) || !skip || !x || !y || !al16(skip) || !al16(x) || !al16(y))
+        return CMNN_EINVAL;
+    const G gg = make_g(g);
+    k_up2_concat_fwd8<<<grid_for(8 * gg.nvox * (cs + cx) / 8), 256, 0, (hipStream_t)hip_stream>>>(
+        gg, (const bf16*)skip, cs, (const bf16*)x, cx, (bf16*)y);
+    return launched();
+}
+
+int cmnn_up2_bwd_act(const cmnn_geom* g, const void* dy, int32_t ldy, int32_t c, const void* gate, int32_t act,
+                     void* dx, void* hip_stream)
+{
+    if (!coarse_ok(g) || !chan_ok(c) || !ld_ok(ldy, c) || !dy || !dx || !al16(dy) || !al16(dx) || !gate_ok(gate, act))
+        return CMNN_EINVAL;
+    const G gg = make_g(g);
+    k_up2_bwd_act8<<<grid_for(gg.nvox * c / 8), 256, 0, (hipStream_t)hip_stream>>>(
+        gg, (const bf16*)dy, ldy, c, (const bf16*)gate, act, (bf16*)dx);
+    return launched();
+}
+
+int cmnn_pool2_bwd_add_act(const cmnn_geom* g, const void* dy, int32_t c, const void* skip, int32_t ldskip,
+                           const void* gate, int32_t act, void* dx, void* hip_stream)
+{
+    if (!geom_ok(g) || (g->d | g->h | g->w) & 1 || !chan_ok(c) || !dy || !dx || !al16(dy) || !al16(dx) ||
+        !gate_ok(gate, act))
+        return CMNN_EINVAL;
+    if (skip && (!al16(skip) || !ld_ok(ldskip, c))) return CMNN_EINVAL;
+    const G gg = make_g(g);
+    k_pool2_bwd_add_act8<<<grid_for(gg.nvox * c / 8), 256, 0, (hipStream_t)hip_stream>>>(
+        gg, (const bf16*)dy, c, (const bf16*)skip, ldskip, (const bf16*)gate, act, (bf16*)dx);
+    return launched();
+}
+
 int cmnn_add(size_t n, const void* a, const void* b, void* y, void* hip_stream)
 {
     if (!a || !b || !y) return CMNN_EINVAL;
@@ -1584,7 +1786,8 @@ int cmnn_channel_mean(const cmnn_geom* g, const void* x, int32_t c, void* y, voi
     const G gg = make_g(g);
     hipStream_t s = (hipStream_t)hip_stream;
     const long long vps = (long long)g->d * g->h * g->w;
-    k_chmean_part<<<(unsigned)(g->n * kMeanParts), 256, 0, s>>>((const bf16*)x, vps, c, kMeanParts, (float*)workspace);
+    k_chmean_part<<<(unsigned)(g->n * kMeanParts), 256, 0, s>>>((const bf16*)x, c, vps, c, kMeanParts,
+                                                                 (float*)workspace);
     if (launched()) return CMNN_EHIP;
     if (c % 8 == 0 && al16(y)) {
         float* mean = (float*)workspace + (size_t)g->n * kMeanParts * c;
@@ -1595,6 +1798,40 @@ int cmnn_channel_mean(const cmnn_geom* g, const void* x, int32_t c, void* y, voi
         return launched();
     }
     k_chmean_bcast<<<grid_for(gg.nvox * c), 256, 0, s>>>((const float*)workspace, vps, c, g->n, kMeanParts, (bf16*)y);
+    return launched();
+}
+
+int cmnn_channel_mean_concat(const cmnn_geom* g, const void* x, int32_t c, void* y, void* workspace,
+                             size_t workspace_bytes, void* hip_stream)
+{
+    size_t need = 0;
+    if (cmnn_channel_mean_workspace(g, c, &need) != CMNN_OK || !chan_ok(c) || !x || !y || !al16(x) || !al16(y) ||
+        !workspace || workspace_bytes < need)
+        return CMNN_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const float* mean = channel_means(g, x, c, c, workspace, s);
+    if (!mean) return CMNN_EHIP;
+    const long long total8 = make_g(g).nvox * 2 * c / 8;
+    k_chmean_concat8<<<grid_for(total8), 256, 0, s>>>(mean, (long long)g->d * g->h * g->w, c, (const bf16*)x,
+                                                      (bf16*)y, total8);
+    return launched();
+}
+
+int cmnn_channel_mean_add_act(const cmnn_geom* g, const void* dy, int32_t ldy, int32_t c, const void* skip,
+                              int32_t ldskip, const void* gate, int32_t act, void* dx, void* workspace,
+                              size_t workspace_bytes, void* hip_stream)
+{
+    size_t need = 0;
+    if (cmnn_channel_mean_workspace(g, c, &need) != CMNN_OK || !chan_ok(c) || !ld_ok(ldy, c) || !ld_ok(ldskip, c) ||
+        !dy || !skip || !dx || !al16(dy) || !al16(skip) || !al16(dx) || !gate_ok(gate, act) || !workspace ||
+        workspace_bytes < need)
+        return CMNN_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const float* mean = channel_means(g, dy, ldy, c, workspace, s);
+    if (!mean) return CMNN_EHIP;
+    const long long total8 = make_g(g).nvox * c / 8;
+    k_chmean_add_act8<<<grid_for(total8), 256, 0, s>>>(mean, (long long)g->d * g->h * g->w, c, (const bf16*)skip,
+                                                       ldskip, (const bf16*)gate, act, (bf16*)dx, total8);
     return launched();
 }
 

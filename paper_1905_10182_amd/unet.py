@@ -131,21 +131,15 @@ class UNet3D:
         A["p1"] = self._t(n, 2, w1)
         cmnn.pool2_fwd(g1, A["s1"], w1, A["p1"])
         A["ma"] = self._conv("ma", g2, A["p1"], 2)
-        gm = self._t(n, 2, w2)
-        cmnn.channel_mean(g2, A["ma"], w2, gm, self._mean_ws(g2, w2))
         A["cm"] = self._t(n, 2, 2 * w2)
-        cmnn.concat_fwd(cmnn.nvox(g2), A["ma"], w2, gm, w2, A["cm"])
+        cmnn.channel_mean_concat(g2, A["ma"], w2, A["cm"], self._mean_ws(g2, w2))
         A["mb"] = self._conv("mb", g2, A["cm"], 2)
-        A["u1"] = self._t(n, 1, w2)
-        cmnn.up2_fwd(g2, A["mb"], w2, A["u1"])
         A["c1"] = self._t(n, 1, w1 + w2)
-        cmnn.concat_fwd(cmnn.nvox(g1), A["s1"], w1, A["u1"], w2, A["c1"])
+        cmnn.up2_concat_fwd(g2, A["s1"], w1, A["mb"], w2, A["c1"])
         A["d1a"] = self._conv("d1a", g1, A["c1"], 1)
         A["d1b"] = self._conv("d1b", g1, A["d1a"], 1)
-        A["u0"] = self._t(n, 0, w1)
-        cmnn.up2_fwd(g1, A["d1b"], w1, A["u0"])
         A["c0"] = self._t(n, 0, w0 + w1)
-        cmnn.concat_fwd(cmnn.nvox(g0), A["s0"], w0, A["u0"], w1, A["c0"])
+        cmnn.up2_concat_fwd(g1, A["s0"], w0, A["d1b"], w1, A["c0"])
         A["d0a"] = self._conv("d0a", g0, A["c0"], 0)
         A["d0b"] = self._conv("d0b", g0, A["d0a"], 0)
         A["y"] = self._conv("head", g0, A["d0b"], 0)
@@ -202,39 +196,34 @@ class UNet3D:
         # where a layer's input is the activation output of the layer below
         # (not a concatenation, pooling or sum), its data gradient also applies
         # that activation's gradient ("into"), and the layer below takes it as
-        # its pre-activation gradient (pre=True)
+        # its pre-activation gradient (pre=True); the skip joins apply it too.
+        # The concatenations' gradients dc0, dc1, dcm are read in place: the
+        # upsampled part by up2_bwd_act, the skip part by pool2_bwd_add_act,
+        # both parts of dcm by channel_mean_add_act.
+        act = {k: L["act"] for k, L in self.layers.items()}
         d = self._conv_bwd("head", g0, A["d0b"], A["y"], dy, 0, into="d0b")
         d = self._conv_bwd("d0b", g0, A["d0a"], A["d0b"], d, 0, pre=True, into="d0a")
-        d = self._conv_bwd("d0a", g0, A["c0"], A["d0a"], d, 0, pre=True)
-        ds0c, du0 = self._t(n, 0, w0), self._t(n, 0, w1)
-        cmnn.concat_bwd(cmnn.nvox(g0), d, w0, w1, ds0c, du0)
+        dc0 = self._conv_bwd("d0a", g0, A["c0"], A["d0a"], d, 0, pre=True)
         d = self._t(n, 1, w1)
-        cmnn.up2_bwd(g1, du0, w1, d)
-        d = self._conv_bwd("d1b", g1, A["d1a"], A["d1b"], d, 1, into="d1a")
-        d = self._conv_bwd("d1a", g1, A["c1"], A["d1a"], d, 1, pre=True)
-        ds1c, du1 = self._t(n, 1, w1), self._t(n, 1, w2)
-        cmnn.concat_bwd(cmnn.nvox(g1), d, w1, w2, ds1c, du1)
+        cmnn.up2_bwd_act(g1, dc0, w0, w0 + w1, w1, A["d1b"], act["d1b"], d)
+        d = self._conv_bwd("d1b", g1, A["d1a"], A["d1b"], d, 1, pre=True, into="d1a")
+        dc1 = self._conv_bwd("d1a", g1, A["c1"], A["d1a"], d, 1, pre=True)
         d = self._t(n, 2, w2)
-        cmnn.up2_bwd(g2, du1, w2, d)
-        d = self._conv_bwd("mb", g2, A["cm"], A["mb"], d, 2)
-        dma, dgm = self._t(n, 2, w2), self._t(n, 2, w2)
-        cmnn.concat_bwd(cmnn.nvox(g2), d, w2, w2, dma, dgm)
-        dmean = self._t(n, 2, w2)
-        cmnn.channel_mean(g2, dgm, w2, dmean, self._mean_ws(g2, w2))  # the mean map is self-adjoint
+        cmnn.up2_bwd_act(g2, dc1, w1, w1 + w2, w2, A["mb"], act["mb"], d)
+        dcm = self._conv_bwd("mb", g2, A["cm"], A["mb"], d, 2, pre=True)
         d = self._t(n, 2, w2)
-        cmnn.add(dma, dmean, d)
-        d = self._conv_bwd("ma", g2, A["p1"], A["ma"], d, 2)
-        ds1p = self._t(n, 1, w1)
-        cmnn.pool2_bwd(g1, d, w1, ds1p)
+        # the mean map is self-adjoint: ma's gradient is the first part of dcm
+        # plus the broadcast channel means of the second
+        cmnn.channel_mean_add_act(g2, dcm, w2, 2 * w2, w2, dcm, 0, 2 * w2, A["ma"], act["ma"], d,
+                                  self._mean_ws(g2, w2))
+        d = self._conv_bwd("ma", g2, A["p1"], A["ma"], d, 2, pre=True)
         ds1 = self._t(n, 1, w1)
-        cmnn.add(ds1c, ds1p, ds1)
-        d = self._conv_bwd("e1b", g1, A["e1a"], A["s1"], ds1, 1, into="e1a")
+        cmnn.pool2_bwd_add_act(g1, d, w1, dc1, 0, w1 + w2, A["s1"], act["e1b"], ds1)
+        d = self._conv_bwd("e1b", g1, A["e1a"], A["s1"], ds1, 1, pre=True, into="e1a")
         d = self._conv_bwd("e1a", g1, A["p0"], A["e1a"], d, 1, pre=True)
-        ds0p = self._t(n, 0, w0)
-        cmnn.pool2_bwd(g0, d, w0, ds0p)
         ds0 = self._t(n, 0, w0)
-        cmnn.add(ds0c, ds0p, ds0)
-        d = self._conv_bwd("e0b", g0, A["e0a"], A["s0"], ds0, 0, into="e0a")
+        cmnn.pool2_bwd_add_act(g0, d, w0, dc0, 0, w0 + w1, A["s0"], act["e0b"], ds0)
+        d = self._conv_bwd("e0b", g0, A["e0a"], A["s0"], ds0, 0, pre=True, into="e0a")
         self._conv_bwd("e0a", g0, A["x"], A["e0a"], d, 0, need_dx=False, pre=True)
 
     def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0, clip=None):

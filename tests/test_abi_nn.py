@@ -130,6 +130,47 @@ def test_elementwise_validation(lib):
                          ctypes.c_float(1e-8), ctypes.c_float(0.0), 0, NULL) == EINVAL  # step counts from 1
 
 
+def test_skip_join_validation(lib):
+    U, B, J = lib.cmnn_up2_concat_fwd, lib.cmnn_up2_bwd_act, lib.cmnn_pool2_bwd_add_act
+    assert U(g(), P, 40, P2, 64, P, NULL) == EINVAL           # channels not a multiple of 32
+    assert U(g(), P, 32, P2, 0, P, NULL) == EINVAL
+    assert U(g(), ODD, 32, P2, 64, P, NULL) == EINVAL         # misaligned skip
+    assert U(g(), P, 32, NULL, 64, P, NULL) == EINVAL
+    assert U(g(n=1 << 12, d=64, h=64, w=32), P, 32, P2, 64, P, NULL) == EINVAL  # fine level over 2^31 - 1 voxels
+    assert B(g(), P, 32, 64, P2, 1, P, NULL) == EINVAL        # stride below the channel count
+    assert B(g(), P, 100, 64, P2, 1, P, NULL) == EINVAL       # stride not a multiple of 8
+    assert B(g(), ODD, 96, 64, P2, 1, P, NULL) == EINVAL      # misaligned part pointer
+    assert B(g(), P, 96, 64, NULL, 1, P, NULL) == EINVAL      # leaky needs its gate
+    assert B(g(), P, 96, 64, ODD, 1, P, NULL) == EINVAL       # misaligned gate
+    assert B(g(), P, 96, 64, P2, 2, P, NULL) == EINVAL        # unknown activation
+    assert B(g(), P, 96, 64, P2, 1, NULL, NULL) == EINVAL
+    assert J(g(d=7), P, 32, P2, 96, P2, 1, P, NULL) == EINVAL  # odd extent
+    assert J(g(), P, 48, P2, 96, P2, 1, P, NULL) == EINVAL
+    assert J(g(), P, 32, P2, 16, P2, 1, P, NULL) == EINVAL    # skip stride below the channel count
+    assert J(g(), P, 32, ODD, 96, P2, 1, P, NULL) == EINVAL   # misaligned skip
+    assert J(g(), P, 32, P2, 96, NULL, 1, P, NULL) == EINVAL
+    assert J(g(), P, 32, P2, 96, P2, -1, P, NULL) == EINVAL
+    assert J(g(), NULL, 32, P2, 96, P2, 1, P, NULL) == EINVAL
+
+
+def test_bottleneck_join_validation(lib):
+    n = ctypes.c_size_t()
+    assert lib.cmnn_channel_mean_workspace(g(), 96, ctypes.byref(n)) == 0
+    W = n.value
+    MC, MA = lib.cmnn_channel_mean_concat, lib.cmnn_channel_mean_add_act
+    assert MC(g(), P, 40, P2, P, W, NULL) == EINVAL            # channels not a multiple of 32
+    assert MC(g(), P, 288, P2, P, 1 << 30, NULL) == EINVAL     # more than 256 channels
+    assert MC(g(), ODD, 96, P2, P, W, NULL) == EINVAL
+    assert MC(g(), P, 96, P2, P, W - 4, NULL) == EINVAL        # workspace too small
+    assert MC(g(), P, 96, P2, NULL, W, NULL) == EINVAL
+    assert MA(g(), P, 64, 96, P2, 192, P, 1, P2, P, W, NULL) == EINVAL    # dy stride below the channels
+    assert MA(g(), P, 192, 96, P2, 100, P, 1, P2, P, W, NULL) == EINVAL   # skip stride not a multiple of 8
+    assert MA(g(), P, 192, 96, NULL, 192, P, 1, P2, P, W, NULL) == EINVAL  # the skip part is required
+    assert MA(g(), P, 192, 96, P2, 192, NULL, 1, P2, P, W, NULL) == EINVAL  # leaky needs its gate
+    assert MA(g(), P, 192, 96, P2, 192, P, 1, ODD, P, W, NULL) == EINVAL
+    assert MA(g(), P, 192, 96, P2, 192, P, 1, P2, P, W - 4, NULL) == EINVAL
+
+
 def test_reduction_workspaces_and_validation(lib):
     n = ctypes.c_size_t()
     assert lib.cmnn_channel_mean_workspace(g(n=3), 96, ctypes.byref(n)) == 0

@@ -216,6 +216,41 @@ def test_elementwise_ops(torch, nn, c, ca, cb, nl):
     assert close_bf16(out.float().cpu().numpy(), C.leaky_grad_from_output(ylr, glr), np.abs(glr)) <= 1.0
 
 
+@pytest.mark.parametrize("cs,cx", [(32, 64), (64, 96)])
+def test_skip_joins(torch, nn, cs, cx):
+    """The U-Net's fused skip joins against the oracle's separate steps
+    (upsampling or pooling, concatenation, sum, activation gradient); the
+    concatenation's gradient is read in place through its channel stride."""
+    log(f"skip joins cs={cs} cx={cx}")
+    fine, coarse, ct = (2, 4, 6, 8), (2, 2, 3, 4), cs + cx
+    g, gc = nn.geom(*fine), nn.geom(*coarse)
+    bf = dict(dtype=torch.bfloat16, device="cuda:0")
+    skip, skr = bf16_tensor(torch, randn(fine + (cs,), 40))
+    x, xr = bf16_tensor(torch, randn(coarse + (cx,), 41))
+    y = torch.full(fine + (ct,), 7.0, **bf)
+    nn.up2_concat_fwd(gc, skip, cs, x, cx, y)
+    assert np.array_equal(y.float().cpu().numpy(), np.concatenate([skr, C.up2(xr)], -1))
+    dcat, dcr = bf16_tensor(torch, randn(fine + (ct,), 42))
+    gate_c, gcr = bf16_tensor(torch, randn(coarse + (cx,), 43))
+    for act in (nn.ACT_LEAKY, nn.ACT_NONE):
+        dx = torch.full(coarse + (cx,), 7.0, **bf)
+        nn.up2_bwd_act(gc, dcat, cs, ct, cx, gate_c, act, dx)
+        ref = C.up2_grad(dcr[..., cs:])
+        if act == nn.ACT_LEAKY:
+            ref = C.leaky_grad_from_output(gcr, ref)
+        assert close_bf16(dx.float().cpu().numpy(), ref, C.up2_grad(np.abs(dcr[..., cs:]))) <= 1.0, act
+    dp, dpr = bf16_tensor(torch, randn(coarse + (cs,), 44))
+    gate_f, gfr = bf16_tensor(torch, randn(fine + (cs,), 45))
+    for act, with_skip in ((nn.ACT_LEAKY, True), (nn.ACT_NONE, True), (nn.ACT_LEAKY, False)):
+        ds = torch.full(fine + (cs,), 7.0, **bf)
+        nn.pool2_bwd_add_act(g, dp, cs, dcat if with_skip else None, 0, ct, gate_f, act, ds)
+        ref = C.pool2_grad(dpr) + (dcr[..., :cs] if with_skip else 0.0)
+        mag = C.pool2_grad(np.abs(dpr)) + (np.abs(dcr[..., :cs]) if with_skip else 0.0)
+        if act == nn.ACT_LEAKY:
+            ref = C.leaky_grad_from_output(gfr, ref)
+        assert close_bf16(ds.float().cpu().numpy(), ref, mag) <= 1.0, (act, with_skip)
+
+
 @pytest.mark.parametrize("c", [64, 12])
 def test_channel_mean(torch, nn, c):
     log(f"channel mean broadcast c={c}")
@@ -227,6 +262,34 @@ def test_channel_mean(torch, nn, c):
     nn.channel_mean(g, x, c, y, ws)
     ref = C.channel_mean(xr)
     assert close_bf16(y.float().cpu().numpy(), ref, C.channel_mean(np.abs(xr))) <= 1.0
+
+
+def test_bottleneck_joins(torch, nn):
+    """The global-context join: [x | channel means] bitwise as the separate
+    mean and concatenation, and its gradient (mean map self-adjoint, both parts
+    of the concatenation's gradient read in place) against the oracle."""
+    log("bottleneck joins c=64")
+    dims, c = (3, 4, 6, 10), 64
+    g = nn.geom(*dims)
+    bf = dict(dtype=torch.bfloat16, device="cuda:0")
+    ws = torch.empty(nn.channel_mean_workspace(g, c) // 4, dtype=torch.float32, device="cuda:0")
+    x, xr = bf16_tensor(torch, randn(dims + (c,), 31))
+    gm = torch.empty_like(x)
+    nn.channel_mean(g, x, c, gm, ws)
+    ref = torch.empty(dims + (2 * c,), **bf)
+    nn.concat_fwd(nn.nvox(g), x, c, gm, c, ref)
+    y = torch.full(dims + (2 * c,), 7.0, **bf)
+    nn.channel_mean_concat(g, x, c, y, ws)
+    assert torch.equal(y, ref)
+    dcat, dcr = bf16_tensor(torch, randn(dims + (2 * c,), 32))
+    for act in (nn.ACT_LEAKY, nn.ACT_NONE):
+        dx = torch.full(dims + (c,), 7.0, **bf)
+        nn.channel_mean_add_act(g, dcat, c, 2 * c, c, dcat, 0, 2 * c, x, act, dx, ws)
+        r = dcr[..., :c] + C.channel_mean(dcr[..., c:])
+        if act == nn.ACT_LEAKY:
+            r = C.leaky_grad_from_output(xr, r)
+        mag = np.abs(dcr[..., :c]) + C.channel_mean(np.abs(dcr[..., c:]))
+        assert close_bf16(dx.float().cpu().numpy(), r, mag) <= 1.0, act
 
 
 def test_clip_grad_norm(torch, nn):
