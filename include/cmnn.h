@@ -197,9 +197,34 @@ int cmnn_adam(size_t n, float* param, const float* grad, float* m, float* v, flo
  * FP32 master weights [27][cout][cin]. */
 int cmnn_pack_weights(const float* w, int32_t cin, int32_t cout, void* w_fwd, void* w_t, void* hip_stream);
 
+/* cmnn_pack_weights for up to CMNN_PACK_MAX layers in one launch (bitwise the
+ * same results).  jobs is a host array of n descriptors, read during the
+ * call; EINVAL if any has a NULL pointer or a non-positive channel count. */
+#define CMNN_PACK_MAX 32
+typedef struct {
+    const float* w; /* FP32 master weights [27][cout][cin] */
+    void* w_fwd;    /* BF16 [27][cout][cin] */
+    void* w_t;      /* BF16 [27][cin][cout] */
+    int32_t cin, cout;
+} cmnn_pack_job;
+int cmnn_pack_weights_batch(int32_t n, const cmnn_pack_job* jobs, void* hip_stream);
+
 /* FP32 planar [cs][nvox] -> BF16 NDHWC [nvox][c] (c >= cs, rest zero), and back. */
 int cmnn_pack_channels(size_t nvox, const float* src, int32_t cs, void* dst, int32_t c, void* hip_stream);
 int cmnn_unpack_channels(size_t nvox, const void* src, int32_t c, float* dst, int32_t cs, void* hip_stream);
+
+/* Minibatch gathers from a data set held sample-major per plane, src FP32
+ * [planes][nsrc][nvs] (nvs voxels per sample): output sample b is source
+ * sample idx[b], idx a device int32 array of nsel entries.  An index outside
+ * [0, nsrc) yields zeros (the call cannot report it).
+ * cmnn_gather_samples: dst FP32 [np][nsel][nvs].
+ * cmnn_gather_pack_channels: the gather of cs planes fused with
+ * cmnn_pack_channels, dst BF16 NDHWC [nsel * nvs][c] (c >= cs, a multiple of
+ * 8; channels from cs on zero). */
+int cmnn_gather_samples(int32_t nsel, const int32_t* idx, size_t nvs, const float* src, int32_t nsrc, int32_t np,
+                        float* dst, void* hip_stream);
+int cmnn_gather_pack_channels(int32_t nsel, const int32_t* idx, size_t nvs, const float* src, int32_t nsrc,
+                              int32_t cs, void* dst, int32_t c, void* hip_stream);
 
 #ifdef __cplusplus
 }

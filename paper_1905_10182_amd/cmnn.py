@@ -18,12 +18,21 @@ EXPORTS = ["cmnn_conv3d_fwd", "cmnn_conv3d_bwd_data", "cmnn_conv3d_bwd_data_act"
            "cmnn_add", "cmnn_channel_mean_workspace", "cmnn_channel_mean",
            "cmnn_channel_mean_concat", "cmnn_channel_mean_add_act", "cmnn_mse_workspace",
            "cmnn_mse", "cmnn_clip_grad_norm_workspace", "cmnn_clip_grad_norm", "cmnn_adam", "cmnn_pack_weights",
-           "cmnn_pack_channels", "cmnn_unpack_channels"]
+           "cmnn_pack_channels", "cmnn_unpack_channels", "cmnn_gather_samples", "cmnn_gather_pack_channels",
+           "cmnn_pack_weights_batch"]
 
 
 class Geom(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("d", ctypes.c_int32), ("h", ctypes.c_int32), ("w", ctypes.c_int32),
                 ("periodic", ctypes.c_int32 * 3)]
+
+
+class PackJob(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_void_p), ("w_fwd", ctypes.c_void_p), ("w_t", ctypes.c_void_p),
+                ("cin", ctypes.c_int32), ("cout", ctypes.c_int32)]
+
+
+PACK_MAX = 32
 
 
 def geom(n, d, h, w, periodic=(1, 0, 1)):
@@ -77,6 +86,9 @@ def load_library():
     lib.cmnn_pack_weights.argtypes = [vp, i32, i32, vp, vp, vp]
     lib.cmnn_pack_channels.argtypes = [sz, vp, i32, vp, i32, vp]
     lib.cmnn_unpack_channels.argtypes = [sz, vp, i32, vp, i32, vp]
+    lib.cmnn_gather_samples.argtypes = [i32, vp, sz, vp, i32, i32, vp, vp]
+    lib.cmnn_pack_weights_batch.argtypes = [i32, ctypes.POINTER(PackJob), vp]
+    lib.cmnn_gather_pack_channels.argtypes = [i32, vp, sz, vp, i32, i32, vp, i32, vp]
     for name in EXPORTS:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -248,9 +260,35 @@ def pack_weights(w, cin, cout, w_fwd, w_t):
     _check(load_library().cmnn_pack_weights(_p(w), cin, cout, _p(w_fwd), _p(w_t), _s()), "pack_weights")
 
 
+def pack_jobs(layers):
+    """Descriptor array for pack_weights_batch from (w, cin, cout, w_fwd, w_t) tuples."""
+    jobs = (PackJob * len(layers))()
+    for j, (w, cin, cout, wf, wt) in zip(jobs, layers):
+        j.w, j.w_fwd, j.w_t, j.cin, j.cout = w.data_ptr(), wf.data_ptr(), wt.data_ptr(), cin, cout
+    return jobs
+
+
+def pack_weights_batch(jobs):
+    _check(load_library().cmnn_pack_weights_batch(len(jobs), jobs, _s()), "pack_weights_batch")
+
+
 def pack_channels(nv, src, cs, dst, c):
     _check(load_library().cmnn_pack_channels(nv, _p(src), cs, _p(dst), c, _s()), "pack_channels")
 
 
 def unpack_channels(nv, src, c, dst, cs):
     _check(load_library().cmnn_unpack_channels(nv, _p(src), c, _p(dst), cs, _s()), "unpack_channels")
+
+
+def gather_samples(idx, src, dst):
+    """dst [np][nsel][nvs] = src [np][nsrc][nvs] at samples idx (device int32 [nsel])."""
+    np_, nsrc, nvs = src.shape
+    _check(load_library().cmnn_gather_samples(idx.numel(), _p(idx), nvs, _p(src), nsrc, np_, _p(dst), _s()),
+           "gather_samples")
+
+
+def gather_pack_channels(idx, src, dst, c):
+    """dst BF16 [nsel * nvs][c] = the packed channels of src [cs][nsrc][nvs] at samples idx."""
+    cs, nsrc, nvs = src.shape
+    _check(load_library().cmnn_gather_pack_channels(idx.numel(), _p(idx), nvs, _p(src), nsrc, cs, _p(dst), c, _s()),
+           "gather_pack_channels")

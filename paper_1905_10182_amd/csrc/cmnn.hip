@@ -1190,6 +1190,31 @@ __global__ void k_mse_grad(long long nvox, const bf16* __restrict__ pred, int c,
     }
 }
 
+// 8 channels per thread: channels below creal get the gradient, the padded
+// ones zeros (their prediction is not read)
+__global__ void k_mse_grad8(long long nvox, const bf16* __restrict__ pred, int c, int creal,
+                            const float* __restrict__ tgt, const float* __restrict__ wt,
+                            const float* __restrict__ norm, bf16* __restrict__ dpred)
+{
+    const float scale = norm[1] > 0.f ? 2.f / norm[1] : 0.f;
+    const int q8 = c / 8;
+    GRID_STRIDE(i, nvox * q8)
+    {
+        const int q = (int)(i % q8);
+        const long long v = i / q8;
+        float f[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (8 * q < creal) {
+            float p[8];
+            unpack8(*(const u4*)(pred + i * 8), p);
+            const float sw = scale * wt[v];
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                if (8 * q + e < creal) f[e] = sw * (p[e] - tgt[(long long)(8 * q + e) * nvox + v]);
+        }
+        *(u4*)(dpred + i * 8) = pack8(f);
+    }
+}
+
 __global__ void k_adam(long long n, float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
                        float* __restrict__ v, float lr, float b1, float b2, float eps, float wd, float c1, float c2)
 {
@@ -1272,6 +1297,32 @@ __global__ void k_pack_w(const float* __restrict__ w, int cin, int cout, bf16* _
     }
 }
 
+// Several layers' packing in one launch: each workgroup belongs to one layer
+// (first_block ranges), so the layer's parameters are wave-uniform.
+struct PackJobs {
+    const float* w[CMNN_PACK_MAX];
+    bf16* wf[CMNN_PACK_MAX];
+    bf16* wt[CMNN_PACK_MAX];
+    int cin[CMNN_PACK_MAX], cout[CMNN_PACK_MAX];
+    int first_block[CMNN_PACK_MAX + 1];
+    int n;
+};
+
+__global__ __launch_bounds__(256) void k_pack_w_batch(const PackJobs J)
+{
+    int l = 0;
+    while (l + 1 < J.n && (int)blockIdx.x >= J.first_block[l + 1]) ++l;
+    const int cin = J.cin[l], cout = J.cout[l];
+    const long long i = (long long)((int)blockIdx.x - J.first_block[l]) * 256 + threadIdx.x;
+    if (i >= 27LL * cin * cout) return;
+    const int ci = (int)(i % cin);
+    const long long r = i / cin;
+    const int co = (int)(r % cout), t = (int)(r / cout);
+    const bf16 b = (bf16)J.w[l][i];
+    J.wf[l][i] = b;
+    J.wt[l][((long long)t * cin + ci) * cout + co] = b;
+}
+
 __global__ void k_pack_ch(long long nvox, const float* __restrict__ src, int cs, bf16* __restrict__ dst, int c)
 {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nvox * c;
@@ -1279,6 +1330,54 @@ __global__ void k_pack_ch(long long nvox, const float* __restrict__ src, int cs,
         const long long v = i / c;
         const int k = (int)(i % c);
         dst[i] = k < cs ? (bf16)src[(long long)k * nvox + v] : (bf16)0.f;
+    }
+}
+
+// Minibatch gathers from sample-major planes src [np][nsrc][nvs]: output
+// sample b is source sample idx[b] (b itself when idx is NULL); an index
+// outside [0, nsrc) gives zeros.
+__device__ __forceinline__ long long pick(const int* __restrict__ idx, long long b, int nsrc)
+{
+    const long long s = idx ? (long long)idx[b] : b;
+    return s >= 0 && s < nsrc ? s : -1;
+}
+
+// BF16 NDHWC [nsel * nvs][c] (channels from cs on zero), 8 channels per thread
+__global__ void k_gather_pack8(int nsel, const int* __restrict__ idx, long long nvs, const float* __restrict__ src,
+                               int nsrc, int cs, bf16* __restrict__ dst, int c)
+{
+    const int q8 = c / 8;
+    GRID_STRIDE(i, (long long)nsel * nvs * q8)
+    {
+        const int q = (int)(i % q8);
+        const long long r = i / q8, v = r % nvs, s = pick(idx, r / nvs, nsrc);
+        float f[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (s >= 0 && 8 * q < cs)
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                if (8 * q + e < cs) f[e] = src[((long long)(8 * q + e) * nsrc + s) * nvs + v];
+        *(u4*)(dst + i * 8) = pack8(f);
+    }
+}
+
+// FP32 [np][nsel][nvs], 4 values per thread (nvs a multiple of 4)
+__global__ void k_gather4(int nsel, const int* __restrict__ idx, long long nvs4, const float4* __restrict__ src,
+                          int nsrc, int np, float4* __restrict__ dst)
+{
+    GRID_STRIDE(i, (long long)np * nsel * nvs4)
+    {
+        const long long v = i % nvs4, r = i / nvs4, b = r % nsel, p = r / nsel, s = pick(idx, b, nsrc);
+        dst[i] = s >= 0 ? src[(p * nsrc + s) * nvs4 + v] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+}
+
+__global__ void k_gather1(int nsel, const int* __restrict__ idx, long long nvs, const float* __restrict__ src,
+                          int nsrc, int np, float* __restrict__ dst)
+{
+    GRID_STRIDE(i, (long long)np * nsel * nvs)
+    {
+        const long long v = i % nvs, r = i / nvs, b = r % nsel, p = r / nsel, s = pick(idx, b, nsrc);
+        dst[i] = s >= 0 ? src[(p * nsrc + s) * nvs + v] : 0.f;
     }
 }
 
@@ -1854,7 +1953,11 @@ int cmnn_mse(size_t nvox, const void* pred, int32_t c, int32_t creal, const floa
     // loss_out[0] = loss, loss_out[1] = normaliser (callers pass two floats)
     k_mse_final<<<1, 256, 0, s>>>(part, kMseBlocks, creal, loss_out);
     if (launched()) return CMNN_EHIP;
-    if (dpred) {
+    if (dpred && c % 8 == 0 && al16(pred) && al16(dpred)) {
+        k_mse_grad8<<<grid_for((long long)nvox * c / 8), 256, 0, s>>>((long long)nvox, (const bf16*)pred, c, creal,
+                                                                     target, weight, loss_out, (bf16*)dpred);
+        if (launched()) return CMNN_EHIP;
+    } else if (dpred) {
         k_mse_grad<<<grid_for((long long)nvox * c), 256, 0, s>>>((long long)nvox, (const bf16*)pred, c, creal, target,
                                                                weight, loss_out, (bf16*)dpred);
         if (launched()) return CMNN_EHIP;
@@ -1902,11 +2005,63 @@ int cmnn_pack_weights(const float* w, int32_t cin, int32_t cout, void* w_fwd, vo
     return launched();
 }
 
+int cmnn_pack_weights_batch(int32_t n, const cmnn_pack_job* jobs, void* hip_stream)
+{
+    if (n <= 0 || n > CMNN_PACK_MAX || !jobs) return CMNN_EINVAL;
+    PackJobs J = {};
+    long long blocks = 0;
+    for (int l = 0; l < n; ++l) {
+        const cmnn_pack_job& j = jobs[l];
+        if (!j.w || !j.w_fwd || !j.w_t || j.cin <= 0 || j.cout <= 0) return CMNN_EINVAL;
+        J.w[l] = j.w;
+        J.wf[l] = (bf16*)j.w_fwd;
+        J.wt[l] = (bf16*)j.w_t;
+        J.cin[l] = j.cin;
+        J.cout[l] = j.cout;
+        J.first_block[l] = (int)blocks;
+        blocks += (27LL * j.cin * j.cout + 255) / 256;
+        if (blocks > 0x7fffffffLL) return CMNN_EINVAL;
+    }
+    J.first_block[n] = (int)blocks;
+    J.n = n;
+    k_pack_w_batch<<<(unsigned)blocks, 256, 0, (hipStream_t)hip_stream>>>(J);
+    return launched();
+}
+
 int cmnn_pack_channels(size_t nvox, const float* src, int32_t cs, void* dst, int32_t c, void* hip_stream)
 {
     if (!src || !dst || cs <= 0 || c < cs) return CMNN_EINVAL;
+    if (c % 8 == 0 && al16(dst)) {
+        // one "sample" of nvox voxels, taken in place
+        k_gather_pack8<<<grid_for((long long)nvox * c / 8), 256, 0, (hipStream_t)hip_stream>>>(
+            1, nullptr, (long long)nvox, src, 1, cs, (bf16*)dst, c);
+        return launched();
+    }
     k_pack_ch<<<grid_for((long long)nvox * c), 256, 0, (hipStream_t)hip_stream>>>((long long)nvox, src, cs, (bf16*)dst,
                                                                                 c);
+    return launched();
+}
+
+int cmnn_gather_pack_channels(int32_t nsel, const int32_t* idx, size_t nvs, const float* src, int32_t nsrc,
+                              int32_t cs, void* dst, int32_t c, void* hip_stream)
+{
+    if (nsel <= 0 || !idx || nvs == 0 || !src || nsrc <= 0 || cs <= 0 || c < cs || c % 8 != 0 || !dst || !al16(dst))
+        return CMNN_EINVAL;
+    k_gather_pack8<<<grid_for((long long)nsel * nvs * c / 8), 256, 0, (hipStream_t)hip_stream>>>(
+        nsel, idx, (long long)nvs, src, nsrc, cs, (bf16*)dst, c);
+    return launched();
+}
+
+int cmnn_gather_samples(int32_t nsel, const int32_t* idx, size_t nvs, const float* src, int32_t nsrc, int32_t np,
+                        float* dst, void* hip_stream)
+{
+    if (nsel <= 0 || !idx || nvs == 0 || !src || nsrc <= 0 || np <= 0 || !dst) return CMNN_EINVAL;
+    if (nvs % 4 == 0 && al16(src) && al16(dst))
+        k_gather4<<<grid_for((long long)np * nsel * nvs / 4), 256, 0, (hipStream_t)hip_stream>>>(
+            nsel, idx, (long long)nvs / 4, (const float4*)src, nsrc, np, (float4*)dst);
+    else
+        k_gather1<<<grid_for((long long)np * nsel * nvs), 256, 0, (hipStream_t)hip_stream>>>(nsel, idx, (long long)nvs,
+                                                                                          src, nsrc, np, dst);
     return launched();
 }
 

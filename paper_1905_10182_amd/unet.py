@@ -83,12 +83,15 @@ class UNet3D:
         self._mws = None
         self._cws = None
         self.grad_norm = None
+        self._jobs = None
         self.pack()
 
     # -- parameters
     def pack(self):
-        for L in self.layers.values():
-            cmnn.pack_weights(L["w"], L["cin"], L["cout"], L["wf"], L["wt"])
+        if self._jobs is None:  # the tensors never move, so the descriptors are built once
+            self._jobs = cmnn.pack_jobs([(L["w"], L["cin"], L["cout"], L["wf"], L["wt"])
+                                         for L in self.layers.values()])
+        cmnn.pack_weights_batch(self._jobs)
 
     def state_dict(self):
         return {"params": self.params.detach().cpu().numpy().copy(), "widths": np.array(self.widths),

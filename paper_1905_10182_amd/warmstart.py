@@ -286,14 +286,18 @@ class Trainer:
         self.n = n
         nvs = NX * NY * NZ
         dev = net.device
-        # planar layouts so that a minibatch is a contiguous slice after index_select on axis 1
-        self.X = torch.as_tensor(np.ascontiguousarray(np.transpose(data["x"].reshape(n, 2, nvs), (1, 0, 2))),
-                                 device=dev)
+        # FP32, plane-major then sample-major: a minibatch gather copies each
+        # sample's plane as one contiguous run
+        f32 = dict(dtype=torch.float32, device=dev)
+        self.X = torch.as_tensor(np.ascontiguousarray(np.transpose(data["x"].reshape(n, 2, nvs), (1, 0, 2))), **f32)
         self.Y = torch.as_tensor(np.ascontiguousarray(np.transpose(data["y"].reshape(n, NOUT, nvs), (1, 0, 2))),
-                                 device=dev)
-        self.W = torch.as_tensor(data["w"].reshape(n, nvs), device=dev)
+                                 **f32)
+        self.W = torch.as_tensor(data["w"].reshape(n, nvs), **f32)
         self.nvox = batch * nvs
         self.xb = torch.empty((batch, NZ, NY, NX, net.cin0), dtype=torch.bfloat16, device=dev)
+        self.idx = torch.empty(batch, dtype=torch.int32, device=dev)
+        self.ys = torch.empty((NOUT, batch, nvs), dtype=torch.float32, device=dev)
+        self.wb = torch.empty((1, batch, nvs), dtype=torch.float32, device=dev)
         self.dy = torch.empty((batch, NZ, NY, NX, net.cout_head), dtype=torch.bfloat16, device=dev)
         self.loss = torch.zeros(2, dtype=torch.float32, device=dev)
         self.ws = torch.empty(cmnn.mse_workspace(self.nvox) // 4, dtype=torch.float32, device=dev)
@@ -301,13 +305,13 @@ class Trainer:
         self.nsteps, self.norm_mean, self.nclipped = 0, 0.0, 0
 
     def minibatch(self, idx):
-        t = self.torch
-        ii = t.as_tensor(idx, device=self.net.device)
-        xs = self.X.index_select(1, ii).contiguous()
-        cmnn.pack_channels(self.nvox, xs, 2, self.xb, self.net.cin0)
-        ys = self.Y.index_select(1, ii).contiguous()
-        ws = self.W.index_select(0, ii).contiguous()
-        return ys, ws
+        """Gather samples idx into the packed network input self.xb and return
+        the planar targets [NOUT][batch * nvs] and weights [batch * nvs]."""
+        self.idx.copy_(self.torch.as_tensor(np.asarray(idx, dtype=np.int32)))
+        cmnn.gather_pack_channels(self.idx, self.X, self.xb, self.net.cin0)
+        cmnn.gather_samples(self.idx, self.Y, self.ys)
+        cmnn.gather_samples(self.idx, self.W.view(1, self.n, -1), self.wb)
+        return self.ys, self.wb
 
     def step(self, lr):
         """One Adam step on a random minibatch.  The global gradient norm is

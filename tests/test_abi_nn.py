@@ -171,6 +171,34 @@ def test_bottleneck_join_validation(lib):
     assert MA(g(), P, 192, 96, P2, 192, P, 1, P2, P, W - 4, NULL) == EINVAL
 
 
+def test_gather_validation(lib):
+    GS, GP = lib.cmnn_gather_samples, lib.cmnn_gather_pack_channels
+    assert GS(0, P, 64, P2, 4, 3, P, NULL) == EINVAL      # empty selection
+    assert GS(2, NULL, 64, P2, 4, 3, P, NULL) == EINVAL   # no index array
+    assert GS(2, P, 0, P2, 4, 3, P, NULL) == EINVAL
+    assert GS(2, P, 64, P2, 0, 3, P, NULL) == EINVAL      # empty source
+    assert GS(2, P, 64, P2, 4, 0, P, NULL) == EINVAL
+    assert GS(2, P, 64, NULL, 4, 3, P, NULL) == EINVAL
+    assert GP(2, P, 64, P2, 4, 2, P, 12, NULL) == EINVAL  # packed width not a multiple of 8
+    assert GP(2, P, 64, P2, 4, 40, P, 32, NULL) == EINVAL  # fewer slots than channels
+    assert GP(2, P, 64, P2, 4, 2, ODD, 32, NULL) == EINVAL
+    assert GP(-1, P, 64, P2, 4, 2, P, 32, NULL) == EINVAL
+
+
+def test_pack_batch_validation(lib):
+    jobs = (N.PackJob * (N.PACK_MAX + 1))()
+    for j in jobs:
+        j.w, j.w_fwd, j.w_t, j.cin, j.cout = 1 << 20, (1 << 20) + 4096, (1 << 20) + 8192, 32, 32
+    B = lib.cmnn_pack_weights_batch
+    assert B(0, jobs, NULL) == EINVAL
+    assert B(N.PACK_MAX + 1, jobs, NULL) == EINVAL  # more layers than one launch takes
+    assert B(2, None, NULL) == EINVAL
+    jobs[1].w_t = None
+    assert B(2, jobs, NULL) == EINVAL
+    jobs[1].w_t, jobs[0].cout = (1 << 20) + 8192, 0
+    assert B(2, jobs, NULL) == EINVAL
+
+
 def test_reduction_workspaces_and_validation(lib):
     n = ctypes.c_size_t()
     assert lib.cmnn_channel_mean_workspace(g(n=3), 96, ctypes.byref(n)) == 0

@@ -311,6 +311,67 @@ def test_clip_grad_norm(torch, nn):
     assert out[1].item() == 0.0 and not g.abs().max().item()
 
 
+@pytest.mark.parametrize("c,creal", [(32, 3), (32, 11), (12, 3)])
+def test_masked_mse(torch, nn, c, creal):
+    """16-byte gradient kernel (c a multiple of 8, creal inside one or two
+    8-channel groups) and the scalar one (c = 12)."""
+    log(f"mse c={c} creal={creal}")
+    nv = 5000
+    p, pr = bf16_tensor(torch, randn((nv, c), 16))
+    tgt = torch.as_tensor(randn((creal, nv), 17), dtype=torch.float32, device="cuda:0")
+    wt = torch.as_tensor((randn((nv,), 18) > -0.5).astype(np.float32), device="cuda:0")
+    loss = torch.empty(2, dtype=torch.float32, device="cuda:0")
+    dp = torch.full_like(p, 7.0)
+    ws = torch.empty(nn.mse_workspace(nv) // 4, dtype=torch.float32, device="cuda:0")
+    nn.mse(nv, p, c, creal, tgt, wt, loss, dp, ws)
+    rl, rg = C.mse(pr[:, :creal], tgt.cpu().numpy().astype(np.float64), wt.cpu().numpy().astype(np.float64))
+    assert abs(loss[0].item() / rl - 1) < 1e-5
+    got = dp.float().cpu().numpy()
+    assert close_bf16(got[:, :creal], rg, np.abs(rg)) <= 1.0
+    assert np.all(got[:, creal:] == 0)
+
+
+def test_minibatch_gathers(torch, nn):
+    """Gathers of samples from plane-major data: exact copies (FP32) or the
+    FP32 -> BF16 rounding of the packing; an out-of-range index gives zeros."""
+    log("minibatch gathers")
+    nsrc, nvs = 7, 24
+    dev = "cuda:0"
+    src = torch.as_tensor(randn((3, nsrc, nvs), 22), dtype=torch.float32, device=dev)
+    for idx in ([4, 0, 6], [2, 9, -1, 5]):
+        ii = torch.as_tensor(idx, dtype=torch.int32, device=dev)
+        ok = np.array([0 <= k < nsrc for k in idx])
+        ref = np.zeros((3, len(idx), nvs), np.float32)
+        ref[:, ok] = src.cpu().numpy()[:, np.array(idx)[ok]]
+        for n_vs in (nvs, nvs - 1):  # 4-wide and scalar kernels
+            s = src[..., :n_vs].contiguous()
+            out = torch.full((3, len(idx), n_vs), 7.0, dtype=torch.float32, device=dev)
+            nn.gather_samples(ii, s, out)
+            assert np.array_equal(out.cpu().numpy(), ref[..., :n_vs])
+        packed = torch.full((len(idx) * nvs, 16), 7.0, dtype=torch.bfloat16, device=dev)
+        nn.gather_pack_channels(ii, src[:2].contiguous(), packed, 16)
+        want = torch.as_tensor(ref[:2].reshape(2, -1).T).to(torch.bfloat16).float().numpy()
+        got = packed.float().cpu().numpy()
+        assert np.array_equal(got[:, :2], want) and np.all(got[:, 2:] == 0)
+
+
+def test_pack_weights_batch(torch, nn):
+    """One launch for several layers, bitwise the per-layer packing."""
+    log("batched weight packing")
+    shapes = [(32, 32), (64, 96), (192, 96), (32, 160)]
+    dev = "cuda:0"
+    ws = [torch.as_tensor(randn((27, co, ci), 50 + k), dtype=torch.float32, device=dev)
+          for k, (ci, co) in enumerate(shapes)]
+    outs = [(torch.empty((27, co, ci), dtype=torch.bfloat16, device=dev),
+             torch.empty((27, ci, co), dtype=torch.bfloat16, device=dev)) for ci, co in shapes]
+    nn.pack_weights_batch(nn.pack_jobs([(w, ci, co, wf, wt) for w, (ci, co), (wf, wt) in zip(ws, shapes, outs)]))
+    for w, (ci, co), (wf, wt) in zip(ws, shapes, outs):
+        rf, rt = torch.empty_like(wf), torch.empty_like(wt)
+        nn.pack_weights(w, ci, co, rf, rt)
+        assert torch.equal(wf, rf) and torch.equal(wt, rt)
+        assert torch.equal(wt, w.to(torch.bfloat16).transpose(1, 2))
+
+
 def test_mse_adam_and_channel_packing(torch, nn):
     log("mse / adam / pack channels")
     nv, c, creal = 5000, 32, 3
@@ -343,3 +404,6 @@ def test_mse_adam_and_channel_packing(torch, nn):
     back = torch.empty((2, 100), dtype=torch.float32, device="cuda:0")
     nn.unpack_channels(100, packed, 32, back, 2)
     assert torch.equal(back, src.to(torch.bfloat16).float())
+    packed12 = torch.full((100, 12), 7.0, dtype=torch.bfloat16, device="cuda:0")  # the scalar packing kernel
+    nn.pack_channels(100, src, 2, packed12, 12)
+    assert torch.equal(packed12[:, :2], packed[:, :2]) and np.all(packed12.float().cpu().numpy()[:, 2:] == 0)
