@@ -351,14 +351,18 @@ __global__ __launch_bounds__(256) void k_conv_tile(G g, const bf16* __restrict__
             }
         }
     }
-    // D[row][col]: row = voxel (lane / 16) * 4 + i of the block's x-row, col = output channel lane % 16
+    // D[row][col]: row = voxel (lane / 16) * 4 + i of the block's x-row, col = output channel lane % 16.
+    // The NB bias values are loaded together, before the stores (one wait instead of one per store group).
+    float bbv[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) bbv[b] = bias ? bias[co0 + 16 * b + (lane & 15)] : 0.f;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         const long long vrow = ((n * g.d + d0 + wave) * g.h + h0 + m) * g.w + x0;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const int co = co0 + 16 * b + (lane & 15);
-            const float bb = bias ? bias[co] : 0.f;
+            const float bb = bbv[b];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const long long idx = (vrow + (lane >> 4) * 4 + i) * cout + co;
