@@ -719,6 +719,122 @@ def test_full_size_taylor_green_512_bf16_sampled(torch):
     assert np.all(err <= 0.5 * ulp + 2e-7 * WGT[:, None])
 
 
+SB = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}
+
+
+def raw_populations(torch, lat, buf, cells, pre=True):
+    """Populations at cells (n, 3: x, y, z) read directly from one of the
+    lattice's two device buffers: 27 planes of (nbatch * nz * ny) rows of nx
+    cells padded to 256 bytes, planes a further 4 KiB apart, each value stored
+    as h = f - w rho0 (FP16: 256 h).  A step stores each cell's post-collision
+    populations at the cell itself and the next step pulls them, so the
+    pre-collision f_i(x) of the state (pre=True) sits at x - c_i, and the
+    post-collision values of the step that wrote the buffer (pre=False) at x.
+    Returns (27, n) FP64."""
+    storage = {0: "fp64", 1: "fp32", 2: "fp16", 3: "bf16"}[lat.storage]
+    sb = SB[storage]
+    _, nz, ny, nx = lat.shape
+    nxp = -(-nx * sb // 256) * 256 // sb
+    pstride = nz * ny * nxp + 4096 // sb
+    view = buf.view({"fp64": torch.float64, "fp32": torch.float32, "fp16": torch.float16,
+                     "bf16": torch.bfloat16}[storage])
+    dims3 = np.array([nx, ny, nz])
+    idx = np.empty((27, len(cells)), np.int64)
+    for i in range(27):
+        d = (cells - np.array([CX[i], CY[i], CZ[i]])) % dims3 if pre else cells
+        idx[i] = i * pstride + (d[:, 2] * ny + d[:, 1]) * nxp + d[:, 0]
+    h = view[torch.as_tensor(idx.ravel(), device=buf.device)].double().cpu().numpy().reshape(27, -1)
+    if storage == "fp16":
+        h = h / 256.0
+    return h + WGT[:, None] * lat.params.rho0
+
+
+def test_raw_population_layout_matches_export(torch):
+    """The raw-buffer reading used at the largest sizes equals the library's
+    population export, for every storage type, before and after a step (the
+    state alternates between the two buffers), and the post-collision values a
+    step leaves at each cell equal the oracle's collision of its pre-collision
+    populations."""
+    for storage in ("fp64", "fp32", "fp16", "bf16"):
+        lat = Lat(nx=37, ny=6, nz=5, tau=0.6, storage=storage)
+        g = W.generator(77)
+        lat.init(1.0 + 1e-3 * g.uniform(-1, 1, lat.shape), 0.05 * g.uniform(-1, 1, (3,) + lat.shape))
+        zz, yy, xx = np.meshgrid(np.arange(5), np.arange(6), np.arange(37), indexing="ij")
+        cells = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], 1)
+        f0 = lat.populations().reshape(27, -1).cpu().numpy()
+        assert np.array_equal(raw_populations(torch, lat, lat._a, cells), f0), storage
+        lat.step(1)
+        ref = lat.populations().reshape(27, -1).cpu().numpy()
+        assert np.array_equal(raw_populations(torch, lat, lat._b, cells), ref), storage
+        post = raw_populations(torch, lat, lat._b, cells, pre=False)
+        err = np.abs(post - O.collide_cells(f0, None, 1.0 / lat.params.tau)) / WGT[:, None]
+        assert err.max() < {"fp64": 1e-13, "fp32": 1e-6, "fp16": 1e-3, "bf16": 1e-2}[storage], storage
+        lat.close()
+
+
+# Population planes of 3 GiB: every in-plane byte offset past 2^31 (the top bit
+# of the 32-bit offsets the kernels use), within the 4 GiB a plane may span.
+LARGEST = [("fp16", (1024, 1024, 1536)), ("fp32", (1024, 1024, 768))]
+
+
+@pytest.mark.parametrize("storage,dims", LARGEST)
+def test_three_gib_planes_sampled(torch, storage, dims):
+    """Initialisation, moments and one step on a lattice whose population
+    planes are 3 GiB (162 GiB of populations), from a seeded per-cell random
+    state (density 1 +- 1e-3, velocity components in +-0.05, drawn on the
+    device): the moments of sampled cells against the oracle's from their
+    stored populations, and their post-collision populations after the step
+    against the oracle's collision (FP16: the rounded oracle value; FP32
+    within 1e-6 w).  Samples include the last cells of the planes and their
+    periodic neighbours at the planes' start."""
+    nx, ny, nz = dims
+    n = nx * ny * nz
+    need = 2 * 27 * (n * SB[storage] + 4096) + 16 * n + (2 << 30)
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    if free < need:
+        pytest.skip(f"needs {need / 2**30:.0f} GiB of free device memory, {free / 2**30:.0f} GiB free")
+    log(f"{storage} {nx}x{ny}x{nz}: {27 * n * SB[storage] / 2**30:.0f} GiB of populations per buffer")
+    lat = Lat(nx=nx, ny=ny, nz=nz, tau=0.6, storage=storage)
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(1536)
+    rho = 1.0 + 2e-3 * (torch.rand(lat.shape, generator=gen, device="cuda:0") - 0.5)
+    u = 0.1 * (torch.rand((3,) + lat.shape, generator=gen, device="cuda:0") - 0.5)
+    lat.init(rho, u, dtype=torch.float32)
+    del rho, u
+    torch.cuda.empty_cache()
+    g = W.generator(1536)
+    corners = np.array([[x, y, z] for x in (0, nx - 1) for y in (0, ny - 1) for z in (0, nz - 1)])
+    cells = np.concatenate([corners, np.stack([g.integers(0, nx, 2048), g.integers(0, ny, 2048),
+                                               g.integers(0, nz, 2048)], 1)])
+    f0 = raw_populations(torch, lat, lat._a, cells)
+    rho_g, u_g = lat.moments(dtype=torch.float32)
+    lin = torch.as_tensor((cells[:, 2] * ny + cells[:, 1]) * nx + cells[:, 0], device="cuda:0")
+    rg = rho_g.reshape(-1)[lin].double().cpu().numpy()
+    ug = u_g.reshape(3, -1)[:, lin].double().cpu().numpy()
+    del rho_g, u_g
+    torch.cuda.empty_cache()
+    mom = [O.macroscopic(f0[:, k]) for k in range(len(cells))]
+    assert np.abs(rg - np.array([m[0] for m in mom])).max() < 1e-6
+    assert np.abs(ug - np.array([m[1] for m in mom]).T).max() < 1e-6
+    lat.step(1)
+    got = raw_populations(torch, lat, lat._b, cells, pre=False)
+    ref = O.collide_cells(f0, None, 1.0 / lat.params.tau)
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    if storage == "fp16":
+        h_ref = ref - WGT[:, None]
+        err = np.abs((got - WGT[:, None]) - h_ref)
+        ulp = ulp16(h_ref, "fp16")
+        log(f"  max error in FP16 ulps {(err / ulp).max():.3f}")
+        assert np.all(err <= 0.5 * ulp + 2e-7 * WGT[:, None])
+    else:
+        err = np.abs(got - ref) / WGT[:, None]
+        log(f"  max |f* - oracle| / w = {err.max():.3e}")
+        assert err.max() < 1e-6
+
+
 @pytest.mark.parametrize("storage", ["fp32", "fp16"])
 def test_full_size_kolmogorov_384_sampled(torch, storage):
     """Kolmogorov flow at its full size, 384^3 (not a power of two: six waves per
