@@ -835,6 +835,99 @@ def test_three_gib_planes_sampled(torch, storage, dims):
         assert err.max() < 1e-6
 
 
+def raw_moments(torch, lat, buf, cells):
+    """The nine stored FP32 numbers (rho - rho0, u, (1 - omega) k4..k8) of
+    moment storage at cells (n, 3), read from a device buffer: nine planes of
+    (nbatch * nz * ny) rows of nx cells padded to 256 bytes, planes a further
+    4 KiB apart, each cell's numbers at the cell itself.  Returns (9, n)."""
+    _, nz, ny, nx = lat.shape
+    nxp = -(-nx * 4 // 256) * 64
+    pstride = nz * ny * nxp + 1024
+    lin = (cells[:, 2] * ny + cells[:, 1]) * nxp + cells[:, 0]
+    idx = np.arange(9)[:, None] * pstride + lin[None, :]
+    return buf.view(torch.float32)[torch.as_tensor(idx.ravel(), device=buf.device)].double().cpu().numpy().reshape(9, -1)
+
+
+def mom32_step_oracle(lat, cells, read):
+    """The oracle's nine numbers after one step at cells, from the state's
+    nine numbers read(points) at any points: each neighbour x - c_i's
+    post-collision populations rebuilt from its numbers (eq.
+    post_collision_central_moments_forcing, then the inverse transform),
+    population i pulled, collided, and its density, velocity and relaxed
+    k4..k8 formed."""
+    _, nz, ny, nx = lat.shape
+    dims3 = np.array([nx, ny, nz])
+    om, rho0 = 1.0 / lat.params.tau, lat.params.rho0
+    f = np.empty((27, len(cells)))
+    for i in range(27):
+        m = read((cells - np.array([CX[i], CY[i], CZ[i]])) % dims3)
+        for j in range(len(cells)):
+            k_post = O.post_collision(rho0 + m[0, j], m[4:9, j] / (1.0 - om), (0.0, 0.0, 0.0), om)
+            f[i, j] = O.reconstruct_fast(m[1:4, j], k_post)[i]
+    out = np.empty((9, len(cells)))
+    for j in range(len(cells)):
+        rho, u = O.macroscopic(f[:, j])
+        out[:, j] = np.concatenate([[rho - rho0], u, (1.0 - om) * O.pre_collision(f[:, j], u)])
+    return out
+
+
+def test_mom32_raw_layout_matches_export_and_oracle(torch):
+    """Moment storage read straight from its buffers: density and velocity
+    equal the library's moment export, and one step's nine numbers at every
+    cell match the oracle's step rebuilt from the previous buffer (1e-6)."""
+    lat = Lat(nx=37, ny=6, nz=5, tau=0.6, storage="mom32")
+    g = W.generator(78)
+    lat.init(1.0 + 1e-3 * g.uniform(-1, 1, lat.shape), 0.05 * g.uniform(-1, 1, (3,) + lat.shape))
+    zz, yy, xx = np.meshgrid(np.arange(5), np.arange(6), np.arange(37), indexing="ij")
+    cells = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], 1)
+    m0 = raw_moments(torch, lat, lat._a, cells)
+    rho, u = lat.moments()
+    assert np.array_equal(m0[0] + lat.params.rho0, rho.reshape(-1).cpu().numpy())
+    assert np.array_equal(m0[1:4], u.reshape(3, -1).cpu().numpy())
+    lat.step(1)
+    got = raw_moments(torch, lat, lat._b, cells)
+    ref = mom32_step_oracle(lat, cells, lambda pts: raw_moments(torch, lat, lat._a, pts))
+    lat.close()
+    log(f"  max |numbers - oracle| = {np.abs(got - ref).max():.3e}")
+    assert np.abs(got - ref).max() < 1e-6
+
+
+def test_mom32_three_gib_planes_sampled(torch):
+    """Moment storage with 3 GiB planes (1024 x 1024 x 768, FP32 numbers, 54
+    GiB per lattice): one step from a seeded per-cell random state drawn on
+    the device, the nine numbers of 520 sampled cells (the planes' last cells
+    and their periodic neighbours among them) against the oracle's step
+    rebuilt from the stored numbers around each (1e-6)."""
+    nx, ny, nz = 1024, 1024, 768
+    n = nx * ny * nz
+    need = 2 * 9 * (4 * n + 4096) + 16 * n + (2 << 30)
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    if free < need:
+        pytest.skip(f"needs {need / 2**30:.0f} GiB of free device memory, {free / 2**30:.0f} GiB free")
+    log(f"mom32 {nx}x{ny}x{nz}: {9 * n * 4 / 2**30:.0f} GiB of numbers per buffer")
+    lat = Lat(nx=nx, ny=ny, nz=nz, tau=0.6, storage="mom32")
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(768)
+    rho = 1.0 + 2e-3 * (torch.rand(lat.shape, generator=gen, device="cuda:0") - 0.5)
+    u = 0.1 * (torch.rand((3,) + lat.shape, generator=gen, device="cuda:0") - 0.5)
+    lat.init(rho, u, dtype=torch.float32)
+    del rho, u
+    torch.cuda.empty_cache()
+    g = W.generator(768)
+    corners = np.array([[x, y, z] for x in (0, nx - 1) for y in (0, ny - 1) for z in (0, nz - 1)])
+    cells = np.concatenate([corners, np.stack([g.integers(0, nx, 512), g.integers(0, ny, 512),
+                                               g.integers(0, nz, 512)], 1)])
+    lat.step(1)
+    got = raw_moments(torch, lat, lat._b, cells)
+    ref = mom32_step_oracle(lat, cells, lambda pts: raw_moments(torch, lat, lat._a, pts))
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    log(f"  max |numbers - oracle| = {np.abs(got - ref).max():.3e}")
+    assert np.abs(got - ref).max() < 1e-6
+
+
 @pytest.mark.parametrize("storage", ["fp32", "fp16"])
 def test_full_size_kolmogorov_384_sampled(torch, storage):
     """Kolmogorov flow at its full size, 384^3 (not a power of two: six waves per
