@@ -228,3 +228,54 @@ def test_bench_size_sampled_step(torch, storage):
         s = np.abs(expect - WGT.reshape(9, 1)) * 256
         ulp = 2.0 ** (np.floor(np.log2(np.maximum(s, 2.0 ** -14))) - 10) / 256
         assert np.all(np.abs(f_t1 - expect) <= ulp * 1.01 + 1e-8)
+
+
+@pytest.mark.parametrize("storage,dims", [("fp32", (32768, 24576)), ("fp16", (32768, 49152))])
+def test_three_gib_planes_sampled_step(torch, storage, dims):
+    """Population planes of 3 GiB (in-plane byte offsets past 2^31, within the
+    4 GiB a plane may span): from a seeded per-cell random state drawn on the
+    device (density 1 +- 1e-3, velocity components within +-0.05), one step on
+    2054 sampled cells (the corners among them) equals the oracle's collision
+    of the exported populations of each cell's upstream neighbours (FP32
+    within 1e-6, FP16 within one unit in the last place)."""
+    nx, ny = dims
+    n = nx * ny
+    sb = 4 if storage == "fp32" else 2
+    need = 2 * 9 * n * sb + 9 * 8 * n + 12 * n + (2 << 30)
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    if free < need:
+        pytest.skip(f"needs {need / 2**30:.0f} GiB of free device memory, {free / 2**30:.0f} GiB free")
+    log(f"d2q9 {storage} {nx}x{ny}: {9 * n * sb / 2**30:.0f} GiB of populations per buffer")
+    lat = Lat(nx, ny, tau=0.6, storage=storage)
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(3)
+    rho = 1.0 + 2e-3 * (torch.rand((ny, nx), generator=gen, device="cuda:0") - 0.5)
+    u = 0.1 * (torch.rand((2, ny, nx), generator=gen, device="cuda:0") - 0.5)
+    lat.init(rho, u, dtype=torch.float32)
+    del rho, u
+    torch.cuda.empty_cache()
+    g = W.generator(5)
+    ys = np.concatenate([[0, 0, ny - 1, ny - 1, 0, ny // 2], g.integers(0, ny, 2048)])
+    xs = np.concatenate([[0, nx - 1, 0, nx - 1, nx // 2, 0], g.integers(0, nx, 2048)])
+    f_t = lat.populations().reshape(9, -1)
+    pre = np.empty((9, 9, ys.size))  # [direction j][population i][sample]: f_i at the cell upstream along c_j
+    for j in range(9):
+        sy, sx = (ys - CY[j]) % ny, (xs - CX[j]) % nx
+        pre[j] = f_t[:, torch.as_tensor(sy * nx + sx, device=f_t.device)].cpu().numpy()
+    del f_t
+    torch.cuda.empty_cache()
+    lat.step(1)
+    f_t1 = lat.populations().reshape(9, -1)[:, torch.as_tensor(ys * nx + xs, device="cuda:0")].cpu().numpy()
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    expect = np.stack([D.collide_cells(pre[j], None, 1.0 / 0.6)[j] for j in range(9)])
+    if storage == "fp32":
+        err = np.abs(f_t1 - expect).max()
+        log(f"  max |f - oracle| = {err:.3e}")
+        assert err < 1e-6
+    else:
+        s = np.abs(expect - WGT.reshape(9, 1)) * 256
+        ulp = 2.0 ** (np.floor(np.log2(np.maximum(s, 2.0 ** -14))) - 10) / 256
+        assert np.all(np.abs(f_t1 - expect) <= ulp * 1.01 + 1e-8)
