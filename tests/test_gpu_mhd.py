@@ -261,3 +261,56 @@ def test_bench_size_magnetic_step_sampled(torch):
             err = max(err, float(np.abs(P1[l, :, k] - want).max()))
     log(f"  max |h - oracle| = {err:.3e}")
     assert err < 2e-9  # FP32 arithmetic on populations of order 1e-3
+
+
+def test_planes_over_2gib_magnetic_step_sampled(torch):
+    """The magnetic lattice with population planes of 2.03 GiB (1024 x 1024 x
+    520, FP32: in-plane byte offsets past 2^31), from a seeded per-cell random
+    field b (components within +-0.01) and velocity u (within +-0.02) drawn on
+    the device: one step on 2056 sampled cells (the corners among them) against
+    the oracle's collision of the exported populations at x - xi_l."""
+    from paper_1905_10182_amd.mhd import MagneticLattice
+    nx, ny, nz, tau_m = 1024, 1024, 520, 0.8
+    n = nx * ny * nz
+    need = 2 * 21 * 4 * n + 21 * 8 * n + 24 * n + (2 << 30)
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    if free < need:
+        pytest.skip(f"needs {need / 2**30:.0f} GiB of free device memory, {free / 2**30:.0f} GiB free")
+    log(f"magnetic lattice {nx}x{ny}x{nz} fp32: {21 * 4 * n / 2**30:.0f} GiB of populations per buffer")
+    lat = MagneticLattice(nx, ny, nz, tau_m, storage="fp32", device="cuda:0")
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(520)
+    b = 0.02 * (torch.rand((3, nz, ny, nx), generator=gen, device="cuda:0") - 0.5)
+    u = 0.04 * (torch.rand((3, nz, ny, nx), generator=gen, device="cuda:0") - 0.5)
+    lat.init(b, u)
+    del b
+    torch.cuda.empty_cache()
+    xi, _ = M.constants()
+    g = W.generator(520)
+    corners = np.array([[x, y, z] for x in (0, nx - 1) for y in (0, ny - 1) for z in (0, nz - 1)])
+    s = np.concatenate([corners, np.stack([g.integers(0, nx, 2048), g.integers(0, ny, 2048),
+                                           g.integers(0, nz, 2048)], 1)])  # (x, y, z)
+    dims3 = np.array([nx, ny, nz])
+    lin = lambda q: torch.as_tensor((q[:, 2] * ny + q[:, 1]) * nx + q[:, 0], device="cuda:0")
+    P0 = lat.populations().reshape(7, 3, -1)
+    src = {l: (s - xi[l]) % dims3 for l in range(7)}
+    h0 = {l: P0[:, :, lin(src[l])].cpu().numpy() for l in range(7)}  # (7, 3, n) at x - xi_l
+    u0 = {l: u.reshape(3, -1)[:, lin(src[l])].double().cpu().numpy() for l in range(7)}
+    del P0
+    torch.cuda.empty_cache()
+    lat.step(u)
+    P1 = lat.populations().reshape(7, 3, -1)[:, :, lin(s)].cpu().numpy()
+    lat.close()
+    del lat, u
+    torch.cuda.empty_cache()
+    om = 1.0 / tau_m
+    err = 0.0
+    for l in range(7):
+        for k in range(len(s)):
+            hp = h0[l][:, :, k]
+            e = M.heq(hp.sum(axis=0), u0[l][:, k])
+            want = hp[l] + om * (e[l] - hp[l])
+            err = max(err, float(np.abs(P1[l, :, k] - want).max()))
+    log(f"  max |h - oracle| = {err:.3e}")
+    assert err < 2e-9
