@@ -303,6 +303,13 @@ class Trainer:
         self.ws = torch.empty(cmnn.mse_workspace(self.nvox) // 4, dtype=torch.float32, device=dev)
         self.gen = np.random.Generator(np.random.PCG64(12345))
         self.nsteps, self.norm_mean, self.nclipped = 0, 0.0, 0
+        # a step's gradient norm (pre-clip norm, applied scale) travels to the
+        # host behind its Adam kernels and is read during the next step, after
+        # that step's forward and backward are queued: the host never holds
+        # the GPU idle waiting for it
+        self._norm_host = torch.empty(2, dtype=torch.float32, pin_memory=True)
+        self._norm_event = None
+        self._norm_clip, self._norm_first = 0.0, True
 
     def minibatch(self, idx):
         """Gather samples idx into the packed network input self.xb and return
@@ -323,15 +330,28 @@ class Trainer:
         out = self.net.forward(self.xb)
         cmnn.mse(self.nvox, out, self.net.cout_head, NOUT, ys, ws, self.loss, self.dy, self.ws)
         self.net.backward(self.dy)
+        self.sync_stats()  # the previous step's norm, before this step's clip uses the mean
         clip = 0.0 if self.nsteps < 50 else 2.0 * self.norm_mean
         self.net.adam_step(lr, clip=clip)
-        gn = float(self.net.grad_norm[0].item())
-        if math.isfinite(gn):
-            gn = min(gn, clip) if clip > 0 else gn
-            self.norm_mean = gn if self.nsteps == 0 else 0.98 * self.norm_mean + 0.02 * gn
-        self.nclipped += int(clip > 0 and float(self.net.grad_norm[1].item()) < 1.0)
+        self._norm_host.copy_(self.net.grad_norm, non_blocking=True)
+        self._norm_event = self.torch.cuda.Event()
+        self._norm_event.record()
+        self._norm_clip, self._norm_first = clip, self.nsteps == 0
         self.nsteps += 1
         return self.loss
+
+    def sync_stats(self):
+        """Fold the last step's gradient norm into norm_mean and nclipped
+        (waits for that step's Adam update)."""
+        if self._norm_event is None:
+            return
+        self._norm_event.synchronize()
+        self._norm_event = None
+        gn, scale, clip = float(self._norm_host[0]), float(self._norm_host[1]), self._norm_clip
+        if math.isfinite(gn):
+            gn = min(gn, clip) if clip > 0 else gn
+            self.norm_mean = gn if self._norm_first else 0.98 * self.norm_mean + 0.02 * gn
+        self.nclipped += int(clip > 0 and scale < 1.0)
 
     def evaluate_loss(self, data=None):
         """Mean masked MSE over a dataset (default: the training data)."""
@@ -363,10 +383,12 @@ def train(data, steps=3000, batch=8, lr=4e-4, lr_min=4e-6, seed=0, log=print, te
         lr_s = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * (s - 1) / steps))
         loss = tr.step(lr_s)
         if s % 500 == 0 or s == 1:
+            tr.sync_stats()
             lv = float(loss[0].item())
             hist.append((s, lv))
             log(f"  step {s}: loss {lv:.3e} lr {lr_s:.2e} grad norm mean {tr.norm_mean:.2e} clipped {tr.nclipped} "
                 f"({time.perf_counter() - t0:.1f} s)")
+    tr.sync_stats()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     flops = 3 * net.flops_per_sample() * batch * steps
