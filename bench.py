@@ -49,6 +49,9 @@ STEP_KERNEL = {"fp32": "k_step<1, 1, false, false, true, 0, false, false>",
                "fp64": "k_step<0, 1, false, false, true, 0, false, false>"}
 # committed rocprofv3 counter summary (FETCH_SIZE, WRITE_SIZE) of every step configuration
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_step_counters.md")
+MOM_COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_step_mom_tgv_counters.md")
+# non-packed FP32 VALU: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1905_10182_amd", "csrc", f) for f in ("cmlbm.hip", "d3q27.hpp")]
 ALL_LEGS = ("fp32", "precision", "fp64", "mom", "d2q9", "mhd", "fused", "copy", "conv", "warmstart", "cpu")
 
@@ -65,18 +68,34 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(key):
-    """HBM bytes per launch of the step configuration `key` from its committed
-    rocprofv3 counter summary, or None if there is none or the kernel sources
-    changed since it was taken."""
-    if not os.path.exists(COUNTERS_FILE):
+def counter_value(path, name, key):
+    """A figure `name[key]` of a committed rocprofv3 counter summary, or None
+    if there is none or the kernel sources changed since it was taken."""
+    if not os.path.exists(path):
         return None
-    text = open(COUNTERS_FILE).read()
+    text = open(path).read()
     m = re.search(r"source_digest:\s*([0-9a-f]+)", text)
-    t = re.search(r"hbm_bytes_per_launch\[" + re.escape(key) + r"\]:\s*([0-9.eE+]+)", text)
+    t = re.search(re.escape(name) + r"\[" + re.escape(key) + r"\]:\s*([0-9.eE+]+)", text)
     if not m or not t or m.group(1) != source_digest():
         return None
     return float(t.group(1))
+
+
+def measured_traffic(key):
+    """HBM bytes per launch of the step configuration `key`."""
+    return counter_value(COUNTERS_FILE, "hbm_bytes_per_launch", key)
+
+
+def alu_roofline(n, glups):
+    """The moment kernel's VALU rate: its counted VALU lane-operations per
+    cell (rocprofv3 SQ_INSTS_VALU x 64 / cells) times the measured cell rate,
+    against the non-packed FP32 VALU peak; None without a current count."""
+    v = counter_value(MOM_COUNTERS_FILE, "valu_lane_ops_per_cell", f"mom32_{n}")
+    if v is None:
+        return None
+    a = v * glups * 1e9
+    return {"bound": "alu", "kernel": "k_step_mom", "achieved": round(a / 1e12, 2), "peak": round(VALU_PEAK_LANE_OPS / 1e12, 2),
+            "unit": "T lane-op/s", "frac": round(a / VALU_PEAK_LANE_OPS, 4), "valu_lane_ops_per_cell": v}
 
 
 def time_steps(lat, steps, warmup, repeats):
@@ -567,7 +586,8 @@ def main():
         rm = run_gpu(n, "mom32", K, W, R, fields=fields)
         extra[f"moment_storage_{n}"] = {
             "workload": f"taylor_green_{n}, nine FP32 numbers per cell (rho - rho0, u, (1 - omega) k4..k8), "
-                        "neighbour populations rebuilt in LDS", "bytes_per_cell": BYTES_PER_CELL["mom32"], **rm}
+                        "neighbour populations rebuilt in LDS", "bytes_per_cell": BYTES_PER_CELL["mom32"], **rm,
+            "roofline": alu_roofline(n, rm["glups"])}
         log(f"moment storage {n}^3: {rm['glups']:.2f} GLUPS")
     del fields
     torch.cuda.empty_cache()
@@ -599,7 +619,8 @@ def main():
         if "mom" in legs and n16 != n:
             log(f"TGV {n16}^3 moment storage (FP32)")
             rm = run_gpu(n16, "mom32", K, W, R, fields=f16)
-            extra[f"moment_storage_{n16}"] = {"bytes_per_cell": BYTES_PER_CELL["mom32"], **rm}
+            extra[f"moment_storage_{n16}"] = {"bytes_per_cell": BYTES_PER_CELL["mom32"], **rm,
+                                              "roofline": alu_roofline(n16, rm["glups"])}
             log(f"moment storage {n16}^3: {rm['glups']:.2f} GLUPS")
         del f16
         torch.cuda.empty_cache()
