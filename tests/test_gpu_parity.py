@@ -972,6 +972,76 @@ def test_full_size_kolmogorov_384_sampled(torch, storage):
 # ---------------------------------------------------------------------------
 # reductions, residual, checkpoint, failure detection
 
+# axes of one or two cells: a cell is its own periodic neighbour along a
+# one-cell axis, and 1 x 1 x 1 pulls every population from itself
+DEGENERATE = [(1, 1, 1), (1, 5, 3), (7, 1, 1), (2, 1, 3), (1, 1, 4), (65, 1, 2)]
+
+
+@pytest.mark.parametrize("dims", DEGENERATE)
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "fp16", "bf16"])
+def test_degenerate_extents_match_oracle(torch, storage, dims):
+    """One- and two-cell axes with a random non-equilibrium state and a
+    per-cell force field: FP64 within 1e-13 of the 80-bit oracle after 4
+    steps, FP32 within 1e-6 w_i, and the 16-bit formats one step from their
+    stored state within half a unit in the last place (+ 2e-7 w_i) of the
+    oracle's value.  A zero-step call changes nothing."""
+    nx, ny, nz = dims
+    shape = (1, nz, ny, nx)
+    log(f"{storage} {nx}x{ny}x{nz}")
+    g = W.generator(61)
+    force = g.uniform(-1e-3, 1e-3, size=(3,) + shape)
+    if storage != "fp64":
+        force = force.astype(np.float32)
+    lat = Lat(nx=nx, ny=ny, nz=nz, tau=0.7, storage=storage)
+    lat.set_force("field", field=force)
+    lat.load_populations(W.random_populations(shape, seed=62))
+    f0 = lat.populations().cpu().numpy()  # the state as stored
+    lat.step(0)
+    assert np.array_equal(lat.populations().cpu().numpy(), f0) and lat.time == 0
+    steps = 4 if storage in ("fp64", "fp32") else 1
+    ref = O.Lattice(nx, ny, nz, tau=0.7, force=force.astype(np.float64), extended=storage == "fp64")
+    ref.load_populations(f0)
+    ref.step(steps)
+    lat.step(steps)
+    out = lat.populations().cpu().numpy().reshape(27, -1)
+    fr = np.asarray(ref.f, np.float64).reshape(27, -1)
+    lat.close()
+    if storage == "fp64":
+        assert np.abs(out - fr).max() / np.abs(fr).max() < 1e-13
+    elif storage == "fp32":
+        assert (np.abs(out - fr) / WGT[:, None]).max() < 1e-6
+    else:
+        h_ref = fr - WGT[:, None]
+        err = np.abs((out - WGT[:, None]) - h_ref)
+        assert np.all(err <= 0.5 * ulp16(h_ref, storage) + 2e-7 * WGT[:, None])
+
+
+@pytest.mark.parametrize("dims", DEGENERATE)
+def test_mom32_degenerate_extents_match_oracle(torch, dims):
+    """Moment storage on one- and two-cell axes, from a random (rho, u) state
+    with a per-cell force field: density and velocity within 1e-6 of the
+    oracle after 4 steps."""
+    nx, ny, nz = dims
+    shape = (1, nz, ny, nx)
+    log(f"mom32 {nx}x{ny}x{nz}")
+    g = W.generator(63)
+    rho = 1.0 + 1e-2 * g.uniform(-1, 1, shape)
+    u = 0.05 * g.uniform(-1, 1, (3,) + shape)
+    force = g.uniform(-1e-3, 1e-3, size=(3,) + shape).astype(np.float32)
+    lat = Lat(nx=nx, ny=ny, nz=nz, tau=0.7, storage="mom32")
+    lat.set_force("field", field=force)
+    lat.init(rho, u)
+    ref = O.Lattice(nx, ny, nz, tau=0.7, force=force.astype(np.float64))
+    ref.init(rho, u)
+    lat.step(4)
+    ref.step(4)
+    r, v = lat.moments()
+    rr, vr = ref.moments()
+    lat.close()
+    assert np.abs(r.cpu().numpy() - rr).max() < 1e-6
+    assert np.abs(v.cpu().numpy() - vr).max() < 1e-6
+
+
 def test_reduce_matches_oracle_sums(torch):
     log("reduce vs oracle sums")
     shape = (2, 5, 6, 70)
