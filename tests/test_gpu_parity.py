@@ -1055,6 +1055,42 @@ def test_narrowest_walled_channels_match_oracle(torch, storage, dims, wall):
         assert (np.abs(out - fr) / WGT[:, None]).max() < 1e-6
 
 
+@pytest.mark.parametrize("stochastic", [False, True])
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+def test_16bit_walls_solids_force_one_step(torch, storage, stochastic):
+    """16-bit storage on the masked kernel: walls in y and z, solid nodes, a
+    per-cell force field, a ragged batch of two (70 cells per row: two cells
+    per lane with a partial last wave), one step from the stored random state:
+    every population within half a unit in the last place of the oracle's
+    value (nearest rounding) or within one unit (stochastic), + 2e-7 w_i."""
+    log(f"{storage} {'stochastic' if stochastic else 'nearest'} walls + solids 70x13x11 nb=2, one step")
+    shape = (2, 11, 13, 70)
+    g = W.generator(66)
+    solid = (g.uniform(size=shape) < 0.08).astype(np.uint8)
+    force = g.uniform(-1e-3, 1e-3, size=(3,) + shape).astype(np.float32)
+    f0 = W.random_populations(shape, seed=67)
+    f0[:, solid.astype(bool)] = 0.0
+    lat = Lat(nx=70, ny=13, nz=11, nbatch=2, tau=0.7, storage=storage, wall=(0, 1, 1), solid=True,
+              stochastic=stochastic)
+    lat.set_solid(solid)
+    lat.set_force("field", field=force)
+    lat.load_populations(f0)
+    f0 = lat.populations().cpu().numpy()  # the state as stored
+    ref = O.Lattice(70, 13, 11, nb=2, tau=0.7, wall=(0, 1, 1), solid=solid, force=force.astype(np.float64))
+    ref.load_populations(f0)
+    ref.step(1)
+    lat.step(1)
+    fluid = ~solid.astype(bool).reshape(-1)
+    out = lat.populations().cpu().numpy().reshape(27, -1)[:, fluid]
+    fr = np.asarray(ref.f, np.float64).reshape(27, -1)[:, fluid]
+    lat.close()
+    h_ref = fr - WGT[:, None]
+    err = np.abs((out - WGT[:, None]) - h_ref)
+    ulp = ulp16(h_ref, storage)
+    log(f"  max error in ulps {(err / ulp).max():.3f}")
+    assert np.all(err <= (1.0 if stochastic else 0.5) * ulp + 2e-7 * WGT[:, None])
+
+
 @pytest.mark.parametrize("dims", DEGENERATE)
 def test_mom32_degenerate_extents_match_oracle(torch, dims):
     """Moment storage on one- and two-cell axes, from a random (rho, u) state
