@@ -90,6 +90,12 @@ __device__ __forceinline__ bool neighbour(const G& g, long long m, int t, int s,
 #define GRID_STRIDE(i, total) \
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < (total); i += (long long)gridDim.x * blockDim.x)
 
+// The same with the index type I: the elementwise kernels below take 32-bit
+// unsigned index arithmetic (a quarter of the 64-bit division's work) when
+// every element index of the call fits, 64-bit otherwise.
+#define GRID_STRIDE_I(I, i, total) \
+    for (I i = (I)blockIdx.x * blockDim.x + threadIdx.x; i < (I)(total); i += (I)gridDim.x * blockDim.x)
+
 __device__ __forceinline__ void unpack8(u4 v, float (&f)[8])
 {
     const bf16x8 b = __builtin_bit_cast(bf16x8, v);
@@ -880,23 +886,24 @@ __global__ void k_act_bwd8(const u4* __restrict__ y, const u4* __restrict__ dy, 
     }
 }
 
+template <typename I>
 __global__ void k_pool2_fwd8(G g, const bf16* __restrict__ x, int c, bf16* __restrict__ y)
 {
-    const int d2 = g.d / 2, h2 = g.h / 2, w2 = g.w / 2, q8 = c / 8;
-    GRID_STRIDE(i, (long long)g.n * d2 * h2 * w2 * q8)
+    const I d2 = g.d / 2, h2 = g.h / 2, w2 = g.w / 2, q8 = c / 8;
+    GRID_STRIDE_I(I, i, (long long)g.n * d2 * h2 * w2 * q8)
     {
-        const int q = (int)(i % q8);
-        long long r = i / q8;
-        const int w = (int)(r % w2);
+        const I q = i % q8;
+        I r = i / q8;
+        const I w = r % w2;
         r /= w2;
-        const int h = (int)(r % h2);
+        const I h = r % h2;
         r /= h2;
-        const int d = (int)(r % d2);
-        const long long n = r / d2;
+        const I d = r % d2;
+        const I n = r / d2;
         float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, f[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const long long v = ((n * g.d + 2 * d + (k >> 2)) * g.h + 2 * h + ((k >> 1) & 1)) * g.w + 2 * w + (k & 1);
+            const I v = ((n * g.d + 2 * d + (k >> 2)) * g.h + 2 * h + ((k >> 1) & 1)) * g.w + 2 * w + (k & 1);
             unpack8(*(const u4*)(x + v * c + 8 * q), f);
 #pragma unroll
             for (int e = 0; e < 8; ++e) s[e] += f[e];
@@ -1020,25 +1027,26 @@ __global__ void k_add8(long long n8, const u4* __restrict__ a, const u4* __restr
 // strides multiples of 8, so every thread moves 8 channels (16 bytes).
 
 // y = [skip | up2(x)] at the fine level; g is the coarse geometry of x.
+template <typename I>
 __global__ void k_up2_concat_fwd8(G g, const bf16* __restrict__ skip, int cs, const bf16* __restrict__ x, int cx,
                                   bf16* __restrict__ y)
 {
-    const int D = 2 * g.d, H = 2 * g.h, W = 2 * g.w, qs = cs / 8, q8 = (cs + cx) / 8;
-    GRID_STRIDE(i, 8 * g.nvox * q8)
+    const I D = 2 * g.d, H = 2 * g.h, W = 2 * g.w, qs = cs / 8, q8 = (cs + cx) / 8;
+    GRID_STRIDE_I(I, i, 8 * g.nvox * q8)
     {
-        const int q = (int)(i % q8);
-        const long long v = i / q8;
+        const I q = i % q8;
+        const I v = i / q8;
         u4 e;
         if (q < qs) {
             e = *(const u4*)(skip + v * cs + 8 * q);
         } else {
-            const int w = (int)(v % W);
-            long long r = v / W;
-            const int h = (int)(r % H);
+            const I w = v % W;
+            I r = v / W;
+            const I h = r % H;
             r /= H;
-            const int d = (int)(r % D);
-            const long long n = r / D;
-            const long long p = ((n * g.d + d / 2) * g.h + h / 2) * g.w + w / 2;
+            const I d = r % D;
+            const I n = r / D;
+            const I p = ((n * g.d + d / 2) * g.h + h / 2) * g.w + w / 2;
             e = *(const u4*)(x + p * cx + 8 * (q - qs));
         }
         *(u4*)(y + i * 8) = e;
@@ -1057,24 +1065,25 @@ __device__ __forceinline__ void act_grad8(const bf16* __restrict__ gate, int act
 
 // dx = act'(gate) * (up2 gradient of dy): dy is the upsampled part of a
 // concatenation's gradient (channel stride ldy), g the coarse geometry.
+template <typename I>
 __global__ void k_up2_bwd_act8(G g, const bf16* __restrict__ dy, int ldy, int c, const bf16* __restrict__ gate,
                                int act, bf16* __restrict__ dx)
 {
-    const int H = 2 * g.h, W = 2 * g.w, q8 = c / 8;
-    GRID_STRIDE(i, g.nvox * q8)
+    const I H = 2 * g.h, W = 2 * g.w, q8 = c / 8;
+    GRID_STRIDE_I(I, i, g.nvox * q8)
     {
-        const int q = (int)(i % q8);
-        long long r = i / q8;
-        const int w = (int)(r % g.w);
+        const I q = i % q8;
+        I r = i / q8;
+        const I w = r % g.w;
         r /= g.w;
-        const int h = (int)(r % g.h);
+        const I h = r % g.h;
         r /= g.h;
-        const int d = (int)(r % g.d);
-        const long long n = r / g.d;
+        const I d = r % g.d;
+        const I n = r / g.d;
         float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, f[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const long long v = ((n * (2 * g.d) + 2 * d + (k >> 2)) * H + 2 * h + ((k >> 1) & 1)) * W + 2 * w + (k & 1);
+            const I v = ((n * (2 * g.d) + 2 * d + (k >> 2)) * H + 2 * h + ((k >> 1) & 1)) * W + 2 * w + (k & 1);
             unpack8(*(const u4*)(dy + v * ldy + 8 * q), f);
 #pragma unroll
             for (int e = 0; e < 8; ++e) s[e] += f[e];
@@ -1087,21 +1096,22 @@ __global__ void k_up2_bwd_act8(G g, const bf16* __restrict__ dy, int ldy, int c,
 // dx = act'(gate) * (pool2 gradient of dy + skip): g is the fine geometry, dy
 // coarse, skip the skip part of a concatenation's gradient (channel stride
 // ldskip) or NULL.
+template <typename I>
 __global__ void k_pool2_bwd_add_act8(G g, const bf16* __restrict__ dy, int c, const bf16* __restrict__ skip,
                                      int ldskip, const bf16* __restrict__ gate, int act, bf16* __restrict__ dx)
 {
-    const int q8 = c / 8;
-    GRID_STRIDE(i, g.nvox * q8)
+    const I q8 = c / 8;
+    GRID_STRIDE_I(I, i, g.nvox * q8)
     {
-        const int q = (int)(i % q8);
-        const long long v = i / q8;
-        const int w = (int)(v % g.w);
-        long long r = v / g.w;
-        const int h = (int)(r % g.h);
+        const I q = i % q8;
+        const I v = i / q8;
+        const I w = v % g.w;
+        I r = v / g.w;
+        const I h = r % g.h;
         r /= g.h;
-        const int d = (int)(r % g.d);
-        const long long n = r / g.d;
-        const long long p = ((n * (g.d / 2) + d / 2) * (g.h / 2) + h / 2) * (g.w / 2) + w / 2;
+        const I d = r % g.d;
+        const I n = r / g.d;
+        const I p = ((n * (g.d / 2) + d / 2) * (g.h / 2) + h / 2) * (g.w / 2) + w / 2;
         float f[8], t[8];
         unpack8(*(const u4*)(dy + p * c + 8 * q), f);
 #pragma unroll
@@ -1196,24 +1206,25 @@ __global__ void k_mse_grad(long long nvox, const bf16* __restrict__ pred, int c,
 
 // 8 channels per thread: channels below creal get the gradient, the padded
 // ones zeros (their prediction is not read)
+template <typename I>
 __global__ void k_mse_grad8(long long nvox, const bf16* __restrict__ pred, int c, int creal,
                             const float* __restrict__ tgt, const float* __restrict__ wt,
                             const float* __restrict__ norm, bf16* __restrict__ dpred)
 {
     const float scale = norm[1] > 0.f ? 2.f / norm[1] : 0.f;
-    const int q8 = c / 8;
-    GRID_STRIDE(i, nvox * q8)
+    const I q8 = c / 8, nv = (I)nvox;
+    GRID_STRIDE_I(I, i, nvox * q8)
     {
-        const int q = (int)(i % q8);
-        const long long v = i / q8;
+        const I q = i % q8;
+        const I v = i / q8;
         float f[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        if (8 * q < creal) {
+        if ((int)(8 * q) < creal) {
             float p[8];
             unpack8(*(const u4*)(pred + i * 8), p);
             const float sw = scale * wt[v];
 #pragma unroll
             for (int e = 0; e < 8; ++e)
-                if (8 * q + e < creal) f[e] = sw * (p[e] - tgt[(long long)(8 * q + e) * nvox + v]);
+                if ((int)(8 * q) + e < creal) f[e] = sw * (p[e] - tgt[(8 * q + e) * nv + v]);
         }
         *(u4*)(dpred + i * 8) = pack8(f);
     }
@@ -1347,19 +1358,21 @@ __device__ __forceinline__ long long pick(const int* __restrict__ idx, long long
 }
 
 // BF16 NDHWC [nsel * nvs][c] (channels from cs on zero), 8 channels per thread
+template <typename I>
 __global__ void k_gather_pack8(int nsel, const int* __restrict__ idx, long long nvs, const float* __restrict__ src,
                                int nsrc, int cs, bf16* __restrict__ dst, int c)
 {
-    const int q8 = c / 8;
-    GRID_STRIDE(i, (long long)nsel * nvs * q8)
+    const I q8 = c / 8, nv = (I)nvs;
+    GRID_STRIDE_I(I, i, (long long)nsel * nvs * q8)
     {
-        const int q = (int)(i % q8);
-        const long long r = i / q8, v = r % nvs, s = pick(idx, r / nvs, nsrc);
+        const I q = i % q8;
+        const I r = i / q8, v = r % nv;
+        const long long s = pick(idx, (long long)(r / nv), nsrc);
         float f[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        if (s >= 0 && 8 * q < cs)
+        if (s >= 0 && (int)(8 * q) < cs)
 #pragma unroll
             for (int e = 0; e < 8; ++e)
-                if (8 * q + e < cs) f[e] = src[((long long)(8 * q + e) * nsrc + s) * nvs + v];
+                if ((int)(8 * q) + e < cs) f[e] = src[((8 * q + e) * (I)nsrc + (I)s) * nv + v];
         *(u4*)(dst + i * 8) = pack8(f);
     }
 }
@@ -1612,6 +1625,19 @@ int static_scratch(void** out)
     return CMNN_OK;
 }
 
+// every element index a call's kernel forms is below 2^32: its 32-bit index variant
+bool idx32(long long elements) { return elements < (1LL << 32); }
+
+void gather_pack(long long nsel, const int* idx, long long nvs, const float* src, int nsrc, int cs, bf16* dst, int c,
+                 hipStream_t s)
+{
+    const long long n8 = nsel * nvs * c / 8;
+    if (idx32(nsel * nvs * c) && idx32((long long)cs * nsrc * nvs))
+        k_gather_pack8<uint32_t><<<grid_for(n8), 256, 0, s>>>((int)nsel, idx, nvs, src, nsrc, cs, dst, c);
+    else
+        k_gather_pack8<uint64_t><<<grid_for(n8), 256, 0, s>>>((int)nsel, idx, nvs, src, nsrc, cs, dst, c);
+}
+
 // the fine level of a coarse geometry must fit the voxel limit too
 bool coarse_ok(const cmnn_geom* g) { return geom_ok(g) && 8LL * g->n * g->d * g->h * g->w <= 0x7fffffffLL; }
 bool ld_ok(int ld, int c) { return ld >= c && ld % 8 == 0; }
@@ -1763,7 +1789,14 @@ int cmnn_pool2_fwd(const cmnn_geom* g, const void* x, int32_t c, void* y, void* 
     if (!geom_ok(g) || c <= 0 || !x || !y || (g->d | g->h | g->w) & 1) return CMNN_EINVAL;
     const G gg = make_g(g);
     if (c % 8 == 0 && al16(x) && al16(y))
-        k_pool2_fwd8<<<grid_for(gg.nvox * c / 64), 256, 0, (hipStream_t)hip_stream>>>(gg, (const bf16*)x, c, (bf16*)y);
+    {
+        if (idx32(gg.nvox * c))
+            k_pool2_fwd8<uint32_t><<<grid_for(gg.nvox * c / 64), 256, 0, (hipStream_t)hip_stream>>>(gg, (const bf16*)x,
+                                                                                                   c, (bf16*)y);
+        else
+            k_pool2_fwd8<uint64_t><<<grid_for(gg.nvox * c / 64), 256, 0, (hipStream_t)hip_stream>>>(gg, (const bf16*)x,
+                                                                                                   c, (bf16*)y);
+    }
     else
         k_pool2_fwd<<<grid_for(gg.nvox * c / 8), 256, 0, (hipStream_t)hip_stream>>>(gg, (const bf16*)x, c, (bf16*)y);
     return launched();
@@ -1832,8 +1865,12 @@ int cmnn_up2_concat_fwd(const cmnn_geom* g, const void* skip, int32_t cs, const 
     if (!coarse_ok(g) || !chan_ok(cs) || !chan_ok(cx) || !skip || !x || !y || !al16(skip) || !al16(x) || !al16(y))
         return CMNN_EINVAL;
     const G gg = make_g(g);
-    k_up2_concat_fwd8<<<grid_for(8 * gg.nvox * (cs + cx) / 8), 256, 0, (hipStream_t)hip_stream>>>(
-        gg, (const bf16*)skip, cs, (const bf16*)x, cx, (bf16*)y);
+    if (idx32(8 * gg.nvox * (cs + cx)))
+        k_up2_concat_fwd8<uint32_t><<<grid_for(8 * gg.nvox * (cs + cx) / 8), 256, 0, (hipStream_t)hip_stream>>>(
+            gg, (const bf16*)skip, cs, (const bf16*)x, cx, (bf16*)y);
+    else
+        k_up2_concat_fwd8<uint64_t><<<grid_for(8 * gg.nvox * (cs + cx) / 8), 256, 0, (hipStream_t)hip_stream>>>(
+            gg, (const bf16*)skip, cs, (const bf16*)x, cx, (bf16*)y);
     return launched();
 }
 
@@ -1843,8 +1880,12 @@ int cmnn_up2_bwd_act(const cmnn_geom* g, const void* dy, int32_t ldy, int32_t c,
     if (!coarse_ok(g) || !chan_ok(c) || !ld_ok(ldy, c) || !dy || !dx || !al16(dy) || !al16(dx) || !gate_ok(gate, act))
         return CMNN_EINVAL;
     const G gg = make_g(g);
-    k_up2_bwd_act8<<<grid_for(gg.nvox * c / 8), 256, 0, (hipStream_t)hip_stream>>>(
-        gg, (const bf16*)dy, ldy, c, (const bf16*)gate, act, (bf16*)dx);
+    if (idx32(8 * gg.nvox * ldy))
+        k_up2_bwd_act8<uint32_t><<<grid_for(gg.nvox * c / 8), 256, 0, (hipStream_t)hip_stream>>>(
+            gg, (const bf16*)dy, ldy, c, (const bf16*)gate, act, (bf16*)dx);
+    else
+        k_up2_bwd_act8<uint64_t><<<grid_for(gg.nvox * c / 8), 256, 0, (hipStream_t)hip_stream>>>(
+            gg, (const bf16*)dy, ldy, c, (const bf16*)gate, act, (bf16*)dx);
     return launched();
 }
 
@@ -1856,8 +1897,12 @@ int cmnn_pool2_bwd_add_act(const cmnn_geom* g, const void* dy, int32_t c, const 
         return CMNN_EINVAL;
     if (skip && (!al16(skip) || !ld_ok(ldskip, c))) return CMNN_EINVAL;
     const G gg = make_g(g);
-    k_pool2_bwd_add_act8<<<grid_for(gg.nvox * c / 8), 256, 0, (hipStream_t)hip_stream>>>(
-        gg, (const bf16*)dy, c, (const bf16*)skip, ldskip, (const bf16*)gate, act, (bf16*)dx);
+    if (idx32(gg.nvox * (skip && ldskip > c ? ldskip : c)))
+        k_pool2_bwd_add_act8<uint32_t><<<grid_for(gg.nvox * c / 8), 256, 0, (hipStream_t)hip_stream>>>(
+            gg, (const bf16*)dy, c, (const bf16*)skip, ldskip, (const bf16*)gate, act, (bf16*)dx);
+    else
+        k_pool2_bwd_add_act8<uint64_t><<<grid_for(gg.nvox * c / 8), 256, 0, (hipStream_t)hip_stream>>>(
+            gg, (const bf16*)dy, c, (const bf16*)skip, ldskip, (const bf16*)gate, act, (bf16*)dx);
     return launched();
 }
 
@@ -1958,8 +2003,12 @@ int cmnn_mse(size_t nvox, const void* pred, int32_t c, int32_t creal, const floa
     k_mse_final<<<1, 256, 0, s>>>(part, kMseBlocks, creal, loss_out);
     if (launched()) return CMNN_EHIP;
     if (dpred && c % 8 == 0 && al16(pred) && al16(dpred)) {
-        k_mse_grad8<<<grid_for((long long)nvox * c / 8), 256, 0, s>>>((long long)nvox, (const bf16*)pred, c, creal,
-                                                                     target, weight, loss_out, (bf16*)dpred);
+        if (idx32((long long)nvox * c))
+            k_mse_grad8<uint32_t><<<grid_for((long long)nvox * c / 8), 256, 0, s>>>(
+                (long long)nvox, (const bf16*)pred, c, creal, target, weight, loss_out, (bf16*)dpred);
+        else
+            k_mse_grad8<uint64_t><<<grid_for((long long)nvox * c / 8), 256, 0, s>>>(
+                (long long)nvox, (const bf16*)pred, c, creal, target, weight, loss_out, (bf16*)dpred);
         if (launched()) return CMNN_EHIP;
     } else if (dpred) {
         k_mse_grad<<<grid_for((long long)nvox * c), 256, 0, s>>>((long long)nvox, (const bf16*)pred, c, creal, target,
@@ -2037,8 +2086,7 @@ int cmnn_pack_channels(size_t nvox, const float* src, int32_t cs, void* dst, int
     if (!src || !dst || cs <= 0 || c < cs) return CMNN_EINVAL;
     if (c % 8 == 0 && al16(dst)) {
         // one "sample" of nvox voxels, taken in place
-        k_gather_pack8<<<grid_for((long long)nvox * c / 8), 256, 0, (hipStream_t)hip_stream>>>(
-            1, nullptr, (long long)nvox, src, 1, cs, (bf16*)dst, c);
+        gather_pack((long long)1, nullptr, (long long)nvox, src, 1, cs, (bf16*)dst, c, (hipStream_t)hip_stream);
         return launched();
     }
     k_pack_ch<<<grid_for((long long)nvox * c), 256, 0, (hipStream_t)hip_stream>>>((long long)nvox, src, cs, (bf16*)dst,
@@ -2051,8 +2099,7 @@ int cmnn_gather_pack_channels(int32_t nsel, const int32_t* idx, size_t nvs, cons
 {
     if (nsel <= 0 || !idx || nvs == 0 || !src || nsrc <= 0 || cs <= 0 || c < cs || c % 8 != 0 || !dst || !al16(dst))
         return CMNN_EINVAL;
-    k_gather_pack8<<<grid_for((long long)nsel * nvs * c / 8), 256, 0, (hipStream_t)hip_stream>>>(
-        nsel, idx, (long long)nvs, src, nsrc, cs, (bf16*)dst, c);
+    gather_pack(nsel, idx, (long long)nvs, src, nsrc, cs, (bf16*)dst, c, (hipStream_t)hip_stream);
     return launched();
 }
 
