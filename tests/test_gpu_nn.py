@@ -251,6 +251,115 @@ def test_skip_joins(torch, nn, cs, cx):
         assert close_bf16(ds.float().cpu().numpy(), ref, mag) <= 1.0, (act, with_skip)
 
 
+def test_joins_past_2_to_32_elements(torch, nn):
+    """The skip joins and pooling on tensors of more than 2^32 elements (their
+    64-bit index variants; 2 x 256 x 256 x 520 fine voxels, 64 channels): the
+    outputs at 2048 sampled voxels against the oracle's operations on each
+    voxel's neighbourhood (a concatenation bitwise, sums within a BF16 ulp)."""
+    fine, coarse = (2, 256, 256, 520), (2, 128, 128, 260)
+    nf = int(np.prod(fine))
+    assert nf * 64 >= 2 ** 32
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    if free < 40 * 2 ** 30:
+        pytest.skip(f"needs 40 GiB of free device memory, {free / 2**30:.0f} GiB free")
+    log("joins past 2^32 elements")
+    dev, bf = "cuda:0", torch.bfloat16
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(32)
+    g, gc = nn.geom(*fine), nn.geom(*coarse)
+    skip = torch.randn(fine + (32,), generator=gen, device=dev).to(bf)
+    x = torch.randn(coarse + (32,), generator=gen, device=dev).to(bf)
+    y = torch.empty(fine + (64,), dtype=bf, device=dev)
+    nn.up2_concat_fwd(gc, skip, 32, x, 32, y)
+    rg = W.generator(33)
+    v = np.stack([rg.integers(0, e, 2048) for e in fine], 1)  # (n, d, h, w) of sampled fine voxels
+    vc = np.stack([rg.integers(0, e, 2048) for e in coarse], 1)
+
+    def at(t, idx):  # values of t (5-D) at rows of (n, d, h, w) indices, FP64
+        i = [torch.as_tensor(idx[:, a], device=dev) for a in range(4)]
+        return t[i[0], i[1], i[2], i[3]].double().cpu().numpy()
+
+    par = v.copy()
+    par[:, 1:] //= 2
+    assert np.array_equal(at(y, v), np.concatenate([at(skip, v), at(x, par)], 1))
+    kids = [vc * np.array([1, 2, 2, 2]) + np.array([0, k >> 2, (k >> 1) & 1, k & 1]) for k in range(8)]
+    # upsampled part of the concatenation's gradient (y as dy), with the activation gradient
+    gate_c = torch.randn(coarse + (32,), generator=gen, device=dev).to(bf)
+    dxc = torch.empty(coarse + (32,), dtype=bf, device=dev)
+    nn.up2_bwd_act(gc, y, 32, 64, 32, gate_c, nn.ACT_LEAKY, dxc)
+    blk = np.stack([at(y, kv)[:, 32:] for kv in kids], 1).reshape(-1, 2, 2, 2, 32)[:, None]  # (s, 1, 2, 2, 2, c)
+    ref = np.stack([C.up2_grad(b[None])[0, 0, 0, 0] for b in blk[:, 0]])
+    ref = C.leaky_grad_from_output(at(gate_c, vc), ref)
+    mag = np.stack([C.up2_grad(np.abs(b[None]))[0, 0, 0, 0] for b in blk[:, 0]])
+    assert close_bf16(at(dxc, vc), ref, mag) <= 1.0
+    # pooling of the 64-channel tensor
+    pc = torch.empty(coarse + (64,), dtype=bf, device=dev)
+    nn.pool2_fwd(g, y, 64, pc)
+    blk = np.stack([at(y, kv) for kv in kids], 1).reshape(-1, 2, 2, 2, 64)
+    ref = np.stack([C.pool2(b[None])[0, 0, 0, 0] for b in blk])
+    mag = np.stack([C.pool2(np.abs(b[None]))[0, 0, 0, 0] for b in blk])
+    assert close_bf16(at(pc, vc), ref, mag) <= 1.0
+    del pc, dxc
+    # encoder join: pooling gradient of a coarse 32-channel dy plus the skip part of y, activation gradient at skip
+    dyc = torch.randn(coarse + (32,), generator=gen, device=dev).to(bf)
+    dxf = torch.empty(fine + (32,), dtype=bf, device=dev)
+    nn.pool2_bwd_add_act(g, dyc, 32, y, 0, 64, skip, nn.ACT_LEAKY, dxf)
+    ref = C.leaky_grad_from_output(at(skip, v), at(dyc, par) / 8.0 + at(y, v)[:, :32])
+    mag = np.abs(at(dyc, par)) / 8.0 + np.abs(at(y, v)[:, :32])
+    assert close_bf16(at(dxf, v), ref, mag) <= 1.0
+    del skip, x, y, gate_c, dyc, dxf
+    torch.cuda.empty_cache()
+
+
+def test_mse_and_gather_past_2_to_32_elements(torch, nn):
+    """The minibatch gather-and-pack and the MSE gradient on more than 2^32
+    output elements (their 64-bit index variants): 2 samples of 67,174,400
+    voxels packed to 32 channels, and the masked MSE over those voxels; sampled
+    voxels against the definitions (the packing's FP32 -> BF16 rounding
+    bitwise, the gradient within a BF16 ulp of 2 w (p - t) / (creal sum w))."""
+    nvs, nsel, nsrc, c = 67_174_400, 2, 3, 32
+    assert nsel * nvs * c >= 2 ** 32
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    if free < 40 * 2 ** 30:
+        pytest.skip(f"needs 40 GiB of free device memory, {free / 2**30:.0f} GiB free")
+    log("gather + mse past 2^32 elements")
+    dev = "cuda:0"
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(34)
+    src = torch.rand((2, nsrc, nvs), generator=gen, device=dev)
+    idx = torch.as_tensor([2, 0], dtype=torch.int32, device=dev)
+    packed = torch.empty((nsel * nvs, c), dtype=torch.bfloat16, device=dev)
+    nn.gather_pack_channels(idx, src, packed, c)
+    rg = W.generator(35)
+    rows = rg.integers(0, nsel * nvs, 2048)
+    rt = torch.as_tensor(rows, device=dev)
+    got = packed[rt].float().cpu().numpy()
+    b, vv = rows // nvs, rows % nvs
+    want = np.stack([src[:, [2, 0][k], int(u)].cpu().numpy() for k, u in zip(b, vv)])
+    want = torch.as_tensor(want).to(torch.bfloat16).float().numpy()
+    assert np.array_equal(got[:, :2], want) and np.all(got[:, 2:] == 0)
+    del src
+    nv, creal = nsel * nvs, 3
+    tgt = torch.rand((creal, nv), generator=gen, device=dev)
+    wt = (torch.rand((nv,), generator=gen, device=dev) > 0.2).float()
+    loss = torch.empty(2, dtype=torch.float32, device=dev)
+    dpred = torch.empty_like(packed)
+    ws = torch.empty(nn.mse_workspace(nv) // 4, dtype=torch.float32, device=dev)
+    nn.mse(nv, packed, c, creal, tgt, wt, loss, dpred, ws)
+    norm = float(loss[1].item())
+    assert abs(norm / (creal * float(wt.double().sum().item())) - 1) < 1e-6
+    p = packed[rt].double().cpu().numpy()[:, :creal]
+    t = tgt[:, rt].double().cpu().numpy().T
+    w = wt[rt].double().cpu().numpy()[:, None]
+    ref = 2.0 * w * (p - t) / norm
+    g = dpred[rt].float().cpu().numpy()
+    assert close_bf16(g[:, :creal], ref, np.abs(ref)) <= 1.0 and np.all(g[:, creal:] == 0)
+    del packed, tgt, wt, dpred, ws
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("c", [64, 12])
 def test_channel_mean(torch, nn, c):
     log(f"channel mean broadcast c={c}")
