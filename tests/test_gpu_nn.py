@@ -173,6 +173,69 @@ def test_conv_large_sampled(torch, nn, kind, dims, cin, cout, per):
         assert np.all(np.abs(yg[tuple(v)] - acc) <= np.abs(acc) * 2.0 ** -8 + 1e-3), (v, kind)
 
 
+def test_conv_past_4_gib_tensors(torch, nn):
+    """Convolutions on activations of more than 4 GiB (16 x 64 x 256 x 272
+    voxels, 32 channels, 4.6 GB per tensor): the forward and data-gradient
+    brick tiles on 64 sampled output voxels from the definition, and the
+    weight gradient (which takes its generic kernel past 2^32 bytes) through
+    the adjoint identity sum_v dy . conv(x, w) = sum w . dW(x, dy), exact up
+    to the BF16 rounding of the forward output."""
+    dims, cin, cout, per = (16, 64, 256, 272), 32, 32, (1, 0, 1)
+    nv = int(np.prod(dims))
+    assert nv * cin * 2 >= 2 ** 32
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    if free < 40 * 2 ** 30:
+        pytest.skip(f"needs 40 GiB of free device memory, {free / 2**30:.0f} GiB free")
+    log(f"conv past 4 GiB: {dims} {cin}->{cout}")
+    dev, bf = "cuda:0", torch.bfloat16
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(36)
+    g = nn.geom(*dims, periodic=per)
+    x = torch.randn(dims + (cin,), generator=gen, device=dev).to(bf)
+    dy = torch.randn(dims + (cout,), generator=gen, device=dev).to(bf)
+    w, wr = bf16_tensor(torch, randn((27, cout, cin), 37, 0.05))
+    wt = w.transpose(1, 2).contiguous()
+    y = torch.empty(dims + (cout,), dtype=bf, device=dev)
+    dx = torch.empty(dims + (cin,), dtype=bf, device=dev)
+    nn.conv_fwd(g, x, cin, w, None, cout, nn.ACT_NONE, y)
+    nn.conv_bwd_data(g, dy, cout, wt, cin, dx)
+    rg = W.generator(38)
+    for kind, src_t, out_t, sign, wmat in (("fwd", x, y, 1, wr), ("bwd", dy, dx, -1, wr.transpose(0, 2, 1))):
+        for _ in range(64):
+            v = [int(rg.integers(s_)) for s_ in dims]
+            acc = np.zeros(out_t.shape[-1])
+            for t, off in enumerate(C.taps()):
+                srcv, ok = [v[0]], True
+                for a in range(3):
+                    q = v[a + 1] + sign * off[a]
+                    if not 0 <= q < dims[a + 1]:
+                        if not per[a]:
+                            ok = False
+                            break
+                        q %= dims[a + 1]
+                    srcv.append(q)
+                if ok:
+                    acc += wmat[t] @ src_t[tuple(srcv)].double().cpu().numpy()
+            got = out_t[tuple(v)].double().cpu().numpy()
+            assert np.all(np.abs(got - acc) <= np.abs(acc) * 2.0 ** -8 + 1e-3), (v, kind)
+    del dx
+    ws = torch.empty(nn.conv_bwd_weight_workspace(g, cin, cout) // 4, dtype=torch.float32, device=dev)
+    dw = torch.empty((27, cout, cin), dtype=torch.float32, device=dev)
+    nn.conv_bwd_weight(g, x, cin, dy, cout, dw, None, ws)
+    prod = dy.double() * y.double()
+    lhs, rms = float(prod.sum().item()), float(prod.square().sum().sqrt().item())
+    del prod
+    rhs = float((w.double() * dw.double()).sum().item())
+    # the forward output's BF16 rounding (<= 2^-9 relative, random in sign)
+    # moves <dy, y> by about 2^-9 rms; one missing tap would move <w, dW> by
+    # about 0.05 x 32 x sqrt(voxels), over ten times more
+    log(f"  <dy, y> = {lhs:.6e}, <w, dW> = {rhs:.6e}, rounding scale {2.0 ** -9 * rms:.3e}")
+    assert abs(lhs - rhs) <= 2.0 ** -6 * rms
+    del x, dy, y, ws, dw
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("c,ca,cb,nl", [(32, 32, 64, 1000), (12, 12, 20, 1001)])
 def test_elementwise_ops(torch, nn, c, ca, cb, nl):
     """Channel counts that are multiples of 8 take the 16-byte kernels, the others the scalar ones."""
