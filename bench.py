@@ -60,6 +60,22 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+_RANGE = []
+
+
+def mark(name):
+    """Consecutive roctx ranges, one per leg (torch.cuda.nvtx is roctx on ROCm),
+    so that a rocprofv3 --marker-trace of a bench run names each leg's kernels;
+    None closes the last one."""
+    import torch
+    if _RANGE:
+        torch.cuda.nvtx.range_pop()
+        _RANGE.pop()
+    if name:
+        torch.cuda.nvtx.range_push(name)
+        _RANGE.append(name)
+
+
 def source_digest():
     import hashlib
     h = hashlib.sha256()
@@ -568,10 +584,12 @@ def main():
     main_run = None
     extra = {}
     if "fp32" in legs:
+        mark("fp32")
         log(f"TGV {n}^3 fp32: {W} warmup + {R} x {K} timed steps")
         main_run = run_gpu(n, "fp32", K, W, R, fields=fields)
         log(f"fp32 {main_run['glups']:.2f} GLUPS ({main_run['window_ms_per_step']} ms per step)")
     if "fp64" in legs:
+        mark("fp64")
         log(f"TGV {n}^3 fp64 storage")
         r64 = run_gpu(n, "fp64", K, W, R, fields=fields)
         extra["fp64_storage"] = {"workload": f"taylor_green_{n}, fp64 populations and arithmetic",
@@ -579,9 +597,11 @@ def main():
                                  "traffic": measured_traffic("fp64"), **r64}
         log(f"fp64 {r64['glups']:.2f} GLUPS")
     if "fused" in legs:
+        mark("fused")
         log(f"fused reductions, TGV {n}^3 fp32")
         extra["fused_reduce"] = run_fused(n, 20, fields)
     if "mom" in legs:
+        mark("mom")
         log(f"TGV {n}^3 moment storage (FP32)")
         rm = run_gpu(n, "mom32", K, W, R, fields=fields)
         extra[f"moment_storage_{n}"] = {
@@ -595,6 +615,7 @@ def main():
     if "precision" in legs or ("mom" in legs and n16 != n):
         f16 = device_fields(n16)
         if "precision" in legs:
+            mark("precision")
             names = [s for s in args.precision.split(",") if s]
             prec = precision_legs(n16, names, K, W, R, args.error_steps, f16)
             ref32 = prec.get("fp32", {}).get("glups")
@@ -617,6 +638,7 @@ def main():
                     "meets_1.7x_at_1e-3": bool(target["speedup_vs_fp32_same_size"] >= 1.7 and e is not None
                                                and e <= 1e-3)}
         if "mom" in legs and n16 != n:
+            mark(f"mom_{n16}")
             log(f"TGV {n16}^3 moment storage (FP32)")
             rm = run_gpu(n16, "mom32", K, W, R, fields=f16)
             extra[f"moment_storage_{n16}"] = {"bytes_per_cell": BYTES_PER_CELL["mom32"], **rm,
@@ -625,6 +647,7 @@ def main():
         del f16
         torch.cuda.empty_cache()
     if "d2q9" in legs:
+        mark("d2q9")
         n2 = 8192
         res2 = {}
         for st in ("fp32", "fp16", "fp64"):
@@ -634,23 +657,28 @@ def main():
         extra["d2q9"] = {"workload": f"four_rolls_mill_2d_{n2} (App. B model, Re 100, u0 1e-3, per-cell force field)",
                          **res2}
     if "mhd" in legs:
+        mark("mhd")
         log("magnetic lattice 256^3 fp32")
         rmag = run_gpu_mhd(256, K, W, R)
         extra["mhd_magnetic_lattice"] = {
             "workload": "D3Q7 vector populations (App. C), 256^3 periodic, fp32, fixed velocity field", **rmag}
         log(f"magnetic lattice {rmag['glups']:.2f} GLUPS")
     if "copy" in legs:
+        mark("copy")
         from paper_1905_10182_amd.cmlbm import device_copy
         extra["device_copy_gbs"] = round(copy_bandwidth(lambda b, a: b.copy_(a)), 1)  # torch's copy
         extra["kernel_copy_gbs"] = round(copy_bandwidth(device_copy), 1)  # 16-byte non-temporal copy kernel
         extra["plane_copy"] = plane_copy_rate()  # the FP32 step's access pattern without arithmetic
     if "conv" in legs:
+        mark("conv")
         log("U-Net training steps and convolution kernels (libcmnn)")
         extra["conv"] = run_conv(max(K // 10, 5), max(W // 10, 2), R)
         log(f"U-Net training step {extra['conv']['ms_per_step']} ms, {extra['conv']['conv_tflops']} TFLOP/s")
     if "warmstart" in legs:
+        mark("warmstart")
         log("warm start: 64 sphere channels 64x32x32, cold vs U-Net init")
         extra["warm_start"] = warm_start()
+    mark(None)
     cpu = None
     if "cpu" in legs:
         log("cpu baseline (oracle, taylor_green 256^3)")
