@@ -308,7 +308,8 @@ class Trainer:
         # that step's forward and backward are queued: the host never holds
         # the GPU idle waiting for it
         self._norm_host = torch.empty(2, dtype=torch.float32, pin_memory=True)
-        self._norm_event = None
+        self._norm_event = torch.cuda.Event()
+        self._norm_pending = False
         self._norm_clip, self._norm_first = 0.0, True
 
     def minibatch(self, idx):
@@ -334,8 +335,8 @@ class Trainer:
         clip = 0.0 if self.nsteps < 50 else 2.0 * self.norm_mean
         self.net.adam_step(lr, clip=clip)
         self._norm_host.copy_(self.net.grad_norm, non_blocking=True)
-        self._norm_event = self.torch.cuda.Event()
         self._norm_event.record()
+        self._norm_pending = True
         self._norm_clip, self._norm_first = clip, self.nsteps == 0
         self.nsteps += 1
         return self.loss
@@ -343,10 +344,10 @@ class Trainer:
     def sync_stats(self):
         """Fold the last step's gradient norm into norm_mean and nclipped
         (waits for that step's Adam update)."""
-        if self._norm_event is None:
+        if not self._norm_pending:
             return
         self._norm_event.synchronize()
-        self._norm_event = None
+        self._norm_pending = False
         gn, scale, clip = float(self._norm_host[0]), float(self._norm_host[1]), self._norm_clip
         if math.isfinite(gn):
             gn = min(gn, clip) if clip > 0 else gn
