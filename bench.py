@@ -21,7 +21,8 @@ and the other legs:
     of the paper) and with the FP32 run; then timed.  The 16-bit speed-ups
     are given against FP32 at the same size;
   - FP64 storage at 256^3, moment storage, the D2Q9 model, the magnetic
-    lattice, the fused reductions, copy kernels and the learned warm start.
+    lattice, the Shan-Chen droplet's coupled step, the fused reductions, copy
+    kernels and the learned warm start.
 """
 import argparse
 import json
@@ -53,7 +54,7 @@ MOM_COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_step_mom_tgv_counters.md")
 # non-packed FP32 VALU: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz
 VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1905_10182_amd", "csrc", f) for f in ("cmlbm.hip", "d3q27.hpp")]
-ALL_LEGS = ("fp32", "precision", "fp64", "mom", "d2q9", "mhd", "fused", "copy", "conv", "warmstart", "cpu")
+ALL_LEGS = ("fp32", "precision", "fp64", "mom", "d2q9", "mhd", "shanchen", "fused", "copy", "conv", "warmstart", "cpu")
 
 
 def log(msg):
@@ -256,6 +257,65 @@ def run_gpu_2d(n, storage, steps, warmup, repeats):
 
 # magnetic lattice (FP32): 21 populations read + 21 written, u (3 values) read
 BYTES_PER_CELL_MHD = 21 * 4 * 2 + 12
+
+
+def run_shan_chen(n, steps, warmup, repeats):
+    """The static droplet's coupled step at n^3 in FP32 (radius n / 5, G = -6):
+    the density from the moment export, the Shan-Chen force from it
+    (k_pseudopotential), then the fused step with that force field; and the
+    force kernel alone, whose algorithmic traffic is the density read once and
+    the three force components written, 16 B per cell."""
+    import torch
+
+    import workloads
+    from paper_1905_10182_amd import Lattice
+    from paper_1905_10182_amd.cmlbm import RED
+
+    wl = workloads.static_droplet(n, n / 5.0)
+    lat = Lattice(n, n, n, tau=wl["tau"], storage="fp32", device="cuda:0")
+    field = torch.zeros((3,) + lat.shape, dtype=torch.float32, device="cuda:0")
+    lat.set_force("field", field=field)
+    lat.init(wl["rho"], wl["u"])
+    g = wl["g"]
+    del wl
+
+    rho = torch.empty(lat.shape, dtype=torch.float32, device="cuda:0")
+
+    def coupled():
+        lat.density(dtype=torch.float32, out=rho)
+        lat.pseudopotential_force(g, rho, out=field)
+        lat.step(1)
+
+    def timed(fn, count):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        ws = []
+        for _ in range(repeats):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(count):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ws.append(e0.elapsed_time(e1) / 1e3 / count)
+        return statistics.median(ws)
+
+    t_step = timed(coupled, steps)
+    lat.density(dtype=torch.float32, out=rho)
+    t_force = timed(lambda: lat.pseudopotential_force(g, rho, out=field), 20)
+    red = lat.reduce(allow_unstable=True)
+    assert red[0, RED["nonfinite"]] == 0, "non-finite droplet state"
+    cells = n ** 3
+    gbs = 16.0 * cells / t_force / 1e9
+    out = {"workload": f"static_droplet_{n} (radius {n / 5:g}, G = -6, tau 2), fp32; per coupled step: density "
+                       "export, pseudo-potential force, fused step", "ms_per_coupled_step": round(t_step * 1e3, 4),
+           "glups_coupled": round(cells / t_step / 1e9, 3), "force_kernel": "k_pseudopotential<float>",
+           "force_us": round(t_force * 1e6, 1), "force_bytes_per_cell": 16, "force_hbm_gbs": round(gbs, 1),
+           "force_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    del lat, field, rho
+    torch.cuda.empty_cache()
+    return out
 
 
 def run_gpu_mhd(n, steps, warmup, repeats):
@@ -663,6 +723,12 @@ def main():
         extra["mhd_magnetic_lattice"] = {
             "workload": "D3Q7 vector populations (App. C), 256^3 periodic, fp32, fixed velocity field", **rmag}
         log(f"magnetic lattice {rmag['glups']:.2f} GLUPS")
+    if "shanchen" in legs:
+        mark("shanchen")
+        log("Shan-Chen droplet 256^3 fp32, coupled step")
+        extra["shan_chen"] = run_shan_chen(256, max(K // 4, 10), max(W // 4, 2), R)
+        log(f"Shan-Chen coupled step {extra['shan_chen']['ms_per_coupled_step']} ms, force kernel "
+            f"{extra['shan_chen']['force_hbm_gbs']} GB/s")
     if "copy" in legs:
         mark("copy")
         from paper_1905_10182_amd.cmlbm import device_copy

@@ -276,6 +276,16 @@ class Lattice:
         self._check(self.lib.cmlbm_moments(self.handle, _ptr(rho), _ptr(u), io, self._stream()), "moments")
         return rho, u
 
+    def density(self, dtype=None, out=None):
+        """rho(x, t) alone: the moment export without the velocity (into out if given)."""
+        dtype = dtype or self.torch.float64
+        io = FP64 if dtype == self.torch.float64 else FP32
+        if out is None:
+            out = self.torch.empty(self.shape, dtype=dtype, device=self.device)
+        assert out.dtype == dtype and out.is_contiguous() and tuple(out.shape) == self.shape
+        self._check(self.lib.cmlbm_moments(self.handle, _ptr(out), None, io, self._stream()), "moments")
+        return out
+
     def populations(self):
         out = self.torch.empty((27,) + self.shape, dtype=self.torch.float64, device=self.device)
         self._check(self.lib.cmlbm_populations(self.handle, _ptr(out), self._stream()), "populations")

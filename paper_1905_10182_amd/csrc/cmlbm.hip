@@ -1031,27 +1031,67 @@ __global__ __launch_bounds__(kBlock) void k_init_mom(float* __restrict__ dst, Ge
 // F(x) = -G psi(x) sum_i w_i c_i psi(x + c_i), psi = 1 - exp(-rho), periodic.
 // rho [N] and F [3][N] in the unpadded cell order of cmlbm_moments.
 
+// Tiles of 64 x 4 cells march up a chunk of kPsiZC planes.  psi = 1 - exp(-rho)
+// of each plane is computed once per tile and halo cell into a rolling window
+// of three planes in LDS (the plane below, the current one, the one above),
+// and every cell sums its 26 neighbours from there, in the velocity order.
+constexpr int kPsiTX = 64, kPsiTY = 4, kPsiZC = 16;
+constexpr int kPsiHX = kPsiTX + 2, kPsiHY = kPsiTY + 2, kPsiPlane = kPsiHX * kPsiHY;
+
+__device__ __forceinline__ int pmod(int v, int n) { return v < 0 ? v + n : (v < n ? v : v % n); }
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pseudopotential(Geom g, T G, const T* __restrict__ rho, T* __restrict__ F)
+__global__ __launch_bounds__(256) void k_pseudopotential(Geom g, T G, const T* __restrict__ rho, T* __restrict__ F)
 {
-    const Cell c = locate(g);
-    if (!c.valid) return;
-    T s[3] = {T(0), T(0), T(0)};
+    __shared__ T psi[3][kPsiPlane];
+    const int ntx = (g.nx + kPsiTX - 1) / kPsiTX, nty = (g.ny + kPsiTY - 1) / kPsiTY;
+    const int nzc = (g.nz + kPsiZC - 1) / kPsiZC;
+    int r = (int)blockIdx.x;
+    const int x0 = (r % ntx) * kPsiTX;
+    r /= ntx;
+    const int y0 = (r % nty) * kPsiTY;
+    r /= nty;
+    const int zs = (r % nzc) * kPsiZC, b = r / nzc;
+    const int ze = zs + kPsiZC < g.nz ? zs + kPsiZC : g.nz;
+    const int tid = (int)threadIdx.x, lx = tid & (kPsiTX - 1), ly = tid / kPsiTX;
     const uint64_t plane = (uint64_t)g.nx * g.ny;
-    const uint64_t base = (uint64_t)c.b * g.nz * plane;
+    const T* rb = rho + (uint64_t)b * g.nz * plane;
+    // psi of halo plane z (-1 <= z <= nz, periodic) into slot; halo positions
+    // past a partial tile's end read some in-range cell and are never used
+    auto load_plane = [&](int z, int slot) {
+        const T* rp = rb + (uint64_t)pmod(z, g.nz) * plane;
+        for (int k = tid; k < kPsiPlane; k += 256) {
+            const int hx = k % kPsiHX, hy = k / kPsiHX;
+            const int x = pmod(x0 + hx - 1, g.nx), y = pmod(y0 + hy - 1, g.ny);
+            psi[slot][k] = T(1) - exp(-rp[(uint64_t)y * g.nx + x]);
+        }
+    };
+    const int x = x0 + lx, y = y0 + ly;
+    const bool live = x < g.nx && y < g.ny;
+    load_plane(zs - 1, 0);
+    load_plane(zs, 1);
+    for (int z = zs; z < ze; ++z) {
+        // planes z - 1, z, z + 1 sit in slots q % 3, q = plane - (zs - 1)
+        const int q = z - zs;
+        load_plane(z + 1, (q + 2) % 3);
+        __syncthreads();
+        if (live) {
+            T s[3] = {T(0), T(0), T(0)};
 #pragma unroll
-    for (int i = 1; i < 27; ++i) {
-        const int x = wrap(c.x + vel_x(i), g.nx), y = wrap(c.y + vel_y(i), g.ny), z = wrap(c.z + vel_z(i), g.nz);
-        const T r = rho[base + (uint64_t)z * plane + (uint64_t)y * g.nx + x];
-        const T psi = T(1) - exp(-r);
-        const T w = T(weight(i));
-        s[0] += w * T(vel_x(i)) * psi;
-        s[1] += w * T(vel_y(i)) * psi;
-        s[2] += w * T(vel_z(i)) * psi;
+            for (int i = 1; i < 27; ++i) {
+                const T p = psi[(q + 1 + vel_z(i)) % 3][(ly + 1 + vel_y(i)) * kPsiHX + lx + 1 + vel_x(i)];
+                const T w = T(weight(i));
+                s[0] += w * T(vel_x(i)) * p;
+                s[1] += w * T(vel_y(i)) * p;
+                s[2] += w * T(vel_z(i)) * p;
+            }
+            const T psi0 = psi[(q + 1) % 3][(ly + 1) * kPsiHX + lx + 1];
+            const uint64_t lin = ((uint64_t)b * g.nz + z) * plane + (uint64_t)y * g.nx + x;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) F[a * g.ncell + lin] = -G * psi0 * s[a];
+        }
+        __syncthreads();  // the next plane overwrites the slot of plane z - 1
     }
-    const T psi0 = T(1) - exp(-rho[c.lin]);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) F[a * g.ncell + c.lin] = -G * psi0 * s[a];
 }
 
 // ---------------------------------------------------------------------------
@@ -2142,11 +2182,14 @@ int cmlbm_pseudopotential_force(cmlbm_lattice* lat, double G, const void* dev_rh
         return fail(lat, CMLBM_EINVAL, "pseudo-potential dtype must be FP64 for FP64 storage, FP32 otherwise");
     const Geom& g = lat->g;
     hipStream_t s = (hipStream_t)hip_stream;
+    const uint64_t tiles = (uint64_t)((g.nx + kPsiTX - 1) / kPsiTX) * ((g.ny + kPsiTY - 1) / kPsiTY) *
+                           ((g.nz + kPsiZC - 1) / kPsiZC) * g.nb;
+    if (tiles > 0x7fffffffULL) return fail(lat, CMLBM_EINVAL, "lattice too large for the pseudo-potential tiles");
     if (need == CMLBM_FP64)
-        k_pseudopotential<double><<<grid_of(g), block_of(g), 0, s>>>(g, G, (const double*)dev_rho, (double*)dev_field);
+        k_pseudopotential<double><<<(unsigned)tiles, 256, 0, s>>>(g, G, (const double*)dev_rho, (double*)dev_field);
     else
-        k_pseudopotential<float><<<grid_of(g), block_of(g), 0, s>>>(g, (float)G, (const float*)dev_rho,
-                                                                   (float*)dev_field);
+        k_pseudopotential<float><<<(unsigned)tiles, 256, 0, s>>>(g, (float)G, (const float*)dev_rho,
+                                                                (float*)dev_field);
     return launch_check(lat, "pseudo-potential force");
 }
 

@@ -407,8 +407,9 @@ def droplet_run(lat, wl, steps, out=sys.stdout, label="", every=lambda t: 10 if 
     lat.init(wl["rho"], wl["u"])
     n = float(np.prod(lat.shape))
     rows, t, nxt = [], 0, 0
+    rho = torch.empty(lat.shape, dtype=dt, device=lat.device)
     while True:
-        rho = lat.moments(dtype=dt)[0]
+        lat.density(dtype=dt, out=rho)
         lat.pseudopotential_force(wl["g"], rho, out=field)
         if t == nxt:
             r = lat.reduce(allow_unstable=True)[0]
