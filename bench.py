@@ -264,7 +264,9 @@ def run_shan_chen(n, radius, steps, warmup, repeats):
     the density from the moment export, the Shan-Chen force from it
     (k_pseudopotential), then the fused step with that force field; and the
     force kernel alone, whose algorithmic traffic is the density read once and
-    the three force components written, 16 B per cell."""
+    the three force components written, 16 B per cell; and the density export
+    alone (k_gather with no velocity: 27 FP32 populations read, the density
+    written, 112 B per cell)."""
     import torch
 
     import workloads
@@ -304,15 +306,19 @@ def run_shan_chen(n, radius, steps, warmup, repeats):
     t_step = timed(coupled, steps)
     lat.density(dtype=torch.float32, out=rho)
     t_force = timed(lambda: lat.pseudopotential_force(g, rho, out=field), 20)
+    t_dens = timed(lambda: lat.density(dtype=torch.float32, out=rho), 20)
     red = lat.reduce(allow_unstable=True)
     cells = n ** 3
     gbs = 16.0 * cells / t_force / 1e9
+    dgbs = 112.0 * cells / t_dens / 1e9
     out = {"workload": f"static_droplet_{n} (radius {radius:g}, G = -6, tau 2), fp32; per coupled step: density "
                        "export, pseudo-potential force, fused step", "steps_run": warmup + repeats * steps,
            "finite": bool(red[0, RED["nonfinite"]] == 0), "ms_per_coupled_step": round(t_step * 1e3, 4),
            "glups_coupled": round(cells / t_step / 1e9, 3), "force_kernel": "k_pseudopotential<float>",
            "force_us": round(t_force * 1e6, 1), "force_bytes_per_cell": 16, "force_hbm_gbs": round(gbs, 1),
-           "force_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+           "force_hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "density_kernel": "k_gather<1, false>",
+           "density_us": round(t_dens * 1e6, 1), "density_bytes_per_cell": 112,
+           "density_hbm_gbs": round(dgbs, 1), "density_hbm_frac": round(dgbs / HBM_PEAK_GBS, 4)}
     del lat, field, rho
     torch.cuda.empty_cache()
     return out

@@ -178,7 +178,9 @@ int cmlbm_init(cmlbm_lattice* lat, const void* dev_rho, const void* dev_u, int i
 int cmlbm_step(cmlbm_lattice* lat, int32_t nsteps, void* hip_stream);
 
 /* rho(x, t) into dev_rho[N] and u(x, t) = (sum f c + F/2)/rho into dev_u[3][N]
- * (either may be NULL), io_dtype CMLBM_FP64 or CMLBM_FP32. */
+ * (either may be NULL), io_dtype CMLBM_FP64 or CMLBM_FP32.  With dev_u NULL
+ * only the populations are read (the force enters the velocity alone); the
+ * density is the same bit for bit as with dev_u given. */
 int cmlbm_moments(cmlbm_lattice* lat, void* dev_rho, void* dev_u, int io_dtype, void* hip_stream);
 
 /* Shan-Chen pseudo-potential interaction force of the static-droplet test
@@ -188,7 +190,9 @@ int cmlbm_moments(cmlbm_lattice* lat, void* dev_rho, void* dev_u, int io_dtype, 
  * and FP32 otherwise, device pointers).  Periodic lattices without solids
  * only.  To drive a step with it, register dev_field once with
  * cmlbm_set_force(CMLBM_FORCE_FIELD) and refresh it from cmlbm_moments before
- * every cmlbm_step. */
+ * every cmlbm_step.  The first call picks the kernel's z chunk for the
+ * lattice's device (an occupancy query, no allocation); results do not
+ * depend on it. */
 int cmlbm_pseudopotential_force(cmlbm_lattice* lat, double G, const void* dev_rho, int io_dtype, void* dev_field,
                                 void* hip_stream);
 

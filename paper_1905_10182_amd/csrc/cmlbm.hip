@@ -1031,67 +1031,115 @@ __global__ __launch_bounds__(kBlock) void k_init_mom(float* __restrict__ dst, Ge
 // F(x) = -G psi(x) sum_i w_i c_i psi(x + c_i), psi = 1 - exp(-rho), periodic.
 // rho [N] and F [3][N] in the unpadded cell order of cmlbm_moments.
 
-// Tiles of 64 x 4 cells march up a chunk of kPsiZC planes.  psi = 1 - exp(-rho)
-// of each plane is computed once per tile and halo cell into a rolling window
-// of three planes in LDS (the plane below, the current one, the one above),
-// and every cell sums its 26 neighbours from there, in the velocity order.
-constexpr int kPsiTX = 64, kPsiTY = 4, kPsiZC = 16;
+// Tiles of 64 x 4 cells march up a chunk of zc planes.  psi = 1 - exp(-rho) of
+// each plane is computed once per tile and halo cell into a rolling window of
+// four plane slots in LDS, and every cell sums its 26 neighbours from there,
+// in the velocity order.  The density of the plane after next is loaded into
+// registers while the current plane is summed, so the global-memory latency
+// overlaps the arithmetic; with four slots one barrier per plane suffices
+// (the slot a plane overwrites was last read two planes earlier, before the
+// previous barrier).
+constexpr int kPsiTX = 64, kPsiTY = 4;
 constexpr int kPsiHX = kPsiTX + 2, kPsiHY = kPsiTY + 2, kPsiPlane = kPsiHX * kPsiHY;
+static_assert(kPsiPlane <= 512 && kPsiTX * kPsiTY == 256, "each of the 256 threads owns at most two halo cells");
 
 __device__ __forceinline__ int pmod(int v, int n) { return v < 0 ? v + n : (v < n ? v : v % n); }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_pseudopotential(Geom g, T G, const T* __restrict__ rho, T* __restrict__ F)
+__global__ __launch_bounds__(256) void k_pseudopotential(Geom g, T G, int zc, const T* __restrict__ rho,
+                                                         T* __restrict__ F)
 {
-    __shared__ T psi[3][kPsiPlane];
+    __shared__ T psi[4][kPsiPlane];
     const int ntx = (g.nx + kPsiTX - 1) / kPsiTX, nty = (g.ny + kPsiTY - 1) / kPsiTY;
-    const int nzc = (g.nz + kPsiZC - 1) / kPsiZC;
+    const int nzc = (g.nz + zc - 1) / zc;
     int r = (int)blockIdx.x;
     const int x0 = (r % ntx) * kPsiTX;
     r /= ntx;
     const int y0 = (r % nty) * kPsiTY;
     r /= nty;
-    const int zs = (r % nzc) * kPsiZC, b = r / nzc;
-    const int ze = zs + kPsiZC < g.nz ? zs + kPsiZC : g.nz;
+    const int zs = (r % nzc) * zc, b = r / nzc;
+    const int ze = zs + zc < g.nz ? zs + zc : g.nz;
     const int tid = (int)threadIdx.x, lx = tid & (kPsiTX - 1), ly = tid / kPsiTX;
     const uint64_t plane = (uint64_t)g.nx * g.ny;
     const T* rb = rho + (uint64_t)b * g.nz * plane;
-    // psi of halo plane z (-1 <= z <= nz, periodic) into slot; halo positions
-    // past a partial tile's end read some in-range cell and are never used
-    auto load_plane = [&](int z, int slot) {
-        const T* rp = rb + (uint64_t)pmod(z, g.nz) * plane;
-        for (int k = tid; k < kPsiPlane; k += 256) {
-            const int hx = k % kPsiHX, hy = k / kPsiHX;
-            const int x = pmod(x0 + hx - 1, g.nx), y = pmod(y0 + hy - 1, g.ny);
-            psi[slot][k] = T(1) - exp(-rp[(uint64_t)y * g.nx + x]);
-        }
+    // this thread's halo cells k0 = tid and k1 = tid + 256 (if inside the
+    // halo plane): their offsets within a plane are the same on every plane;
+    // halo positions past a partial tile's end read some in-range cell and
+    // are never used
+    const int k1 = tid + 256;
+    const bool has1 = k1 < kPsiPlane;
+    auto halo_off = [&](int k) {
+        const int hx = k % kPsiHX, hy = k / kPsiHX;
+        return (uint64_t)pmod(y0 + hy - 1, g.ny) * g.nx + (uint64_t)pmod(x0 + hx - 1, g.nx);
     };
+    const uint64_t o0 = halo_off(tid), o1 = has1 ? halo_off(k1) : 0;
+    auto fetch = [&](int z, T& v0, T& v1) {  // density of halo plane z (-1 <= z <= nz + 1, periodic)
+        const T* rp = rb + (uint64_t)pmod(z, g.nz) * plane;
+        v0 = rp[o0];
+        if (has1) v1 = rp[o1];
+    };
+    auto put = [&](int slot, T v0, T v1) {
+        psi[slot][tid] = T(1) - exp(-v0);
+        if (has1) psi[slot][k1] = T(1) - exp(-v1);
+    };
+    // plane z sits in slot (z - zs + 1) & 3; the first three planes are
+    // loaded together
+    T a0, a1 = T(0), b0, b1 = T(0), r0, r1 = T(0);
+    fetch(zs - 1, a0, a1);
+    fetch(zs, b0, b1);
+    fetch(zs + 1, r0, r1);
+    put(0, a0, a1);
+    put(1, b0, b1);
     const int x = x0 + lx, y = y0 + ly;
     const bool live = x < g.nx && y < g.ny;
-    load_plane(zs - 1, 0);
-    load_plane(zs, 1);
     for (int z = zs; z < ze; ++z) {
-        // planes z - 1, z, z + 1 sit in slots q % 3, q = plane - (zs - 1)
         const int q = z - zs;
-        load_plane(z + 1, (q + 2) % 3);
+        put((q + 2) & 3, r0, r1);  // plane z + 1, loaded during the previous plane
+        if (z + 1 < ze) fetch(z + 2, r0, r1);
         __syncthreads();
         if (live) {
             T s[3] = {T(0), T(0), T(0)};
 #pragma unroll
             for (int i = 1; i < 27; ++i) {
-                const T p = psi[(q + 1 + vel_z(i)) % 3][(ly + 1 + vel_y(i)) * kPsiHX + lx + 1 + vel_x(i)];
+                const T p = psi[(q + 1 + vel_z(i)) & 3][(ly + 1 + vel_y(i)) * kPsiHX + lx + 1 + vel_x(i)];
                 const T w = T(weight(i));
                 s[0] += w * T(vel_x(i)) * p;
                 s[1] += w * T(vel_y(i)) * p;
                 s[2] += w * T(vel_z(i)) * p;
             }
-            const T psi0 = psi[(q + 1) % 3][(ly + 1) * kPsiHX + lx + 1];
+            const T psi0 = psi[(q + 1) & 3][(ly + 1) * kPsiHX + lx + 1];
             const uint64_t lin = ((uint64_t)b * g.nz + z) * plane + (uint64_t)y * g.nx + x;
 #pragma unroll
             for (int a = 0; a < 3; ++a) F[a * g.ncell + lin] = -G * psi0 * s[a];
         }
-        __syncthreads();  // the next plane overwrites the slot of plane z - 1
     }
+}
+
+// z chunk of the pseudo-potential tiles: the fewest generations of resident
+// workgroups, each costing its chunk length plus the two halo planes; ties go
+// to the longer chunk (fewer halo planes read)
+template <typename T>
+int psi_chunk(const Geom& g, int cus)
+{
+    int per_cu = 0;
+    if (cus <= 0 ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pseudopotential<T>, 256, 0) != hipSuccess ||
+        per_cu <= 0)
+        return 16;
+    const uint64_t cap = (uint64_t)cus * (uint64_t)per_cu;
+    const uint64_t cols = (uint64_t)((g.nx + kPsiTX - 1) / kPsiTX) * (uint64_t)((g.ny + kPsiTY - 1) / kPsiTY) * g.nb;
+    const int top = g.nz < 64 ? g.nz : 64;
+    int best = top;
+    uint64_t best_cost = ~0ULL;
+    for (int zc = top; zc >= 1; --zc) {
+        const uint64_t blocks = cols * (uint64_t)((g.nz + zc - 1) / zc);
+        const uint64_t cost = ((blocks + cap - 1) / cap) * (uint64_t)(zc + 2);
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = zc;
+        }
+    }
+    return best;
 }
 
 // ---------------------------------------------------------------------------
@@ -1173,7 +1221,15 @@ __global__ __launch_bounds__(kBlock) void k_gather(const typename storage<ST>::S
             for (int i = 0; i < 27; ++i) pops_out[(uint64_t)i * g.ncell + c.lin] = fluid ? h[i] + weight(i) * rho0 : 0.0;
         }
         if (!rho_out && !u_out) return;
-        if (fluid) {
+        if (fluid && !u_out) {
+            // the density alone: the force enters only the velocity, so
+            // neither the force nor the divisions are needed (same sum order
+            // as macro64, hence the same density bit for bit)
+            double s = 0;
+#pragma unroll
+            for (int i = 0; i < 27; ++i) s += h[i];
+            rho = rho0 + s;
+        } else if (fluid) {
             double F[3], j[3], drho;
             cell_force64(g, c, ftab, field, field_f64, F);
             macro64(h, rho0, F, rho, u, j, drho);
@@ -1435,6 +1491,8 @@ struct cmlbm_lattice {
     int field_dtype;
     int64_t t;
     int cu_per_xcd;  // compute units per XCD of the lattice's device (the moment kernel's generation size)
+    int cus;         // compute units of the lattice's device (0 if unknown)
+    int psi_zc;      // z chunk of the pseudo-potential tiles (0 until the first launch)
     std::string err;
 };
 
@@ -2022,7 +2080,9 @@ int cmlbm_create(const cmlbm_params* params, void* pop_a, size_t pop_a_bytes, vo
         if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             cus = 0;
         lat->cu_per_xcd = cus % 8 == 0 ? cus / 8 : 0;
+        lat->cus = cus;
     }
+    lat->psi_zc = 0;  // chosen at the first pseudo-potential launch
     lat->field = nullptr;
     lat->field_dtype = CMLBM_FP64;
     lat->t = 0;
@@ -2182,13 +2242,17 @@ int cmlbm_pseudopotential_force(cmlbm_lattice* lat, double G, const void* dev_rh
         return fail(lat, CMLBM_EINVAL, "pseudo-potential dtype must be FP64 for FP64 storage, FP32 otherwise");
     const Geom& g = lat->g;
     hipStream_t s = (hipStream_t)hip_stream;
+    if (!lat->psi_zc)
+        lat->psi_zc = need == CMLBM_FP64 ? psi_chunk<double>(g, lat->cus) : psi_chunk<float>(g, lat->cus);
+    const int zc = lat->psi_zc;
     const uint64_t tiles = (uint64_t)((g.nx + kPsiTX - 1) / kPsiTX) * ((g.ny + kPsiTY - 1) / kPsiTY) *
-                           ((g.nz + kPsiZC - 1) / kPsiZC) * g.nb;
+                           ((g.nz + zc - 1) / zc) * g.nb;
     if (tiles > 0x7fffffffULL) return fail(lat, CMLBM_EINVAL, "lattice too large for the pseudo-potential tiles");
     if (need == CMLBM_FP64)
-        k_pseudopotential<double><<<(unsigned)tiles, 256, 0, s>>>(g, G, (const double*)dev_rho, (double*)dev_field);
+        k_pseudopotential<double><<<(unsigned)tiles, 256, 0, s>>>(g, G, zc, (const double*)dev_rho,
+                                                                 (double*)dev_field);
     else
-        k_pseudopotential<float><<<(unsigned)tiles, 256, 0, s>>>(g, (float)G, (const float*)dev_rho,
+        k_pseudopotential<float><<<(unsigned)tiles, 256, 0, s>>>(g, (float)G, zc, (const float*)dev_rho,
                                                                 (float*)dev_field);
     return launch_check(lat, "pseudo-potential force");
 }

@@ -400,7 +400,11 @@ def test_mom32_blocked_schedule_batch_field_force(torch):
 
 # (nbatch, nz, ny, nx): partial tiles in x and y within one z chunk; several x
 # tiles and z chunks with partial last ones; one-cell axes
-PSI_SHAPES = [(2, 9, 10, 11), (1, 37, 9, 130), (1, 1, 1, 1), (1, 17, 1, 3)]
+# (nb, nz, ny, nx).  The z chunk of the force tiles is chosen from the device's
+# resident workgroups: the small shapes run one plane per chunk, the last two
+# need more tiles than one generation holds, so their chunks march several
+# planes through the rolling LDS window (ragged x, y and last z chunk).
+PSI_SHAPES = [(2, 9, 10, 11), (1, 37, 9, 130), (1, 1, 1, 1), (1, 17, 1, 3), (2, 160, 99, 130), (1, 128, 128, 128)]
 
 
 @pytest.mark.parametrize("shape", PSI_SHAPES)
@@ -417,15 +421,32 @@ def test_pseudopotential_force_matches_oracle(torch, storage, tol, shape):
     assert err < tol
 
 
-@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "fp16"])
 def test_density_export_equals_moments(torch, storage):
-    """The density-only export (velocity pointer NULL) equals the density of the full moment export."""
-    lat = Lat(nx=37, ny=6, nz=5, tau=0.7, storage=storage)
+    """The density-only export (velocity pointer NULL) equals the density of
+    the full moment export bit for bit, with a per-cell force field (which
+    enters only the velocity), walls, solid nodes and a ragged batch of two;
+    and, in FP64, the oracle's density (eq. macroscopic)."""
+    shape = (2, 5, 6, 37)
     g = W.generator(79)
-    lat.init(1.0 + 1e-2 * g.uniform(-1, 1, lat.shape), 0.05 * g.uniform(-1, 1, (3,) + lat.shape))
+    solid = (g.uniform(size=shape) < 0.08).astype(np.uint8)
+    force = g.uniform(-1e-3, 1e-3, size=(3,) + shape)
+    f0 = W.random_populations(shape, seed=80)
+    f0[:, solid.astype(bool)] = 0.0
+    lat = Lat(nx=37, ny=6, nz=5, nbatch=2, tau=0.7, storage=storage, wall=(0, 1, 1), solid=True)
+    lat.set_solid(solid)
+    lat.set_force("field", field=force)
+    lat.load_populations(f0)
     lat.step(3)
     dt = torch.float64 if storage == "fp64" else torch.float32
-    assert torch.equal(lat.density(dtype=dt), lat.moments(dtype=dt)[0])
+    rho = lat.density(dtype=dt)
+    assert torch.equal(rho, lat.moments(dtype=dt)[0])
+    if storage == "fp64":
+        ref = O.Lattice(37, 6, 5, nb=2, tau=0.7, wall=(0, 1, 1), solid=solid, force=force, extended=True)
+        ref.load_populations(f0)
+        ref.step(3)
+        m = ~solid.astype(bool)
+        assert rel(rho.cpu().numpy()[m], ref.moments()[0][m]) < 1e-14
     lat.close()
 
 
