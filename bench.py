@@ -477,31 +477,31 @@ def run_conv(steps, warmup, repeats):
 
 def plane_copy_rate(n=256, repeats=5, launches=20):
     """The FP32 step's memory traffic without its arithmetic on the headline
-    lattice's layout (27 planes of n^3 cells, the library's plane stride):
-    median of `repeats` windows of `launches` plane copies."""
+    lattice's layout (n^2 lattice rows, each a block of 27 population rows of
+    n cells): median of `repeats` windows of `launches` row-block copies."""
     import torch
     from paper_1905_10182_amd import cmlbm
-    assert (4 * n) % 256 == 0  # rows are whole 256-byte lines, so the plane is n^3 values
+    assert (4 * n) % 256 == 0  # rows are whole 256-byte lines, so a population row is n values
     cells = n ** 3
-    stride = cells + 1024  # planes 4 KiB apart beyond their rows, as the library lays them out
-    a = torch.zeros(27 * stride, dtype=torch.float32, device="cuda:0")
+    a = torch.zeros(27 * cells, dtype=torch.float32, device="cuda:0")
     b = torch.zeros_like(a)
     for _ in range(3):
-        cmlbm.plane_copy(b, a, 27, cells, stride)
+        cmlbm.row_block_copy(b, a, n * n, n)
     torch.cuda.synchronize()
     ts = []
     for _ in range(repeats):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(launches):
-            cmlbm.plane_copy(b, a, 27, cells, stride)
+            cmlbm.row_block_copy(b, a, n * n, n)
         e1.record()
         torch.cuda.synchronize()
         ts.append(e0.elapsed_time(e1) / launches)
     ms = statistics.median(ts)
     del a, b
     torch.cuda.empty_cache()
-    return {"workload": f"27 FP32 planes of {n}^3 cells in, 27 out, one cell per lane, no arithmetic",
+    return {"workload": f"{n}^3 FP32 cells, 27 population rows per lattice row in, 27 out, one cell per lane, "
+                        "no arithmetic",
             "ms_per_launch": round(ms, 5), "gbs": round(2 * 27 * 4 * cells / (ms * 1e-3) / 1e9, 1)}
 
 

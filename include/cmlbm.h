@@ -137,10 +137,13 @@ typedef struct {
 
 /* Bytes the caller must provide for each of the two population buffers and for
  * the scratch buffer.  Pure host computation.  EINVAL on invalid params,
- * including a population plane (one population over all cells, rows padded to
- * 256 bytes, planes 4 KiB apart beyond that) of 4 GiB or more: the kernels
- * address within a plane with 32-bit byte offsets (FP32 up to ~1.07e9 cells,
- * 16-bit up to ~2.1e9 cells). */
+ * including one population over all cells (rows padded to 256 bytes, plus
+ * 4 KiB) of 4 GiB or more: the link mask and the moment planes are addressed
+ * with 32-bit offsets (FP32 up to ~1.07e9 cells, 16-bit up to ~2.1e9 cells).
+ * Layout of a buffer: rows of nx values padded to 256 bytes, rows ordered
+ * [nbatch][nz][ny]; population storage keeps the 27 population rows of one
+ * lattice row together ([nbatch][nz][ny][27][row]), moment storage (nine
+ * FP32 numbers per cell) keeps nine planes 4 KiB apart beyond their rows. */
 int cmlbm_required_bytes(const cmlbm_params* params, size_t* pop_buffer_bytes, size_t* scratch_bytes);
 
 /* Create a handle over caller-allocated device buffers (borrowed; each must be
@@ -273,6 +276,17 @@ int cmlbm_device_copy(void* dev_dst, const void* dev_src, size_t bytes, void* hi
  * nothing is enqueued then. */
 int cmlbm_plane_copy(void* dev_dst, const void* dev_src, int32_t planes, int64_t cells, int64_t plane_stride,
                      void* hip_stream);
+
+/* Measurement aid, not part of the method: the FP32 population step's memory
+ * traffic in its row-block layout, without the arithmetic.  For every lattice
+ * row r < rows, population p < 27 and cell x < row_len, the FP32 element at
+ * (r * 27 + p) * row_len + x is copied from dev_src to dev_dst (both device
+ * pointers 4-byte aligned, the two spans of rows * 27 * row_len elements not
+ * overlapping), one cell per lane in 1024-thread workgroups: each lane loads
+ * its 27 values, then stores them non-temporally.  EINVAL on NULL or
+ * misaligned pointers, rows < 1, row_len < 1, spans of 2^40 bytes or more,
+ * or overlapping spans; nothing is enqueued then. */
+int cmlbm_row_block_copy(void* dev_dst, const void* dev_src, int64_t rows, int32_t row_len, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -36,7 +36,8 @@ EXPORTS = ["cmlbm_required_bytes", "cmlbm_create", "cmlbm_set_solid", "cmlbm_set
            "cmlbm_step", "cmlbm_moments", "cmlbm_reduce", "cmlbm_step_reduce", "cmlbm_populations",
            "cmlbm_load_populations",
            "cmlbm_save_state", "cmlbm_restore_state", "cmlbm_get_time", "cmlbm_set_time", "cmlbm_destroy",
-           "cmlbm_last_error", "cmlbm_status_string", "cmlbm_pseudopotential_force", "cmlbm_device_copy", "cmlbm_plane_copy"]
+           "cmlbm_last_error", "cmlbm_status_string", "cmlbm_pseudopotential_force", "cmlbm_device_copy", "cmlbm_plane_copy",
+           "cmlbm_row_block_copy"]
 
 
 class Params(ctypes.Structure):
@@ -85,6 +86,7 @@ def load_library():
     lib.cmlbm_last_error.restype = ctypes.c_char_p
     lib.cmlbm_device_copy.argtypes = [vp, vp, sz, vp]
     lib.cmlbm_plane_copy.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, vp]
+    lib.cmlbm_row_block_copy.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, vp]
     lib.cmlbm_status_string.argtypes = [ctypes.c_int]
     lib.cmlbm_status_string.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -128,6 +130,23 @@ def plane_copy(dst, src, planes, cells, plane_stride, stream=None):
                                          cells, plane_stride, ctypes.c_void_p(s))
     if rc != OK:
         raise CmlbmError(rc, "plane_copy")
+
+
+def row_block_copy(dst, src, rows, row_len, stream=None):
+    """Copy rows * 27 * row_len FP32 values laid out as row blocks
+    (population p of cell x in row r at (r * 27 + p) * row_len + x), one cell
+    per lane, with the library's row-block copy kernel: the FP32 population
+    step's access pattern without its arithmetic (a bandwidth measurement
+    aid)."""
+    import torch
+    span = rows * 27 * row_len
+    assert src.dtype == torch.float32 and dst.dtype == torch.float32
+    assert src.numel() >= span and dst.numel() >= span
+    s = torch.cuda.current_stream().cuda_stream if stream is None else stream
+    rc = load_library().cmlbm_row_block_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), rows,
+                                             row_len, ctypes.c_void_p(s))
+    if rc != OK:
+        raise CmlbmError(rc, "row_block_copy")
 
 
 def make_params(nx, ny, nz, nbatch=1, tau=0.8, rho0=1.0, storage="fp32", wall=(0, 0, 0), flags=0):

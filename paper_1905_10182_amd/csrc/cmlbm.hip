@@ -12,10 +12,12 @@
 //   k_linkmask   per-cell 27-bit bounce-back mask from walls and solid nodes
 //   k_fill       plain fill (used instead of memset so work stays in kernels)
 //
-// Memory layout in HBM (structure of arrays): population plane i holds one
-// value per cell, rows of nxp elements (nx rounded up to 256 bytes), cells
-// ordered [nbatch][nz][ny][nxp], consecutive planes kPlanePad bytes apart
-// beyond their rows; two such buffers alternate between steps.
+// Memory layout in HBM: every population is stored in rows of nxp elements
+// (nx rounded up to 256 bytes), one value per cell, rows ordered
+// [nbatch][nz][ny].  Population storage keeps the 27 population rows of one
+// lattice row together (row blocks, [nbatch][nz][ny][27][nxp]); moment
+// storage keeps planes ([9][nbatch][nz][ny][nxp], planes kPlanePad bytes
+// apart beyond their rows).  Two such buffers alternate between steps.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -184,14 +186,16 @@ struct Geom {
     int rows;          // ny * nz * nb
     int xblocks;       // workgroups along x per row group
     int bx, by;        // workgroup shape: bx threads along x (multiple of 64), by rows
-    uint64_t pstride;  // elements per population plane
+    uint64_t pstride;  // elements from population i to i + 1 of one row
+    uint64_t rstride;  // elements from one row of a population to the next row
     uint64_t ncell;    // nb * nz * ny * nx (unpadded)
 };
 
 struct Cell {
     int x, y, z, b;
     bool valid;
-    uint32_t own;     // padded index within a plane
+    uint32_t own;     // padded index within a plane (the link mask's index)
+    uint64_t pown;    // index of the cell's population 0 (population i at + i * pstride)
     uint64_t lin;     // unpadded linear index
 };
 
@@ -213,16 +217,17 @@ __device__ __forceinline__ Cell locate(const Geom& g)
     c.z = zb % g.nz;
     c.b = zb / g.nz;
     c.own = (uint32_t)row * (uint32_t)g.nxp + (uint32_t)c.x;
+    c.pown = (uint64_t)row * g.rstride + (uint64_t)c.x;
     c.lin = (uint64_t)row * (uint64_t)g.nx + (uint64_t)c.x;
     return c;
 }
 
 __device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
-// Source offsets (within a population plane) of the pull gather for the 27
+// Source offsets (relative to population 0) of the pull gather for the 27
 // directions: direction i reads cell x - c_i with periodic wrap.
 struct Pull {
-    uint32_t rowoff[3][3];  // [cy+1][cz+1] offset of the source row (wave-uniform)
+    uint64_t rowoff[3][3];  // [cy+1][cz+1] offset of the source row (wave-uniform)
     uint32_t xs[3];         // [cx+1] source x
 };
 
@@ -235,7 +240,7 @@ __device__ __forceinline__ Pull make_pull(const Geom& g, const Cell& c)
         for (int d = 0; d < 3; ++d) {
             const int ys = wrap(c.y - (b - 1), g.ny);
             const int zs = wrap(c.z - (d - 1), g.nz);
-            p.rowoff[b][d] = (uint32_t)(((c.b * g.nz + zs) * g.ny + ys) * g.nxp);
+            p.rowoff[b][d] = (uint64_t)((c.b * g.nz + zs) * g.ny + ys) * g.rstride;
         }
 #pragma unroll
     for (int a = 0; a < 3; ++a) p.xs[a] = (uint32_t)wrap(c.x - (a - 1), g.nx);
@@ -296,10 +301,10 @@ __device__ __forceinline__ void gather(const typename storage<ST>::S* __restrict
     const Pull p = make_pull(g, c);
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
-        const uint32_t off = p.rowoff[vel_y(i) + 1][vel_z(i) + 1] + p.xs[vel_x(i) + 1];
+        const uint64_t off = p.rowoff[vel_y(i) + 1][vel_z(i) + 1] + p.xs[vel_x(i) + 1];
         if (MASK) {
             const bool bounce = (m >> i) & 1u;
-            const uint64_t e = bounce ? (uint64_t)opposite(i) * g.pstride + c.own : (uint64_t)i * g.pstride + off;
+            const uint64_t e = bounce ? (uint64_t)opposite(i) * g.pstride + c.pown : (uint64_t)i * g.pstride + off;
             h[i] = SS::load(src + e);
         } else {
             // wave-uniform source row plus a 32-bit per-lane byte offset (the
@@ -462,9 +467,10 @@ __global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename st
         for (int d = 0; d < 3; ++d) {
             const int ys = wrap(y - (bb - 1), g.ny);
             const int zs = wrap(z - (d - 1), g.nz);
-            srow[bb][d] = src + (uint64_t)(((b * g.nz + zs) * g.ny + ys) * g.nxp);
+            srow[bb][d] = src + (uint64_t)((b * g.nz + zs) * g.ny + ys) * g.rstride;
         }
-    const uint32_t own_row = (uint32_t)row * (uint32_t)g.nxp;
+    const uint32_t own_row = (uint32_t)row * (uint32_t)g.nxp;  // the link mask's row
+    const uint64_t pop_row = (uint64_t)row * g.rstride;       // population 0 of this row
     T h[V][27];
     bool live = active;  // this lane holds fluid cells (RED: a lane without one stays for the wave sum)
     if constexpr (V == 1) {
@@ -482,7 +488,7 @@ __global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename st
             const S* plane_row = srow[vel_y(i) + 1][vel_z(i) + 1] + (uint64_t)i * g.pstride;
             S e;
             if (MASK && ((m >> i) & 1u))
-                e = ld_off<S>(src + (uint64_t)opposite(i) * g.pstride + own_row, bx[1]);
+                e = ld_off<S>(src + (uint64_t)opposite(i) * g.pstride + pop_row, bx[1]);
             else
                 e = ld_off<S>(plane_row, bx[vel_x(i) + 1]);
             h[0][i] = SS::load_raw(&e);
@@ -597,7 +603,7 @@ __global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename st
                     sr_words<V>((uint32_t)((uint64_t)row * (uint64_t)g.nx + (uint64_t)x0), step, rw);
 #pragma unroll
                     for (int i = 0; i < 27; ++i) {
-                        gchar* plane_row = uniform_ptr(dst + (uint64_t)i * g.pstride + own_row);
+                        gchar* plane_row = uniform_ptr(dst + (uint64_t)i * g.pstride + pop_row);
                         if constexpr (V == 1)
                             st_off<NT>(plane_row, bst, SS::pack_sr_raw(h[0][i], sr_operand(rw[0], i)));
                         else
@@ -609,7 +615,7 @@ __global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename st
             }
 #pragma unroll
             for (int i = 0; i < 27; ++i) {
-                gchar* plane_row = uniform_ptr(dst + (uint64_t)i * g.pstride + own_row);
+                gchar* plane_row = uniform_ptr(dst + (uint64_t)i * g.pstride + pop_row);
                 if constexpr (V == 1) {
                     st_off<NT>(plane_row, bst, SS::pack_raw(h[0][i]));
                 } else {
@@ -666,7 +672,7 @@ __global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename st
             sr_words<V>((uint32_t)((uint64_t)row * (uint64_t)g.nx + (uint64_t)x0), step, rw);
 #pragma unroll
             for (int i = 0; i < 27; ++i) {
-                gchar* plane_row = uniform_ptr(dst + (uint64_t)i * g.pstride + own_row);
+                gchar* plane_row = uniform_ptr(dst + (uint64_t)i * g.pstride + pop_row);
                 if constexpr (V == 1)
                     st_off<NT>(plane_row, bst, SS::pack_sr_raw(h[0][i], sr_operand(rw[0], i)));
                 else
@@ -678,7 +684,7 @@ __global__ __launch_bounds__(step_block(ST, MASK)) void k_step(const typename st
     }
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
-        gchar* plane_row = uniform_ptr(dst + (uint64_t)i * g.pstride + own_row);
+        gchar* plane_row = uniform_ptr(dst + (uint64_t)i * g.pstride + pop_row);
         if constexpr (V == 1) {
             st_off<NT>(plane_row, bst, SS::pack_raw(h[0][i]));
         } else {
@@ -758,9 +764,9 @@ __global__ __launch_bounds__(kBlock) void k_init(typename storage<ST>::S* __rest
     const Pull p = make_pull(g, c);
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
-        const uint32_t off = p.rowoff[vel_y(i) + 1][vel_z(i) + 1] + p.xs[vel_x(i) + 1];
+        const uint64_t off = p.rowoff[vel_y(i) + 1][vel_z(i) + 1] + p.xs[vel_x(i) + 1];
         const bool bounce = MASK && ((m >> i) & 1u);
-        const uint64_t d = bounce ? (uint64_t)opposite(i) * g.pstride + c.own : (uint64_t)i * g.pstride + off;
+        const uint64_t d = bounce ? (uint64_t)opposite(i) * g.pstride + c.pown : (uint64_t)i * g.pstride + off;
         dst[d] = SS::pack(e[i]);
     }
 }
@@ -1023,7 +1029,7 @@ __global__ __launch_bounds__(kBlock) void k_init_mom(float* __restrict__ dst, Ge
         mom_force<false>(g, c.lin, c.b, c.y, ftab, field, F);
     float drho, ux, uy, uz, k[5];
     pre_collision<float>(e, F[0], F[1], F[2], rho0, drho, ux, uy, uz, k);
-    mom_store(dst, g.pstride, c.own, drho, ux, uy, uz, k, 1.f - omega);
+    mom_store(dst, g.pstride, c.pown, drho, ux, uy, uz, k, 1.f - omega);
 }
 
 // ---------------------------------------------------------------------------
@@ -1211,8 +1217,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(const typename storage<ST>::S
     double rho = rho0, u[3] = {0, 0, 0};
     if constexpr (ST == CMLBM_MOM32) {
         // the stored numbers of the post-collision state are its density and velocity
-        rho = rho0 + (double)src[c.own];
-        for (int a = 0; a < 3; ++a) u[a] = (double)src[(1 + a) * g.pstride + c.own];
+        rho = rho0 + (double)src[c.pown];
+        for (int a = 0; a < 3; ++a) u[a] = (double)src[(1 + a) * g.pstride + c.pown];
     } else {
         double h[27];
         const bool fluid = gather_f64<ST, MASK>(src, g, c, mask, h);
@@ -1280,15 +1286,16 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const typename storage<ST>::S
         c.b = b;
         const int row = b * rows + r;
         c.own = (uint32_t)row * (uint32_t)g.nxp + (uint32_t)x;
+        c.pown = (uint64_t)row * g.rstride + (uint64_t)x;
         c.lin = (uint64_t)row * g.nx + x;
         c.valid = true;
         double F[3], rho, u[3], j[3], drho;
         if constexpr (ST == CMLBM_MOM32) {
             cell_force64(g, c, ftab, field, field_f64, F);
-            drho = (double)src[c.own];
+            drho = (double)src[c.pown];
             rho = rho0 + drho;
             for (int a = 0; a < 3; ++a) {
-                u[a] = (double)src[(1 + a) * g.pstride + c.own];
+                u[a] = (double)src[(1 + a) * g.pstride + c.pown];
                 j[a] = rho * u[a] - 0.5 * F[a];  // sum_i f_i c_i
             }
         } else {
@@ -1466,6 +1473,21 @@ __global__ __launch_bounds__(1024) void k_copy_planes(const float* __restrict__ 
     for (int p = 0; p < NP; ++p) __builtin_nontemporal_store(v[p], dst + p * pstride + c);
 }
 
+// The same for the row-block layout of the population step: population p of
+// cell x in lattice row r at (r * 27 + p) * row_len + x.
+__global__ __launch_bounds__(1024) void k_copy_row_blocks(const float* __restrict__ src, float* __restrict__ dst,
+                                                          uint64_t cells, uint32_t row_len)
+{
+    const uint64_t c = (uint64_t)blockIdx.x * 1024 + threadIdx.x;
+    if (c >= cells) return;
+    const uint64_t base = c / row_len * 27 * row_len + c % row_len;
+    float v[27];
+#pragma unroll
+    for (int p = 0; p < 27; ++p) v[p] = src[base + (uint64_t)p * row_len];
+#pragma unroll
+    for (int p = 0; p < 27; ++p) __builtin_nontemporal_store(v[p], dst + base + (uint64_t)p * row_len);
+}
+
 __global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v)
 {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
@@ -1546,6 +1568,12 @@ int validate(const cmlbm_params* p)
     return CMLBM_OK;
 }
 
+// Population layout.  Planes: population i of every row together, planes
+// kPlanePad bytes apart.  Row blocks: the 27 population rows of one lattice
+// row stored together, rows one after another, so that a wave's 27 stores go
+// to one contiguous block and its loads to nine.  Moment storage uses planes.
+bool row_blocks(int storage) { return storage != CMLBM_MOM32; }
+
 int make_layout(const cmlbm_params* p, Layout* L)
 {
     int rc = validate(p);
@@ -1563,8 +1591,11 @@ int make_layout(const cmlbm_params* p, Layout* L)
     g.rows = (int)rows;
     // planes are kPlanePad bytes apart beyond their rows: at power-of-two plane sizes the 27
     // concurrent plane streams would otherwise map onto the same HBM channels
-    g.pstride = rows * (uint64_t)g.nxp + kPlanePad / sb;
-    if (g.pstride * sb >= (1ULL << 32)) return CMLBM_EINVAL;  // per-plane byte offsets are 32-bit
+    const uint64_t plane = rows * (uint64_t)g.nxp + kPlanePad / sb;
+    if (plane * sb >= (1ULL << 32)) return CMLBM_EINVAL;  // per-plane (and link-mask) offsets are 32-bit
+    const bool blocks = row_blocks(p->storage);
+    g.pstride = blocks ? (uint64_t)g.nxp : plane;
+    g.rstride = blocks ? 27ull * g.nxp : (uint64_t)g.nxp;
     g.ncell = rows * (uint64_t)p->nx;
     const int nx64 = (p->nx + 63) / 64 * 64;
     g.bx = nx64 < kBlock ? nx64 : kBlock;
@@ -1577,7 +1608,7 @@ int make_layout(const cmlbm_params* p, Layout* L)
         if (tiles * 9 * 64 > 0xffffffffULL) return CMLBM_EINVAL;
     }
 
-    L->pop_bytes = align256((uint64_t)planes_of(p->storage) * g.pstride * sb);
+    L->pop_bytes = align256(blocks ? rows * g.rstride * sb : (uint64_t)planes_of(p->storage) * plane * sb);
     L->needs_mask = (p->flags & CMLBM_FLAG_SOLID) || p->wall[0] || p->wall[1] || p->wall[2];
     const uint64_t per = (uint64_t)p->nz * p->ny * p->nx;
     uint64_t gpb = (per + kBlock - 1) / kBlock;
@@ -1590,7 +1621,7 @@ int make_layout(const cmlbm_params* p, Layout* L)
     L->off_ftab32 = off;
     off = align256(off + (size_t)p->nbatch * p->ny * 3 * sizeof(float));
     L->off_mask = off;
-    if (L->needs_mask) off = align256(off + g.pstride * sizeof(uint32_t));
+    if (L->needs_mask) off = align256(off + plane * sizeof(uint32_t));
     L->off_part = off;
     off = align256(off + (size_t)p->nbatch * gpb * kNPart * sizeof(double));
     L->off_final = off;
@@ -1631,7 +1662,7 @@ int build_mask(cmlbm_lattice* lat, const uint8_t* solid, hipStream_t s)
 {
     const Geom& g = lat->g;
     uint32_t* m = mask_ptr(lat);
-    k_fill_u32<<<1024, 256, 0, s>>>(m, g.pstride, kSolidBit);  // padding columns count as solid
+    k_fill_u32<<<1024, 256, 0, s>>>(m, (uint64_t)g.rows * g.nxp, kSolidBit);  // padding columns count as solid
     int rc = launch_check(lat, "link mask clear");
     if (rc) return rc;
     k_linkmask<<<grid_of(g), block_of(g), 0, s>>>(g, lat->p.wall[0], lat->p.wall[1], lat->p.wall[2], solid, m);
@@ -2388,6 +2419,22 @@ int cmlbm_plane_copy(void* dev_dst, const void* dev_src, int32_t planes, int64_t
     else
         k_copy_planes<9><<<dim3((unsigned)blocks), dim3(1024), 0, s>>>((const float*)dev_src, (float*)dev_dst,
                                                                       (uint64_t)cells, (uint64_t)plane_stride);
+    return hipGetLastError() == hipSuccess ? CMLBM_OK : CMLBM_EHIP;
+}
+
+int cmlbm_row_block_copy(void* dev_dst, const void* dev_src, int64_t rows, int32_t row_len, void* hip_stream)
+{
+    if (!dev_dst || !dev_src || rows < 1 || row_len < 1 || ((uintptr_t)dev_dst | (uintptr_t)dev_src) % 4)
+        return CMLBM_EINVAL;
+    if ((uint64_t)rows >= (1ULL << 40) / (27ULL * 4ULL * (uint64_t)row_len)) return CMLBM_EINVAL;  // 2^40-byte spans
+    const uint64_t cells = (uint64_t)rows * (uint64_t)row_len;
+    const uint64_t span = cells * 27 * 4;
+    const char *d = (const char*)dev_dst, *sp = (const char*)dev_src;
+    if (d < sp + span && sp < d + span) return CMLBM_EINVAL;  // overlapping
+    const uint64_t blocks = (cells + 1023) / 1024;
+    if (blocks > 0x7fffffffULL) return CMLBM_EINVAL;
+    k_copy_row_blocks<<<dim3((unsigned)blocks), dim3(1024), 0, (hipStream_t)hip_stream>>>(
+        (const float*)dev_src, (float*)dev_dst, cells, (uint32_t)row_len);
     return hipGetLastError() == hipSuccess ? CMLBM_OK : CMLBM_EHIP;
 }
 

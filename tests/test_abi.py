@@ -46,19 +46,21 @@ def req(**kw):
     return B.make_params(**base)
 
 
-PLANE_PAD = 4096  # bytes between consecutive population planes
+PLANE_PAD = 4096  # bytes between consecutive moment planes
 
 
 def test_required_bytes_padding():
-    # rows padded to 256 bytes; 27 planes of rows * padded row length, planes 4 KiB apart
+    # rows padded to 256 bytes; population storage: one block of 27 population rows per lattice row
     pop, scratch = B.required_bytes(req(nx=32, storage="fp32"))
-    assert pop == 27 * (16 * 16 * 64 * 4 + PLANE_PAD)
+    assert pop == 16 * 16 * 27 * 64 * 4
     pop, _ = B.required_bytes(req(nx=256, ny=256, nz=256, storage="fp32"))
-    assert pop == 27 * (256 ** 3 * 4 + PLANE_PAD)
+    assert pop == 27 * 256 ** 3 * 4
     pop, _ = B.required_bytes(req(nx=512, ny=512, nz=512, storage="fp16"))
-    assert pop == 27 * (512 ** 3 * 2 + PLANE_PAD)
+    assert pop == 27 * 512 ** 3 * 2
     pop, _ = B.required_bytes(req(nx=37, ny=13, nz=11, nbatch=2, storage="fp64"))
-    assert pop == 27 * (13 * 11 * 2 * 64 * 8 + PLANE_PAD)
+    assert pop == 13 * 11 * 2 * 27 * 64 * 8
+    pop, _ = B.required_bytes(req(nx=3, ny=5, nz=7, storage="bf16"))
+    assert pop == -(-(5 * 7 * 27 * 128 * 2) // 256) * 256
     # a mask (walls/solid) and the residual snapshot enlarge the scratch
     _, s0 = B.required_bytes(req())
     _, s1 = B.required_bytes(req(wall=(0, 1, 0)))
@@ -68,11 +70,12 @@ def test_required_bytes_padding():
 
 
 def test_plane_size_limit():
-    # per-plane byte offsets are 32-bit: 1024^3 FP32 planes (4 GiB) are refused, FP16 ones accepted
+    # one population's values (and the link mask) are indexed with 32-bit byte offsets: 1024^3 FP32
+    # (4 GiB per population) is refused, FP16 accepted
     with pytest.raises(B.CmlbmError):
         B.required_bytes(req(nx=1024, ny=1024, nz=1024, storage="fp32"))
     pop, _ = B.required_bytes(req(nx=1024, ny=1024, nz=1024, storage="fp16"))
-    assert pop == 27 * (1024 ** 3 * 2 + PLANE_PAD)
+    assert pop == 27 * 1024 ** 3 * 2
 
 
 @pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=0.3), dict(tau=float("nan")), dict(nx=0), dict(ny=-1),
@@ -145,7 +148,7 @@ def test_moment_storage_bytes():
     pop, _ = B.required_bytes(req(nx=64, ny=8, nz=8, storage="mom32"))
     assert pop == 9 * (8 * 8 * 64 * 4 + PLANE_PAD)
     pop32, _ = B.required_bytes(req(nx=64, ny=8, nz=8, storage="fp32"))
-    assert pop32 == 3 * pop
+    assert pop32 == 27 * 8 * 8 * 64 * 4
     B.required_bytes(req(storage="mom32", flags=B.FLAG_RESIDUAL))  # residual snapshots are allowed
 
 
@@ -189,3 +192,17 @@ def test_plane_copy_validation(lib):
     assert lib.cmlbm_plane_copy(P(far), P(0x1000), 27, 64, 63, None) == B.EINVAL    # stride below the cells
     assert lib.cmlbm_plane_copy(P(far + 2), P(0x1000), 27, 64, 64, None) == B.EINVAL  # misaligned
     assert lib.cmlbm_plane_copy(P(0x1000 + 256), P(0x1000), 9, 64, 64, None) == B.EINVAL  # overlapping
+
+
+def test_row_block_copy_validation(lib):
+    """Argument checks of the row-block copy, all before any GPU call."""
+    P = ctypes.c_void_p
+    lib.cmlbm_row_block_copy.argtypes = [P, P, ctypes.c_int64, ctypes.c_int32, P]
+    far = 1 << 44
+    assert lib.cmlbm_row_block_copy(None, P(0x1000), 4, 64, None) == B.EINVAL
+    assert lib.cmlbm_row_block_copy(P(far), None, 4, 64, None) == B.EINVAL
+    assert lib.cmlbm_row_block_copy(P(far), P(0x1000), 0, 64, None) == B.EINVAL      # no rows
+    assert lib.cmlbm_row_block_copy(P(far), P(0x1000), 4, 0, None) == B.EINVAL       # empty rows
+    assert lib.cmlbm_row_block_copy(P(far + 2), P(0x1000), 4, 64, None) == B.EINVAL  # misaligned
+    assert lib.cmlbm_row_block_copy(P(0x1000 + 27 * 64 * 4 * 4 - 4), P(0x1000), 4, 64, None) == B.EINVAL  # overlap
+    assert lib.cmlbm_row_block_copy(P(far), P(0x1000), (1 << 40) // (27 * 4 * 64), 64, None) == B.EINVAL  # 2^40 B

@@ -764,9 +764,9 @@ SB = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}
 
 def raw_populations(torch, lat, buf, cells, pre=True):
     """Populations at cells (n, 3: x, y, z) read directly from one of the
-    lattice's two device buffers: 27 planes of (nbatch * nz * ny) rows of nx
-    cells padded to 256 bytes, planes a further 4 KiB apart, each value stored
-    as h = f - w rho0 (FP16: 256 h).  A step stores each cell's post-collision
+    lattice's two device buffers: (nbatch * nz * ny) row blocks, each the 27
+    population rows of one lattice row, nx cells padded to 256 bytes, each
+    value stored as h = f - w rho0 (FP16: 256 h).  A step stores each cell's post-collision
     populations at the cell itself and the next step pulls them, so the
     pre-collision f_i(x) of the state (pre=True) sits at x - c_i, and the
     post-collision values of the step that wrote the buffer (pre=False) at x.
@@ -775,14 +775,13 @@ def raw_populations(torch, lat, buf, cells, pre=True):
     sb = SB[storage]
     _, nz, ny, nx = lat.shape
     nxp = -(-nx * sb // 256) * 256 // sb
-    pstride = nz * ny * nxp + 4096 // sb
     view = buf.view({"fp64": torch.float64, "fp32": torch.float32, "fp16": torch.float16,
                      "bf16": torch.bfloat16}[storage])
     dims3 = np.array([nx, ny, nz])
     idx = np.empty((27, len(cells)), np.int64)
     for i in range(27):
         d = (cells - np.array([CX[i], CY[i], CZ[i]])) % dims3 if pre else cells
-        idx[i] = i * pstride + (d[:, 2] * ny + d[:, 1]) * nxp + d[:, 0]
+        idx[i] = ((d[:, 2] * ny + d[:, 1]) * 27 + i) * nxp + d[:, 0]
     h = view[torch.as_tensor(idx.ravel(), device=buf.device)].double().cpu().numpy().reshape(27, -1)
     if storage == "fp16":
         h = h / 256.0
@@ -1269,3 +1268,19 @@ def test_plane_copy_bitwise(torch, planes):
     torch.cuda.synchronize()
     assert torch.equal(a[:, :cells], b[:, :cells])
     assert torch.all(b[:, cells:] == -7.0)
+
+
+def test_row_block_copy_bitwise(torch):
+    """The row-block copy copies every value of rows * 27 * row_len (a row
+    length that is not a multiple of 64, a ragged last workgroup) and writes
+    nothing beyond that span."""
+    from paper_1905_10182_amd.cmlbm import row_block_copy
+    g = torch.Generator(device="cuda:0").manual_seed(6)
+    rows, row_len = 293, 101
+    span = rows * 27 * row_len
+    a = torch.randn(span + 777, device="cuda:0", generator=g)
+    b = torch.full_like(a, -7.0)
+    row_block_copy(b, a, rows, row_len)
+    torch.cuda.synchronize()
+    assert torch.equal(a[:span], b[:span])
+    assert torch.all(b[span:] == -7.0)
