@@ -475,7 +475,7 @@ def run_conv(steps, warmup, repeats):
     return out
 
 
-def plane_copy_rate(n=256, repeats=5, launches=20):
+def pattern_copy_rate(n=256, repeats=5, launches=20):
     """The FP32 step's memory traffic without its arithmetic on the headline
     lattice's layout (n^2 lattice rows, each a block of 27 population rows of
     n cells): median of `repeats` windows of `launches` row-block copies."""
@@ -740,7 +740,7 @@ def main():
         from paper_1905_10182_amd.cmlbm import device_copy
         extra["device_copy_gbs"] = round(copy_bandwidth(lambda b, a: b.copy_(a)), 1)  # torch's copy
         extra["kernel_copy_gbs"] = round(copy_bandwidth(device_copy), 1)  # 16-byte non-temporal copy kernel
-        extra["plane_copy"] = plane_copy_rate()  # the FP32 step's access pattern without arithmetic
+        extra["pattern_copy"] = pattern_copy_rate()  # the FP32 step's access pattern without arithmetic
     if "conv" in legs:
         mark("conv")
         log("U-Net training steps and convolution kernels (libcmnn)")
@@ -777,8 +777,8 @@ def main():
             "unit": "GB/s", "frac": main_run["hbm_frac"], "traffic": measured_traffic("fp32"),
             "bytes_per_cell": BYTES_PER_CELL["fp32"], "window_ms_per_step": main_run["window_ms_per_step"],
             "source_digest": source_digest(),
-            # the same 27-plane access pattern with no arithmetic, timed in this run (copy leg)
-            "pattern_copy_gbs": extra["plane_copy"]["gbs"] if "plane_copy" in extra else None},
+            # the same row-block access pattern with no arithmetic, timed in this run (copy leg)
+            "pattern_copy_gbs": extra["pattern_copy"]["gbs"] if "pattern_copy" in extra else None},
         "cpu_baseline": cpu,
         "mass_drift": main_run["mass_drift"] if main_run else None,
     }
