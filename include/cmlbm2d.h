@@ -73,11 +73,13 @@ typedef struct {
     uint32_t flags;  /* reserved, must be 0 */
 } cmlbm2d_params;
 
-/* Bytes the caller must provide for each of the two population buffers (nine
- * planes of ny rows, each row padded to 256 bytes; FP64 planes 4 KiB apart
- * beyond that).  Pure host computation.
- * EINVAL on invalid params, including a plane of 4 GiB or more (the kernels
- * address within a plane with 32-bit byte offsets). */
+/* Bytes the caller must provide for each of the two population buffers.
+ * Every population is stored in rows of nx values padded to 256 bytes; FP32
+ * and 16-bit storage keep the nine population rows of one lattice row
+ * together ([ny][9][row]), FP64 keeps nine planes of ny rows, 4 KiB apart
+ * beyond that.  Pure host computation.
+ * EINVAL on invalid params, including one population over all cells of
+ * 4 GiB or more (32-bit byte offsets). */
 int cmlbm2d_required_bytes(const cmlbm2d_params* params, size_t* pop_buffer_bytes);
 
 /* Create a handle over two caller-allocated device buffers (borrowed, each

@@ -46,7 +46,8 @@ PLANE_PAD = 4096  # bytes between consecutive FP64 population planes
 
 
 def test_required_bytes_padding():
-    # nine planes of ny rows, rows padded to 256 bytes, FP64 planes 4 KiB apart
+    # rows padded to 256 bytes; FP32/16-bit: nine population rows per lattice row; FP64: nine planes
+    # of ny rows, 4 KiB apart (either way nine times the rows of one population, plus the FP64 gaps)
     assert B.required_bytes(B.make_params(32, 16, storage="fp32")) == 9 * 16 * 64 * 4
     assert B.required_bytes(B.make_params(8192, 8192, storage="fp32")) == 9 * 8192 * 8192 * 4
     assert B.required_bytes(B.make_params(37, 13, storage="fp64")) == 9 * (13 * 64 * 8 + PLANE_PAD)
